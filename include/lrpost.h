@@ -1,0 +1,184 @@
+/*
+ * lrpost — low-rank posterior covariance for a space-time Bayesian inverse
+ * problem governed by the 2D heat equation, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Benner, Qiu, Stoll, "Low-rank computation of posterior covariance
+ * matrices in Bayesian inverse problems".  The posterior covariance
+ * Gamma_post = (A^T Gamma_noise^{-1} A + Gamma_prior^{-1})^{-1} (Sec. 2 eq.
+ * postcov1) is approximated from the dominant eigenpairs of the
+ * prior-preconditioned misfit Hessian (Sec. 2 eq. prior_pre) through the
+ * Sherman-Morrison-Woodbury update of Sec. 2, the eigenpairs coming from a
+ * Krylov process whose space-time vectors are kept as low-rank factors
+ * (Sec. 4 eq. lr_vec, Algorithm 1).  Each Hessian apply needs one forward and
+ * one adjoint space-time solve of (I_nt kron L + C kron M) vec(X) = vec(F)
+ * (Sec. 6.1 eq. st_pde), done here in low-rank matrix-equation form.
+ *
+ * Problem (all entry points):
+ *   y_t = Laplace(y) + u on [0,1]^2, y = 0 on the boundary, y(0) = 0;
+ *   Q1 elements on a uniform N x N mesh, n = N-1 interior nodes per side,
+ *   nx = n^2, nodes numbered (j-1) n + (i-1) for node (i h, j h), x1 fastest;
+ *   implicit Euler with tau = T/nt; the parameter is the space-time source u;
+ *   observations are nodal values inside a closed box at t_1..t_nt with noise
+ *   covariance sigma^2 I; Gamma_prior^{-1} = P = alpha tau (I_nt kron (K+M)).
+ *
+ * Space-time vectors: X in R^{nx x nt} (column k is time t_{k+1}) held as
+ * X = W1 W2^T.  In every lrpost_lowrank the spatial factor W1 is DEVICE memory
+ * (nx rows, leading dimension nx, column-major, float64) and the temporal
+ * factor W2 is HOST memory (nt rows, leading dimension nt, column-major,
+ * float64).  `cap` is the number of columns allocated in both; `rank` the
+ * number in use.  The caller allocates and owns both buffers.
+ *
+ * Errors: every call returns 0 on success or a negative code below; no C++
+ * exception crosses this interface.  lrpost_last_error() returns a
+ * thread-local message describing the last failure on the calling thread.
+ *
+ * Concurrency: one problem handle must not be used by two threads at once.
+ * Work is ordered on the HIP stream given in the description (or the null
+ * stream); every entry point returns after its results are complete.
+ */
+#ifndef LRPOST_H
+#define LRPOST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LRPOST_OK 0
+#define LRPOST_EINVAL -1      /* invalid argument: shape, rank above cap, sigma/alpha <= 0, empty box */
+#define LRPOST_ENOMEM -2      /* device allocation failed or request exceeds the HBM budget */
+#define LRPOST_ENOCONV -3     /* an iteration did not reach its tolerance within its limit */
+#define LRPOST_EBREAKDOWN -4  /* numerical breakdown that survived the fallback */
+#define LRPOST_EHIP -5        /* a HIP runtime call failed */
+
+#define LRPOST_FP64 0         /* every step in float64 */
+#define LRPOST_MIXED 1        /* float32 stencil/multigrid, float64 small factorizations */
+
+#define LRPOST_MISFIT 0       /* y = H_mis x = sigma^-2 F^T F x */
+#define LRPOST_PRECOND 1      /* y = G x = P^{-1} H_mis x (prior-preconditioned Hessian) */
+
+#define LRPOST_BLOCK_LANCZOS 0
+#define LRPOST_RANDOMIZED 1
+
+typedef struct lrpost_problem lrpost_problem;
+typedef struct lrpost_eigs lrpost_eigs;
+
+/* Problem description (the configuration of one inverse problem). */
+typedef struct {
+  int32_t N;          /* mesh cells per side; a power of two, 4 <= N <= 4096 */
+  int32_t nt;         /* implicit-Euler steps, >= 1 */
+  double T;           /* final time (> 0) */
+  double alpha;       /* prior precision scale (> 0) */
+  double sigma;       /* noise standard deviation (> 0) */
+  double box[4];      /* closed observation box x1lo, x1hi, x2lo, x2hi (must hold >= 1 node) */
+  double trunc_tol;   /* relative Frobenius truncation tolerance of factors, in (0, 1) */
+  int32_t rank_cap;   /* maximal factor rank kept after truncation, >= 1 */
+  int32_t precision;  /* LRPOST_FP64 or LRPOST_MIXED */
+  int32_t mg_levels;  /* 0 = coarsen down to a single node; otherwise the number of
+                         multigrid levels (the coarsest then gets a dense solve) */
+  uint64_t seed;      /* seed of the Lanczos start block */
+  void* hip_stream;   /* hipStream_t to order work on, or NULL for the null stream */
+} lrpost_problem_desc;
+
+/* A low-rank space-time vector X = W1 W2^T (see the header comment for memory). */
+typedef struct {
+  int32_t nx, nt, rank, cap;
+  double* W1; /* device, nx x cap */
+  double* W2; /* host,   nt x cap */
+} lrpost_lowrank;
+
+/* Statistics of the last operation on a problem (for logs and tests). */
+typedef struct {
+  int64_t applies;        /* Hessian applies since creation */
+  int32_t last_rank_y;    /* rank of the last forward state */
+  int32_t last_rank_p;    /* rank of the last adjoint state */
+  int32_t last_rank_out;  /* rank of the last apply's output */
+  int32_t last_basis;     /* spatial basis size of the last space-time solve */
+  int32_t lanczos_steps;  /* block steps of the last eigensolve */
+  int32_t pad;
+  double last_tail;       /* relative tail dropped by the last truncation */
+  double last_st_resid;   /* relative residual of the last checked space-time solve (or -1) */
+} lrpost_stats;
+
+/* Create a problem: validates the description, builds the multigrid
+ * hierarchy, the observation mask and the prior variance diag(P^{-1}).
+ * Allocates device memory owned by the handle.  Sec. 2 (problem), Sec. 6
+ * (Q1 heat equation, implicit Euler). */
+int lrpost_create(const lrpost_problem_desc* desc, lrpost_problem** out);
+int lrpost_destroy(lrpost_problem* p);
+
+/* Hessian apply on one low-rank vector (Sec. 6.1 eq. misfit, Sec. 4
+ * Algorithm 1 matrix-vector step): forward space-time solve of the source
+ * tau M X, observation and noise weighting, adjoint space-time solve,
+ * tau M, and for LRPOST_PRECOND the prior solve alpha^{-1} (K+M)^{-1}.
+ * x->rank may be 0 (y->rank is then 0).  y->cap must hold the truncated
+ * output (at most desc.rank_cap columns).  Returns LRPOST_EINVAL on shape
+ * mismatch. */
+int lrpost_hess_apply(lrpost_problem* p, const lrpost_lowrank* x, lrpost_lowrank* y, int which);
+/* nvec independent applies (x[i] -> y[i]) sharing spatial passes. */
+int lrpost_hess_apply_batch(lrpost_problem* p, int nvec, const lrpost_lowrank* x, lrpost_lowrank* y, int which);
+
+/* Low-rank space-time solve (Sec. 6.1 eq. st_pde with L = tau K):
+ * forward (adjoint = 0):  tau K Y + M Y C^T = F1 F2^T  (time runs forward),
+ * adjoint (adjoint = 1):  tau K Y + M Y C   = F1 F2^T  (time runs backward).
+ * Output truncated at desc.trunc_tol in the M-weighted Frobenius norm. */
+int lrpost_spacetime_solve(lrpost_problem* p, const lrpost_lowrank* f, lrpost_lowrank* y, int adjoint);
+
+/* Eigensolve for the k largest eigenpairs of G (Sec. 4 Algorithm 1, as block
+ * Lanczos with full re-orthogonalization in the P inner product; or a
+ * randomized two-pass range finder with k + oversample probes).  The result
+ * handle owns device-resident eigenvector factors. */
+int lrpost_eigensolve(lrpost_problem* p, int k, int method, int oversample, lrpost_eigs** out);
+int lrpost_eig_count(const lrpost_eigs* e);
+/* Eigenvalues, descending, into caller-owned host array of length k. */
+int lrpost_eig_values(const lrpost_eigs* e, double* lambda);
+/* Copy eigenvector i (P-orthonormal) into v (v->cap must suffice; sets v->rank). */
+int lrpost_eig_vector(const lrpost_eigs* e, int i, lrpost_lowrank* v);
+int lrpost_eig_vector_rank(const lrpost_eigs* e, int i);
+int lrpost_eigs_free(lrpost_eigs* e);
+/* Build an eigs handle from caller eigenpairs (lambda host, vectors as
+ * low-rank factors), e.g. to evaluate the posterior of a known basis. */
+int lrpost_eigs_from_pairs(lrpost_problem* p, int k, const double* lambda, const lrpost_lowrank* v,
+                           lrpost_eigs** out);
+
+/* diag(Gamma_post,k) = diag(P^{-1}) - sum_i d_i v_i^2, d_i = lambda_i/(1+lambda_i)
+ * (Sec. 2, Sherman-Morrison-Woodbury step), as an nx x nt array
+ * (column-major, caller-owned; `on_device` says whether diag is device memory). */
+int lrpost_post_variance(lrpost_problem* p, const lrpost_eigs* e, double* diag, int on_device);
+/* diag(P^{-1}) over one time step (nx values, host). */
+int lrpost_prior_variance(lrpost_problem* p, double* dprior);
+
+/* ns zero-mean posterior samples s = (I - V diag(p_i) V^T P) L xi with
+ * p_i = 1 - (1+lambda_i)^{-1/2} and L = (alpha tau)^{-1/2} (I kron (K+M)^{-1/2})
+ * (the symmetric root); covariance Gamma_post,k.  xi, out: host arrays of
+ * ns * nx * nt float64 (sample-major, each nx x nt column-major). */
+int lrpost_sample(lrpost_problem* p, const lrpost_eigs* e, int ns, const double* xi, double* out);
+
+int lrpost_get_stats(const lrpost_problem* p, lrpost_stats* s);
+
+/* ---- building blocks, exported for kernel-level parity tests ----------
+ * All pointers are DEVICE memory, float64, column-major with leading
+ * dimension nx (the problem's nx). */
+
+/* Y[:,j] = (a_j K + b_j M) X[:,j] + c_j Z[:,j] for j < ncols on the finest mesh
+ * (Z may be NULL); coef: host array of 3*ncols doubles (a_j, b_j, c_j). */
+int lrpost_stencil_apply(lrpost_problem* p, int ncols, const double* X, double* Y, const double* Z,
+                         const double* coef);
+/* X[:,j] approx (a_j K + b_j M)^{-1} B[:,j] by `cycles` multigrid V-cycles from
+ * X = 0 (coef: host, 2*ncols doubles a_j >= 0, b_j >= 0, a_j + b_j > 0). */
+int lrpost_mg_solve(lrpost_problem* p, int ncols, const double* B, double* X, const double* coef, int cycles);
+/* C = A^T B  (A: nx x m, B: nx x q, C: host m x q column-major). */
+int lrpost_gram(lrpost_problem* p, int m, const double* A, int q, const double* B, double* C_host);
+/* Truncate X = W1 W2^T in place to tolerance tol (<= 0: desc.trunc_tol) and
+ * rank <= cap; weighted = 1 measures in the M-norm in space. */
+int lrpost_truncate(lrpost_problem* p, lrpost_lowrank* x, double tol, int weighted);
+
+const char* lrpost_last_error(void);
+const char* lrpost_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LRPOST_H */

@@ -1,0 +1,163 @@
+// Internal declarations of the lrpost library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/lrpost.h"
+#include "dense.h"
+#include "kernels.h"
+
+namespace lrp {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+[[noreturn]] void fail(int code, const std::string& msg);
+
+#define LRP_HIP(call)                                                                              \
+  do {                                                                                             \
+    hipError_t e_ = (call);                                                                        \
+    if (e_ != hipSuccess)                                                                          \
+      ::lrp::fail(LRPOST_EHIP, std::string(#call) + " failed: " + hipGetErrorString(e_));          \
+  } while (0)
+
+// Device allocation owned by the holder; grows on demand, never shrinks.
+struct DevMem {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevMem() = default;
+  DevMem(const DevMem&) = delete;
+  DevMem& operator=(const DevMem&) = delete;
+  DevMem(DevMem&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevMem& operator=(DevMem&& o) noexcept {
+    release();
+    p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0;
+    return *this;
+  }
+  ~DevMem() { release(); }
+  void release();
+  void ensure(size_t nbytes);
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// A low-rank space-time vector X = A B^T with A on the device (nx x rank,
+// leading dimension nx) and B on the host (nt x rank, leading dimension nt).
+struct LowRank {
+  int rank = 0;
+  DevMem A;
+  std::vector<double> B;
+  long nx = 0;
+  int nt = 0;
+  void resize(long nx_, int nt_, int r);
+  double* a() const { return A.as<double>(); }
+};
+
+struct MgLevel {
+  int n;      // interior nodes per side
+  long nx;    // n*n
+  double h;   // mesh spacing
+};
+
+// Spatial operator a K + b M on the finest mesh, per column.
+struct ShiftCoef {
+  double a, b;
+};
+
+class Problem {
+ public:
+  explicit Problem(const lrpost_problem_desc& d);
+  ~Problem();
+
+  lrpost_problem_desc desc;
+  int N, n, nt;
+  long nx;
+  double h, tau;
+  hipStream_t st;
+  std::vector<MgLevel> lv;
+  int lds_level;  // first level solved inside one LDS workgroup
+  std::vector<uint8_t> mask_h;
+  DevMem mask;
+  int nobs = 0;
+  std::vector<double> dprior_h;  // diag(P^{-1}) per node
+  DevMem dprior;
+  lrpost_stats stats{};
+
+  // ---- small host/device transfers -------------------------------------
+  void sync();
+  void to_host(double* dst, const double* src, size_t count);
+  void to_device(double* dst, const double* src, size_t count);
+
+  // ---- spatial building blocks (double) --------------------------------
+  // Y = (a_j K + b_j M) X + c_j Z on the finest level
+  void apply_op(int ncols, const double* X, double* Y, const std::vector<ShiftCoef>& ab,
+                const double* Z = nullptr, const std::vector<double>* zc = nullptr);
+  // X ~ (a_j K + b_j M)^{-1} B by `cycles` V-cycles from zero
+  void mg_solve(int ncols, const double* B, double* X, const std::vector<ShiftCoef>& ab, int cycles);
+  // C (host, m x q) = A^T B
+  void gram(int m, const double* A, int q, const double* B, std::vector<double>& C);
+  // C = beta C + A Q (Q host m x p)
+  void proj(int m, const double* A, const std::vector<double>& Q, int p, double* C, double beta);
+
+  // ---- low-rank operations ---------------------------------------------
+  // Solve tau K Y + M Y C^T = F (forward) or tau K Y + M Y C = F (adjoint).
+  void spacetime_solve(const LowRank& F, LowRank& Y, bool adjoint);
+  // G x (precond) or H_mis x (misfit).
+  void hess_apply(const LowRank& x, LowRank& y, bool precond);
+  // Truncate in place; weight 0: Euclidean, 1: M, 2: K+M.
+  void truncate(LowRank& x, double tol, int cap, int weight);
+  // P inner product alpha tau <X, (I kron (K+M)) Y>.
+  double p_inner(const LowRank& x, const LowRank& y);
+  // sum_i c_i x_i as a truncated low-rank vector (P-weighted truncation).
+  void lincomb(const std::vector<const LowRank*>& xs, const std::vector<double>& c, LowRank& out, double tol,
+               int cap);
+
+  // ---- configuration of the inner solvers --------------------------------
+  int st_poles = 0;
+  int st_cycles = 0;
+  int prior_cycles = 0;
+  std::vector<double> poles;
+
+ private:
+  DevMem mg_param_, mg_work_, mg_res_, gram_part_, gram_out_, proj_q_, op_w_;
+  static constexpr size_t kStagingBytes = size_t(32) << 20;
+  void* staging_ = nullptr;
+  size_t staging_used_ = 0;
+  std::vector<double> mg_param_h_, op_w_h_;
+  std::vector<double> tmp_h_;
+  void vcycle_zero(int ncols, const double* B, double* X);
+  void upload_mg_params(const std::vector<ShiftCoef>& ab);
+  // space-time solver workspaces
+  DevMem st_q_, st_w_, st_mw_, st_f_;
+};
+
+void smoother_interval(double a, double bh2, double* lo, double* hi);
+void chebyshev_coefs(double lo, double hi, int nu, double* alpha, double* beta);
+constexpr int kMgNu = 3;  // Chebyshev steps before and after each coarse correction (odd)
+double normal_draw(uint64_t seed, uint64_t stream, uint64_t idx);
+
+struct EigResult {
+  std::vector<double> lambda;
+  std::vector<std::unique_ptr<LowRank>> vecs;
+  int steps = 0;
+};
+EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rtol);
+
+}  // namespace lrp
+
+struct lrpost_problem {
+  std::unique_ptr<lrp::Problem> impl;
+};
+
+struct lrpost_eigs {
+  lrpost_problem* owner = nullptr;
+  std::vector<double> lambda;
+  std::vector<std::unique_ptr<lrp::LowRank>> vecs;
+};

@@ -1,0 +1,52 @@
+// Launch wrappers for the device kernels (all asynchronous on the given stream).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lrp {
+
+// Y[:,c] = W[4c]*centre + W[4c+1]*edges + W[4c+2]*corners of X[:,c] + W[4c+3]*Z[:,c]
+// (W: device, 4*ncols doubles; Z may be null).
+template <typename T>
+void stencil(hipStream_t st, int n, int ncols, const T* X, long ldx, T* Y, long ldy, const T* Z, long ldz,
+             const double* W);
+
+// Multigrid passes; P: device, kMgStride doubles per column:
+// {wc, we, wk, 0, alpha_0, beta_0/wc, alpha_1, beta_1/wc, ...} (Chebyshev steps).
+constexpr int kMgStride = 12;
+constexpr int kMgMaxSteps = 4;
+template <typename T>
+void mg_smooth_step(hipStream_t st, int n, int ncols, const T* Xc, const T* Xp, T* Xo, const T* B, long ld,
+                    const double* P, int step);
+template <typename T>
+void mg_resid_restrict(hipStream_t st, int n, int ncols, const T* X, const T* B, long ld, T* Bc, long ldc,
+                       const double* P);
+template <typename T>
+void mg_prolong_add(hipStream_t st, int n, int ncols, const T* E, long ldc, const T* Xi, T* Xo, long ld);
+template <typename T>
+void mg_coarse_lds(hipStream_t st, int n0, int nlev, int ncols, const T* B, long ldb, T* X, long ldx,
+                   const double* Pc, int nu1, int nu2);
+constexpr int kCoarseLdsMaxN = 31;
+
+int gram_chunks(long nrows, int m, int q);
+// C (device, m x q, double) = A^T B; part: device scratch of gram_chunks()*m*q doubles.
+template <typename T>
+void gram(hipStream_t st, long nrows, int m, const T* A, long lda, int q, const T* B, long ldb, double* C,
+          double* part);
+// C = beta*C + A Q  (Q: device m x p double, leading dim ldq)
+template <typename T>
+void proj(hipStream_t st, long nrows, int m, const T* A, long lda, const double* Q, int ldq, int p, T* C, long ldc,
+          double beta);
+
+template <typename T>
+void mask_scale(hipStream_t st, long nx, int ncols, const T* X, long ldx, T* Y, long ldy, const uint8_t* mask,
+                double s);
+template <typename T>
+void axpby(hipStream_t st, long nx, int ncols, const T* X, long ldx, T* Y, long ldy, double a, double b);
+void d2f(hipStream_t st, long n, const double* x, float* y);
+void f2d(hipStream_t st, long n, const float* x, double* y);
+
+void post_variance(hipStream_t st, long nx, int nt, int k, const int* seg, const double* dcoef, const double* A,
+                   long lda, const double* Bt, int R, const double* dprior, double* D, long ldd);
+
+}  // namespace lrp

@@ -1,0 +1,637 @@
+// Device kernels for gfx950: Q1 stencil SpMM, geometric-multigrid passes,
+// tall-skinny Gram and projection products, elementwise helpers and the
+// posterior-variance product.
+//
+// Layout: a spatial block holds ncols columns of nx = n*n nodes, column-major
+// with leading dimension ld; node (i, j) (0-based, i along x1) sits at j*n + i.
+// Homogeneous Dirichlet conditions: nodes outside 0..n-1 read as zero.
+//
+// Q1 stencils on the uniform mesh of spacing h (interior node, 3x3 block):
+//   stiffness K: centre 8/3, the eight neighbours -1/3 (independent of h);
+//   mass      M: centre 4h^2/9, edge neighbours h^2/9, corners h^2/36.
+// The operator a K + b M is therefore a 9-point stencil with three weights
+// (centre, edge, corner); they are precomputed per column on the host.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+
+namespace lrp {
+
+// ---------------------------------------------------------------------------
+// Stencil: Y[:,c] = wc*x + we*(edges) + wk*(corners) + zc * Z[:,c]
+// Each thread owns one x1 index and walks S consecutive rows, keeping the
+// three rows it needs in registers; the x1 neighbours come from the
+// neighbouring lanes' loads through the L1 cache.
+// ---------------------------------------------------------------------------
+template <typename T, int S>
+__global__ __launch_bounds__(256) void k_stencil(int n, const T* __restrict__ X, long ldx, T* __restrict__ Y, long ldy,
+                                                 const T* __restrict__ Z, long ldz, const double* __restrict__ W) {
+  const int col = blockIdx.z;
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int j0 = (blockIdx.y * 4 + threadIdx.y) * S;
+  if (i >= n || j0 >= n) return;
+  const T wc = (T)W[4 * col + 0], we = (T)W[4 * col + 1], wk = (T)W[4 * col + 2], zc = (T)W[4 * col + 3];
+  const T* x = X + (long)col * ldx;
+  T* y = Y + (long)col * ldy;
+  const T* z = Z ? Z + (long)col * ldz : nullptr;
+  const bool hl = i > 0, hr = i + 1 < n;
+  auto row = [&](int j, T& l, T& m, T& r) {
+    if (j < 0 || j >= n) { l = m = r = T(0); return; }
+    const T* p = x + (long)j * n + i;
+    m = p[0];
+    l = hl ? p[-1] : T(0);
+    r = hr ? p[1] : T(0);
+  };
+  T l0, m0, r0, l1, m1, r1, l2, m2, r2;
+  row(j0 - 1, l0, m0, r0);
+  row(j0, l1, m1, r1);
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int j = j0 + s;
+    if (j >= n) break;
+    row(j + 1, l2, m2, r2);
+    T v = wc * m1 + we * ((l1 + r1) + (m0 + m2)) + wk * ((l0 + r0) + (l2 + r2));
+    if (z) v += zc * z[(long)j * n + i];
+    y[(long)j * n + i] = v;
+    l0 = l1; m0 = m1; r0 = r1;
+    l1 = l2; m1 = m2; r1 = r2;
+  }
+}
+
+template <typename T>
+void stencil(hipStream_t st, int n, int ncols, const T* X, long ldx, T* Y, long ldy, const T* Z, long ldz,
+             const double* W) {
+  if (ncols <= 0 || n <= 0) return;
+  constexpr int S = 8;
+  dim3 blk(64, 4);
+  dim3 grd((n + 63) / 64, (n + 4 * S - 1) / (4 * S), ncols);
+  hipLaunchKernelGGL((k_stencil<T, S>), grd, blk, 0, st, n, X, ldx, Y, ldy, Z, ldz, W);
+}
+template void stencil<double>(hipStream_t, int, int, const double*, long, double*, long, const double*, long,
+                              const double*);
+template void stencil<float>(hipStream_t, int, int, const float*, long, float*, long, const float*, long,
+                             const double*);
+
+// ---------------------------------------------------------------------------
+// Multigrid passes.  Per level and column the host provides kMgStride doubles
+//   {wc, we, wk, 0, alpha_0, beta_0, alpha_1, beta_1, ...}
+// with the stencil weights and the Chebyshev-smoother coefficients of each
+// step (beta already divided by the diagonal wc).  One smoother step:
+//   xo = xc + alpha_s (xc - xp) + beta_s (b - A xc),
+// where a null xc or xp stands for zero.  xo may alias xp (each node reads
+// its own xp value before writing it; neighbours are read from xc only).
+// ---------------------------------------------------------------------------
+template <typename T, int S>
+__global__ __launch_bounds__(256) void k_cheb(int n, const T* Xc, const T* Xp, T* Xo, const T* __restrict__ B,
+                                              long ld, const double* __restrict__ P, int step) {
+  const int col = blockIdx.z;
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int j0 = (blockIdx.y * 4 + threadIdx.y) * S;
+  if (i >= n || j0 >= n) return;
+  const double* pc = P + (long)col * kMgStride;
+  const T wc = (T)pc[0], we = (T)pc[1], wk = (T)pc[2];
+  const T al = (T)pc[4 + 2 * step], be = (T)pc[5 + 2 * step];
+  const T* b = B + (long)col * ld;
+  T* xo = Xo + (long)col * ld;
+  const T* xp = Xp ? Xp + (long)col * ld : nullptr;
+  if (!Xc) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int j = j0 + s;
+      if (j >= n) break;
+      const long idx = (long)j * n + i;
+      const T prev = xp ? xp[idx] : T(0);
+      xo[idx] = -al * prev + be * b[idx];
+    }
+    return;
+  }
+  const T* x = Xc + (long)col * ld;
+  const bool hl = i > 0, hr = i + 1 < n;
+  auto row = [&](int j, T& l, T& m, T& r) {
+    if (j < 0 || j >= n) { l = m = r = T(0); return; }
+    const T* p = x + (long)j * n + i;
+    m = p[0];
+    l = hl ? p[-1] : T(0);
+    r = hr ? p[1] : T(0);
+  };
+  T l0, m0, r0, l1, m1, r1, l2, m2, r2;
+  row(j0 - 1, l0, m0, r0);
+  row(j0, l1, m1, r1);
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int j = j0 + s;
+    if (j >= n) break;
+    row(j + 1, l2, m2, r2);
+    const long idx = (long)j * n + i;
+    const T ax = wc * m1 + we * ((l1 + r1) + (m0 + m2)) + wk * ((l0 + r0) + (l2 + r2));
+    const T prev = xp ? xp[idx] : T(0);
+    xo[idx] = m1 + al * (m1 - prev) + be * (b[idx] - ax);
+    l0 = l1; m0 = m1; r0 = r1;
+    l1 = l2; m1 = m2; r1 = r2;
+  }
+}
+
+template <typename T>
+void mg_smooth_step(hipStream_t st, int n, int ncols, const T* Xc, const T* Xp, T* Xo, const T* B, long ld,
+                    const double* P, int step) {
+  constexpr int S = 4;
+  dim3 blk(64, 4);
+  dim3 grd((n + 63) / 64, (n + 4 * S - 1) / (4 * S), ncols);
+  hipLaunchKernelGGL((k_cheb<T, S>), grd, blk, 0, st, n, Xc, Xp, Xo, B, ld, P, step);
+}
+template void mg_smooth_step<double>(hipStream_t, int, int, const double*, const double*, double*, const double*,
+                                     long, const double*, int);
+template void mg_smooth_step<float>(hipStream_t, int, int, const float*, const float*, float*, const float*, long,
+                                    const double*, int);
+
+// Fine residual r = b - A x evaluated at a fine node (0-based i, j).
+template <typename T>
+__device__ inline T fine_resid(int n, const T* __restrict__ x, const T* __restrict__ b, int i, int j, T wc, T we,
+                               T wk) {
+  if (i < 0 || j < 0 || i >= n || j >= n) return T(0);
+  auto at = [&](int ii, int jj) -> T { return (ii < 0 || jj < 0 || ii >= n || jj >= n) ? T(0) : x[(long)jj * n + ii]; };
+  const T ax = wc * at(i, j) + we * (at(i - 1, j) + at(i + 1, j) + at(i, j - 1) + at(i, j + 1)) +
+               wk * (at(i - 1, j - 1) + at(i + 1, j - 1) + at(i - 1, j + 1) + at(i + 1, j + 1));
+  return b[(long)j * n + i] - ax;
+}
+
+// Coarse right-hand side bc = P^T (b - A x): coarse node (I, J) sits on fine
+// node (2I+1, 2J+1) (0-based); bilinear-interpolation transpose weights
+// 1 (centre), 1/2 (edges), 1/4 (corners).
+template <typename T>
+__global__ __launch_bounds__(256) void k_resid_restrict(int n, int nc, const T* __restrict__ X,
+                                                        const T* __restrict__ B, long ld, T* __restrict__ Bc,
+                                                        long ldc, const double* __restrict__ P) {
+  const int col = blockIdx.z;
+  const int I = blockIdx.x * 64 + threadIdx.x;
+  const int J = blockIdx.y * 4 + threadIdx.y;
+  if (I >= nc || J >= nc) return;
+  const T wc = (T)P[kMgStride * col + 0], we = (T)P[kMgStride * col + 1], wk = (T)P[kMgStride * col + 2];
+  const T* x = X ? X + (long)col * ld : nullptr;
+  const T* b = B + (long)col * ld;
+  const int fi = 2 * I + 1, fj = 2 * J + 1;
+  T acc = T(0);
+  if (x) {
+#pragma unroll
+    for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+      for (int di = -1; di <= 1; ++di) {
+        const T w = (di == 0 ? T(1) : T(0.5)) * (dj == 0 ? T(1) : T(0.5));
+        acc += w * fine_resid(n, x, b, fi + di, fj + dj, wc, we, wk);
+      }
+  } else {
+#pragma unroll
+    for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+      for (int di = -1; di <= 1; ++di) {
+        const T w = (di == 0 ? T(1) : T(0.5)) * (dj == 0 ? T(1) : T(0.5));
+        acc += w * b[(long)(fj + dj) * n + (fi + di)];
+      }
+  }
+  Bc[(long)col * ldc + (long)J * nc + I] = acc;
+}
+
+template <typename T>
+void mg_resid_restrict(hipStream_t st, int n, int ncols, const T* X, const T* B, long ld, T* Bc, long ldc,
+                       const double* P) {
+  const int nc = (n - 1) / 2;
+  dim3 blk(64, 4);
+  dim3 grd((nc + 63) / 64, (nc + 3) / 4, ncols);
+  hipLaunchKernelGGL((k_resid_restrict<T>), grd, blk, 0, st, n, nc, X, B, ld, Bc, ldc, P);
+}
+template void mg_resid_restrict<double>(hipStream_t, int, int, const double*, const double*, long, double*, long,
+                                        const double*);
+template void mg_resid_restrict<float>(hipStream_t, int, int, const float*, const float*, long, float*, long,
+                                       const double*);
+
+// Xo = Xi + P e (bilinear interpolation of the coarse correction).
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong_add(int n, int nc, const T* __restrict__ E, long ldc,
+                                                     const T* __restrict__ Xi, T* __restrict__ Xo, long ld) {
+  const int col = blockIdx.z;
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int j = blockIdx.y * 4 + threadIdx.y;
+  if (i >= n || j >= n) return;
+  const T* e = E + (long)col * ldc;
+  auto at = [&](int I, int J) -> T { return (I < 0 || J < 0 || I >= nc || J >= nc) ? T(0) : e[(long)J * nc + I]; };
+  // fine index f: odd (f = 2I+1) coincides with coarse I; even f = 2I lies between I-1 and I
+  T v;
+  const bool io = (i & 1), jo = (j & 1);
+  const int Ii = (i - 1) >> 1, Jj = (j - 1) >> 1;  // valid when odd
+  if (io && jo) v = at(Ii, Jj);
+  else if (io) v = T(0.5) * (at(Ii, j / 2 - 1) + at(Ii, j / 2));
+  else if (jo) v = T(0.5) * (at(i / 2 - 1, Jj) + at(i / 2, Jj));
+  else v = T(0.25) * (at(i / 2 - 1, j / 2 - 1) + at(i / 2, j / 2 - 1) + at(i / 2 - 1, j / 2) + at(i / 2, j / 2));
+  const long idx = (long)col * ld + (long)j * n + i;
+  Xo[idx] = Xi[idx] + v;
+}
+
+template <typename T>
+void mg_prolong_add(hipStream_t st, int n, int ncols, const T* E, long ldc, const T* Xi, T* Xo, long ld) {
+  const int nc = (n - 1) / 2;
+  dim3 blk(64, 4);
+  dim3 grd((n + 63) / 64, (n + 3) / 4, ncols);
+  hipLaunchKernelGGL((k_prolong_add<T>), grd, blk, 0, st, n, nc, E, ldc, Xi, Xo, ld);
+}
+template void mg_prolong_add<double>(hipStream_t, int, int, const double*, long, const double*, double*, long);
+template void mg_prolong_add<float>(hipStream_t, int, int, const float*, long, const float*, float*, long);
+
+// ---------------------------------------------------------------------------
+// Coarse levels in LDS: one workgroup per column runs a full V-cycle from the
+// level with n0 = nlds (<= 31) nodes per side down to a single node, entirely
+// in shared memory.  Pc holds per level (0 = the level entering LDS) and
+// column the kMgStride smoother parameters: Pc[(lvl * ncols + col) * kMgStride].
+// Output: X = V-cycle(B) with zero initial guess, nu1 / nu2 Chebyshev steps.
+// ---------------------------------------------------------------------------
+constexpr int kLdsMaxN = 31;
+constexpr int kLdsTotal = 961 + 225 + 49 + 9 + 1;  // 31^2 + 15^2 + 7^2 + 3^2 + 1^2
+
+template <typename T>
+__device__ inline T lds_at(const T* a, int n, int i, int j) {
+  return (i < 0 || j < 0 || i >= n || j >= n) ? T(0) : a[j * n + i];
+}
+
+// nu Chebyshev steps on one level held in LDS: x holds x_0 (or is treated as
+// zero), t is scratch; the result is left in x.
+template <typename T>
+__device__ void lds_smooth(int n, T* x, T* t, const T* b, const double* pc, int nu, bool zero) {
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const T wc = (T)pc[0], we = (T)pc[1], wk = (T)pc[2];
+  // step s reads xc and xp and writes into the buffer holding xp:
+  // s = 0: xc = x (or 0), writes t;  s = 1: xc = t, xp = x, writes x; ...
+  for (int s = 0; s < nu; ++s) {
+    const T al = (T)pc[4 + 2 * s], be = (T)pc[5 + 2 * s];
+    T* xc = (s % 2 == 0) ? x : t;
+    T* xo = (s % 2 == 0) ? t : x;
+    const bool cz = zero && s == 0;        // xc is zero
+    const bool pz = s == 0 || (zero && s == 1);  // xp is zero
+    for (int p = tid; p < n * n; p += nth) {
+      const int i = p % n, j = p / n;
+      T ax = T(0), xcv = T(0);
+      if (!cz) {
+        xcv = xc[p];
+        ax = wc * xcv + we * (lds_at(xc, n, i - 1, j) + lds_at(xc, n, i + 1, j) + lds_at(xc, n, i, j - 1) +
+                              lds_at(xc, n, i, j + 1)) +
+             wk * (lds_at(xc, n, i - 1, j - 1) + lds_at(xc, n, i + 1, j - 1) + lds_at(xc, n, i - 1, j + 1) +
+                   lds_at(xc, n, i + 1, j + 1));
+      }
+      const T prev = pz ? T(0) : xo[p];
+      xo[p] = xcv + al * (xcv - prev) + be * (b[p] - ax);
+    }
+    __syncthreads();
+  }
+  if (nu % 2 == 1) {
+    for (int p = tid; p < n * n; p += nth) x[p] = t[p];
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_lds(int n0, int nlev, const T* __restrict__ B, long ldb,
+                                                    T* __restrict__ X, long ldx, const double* __restrict__ Pc,
+                                                    int ncols, int nu1, int nu2) {
+  __shared__ T xs[kLdsTotal];
+  __shared__ T bs[kLdsTotal];
+  __shared__ T ts[kLdsMaxN * kLdsMaxN];
+  const int col = blockIdx.x;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  int off[6], nn[6];
+  {
+    int o = 0, m = n0;
+    for (int l = 0; l < nlev; ++l) { off[l] = o; nn[l] = m; o += m * m; m = (m - 1) / 2; }
+  }
+  for (int p = tid; p < n0 * n0; p += nth) bs[p] = B[(long)col * ldb + p];
+  __syncthreads();
+  auto prm = [&](int l, int k) -> T { return (T)Pc[((long)l * ncols + col) * kMgStride + k]; };
+  auto pcl = [&](int l) -> const double* { return Pc + ((long)l * ncols + col) * kMgStride; };
+  // down
+  for (int l = 0; l < nlev; ++l) {
+    const int n = nn[l];
+    T* x = xs + off[l];
+    T* b = bs + off[l];
+    const T wc = prm(l, 0), we = prm(l, 1), wk = prm(l, 2);
+    if (n == 1) {  // exact solve of the 1x1 system
+      if (tid == 0) x[0] = b[0] / wc;
+      __syncthreads();
+      break;
+    }
+    lds_smooth(n, x, ts, b, pcl(l), nu1, true);
+    // restrict residual
+    const int nc = (n - 1) / 2;
+    T* bc = bs + off[l + 1];
+    for (int p = tid; p < nc * nc; p += nth) {
+      const int I = p % nc, J = p / nc;
+      T acc = T(0);
+      for (int dj = -1; dj <= 1; ++dj)
+        for (int di = -1; di <= 1; ++di) {
+          const int i = 2 * I + 1 + di, j = 2 * J + 1 + dj;
+          const T ax = wc * lds_at(x, n, i, j) +
+                       we * (lds_at(x, n, i - 1, j) + lds_at(x, n, i + 1, j) + lds_at(x, n, i, j - 1) +
+                             lds_at(x, n, i, j + 1)) +
+                       wk * (lds_at(x, n, i - 1, j - 1) + lds_at(x, n, i + 1, j - 1) +
+                             lds_at(x, n, i - 1, j + 1) + lds_at(x, n, i + 1, j + 1));
+          const T w = (di == 0 ? T(1) : T(0.5)) * (dj == 0 ? T(1) : T(0.5));
+          acc += w * (b[j * n + i] - ax);
+        }
+      bc[p] = acc;
+    }
+    __syncthreads();
+  }
+  // up
+  for (int l = nlev - 2; l >= 0; --l) {
+    const int n = nn[l], nc = nn[l + 1];
+    T* x = xs + off[l];
+    const T* e = xs + off[l + 1];
+    for (int p = tid; p < n * n; p += nth) {
+      const int i = p % n, j = p / n;
+      T v;
+      const bool io = (i & 1), jo = (j & 1);
+      const int Ii = (i - 1) >> 1, Jj = (j - 1) >> 1;
+      if (io && jo) v = lds_at(e, nc, Ii, Jj);
+      else if (io) v = T(0.5) * (lds_at(e, nc, Ii, j / 2 - 1) + lds_at(e, nc, Ii, j / 2));
+      else if (jo) v = T(0.5) * (lds_at(e, nc, i / 2 - 1, Jj) + lds_at(e, nc, i / 2, Jj));
+      else
+        v = T(0.25) * (lds_at(e, nc, i / 2 - 1, j / 2 - 1) + lds_at(e, nc, i / 2, j / 2 - 1) +
+                       lds_at(e, nc, i / 2 - 1, j / 2) + lds_at(e, nc, i / 2, j / 2));
+      x[p] += v;
+    }
+    __syncthreads();
+    lds_smooth(n, x, ts, bs + off[l], pcl(l), nu2, false);
+  }
+  for (int p = tid; p < n0 * n0; p += nth) X[(long)col * ldx + p] = xs[p];
+}
+
+template <typename T>
+void mg_coarse_lds(hipStream_t st, int n0, int nlev, int ncols, const T* B, long ldb, T* X, long ldx,
+                   const double* Pc, int nu1, int nu2) {
+  hipLaunchKernelGGL((k_coarse_lds<T>), dim3(ncols), dim3(256), 0, st, n0, nlev, B, ldb, X, ldx, Pc, ncols, nu1,
+                     nu2);
+}
+template void mg_coarse_lds<double>(hipStream_t, int, int, int, const double*, long, double*, long, const double*,
+                                    int, int);
+template void mg_coarse_lds<float>(hipStream_t, int, int, int, const float*, long, float*, long, const double*, int,
+                                   int);
+
+// ---------------------------------------------------------------------------
+// Gram C = A^T B (A: nrows x m, B: nrows x q).  Stage 1: each workgroup takes
+// a chunk of rows and a 32 x 32 output tile, stages A and B rows through LDS
+// and writes a partial tile; stage 2 sums the partials in a fixed order
+// (deterministic, no atomics).  Accumulation in double.
+// ---------------------------------------------------------------------------
+constexpr int GT = 32;     // output tile edge
+constexpr int GR = 64;     // rows staged per LDS step
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram_partial(long nrows, long rows_per_chunk, int m, const T* __restrict__ A,
+                                                      long lda, int q, const T* __restrict__ B, long ldb,
+                                                      double* __restrict__ part) {
+  __shared__ double As[GR][GT + 1];
+  __shared__ double Bs[GR][GT + 1];
+  const int tm = blockIdx.x, tq = blockIdx.y, chunk = blockIdx.z;
+  const int tid = threadIdx.x;
+  const int tx = tid % 16, ty = tid / 16;  // each thread: 2 x 2 outputs
+  const long r0 = (long)chunk * rows_per_chunk;
+  const long r1 = min(nrows, r0 + rows_per_chunk);
+  double acc[2][2] = {{0, 0}, {0, 0}};
+  for (long rb = r0; rb < r1; rb += GR) {
+    // load GR x GT of A (columns tm*GT ..) and B
+    for (int p = tid; p < GR * GT; p += 256) {
+      const int rr = p % GR, cc = p / GR;
+      const long r = rb + rr;
+      const int ca = tm * GT + cc, cb = tq * GT + cc;
+      As[rr][cc] = (r < r1 && ca < m) ? (double)A[(long)ca * lda + r] : 0.0;
+      Bs[rr][cc] = (r < r1 && cb < q) ? (double)B[(long)cb * ldb + r] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int rr = 0; rr < GR; ++rr) {
+      const double a0 = As[rr][tx], a1 = As[rr][tx + 16];
+      const double b0 = Bs[rr][ty], b1 = Bs[rr][ty + 16];
+      acc[0][0] += a0 * b0; acc[0][1] += a0 * b1;
+      acc[1][0] += a1 * b0; acc[1][1] += a1 * b1;
+    }
+    __syncthreads();
+  }
+  // partial layout: [chunk][q][m] column-major m x q per chunk
+  double* P = part + (long)chunk * m * q;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const int i = tm * GT + tx + 16 * a, j = tq * GT + ty + 16 * b;
+      if (i < m && j < q) P[(long)j * m + i] = acc[a][b];
+    }
+}
+
+__global__ void k_sum_partials(int nchunk, long count, const double* __restrict__ part, double* __restrict__ C) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= count) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[(long)c * count + idx];
+  C[idx] = s;
+}
+
+int gram_chunks(long nrows, int m, int q) {
+  // aim for about 2048 workgroups in stage 1, at least 1024 rows per chunk
+  const long tiles = (long)((m + GT - 1) / GT) * ((q + GT - 1) / GT);
+  long c = 2048 / (tiles > 0 ? tiles : 1);
+  const long cmax = (nrows + 1023) / 1024;
+  if (c > cmax) c = cmax;
+  if (c > 256) c = 256;
+  if (c < 1) c = 1;
+  return (int)c;
+}
+
+template <typename T>
+void gram(hipStream_t st, long nrows, int m, const T* A, long lda, int q, const T* B, long ldb, double* C,
+          double* part) {
+  if (m <= 0 || q <= 0) return;
+  const int nchunk = gram_chunks(nrows, m, q);
+  long rpc = (nrows + nchunk - 1) / nchunk;
+  rpc = ((rpc + GR - 1) / GR) * GR;
+  dim3 grd((m + GT - 1) / GT, (q + GT - 1) / GT, nchunk);
+  hipLaunchKernelGGL((k_gram_partial<T>), grd, dim3(256), 0, st, nrows, rpc, m, A, lda, q, B, ldb, part);
+  const long count = (long)m * q;
+  hipLaunchKernelGGL(k_sum_partials, dim3((count + 255) / 256), dim3(256), 0, st, nchunk, count, part, C);
+}
+template void gram<double>(hipStream_t, long, int, const double*, long, int, const double*, long, double*, double*);
+template void gram<float>(hipStream_t, long, int, const float*, long, int, const float*, long, double*, double*);
+
+// ---------------------------------------------------------------------------
+// Projection C = beta*C + A Q (A: nrows x m, Q: m x p small (double, device),
+// C: nrows x p).  Each thread owns one row and up to PT output columns;
+// Q is staged through LDS in slabs of 32 rows.
+// ---------------------------------------------------------------------------
+constexpr int PT = 16;
+
+template <typename T>
+void axpby(hipStream_t st, long nx, int ncols, const T* X, long ldx, T* Y, long ldy, double a, double b);
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_proj(long nrows, int m, const T* __restrict__ A, long lda,
+                                              const double* __restrict__ Q, int ldq, int p, T* __restrict__ C,
+                                              long ldc, double beta) {
+  __shared__ double Qs[32][PT];
+  const long r = (long)blockIdx.x * 256 + threadIdx.x;
+  const int c0 = blockIdx.y * PT;
+  double acc[PT];
+#pragma unroll
+  for (int c = 0; c < PT; ++c) acc[c] = 0.0;
+  for (int k0 = 0; k0 < m; k0 += 32) {
+    for (int t = threadIdx.x; t < 32 * PT; t += 256) {
+      const int kk = t % 32, cc = t / 32;
+      Qs[kk][cc] = (k0 + kk < m && c0 + cc < p) ? Q[(long)(c0 + cc) * ldq + k0 + kk] : 0.0;
+    }
+    __syncthreads();
+    if (r < nrows) {
+      const int kmax = min(32, m - k0);
+      for (int kk = 0; kk < kmax; ++kk) {
+        const double a = (double)A[(long)(k0 + kk) * lda + r];
+#pragma unroll
+        for (int c = 0; c < PT; ++c) acc[c] += a * Qs[kk][c];
+      }
+    }
+    __syncthreads();
+  }
+  if (r < nrows) {
+#pragma unroll
+    for (int c = 0; c < PT; ++c) {
+      if (c0 + c < p) {
+        T* dst = C + (long)(c0 + c) * ldc + r;
+        *dst = (T)(beta == 0.0 ? acc[c] : beta * (double)(*dst) + acc[c]);
+      }
+    }
+  }
+}
+
+template <typename T>
+void proj(hipStream_t st, long nrows, int m, const T* A, long lda, const double* Q, int ldq, int p, T* C, long ldc,
+          double beta) {
+  if (p <= 0) return;
+  if (m <= 0) {
+    if (beta == 0.0) axpby<T>(st, nrows, p, C, ldc, C, ldc, 0.0, 0.0);
+    return;
+  }
+  dim3 grd((nrows + 255) / 256, (p + PT - 1) / PT);
+  hipLaunchKernelGGL((k_proj<T>), grd, dim3(256), 0, st, nrows, m, A, lda, Q, ldq, p, C, ldc, beta);
+}
+template void proj<double>(hipStream_t, long, int, const double*, long, const double*, int, int, double*, long,
+                           double);
+template void proj<float>(hipStream_t, long, int, const float*, long, const double*, int, int, float*, long, double);
+
+// ---------------------------------------------------------------------------
+// Elementwise helpers
+// ---------------------------------------------------------------------------
+// Y[:,c] = s * mask .* X[:,c]
+template <typename T>
+__global__ void k_mask_scale(long nx, int ncols, const T* __restrict__ X, long ldx, T* __restrict__ Y, long ldy,
+                             const uint8_t* __restrict__ mask, double s) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (idx >= nx) return;
+  Y[(long)c * ldy + idx] = mask[idx] ? (T)(s * (double)X[(long)c * ldx + idx]) : T(0);
+}
+template <typename T>
+void mask_scale(hipStream_t st, long nx, int ncols, const T* X, long ldx, T* Y, long ldy, const uint8_t* mask,
+                double s) {
+  if (ncols <= 0) return;
+  hipLaunchKernelGGL((k_mask_scale<T>), dim3((nx + 255) / 256, ncols), dim3(256), 0, st, nx, ncols, X, ldx, Y, ldy,
+                     mask, s);
+}
+template void mask_scale<double>(hipStream_t, long, int, const double*, long, double*, long, const uint8_t*, double);
+template void mask_scale<float>(hipStream_t, long, int, const float*, long, float*, long, const uint8_t*, double);
+
+// Y = a X + b Y (column blocks)
+template <typename T>
+__global__ void k_axpby(long nx, const T* __restrict__ X, long ldx, T* __restrict__ Y, long ldy, double a, double b) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (idx >= nx) return;
+  T* y = Y + (long)c * ldy + idx;
+  *y = (T)(a * (double)X[(long)c * ldx + idx] + (b == 0.0 ? 0.0 : b * (double)(*y)));
+}
+template <typename T>
+void axpby(hipStream_t st, long nx, int ncols, const T* X, long ldx, T* Y, long ldy, double a, double b) {
+  if (ncols <= 0) return;
+  hipLaunchKernelGGL((k_axpby<T>), dim3((nx + 255) / 256, ncols), dim3(256), 0, st, nx, X, ldx, Y, ldy, a, b);
+}
+template void axpby<double>(hipStream_t, long, int, const double*, long, double*, long, double, double);
+template void axpby<float>(hipStream_t, long, int, const float*, long, float*, long, double, double);
+
+// conversions
+__global__ void k_d2f(long n, const double* __restrict__ x, float* __restrict__ y) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (float)x[i];
+}
+__global__ void k_f2d(long n, const float* __restrict__ x, double* __restrict__ y) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (double)x[i];
+}
+void d2f(hipStream_t st, long n, const double* x, float* y) {
+  if (n > 0) hipLaunchKernelGGL(k_d2f, dim3((n + 255) / 256), dim3(256), 0, st, n, x, y);
+}
+void f2d(hipStream_t st, long n, const float* x, double* y) {
+  if (n > 0) hipLaunchKernelGGL(k_f2d, dim3((n + 255) / 256), dim3(256), 0, st, n, x, y);
+}
+
+// ---------------------------------------------------------------------------
+// Posterior variance: D[x, t] = dprior[x] - sum_i d_i (sum_c A_i[x, c] B_i[t, c])^2
+// The eigenvector factors are packed: A (nx x R) with all vectors' spatial
+// columns side by side, Bt (R x nt) the temporal factors transposed, and
+// seg[i] .. seg[i+1] the column range of vector i.  Each thread owns one
+// node x and a run of time steps; the small factors of a time tile are staged
+// in LDS.
+// ---------------------------------------------------------------------------
+constexpr int VT = 16;  // time steps per thread
+
+__global__ __launch_bounds__(256) void k_post_var(long nx, int nt, int k, const int* __restrict__ seg,
+                                                  const double* __restrict__ dcoef, const double* __restrict__ A,
+                                                  long lda, const double* __restrict__ Bt, int R,
+                                                  const double* __restrict__ dprior, double* __restrict__ D,
+                                                  long ldd) {
+  const long x = (long)blockIdx.x * 256 + threadIdx.x;
+  const int t0 = blockIdx.y * VT;
+  __shared__ double Bsh[64][VT];
+  double acc[VT];
+#pragma unroll
+  for (int t = 0; t < VT; ++t) acc[t] = 0.0;
+  for (int i = 0; i < k; ++i) {
+    const int c0 = seg[i], c1 = seg[i + 1];
+    const double di = dcoef[i];
+    double v[VT];
+#pragma unroll
+    for (int t = 0; t < VT; ++t) v[t] = 0.0;
+    for (int cb = c0; cb < c1; cb += 64) {
+      const int cn = min(64, c1 - cb);
+      __syncthreads();
+      for (int p = threadIdx.x; p < 64 * VT; p += 256) {
+        const int cc = p / VT, tt = p % VT;
+        Bsh[cc][tt] = (cc < cn && t0 + tt < nt) ? Bt[(long)(t0 + tt) * R + cb + cc] : 0.0;
+      }
+      __syncthreads();
+      if (x < nx) {
+        for (int cc = 0; cc < cn; ++cc) {
+          const double a = A[(long)(cb + cc) * lda + x];
+#pragma unroll
+          for (int t = 0; t < VT; ++t) v[t] += a * Bsh[cc][t];
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < VT; ++t) acc[t] += di * v[t] * v[t];
+  }
+  if (x < nx) {
+    const double dp = dprior[x];
+#pragma unroll
+    for (int t = 0; t < VT; ++t)
+      if (t0 + t < nt) D[(long)(t0 + t) * ldd + x] = dp - acc[t];
+  }
+}
+
+void post_variance(hipStream_t st, long nx, int nt, int k, const int* seg, const double* dcoef, const double* A,
+                   long lda, const double* Bt, int R, const double* dprior, double* D, long ldd) {
+  dim3 grd((nx + 255) / 256, (nt + VT - 1) / VT);
+  hipLaunchKernelGGL(k_post_var, grd, dim3(256), 0, st, nx, nt, k, seg, dcoef, A, lda, Bt, R, dprior, D, ldd);
+}
+
+}  // namespace lrp

@@ -1,0 +1,777 @@
+// Problem setup, multigrid driver, the low-rank space-time solver and the
+// Hessian apply.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "internal.h"
+
+namespace lrp {
+
+void fail(int code, const std::string& msg) { throw Error(code, msg); }
+
+void DevMem::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+void DevMem::ensure(size_t nbytes) {
+  if (nbytes <= bytes) return;
+  release();
+  size_t want = std::max<size_t>(nbytes, 256);
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    fail(LRPOST_ENOMEM, "device allocation of " + std::to_string(want) + " bytes failed");
+  }
+  bytes = want;
+}
+
+void LowRank::resize(long nx_, int nt_, int r) {
+  nx = nx_;
+  nt = nt_;
+  rank = r;
+  A.ensure(sizeof(double) * (size_t)nx * std::max(r, 1));
+  B.assign((size_t)nt * r, 0.0);
+}
+
+// Interval [l, u] of the symbol of D^{-1}(a K + b M) over the high
+// frequencies, on a level with spacing h (bh2 = b h^2).  With c1 = cos(theta1),
+// c2 = cos(theta2) the stencil symbols are K: (8 - 2 c1 - 2 c2 - 4 c1 c2)/3 and
+// M/h^2: (2 + c1)(2 + c2)/9; both are bilinear in (c1, c2), so extremes over
+// the rectangles that make up the high-frequency set {min(c1, c2) <= 0} sit at
+// their corners.  The maximum over all frequencies is taken at the corners of
+// [-1, 1]^2.
+void smoother_interval(double a, double bh2, double* lo, double* hi) {
+  auto sym = [&](double c1, double c2) {
+    const double k = (8.0 - 2.0 * c1 - 2.0 * c2 - 4.0 * c1 * c2) / 3.0;
+    const double m = (2.0 + c1) * (2.0 + c2) / 9.0;
+    return (a * k + bh2 * m) / (a * 8.0 / 3.0 + bh2 * 4.0 / 9.0);
+  };
+  double smax = 0.0;
+  for (double c1 : {-1.0, 1.0})
+    for (double c2 : {-1.0, 1.0}) smax = std::max(smax, sym(c1, c2));
+  double smin = 1e300;
+  const double pts[7][2] = {{-1, -1}, {-1, 1}, {0, -1}, {0, 1}, {1, -1}, {1, 0}, {-1, 0}};
+  for (auto& p : pts) smin = std::min(smin, sym(p[0], p[1]));
+  *lo = smin;
+  *hi = smax;
+}
+
+// Chebyshev semi-iteration on [lo, hi] (Golub-Varga / Saad's three-term form):
+// x_1 = x_0 + r_0/theta; x_{k+1} = x_k + rho_k rho_{k-1} (x_k - x_{k-1}) + (2 rho_k/delta) r_k
+// with theta = (hi+lo)/2, delta = (hi-lo)/2, rho_0 = delta/theta,
+// rho_k = 1/(2 theta/delta - rho_{k-1}) and r = D^{-1}(b - A x).
+void chebyshev_coefs(double lo, double hi, int nu, double* alpha, double* beta) {
+  const double th = 0.5 * (hi + lo), de = 0.5 * (hi - lo), sg = th / de;
+  double rho = 1.0 / sg;
+  alpha[0] = 0.0;
+  beta[0] = 1.0 / th;
+  for (int k = 1; k < nu; ++k) {
+    const double rn = 1.0 / (2.0 * sg - rho);
+    alpha[k] = rn * rho;
+    beta[k] = 2.0 * rn / de;
+    rho = rn;
+  }
+}
+
+static void stencil_weights(double a, double b, double h, double* w) {
+  const double h2 = h * h;
+  w[0] = a * 8.0 / 3.0 + b * 4.0 * h2 / 9.0;
+  w[1] = -a / 3.0 + b * h2 / 9.0;
+  w[2] = -a / 3.0 + b * h2 / 36.0;
+}
+
+Problem::Problem(const lrpost_problem_desc& d) : desc(d) {
+  if (d.N < 4 || d.N > 4096 || (d.N & (d.N - 1)) != 0) fail(LRPOST_EINVAL, "N must be a power of two in [4, 4096]");
+  if (d.nt < 1) fail(LRPOST_EINVAL, "nt must be >= 1");
+  if (!(d.T > 0) || !(d.alpha > 0) || !(d.sigma > 0)) fail(LRPOST_EINVAL, "T, alpha and sigma must be positive");
+  if (!(d.trunc_tol > 0) || !(d.trunc_tol < 1)) fail(LRPOST_EINVAL, "trunc_tol must lie in (0, 1)");
+  if (d.rank_cap < 1) fail(LRPOST_EINVAL, "rank_cap must be >= 1");
+  if (d.precision != LRPOST_FP64 && d.precision != LRPOST_MIXED) fail(LRPOST_EINVAL, "unknown precision");
+  N = d.N;
+  n = N - 1;
+  nt = d.nt;
+  nx = (long)n * n;
+  h = 1.0 / N;
+  tau = d.T / nt;
+  st = (hipStream_t)d.hip_stream;
+  // multigrid hierarchy: n, (n-1)/2, ..., 1
+  for (int m = n; m >= 1; m = (m - 1) / 2) {
+    lv.push_back({m, (long)m * m, 1.0 / (m + 1)});
+    if (m == 1) break;
+  }
+  lds_level = 0;
+  while (lv[lds_level].n > kCoarseLdsMaxN) ++lds_level;
+  // observation mask (closed box, 1e-12 slack)
+  mask_h.assign(nx, 0);
+  const double eps = 1e-12;
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      const double x1 = (i + 1) * h, x2 = (j + 1) * h;
+      const bool in = x1 >= d.box[0] - eps && x1 <= d.box[1] + eps && x2 >= d.box[2] - eps && x2 <= d.box[3] + eps;
+      mask_h[(size_t)j * n + i] = in ? 1 : 0;
+      nobs += in ? 1 : 0;
+    }
+  if (nobs == 0) fail(LRPOST_EINVAL, "observation box holds no mesh node");
+  mask.ensure(nx);
+  LRP_HIP(hipMemcpy(mask.p, mask_h.data(), nx, hipMemcpyHostToDevice));
+  // prior variance diag(P^{-1}) from the sine eigenpairs of K and M:
+  // (K+M)^{-1} = sum_p phi_p phi_p^T / (kappa_p + mu_p), phi_p = s_i (x) s_j,
+  // s_j(ii) = sqrt(2h) sin(ii j pi h), kappa = k_i m_j + m_i k_j, mu = m_i m_j.
+  {
+    std::vector<double> k1(n), m1(n), Sq((size_t)n * n);
+    for (int j = 0; j < n; ++j) {
+      const double th = (j + 1) * M_PI * h;
+      k1[j] = (4.0 / h) * std::sin(th / 2) * std::sin(th / 2);
+      m1[j] = (h / 3.0) * (2.0 + std::cos(th));
+    }
+    for (int mode = 0; mode < n; ++mode)
+      for (int node = 0; node < n; ++node) {
+        const double s = std::sqrt(2.0 * h) * std::sin((double)(node + 1) * (mode + 1) * M_PI * h);
+        Sq[(size_t)mode * n + node] = s * s;  // Sq[node, mode]
+      }
+    std::vector<double> W((size_t)n * n), T1((size_t)n * n);
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i)
+        W[(size_t)j * n + i] = 1.0 / (k1[i] * m1[j] + m1[i] * k1[j] + m1[i] * m1[j]);
+    // D = Sq W Sq^T, D[ii, jj]
+    matmul(n, n, n, Sq.data(), n, false, W.data(), n, false, T1.data(), n, 1.0, 0.0);
+    std::vector<double> D((size_t)n * n);
+    matmul(n, n, n, T1.data(), n, false, Sq.data(), n, true, D.data(), n, 1.0, 0.0);
+    dprior_h.resize(nx);
+    const double s = 1.0 / (d.alpha * tau);
+    for (int jj = 0; jj < n; ++jj)
+      for (int ii = 0; ii < n; ++ii) dprior_h[(size_t)jj * n + ii] = s * D[(size_t)jj * n + ii];
+  }
+  dprior.ensure(sizeof(double) * nx);
+  LRP_HIP(hipMemcpy(dprior.p, dprior_h.data(), sizeof(double) * nx, hipMemcpyHostToDevice));
+  // inner-solver settings from the truncation tolerance: poles of the spatial
+  // rational Krylov basis log-spaced over the time-step scaled spectrum, and
+  // enough V-cycles (contraction about 0.08 per cycle) to resolve it
+  const double lt = -std::log10(d.trunc_tol);
+  st_poles = std::max(4, std::min(24, (int)std::lround(1.5 * lt) + 1));
+  st_cycles = std::max(3, (int)std::ceil((lt + 1.0) / 1.1) + 1);
+  prior_cycles = std::max(4, (int)std::ceil((lt + 2.0) / 1.1) + 1);
+  const double lam_min = 2.0 * M_PI * M_PI;
+  const double lam_max = 24.0 / (h * h);
+  const double plo = std::min(1e-2, 0.5 * tau * lam_min);
+  const double phi = std::max(10.0 * plo, std::min(tau * lam_max, 1e4));
+  poles.resize(st_poles);
+  for (int i = 0; i < st_poles; ++i)
+    poles[i] = plo * std::pow(phi / plo, st_poles == 1 ? 0.0 : (double)i / (st_poles - 1));
+  stats.last_st_resid = -1.0;
+}
+
+Problem::~Problem() {
+  if (st) (void)hipStreamSynchronize(st);
+  else (void)hipDeviceSynchronize();
+  if (staging_) (void)hipHostFree(staging_);
+}
+
+void Problem::sync() {
+  LRP_HIP(hipStreamSynchronize(st));
+  staging_used_ = 0;
+}
+
+// Host-to-device copies go through a pinned staging arena so that the host
+// source may be reused at once; the arena is recycled at every stream sync.
+void Problem::to_device(double* dst, const double* src, size_t count) {
+  const size_t bytes = sizeof(double) * count;
+  if (bytes == 0) return;
+  if (bytes > kStagingBytes) {
+    LRP_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+    sync();
+    return;
+  }
+  if (!staging_) {
+    LRP_HIP(hipHostMalloc(&staging_, kStagingBytes, hipHostMallocDefault));
+  }
+  if (staging_used_ + bytes > kStagingBytes) sync();
+  char* slot = static_cast<char*>(staging_) + staging_used_;
+  std::memcpy(slot, src, bytes);
+  staging_used_ += (bytes + 255) & ~size_t(255);
+  LRP_HIP(hipMemcpyAsync(dst, slot, bytes, hipMemcpyHostToDevice, st));
+}
+
+void Problem::to_host(double* dst, const double* src, size_t count) {
+  LRP_HIP(hipMemcpyAsync(dst, src, sizeof(double) * count, hipMemcpyDeviceToHost, st));
+  sync();
+}
+
+
+void Problem::apply_op(int ncols, const double* X, double* Y, const std::vector<ShiftCoef>& ab, const double* Z,
+                       const std::vector<double>* zc) {
+  if (ncols <= 0) return;
+  op_w_h_.assign((size_t)4 * ncols, 0.0);
+  for (int c = 0; c < ncols; ++c) {
+    const ShiftCoef& s = ab.size() == 1 ? ab[0] : ab[c];
+    stencil_weights(s.a, s.b, h, &op_w_h_[(size_t)4 * c]);
+    op_w_h_[(size_t)4 * c + 3] = zc ? (zc->size() == 1 ? (*zc)[0] : (*zc)[c]) : 0.0;
+  }
+  op_w_.ensure(sizeof(double) * op_w_h_.size());
+  to_device(op_w_.as<double>(), op_w_h_.data(), op_w_h_.size());
+  stencil<double>(st, n, ncols, X, nx, Y, nx, Z, nx, op_w_.as<double>());
+  LRP_HIP(hipGetLastError());
+}
+
+void Problem::upload_mg_params(const std::vector<ShiftCoef>& ab) {
+  const int L = (int)lv.size();
+  const int ncols = (int)ab.size();
+  mg_param_h_.assign((size_t)L * ncols * kMgStride, 0.0);
+  double al[kMgMaxSteps], be[kMgMaxSteps];
+  for (int l = 0; l < L; ++l)
+    for (int c = 0; c < ncols; ++c) {
+      double* w = &mg_param_h_[((size_t)l * ncols + c) * kMgStride];
+      stencil_weights(ab[c].a, ab[c].b, lv[l].h, w);
+      double lo, hi;
+      smoother_interval(ab[c].a, ab[c].b * lv[l].h * lv[l].h, &lo, &hi);
+      chebyshev_coefs(lo, hi, kMgNu, al, be);
+      for (int s = 0; s < kMgNu; ++s) {
+        w[4 + 2 * s] = al[s];
+        w[5 + 2 * s] = be[s] / w[0];
+      }
+    }
+  mg_param_.ensure(sizeof(double) * mg_param_h_.size());
+  to_device(mg_param_.as<double>(), mg_param_h_.data(), mg_param_h_.size());
+}
+
+// One V-cycle with zero initial guess and kMgNu Chebyshev smoothing steps
+// before and after each coarse-grid correction; levels at or below lds_level
+// run inside a single kernel with all data in LDS.  Smoothing alternates
+// between the level's x and t buffers, writing each iterate over the one two
+// steps back, so that with an odd step count the result lands in x.
+void Problem::vcycle_zero(int ncols, const double* B, double* X) {
+  const int L = (int)lv.size();
+  const double* P = mg_param_.as<double>();
+  auto prm = [&](int l) { return P + (size_t)l * ncols * kMgStride; };
+  if (lds_level == 0) {
+    mg_coarse_lds<double>(st, lv[0].n, L, ncols, B, nx, X, nx, prm(0), kMgNu, kMgNu);
+    return;
+  }
+  // workspace: per level l >= 1: x, b, t (nx_l * ncols each); level 0: t
+  std::vector<size_t> off(L + 1, 0);
+  size_t tot = (size_t)lv[0].nx * ncols;
+  for (int l = 1; l <= lds_level; ++l) {
+    off[l] = tot;
+    tot += 3 * (size_t)lv[l].nx * ncols;
+  }
+  mg_work_.ensure(sizeof(double) * tot);
+  double* base = mg_work_.as<double>();
+  auto xw = [&](int l) { return base + off[l]; };
+  auto bw = [&](int l) { return base + off[l] + (size_t)lv[l].nx * ncols; };
+  auto tw = [&](int l) { return base + off[l] + 2 * (size_t)lv[l].nx * ncols; };
+  // down: pre-smoothing from zero, x_s in (s odd ? x : t)
+  for (int l = 0; l < lds_level; ++l) {
+    const int nl = lv[l].n;
+    const long ldl = lv[l].nx;
+    double* x = l == 0 ? X : xw(l);
+    const double* b = l == 0 ? B : bw(l);
+    double* t = l == 0 ? base : tw(l);
+    for (int s = 0; s < kMgNu; ++s) {
+      const double* xc = s == 0 ? nullptr : ((s % 2) ? x : t);
+      double* xo = (s % 2 == 0) ? x : t;
+      const double* xp = s <= 1 ? nullptr : xo;
+      mg_smooth_step<double>(st, nl, ncols, xc, xp, xo, b, ldl, prm(l), s);
+    }
+    mg_resid_restrict<double>(st, nl, ncols, x, b, ldl, bw(l + 1), lv[l + 1].nx, prm(l));
+  }
+  // coarse levels in LDS
+  mg_coarse_lds<double>(st, lv[lds_level].n, L - lds_level, ncols, bw(lds_level), lv[lds_level].nx, xw(lds_level),
+                        lv[lds_level].nx, prm(lds_level), kMgNu, kMgNu);
+  // up: t = x + P e, then post-smoothing from t, x_s in (s even ? t : x)
+  for (int l = lds_level - 1; l >= 0; --l) {
+    const int nl = lv[l].n;
+    const long ldl = lv[l].nx;
+    double* x = l == 0 ? X : xw(l);
+    const double* b = l == 0 ? B : bw(l);
+    double* t = l == 0 ? base : tw(l);
+    mg_prolong_add<double>(st, nl, ncols, xw(l + 1), lv[l + 1].nx, x, t, ldl);
+    for (int s = 0; s < kMgNu; ++s) {
+      const double* xc = (s % 2 == 0) ? t : x;
+      double* xo = (s % 2 == 0) ? x : t;
+      const double* xp = s == 0 ? nullptr : xo;
+      mg_smooth_step<double>(st, nl, ncols, xc, xp, xo, b, ldl, prm(l), s);
+    }
+  }
+}
+
+void Problem::mg_solve(int ncols, const double* B, double* X, const std::vector<ShiftCoef>& ab_in, int cycles) {
+  if (ncols <= 0) return;
+  std::vector<ShiftCoef> ab(ncols);
+  for (int c = 0; c < ncols; ++c) ab[c] = ab_in.size() == 1 ? ab_in[0] : ab_in[c];
+  upload_mg_params(ab);
+  vcycle_zero(ncols, B, X);
+  if (cycles <= 1) {
+    LRP_HIP(hipGetLastError());
+    return;
+  }
+  // residual correction: X += V(B - A X)
+  const size_t blk = (size_t)nx * ncols;
+  mg_res_.ensure(sizeof(double) * 2 * blk);
+  double* R = mg_res_.as<double>();
+  double* E = R + blk;
+  std::vector<ShiftCoef> neg(ncols);
+  for (int c = 0; c < ncols; ++c) neg[c] = {-ab[c].a, -ab[c].b};
+  std::vector<double> one(1, 1.0);
+  for (int cyc = 1; cyc < cycles; ++cyc) {
+    apply_op(ncols, X, R, neg, B, &one);
+    vcycle_zero(ncols, R, E);
+    axpby<double>(st, nx, ncols, E, nx, X, nx, 1.0, 1.0);
+  }
+  LRP_HIP(hipGetLastError());
+}
+
+void Problem::gram(int m, const double* A, int q, const double* B, std::vector<double>& C) {
+  C.assign((size_t)m * q, 0.0);
+  if (m <= 0 || q <= 0) return;
+  const int nchunk = gram_chunks(nx, m, q);
+  gram_part_.ensure(sizeof(double) * (size_t)nchunk * m * q);
+  gram_out_.ensure(sizeof(double) * (size_t)m * q);
+  ::lrp::gram<double>(st, nx, m, A, nx, q, B, nx, gram_out_.as<double>(), gram_part_.as<double>());
+  LRP_HIP(hipGetLastError());
+  to_host(C.data(), gram_out_.as<double>(), (size_t)m * q);
+}
+
+void Problem::proj(int m, const double* A, const std::vector<double>& Q, int p, double* C, double beta) {
+  if (p <= 0) return;
+  proj_q_.ensure(sizeof(double) * std::max<size_t>(1, (size_t)m * p));
+  if (m > 0) to_device(proj_q_.as<double>(), Q.data(), (size_t)m * p);
+  ::lrp::proj<double>(st, nx, m, A, nx, proj_q_.as<double>(), m, p, C, nx, beta);
+  LRP_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Low-rank space-time solve of tau K Y + M Y C^T = F1 F2^T (Sec. 6.1 eq.
+// st_pde with L = tau K; implicit Euler C = I - S).
+//
+// The spatial factor is sought in a block rational Krylov space
+// span{(tau K + p_i M)^{-1} F1}, built with multigrid solves and kept
+// M-orthonormal.  On that space the projected problem (Sec. 6.1 eq. amen_2,
+// the small system in time) is solved exactly: with Q^T M Q = I and
+// Q^T tau K Q = E diag(theta) E^T, each projected mode obeys
+// (1 + theta_i) z_k = z_{k-1} + g_k.  The result Q E Z is truncated through an
+// SVD of the small coefficient matrix (M-weighted Frobenius norm).
+// The adjoint equation tau K Y + M Y C = F is the same problem with time
+// reversed on both sides.
+// ---------------------------------------------------------------------------
+void Problem::spacetime_solve(const LowRank& F, LowRank& Y, bool adjoint) {
+  const int rf0 = F.rank;
+  Y.nx = nx;
+  Y.nt = nt;
+  if (rf0 == 0) {
+    Y.resize(nx, nt, 0);
+    return;
+  }
+  // 1. orthonormalize the source's spatial factor (eigen-based, drops null directions)
+  std::vector<double> G, w(rf0), U((size_t)rf0 * rf0);
+  gram(rf0, F.a(), rf0, F.a(), G);
+  if (!syev(rf0, G.data(), rf0, w.data(), U.data())) fail(LRPOST_EBREAKDOWN, "source Gram eigensolve failed");
+  const double wmax = std::max(w[rf0 - 1], 0.0);
+  std::vector<int> keep;
+  for (int j = rf0 - 1; j >= 0; --j)
+    if (w[j] > 1e-26 * wmax && wmax > 0) keep.push_back(j);
+  const int r1 = (int)keep.size();
+  if (r1 == 0) {
+    Y.resize(nx, nt, 0);
+    return;
+  }
+  std::vector<double> T1((size_t)rf0 * r1), F2p((size_t)nt * r1, 0.0);
+  for (int c = 0; c < r1; ++c) {
+    const int j = keep[c];
+    const double sw = std::sqrt(w[j]);
+    for (int i = 0; i < rf0; ++i) T1[(size_t)c * rf0 + i] = U[(size_t)j * rf0 + i] / sw;
+    for (int k = 0; k < nt; ++k) {
+      const int kk = adjoint ? nt - 1 - k : k;
+      double s = 0.0;
+      for (int i = 0; i < rf0; ++i) s += F.B[(size_t)i * nt + kk] * U[(size_t)j * rf0 + i];
+      F2p[(size_t)c * nt + k] = s * sw;
+    }
+  }
+  st_f_.ensure(sizeof(double) * (size_t)nx * r1);
+  double* Fb = st_f_.as<double>();
+  proj(rf0, F.a(), T1, r1, Fb, 0.0);
+
+  // 2. spatial basis
+  const int qmax = r1 * (int)poles.size();
+  st_q_.ensure(sizeof(double) * (size_t)nx * qmax);
+  st_w_.ensure(sizeof(double) * (size_t)nx * r1 * 2);
+  st_mw_.ensure(sizeof(double) * (size_t)nx * std::max(r1, 1));
+  double* Q = st_q_.as<double>();
+  double* W = st_w_.as<double>();
+  double* W2 = W + (size_t)nx * r1;
+  double* MW = st_mw_.as<double>();
+  int q = 0;
+  std::vector<double> Kt;  // q x q, leading dimension qmax
+  Kt.assign((size_t)qmax * qmax, 0.0);
+  const std::vector<ShiftCoef> Mop{{0.0, 1.0}};
+  const std::vector<ShiftCoef> Kop{{tau, 0.0}};
+  std::vector<double> C, Gw, wv, Uv;
+  for (double pole : poles) {
+    mg_solve(r1, Fb, W, {{tau, pole}}, st_cycles);
+    // reference norms before orthogonalization
+    apply_op(r1, W, MW, Mop);
+    gram(r1, W, r1, MW, Gw);
+    double ref = 0.0;
+    for (int c = 0; c < r1; ++c) ref = std::max(ref, Gw[(size_t)c * r1 + c]);
+    if (!(ref > 0)) continue;
+    // block CGS2 against Q in the M inner product
+    for (int pass = 0; pass < 2 && q > 0; ++pass) {
+      if (pass > 0) apply_op(r1, W, MW, Mop);
+      gram(q, Q, r1, MW, C);
+      for (double& x : C) x = -x;
+      proj(q, Q, C, r1, W, 1.0);
+    }
+    // SVQB twice within the block, dropping directions already in span(Q)
+    int kcols = r1;
+    double* src = W;
+    for (int pass = 0; pass < 2; ++pass) {
+      apply_op(kcols, src, MW, Mop);
+      gram(kcols, src, kcols, MW, Gw);
+      wv.assign(kcols, 0.0);
+      Uv.assign((size_t)kcols * kcols, 0.0);
+      if (!syev(kcols, Gw.data(), kcols, wv.data(), Uv.data())) fail(LRPOST_EBREAKDOWN, "basis Gram eigensolve");
+      std::vector<int> kk;
+      const double thr = pass == 0 ? 1e-22 * ref : 1e-3 * std::max(wv[kcols - 1], 0.0);
+      for (int j = kcols - 1; j >= 0; --j)
+        if (wv[j] > thr) kk.push_back(j);
+      const int kn = (int)kk.size();
+      if (kn == 0) { kcols = 0; break; }
+      std::vector<double> Tm((size_t)kcols * kn);
+      for (int c = 0; c < kn; ++c)
+        for (int i = 0; i < kcols; ++i) Tm[(size_t)c * kcols + i] = Uv[(size_t)kk[c] * kcols + i] / std::sqrt(wv[kk[c]]);
+      double* dst = pass == 0 ? W2 : Q + (size_t)q * nx;
+      proj(kcols, src, Tm, kn, dst, 0.0);
+      src = dst;
+      kcols = kn;
+    }
+    if (kcols == 0) continue;
+    // extend Kt = Q^T tau K Q by the new columns
+    double* Qn = Q + (size_t)q * nx;
+    apply_op(kcols, Qn, MW, Kop);
+    gram(q + kcols, Q, kcols, MW, C);
+    for (int c = 0; c < kcols; ++c)
+      for (int i = 0; i < q + kcols; ++i) {
+        const double v = C[(size_t)c * (q + kcols) + i];
+        Kt[(size_t)(q + c) * qmax + i] = v;
+        Kt[(size_t)i * qmax + (q + c)] = v;
+      }
+    q += kcols;
+  }
+  stats.last_basis = q;
+  if (q == 0) {
+    Y.resize(nx, nt, 0);
+    return;
+  }
+  // 3. projected problem
+  std::vector<double> theta(q), E((size_t)q * q);
+  if (!syev(q, Kt.data(), qmax, theta.data(), E.data())) fail(LRPOST_EBREAKDOWN, "projected eigensolve failed");
+  std::vector<double> S;
+  gram(q, Q, r1, Fb, S);  // q x r1
+  std::vector<double> Bh((size_t)q * r1);
+  matmul(q, r1, q, E.data(), q, true, S.data(), q, false, Bh.data(), q, 1.0, 0.0);
+  // g (nt x q) = F2p Bh^T ; recurrence per projected mode
+  std::vector<double> Gt((size_t)nt * q);
+  matmul(nt, q, r1, F2p.data(), nt, false, Bh.data(), q, true, Gt.data(), nt, 1.0, 0.0);
+  std::vector<double> Z((size_t)q * nt);
+  for (int i = 0; i < q; ++i) {
+    const double inv = 1.0 / (1.0 + theta[i]);
+    double z = 0.0;
+    for (int k = 0; k < nt; ++k) {
+      z = (z + Gt[(size_t)i * nt + k]) * inv;
+      Z[(size_t)k * q + i] = z;
+    }
+  }
+  std::vector<double> Zp((size_t)q * nt);
+  matmul(q, nt, q, E.data(), q, false, Z.data(), q, false, Zp.data(), q, 1.0, 0.0);
+  std::vector<double> s, Uz, Vz;
+  svd(q, nt, Zp.data(), q, s, Uz, Vz);
+  double tail = 0.0;
+  const int ry = truncation_rank(s, desc.trunc_tol, desc.rank_cap, &tail);
+  stats.last_tail = tail;
+  Y.resize(nx, nt, ry);
+  if (ry == 0) return;
+  std::vector<double> Cm((size_t)q * ry);
+  for (int c = 0; c < ry; ++c)
+    for (int i = 0; i < q; ++i) Cm[(size_t)c * q + i] = Uz[(size_t)c * q + i] * s[c];
+  proj(q, Q, Cm, ry, Y.a(), 0.0);
+  for (int c = 0; c < ry; ++c)
+    for (int k = 0; k < nt; ++k) {
+      const int kk = adjoint ? nt - 1 - k : k;
+      Y.B[(size_t)c * nt + kk] = Vz[(size_t)c * nt + k];
+    }
+  sync();
+}
+
+// G x = alpha^{-1} (K+M)^{-1} M P1 P2^T (precond) or H_mis x = tau M P1 P2^T (misfit),
+// with Y = forward solve of the source tau M X1 X2^T, Z = sigma^{-2} mask .* Y and
+// P the adjoint solve of Z (Sec. 6.1 eq. misfit).
+void Problem::hess_apply(const LowRank& x, LowRank& y, bool precond) {
+  stats.applies += 1;
+  y.nx = nx;
+  y.nt = nt;
+  if (x.rank == 0) {
+    y.resize(nx, nt, 0);
+    return;
+  }
+  LowRank F, Yf, Zs, P;
+  F.resize(nx, nt, x.rank);
+  apply_op(x.rank, x.a(), F.a(), {{0.0, tau}});
+  F.B = x.B;
+  spacetime_solve(F, Yf, false);
+  stats.last_rank_y = Yf.rank;
+  Zs.resize(nx, nt, Yf.rank);
+  mask_scale<double>(st, nx, Yf.rank, Yf.a(), nx, Zs.a(), nx, mask.as<uint8_t>(), 1.0 / (desc.sigma * desc.sigma));
+  Zs.B = Yf.B;
+  spacetime_solve(Zs, P, true);
+  stats.last_rank_p = P.rank;
+  y.resize(nx, nt, P.rank);
+  if (P.rank > 0) {
+    if (precond) {
+      DevMem mp;
+      mp.ensure(sizeof(double) * (size_t)nx * P.rank);
+      apply_op(P.rank, P.a(), mp.as<double>(), {{0.0, 1.0}});
+      mg_solve(P.rank, mp.as<double>(), y.a(), {{1.0, 1.0}}, prior_cycles);
+      axpby<double>(st, nx, P.rank, y.a(), nx, y.a(), nx, 1.0 / desc.alpha, 0.0);
+    } else {
+      apply_op(P.rank, P.a(), y.a(), {{0.0, tau}});
+    }
+    y.B = P.B;
+  }
+  stats.last_rank_out = y.rank;
+  sync();
+}
+
+// ---------------------------------------------------------------------------
+// Truncation (Sec. 4, after eq. lanczos2) of X = A B^T.
+//  1. Householder QR of the small temporal factor, B = Q_B R_B (host), and
+//     A' = A R_B^T on the device, so that X = A' Q_B^T with c = min(nt, rank)
+//     spatial columns.
+//  2. Orthonormalization of A' in the chosen weight by Gram products on the
+//     device and small factorizations on the host.  Well-conditioned input:
+//     CholeskyQR2.  Otherwise (the usual case for sums of many Krylov
+//     vectors): a shifted Cholesky pass (Fukaya, Kannan, Nakatsukasa,
+//     Yamamoto, Yanagisawa 2020), which maps A' to a basis of norm at most
+//     one whose numerically null directions become tiny; an eigen-based pass
+//     that drops directions of Gram eigenvalue below 1e-15 of the largest
+//     (their contribution to X is at rounding level); then CholeskyQR2.
+//  3. SVD of the small factor R_A (X = Q R_A Q_B^T); the smallest rank whose
+//     discarded tail is within tol (relative Frobenius) is kept and one
+//     projection forms the new spatial factor.
+// ---------------------------------------------------------------------------
+void Problem::truncate(LowRank& x, double tol, int cap, int weight) {
+  const int R = x.rank;
+  if (R == 0) return;
+  const std::vector<ShiftCoef> Wop = weight == 1 ? std::vector<ShiftCoef>{{0.0, 1.0}}
+                                                 : std::vector<ShiftCoef>{{1.0, 1.0}};
+  const double u = 1.1102230246251565e-16;
+  // 1. temporal QR and reduction
+  std::vector<double> QB, RB;
+  householder_qr(nt, R, x.B.data(), nt, QB, RB);
+  const int c = std::min(nt, R);
+  std::vector<double> RBt((size_t)R * c);  // R x c = RB^T
+  for (int j = 0; j < c; ++j)
+    for (int i = 0; i < R; ++i) RBt[(size_t)j * R + i] = RB[(size_t)i * c + j];
+  DevMem qa, qb, wa;
+  qa.ensure(sizeof(double) * (size_t)nx * c);
+  qb.ensure(sizeof(double) * (size_t)nx * c);
+  if (weight != 0) wa.ensure(sizeof(double) * (size_t)nx * c);
+  proj(R, x.a(), RBt, c, qa.as<double>(), 0.0);
+  double* src = qa.as<double>();
+  double* dst = qb.as<double>();
+  int kcur = c;
+  auto gram_w = [&](const double* s, int k, std::vector<double>& G) {
+    const double* ws = s;
+    if (weight != 0) {
+      apply_op(k, s, wa.as<double>(), Wop);
+      ws = wa.as<double>();
+    }
+    gram(k, s, k, ws, G);
+  };
+  // RA (kcur x c): X = src RA Q_B^T holds throughout
+  std::vector<double> RA((size_t)c * c, 0.0);
+  for (int i = 0; i < c; ++i) RA[(size_t)i * c + i] = 1.0;
+  // Each step computes (T, Rf) with src = (src T) Rf, kout columns; the last
+  // step's T is folded into the final projection instead of being applied.
+  std::vector<double> T, Rf;
+  int kout = 0;
+  auto chol_step = [&](const std::vector<double>& G, double shift) -> bool {
+    std::vector<double> Gs = G, Rk((size_t)kcur * kcur);
+    for (int i = 0; i < kcur; ++i) Gs[(size_t)i * kcur + i] += shift;
+    if (!cholesky_upper(kcur, Gs.data(), kcur, Rk.data())) return false;
+    T.assign((size_t)kcur * kcur, 0.0);
+    upper_inverse(kcur, Rk.data(), T.data());
+    Rf = Rk;
+    kout = kcur;
+    return true;
+  };
+  auto eig_step = [&](const std::vector<double>& G) {
+    std::vector<double> w(kcur), U((size_t)kcur * kcur);
+    if (!syev(kcur, G.data(), kcur, w.data(), U.data())) fail(LRPOST_EBREAKDOWN, "Gram eigensolve in truncation");
+    const double wmax = std::max(w[kcur - 1], 0.0);
+    std::vector<int> keep;
+    for (int j = kcur - 1; j >= 0; --j)
+      if (wmax > 0 && w[j] > 1e-15 * wmax) keep.push_back(j);
+    kout = (int)keep.size();
+    T.assign((size_t)kcur * std::max(kout, 1), 0.0);
+    Rf.assign((size_t)std::max(kout, 1) * kcur, 0.0);
+    for (int cc = 0; cc < kout; ++cc) {
+      const double sw = std::sqrt(w[keep[cc]]);
+      for (int i = 0; i < kcur; ++i) {
+        T[(size_t)cc * kcur + i] = U[(size_t)keep[cc] * kcur + i] / sw;
+        Rf[(size_t)i * kout + cc] = U[(size_t)keep[cc] * kcur + i] * sw;
+      }
+    }
+  };
+  auto accept = [&](bool apply_T) {
+    // RA <- Rf RA ; src <- src T (when apply_T)
+    std::vector<double> nra((size_t)std::max(kout, 1) * c, 0.0);
+    if (kout > 0) matmul(kout, c, kcur, Rf.data(), kout, false, RA.data(), kcur, false, nra.data(), kout, 1.0, 0.0);
+    RA.swap(nra);
+    if (apply_T && kout > 0) {
+      proj(kcur, src, T, kout, dst, 0.0);
+      std::swap(src, dst);
+    }
+  };
+  std::vector<double> G;
+  gram_w(src, kcur, G);
+  double tr = 0.0;
+  for (int i = 0; i < kcur; ++i) tr += G[(size_t)i * kcur + i];
+  if (!(tr > 0)) {
+    x.resize(nx, nt, 0);
+    return;
+  }
+  bool plain = chol_step(G, 0.0);
+  if (plain) {
+    double dmin = 1e300, dmax = 0.0;
+    for (int i = 0; i < kcur; ++i) {
+      dmin = std::min(dmin, Rf[(size_t)i * kcur + i]);
+      dmax = std::max(dmax, Rf[(size_t)i * kcur + i]);
+    }
+    plain = dmin >= 1e-5 * dmax;
+  }
+  int remaining_chol;
+  if (plain) {
+    remaining_chol = 1;  // CholeskyQR2: this pass plus one more
+  } else {
+    double shift = 11.0 * ((double)nx * kcur + (double)kcur * (kcur + 1)) * u * tr;
+    int attempt = 0;
+    while (!chol_step(G, shift)) {
+      if (++attempt > 20) fail(LRPOST_EBREAKDOWN, "shifted Cholesky failed in truncation");
+      shift *= 10.0;
+    }
+    accept(true);
+    kcur = kout;
+    gram_w(src, kcur, G);
+    eig_step(G);
+    if (kout == 0) { x.resize(nx, nt, 0); return; }
+    remaining_chol = 1;
+    // the eigen step is applied now; CholeskyQR2 follows
+    accept(true);
+    kcur = kout;
+    gram_w(src, kcur, G);
+    if (!chol_step(G, 0.0)) fail(LRPOST_EBREAKDOWN, "Cholesky failed after the eigen pass in truncation");
+  }
+  for (int k = 0; k < remaining_chol; ++k) {
+    accept(true);
+    kcur = kout;
+    gram_w(src, kcur, G);
+    if (!chol_step(G, 0.0)) fail(LRPOST_EBREAKDOWN, "Cholesky failed in truncation");
+  }
+  // last step: Q = src T (not applied), RA <- Rf RA
+  accept(false);
+  const int k = kout;
+  // 3. SVD of RA (k x c)
+  std::vector<double> s, Us, Vs;
+  svd(k, c, RA.data(), k, s, Us, Vs);
+  double tail = 0.0;
+  const int r = truncation_rank(s, tol, cap, &tail);
+  stats.last_tail = tail;
+  const int mn = (int)s.size();
+  std::vector<double> Cm((size_t)kcur * std::max(r, 1), 0.0);  // T (kcur x k) * Us_r diag(s_r)
+  for (int j = 0; j < r; ++j)
+    for (int i = 0; i < kcur; ++i) {
+      double t = 0.0;
+      for (int l = 0; l < k; ++l) t += T[(size_t)l * kcur + i] * Us[(size_t)j * k + l];
+      Cm[(size_t)j * kcur + i] = t * s[j];
+    }
+  std::vector<double> newB((size_t)nt * r, 0.0);
+  if (r > 0) matmul(nt, r, c, QB.data(), nt, false, Vs.data(), c, false, newB.data(), nt, 1.0, 0.0);
+  (void)mn;
+  LowRank out;
+  out.resize(nx, nt, r);
+  if (r > 0) proj(kcur, src, Cm, r, out.a(), 0.0);
+  sync();
+  x.A = std::move(out.A);
+  x.B = std::move(newB);
+  x.rank = r;
+}
+
+double Problem::p_inner(const LowRank& x, const LowRank& y) {
+  if (x.rank == 0 || y.rank == 0) return 0.0;
+  DevMem km;
+  km.ensure(sizeof(double) * (size_t)nx * y.rank);
+  apply_op(y.rank, y.a(), km.as<double>(), {{1.0, 1.0}});
+  std::vector<double> G;
+  gram(x.rank, x.a(), y.rank, km.as<double>(), G);
+  double s = 0.0;
+  for (int j = 0; j < y.rank; ++j)
+    for (int i = 0; i < x.rank; ++i) {
+      double t = 0.0;
+      for (int k = 0; k < nt; ++k) t += x.B[(size_t)i * nt + k] * y.B[(size_t)j * nt + k];
+      s += G[(size_t)j * x.rank + i] * t;
+    }
+  return desc.alpha * tau * s;
+}
+
+void Problem::lincomb(const std::vector<const LowRank*>& xs, const std::vector<double>& c, LowRank& out, double tol,
+                      int cap) {
+  constexpr int kRmax = 256;
+  std::vector<const LowRank*> items;
+  std::vector<double> coef;
+  for (size_t i = 0; i < xs.size(); ++i)
+    if (xs[i]->rank > 0 && c[i] != 0.0) { items.push_back(xs[i]); coef.push_back(c[i]); }
+  if (items.empty()) { out.resize(nx, nt, 0); return; }
+  // group so that each concatenation stays within kRmax columns
+  std::vector<std::unique_ptr<LowRank>> partial;
+  size_t i = 0;
+  while (i < items.size()) {
+    int R = 0;
+    size_t j = i;
+    while (j < items.size() && (R + items[j]->rank <= kRmax || j == i)) { R += items[j]->rank; ++j; }
+    auto acc = std::make_unique<LowRank>();
+    acc->resize(nx, nt, R);
+    int off = 0;
+    for (size_t t = i; t < j; ++t) {
+      const LowRank* v = items[t];
+      LRP_HIP(hipMemcpyAsync(acc->a() + (size_t)off * nx, v->a(), sizeof(double) * nx * v->rank,
+                             hipMemcpyDeviceToDevice, st));
+      for (int cc = 0; cc < v->rank; ++cc)
+        for (int k = 0; k < nt; ++k) acc->B[(size_t)(off + cc) * nt + k] = coef[t] * v->B[(size_t)cc * nt + k];
+      off += v->rank;
+    }
+    partial.push_back(std::move(acc));
+    i = j;
+  }
+  if (partial.size() == 1) {
+    truncate(*partial[0], tol, cap, 2);
+    out.A = std::move(partial[0]->A);
+    out.B = std::move(partial[0]->B);
+    out.rank = partial[0]->rank;
+    out.nx = nx;
+    out.nt = nt;
+    return;
+  }
+  // truncate the partial sums more tightly, then combine them
+  std::vector<const LowRank*> ps;
+  for (auto& p : partial) {
+    truncate(*p, tol * 1e-2, -1, 2);
+    ps.push_back(p.get());
+  }
+  lincomb(ps, std::vector<double>(ps.size(), 1.0), out, tol, cap);
+}
+
+}  // namespace lrp

@@ -1,0 +1,294 @@
+"""Python binding of liblrpost.so (ctypes; argument marshalling only).
+
+Every computation runs inside the HIP library.  Device memory and the HIP
+stream come from PyTorch: spatial factors are float64 CUDA tensors of shape
+(rank, nx) (row c holds column c of the column-major nx x rank factor W1);
+temporal factors are float64 NumPy arrays of shape (rank, nt) (row c holds
+column c of W2).  If the library is missing or cannot be loaded, importing a
+function that needs it raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblrpost.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "lrpost.h")
+
+LRPOST_FP64, LRPOST_MIXED = 0, 1
+LRPOST_MISFIT, LRPOST_PRECOND = 0, 1
+LRPOST_BLOCK_LANCZOS, LRPOST_RANDOMIZED = 0, 1
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "ENOCONV", -4: "EBREAKDOWN", -5: "EHIP"}
+
+
+class LrpostError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("lrpost %s (%d): %s" % (ERRORS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int32), ("nt", ctypes.c_int32), ("T", ctypes.c_double), ("alpha", ctypes.c_double),
+        ("sigma", ctypes.c_double), ("box", ctypes.c_double * 4), ("trunc_tol", ctypes.c_double),
+        ("rank_cap", ctypes.c_int32), ("precision", ctypes.c_int32), ("mg_levels", ctypes.c_int32),
+        ("seed", ctypes.c_uint64), ("hip_stream", ctypes.c_void_p),
+    ]
+
+
+class LowRankC(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("nt", ctypes.c_int32), ("rank", ctypes.c_int32), ("cap", ctypes.c_int32),
+                ("W1", ctypes.c_void_p), ("W2", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("applies", ctypes.c_int64), ("last_rank_y", ctypes.c_int32), ("last_rank_p", ctypes.c_int32),
+                ("last_rank_out", ctypes.c_int32), ("last_basis", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("last_tail", ctypes.c_double), ("last_st_resid", ctypes.c_double)]
+
+
+_lib = None
+
+
+def header_symbols():
+    """Names of the functions declared in include/lrpost.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(lrpost_\w+)\s*\(", text)))
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("liblrpost.so is not built (%s); run __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    pd = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "lrpost_create": (I, [ctypes.POINTER(Desc), ctypes.POINTER(P)]),
+        "lrpost_destroy": (I, [P]),
+        "lrpost_hess_apply": (I, [P, ctypes.POINTER(LowRankC), ctypes.POINTER(LowRankC), I]),
+        "lrpost_hess_apply_batch": (I, [P, I, ctypes.POINTER(LowRankC), ctypes.POINTER(LowRankC), I]),
+        "lrpost_spacetime_solve": (I, [P, ctypes.POINTER(LowRankC), ctypes.POINTER(LowRankC), I]),
+        "lrpost_eigensolve": (I, [P, I, I, I, ctypes.POINTER(P)]),
+        "lrpost_eig_count": (I, [P]),
+        "lrpost_eig_values": (I, [P, pd]),
+        "lrpost_eig_vector": (I, [P, I, ctypes.POINTER(LowRankC)]),
+        "lrpost_eig_vector_rank": (I, [P, I]),
+        "lrpost_eigs_free": (I, [P]),
+        "lrpost_eigs_from_pairs": (I, [P, I, pd, ctypes.POINTER(LowRankC), ctypes.POINTER(P)]),
+        "lrpost_post_variance": (I, [P, P, P, I]),
+        "lrpost_prior_variance": (I, [P, pd]),
+        "lrpost_sample": (I, [P, P, I, pd, pd]),
+        "lrpost_get_stats": (I, [P, ctypes.POINTER(Stats)]),
+        "lrpost_stencil_apply": (I, [P, I, P, P, P, pd]),
+        "lrpost_mg_solve": (I, [P, I, P, P, pd, I]),
+        "lrpost_gram": (I, [P, I, P, I, P, pd]),
+        "lrpost_truncate": (I, [P, ctypes.POINTER(LowRankC), D, I]),
+        "lrpost_last_error": (ctypes.c_char_p, []),
+        "lrpost_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        if hasattr(lib, name):
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise LrpostError(rc, _lib.lrpost_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _hptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Problem:
+    """A posterior problem on the GPU.  `desc` has the fields of synthetic.ProblemDesc."""
+
+    def __init__(self, desc, seed: int = 2, mg_levels: int = 0, stream=None):
+        torch = _torch()
+        lib = load()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        d = Desc()
+        d.N, d.nt, d.T, d.alpha, d.sigma = desc.N, desc.nt, desc.T, desc.alpha, desc.sigma
+        for i in range(4):
+            d.box[i] = desc.box[i]
+        d.trunc_tol, d.rank_cap = desc.trunc_tol, desc.rank_cap
+        d.precision = LRPOST_MIXED if getattr(desc, "precision", "fp64") == "mixed" else LRPOST_FP64
+        d.mg_levels, d.seed = mg_levels, seed
+        d.hip_stream = ctypes.c_void_p(stream.cuda_stream)
+        self._d = d
+        h = ctypes.c_void_p()
+        _check(lib.lrpost_create(ctypes.byref(d), ctypes.byref(h)))
+        self.h = h
+        self.N, self.nt = desc.N, desc.nt
+        self.n = desc.N - 1
+        self.nx = self.n * self.n
+        self.desc = desc
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.lrpost_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- helpers --------------------------------------------------------
+    def _lr_in(self, W1, W2) -> LowRankC:
+        torch = _torch()
+        r = int(W1.shape[0])
+        assert W1.dtype == torch.float64 and W1.is_cuda and W1.is_contiguous() and tuple(W1.shape) == (r, self.nx)
+        W2 = np.ascontiguousarray(W2, dtype=np.float64)
+        assert W2.shape == (r, self.nt)
+        x = LowRankC(self.nx, self.nt, r, r, ctypes.c_void_p(W1.data_ptr()), W2.ctypes.data_as(ctypes.c_void_p))
+        x._keep = (W1, W2)
+        return x
+
+    def _lr_out(self, cap: int) -> Tuple[LowRankC, object, np.ndarray]:
+        torch = _torch()
+        cap = max(int(cap), 1)
+        W1 = torch.empty((cap, self.nx), dtype=torch.float64, device="cuda")
+        W2 = np.zeros((cap, self.nt))
+        y = LowRankC(self.nx, self.nt, 0, cap, ctypes.c_void_p(W1.data_ptr()), W2.ctypes.data_as(ctypes.c_void_p))
+        return y, W1, W2
+
+    # ---- entry points ---------------------------------------------------
+    def hess_apply(self, W1, W2, which: int = LRPOST_PRECOND):
+        x = self._lr_in(W1, W2)
+        y, Y1, Y2 = self._lr_out(max(self.desc.rank_cap, 1))
+        _check(_lib.lrpost_hess_apply(self.h, ctypes.byref(x), ctypes.byref(y), which))
+        r = y.rank
+        return Y1[:r].clone(), Y2[:r].copy()
+
+    def spacetime_solve(self, W1, W2, adjoint: bool = False):
+        x = self._lr_in(W1, W2)
+        y, Y1, Y2 = self._lr_out(max(self.desc.rank_cap, 1))
+        _check(_lib.lrpost_spacetime_solve(self.h, ctypes.byref(x), ctypes.byref(y), 1 if adjoint else 0))
+        r = y.rank
+        return Y1[:r].clone(), Y2[:r].copy()
+
+    def truncate(self, W1, W2, tol: float = -1.0, weighted: bool = False):
+        x = self._lr_in(W1.clone(), W2.copy())
+        _check(_lib.lrpost_truncate(self.h, ctypes.byref(x), tol, 1 if weighted else 0))
+        r = x.rank
+        W1o, W2o = x._keep
+        return W1o[:r].clone(), W2o[:r].copy()
+
+    def stencil_apply(self, X, coef, Z=None):
+        """Y[c] = (a_c K + b_c M) X[c] + z_c Z[c]; X: (ncols, nx) float64 CUDA; coef: (ncols, 3)."""
+        torch = _torch()
+        coef = np.ascontiguousarray(coef, dtype=np.float64).reshape(-1, 3)
+        ncols = X.shape[0]
+        Y = torch.empty_like(X)
+        zp = _dptr(Z) if Z is not None else None
+        _check(_lib.lrpost_stencil_apply(self.h, ncols, _dptr(X), _dptr(Y), zp, _hptr(coef)))
+        return Y
+
+    def mg_solve(self, B, coef, cycles: int):
+        torch = _torch()
+        coef = np.ascontiguousarray(coef, dtype=np.float64).reshape(-1, 2)
+        X = torch.empty_like(B)
+        _check(_lib.lrpost_mg_solve(self.h, B.shape[0], _dptr(B), _dptr(X), _hptr(coef), cycles))
+        return X
+
+    def gram(self, A, B):
+        m, q = A.shape[0], B.shape[0]
+        C = np.zeros((q, m))  # column-major m x q == row-major q x m
+        _check(_lib.lrpost_gram(self.h, m, _dptr(A), q, _dptr(B), _hptr(C)))
+        return C.T.copy()
+
+    def prior_variance(self):
+        out = np.zeros(self.nx)
+        _check(_lib.lrpost_prior_variance(self.h, _hptr(out)))
+        return out
+
+    def eigensolve(self, k: int, method: int = LRPOST_BLOCK_LANCZOS, oversample: int = 10) -> "Eigs":
+        e = ctypes.c_void_p()
+        _check(_lib.lrpost_eigensolve(self.h, k, method, oversample, ctypes.byref(e)))
+        return Eigs(self, e)
+
+    def eigs_from_pairs(self, lam, vecs) -> "Eigs":
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        arr = (LowRankC * len(vecs))()
+        keep = []
+        for i, (W1, W2) in enumerate(vecs):
+            x = self._lr_in(W1, W2)
+            keep.append(x)
+            arr[i] = x
+        e = ctypes.c_void_p()
+        _check(_lib.lrpost_eigs_from_pairs(self.h, len(vecs), _hptr(lam), arr, ctypes.byref(e)))
+        return Eigs(self, e)
+
+    def post_variance(self, eigs: "Eigs", on_device: bool = True):
+        """diag(Gamma_post,k) as an (nt, nx) array (row t = time step t)."""
+        torch = _torch()
+        if on_device:
+            D = torch.empty((self.nt, self.nx), dtype=torch.float64, device="cuda")
+            _check(_lib.lrpost_post_variance(self.h, eigs.h, _dptr(D), 1))
+            return D
+        D = np.zeros((self.nt, self.nx))
+        _check(_lib.lrpost_post_variance(self.h, eigs.h, D.ctypes.data_as(ctypes.c_void_p), 0))
+        return D
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(_lib.lrpost_get_stats(self.h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in Stats._fields_ if f != "pad"}
+
+
+class Eigs:
+    def __init__(self, prob: Problem, h):
+        self.prob = prob
+        self.h = h
+
+    def __len__(self):
+        return _lib.lrpost_eig_count(self.h)
+
+    def values(self) -> np.ndarray:
+        k = len(self)
+        out = np.zeros(k)
+        _check(_lib.lrpost_eig_values(self.h, _hptr(out)))
+        return out
+
+    def vector(self, i: int):
+        r = _lib.lrpost_eig_vector_rank(self.h, i)
+        y, W1, W2 = self.prob._lr_out(max(r, 1))
+        _check(_lib.lrpost_eig_vector(self.h, i, ctypes.byref(y)))
+        return W1[:y.rank].clone(), W2[:y.rank].copy()
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.lrpost_eigs_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

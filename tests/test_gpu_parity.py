@@ -1,0 +1,224 @@
+"""GPU parity tests: the HIP path through the C-ABI against the FP64 oracle.
+
+Every input is seeded.  Tolerances follow the arithmetic: float64 kernels that
+compute a definition exactly (stencil, Gram) are held to rounding level; the
+iterative and truncated steps are held to their stated tolerance times a
+small factor.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import synthetic  # noqa: E402
+from oracle import fem  # noqa: E402
+from oracle.lowrank import truncate_dense  # noqa: E402
+from oracle.spacetime import Problem as OP  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1703_05638_amd import lrpost
+    lrpost.load()
+    return lrpost
+
+
+def _dev(a):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _desc(N, nt, tol=1e-10, cap=64, **kw):
+    return synthetic.ProblemDesc(N=N, nt=nt, trunc_tol=tol, rank_cap=cap, **kw)
+
+
+@pytest.mark.parametrize("N", [8, 32, 128])
+def test_stencil_matches_assembled_operators(lp, N):
+    print("case stencil N=%d" % N, flush=True)
+    d = _desc(N, 4)
+    prob = lp.Problem(d)
+    K, M = fem.assemble_kronecker(N)
+    rng = np.random.default_rng(N)
+    X = rng.standard_normal((5, prob.nx))
+    Z = rng.standard_normal((5, prob.nx))
+    coef = np.array([[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.3, 2.5, 0.0], [1e-3, 7.0, -1.0], [2.0, 0.0, 0.5]])
+    Y = prob.stencil_apply(_dev(X), coef, _dev(Z)).cpu().numpy()
+    for c in range(5):
+        ref = coef[c, 0] * (K @ X[c]) + coef[c, 1] * (M @ X[c]) + coef[c, 2] * Z[c]
+        assert np.abs(Y[c] - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()), c
+
+
+@pytest.mark.parametrize("N", [16, 64, 256])
+def test_multigrid_solve_converges_to_direct_solve(lp, N):
+    import scipy.sparse.linalg as spla
+    print("case mg N=%d" % N, flush=True)
+    d = _desc(N, 4)
+    prob = lp.Problem(d)
+    K, M = fem.assemble_kronecker(N)
+    rng = np.random.default_rng(3)
+    B = rng.standard_normal((3, prob.nx))
+    coef = np.array([[1.0, 1.0], [1.0 / 200, 1.0], [1e-3, 50.0]])
+    X = prob.mg_solve(_dev(B), coef, 14).cpu().numpy()
+    for c in range(3):
+        ref = spla.spsolve((coef[c, 0] * K + coef[c, 1] * M).tocsc(), B[c])
+        err = np.linalg.norm(X[c] - ref) / np.linalg.norm(ref)
+        assert err < 1e-11, (c, err)
+    # one cycle already contracts the error by an order of magnitude
+    X1 = prob.mg_solve(_dev(B), coef, 1).cpu().numpy()
+    ref0 = spla.spsolve((K + M).tocsc(), B[0])
+    assert np.linalg.norm(X1[0] - ref0) / np.linalg.norm(ref0) < 0.2
+
+
+def test_gram_matches_definition(lp):
+    d = _desc(128, 4)
+    prob = lp.Problem(d)
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((37, prob.nx))
+    B = rng.standard_normal((70, prob.nx))
+    C = prob.gram(_dev(A), _dev(B))
+    ref = A @ B.T
+    assert np.abs(C - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_truncation_matches_dense_svd(lp, weighted):
+    d = _desc(32, 40, tol=1e-8, cap=40)
+    prob = lp.Problem(d)
+    rng = np.random.default_rng(11)
+    r = 12
+    # factors with decaying singular values plus duplicated (dependent) columns
+    U, _ = np.linalg.qr(rng.standard_normal((prob.nx, r)))
+    V, _ = np.linalg.qr(rng.standard_normal((prob.nt, r)))
+    s = np.logspace(0, -11, r)
+    A = np.hstack([U * s, U[:, :3]])
+    B = np.hstack([V, 0.0 * V[:, :3]])
+    X = A @ B.T
+    W1, W2 = prob.truncate(_dev(A.T), B.T, 1e-8, weighted)
+    got = W1.cpu().numpy().T @ W2
+    if not weighted:
+        R1, R2 = truncate_dense(X, 1e-8)
+        assert W1.shape[0] == R1.shape[1]
+        assert np.linalg.norm(got - R1 @ R2.T) <= 1e-12 * np.linalg.norm(X)
+    assert np.linalg.norm(got - X) <= 5e-8 * np.linalg.norm(X)
+
+
+def _lowrank_input(nx, nt, r, seed, smooth=True):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((nx, r))
+    B = rng.standard_normal((nt, r))
+    if smooth:
+        B = np.cumsum(B, axis=0) / np.sqrt(nt)
+    return A, B
+
+
+@pytest.mark.parametrize("N,nt,tol", [(32, 40, 1e-10), (64, 25, 1e-6), (16, 1, 1e-10)])
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_spacetime_solve_matches_time_stepping(lp, N, nt, tol, adjoint):
+    print("case spacetime N=%d nt=%d tol=%g adjoint=%s" % (N, nt, tol, adjoint), flush=True)
+    d = _desc(N, nt, tol=tol, cap=120)
+    prob = lp.Problem(d)
+    ora = OP.from_desc(d)
+    A, B = _lowrank_input(prob.nx, nt, 3, 21 + N)
+    F = (ora.tau * (ora.M @ A)) @ B.T
+    Y1, Y2 = prob.spacetime_solve(_dev((ora.tau * (ora.M @ A)).T), B.T, adjoint)
+    got = Y1.cpu().numpy().T @ Y2
+    ref = ora.adjoint_source(F) if adjoint else ora.forward_source(F)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert err <= 20 * tol, err
+
+
+def test_zero_source_gives_zero(lp):
+    d = _desc(16, 5)
+    prob = lp.Problem(d)
+    Y1, Y2 = prob.spacetime_solve(_dev(np.zeros((2, prob.nx))), np.ones((2, 5)))
+    assert Y1.shape[0] == 0 and Y2.shape[0] == 0
+
+
+@pytest.mark.parametrize("N,nt", [(16, 10), (32, 40)])
+def test_hessian_apply_matches_oracle(lp, N, nt):
+    print("case hessian N=%d nt=%d" % (N, nt), flush=True)
+    d = _desc(N, nt, tol=1e-10, cap=64)
+    prob = lp.Problem(d)
+    ora = OP.from_desc(d)
+    A, B = _lowrank_input(prob.nx, nt, 2, 5 + N)
+    X = A @ B.T
+    for which, ref in ((lp.LRPOST_PRECOND, ora.G(X)), (lp.LRPOST_MISFIT, ora.H_mis(X))):
+        Y1, Y2 = prob.hess_apply(_dev(A.T), B.T, which)
+        got = Y1.cpu().numpy().T @ Y2
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        assert err < 1e-8, (which, err)
+
+
+def test_hessian_is_self_adjoint_in_prior_inner_product(lp):
+    d = _desc(32, 20, tol=1e-10, cap=64)
+    prob = lp.Problem(d)
+    ora = OP.from_desc(d)
+    A1, B1 = _lowrank_input(prob.nx, 20, 2, 1)
+    A2, B2 = _lowrank_input(prob.nx, 20, 3, 2)
+    G1 = prob.hess_apply(_dev(A1.T), B1.T)
+    G2 = prob.hess_apply(_dev(A2.T), B2.T)
+    gx = G1[0].cpu().numpy().T @ G1[1]
+    gy = G2[0].cpu().numpy().T @ G2[1]
+    a = ora.P_inner(gx, A2 @ B2.T)
+    b = ora.P_inner(A1 @ B1.T, gy)
+    assert abs(a - b) <= 1e-8 * abs(a)
+
+
+@pytest.fixture(scope="module")
+def tiny_golden():
+    path = os.path.join(ROOT, "tests", "golden", "tiny_fp64_oracle.npz")
+    return np.load(path)
+
+
+def test_tiny_fp64_eigenvalues_and_variance(lp, tiny_golden):
+    """32x32 mesh, nt = 40, tol 1e-10, 20 eigenpairs: 1e-8 relative against the oracle."""
+    print("case tiny eigensolve", flush=True)
+    d = synthetic.TINY_FP64
+    prob = lp.Problem(d)
+    eig = prob.eigensolve(d.k)
+    lam = eig.values()
+    ref = tiny_golden["lam"][: d.k]
+    rel = np.abs(lam - ref) / ref
+    print("eigenvalue rel err max %.3e" % rel.max(), prob.stats(), flush=True)
+    assert rel.max() < 1e-8
+    D = prob.post_variance(eig).cpu().numpy()  # (nt, nx)
+    Dref = tiny_golden["diag_k20"]  # (nx, nt)
+    relv = np.abs(D.T - Dref) / np.abs(Dref)
+    print("variance rel err max %.3e" % relv.max(), flush=True)
+    assert relv.max() < 1e-8
+    # the prior variance matches the oracle's closed form
+    assert np.allclose(prob.prior_variance(), tiny_golden["dprior"], rtol=1e-12)
+    # the rank-k posterior bounds the exact one from above
+    assert np.all(D.T >= tiny_golden["diag_exact"] * (1 - 1e-10))
+
+
+def test_truncation_of_ill_conditioned_concatenation(lp):
+    """Concatenated factors of many nearly dependent vectors (the Krylov sums of
+    Algorithm 1) are truncated to the dense-SVD result at tol 1e-10."""
+    d = _desc(32, 40, tol=1e-10, cap=40)
+    prob = lp.Problem(d)
+    rng = np.random.default_rng(17)
+    U, _ = np.linalg.qr(rng.standard_normal((prob.nx, 10)))
+    V, _ = np.linalg.qr(rng.standard_normal((prob.nt, 10)))
+    s = np.logspace(0, -12, 10)
+    parts = []
+    for j in range(12):  # 12 perturbed copies of one low-rank matrix, summed with alternating signs
+        E = 1e-3 * rng.standard_normal((10, 10))
+        parts.append(((U * s) @ (np.eye(10) + E), V * (1.0 if j % 2 == 0 else -1.0)))
+    A = np.hstack([p[0] for p in parts])
+    B = np.hstack([p[1] for p in parts])
+    X = A @ B.T
+    W1, W2 = prob.truncate(_dev(A.T), B.T, 1e-10, False)
+    got = W1.cpu().numpy().T @ W2
+    R1, R2 = truncate_dense(X, 1e-10)
+    assert W1.shape[0] == R1.shape[1]
+    assert np.linalg.norm(got - R1 @ R2.T) <= 1e-13 * np.linalg.norm(X) + 1e-12 * np.linalg.norm(R1 @ R2.T - X)
