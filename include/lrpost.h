@@ -158,6 +158,21 @@ int lrpost_sample(lrpost_problem* p, const lrpost_eigs* e, int ns, const double*
 
 int lrpost_get_stats(const lrpost_problem* p, lrpost_stats* s);
 
+/* Progress logging: level > 0 prints one JSON line per eigensolver step to
+ * stderr (step, vectors, applies, time in applies and in re-orthogonalization,
+ * worst relative Ritz residual of the wanted pairs). */
+int lrpost_set_log(lrpost_problem* p, int level);
+
+/* Kernel timing for measurement: while enabled, every launch of the
+ * multigrid smoother kernel (the dominant kernel of the apply) is bracketed
+ * by HIP events on the problem's stream, and its algorithmic traffic is
+ * counted (read x_cur, x_prev and b once, write x_new once; float64).
+ * lrpost_profile_read synchronizes, returns the launch count, the summed
+ * kernel time in ms and the counted bytes since the last read, and resets
+ * the counters. */
+int lrpost_profile(lrpost_problem* p, int enable);
+int lrpost_profile_read(lrpost_problem* p, int64_t* launches, double* total_ms, double* bytes);
+
 /* ---- building blocks, exported for kernel-level parity tests ----------
  * All pointers are DEVICE memory, float64, column-major with leading
  * dimension nx (the problem's nx). */

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "liblrpost.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels.hip", "dense.cpp", "problem.cpp", "eigen.cpp", "api.cpp"]
+SOURCES = ["kernels.hip", "dense.cpp", "gpu_dense.cpp", "problem.cpp", "eigen.cpp", "api.cpp"]
 ARCH = os.environ.get("LRPOST_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -36,7 +36,7 @@ def build(verbose=False):
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-lpthread"]
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-lrocsolver", "-lrocblas", "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))

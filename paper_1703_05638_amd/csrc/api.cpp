@@ -97,6 +97,7 @@ int lrpost_get_stats(const lrpost_problem* p, lrpost_stats* s) {
 int lrpost_hess_apply(lrpost_problem* p, const lrpost_lowrank* x, lrpost_lowrank* y, int which) {
   return guarded([&] {
     Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
     check_lr(P, x, true);
     if (!y || y->nx != P->nx || y->nt != P->nt) fail(LRPOST_EINVAL, "output shape does not match the problem");
     if (which != LRPOST_MISFIT && which != LRPOST_PRECOND) fail(LRPOST_EINVAL, "unknown apply kind");
@@ -120,6 +121,7 @@ int lrpost_hess_apply_batch(lrpost_problem* p, int nvec, const lrpost_lowrank* x
 int lrpost_spacetime_solve(lrpost_problem* p, const lrpost_lowrank* f, lrpost_lowrank* y, int adjoint) {
   return guarded([&] {
     Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
     check_lr(P, f, true);
     if (!y || y->nx != P->nx || y->nt != P->nt) fail(LRPOST_EINVAL, "output shape does not match the problem");
     LowRank fi, yo;
@@ -132,12 +134,15 @@ int lrpost_spacetime_solve(lrpost_problem* p, const lrpost_lowrank* f, lrpost_lo
 int lrpost_eigensolve(lrpost_problem* p, int k, int method, int oversample, lrpost_eigs** out) {
   return guarded([&] {
     Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
     if (!out) fail(LRPOST_EINVAL, "null output");
     *out = nullptr;
     if (k < 1) fail(LRPOST_EINVAL, "k must be >= 1");
     if (method != LRPOST_BLOCK_LANCZOS) fail(LRPOST_EINVAL, "unsupported eigensolver method");
     (void)oversample;
-    const double rtol = P->desc.precision == LRPOST_FP64 ? 1e-9 : 1e-6;
+    // Ritz residual target: the truncation tolerance bounds how far the
+    // residual of the truncated process can go down
+    const double rtol = std::max(P->desc.precision == LRPOST_FP64 ? 1e-9 : 1e-7, 0.1 * P->desc.trunc_tol);
     const int bsize = 4;
     const int maxv = std::max(8 * k, 64);
     EigResult r = block_lanczos(P, k, bsize, std::min(maxv, 800), rtol);
@@ -167,6 +172,7 @@ int lrpost_eig_vector(const lrpost_eigs* e, int i, lrpost_lowrank* v) {
   return guarded([&] {
     if (!e || !v || i < 0 || i >= (int)e->vecs.size()) fail(LRPOST_EINVAL, "bad eigenvector index");
     Problem* P = impl(e->owner);
+    PoolScope pool_scope(P->pool);
     if (v->nx != P->nx || v->nt != P->nt) fail(LRPOST_EINVAL, "output shape does not match the problem");
     store_lr(P, *e->vecs[i], v);
   });
@@ -180,6 +186,7 @@ int lrpost_eigs_from_pairs(lrpost_problem* p, int k, const double* lambda, const
                            lrpost_eigs** out) {
   return guarded([&] {
     Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
     if (!out || k < 0 || (k > 0 && (!lambda || !v))) fail(LRPOST_EINVAL, "bad arguments");
     auto e = new lrpost_eigs();
     e->owner = p;
@@ -204,6 +211,7 @@ int lrpost_eigs_from_pairs(lrpost_problem* p, int k, const double* lambda, const
 int lrpost_post_variance(lrpost_problem* p, const lrpost_eigs* e, double* diag, int on_device) {
   return guarded([&] {
     Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
     if (!e || !diag) fail(LRPOST_EINVAL, "null argument");
     const int k = (int)e->vecs.size();
     int R = 0;
@@ -245,6 +253,7 @@ int lrpost_post_variance(lrpost_problem* p, const lrpost_eigs* e, double* diag, 
 int lrpost_prior_variance(lrpost_problem* p, double* dprior) {
   return guarded([&] {
     Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
     if (!dprior) fail(LRPOST_EINVAL, "null argument");
     std::memcpy(dprior, P->dprior_h.data(), sizeof(double) * P->nx);
   });
@@ -257,10 +266,35 @@ int lrpost_sample(lrpost_problem* p, const lrpost_eigs* e, int ns, const double*
   });
 }
 
+int lrpost_set_log(lrpost_problem* p, int level) {
+  return guarded([&] { impl(p)->log_level = level; });
+}
+
+int lrpost_profile(lrpost_problem* p, int enable) {
+  return guarded([&] {
+    Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
+    P->sync();
+    P->prof_on = enable != 0;
+    P->prof_used = 0;
+    P->prof_bytes = 0.0;
+  });
+}
+
+int lrpost_profile_read(lrpost_problem* p, int64_t* launches, double* total_ms, double* bytes) {
+  return guarded([&] {
+    Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
+    if (!launches || !total_ms || !bytes) fail(LRPOST_EINVAL, "null argument");
+    P->prof_read(launches, total_ms, bytes);
+  });
+}
+
 int lrpost_stencil_apply(lrpost_problem* p, int ncols, const double* X, double* Y, const double* Z,
                          const double* coef) {
   return guarded([&] {
     Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
     if (ncols < 0 || (ncols > 0 && (!X || !Y || !coef))) fail(LRPOST_EINVAL, "bad arguments");
     std::vector<ShiftCoef> ab(ncols);
     std::vector<double> zc(ncols);
@@ -273,6 +307,7 @@ int lrpost_stencil_apply(lrpost_problem* p, int ncols, const double* X, double* 
 int lrpost_mg_solve(lrpost_problem* p, int ncols, const double* B, double* X, const double* coef, int cycles) {
   return guarded([&] {
     Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
     if (ncols < 0 || (ncols > 0 && (!B || !X || !coef)) || cycles < 1) fail(LRPOST_EINVAL, "bad arguments");
     std::vector<ShiftCoef> ab(ncols);
     for (int c = 0; c < ncols; ++c) {
@@ -287,6 +322,7 @@ int lrpost_mg_solve(lrpost_problem* p, int ncols, const double* B, double* X, co
 int lrpost_gram(lrpost_problem* p, int m, const double* A, int q, const double* B, double* C_host) {
   return guarded([&] {
     Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
     if (m < 0 || q < 0 || (m > 0 && q > 0 && (!A || !B || !C_host))) fail(LRPOST_EINVAL, "bad arguments");
     std::vector<double> C;
     P->gram(m, A, q, B, C);
@@ -297,6 +333,7 @@ int lrpost_gram(lrpost_problem* p, int m, const double* A, int q, const double* 
 int lrpost_truncate(lrpost_problem* p, lrpost_lowrank* x, double tol, int weighted) {
   return guarded([&] {
     Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
     check_lr(P, x, true);
     LowRank t;
     load_lr(P, x, t);

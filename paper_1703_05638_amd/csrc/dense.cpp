@@ -77,11 +77,12 @@ static void tridiagonalize(int n, double* A, double* d, double* e, double* Z) {
     for (int i = 0; i < m; ++i) vv += v[i] * v[i];
     if (vv == 0.0) continue;
     const double beta = 2.0 / vv;
-    // p = beta * A22 v
-    for (int i = 0; i < m; ++i) {
-      double s = 0.0;
-      for (int j = 0; j < m; ++j) s += a(k + 1 + i, k + 1 + j) * v[j];
-      p[i] = beta * s;
+    // p = beta * A22 v, accumulated column by column (contiguous access)
+    for (int i = 0; i < m; ++i) p[i] = 0.0;
+    for (int j = 0; j < m; ++j) {
+      const double vj = beta * v[j];
+      const double* col = &A[(size_t)(k + 1 + j) * n + (k + 1)];
+      for (int i = 0; i < m; ++i) p[i] += col[i] * vj;
     }
     double pv = 0.0;
     for (int i = 0; i < m; ++i) pv += p[i] * v[i];

@@ -11,6 +11,7 @@ void matmul(int m, int n, int k, const double* A, int lda, bool ta, const double
 // G = R^T R; false when G is not numerically positive definite.
 bool cholesky_upper(int n, const double* G, int ldg, double* R);
 void upper_inverse(int n, const double* R, double* Ri);
+
 // Symmetric eigensolver: eigenvalues ascending in w, eigenvectors in V (n x n).
 bool syev(int n, const double* A, int lda, double* w, double* V);
 // Thin SVD A = U diag(s) V^T (U m x r, V n x r, r = min(m, n)), s descending.

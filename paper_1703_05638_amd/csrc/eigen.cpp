@@ -2,13 +2,25 @@
 //
 // Block Lanczos with full re-orthogonalization in the P inner product: the
 // low-rank Arnoldi process of Sec. 4 Algorithm 1 applied to a self-adjoint
-// operator.  Every Krylov vector is a low-rank space-time vector; after each
-// Hessian apply the new block is orthogonalized against all stored vectors
-// (classical Gram-Schmidt, applied twice) and every linear combination is
-// truncated back to low rank (Sec. 4 eq. lanczos2 and the truncation step
-// that follows it).  Ritz pairs come from the symmetrized projected matrix.
+// operator (the truncated applies break exact symmetry; the projected matrix
+// is symmetrized before its eigensolve).
+//
+// Storage: every Krylov vector is a low-rank space-time vector whose spatial
+// factor lies in one shared spatial basis U (nx x s) with U^T (K+M) U = I,
+// so that v_k = U C_k B_k^T with a small coefficient core C_k (s x r_k) and
+// temporal factor B_k (nt x r_k).  A new apply output is absorbed by
+// projecting its spatial factor on U (classical Gram-Schmidt, twice),
+// truncating the remainder, sweeping its normalized directions against U
+// once more and appending them to U.
+// Inner products, Gram-Schmidt subtraction (the dot products and updates of
+// Algorithm 1; the factor concatenation of eq. lanczos2) and Ritz
+// combinations then act on the cores only: dense s x nt cores formed by
+// GEMMs and truncated through a small SVD.  Only absorbing and materializing
+// spatial factors touch nx-sized data.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <numeric>
 
 #include "internal.h"
@@ -31,82 +43,371 @@ double normal_draw(uint64_t seed, uint64_t stream, uint64_t idx) {
   return (idx & 1) ? r * std::sin(2.0 * M_PI * u2) : r * std::cos(2.0 * M_PI * u2);
 }
 
-// All basis vectors' spatial factors side by side on the device, so that the
-// coefficients against every stored vector come from one Gram product.
-struct Basis {
-  Problem* P;
-  DevMem A;
-  long cap_cols = 0, used = 0;
-  std::vector<long> off;
-  std::vector<std::unique_ptr<LowRank>> vec;
+// A vector in coefficient form: v = U C B^T with C (s x r, leading
+// dimension s) and B (nt x r), both on the device.
+struct CVec {
+  int s = 0, r = 0;
+  DevMem C, B;
+};
 
-  explicit Basis(Problem* p) : P(p) {}
-  int size() const { return (int)vec.size(); }
-
-  void append(std::unique_ptr<LowRank> v) {
-    const long r = v->rank;
-    if (used + r > cap_cols) {
-      long nc = std::max<long>(2 * cap_cols, used + r + 64);
-      DevMem na;
-      na.ensure(sizeof(double) * (size_t)P->nx * nc);
-      if (used > 0)
-        LRP_HIP(hipMemcpyAsync(na.p, A.p, sizeof(double) * (size_t)P->nx * used, hipMemcpyDeviceToDevice, P->st));
-      P->sync();
-      A = std::move(na);
-      cap_cols = nc;
-    }
-    if (r > 0)
-      LRP_HIP(hipMemcpyAsync(A.as<double>() + (size_t)used * P->nx, v->a(), sizeof(double) * (size_t)P->nx * r,
-                             hipMemcpyDeviceToDevice, P->st));
-    off.push_back(used);
-    used += r;
-    vec.push_back(std::move(v));
+class SharedBasis {
+ public:
+  SharedBasis(Problem* p, int s_reserve, int rcap_total)
+      : P(p), nx(p->nx), nt(p->nt), scale(p->desc.alpha * p->tau) {
+    grow_U(std::max(std::min<long>(s_reserve, nx), (long)1));
+    grow_all(std::max(rcap_total, 64));
   }
 
-  // <v_k, w>_P for every stored vector k
-  std::vector<double> coeffs(const LowRank& w) {
-    std::vector<double> c(vec.size(), 0.0);
-    if (w.rank == 0 || used == 0) return c;
-    DevMem km;
-    km.ensure(sizeof(double) * (size_t)P->nx * w.rank);
-    P->apply_op(w.rank, w.a(), km.as<double>(), {{1.0, 1.0}});
-    std::vector<double> G;
-    P->gram((int)used, A.as<double>(), w.rank, km.as<double>(), G);
-    const int nt = P->nt;
-    for (size_t k = 0; k < vec.size(); ++k) {
-      const LowRank& v = *vec[k];
-      double s = 0.0;
-      for (int j = 0; j < w.rank; ++j)
-        for (int i = 0; i < v.rank; ++i) {
-          double t = 0.0;
-          for (int q = 0; q < nt; ++q) t += v.B[(size_t)i * nt + q] * w.B[(size_t)j * nt + q];
-          s += G[(size_t)j * used + off[k] + i] * t;
+  Problem* P;
+  long nx;
+  int nt;
+  double scale;  // alpha * tau: <X, Y>_P = scale * <X, (I kron (K+M)) Y>
+  DevMem U;
+  int s = 0, s_cap = 0;
+  // basis vectors: cores padded to s_cap rows in C_all, temporal factors in B_all
+  DevMem C_all, B_all;
+  int used = 0, all_cap = 0;
+  std::vector<int> off, rk;
+  DevMem work1, work2, work3, wev, eye;
+
+  int size() const { return (int)off.size(); }
+
+  void grow_U(long need) {
+    if (need <= s_cap) return;
+    long nc = std::max<long>(need, 2L * s_cap);
+    nc = std::min<long>(nc, nx);
+    if (nc < need) fail(LRPOST_EINVAL, "shared spatial basis exceeds the number of nodes");
+    DevMem nu;
+    nu.ensure(sizeof(double) * (size_t)nx * nc);
+    if (s > 0)
+      LRP_HIP(hipMemcpyAsync(nu.p, U.p, sizeof(double) * (size_t)nx * s, hipMemcpyDeviceToDevice, P->st));
+    if (all_cap > 0) {
+      DevMem nC;
+      nC.ensure(sizeof(double) * (size_t)nc * all_cap);
+      LRP_HIP(hipMemsetAsync(nC.p, 0, sizeof(double) * (size_t)nc * all_cap, P->st));
+      if (used > 0)
+        LRP_HIP(hipMemcpy2DAsync(nC.p, sizeof(double) * nc, C_all.p, sizeof(double) * s_cap, sizeof(double) * s_cap,
+                                 used, hipMemcpyDeviceToDevice, P->st));
+      P->sync();
+      C_all = std::move(nC);
+    }
+    P->sync();
+    U = std::move(nu);
+    s_cap = (int)nc;
+  }
+
+  void grow_all(int need) {
+    if (need <= all_cap) return;
+    const int nc = std::max(need, 2 * all_cap);
+    DevMem nC, nB;
+    nC.ensure(sizeof(double) * (size_t)s_cap * nc);
+    nB.ensure(sizeof(double) * (size_t)nt * nc);
+    LRP_HIP(hipMemsetAsync(nC.p, 0, sizeof(double) * (size_t)s_cap * nc, P->st));
+    if (used > 0) {
+      LRP_HIP(hipMemcpyAsync(nC.p, C_all.p, sizeof(double) * (size_t)s_cap * used, hipMemcpyDeviceToDevice, P->st));
+      LRP_HIP(hipMemcpyAsync(nB.p, B_all.p, sizeof(double) * (size_t)nt * used, hipMemcpyDeviceToDevice, P->st));
+    }
+    P->sync();
+    C_all = std::move(nC);
+    B_all = std::move(nB);
+    all_cap = nc;
+  }
+
+  // Express a low-rank vector in the basis, extending U by the directions of
+  // its spatial factor outside span(U) (remainder truncated at a tenth of tol
+  // relative to the vector's norm).  Returns the truncated core.
+  CVec absorb(const LowRank& w, double tol, int cap) {
+    CVec out;
+    out.s = s;
+    const int rw = w.rank;
+    if (rw == 0) return out;
+    DevMem R, KR;
+    R.ensure(sizeof(double) * (size_t)nx * rw);
+    KR.ensure(sizeof(double) * (size_t)nx * rw);
+    LRP_HIP(hipMemcpyAsync(R.p, w.a(), sizeof(double) * (size_t)nx * rw, hipMemcpyDeviceToDevice, P->st));
+    // ||w||^2 in the (K+M)-weighted Frobenius norm (without alpha tau)
+    P->apply_op(rw, R.as<double>(), KR.as<double>(), {{1.0, 1.0}});
+    std::vector<double> Gw;
+    P->gram(rw, R.as<double>(), rw, KR.as<double>(), Gw);
+    double wn2 = 0.0;
+    for (int j = 0; j < rw; ++j)
+      for (int i = 0; i < rw; ++i) {
+        double t = 0.0;
+        for (int k = 0; k < nt; ++k) t += w.B[(size_t)i * nt + k] * w.B[(size_t)j * nt + k];
+        wn2 += Gw[(size_t)j * rw + i] * t;
+      }
+    const double wnorm = std::sqrt(std::max(wn2, 0.0));
+    // coefficients on U, classical Gram-Schmidt twice: G = U^T (K+M) R
+    const int s0 = s;
+    // G, G2 (s0 x rw each), then Cq and its second-pass term (s0 x rq each, rq <= rw)
+    work1.ensure(sizeof(double) * (size_t)std::max(s0, 1) * rw * 4);
+    double* G = work1.as<double>();
+    double* G2 = G + (size_t)std::max(s0, 1) * rw;
+    for (int pass = 0; pass < 2 && s0 > 0; ++pass) {
+      if (pass > 0) P->apply_op(rw, R.as<double>(), KR.as<double>(), {{1.0, 1.0}});
+      double* dst = pass == 0 ? G : G2;
+      P->gram_dev(s0, U.as<double>(), rw, KR.as<double>(), dst);
+      P->dense->scal(s0 * rw, -1.0, dst);
+      P->proj_dev(s0, U.as<double>(), dst, s0, rw, R.as<double>(), 1.0);
+      if (pass > 0) axpby<double>(P->st, (long)s0 * rw, 1, G2, (long)s0 * rw, G, (long)s0 * rw, 1.0, 1.0);
+    }
+    if (s0 > 0) P->dense->scal(s0 * rw, -1.0, G);
+    // remainder R w.B^T: truncated relative to ||w||, (K+M)-orthonormal spatial factor
+    LowRank rem;
+    rem.nx = nx;
+    rem.nt = nt;
+    rem.rank = rw;
+    rem.A = std::move(R);
+    rem.B = w.B;
+    P->truncate(rem, 0.1 * tol, cap, 2, wnorm, true);
+    const int rq = rem.rank;  // truncated remainder = Q Bq^T, Q (K+M)-orthonormal
+    std::vector<double> Bq = rem.B;
+    // The remainder can lie many orders of magnitude below ||w||, and the
+    // rounding left by the sweeps above is of order u ||w||: normalizing it
+    // would amplify that leak by ||w|| / ||remainder|| and U would lose its
+    // orthonormality step by step.  So the normalized directions are swept
+    // against U once more (twice), the removed components Cq go to the core
+    // (Q = U Cq + Q'), and Q' is re-orthonormalized through the eigenpairs
+    // of its Gram matrix (directions that were mostly inside span(U) drop).
+    double* Cq = nullptr;
+    if (rq > 0 && s0 > 0) {
+      Cq = G + (size_t)s0 * rw * 2;
+      double* C2 = Cq + (size_t)s0 * rq;
+      for (int pass = 0; pass < 2; ++pass) {
+        P->apply_op(rq, rem.a(), KR.as<double>(), {{1.0, 1.0}});
+        double* dst = pass == 0 ? Cq : C2;
+        P->gram_dev(s0, U.as<double>(), rq, KR.as<double>(), dst);
+        P->dense->scal(s0 * rq, -1.0, dst);
+        P->proj_dev(s0, U.as<double>(), dst, s0, rq, rem.a(), 1.0);
+        if (pass > 0) axpby<double>(P->st, (long)s0 * rq, 1, C2, (long)s0 * rq, Cq, (long)s0 * rq, 1.0, 1.0);
+      }
+      P->dense->scal(s0 * rq, -1.0, Cq);
+      P->apply_op(rq, rem.a(), KR.as<double>(), {{1.0, 1.0}});
+      std::vector<double> Gq;
+      P->gram(rq, rem.a(), rq, KR.as<double>(), Gq);
+      std::vector<double> e(rq), V((size_t)rq * rq);
+      if (!syev(rq, Gq.data(), rq, e.data(), V.data())) fail(LRPOST_EBREAKDOWN, "basis extension eigensolve failed");
+      std::vector<int> keep;
+      for (int j = rq - 1; j >= 0; --j)
+        if (e[j] > 0.1) keep.push_back(j);
+      const int rk2 = (int)keep.size();
+      std::vector<double> Tq((size_t)rq * std::max(rk2, 1)), Bn((size_t)nt * std::max(rk2, 1), 0.0);
+      for (int c = 0; c < rk2; ++c) {
+        const double se = std::sqrt(e[keep[c]]);
+        const double* v = V.data() + (size_t)keep[c] * rq;
+        for (int i = 0; i < rq; ++i) Tq[(size_t)c * rq + i] = v[i] / se;
+        for (int i = 0; i < rq; ++i)
+          for (int t = 0; t < nt; ++t) Bn[(size_t)c * nt + t] += Bq[(size_t)i * nt + t] * v[i] * se;
+      }
+      LowRank q2;
+      q2.resize(nx, nt, rk2);
+      if (rk2 > 0) P->proj(rq, rem.a(), Tq, rk2, q2.a(), 0.0);
+      rem.A = std::move(q2.A);
+      rem.B.assign(Bn.begin(), Bn.begin() + (size_t)nt * rk2);
+      rem.rank = rk2;
+    }
+    const int rn = rem.rank;
+    grow_U((long)s0 + rn);
+    if (rn > 0)
+      LRP_HIP(hipMemcpyAsync(U.as<double>() + (size_t)s0 * nx, rem.a(), sizeof(double) * (size_t)nx * rn,
+                             hipMemcpyDeviceToDevice, P->st));
+    s = s0 + rn;
+    // core S (s x nt) = [G w.B^T + Cq Bq^T ; rem.B^T]
+    work2.ensure(sizeof(double) * ((size_t)s * nt + (size_t)nt * (rw + rq + rn) + 64));
+    double* S = work2.as<double>();
+    double* Bd = S + (size_t)s * nt;  // nt x rw, then nt x rq, then nt x rn
+    double* Bqd = Bd + (size_t)nt * rw;
+    double* Bnd = Bqd + (size_t)nt * rq;
+    P->to_device(Bd, w.B.data(), (size_t)nt * rw);
+    if (Cq) P->to_device(Bqd, Bq.data(), (size_t)nt * rq);
+    if (rn > 0) P->to_device(Bnd, rem.B.data(), (size_t)nt * rn);
+    if (s0 > 0) P->dense->gemm(false, true, s0, nt, rw, 1.0, G, s0, Bd, nt, 0.0, S, s);
+    if (Cq) P->dense->gemm(false, true, s0, nt, rq, 1.0, Cq, s0, Bqd, nt, 1.0, S, s);
+    if (rn > 0) {
+      // bottom rn rows: rem.B^T, written as I * rem.B^T
+      eye.ensure(sizeof(double) * (size_t)rn * rn);
+      std::vector<double> id((size_t)rn * rn, 0.0);
+      for (int i = 0; i < rn; ++i) id[(size_t)i * rn + i] = 1.0;
+      P->to_device(eye.as<double>(), id.data(), id.size());
+      P->dense->gemm(false, true, rn, nt, rn, 1.0, eye.as<double>(), rn, Bnd, nt, 0.0, S + s0, s);
+    }
+    return truncate_core(S, s, s, tol, cap);
+  }
+
+  // Truncate a dense core S (rows x nt, leading dimension lds) to rank <= cap
+  // at relative Frobenius tolerance tol.  Below 1e-7 the SVD runs on the host
+  // by one-sided Jacobi (relative accuracy of small singular values);
+  // otherwise through the eigenpairs of S^T S on the device.
+  CVec truncate_core(const double* S, int rows, int lds, double tol, int cap) {
+    CVec out;
+    out.s = rows;
+    if (rows == 0) return out;
+    std::vector<double> sv;
+    int r = 0;
+    double tail = 0.0;
+    if (tol < 1e-7) {
+      std::vector<double> Sh((size_t)rows * nt);
+      LRP_HIP(hipMemcpy2DAsync(Sh.data(), sizeof(double) * rows, S, sizeof(double) * lds, sizeof(double) * rows, nt,
+                               hipMemcpyDeviceToHost, P->st));
+      P->sync();
+      std::vector<double> Us, Vs;
+      svd(rows, nt, Sh.data(), rows, sv, Us, Vs);
+      r = truncation_rank(sv, tol, cap, &tail);
+      out.r = r;
+      out.C.ensure(sizeof(double) * (size_t)rows * std::max(r, 1));
+      out.B.ensure(sizeof(double) * (size_t)nt * std::max(r, 1));
+      if (r > 0) {
+        std::vector<double> Cm((size_t)rows * r);
+        for (int j = 0; j < r; ++j)
+          for (int i = 0; i < rows; ++i) Cm[(size_t)j * rows + i] = Us[(size_t)j * rows + i] * sv[j];
+        P->to_device(out.C.as<double>(), Cm.data(), Cm.size());
+        P->to_device(out.B.as<double>(), Vs.data(), (size_t)nt * r);
+      }
+      P->sync();
+      return out;
+    }
+    work3.ensure(sizeof(double) * ((size_t)nt * nt + nt + 64));
+    double* Gt = work3.as<double>();
+    double* w = Gt + (size_t)nt * nt;
+    P->dense->gemm(true, false, nt, nt, rows, 1.0, S, lds, S, lds, 0.0, Gt, nt);
+    P->dense->syevd(nt, Gt, nt, w, wev);
+    std::vector<double> wh(nt);
+    P->to_host(wh.data(), w, nt);
+    sv.assign(nt, 0.0);
+    for (int c = 0; c < nt; ++c) sv[c] = std::sqrt(std::max(wh[nt - 1 - c], 0.0));
+    r = truncation_rank(sv, tol, cap, &tail);
+    out.r = r;
+    out.C.ensure(sizeof(double) * (size_t)rows * std::max(r, 1));
+    out.B.ensure(sizeof(double) * (size_t)nt * std::max(r, 1));
+    if (r > 0) {
+      const double* Vr = Gt + (size_t)(nt - r) * nt;  // eigenvectors of the r largest eigenvalues
+      P->dense->gemm(false, false, rows, r, nt, 1.0, S, lds, Vr, nt, 0.0, out.C.as<double>(), rows);
+      LRP_HIP(hipMemcpyAsync(out.B.p, Vr, sizeof(double) * (size_t)nt * r, hipMemcpyDeviceToDevice, P->st));
+    }
+    P->sync();
+    return out;
+  }
+
+  // Dense core S (s x nt) = sum_t tc[t] C_t B_t^T over temporaries plus
+  // sum_k coef[k] C_k B_k^T over stored vectors.
+  void combine(const std::vector<const CVec*>& tv, const std::vector<double>& tc, const std::vector<double>& coef,
+               double* S) {
+    LRP_HIP(hipMemsetAsync(S, 0, sizeof(double) * (size_t)s * nt, P->st));
+    for (size_t t = 0; t < tv.size(); ++t) {
+      const CVec& v = *tv[t];
+      if (v.r == 0 || tc[t] == 0.0) continue;
+      P->dense->gemm(false, true, v.s, nt, v.r, tc[t], v.C.as<double>(), v.s, v.B.as<double>(), nt, 1.0, S, s);
+    }
+    if (!coef.empty() && used > 0) {
+      std::vector<double> ce((size_t)used, 0.0);
+      bool any = false;
+      for (int k = 0; k < size(); ++k)
+        for (int c = 0; c < rk[k]; ++c) {
+          ce[(size_t)off[k] + c] = coef[k];
+          any = any || coef[k] != 0.0;
         }
-      c[k] = P->desc.alpha * P->tau * s;
+      if (any) {
+        work1.ensure(sizeof(double) * ((size_t)s_cap * used + used + 64));
+        double* Cs = work1.as<double>();
+        double* cd = Cs + (size_t)s_cap * used;
+        P->to_device(cd, ce.data(), ce.size());
+        P->dense->dgmm_right(s, used, C_all.as<double>(), s_cap, cd, Cs, s_cap);
+        P->dense->gemm(false, true, s, nt, used, 1.0, Cs, s_cap, B_all.as<double>(), nt, 1.0, S, s);
+      }
+    }
+  }
+
+  // <v_k, x>_P for every stored vector k.
+  std::vector<double> inner_all(const CVec& x) {
+    std::vector<double> c(size(), 0.0);
+    if (x.r == 0 || used == 0) return c;
+    work3.ensure(sizeof(double) * (size_t)used * x.r * 2);
+    double* G1 = work3.as<double>();
+    double* G2 = G1 + (size_t)used * x.r;
+    const int sm = std::min(x.s, s);
+    P->dense->gemm(true, false, used, x.r, sm, 1.0, C_all.as<double>(), s_cap, x.C.as<double>(), x.s, 0.0, G1, used);
+    P->dense->gemm(true, false, used, x.r, nt, 1.0, B_all.as<double>(), nt, x.B.as<double>(), nt, 0.0, G2, used);
+    std::vector<double> h((size_t)used * x.r * 2);
+    P->to_host(h.data(), G1, h.size());
+    const size_t half = (size_t)used * x.r;
+    for (int k = 0; k < size(); ++k) {
+      double acc = 0.0;
+      for (int j = 0; j < x.r; ++j)
+        for (int c2 = 0; c2 < rk[k]; ++c2) {
+          const size_t idx = (size_t)j * used + off[k] + c2;
+          acc += h[idx] * h[half + idx];
+        }
+      c[k] = scale * acc;
     }
     return c;
   }
+
+  double inner(const CVec& x, const CVec& y) {
+    if (x.r == 0 || y.r == 0) return 0.0;
+    const int sm = std::min(x.s, y.s);
+    work3.ensure(sizeof(double) * (size_t)x.r * y.r * 2);
+    double* G1 = work3.as<double>();
+    double* G2 = G1 + (size_t)x.r * y.r;
+    P->dense->gemm(true, false, x.r, y.r, sm, 1.0, x.C.as<double>(), x.s, y.C.as<double>(), y.s, 0.0, G1, x.r);
+    P->dense->gemm(true, false, x.r, y.r, nt, 1.0, x.B.as<double>(), nt, y.B.as<double>(), nt, 0.0, G2, x.r);
+    std::vector<double> h((size_t)x.r * y.r * 2);
+    P->to_host(h.data(), G1, h.size());
+    double acc = 0.0;
+    for (size_t i = 0; i < (size_t)x.r * y.r; ++i) acc += h[i] * h[(size_t)x.r * y.r + i];
+    return scale * acc;
+  }
+
+  void append(const CVec& v) {
+    grow_all(used + v.r);
+    if (v.r > 0) {
+      LRP_HIP(hipMemcpy2DAsync(C_all.as<double>() + (size_t)used * s_cap, sizeof(double) * s_cap, v.C.p,
+                               sizeof(double) * v.s, sizeof(double) * v.s, v.r, hipMemcpyDeviceToDevice, P->st));
+      LRP_HIP(hipMemcpyAsync(B_all.as<double>() + (size_t)used * nt, v.B.p, sizeof(double) * (size_t)nt * v.r,
+                             hipMemcpyDeviceToDevice, P->st));
+    }
+    off.push_back(used);
+    rk.push_back(v.r);
+    used += v.r;
+  }
+
+  // Spatial factor U C (nx x r) and host temporal factor.
+  void materialize(const CVec& v, LowRank& out) {
+    out.resize(nx, nt, v.r);
+    if (v.r == 0) return;
+    P->proj_dev(v.s, U.as<double>(), v.C.as<double>(), v.s, v.r, out.a(), 0.0);
+    LRP_HIP(hipMemcpyAsync(out.B.data(), v.B.p, sizeof(double) * (size_t)nt * v.r, hipMemcpyDeviceToHost, P->st));
+    P->sync();
+  }
+
+  CVec stored(int k) {
+    CVec v;
+    v.s = s;
+    v.r = rk[k];
+    v.C.ensure(sizeof(double) * (size_t)s * std::max(v.r, 1));
+    v.B.ensure(sizeof(double) * (size_t)nt * std::max(v.r, 1));
+    if (v.r > 0) {
+      LRP_HIP(hipMemcpy2DAsync(v.C.p, sizeof(double) * s, C_all.as<double>() + (size_t)off[k] * s_cap,
+                               sizeof(double) * s_cap, sizeof(double) * s, v.r, hipMemcpyDeviceToDevice, P->st));
+      LRP_HIP(hipMemcpyAsync(v.B.p, B_all.as<double>() + (size_t)off[k] * nt, sizeof(double) * (size_t)nt * v.r,
+                             hipMemcpyDeviceToDevice, P->st));
+    }
+    return v;
+  }
 };
 
-static std::unique_ptr<LowRank> copy_lr(Problem* P, const LowRank& x) {
-  auto y = std::make_unique<LowRank>();
-  y->resize(P->nx, P->nt, x.rank);
-  if (x.rank > 0)
-    LRP_HIP(hipMemcpyAsync(y->a(), x.a(), sizeof(double) * (size_t)P->nx * x.rank, hipMemcpyDeviceToDevice, P->st));
-  y->B = x.B;
-  return y;
-}
-
-// P-orthonormalize a block of vectors: returns the new vectors and the factor
-// Rb (kout x b) with W_i = sum_l V_l Rb[l, i].
-static std::vector<std::unique_ptr<LowRank>> orthonormalize_block(Problem* P, std::vector<std::unique_ptr<LowRank>>& W,
-                                                                  std::vector<double>& Rb, int& kout, double tol,
-                                                                  int cap) {
+// P-orthonormalize a block of temporaries: returns the new cores and the
+// factor Rb (kout x b) with W_i = sum_l V_l Rb[l, i].  Directions whose
+// P-norm is at most abs_drop are deflated: after the truncated applies and
+// the Gram-Schmidt sweep they carry only truncation noise (a block direction
+// of a converged invariant subspace).
+static std::vector<CVec> orthonormalize_block(SharedBasis& sb, std::vector<CVec>& W, std::vector<double>& Rb,
+                                              int& kout, double tol, int cap, double abs_drop) {
+  Problem* P = sb.P;
   const int b = (int)W.size();
   std::vector<double> Gb((size_t)b * b);
   for (int i = 0; i < b; ++i)
     for (int l = i; l < b; ++l) {
-      const double g = P->p_inner(*W[i], *W[l]);
+      const double g = sb.inner(W[i], W[l]);
       Gb[(size_t)l * b + i] = g;
       Gb[(size_t)i * b + l] = g;
     }
@@ -115,12 +416,19 @@ static std::vector<std::unique_ptr<LowRank>> orthonormalize_block(Problem* P, st
   const double wmax = std::max(w[b - 1], 0.0);
   std::vector<int> keep;
   for (int j = b - 1; j >= 0; --j)
-    if (wmax > 0 && w[j] > 1e-20 * wmax) keep.push_back(j);
+    if (wmax > 0 && w[j] > 1e-20 * wmax && w[j] > abs_drop * abs_drop) keep.push_back(j);
   kout = (int)keep.size();
+  if (P->log_level > 1) {
+    std::fprintf(stderr, "{\"block_norms\": [");
+    for (int j = b - 1; j >= 0; --j) std::fprintf(stderr, "%s%.4e", j == b - 1 ? "" : ", ", std::sqrt(std::max(w[j], 0.0)));
+    std::fprintf(stderr, "], \"abs_drop\": %.3e, \"kept\": %d}\n", abs_drop, kout);
+  }
   Rb.assign((size_t)kout * b, 0.0);
-  std::vector<std::unique_ptr<LowRank>> out;
-  std::vector<const LowRank*> xs;
-  for (auto& p : W) xs.push_back(p.get());
+  std::vector<CVec> out;
+  std::vector<const CVec*> tv;
+  for (auto& x : W) tv.push_back(&x);
+  DevMem Sbuf;
+  Sbuf.ensure(sizeof(double) * (size_t)std::max(sb.s, 1) * sb.nt);
   for (int c = 0; c < kout; ++c) {
     const int j = keep[c];
     const double sw = std::sqrt(w[j]);
@@ -129,12 +437,10 @@ static std::vector<std::unique_ptr<LowRank>> orthonormalize_block(Problem* P, st
       coef[i] = U[(size_t)j * b + i] / sw;
       Rb[(size_t)i * kout + c] = U[(size_t)j * b + i] * sw;
     }
-    auto v = std::make_unique<LowRank>();
-    P->lincomb(xs, coef, *v, tol, cap);
-    // renormalize after truncation
-    const double nv = std::sqrt(std::max(P->p_inner(*v, *v), 0.0));
-    if (nv > 0)
-      for (double& x : v->B) x /= nv;
+    sb.combine(tv, coef, {}, Sbuf.as<double>());
+    CVec v = sb.truncate_core(Sbuf.as<double>(), sb.s, sb.s, tol, cap);
+    const double nv = std::sqrt(std::max(sb.inner(v, v), 0.0));
+    if (nv > 0) P->dense->scal(P->nt * v.r, 1.0 / nv, v.B.as<double>());
     out.push_back(std::move(v));
   }
   return out;
@@ -145,77 +451,85 @@ EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rt
   const long nx = P->nx;
   const double tol = P->desc.trunc_tol;
   const int cap = P->desc.rank_cap;
+  const long s_reserve = std::min<long>(nx, (long)std::min(max_vectors, 4 * k + 16) * 16 + 64);
+  SharedBasis sb(P, (int)s_reserve, std::max(max_vectors * cap / 2, 64));
+  using clk = std::chrono::steady_clock;
+  const auto t_start = clk::now();
+  double t_apply = 0.0, t_orth = 0.0;
   // seeded start block of rank-one vectors a_j (x) b_j
-  std::vector<std::unique_ptr<LowRank>> W;
+  std::vector<CVec> W;
   {
     std::vector<double> ha((size_t)nx);
     for (int j = 0; j < bsize; ++j) {
-      auto v = std::make_unique<LowRank>();
-      v->resize(nx, nt, 1);
+      LowRank v;
+      v.resize(nx, nt, 1);
       for (long i = 0; i < nx; ++i) ha[i] = normal_draw(P->desc.seed, 2 * j, i);
-      for (int t = 0; t < nt; ++t) v->B[t] = normal_draw(P->desc.seed, 2 * j + 1, t);
-      P->to_device(v->a(), ha.data(), nx);
+      for (int t = 0; t < nt; ++t) v.B[t] = normal_draw(P->desc.seed, 2 * j + 1, t);
+      P->to_device(v.a(), ha.data(), nx);
       P->sync();
-      W.push_back(std::move(v));
+      W.push_back(sb.absorb(v, tol, cap));
     }
   }
-  Basis basis(P);
   std::vector<double> Rb;
   int kb = 0;
-  auto V = orthonormalize_block(P, W, Rb, kb, tol, cap);
+  auto V = orthonormalize_block(sb, W, Rb, kb, tol, cap, 0.0);
   if (kb == 0) fail(LRPOST_EBREAKDOWN, "start block is zero");
-  std::vector<int> block_start;  // basis index of each block's first vector
-  std::vector<int> block_size;
-  block_start.push_back(0);
-  block_size.push_back(kb);
-  for (auto& v : V) basis.append(std::move(v));
+  std::vector<int> block_start{0}, block_size{kb};
+  for (auto& v : V) sb.append(v);
   const int mmax = max_vectors;
   std::vector<double> T((size_t)mmax * mmax, 0.0);
   EigResult res;
   std::vector<double> theta, Y;
   int m_conv = 0;
+  DevMem Sbuf;
   for (int step = 0;; ++step) {
     const int j0 = block_start.back(), bj = block_size.back();
     // W = G V_j
-    std::vector<std::unique_ptr<LowRank>> Wn;
+    auto t0 = clk::now();
+    std::vector<LowRank> outs(bj);
     for (int i = 0; i < bj; ++i) {
-      auto y = std::make_unique<LowRank>();
-      P->hess_apply(*basis.vec[j0 + i], *y, true);
-      Wn.push_back(std::move(y));
+      LowRank x;
+      sb.materialize(sb.stored(j0 + i), x);
+      P->hess_apply(x, outs[i], true);
+      if (P->log_level > 1)
+        std::fprintf(stderr, "{\"apply\": %d, \"rank_in\": %d, \"rank_y\": %d, \"rank_p\": %d, \"rank_out\": %d, "
+                             "\"basis\": %d, \"tail\": %.3e}\n",
+                     j0 + i, x.rank, P->stats.last_rank_y, P->stats.last_rank_p, P->stats.last_rank_out,
+                     P->stats.last_basis, P->stats.last_tail);
     }
-    // full re-orthogonalization, classical Gram-Schmidt twice
+    auto t1 = clk::now();
+    t_apply += std::chrono::duration<double>(t1 - t0).count();
+    std::vector<CVec> Wn;
+    for (int i = 0; i < bj; ++i) Wn.push_back(sb.absorb(outs[i], tol, cap));
+    outs.clear();
+    // full re-orthogonalization, classical Gram-Schmidt twice, on the cores
     for (int pass = 0; pass < 2; ++pass) {
       for (int i = 0; i < bj; ++i) {
-        std::vector<double> c = basis.coeffs(*Wn[i]);
-        const int m = basis.size();
+        std::vector<double> c = sb.inner_all(Wn[i]);
+        const int m = sb.size();
         for (int kk = 0; kk < m; ++kk) T[(size_t)(j0 + i) * mmax + kk] += c[kk];
-        std::vector<const LowRank*> xs{Wn[i].get()};
-        std::vector<double> cf{1.0};
-        for (int kk = 0; kk < m; ++kk) {
-          xs.push_back(basis.vec[kk].get());
-          cf.push_back(-c[kk]);
-        }
-        auto out = std::make_unique<LowRank>();
-        P->lincomb(xs, cf, *out, tol * 1e-1, cap);
-        Wn[i] = std::move(out);
+        for (double& x : c) x = -x;
+        Sbuf.ensure(sizeof(double) * (size_t)sb.s * nt);
+        sb.combine({&Wn[i]}, {1.0}, c, Sbuf.as<double>());
+        Wn[i] = sb.truncate_core(Sbuf.as<double>(), sb.s, sb.s, tol * 1e-1, cap);
       }
     }
-    const int m = basis.size();
+    const int m = sb.size();
     // Ritz values of the symmetrized projected matrix
     std::vector<double> Tm((size_t)m * m);
     for (int c = 0; c < m; ++c)
-      for (int r = 0; r < m; ++r)
-        Tm[(size_t)c * m + r] = 0.5 * (T[(size_t)c * mmax + r] + T[(size_t)r * mmax + c]);
-    theta.assign(m, 0.0);
-    Y.assign((size_t)m * m, 0.0);
-    if (!syev(m, Tm.data(), m, theta.data(), Y.data())) fail(LRPOST_EBREAKDOWN, "projected eigensolve failed");
+      for (int r = 0; r < m; ++r) Tm[(size_t)c * m + r] = 0.5 * (T[(size_t)c * mmax + r] + T[(size_t)r * mmax + c]);
+    P->sym_eig(m, Tm.data(), m, theta, Y);
     // next block and its coupling factor
     std::vector<double> Rn;
     int kn = 0;
-    auto Vn = orthonormalize_block(P, Wn, Rn, kn, tol, cap);
+    double theta_max = 0.0;
+    for (double t : theta) theta_max = std::max(theta_max, std::fabs(t));
+    auto Vn = orthonormalize_block(sb, Wn, Rn, kn, tol, cap, 10.0 * tol * theta_max);
     // residual estimates ||G x - theta x||_P = ||Rn * Y[last block, s]||
     bool done = m >= k;
-    for (int s = 0; s < std::min(k, m) && done; ++s) {
+    double worst = 0.0;
+    for (int s = 0; s < std::min(k, m); ++s) {
       const int col = m - 1 - s;  // descending order
       double r2 = 0.0;
       for (int l = 0; l < kn; ++l) {
@@ -223,35 +537,73 @@ EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rt
         for (int i = 0; i < bj; ++i) t += Rn[(size_t)i * kn + l] * Y[(size_t)col * m + (j0 + i)];
         r2 += t * t;
       }
-      if (std::sqrt(r2) > rtol * std::fabs(theta[col])) done = false;
+      const double rel = std::sqrt(r2) / std::max(std::fabs(theta[col]), 1e-300);
+      worst = std::max(worst, rel);
+      if (rel > rtol) done = false;
     }
     res.steps = step + 1;
     m_conv = m;
+    t_orth += std::chrono::duration<double>(clk::now() - t1).count();
+    if (P->log_level > 1) {
+      // orthonormality of the stored basis and symmetry of the projected matrix
+      double orth = 0.0, asym = 0.0;
+      int ar = -1, ac = -1;
+      for (int a = 0; a < m; ++a) {
+        CVec va = sb.stored(a);
+        std::vector<double> ca = sb.inner_all(va);
+        for (int b2 = 0; b2 < m; ++b2) orth = std::max(orth, std::fabs(ca[b2] - (a == b2 ? 1.0 : 0.0)));
+        for (int b2 = 0; b2 < m; ++b2) {
+          const double d = std::fabs(T[(size_t)a * mmax + b2] - T[(size_t)b2 * mmax + a]);
+          if (d > asym) { asym = d; ar = b2; ac = a; }
+        }
+      }
+      if (ar >= 0)
+        std::fprintf(stderr, "{\"lanczos_asym_at\": [%d, %d], \"T_rc\": %.6e, \"T_cr\": %.6e}\n", ar, ac,
+                     T[(size_t)ac * mmax + ar], T[(size_t)ar * mmax + ac]);
+      std::vector<int> ranks;
+      for (auto& v : Vn) ranks.push_back(v.r);
+      std::fprintf(stderr, "{\"lanczos_check\": %d, \"next_block\": %d, \"orth_err\": %.3e, \"T_asym\": %.3e, "
+                           "\"next_ranks\": [%d, %d, %d, %d]}\n",
+                   step, kn, orth, asym, ranks.size() > 0 ? ranks[0] : -1, ranks.size() > 1 ? ranks[1] : -1,
+                   ranks.size() > 2 ? ranks[2] : -1, ranks.size() > 3 ? ranks[3] : -1);
+    }
+    if (P->log_level > 0) {
+      size_t fr = 0, tot = 0;
+      (void)hipMemGetInfo(&fr, &tot);
+      std::fprintf(stderr,
+                   "{\"lanczos_step\": %d, \"vectors\": %d, \"basis_s\": %d, \"applies\": %lld, \"t_apply_s\": %.3f, "
+                   "\"t_orth_s\": %.3f, \"t_total_s\": %.3f, \"worst_rel_resid\": %.3e, \"theta1\": %.10e, "
+                   "\"pool_in_use_mb\": %.1f, \"device_free_mb\": %.1f}\n",
+                   step, m, sb.s, (long long)P->stats.applies, t_apply, t_orth,
+                   std::chrono::duration<double>(clk::now() - t_start).count(), worst, theta[m - 1],
+                   P->pool->bytes_in_use() / 1048576.0, fr / 1048576.0);
+      std::fflush(stderr);
+    }
     if (done || kn == 0 || m + kn > mmax) break;
-    // store the coupling block below the diagonal: W_i = sum_l Vn_l Rn[l, i]
+    // coupling block below the diagonal: W_i = sum_l Vn_l Rn[l, i]
     for (int i = 0; i < bj; ++i)
       for (int l = 0; l < kn; ++l) T[(size_t)(j0 + i) * mmax + (m + l)] = Rn[(size_t)i * kn + l];
     block_start.push_back(m);
     block_size.push_back(kn);
-    for (auto& v : Vn) basis.append(std::move(v));
+    for (auto& v : Vn) sb.append(v);
   }
   P->stats.lanczos_steps = res.steps;
   // Ritz vectors of the k largest Ritz values
   const int m = m_conv;
   const int kk = std::min(k, m);
-  std::vector<const LowRank*> xs;
-  for (int i = 0; i < m; ++i) xs.push_back(basis.vec[i].get());
+  Sbuf.ensure(sizeof(double) * (size_t)sb.s * nt);
   for (int s = 0; s < kk; ++s) {
     const int col = m - 1 - s;
     res.lambda.push_back(theta[col]);
-    std::vector<double> coef(m);
+    std::vector<double> coef(sb.size(), 0.0);
     for (int i = 0; i < m; ++i) coef[i] = Y[(size_t)col * m + i];
-    auto v = std::make_unique<LowRank>();
-    P->lincomb(xs, coef, *v, tol, cap);
-    const double nv = std::sqrt(std::max(P->p_inner(*v, *v), 0.0));
-    if (nv > 0)
-      for (double& x : v->B) x /= nv;
-    res.vecs.push_back(std::move(v));
+    sb.combine({}, {}, coef, Sbuf.as<double>());
+    CVec v = sb.truncate_core(Sbuf.as<double>(), sb.s, sb.s, tol, cap);
+    const double nv = std::sqrt(std::max(sb.inner(v, v), 0.0));
+    if (nv > 0) P->dense->scal(nt * v.r, 1.0 / nv, v.B.as<double>());
+    auto out = std::make_unique<LowRank>();
+    sb.materialize(v, *out);
+    res.vecs.push_back(std::move(out));
   }
   return res;
 }

@@ -1,0 +1,151 @@
+// Dense helpers on the device through rocBLAS (plain GEMMs) and rocSOLVER
+// (symmetric eigensolver), used for the projected problems whose sizes are
+// the spatial basis size q or the number of Lanczos vectors (tens to about a
+// thousand).  Also the caching device allocator.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+
+#include "internal.h"
+
+namespace lrp {
+
+// ---- caching allocator ---------------------------------------------------
+// Blocks are rounded up to a power of two (at least 4 KiB) and kept in
+// per-size free lists.  A pool belongs to one problem, whose work is ordered
+// on one stream, so a block freed by one operation can be handed to the next
+// without waiting: any reuse is ordered after the earlier use on that stream.
+struct Pool::Impl {
+  std::mutex mu;
+  std::vector<std::vector<void*>> free_lists = std::vector<std::vector<void*>>(64);
+  size_t cached = 0, in_use = 0, peak = 0;
+};
+
+Pool::Pool() : impl_(new Impl) {}
+Pool::~Pool() {
+  (void)hipDeviceSynchronize();
+  for (auto& fl : impl_->free_lists)
+    for (void* p : fl) (void)hipFree(p);
+  delete impl_;
+}
+
+static int bucket_of(size_t bytes, size_t* rounded) {
+  size_t s = 4096;
+  int b = 12;
+  while (s < bytes) { s <<= 1; ++b; }
+  *rounded = s;
+  return b;
+}
+
+void* Pool::alloc(size_t bytes, size_t* got) {
+  size_t r;
+  const int b = bucket_of(bytes, &r);
+  {
+    std::lock_guard<std::mutex> lk(impl_->mu);
+    auto& fl = impl_->free_lists[b];
+    if (!fl.empty()) {
+      void* p = fl.back();
+      fl.pop_back();
+      impl_->cached -= r;
+      impl_->in_use += r;
+      impl_->peak = std::max(impl_->peak, impl_->in_use);
+      *got = r;
+      return p;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, r);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    // release cached blocks and retry once
+    trim();
+    e = hipMalloc(&p, r);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      fail(LRPOST_ENOMEM, "device allocation of " + std::to_string(r) + " bytes failed");
+    }
+  }
+  std::lock_guard<std::mutex> lk(impl_->mu);
+  impl_->in_use += r;
+  impl_->peak = std::max(impl_->peak, impl_->in_use);
+  *got = r;
+  return p;
+}
+
+void Pool::release(void* p, size_t bytes) {
+  if (!p) return;
+  size_t r;
+  const int b = bucket_of(bytes, &r);
+  std::lock_guard<std::mutex> lk(impl_->mu);
+  impl_->free_lists[b].push_back(p);
+  impl_->cached += r;
+  impl_->in_use -= r;
+}
+
+void Pool::trim() {
+  std::vector<void*> drop;
+  {
+    std::lock_guard<std::mutex> lk(impl_->mu);
+    for (auto& fl : impl_->free_lists) {
+      drop.insert(drop.end(), fl.begin(), fl.end());
+      fl.clear();
+    }
+    impl_->cached = 0;
+  }
+  if (!drop.empty()) {
+    (void)hipDeviceSynchronize();
+    for (void* p : drop) (void)hipFree(p);
+  }
+}
+
+size_t Pool::bytes_in_use() const { return impl_->in_use; }
+size_t Pool::peak_bytes() const { return impl_->peak; }
+
+// ---- rocBLAS / rocSOLVER ---------------------------------------------------
+static void rb_check(rocblas_status s, const char* what) {
+  if (s != rocblas_status_success) fail(LRPOST_EHIP, std::string(what) + " failed (rocblas status " + std::to_string((int)s) + ")");
+}
+
+GpuDense::GpuDense(hipStream_t st) {
+  rocblas_handle h;
+  rb_check(rocblas_create_handle(&h), "rocblas_create_handle");
+  rb_check(rocblas_set_stream(h, st), "rocblas_set_stream");
+  handle = h;
+}
+
+GpuDense::~GpuDense() {
+  if (handle) rocblas_destroy_handle((rocblas_handle)handle);
+}
+
+void GpuDense::gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda, const double* B,
+                    int ldb, double beta, double* C, int ldc) {
+  if (m <= 0 || n <= 0) return;
+  rb_check(rocblas_dgemm((rocblas_handle)handle, ta ? rocblas_operation_transpose : rocblas_operation_none,
+                         tb ? rocblas_operation_transpose : rocblas_operation_none, m, n, k, &alpha, A, lda, B, ldb,
+                         &beta, C, ldc),
+           "rocblas_dgemm");
+}
+
+void GpuDense::syevd(int n, double* A, int lda, double* w, DevMem& work) {
+  if (n <= 0) return;
+  work.ensure(sizeof(double) * (size_t)n + 64);
+  int* info = reinterpret_cast<int*>(work.as<char>() + sizeof(double) * (size_t)n);
+  rb_check(rocsolver_dsyevd((rocblas_handle)handle, rocblas_evect_original, rocblas_fill_upper, n, A, lda, w,
+                            work.as<double>(), info),
+           "rocsolver_dsyevd");
+}
+
+void GpuDense::dgmm_right(int m, int n, const double* A, int lda, const double* x, double* C, int ldc) {
+  if (m <= 0 || n <= 0) return;
+  rb_check(rocblas_ddgmm((rocblas_handle)handle, rocblas_side_right, m, n, A, lda, x, 1, C, ldc), "rocblas_ddgmm");
+}
+
+void GpuDense::scal(int n, double alpha, double* x) {
+  if (n <= 0) return;
+  rb_check(rocblas_dscal((rocblas_handle)handle, n, &alpha, x, 1), "rocblas_dscal");
+}
+
+}  // namespace lrp

@@ -28,17 +28,42 @@ struct Error : std::runtime_error {
       ::lrp::fail(LRPOST_EHIP, std::string(#call) + " failed: " + hipGetErrorString(e_));          \
   } while (0)
 
+// Caching device allocator of one problem (see gpu_dense.cpp).
+class Pool {
+ public:
+  Pool();
+  ~Pool();
+  void* alloc(size_t bytes, size_t* got);
+  void release(void* p, size_t bytes);
+  void trim();
+  size_t bytes_in_use() const;
+  size_t peak_bytes() const;
+
+ private:
+  struct Impl;
+  Impl* impl_;
+};
+
+// Pool that DevMem allocations on this thread draw from (set per API call).
+std::shared_ptr<Pool>& current_pool();
+struct PoolScope {
+  std::shared_ptr<Pool> prev;
+  explicit PoolScope(const std::shared_ptr<Pool>& p) : prev(current_pool()) { current_pool() = p; }
+  ~PoolScope() { current_pool() = prev; }
+};
+
 // Device allocation owned by the holder; grows on demand, never shrinks.
 struct DevMem {
   void* p = nullptr;
   size_t bytes = 0;
+  std::shared_ptr<Pool> pool;
   DevMem() = default;
   DevMem(const DevMem&) = delete;
   DevMem& operator=(const DevMem&) = delete;
-  DevMem(DevMem&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevMem(DevMem&& o) noexcept : p(o.p), bytes(o.bytes), pool(std::move(o.pool)) { o.p = nullptr; o.bytes = 0; }
   DevMem& operator=(DevMem&& o) noexcept {
     release();
-    p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0;
+    p = o.p; bytes = o.bytes; pool = std::move(o.pool); o.p = nullptr; o.bytes = 0;
     return *this;
   }
   ~DevMem() { release(); }
@@ -46,6 +71,23 @@ struct DevMem {
   void ensure(size_t nbytes);
   template <typename T>
   T* as() const { return static_cast<T*>(p); }
+};
+
+// rocBLAS GEMM and rocSOLVER symmetric eigensolver on the problem's stream.
+class GpuDense {
+ public:
+  explicit GpuDense(hipStream_t st);
+  ~GpuDense();
+  void gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda, const double* B, int ldb,
+            double beta, double* C, int ldc);
+  // A (n x n, upper triangle) -> eigenvectors in place, eigenvalues ascending in w (all device)
+  void syevd(int n, double* A, int lda, double* w, DevMem& work);
+  // C = A diag(x) (A, C: m x n device; x: n device)
+  void dgmm_right(int m, int n, const double* A, int lda, const double* x, double* C, int ldc);
+  void scal(int n, double alpha, double* x);
+
+ private:
+  void* handle = nullptr;
 };
 
 // A low-rank space-time vector X = A B^T with A on the device (nx x rank,
@@ -103,16 +145,45 @@ class Problem {
   void mg_solve(int ncols, const double* B, double* X, const std::vector<ShiftCoef>& ab, int cycles);
   // C (host, m x q) = A^T B
   void gram(int m, const double* A, int q, const double* B, std::vector<double>& C);
+  // C (device, m x q, leading dimension m) = A^T B
+  void gram_dev(int m, const double* A, int q, const double* B, double* C);
   // C = beta C + A Q (Q host m x p)
   void proj(int m, const double* A, const std::vector<double>& Q, int p, double* C, double beta);
+  // C = beta C + A Q (Q device m x p, leading dimension ldq)
+  void proj_dev(int m, const double* A, const double* Q, int ldq, int p, double* C, double beta);
+  // symmetric eigenproblem of a host matrix (ascending), on the GPU above a small size
+  void sym_eig(int n, const double* A, int lda, std::vector<double>& w, std::vector<double>& V);
+  // thin SVD of a small host matrix; `accurate` asks for relative accuracy of
+  // small singular values (one-sided Jacobi), otherwise the smaller Gram's
+  // eigenpairs are used (resolves singular values down to about 1e-8 of the largest)
+  void small_svd(int m, int n, const double* A, int lda, bool accurate, std::vector<double>& s,
+                 std::vector<double>& U, std::vector<double>& V);
+
+  std::shared_ptr<Pool> pool;
+  std::unique_ptr<GpuDense> dense;
+
+  // progress lines (JSON, stderr) of the eigensolvers when > 0
+  int log_level = 0;
+
+  // opt-in timing of the multigrid smoother kernel with HIP events
+  bool prof_on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
+  size_t prof_used = 0;
+  double prof_bytes = 0.0;
+  void smooth_step(int nl, int ncols, const double* xc, const double* xp, double* xo, const double* b, long ld,
+                   const double* prm, int s);
+  void prof_read(int64_t* launches, double* ms, double* bytes);
 
   // ---- low-rank operations ---------------------------------------------
   // Solve tau K Y + M Y C^T = F (forward) or tau K Y + M Y C = F (adjoint).
   void spacetime_solve(const LowRank& F, LowRank& Y, bool adjoint);
   // G x (precond) or H_mis x (misfit).
   void hess_apply(const LowRank& x, LowRank& y, bool precond);
-  // Truncate in place; weight 0: Euclidean, 1: M, 2: K+M.
-  void truncate(LowRank& x, double tol, int cap, int weight);
+  // Truncate in place; weight 0: Euclidean, 1: M, 2: K+M.  With ref_norm > 0
+  // the discarded tail is bounded by tol * ref_norm instead of tol * ||x||;
+  // with orth_spatial the new spatial factor is W-orthonormal and the
+  // singular values go to the temporal factor.
+  void truncate(LowRank& x, double tol, int cap, int weight, double ref_norm = 0.0, bool orth_spatial = false);
   // P inner product alpha tau <X, (I kron (K+M)) Y>.
   double p_inner(const LowRank& x, const LowRank& y);
   // sum_i c_i x_i as a truncated low-rank vector (P-weighted truncation).
@@ -135,7 +206,7 @@ class Problem {
   void vcycle_zero(int ncols, const double* B, double* X);
   void upload_mg_params(const std::vector<ShiftCoef>& ab);
   // space-time solver workspaces
-  DevMem st_q_, st_w_, st_mw_, st_f_;
+  DevMem st_q_, st_w_, st_mw_, st_f_, st_kt_, st_small_, eig_work_;
 };
 
 void smoother_interval(double a, double bh2, double* lo, double* hi);

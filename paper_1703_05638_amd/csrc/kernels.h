@@ -46,6 +46,8 @@ void axpby(hipStream_t st, long nx, int ncols, const T* X, long ldx, T* Y, long 
 void d2f(hipStream_t st, long n, const double* x, float* y);
 void f2d(hipStream_t st, long n, const float* x, double* y);
 
+void time_recurrence(hipStream_t st, int q, int nt, const double* theta, const double* G, double* Z);
+
 void post_variance(hipStream_t st, long nx, int nt, int k, const int* seg, const double* dcoef, const double* A,
                    long lda, const double* Bt, int R, const double* dprior, double* D, long ldd);
 

@@ -575,6 +575,28 @@ void f2d(hipStream_t st, long n, const float* x, double* y) {
 }
 
 // ---------------------------------------------------------------------------
+// Projected time stepping: for every projected spatial mode i (Q^T M Q = I,
+// Q^T tau K Q = E diag(theta) E^T) the implicit-Euler recurrence
+// (1 + theta_i) z_k = z_{k-1} + g_k, z_0 = 0.  G: nt x q (column i = mode i),
+// Z: q x nt.
+// ---------------------------------------------------------------------------
+__global__ void k_time_recurrence(int q, int nt, const double* __restrict__ theta, const double* __restrict__ G,
+                                  double* __restrict__ Z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= q) return;
+  const double inv = 1.0 / (1.0 + theta[i]);
+  double z = 0.0;
+  for (int k = 0; k < nt; ++k) {
+    z = (z + G[(long)i * nt + k]) * inv;
+    Z[(long)k * q + i] = z;
+  }
+}
+void time_recurrence(hipStream_t st, int q, int nt, const double* theta, const double* G, double* Z) {
+  if (q <= 0) return;
+  hipLaunchKernelGGL(k_time_recurrence, dim3((q + 63) / 64), dim3(64), 0, st, q, nt, theta, G, Z);
+}
+
+// ---------------------------------------------------------------------------
 // Posterior variance: D[x, t] = dprior[x] - sum_i d_i (sum_c A_i[x, c] B_i[t, c])^2
 // The eigenvector factors are packed: A (nx x R) with all vectors' spatial
 // columns side by side, Bt (R x nt) the temporal factors transposed, and

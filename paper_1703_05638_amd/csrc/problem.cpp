@@ -11,8 +11,16 @@ namespace lrp {
 
 void fail(int code, const std::string& msg) { throw Error(code, msg); }
 
+std::shared_ptr<Pool>& current_pool() {
+  static thread_local std::shared_ptr<Pool> pool;
+  return pool;
+}
+
 void DevMem::release() {
-  if (p) (void)hipFree(p);
+  if (p) {
+    if (pool) pool->release(p, bytes);
+    else (void)hipFree(p);
+  }
   p = nullptr;
   bytes = 0;
 }
@@ -20,6 +28,11 @@ void DevMem::release() {
 void DevMem::ensure(size_t nbytes) {
   if (nbytes <= bytes) return;
   release();
+  if (!pool) pool = current_pool();
+  if (pool) {
+    p = pool->alloc(std::max<size_t>(nbytes, 256), &bytes);
+    return;
+  }
   size_t want = std::max<size_t>(nbytes, 256);
   hipError_t e = hipMalloc(&p, want);
   if (e != hipSuccess) {
@@ -92,6 +105,8 @@ Problem::Problem(const lrpost_problem_desc& d) : desc(d) {
   if (!(d.trunc_tol > 0) || !(d.trunc_tol < 1)) fail(LRPOST_EINVAL, "trunc_tol must lie in (0, 1)");
   if (d.rank_cap < 1) fail(LRPOST_EINVAL, "rank_cap must be >= 1");
   if (d.precision != LRPOST_FP64 && d.precision != LRPOST_MIXED) fail(LRPOST_EINVAL, "unknown precision");
+  pool = std::make_shared<Pool>();
+  PoolScope scope(pool);
   N = d.N;
   n = N - 1;
   nt = d.nt;
@@ -99,6 +114,7 @@ Problem::Problem(const lrpost_problem_desc& d) : desc(d) {
   h = 1.0 / N;
   tau = d.T / nt;
   st = (hipStream_t)d.hip_stream;
+  dense = std::make_unique<GpuDense>(st);
   // multigrid hierarchy: n, (n-1)/2, ..., 1
   for (int m = n; m >= 1; m = (m - 1) / 2) {
     lv.push_back({m, (long)m * m, 1.0 / (m + 1)});
@@ -151,11 +167,12 @@ Problem::Problem(const lrpost_problem_desc& d) : desc(d) {
   LRP_HIP(hipMemcpy(dprior.p, dprior_h.data(), sizeof(double) * nx, hipMemcpyHostToDevice));
   // inner-solver settings from the truncation tolerance: poles of the spatial
   // rational Krylov basis log-spaced over the time-step scaled spectrum, and
-  // enough V-cycles (contraction about 0.08 per cycle) to resolve it
+  // enough V-cycles to resolve it
   const double lt = -std::log10(d.trunc_tol);
   st_poles = std::max(4, std::min(24, (int)std::lround(1.5 * lt) + 1));
-  st_cycles = std::max(3, (int)std::ceil((lt + 1.0) / 1.1) + 1);
-  prior_cycles = std::max(4, (int)std::ceil((lt + 2.0) / 1.1) + 1);
+  // the Chebyshev-smoothed V-cycle contracts the error by about 0.05 per cycle
+  st_cycles = std::max(3, (int)std::ceil((lt + 2.0) / 1.25));
+  prior_cycles = std::max(4, (int)std::ceil((lt + 3.0) / 1.25));
   const double lam_min = 2.0 * M_PI * M_PI;
   const double lam_max = 24.0 / (h * h);
   const double plo = std::min(1e-2, 0.5 * tau * lam_min);
@@ -169,6 +186,10 @@ Problem::Problem(const lrpost_problem_desc& d) : desc(d) {
 Problem::~Problem() {
   if (st) (void)hipStreamSynchronize(st);
   else (void)hipDeviceSynchronize();
+  for (auto& ev : prof_ev) {
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
   if (staging_) (void)hipHostFree(staging_);
 }
 
@@ -275,7 +296,7 @@ void Problem::vcycle_zero(int ncols, const double* B, double* X) {
       const double* xc = s == 0 ? nullptr : ((s % 2) ? x : t);
       double* xo = (s % 2 == 0) ? x : t;
       const double* xp = s <= 1 ? nullptr : xo;
-      mg_smooth_step<double>(st, nl, ncols, xc, xp, xo, b, ldl, prm(l), s);
+      smooth_step(nl, ncols, xc, xp, xo, b, ldl, prm(l), s);
     }
     mg_resid_restrict<double>(st, nl, ncols, x, b, ldl, bw(l + 1), lv[l + 1].nx, prm(l));
   }
@@ -294,9 +315,47 @@ void Problem::vcycle_zero(int ncols, const double* B, double* X) {
       const double* xc = (s % 2 == 0) ? t : x;
       double* xo = (s % 2 == 0) ? x : t;
       const double* xp = s == 0 ? nullptr : xo;
-      mg_smooth_step<double>(st, nl, ncols, xc, xp, xo, b, ldl, prm(l), s);
+      smooth_step(nl, ncols, xc, xp, xo, b, ldl, prm(l), s);
     }
   }
+}
+
+// One Chebyshev smoother step; with profiling on, bracketed by HIP events on
+// the problem's stream and credited with its algorithmic traffic: read xc,
+// xp and b once, write xo once (neighbour reads of xc are cache hits).
+void Problem::smooth_step(int nl, int ncols, const double* xc, const double* xp, double* xo, const double* b, long ld,
+                          const double* prm, int s) {
+  if (!prof_on) {
+    mg_smooth_step<double>(st, nl, ncols, xc, xp, xo, b, ld, prm, s);
+    return;
+  }
+  if (prof_used == prof_ev.size()) {
+    hipEvent_t a, e;
+    LRP_HIP(hipEventCreate(&a));
+    LRP_HIP(hipEventCreate(&e));
+    prof_ev.push_back({a, e});
+  }
+  auto& ev = prof_ev[prof_used++];
+  LRP_HIP(hipEventRecord(ev.first, st));
+  mg_smooth_step<double>(st, nl, ncols, xc, xp, xo, b, ld, prm, s);
+  LRP_HIP(hipEventRecord(ev.second, st));
+  const int streams = 2 + (xc ? 1 : 0) + (xp ? 1 : 0);
+  prof_bytes += (double)streams * sizeof(double) * (double)nl * nl * ncols;
+}
+
+void Problem::prof_read(int64_t* launches, double* ms, double* bytes) {
+  sync();
+  double tot = 0.0;
+  for (size_t i = 0; i < prof_used; ++i) {
+    float t = 0.0f;
+    LRP_HIP(hipEventElapsedTime(&t, prof_ev[i].first, prof_ev[i].second));
+    tot += t;
+  }
+  *launches = (int64_t)prof_used;
+  *ms = tot;
+  *bytes = prof_bytes;
+  prof_used = 0;
+  prof_bytes = 0.0;
 }
 
 void Problem::mg_solve(int ncols, const double* B, double* X, const std::vector<ShiftCoef>& ab_in, int cycles) {
@@ -342,6 +401,83 @@ void Problem::proj(int m, const double* A, const std::vector<double>& Q, int p, 
   if (m > 0) to_device(proj_q_.as<double>(), Q.data(), (size_t)m * p);
   ::lrp::proj<double>(st, nx, m, A, nx, proj_q_.as<double>(), m, p, C, nx, beta);
   LRP_HIP(hipGetLastError());
+}
+
+void Problem::gram_dev(int m, const double* A, int q, const double* B, double* C) {
+  if (m <= 0 || q <= 0) return;
+  const int nchunk = gram_chunks(nx, m, q);
+  gram_part_.ensure(sizeof(double) * (size_t)nchunk * m * q);
+  ::lrp::gram<double>(st, nx, m, A, nx, q, B, nx, C, gram_part_.as<double>());
+  LRP_HIP(hipGetLastError());
+}
+
+void Problem::proj_dev(int m, const double* A, const double* Q, int ldq, int p, double* C, double beta) {
+  if (p <= 0) return;
+  ::lrp::proj<double>(st, nx, m, A, nx, Q, ldq, p, C, nx, beta);
+  LRP_HIP(hipGetLastError());
+}
+
+void Problem::sym_eig(int nn, const double* A, int lda, std::vector<double>& w, std::vector<double>& V) {
+  w.assign(nn, 0.0);
+  V.assign((size_t)nn * nn, 0.0);
+  if (nn == 0) return;
+  if (nn <= 64) {
+    if (!syev(nn, A, lda, w.data(), V.data())) fail(LRPOST_EBREAKDOWN, "symmetric eigensolve failed");
+    return;
+  }
+  std::vector<double> tmp((size_t)nn * nn);
+  for (int j = 0; j < nn; ++j)
+    for (int i = 0; i < nn; ++i) tmp[(size_t)j * nn + i] = 0.5 * (A[(size_t)j * lda + i] + A[(size_t)i * lda + j]);
+  st_small_.ensure(sizeof(double) * ((size_t)nn * nn + nn));
+  double* dA = st_small_.as<double>();
+  double* dw = dA + (size_t)nn * nn;
+  to_device(dA, tmp.data(), tmp.size());
+  dense->syevd(nn, dA, nn, dw, eig_work_);
+  LRP_HIP(hipMemcpyAsync(V.data(), dA, sizeof(double) * (size_t)nn * nn, hipMemcpyDeviceToHost, st));
+  LRP_HIP(hipMemcpyAsync(w.data(), dw, sizeof(double) * nn, hipMemcpyDeviceToHost, st));
+  sync();
+}
+
+void Problem::small_svd(int m, int nn, const double* A, int lda, bool accurate, std::vector<double>& s,
+                        std::vector<double>& U, std::vector<double>& V) {
+  const int k = std::min(m, nn);
+  if (accurate || k <= 48) {
+    svd(m, nn, A, lda, s, U, V);
+    return;
+  }
+  // eigenpairs of the smaller Gram matrix
+  const bool right = nn <= m;  // A^T A (nn x nn) when nn <= m
+  const int g = right ? nn : m;
+  std::vector<double> G((size_t)g * g);
+  if (right) matmul(g, g, m, A, lda, true, A, lda, false, G.data(), g, 1.0, 0.0);
+  else matmul(g, g, nn, A, lda, false, A, lda, true, G.data(), g, 1.0, 0.0);
+  std::vector<double> w, E;
+  sym_eig(g, G.data(), g, w, E);
+  s.assign(k, 0.0);
+  U.assign((size_t)m * k, 0.0);
+  V.assign((size_t)nn * k, 0.0);
+  for (int c = 0; c < k; ++c) {
+    const int j = g - 1 - c;  // descending
+    const double sv = std::sqrt(std::max(w[j], 0.0));
+    s[c] = sv;
+    if (right) {
+      for (int i = 0; i < nn; ++i) V[(size_t)c * nn + i] = E[(size_t)j * g + i];
+      if (sv > 0)
+        for (int i = 0; i < m; ++i) {
+          double t = 0.0;
+          for (int l = 0; l < nn; ++l) t += A[(size_t)l * lda + i] * E[(size_t)j * g + l];
+          U[(size_t)c * m + i] = t / sv;
+        }
+    } else {
+      for (int i = 0; i < m; ++i) U[(size_t)c * m + i] = E[(size_t)j * g + i];
+      if (sv > 0)
+        for (int i = 0; i < nn; ++i) {
+          double t = 0.0;
+          for (int l = 0; l < m; ++l) t += A[(size_t)i * lda + l] * E[(size_t)j * g + l];
+          V[(size_t)c * nn + i] = t / sv;
+        }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -395,23 +531,35 @@ void Problem::spacetime_solve(const LowRank& F, LowRank& Y, bool adjoint) {
   double* Fb = st_f_.as<double>();
   proj(rf0, F.a(), T1, r1, Fb, 0.0);
 
-  // 2. spatial basis
-  const int qmax = r1 * (int)poles.size();
+  // 2. spatial basis: all pole solves in one batched multigrid solve with
+  // per-column shifts, then block-by-block M-orthonormalization
+  const int npol = (int)poles.size();
+  const int qmax = r1 * npol;
   st_q_.ensure(sizeof(double) * (size_t)nx * qmax);
-  st_w_.ensure(sizeof(double) * (size_t)nx * r1 * 2);
+  st_w_.ensure(sizeof(double) * (size_t)nx * qmax * 2 + sizeof(double) * (size_t)nx * r1);
   st_mw_.ensure(sizeof(double) * (size_t)nx * std::max(r1, 1));
   double* Q = st_q_.as<double>();
-  double* W = st_w_.as<double>();
-  double* W2 = W + (size_t)nx * r1;
+  double* Wall = st_w_.as<double>();
+  double* Brep = Wall + (size_t)nx * qmax;
+  double* W2 = Brep + (size_t)nx * qmax;
   double* MW = st_mw_.as<double>();
+  {
+    std::vector<ShiftCoef> ab((size_t)qmax);
+    for (int i = 0; i < npol; ++i) {
+      LRP_HIP(hipMemcpyAsync(Brep + (size_t)i * r1 * nx, Fb, sizeof(double) * (size_t)nx * r1,
+                             hipMemcpyDeviceToDevice, st));
+      for (int c = 0; c < r1; ++c) ab[(size_t)i * r1 + c] = {tau, poles[i]};
+    }
+    mg_solve(qmax, Brep, Wall, ab, st_cycles);
+  }
   int q = 0;
-  std::vector<double> Kt;  // q x q, leading dimension qmax
-  Kt.assign((size_t)qmax * qmax, 0.0);
+  st_kt_.ensure(sizeof(double) * (size_t)qmax * qmax);
+  double* Kt = st_kt_.as<double>();  // q x q projected tau K, leading dimension qmax (device)
   const std::vector<ShiftCoef> Mop{{0.0, 1.0}};
   const std::vector<ShiftCoef> Kop{{tau, 0.0}};
   std::vector<double> C, Gw, wv, Uv;
-  for (double pole : poles) {
-    mg_solve(r1, Fb, W, {{tau, pole}}, st_cycles);
+  for (int ip = 0; ip < npol; ++ip) {
+    double* W = Wall + (size_t)ip * r1 * nx;
     // reference norms before orthogonalization
     apply_op(r1, W, MW, Mop);
     gram(r1, W, r1, MW, Gw);
@@ -425,7 +573,11 @@ void Problem::spacetime_solve(const LowRank& F, LowRank& Y, bool adjoint) {
       for (double& x : C) x = -x;
       proj(q, Q, C, r1, W, 1.0);
     }
-    // SVQB twice within the block, dropping directions already in span(Q)
+    // within the block: two eigen-based orthonormalization passes in the M
+    // inner product (SVQB, Stathopoulos and Wu 2002), dropping directions whose
+    // M-norm after the projection is below 1e-11 of the block's original
+    // scale (already in span(Q)).  A Gram-based Cholesky cannot tell such
+    // directions from rounding noise, so it is not used here.
     int kcols = r1;
     double* src = W;
     for (int pass = 0; pass < 2; ++pass) {
@@ -435,9 +587,8 @@ void Problem::spacetime_solve(const LowRank& F, LowRank& Y, bool adjoint) {
       Uv.assign((size_t)kcols * kcols, 0.0);
       if (!syev(kcols, Gw.data(), kcols, wv.data(), Uv.data())) fail(LRPOST_EBREAKDOWN, "basis Gram eigensolve");
       std::vector<int> kk;
-      const double thr = pass == 0 ? 1e-22 * ref : 1e-3 * std::max(wv[kcols - 1], 0.0);
       for (int j = kcols - 1; j >= 0; --j)
-        if (wv[j] > thr) kk.push_back(j);
+        if (wv[j] > 1e-22 * ref) kk.push_back(j);
       const int kn = (int)kk.size();
       if (kn == 0) { kcols = 0; break; }
       std::vector<double> Tm((size_t)kcols * kn);
@@ -449,16 +600,14 @@ void Problem::spacetime_solve(const LowRank& F, LowRank& Y, bool adjoint) {
       kcols = kn;
     }
     if (kcols == 0) continue;
-    // extend Kt = Q^T tau K Q by the new columns
+    // extend Kt = Q^T tau K Q by the new columns (upper triangle suffices)
     double* Qn = Q + (size_t)q * nx;
     apply_op(kcols, Qn, MW, Kop);
-    gram(q + kcols, Q, kcols, MW, C);
-    for (int c = 0; c < kcols; ++c)
-      for (int i = 0; i < q + kcols; ++i) {
-        const double v = C[(size_t)c * (q + kcols) + i];
-        Kt[(size_t)(q + c) * qmax + i] = v;
-        Kt[(size_t)i * qmax + (q + c)] = v;
-      }
+    gram_out_.ensure(sizeof(double) * (size_t)(q + kcols) * kcols);
+    gram_dev(q + kcols, Q, kcols, MW, gram_out_.as<double>());
+    LRP_HIP(hipMemcpy2DAsync(Kt + (size_t)q * qmax, sizeof(double) * qmax, gram_out_.as<double>(),
+                             sizeof(double) * (q + kcols), sizeof(double) * (q + kcols), kcols,
+                             hipMemcpyDeviceToDevice, st));
     q += kcols;
   }
   stats.last_basis = q;
@@ -466,43 +615,79 @@ void Problem::spacetime_solve(const LowRank& F, LowRank& Y, bool adjoint) {
     Y.resize(nx, nt, 0);
     return;
   }
-  // 3. projected problem
-  std::vector<double> theta(q), E((size_t)q * q);
-  if (!syev(q, Kt.data(), qmax, theta.data(), E.data())) fail(LRPOST_EBREAKDOWN, "projected eigensolve failed");
-  std::vector<double> S;
-  gram(q, Q, r1, Fb, S);  // q x r1
-  std::vector<double> Bh((size_t)q * r1);
-  matmul(q, r1, q, E.data(), q, true, S.data(), q, false, Bh.data(), q, 1.0, 0.0);
-  // g (nt x q) = F2p Bh^T ; recurrence per projected mode
-  std::vector<double> Gt((size_t)nt * q);
-  matmul(nt, q, r1, F2p.data(), nt, false, Bh.data(), q, true, Gt.data(), nt, 1.0, 0.0);
-  std::vector<double> Z((size_t)q * nt);
-  for (int i = 0; i < q; ++i) {
-    const double inv = 1.0 / (1.0 + theta[i]);
-    double z = 0.0;
-    for (int k = 0; k < nt; ++k) {
-      z = (z + Gt[(size_t)i * nt + k]) * inv;
-      Z[(size_t)k * q + i] = z;
+  // 3. projected problem on the device: Kt = E diag(theta) E^T
+  st_small_.ensure(sizeof(double) * ((size_t)q + (size_t)q * r1 * 2 + (size_t)nt * r1 + (size_t)nt * q * 3 +
+                                     (size_t)q * q + (size_t)nt * nt + 64));
+  double* theta = st_small_.as<double>();
+  double* S = theta + q;                    // q x r1 = Q^T Fb
+  double* Bh = S + (size_t)q * r1;          // q x r1 = E^T S
+  double* F2d = Bh + (size_t)q * r1;        // nt x r1
+  double* Gt = F2d + (size_t)nt * r1;       // nt x q
+  double* Z = Gt + (size_t)nt * q;          // q x nt
+  double* Zp = Z + (size_t)q * nt;          // q x nt = E Z
+  double* Gsm = Zp + (size_t)q * nt;        // Gram for the truncation (max(q, nt)^2)
+  dense->syevd(q, Kt, qmax, theta, eig_work_);
+  gram_dev(q, Q, r1, Fb, S);
+  dense->gemm(true, false, q, r1, q, 1.0, Kt, qmax, S, q, 0.0, Bh, q);
+  to_device(F2d, F2p.data(), (size_t)nt * r1);
+  dense->gemm(false, true, nt, q, r1, 1.0, F2d, nt, Bh, q, 0.0, Gt, nt);
+  time_recurrence(st, q, nt, theta, Gt, Z);
+  dense->gemm(false, false, q, nt, q, 1.0, Kt, qmax, Z, q, 0.0, Zp, q);
+  // 4. truncation of Y = Q Zp (Q M-orthonormal: M-weighted Frobenius norm)
+  const bool accurate = desc.trunc_tol < 1e-7;
+  double tail = 0.0;
+  int ry = 0;
+  if (accurate) {
+    std::vector<double> Zh((size_t)q * nt);
+    to_host(Zh.data(), Zp, Zh.size());
+    std::vector<double> s, Uz, Vz;
+    svd(q, nt, Zh.data(), q, s, Uz, Vz);
+    ry = truncation_rank(s, desc.trunc_tol, desc.rank_cap, &tail);
+    Y.resize(nx, nt, ry);
+    if (ry > 0) {
+      std::vector<double> Cm((size_t)q * ry);
+      for (int c = 0; c < ry; ++c)
+        for (int i = 0; i < q; ++i) Cm[(size_t)c * q + i] = Uz[(size_t)c * q + i] * s[c];
+      proj(q, Q, Cm, ry, Y.a(), 0.0);
+      for (int c = 0; c < ry; ++c)
+        for (int k = 0; k < nt; ++k) Y.B[(size_t)c * nt + (adjoint ? nt - 1 - k : k)] = Vz[(size_t)c * nt + k];
+    }
+  } else {
+    const bool right = nt <= q;  // Gram of the smaller side
+    const int g = right ? nt : q;
+    if (right) dense->gemm(true, false, nt, nt, q, 1.0, Zp, q, Zp, q, 0.0, Gsm, nt);
+    else dense->gemm(false, true, q, q, nt, 1.0, Zp, q, Zp, q, 0.0, Gsm, q);
+    double* wg = Gt;  // reuse: g values
+    dense->syevd(g, Gsm, g, wg, eig_work_);
+    std::vector<double> w(g);
+    to_host(w.data(), wg, g);
+    std::vector<double> s(g);
+    for (int c = 0; c < g; ++c) s[c] = std::sqrt(std::max(w[g - 1 - c], 0.0));
+    ry = truncation_rank(s, desc.trunc_tol, desc.rank_cap, &tail);
+    Y.resize(nx, nt, ry);
+    if (ry > 0) {
+      // eigenvectors of the kept directions are the last ry columns of Gsm
+      const double* Ek = Gsm + (size_t)(g - ry) * g;
+      std::vector<double> B2((size_t)nt * ry);
+      if (right) {
+        // Y = Q (Zp V_r) V_r^T
+        double* Cm = Z;  // q x ry
+        dense->gemm(false, false, q, ry, nt, 1.0, Zp, q, Ek, nt, 0.0, Cm, q);
+        proj_dev(q, Q, Cm, q, ry, Y.a(), 0.0);
+        LRP_HIP(hipMemcpyAsync(B2.data(), Ek, sizeof(double) * (size_t)nt * ry, hipMemcpyDeviceToHost, st));
+      } else {
+        // Y = Q U_r (Zp^T U_r)^T
+        double* Vt = Z;  // nt x ry
+        dense->gemm(true, false, nt, ry, q, 1.0, Zp, q, Ek, q, 0.0, Vt, nt);
+        proj_dev(q, Q, Ek, q, ry, Y.a(), 0.0);
+        LRP_HIP(hipMemcpyAsync(B2.data(), Vt, sizeof(double) * (size_t)nt * ry, hipMemcpyDeviceToHost, st));
+      }
+      sync();
+      for (int c = 0; c < ry; ++c)
+        for (int k = 0; k < nt; ++k) Y.B[(size_t)c * nt + (adjoint ? nt - 1 - k : k)] = B2[(size_t)c * nt + k];
     }
   }
-  std::vector<double> Zp((size_t)q * nt);
-  matmul(q, nt, q, E.data(), q, false, Z.data(), q, false, Zp.data(), q, 1.0, 0.0);
-  std::vector<double> s, Uz, Vz;
-  svd(q, nt, Zp.data(), q, s, Uz, Vz);
-  double tail = 0.0;
-  const int ry = truncation_rank(s, desc.trunc_tol, desc.rank_cap, &tail);
   stats.last_tail = tail;
-  Y.resize(nx, nt, ry);
-  if (ry == 0) return;
-  std::vector<double> Cm((size_t)q * ry);
-  for (int c = 0; c < ry; ++c)
-    for (int i = 0; i < q; ++i) Cm[(size_t)c * q + i] = Uz[(size_t)c * q + i] * s[c];
-  proj(q, Q, Cm, ry, Y.a(), 0.0);
-  for (int c = 0; c < ry; ++c)
-    for (int k = 0; k < nt; ++k) {
-      const int kk = adjoint ? nt - 1 - k : k;
-      Y.B[(size_t)c * nt + kk] = Vz[(size_t)c * nt + k];
-    }
   sync();
 }
 
@@ -562,7 +747,7 @@ void Problem::hess_apply(const LowRank& x, LowRank& y, bool precond) {
 //     discarded tail is within tol (relative Frobenius) is kept and one
 //     projection forms the new spatial factor.
 // ---------------------------------------------------------------------------
-void Problem::truncate(LowRank& x, double tol, int cap, int weight) {
+void Problem::truncate(LowRank& x, double tol, int cap, int weight, double ref_norm, bool orth_spatial) {
   const int R = x.rank;
   if (R == 0) return;
   const std::vector<ShiftCoef> Wop = weight == 1 ? std::vector<ShiftCoef>{{0.0, 1.0}}
@@ -686,9 +871,16 @@ void Problem::truncate(LowRank& x, double tol, int cap, int weight) {
   const int k = kout;
   // 3. SVD of RA (k x c)
   std::vector<double> s, Us, Vs;
-  svd(k, c, RA.data(), k, s, Us, Vs);
+  small_svd(k, c, RA.data(), k, tol < 1e-7, s, Us, Vs);
   double tail = 0.0;
-  const int r = truncation_rank(s, tol, cap, &tail);
+  double tol_eff = tol;
+  if (ref_norm > 0) {
+    double tot = 0.0;
+    for (double x2 : s) tot += x2 * x2;
+    tot = std::sqrt(tot);
+    tol_eff = tot > 0 ? tol * ref_norm / tot : 1.0;
+  }
+  const int r = truncation_rank(s, tol_eff, cap, &tail);
   stats.last_tail = tail;
   const int mn = (int)s.size();
   std::vector<double> Cm((size_t)kcur * std::max(r, 1), 0.0);  // T (kcur x k) * Us_r diag(s_r)
@@ -696,10 +888,13 @@ void Problem::truncate(LowRank& x, double tol, int cap, int weight) {
     for (int i = 0; i < kcur; ++i) {
       double t = 0.0;
       for (int l = 0; l < k; ++l) t += T[(size_t)l * kcur + i] * Us[(size_t)j * k + l];
-      Cm[(size_t)j * kcur + i] = t * s[j];
+      Cm[(size_t)j * kcur + i] = orth_spatial ? t : t * s[j];
     }
   std::vector<double> newB((size_t)nt * r, 0.0);
   if (r > 0) matmul(nt, r, c, QB.data(), nt, false, Vs.data(), c, false, newB.data(), nt, 1.0, 0.0);
+  if (orth_spatial)
+    for (int j = 0; j < r; ++j)
+      for (int t = 0; t < nt; ++t) newB[(size_t)j * nt + t] *= s[j];
   (void)mn;
   LowRank out;
   out.resize(nx, nt, r);

@@ -92,6 +92,9 @@ def load(path: str = LIB_PATH):
         "lrpost_mg_solve": (I, [P, I, P, P, pd, I]),
         "lrpost_gram": (I, [P, I, P, I, P, pd]),
         "lrpost_truncate": (I, [P, ctypes.POINTER(LowRankC), D, I]),
+        "lrpost_set_log": (I, [P, I]),
+        "lrpost_profile": (I, [P, I]),
+        "lrpost_profile_read": (I, [P, ctypes.POINTER(ctypes.c_int64), pd, pd]),
         "lrpost_last_error": (ctypes.c_char_p, []),
         "lrpost_version": (ctypes.c_char_p, []),
     }
@@ -255,6 +258,22 @@ class Problem:
         D = np.zeros((self.nt, self.nx))
         _check(_lib.lrpost_post_variance(self.h, eigs.h, D.ctypes.data_as(ctypes.c_void_p), 0))
         return D
+
+    def set_log(self, level: int):
+        """Progress lines (JSON on stderr) from the eigensolvers when level > 0."""
+        _check(_lib.lrpost_set_log(self.h, level))
+
+    def profile(self, enable: bool):
+        """Turn event timing of the multigrid smoother kernel on or off."""
+        _check(_lib.lrpost_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        """(launches, kernel ms, algorithmic bytes) since the last read."""
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        _check(_lib.lrpost_profile_read(self.h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+        return n.value, ms.value, by.value
 
     def stats(self) -> dict:
         s = Stats()

@@ -133,6 +133,7 @@ def test_spacetime_solve_matches_time_stepping(lp, N, nt, tol, adjoint):
     got = Y1.cpu().numpy().T @ Y2
     ref = ora.adjoint_source(F) if adjoint else ora.forward_source(F)
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print("space-time solve relative error %.3e (tol %g)" % (err, tol), flush=True)
     assert err <= 20 * tol, err
 
 
@@ -155,6 +156,8 @@ def test_hessian_apply_matches_oracle(lp, N, nt):
         Y1, Y2 = prob.hess_apply(_dev(A.T), B.T, which)
         got = Y1.cpu().numpy().T @ Y2
         err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        print("Hessian apply (%s) relative error %.3e" % ("G" if which == lp.LRPOST_PRECOND else "H_mis", err),
+              flush=True)
         assert err < 1e-8, (which, err)
 
 
