@@ -26,6 +26,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+COPY_BYTES = 256 << 20  # calibration copy for the HBM byte counters, each way
+TRAFFIC_REPORT = os.path.join(ROOT, "profiles", "k_cheb_mesh256_nt200_traffic.txt")
 
 
 def cpu_baseline(desc, budget_s=20.0):
@@ -52,6 +54,58 @@ def cpu_baseline(desc, budget_s=20.0):
                       "(SuperLU factor reused; single-threaded)" % n}
 
 
+def serving(args):
+    """Replay the first --serving requests of the seeded Poisson request stream
+    (20 req/s; mesh side 64/128/256, nt 50/100/200, k = 30 eigenpairs plus the
+    posterior variance, tol 1e-6, rank <= 64) through the serving loop, then
+    run the same requests one after another on one stream (the plain FP64
+    path) and report latency percentiles, throughput and the speedup."""
+    import torch
+
+    import synthetic
+    from paper_1703_05638_amd import lrpost as lp
+
+    lp.load()
+    torch.cuda.set_device(0)
+    reqs = synthetic.serving_stream()[: args.serving]
+    srv = lp.Server(hbm_budget_bytes=200 << 30, workers=args.workers)
+    t0 = time.perf_counter()
+    tickets = []
+    for r in reqs:
+        delay = r.arrival_s - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(srv.submit(r.desc, r.desc.k))
+    lat = []
+    for i, t in enumerate(tickets):
+        lat.append(srv.wait(t)[2])
+        print("request %d done (latency %.2f s)" % (i, lat[-1]), file=sys.stderr, flush=True)
+    t_serve = time.perf_counter() - t0
+    info = srv.info()
+    srv.close()
+    t1 = time.perf_counter()
+    for i, r in enumerate(reqs):
+        prob = lp.Problem(r.desc)
+        eig = prob.eigensolve(r.desc.k)
+        prob.post_variance(eig, on_device=False)
+        del eig, prob
+        print("sequential request %d done" % i, file=sys.stderr, flush=True)
+    t_seq = time.perf_counter() - t1
+    lat_sorted = sorted(lat)
+    out = {
+        "metric": "posterior requests served: p50/p99 latency",
+        "value": len(reqs) / t_serve, "unit": "requests/s", "n_gpus": 1, "higher_is_better": True,
+        "data": "synthetic", "dtype": "f64",
+        "config": {"workload": "poisson20_mesh64-256_nt50-200_k30", "requests": len(reqs), "workers": args.workers,
+                   "hbm_budget_gb": 200},
+        "latency_s": {"p50": statistics.median(lat),
+                      "p99": lat_sorted[min(len(lat) - 1, int(0.99 * len(lat)))]},
+        "makespan_s": t_serve, "sequential_fp64_s": t_seq, "speedup_vs_sequential": t_seq / t_serve,
+        "peak_running": info["peak_running"], "peak_admitted_gb": info["peak_admitted_bytes"] / 2 ** 30,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,11 +113,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving", type=int, default=0,
+                    help="measure the serving loop on this many requests instead of the eigensolve step")
+    ap.add_argument("--workers", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; runs on %d GPUs are not part of this build" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+    if args.serving > 0:
+        serving(args)
+        return
 
     import dataclasses
 
@@ -74,6 +134,14 @@ def main():
 
     lp.load()
     torch.cuda.set_device(0)
+    # A plain elementwise copy of known size (8-byte elements, read once and
+    # written once): its FETCH_SIZE / WRITE_SIZE counters scale the smoother's.
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
     desc = dataclasses.replace(synthetic.MESH256_NT200, precision=args.precision)
     prob = lp.Problem(desc)
     prob.set_log(1)
@@ -109,6 +177,9 @@ def main():
     applies = prob.stats()["applies"] - applies0
     st = prob.stats()
 
+    from paper_1703_05638_amd.profile_summary import read_traffic
+
+    traffic = read_traffic(TRAFFIC_REPORT)
     avg_ms = kern_ms / max(launches, 1)
     bytes_per_launch = kern_bytes / max(launches, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if launches else 0.0
@@ -135,7 +206,7 @@ def main():
         "lambda_1_to_3": [float(x) for x in lam[:3]],
         "roofline": {"kernel": "k_cheb<double,4> (multigrid Chebyshev smoother step)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "launches": launches, "avg_launch_us": avg_ms * 1e3,
                      "bytes_per_launch": bytes_per_launch},
     }

@@ -100,6 +100,7 @@ typedef struct {
   int32_t pad;
   double last_tail;       /* relative tail dropped by the last truncation */
   double last_st_resid;   /* relative residual of the last checked space-time solve (or -1) */
+  double ritz_resid;      /* largest ||G x - theta x||_P / theta over the pairs of the last eigensolve */
 } lrpost_stats;
 
 /* Create a problem: validates the description, builds the multigrid
@@ -131,6 +132,18 @@ int lrpost_spacetime_solve(lrpost_problem* p, const lrpost_lowrank* f, lrpost_lo
  * randomized two-pass range finder with k + oversample probes).  The result
  * handle owns device-resident eigenvector factors. */
 int lrpost_eigensolve(lrpost_problem* p, int k, int method, int oversample, lrpost_eigs** out);
+/* The two-pass randomized eigensolver (method LRPOST_RANDOMIZED) on caller
+ * probes: Y_j = G Omega_j, a P-orthonormal basis Q of range(Y) through the
+ * Gram [<Y_i, Y_j>_P], T = Q^T P G Q from a second pass of applies, Ritz
+ * pairs of T (Halko, Martinsson, Tropp 2011, range finder and Rayleigh-Ritz;
+ * the pencil is the one of Sec. 2, eq. prior_pre).  probes: nprobe low-rank
+ * space-time vectors (W1 device, W2 host), read only.  Returns
+ * min(k, rank of the probes' images) pairs; their largest relative Ritz
+ * residual is in lrpost_stats.ritz_resid.  With method LRPOST_RANDOMIZED,
+ * lrpost_eigensolve draws k + oversample probes G1 G2^T / sqrt(r),
+ * r = min(32, rank_cap), from the library's counter-based normal generator. */
+int lrpost_eigensolve_probes(lrpost_problem* p, int k, int nprobe, const lrpost_lowrank* probes,
+                             lrpost_eigs** out);
 int lrpost_eig_count(const lrpost_eigs* e);
 /* Eigenvalues, descending, into caller-owned host array of length k. */
 int lrpost_eig_values(const lrpost_eigs* e, double* lambda);
@@ -152,9 +165,13 @@ int lrpost_prior_variance(lrpost_problem* p, double* dprior);
 
 /* ns zero-mean posterior samples s = (I - V diag(p_i) V^T P) L xi with
  * p_i = 1 - (1+lambda_i)^{-1/2} and L = (alpha tau)^{-1/2} (I kron (K+M)^{-1/2})
- * (the symmetric root); covariance Gamma_post,k.  xi, out: host arrays of
- * ns * nx * nt float64 (sample-major, each nx x nt column-major). */
-int lrpost_sample(lrpost_problem* p, const lrpost_eigs* e, int ns, const double* xi, double* out);
+ * (the symmetric root, applied through the sine basis that diagonalizes K and
+ * M).  The covariance of s is Gamma_post,k: the low-rank update of Sec. 2
+ * (eq. prior_pre) written as a factor L_post L_post^T.  xi: caller-supplied
+ * standard normal draws; xi and out: ns * nx * nt float64 each (sample-major,
+ * each sample nx x nt column-major), caller-owned, device memory when
+ * on_device != 0, else host.  ns * nt <= 65535. */
+int lrpost_sample(lrpost_problem* p, const lrpost_eigs* e, int ns, const double* xi, double* out, int on_device);
 
 int lrpost_get_stats(const lrpost_problem* p, lrpost_stats* s);
 
@@ -189,6 +206,31 @@ int lrpost_gram(lrpost_problem* p, int m, const double* A, int q, const double* 
 /* Truncate X = W1 W2^T in place to tolerance tol (<= 0: desc.trunc_tol) and
  * rank <= cap; weighted = 1 measures in the M-norm in space. */
 int lrpost_truncate(lrpost_problem* p, lrpost_lowrank* x, double tol, int weighted);
+
+/* ---- serving loop ------------------------------------------------------
+ * Posterior requests (the k leading eigenpairs by block Lanczos and, when
+ * want_diag != 0, diag(Gamma_post,k) over nx * nt points; Sec. 2, Sec. 6
+ * eq. postvar) of any mesh and time size, served concurrently.  `workers`
+ * threads (1..16) each own a HIP stream; a worker takes the oldest pending
+ * request whose device-memory estimate fits in what is left of
+ * hbm_budget_bytes (a request always runs when nothing else does), so that
+ * requests arriving while others run are admitted as workers and memory free
+ * up and overlap with them on the device.  Every request builds its own
+ * problem on the worker's stream; its result is the one it would have alone.
+ * submit copies the description and returns a ticket at once; wait blocks
+ * until that request is done, writes k eigenvalues (host) and, if diag is
+ * not NULL and the request asked for it, nx * nt variances (host,
+ * column-major nx x nt), and the latency from submit to completion in
+ * seconds, then forgets the ticket.  A request's error code and message are
+ * returned by its wait.  destroy finishes running requests, fails pending
+ * ones, and must not run concurrently with a wait on the same server. */
+typedef struct lrpost_server lrpost_server;
+int lrpost_server_create(size_t hbm_budget_bytes, int workers, lrpost_server** out);
+int lrpost_server_submit(lrpost_server* s, const lrpost_problem_desc* desc, int k, int want_diag, uint64_t* ticket);
+int lrpost_server_wait(lrpost_server* s, uint64_t ticket, double* lambda, int k, double* diag, double* latency_s);
+/* largest number of requests that ran at once and largest admitted memory estimate */
+int lrpost_server_info(lrpost_server* s, int* peak_running, size_t* peak_admitted_bytes);
+int lrpost_server_destroy(lrpost_server* s);
 
 const char* lrpost_last_error(void);
 const char* lrpost_version(void);

@@ -11,6 +11,10 @@ using namespace lrp;
 
 static thread_local std::string g_last_error;
 
+namespace lrp {
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace lrp
+
 template <typename F>
 static int guarded(F&& f) {
   try {
@@ -131,6 +135,15 @@ int lrpost_spacetime_solve(lrpost_problem* p, const lrpost_lowrank* f, lrpost_lo
   });
 }
 
+static void finish_eigs(lrpost_problem* p, Problem* P, EigResult& r, lrpost_eigs** out) {
+  P->stats.ritz_resid = r.max_resid;
+  auto e = new lrpost_eigs();
+  e->owner = p;
+  e->lambda = r.lambda;
+  e->vecs = std::move(r.vecs);
+  *out = e;
+}
+
 int lrpost_eigensolve(lrpost_problem* p, int k, int method, int oversample, lrpost_eigs** out) {
   return guarded([&] {
     Problem* P = impl(p);
@@ -138,19 +151,60 @@ int lrpost_eigensolve(lrpost_problem* p, int k, int method, int oversample, lrpo
     if (!out) fail(LRPOST_EINVAL, "null output");
     *out = nullptr;
     if (k < 1) fail(LRPOST_EINVAL, "k must be >= 1");
-    if (method != LRPOST_BLOCK_LANCZOS) fail(LRPOST_EINVAL, "unsupported eigensolver method");
-    (void)oversample;
-    // Ritz residual target: the truncation tolerance bounds how far the
-    // residual of the truncated process can go down
-    const double rtol = std::max(P->desc.precision == LRPOST_FP64 ? 1e-9 : 1e-7, 0.1 * P->desc.trunc_tol);
-    const int bsize = 4;
-    const int maxv = std::max(8 * k, 64);
-    EigResult r = block_lanczos(P, k, bsize, std::min(maxv, 800), rtol);
-    auto e = new lrpost_eigs();
-    e->owner = p;
-    e->lambda = r.lambda;
-    e->vecs = std::move(r.vecs);
-    *out = e;
+    if (method == LRPOST_BLOCK_LANCZOS) {
+      // Ritz residual target: the truncation tolerance bounds how far the
+      // residual of the truncated process can go down
+      const double rtol = std::max(P->desc.precision == LRPOST_FP64 ? 1e-9 : 1e-7, 0.1 * P->desc.trunc_tol);
+      const int bsize = 4;
+      const int maxv = std::max(8 * k, 64);
+      EigResult r = block_lanczos(P, k, bsize, std::min(maxv, 800), rtol);
+      finish_eigs(p, P, r, out);
+      return;
+    }
+    if (method != LRPOST_RANDOMIZED) fail(LRPOST_EINVAL, "unsupported eigensolver method");
+    if (oversample < 0) fail(LRPOST_EINVAL, "oversample must be >= 0");
+    // k + oversample Gaussian probes G1 G2^T / sqrt(rp) of rank rp = min(32, rank_cap),
+    // drawn with the library's counter-based generator (streams 1000 + 2j, 1001 + 2j)
+    const int l = k + oversample;
+    const int rp = std::min(32, P->desc.rank_cap);
+    const long nx = P->nx;
+    const int nt = P->nt;
+    std::vector<LowRank> probes(l);
+    std::vector<double> ha((size_t)nx * rp);
+    for (int j = 0; j < l; ++j) {
+      LowRank& w = probes[j];
+      w.resize(nx, nt, rp);
+      for (size_t i = 0; i < ha.size(); ++i) ha[i] = normal_draw(P->desc.seed, 1000 + 2 * (uint64_t)j, i);
+      for (size_t i = 0; i < (size_t)nt * rp; ++i)
+        w.B[i] = normal_draw(P->desc.seed, 1001 + 2 * (uint64_t)j, i) / std::sqrt((double)rp);
+      P->to_device(w.a(), ha.data(), ha.size());
+      P->sync();
+    }
+    std::vector<const LowRank*> pp;
+    for (auto& w : probes) pp.push_back(&w);
+    EigResult r = randomized_eig(P, k, pp);
+    finish_eigs(p, P, r, out);
+  });
+}
+
+int lrpost_eigensolve_probes(lrpost_problem* p, int k, int nprobe, const lrpost_lowrank* probes,
+                             lrpost_eigs** out) {
+  return guarded([&] {
+    Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
+    if (!out || !probes) fail(LRPOST_EINVAL, "null argument");
+    *out = nullptr;
+    if (k < 1 || nprobe < 1) fail(LRPOST_EINVAL, "k and nprobe must be >= 1");
+    std::vector<LowRank> ws(nprobe);
+    for (int j = 0; j < nprobe; ++j) {
+      check_lr(P, &probes[j], true);
+      load_lr(P, &probes[j], ws[j]);
+    }
+    P->sync();
+    std::vector<const LowRank*> pp;
+    for (auto& w : ws) pp.push_back(&w);
+    EigResult r = randomized_eig(P, k, pp);
+    finish_eigs(p, P, r, out);
   });
 }
 
@@ -259,10 +313,74 @@ int lrpost_prior_variance(lrpost_problem* p, double* dprior) {
   });
 }
 
-int lrpost_sample(lrpost_problem* p, const lrpost_eigs* e, int ns, const double* xi, double* out) {
+// s = L xi - sum_i p_i <v_i, L xi>_P v_i with p_i = 1 - (1 + lambda_i)^{-1/2}:
+// the prior draw L xi, then the low-rank correction of its covariance.
+int lrpost_sample(lrpost_problem* p, const lrpost_eigs* e, int ns, const double* xi, double* out, int on_device) {
   return guarded([&] {
-    (void)p; (void)e; (void)ns; (void)xi; (void)out;
-    fail(LRPOST_EINVAL, "sampling is not available in this build");
+    Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
+    if (!e || !xi || !out) fail(LRPOST_EINVAL, "null argument");
+    if (ns < 0) fail(LRPOST_EINVAL, "ns must be >= 0");
+    if (ns == 0) return;
+    const int nt = P->nt;
+    const long nx = P->nx;
+    const long cols = (long)ns * nt;
+    if (cols > 65535) fail(LRPOST_EINVAL, "ns * nt must be at most 65535");
+    const int k = (int)e->vecs.size();
+    int R = 0;
+    std::vector<int> seg{0};
+    for (auto& v : e->vecs) { R += v->rank; seg.push_back(R); }
+    DevMem Xd, Ls, Y, A, Z, Cm;
+    const double* X = xi;
+    if (!on_device) {
+      Xd.ensure(sizeof(double) * (size_t)nx * cols);
+      LRP_HIP(hipMemcpyAsync(Xd.p, xi, sizeof(double) * (size_t)nx * cols, hipMemcpyHostToDevice, P->st));
+      X = Xd.as<double>();
+    }
+    double* Lx = out;
+    if (!on_device) {
+      Ls.ensure(sizeof(double) * (size_t)nx * cols);
+      Lx = Ls.as<double>();
+    }
+    P->prior_sqrt((int)cols, X, Lx);
+    if (R > 0) {
+      // <v_i, L xi>_P = alpha tau sum(B_i^T .* (A_i^T (K+M) L xi)) per sample
+      Y.ensure(sizeof(double) * (size_t)nx * cols);
+      P->apply_op((int)cols, Lx, Y.as<double>(), {{1.0, 1.0}});
+      A.ensure(sizeof(double) * (size_t)nx * R);
+      for (int i = 0; i < k; ++i) {
+        const LowRank& v = *e->vecs[i];
+        if (v.rank > 0)
+          LRP_HIP(hipMemcpyAsync(A.as<double>() + (size_t)seg[i] * nx, v.a(), sizeof(double) * nx * v.rank,
+                                 hipMemcpyDeviceToDevice, P->st));
+      }
+      Z.ensure(sizeof(double) * (size_t)R * cols);
+      P->dense->gemm(true, false, R, (int)cols, (int)nx, 1.0, A.as<double>(), (int)nx, Y.as<double>(), (int)nx, 0.0,
+                     Z.as<double>(), R);
+      std::vector<double> Zh((size_t)R * cols);
+      P->to_host(Zh.data(), Z.as<double>(), Zh.size());
+      const double at = P->desc.alpha * P->tau;
+      std::vector<double> Ch((size_t)R * cols, 0.0);
+      for (int s = 0; s < ns; ++s)
+        for (int i = 0; i < k; ++i) {
+          const LowRank& v = *e->vecs[i];
+          double c = 0.0;
+          for (int cc = 0; cc < v.rank; ++cc)
+            for (int t = 0; t < nt; ++t)
+              c += Zh[((size_t)s * nt + t) * R + seg[i] + cc] * v.B[(size_t)cc * nt + t];
+          const double coef = -(1.0 - 1.0 / std::sqrt(1.0 + e->lambda[i])) * at * c;
+          for (int cc = 0; cc < v.rank; ++cc)
+            for (int t = 0; t < nt; ++t)
+              Ch[((size_t)s * nt + t) * R + seg[i] + cc] = coef * v.B[(size_t)cc * nt + t];
+        }
+      Cm.ensure(sizeof(double) * Ch.size());
+      P->to_device(Cm.as<double>(), Ch.data(), Ch.size());
+      P->dense->gemm(false, false, (int)nx, (int)cols, R, 1.0, A.as<double>(), (int)nx, Cm.as<double>(), R, 1.0, Lx,
+                     (int)nx);
+    }
+    if (!on_device)
+      LRP_HIP(hipMemcpyAsync(out, Lx, sizeof(double) * (size_t)nx * cols, hipMemcpyDeviceToHost, P->st));
+    P->sync();
   });
 }
 

@@ -68,7 +68,7 @@ class SharedBasis {
   DevMem C_all, B_all;
   int used = 0, all_cap = 0;
   std::vector<int> off, rk;
-  DevMem work1, work2, work3, wev, eye;
+  DevMem work1, work2, work3, wev, eye, eye_nt;
 
   int size() const { return (int)off.size(); }
 
@@ -116,7 +116,7 @@ class SharedBasis {
   // Express a low-rank vector in the basis, extending U by the directions of
   // its spatial factor outside span(U) (remainder truncated at a tenth of tol
   // relative to the vector's norm).  Returns the truncated core.
-  CVec absorb(const LowRank& w, double tol, int cap) {
+  CVec absorb(const LowRank& w, double tol, int cap, bool truncate_out = true) {
     CVec out;
     out.s = s;
     const int rw = w.rank;
@@ -231,7 +231,27 @@ class SharedBasis {
       P->to_device(eye.as<double>(), id.data(), id.size());
       P->dense->gemm(false, true, rn, nt, rn, 1.0, eye.as<double>(), rn, Bnd, nt, 0.0, S + s0, s);
     }
-    return truncate_core(S, s, s, tol, cap);
+    return truncate_out ? truncate_core(S, s, s, tol, cap) : dense_core(S, s);
+  }
+
+  // A dense core S (rows x nt, leading dimension rows) as a vector in
+  // coefficient form without truncation: C = S, B = I.
+  CVec dense_core(const double* S, int rows) {
+    CVec out;
+    out.s = rows;
+    out.r = nt;
+    out.C.ensure(sizeof(double) * (size_t)std::max(rows, 1) * nt);
+    out.B.ensure(sizeof(double) * (size_t)nt * nt);
+    if (!eye_nt.p) {
+      std::vector<double> id((size_t)nt * nt, 0.0);
+      for (int i = 0; i < nt; ++i) id[(size_t)i * nt + i] = 1.0;
+      eye_nt.ensure(sizeof(double) * id.size());
+      P->to_device(eye_nt.as<double>(), id.data(), id.size());
+    }
+    if (rows > 0)
+      LRP_HIP(hipMemcpyAsync(out.C.p, S, sizeof(double) * (size_t)rows * nt, hipMemcpyDeviceToDevice, P->st));
+    LRP_HIP(hipMemcpyAsync(out.B.p, eye_nt.p, sizeof(double) * (size_t)nt * nt, hipMemcpyDeviceToDevice, P->st));
+    return out;
   }
 
   // Truncate a dense core S (rows x nt, leading dimension lds) to rank <= cap
@@ -481,6 +501,7 @@ EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rt
   EigResult res;
   std::vector<double> theta, Y;
   int m_conv = 0;
+  double last_worst = -1.0;
   DevMem Sbuf;
   for (int step = 0;; ++step) {
     const int j0 = block_start.back(), bj = block_size.back();
@@ -500,7 +521,9 @@ EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rt
     auto t1 = clk::now();
     t_apply += std::chrono::duration<double>(t1 - t0).count();
     std::vector<CVec> Wn;
-    for (int i = 0; i < bj; ++i) Wn.push_back(sb.absorb(outs[i], tol, cap));
+    // the apply outputs and the first sweep's results stay dense cores (no
+    // truncation); the second sweep's results are truncated
+    for (int i = 0; i < bj; ++i) Wn.push_back(sb.absorb(outs[i], tol, cap, false));
     outs.clear();
     // full re-orthogonalization, classical Gram-Schmidt twice, on the cores
     for (int pass = 0; pass < 2; ++pass) {
@@ -511,7 +534,8 @@ EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rt
         for (double& x : c) x = -x;
         Sbuf.ensure(sizeof(double) * (size_t)sb.s * nt);
         sb.combine({&Wn[i]}, {1.0}, c, Sbuf.as<double>());
-        Wn[i] = sb.truncate_core(Sbuf.as<double>(), sb.s, sb.s, tol * 1e-1, cap);
+        Wn[i] = pass == 0 ? sb.dense_core(Sbuf.as<double>(), sb.s)
+                          : sb.truncate_core(Sbuf.as<double>(), sb.s, sb.s, tol * 1e-1, cap);
       }
     }
     const int m = sb.size();
@@ -543,6 +567,7 @@ EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rt
     }
     res.steps = step + 1;
     m_conv = m;
+    last_worst = worst;
     t_orth += std::chrono::duration<double>(clk::now() - t1).count();
     if (P->log_level > 1) {
       // orthonormality of the stored basis and symmetry of the projected matrix
@@ -588,6 +613,7 @@ EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rt
     for (auto& v : Vn) sb.append(v);
   }
   P->stats.lanczos_steps = res.steps;
+  res.max_resid = last_worst;
   // Ritz vectors of the k largest Ritz values
   const int m = m_conv;
   const int kk = std::min(k, m);
@@ -605,6 +631,147 @@ EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rt
     sb.materialize(v, *out);
     res.vecs.push_back(std::move(out));
   }
+  return res;
+}
+
+// ---------------------------------------------------------------------------
+// Two-pass randomized eigensolver (range finder and Rayleigh-Ritz of Halko,
+// Martinsson and Tropp 2011) in the P inner product, on the shared spatial
+// basis: pass one absorbs Y_j = G Omega_j; the Gram [<Y_i, Y_j>_P] gives a
+// P-orthonormal basis Q_c = sum_j Y_j U_jc / sqrt(mu_c) (directions with
+// mu_c <= 1e-14 max(mu) dropped) formed on the cores; pass two absorbs
+// W_c = G Q_c; with MQ = [<Q_a, Q_b>_P] (the identity up to truncation) and
+// T = [<Q_a, W_b>_P] the Ritz pairs solve T v = theta MQ v.  Ritz residuals
+// ||sum_a (W_a - theta Q_a) v_a||_P come from the Grams of Q and W.
+// ---------------------------------------------------------------------------
+EigResult randomized_eig(Problem* P, int k, const std::vector<const LowRank*>& probes) {
+  const int l = (int)probes.size();
+  const double tol = P->desc.trunc_tol;
+  const int cap = P->desc.rank_cap;
+  const long nx = P->nx;
+  const int nt = P->nt;
+  if (l < 1) fail(LRPOST_EINVAL, "no probes");
+  const long s_reserve = std::min<long>(nx, (long)(3 * l) * std::min(cap, 32) + 64);
+  SharedBasis sb(P, (int)s_reserve, std::max(3 * l * cap, 64));
+  using clk = std::chrono::steady_clock;
+  const auto t0 = clk::now();
+  auto logline = [&](const char* phase, int done) {
+    if (P->log_level > 0) {
+      std::fprintf(stderr, "{\"randomized\": \"%s\", \"done\": %d, \"applies\": %lld, \"basis_s\": %d, \"t_s\": %.3f}\n",
+                   phase, done, (long long)P->stats.applies, sb.s,
+                   std::chrono::duration<double>(clk::now() - t0).count());
+      std::fflush(stderr);
+    }
+  };
+  // pass one
+  std::vector<CVec> Y;
+  for (int j = 0; j < l; ++j) {
+    LowRank y;
+    P->hess_apply(*probes[j], y, true);
+    Y.push_back(sb.absorb(y, tol, cap));
+    if ((j + 1) % 8 == 0 || j + 1 == l) logline("pass1", j + 1);
+  }
+  for (auto& y : Y) sb.append(y);
+  std::vector<double> Gy((size_t)l * l);
+  for (int j = 0; j < l; ++j) {
+    std::vector<double> c = sb.inner_all(Y[j]);
+    for (int i = 0; i < l; ++i) Gy[(size_t)j * l + i] = c[i];
+  }
+  for (int j = 0; j < l; ++j)
+    for (int i = 0; i < j; ++i) Gy[(size_t)j * l + i] = Gy[(size_t)i * l + j] = 0.5 * (Gy[(size_t)j * l + i] + Gy[(size_t)i * l + j]);
+  std::vector<double> mu(l), U((size_t)l * l);
+  if (!syev(l, Gy.data(), l, mu.data(), U.data())) fail(LRPOST_EBREAKDOWN, "probe Gram eigensolve failed");
+  std::vector<int> keep;
+  for (int c = l - 1; c >= 0; --c)
+    if (mu[l - 1] > 0 && mu[c] > 1e-14 * mu[l - 1]) keep.push_back(c);
+  const int m = (int)keep.size();
+  if (m == 0) fail(LRPOST_EBREAKDOWN, "the probes' images are zero");
+  DevMem Sbuf;
+  std::vector<CVec> Q;
+  for (int c : keep) {
+    std::vector<double> coef(sb.size(), 0.0);
+    for (int j = 0; j < l; ++j) coef[j] = U[(size_t)c * l + j] / std::sqrt(mu[c]);
+    Sbuf.ensure(sizeof(double) * (size_t)sb.s * nt);
+    sb.combine({}, {}, coef, Sbuf.as<double>());
+    Q.push_back(sb.truncate_core(Sbuf.as<double>(), sb.s, sb.s, tol, cap));
+  }
+  // pass two
+  std::vector<CVec> W;
+  for (int a = 0; a < m; ++a) {
+    LowRank q, w;
+    sb.materialize(Q[a], q);
+    P->hess_apply(q, w, true);
+    W.push_back(sb.absorb(w, tol, cap));
+    if ((a + 1) % 8 == 0 || a + 1 == m) logline("pass2", a + 1);
+  }
+  // stored vectors: Y (0 .. l-1), Q (l .. l+m-1), W (l+m .. l+2m-1)
+  for (auto& q : Q) sb.append(q);
+  for (auto& w : W) sb.append(w);
+  std::vector<double> MQ((size_t)m * m), T((size_t)m * m), GW((size_t)m * m);
+  for (int b = 0; b < m; ++b) {
+    std::vector<double> cq = sb.inner_all(Q[b]);
+    std::vector<double> cw = sb.inner_all(W[b]);
+    for (int a = 0; a < m; ++a) {
+      MQ[(size_t)b * m + a] = cq[l + a];
+      T[(size_t)b * m + a] = cw[l + a];
+      GW[(size_t)b * m + a] = cw[l + m + a];
+    }
+  }
+  // generalized Rayleigh-Ritz through the eigenpairs of MQ: B = V_Q e^{-1/2}
+  std::vector<double> eq(m), VQ((size_t)m * m);
+  {
+    std::vector<double> Ms((size_t)m * m);
+    for (int b = 0; b < m; ++b)
+      for (int a = 0; a < m; ++a) Ms[(size_t)b * m + a] = 0.5 * (MQ[(size_t)b * m + a] + MQ[(size_t)a * m + b]);
+    if (!syev(m, Ms.data(), m, eq.data(), VQ.data())) fail(LRPOST_EBREAKDOWN, "basis Gram eigensolve failed");
+  }
+  std::vector<int> kq;
+  for (int c = m - 1; c >= 0; --c)
+    if (eq[c] > 1e-10 * eq[m - 1]) kq.push_back(c);
+  const int mq = (int)kq.size();
+  std::vector<double> Bm((size_t)m * mq);
+  for (int c = 0; c < mq; ++c)
+    for (int a = 0; a < m; ++a) Bm[(size_t)c * m + a] = VQ[(size_t)kq[c] * m + a] / std::sqrt(eq[kq[c]]);
+  // Ts = B^T sym(T) B
+  std::vector<double> Tsym((size_t)m * m), TB((size_t)m * mq), Ts((size_t)mq * mq);
+  for (int b = 0; b < m; ++b)
+    for (int a = 0; a < m; ++a) Tsym[(size_t)b * m + a] = 0.5 * (T[(size_t)b * m + a] + T[(size_t)a * m + b]);
+  matmul(m, mq, m, Tsym.data(), m, false, Bm.data(), m, false, TB.data(), m, 1.0, 0.0);
+  matmul(mq, mq, m, Bm.data(), m, true, TB.data(), m, false, Ts.data(), mq, 1.0, 0.0);
+  std::vector<double> theta, V;
+  P->sym_eig(mq, Ts.data(), mq, theta, V);
+  const int kk = std::min(k, mq);
+  EigResult res;
+  res.steps = 2;
+  double worst = 0.0;
+  for (int i = 0; i < kk; ++i) {
+    const int col = mq - 1 - i;
+    const double th = theta[col];
+    // coefficients on Q: c = B V[:, col]
+    std::vector<double> c(m, 0.0);
+    for (int a = 0; a < m; ++a)
+      for (int b = 0; b < mq; ++b) c[a] += Bm[(size_t)b * m + a] * V[(size_t)col * mq + b];
+    // residual ||sum c_a (W_a - theta Q_a)||_P^2 = c^T (GW - theta (T + T^T) + theta^2 MQ) c
+    double r2 = 0.0;
+    for (int b = 0; b < m; ++b)
+      for (int a = 0; a < m; ++a)
+        r2 += c[a] * c[b] * (GW[(size_t)b * m + a] - th * (T[(size_t)b * m + a] + T[(size_t)a * m + b]) +
+                             th * th * MQ[(size_t)b * m + a]);
+    worst = std::max(worst, std::sqrt(std::max(r2, 0.0)) / std::max(std::fabs(th), 1e-300));
+    std::vector<double> coef(sb.size(), 0.0);
+    for (int a = 0; a < m; ++a) coef[l + a] = c[a];
+    Sbuf.ensure(sizeof(double) * (size_t)sb.s * nt);
+    sb.combine({}, {}, coef, Sbuf.as<double>());
+    CVec v = sb.truncate_core(Sbuf.as<double>(), sb.s, sb.s, tol, cap);
+    const double nv = std::sqrt(std::max(sb.inner(v, v), 0.0));
+    if (nv > 0) P->dense->scal(nt * v.r, 1.0 / nv, v.B.as<double>());
+    auto out = std::make_unique<LowRank>();
+    sb.materialize(v, *out);
+    res.lambda.push_back(th);
+    res.vecs.push_back(std::move(out));
+  }
+  res.max_resid = worst;
+  logline("done", kk);
   return res;
 }
 

@@ -114,6 +114,7 @@ GpuDense::GpuDense(hipStream_t st) {
   rb_check(rocblas_create_handle(&h), "rocblas_create_handle");
   rb_check(rocblas_set_stream(h, st), "rocblas_set_stream");
   handle = h;
+  st_ = st;
 }
 
 GpuDense::~GpuDense() {
@@ -129,6 +130,16 @@ void GpuDense::gemm(bool ta, bool tb, int m, int n, int k, double alpha, const d
            "rocblas_dgemm");
 }
 
+void GpuDense::gemm_strided_batched(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda,
+                                    long sa, const double* B, int ldb, long sb, double beta, double* C, int ldc,
+                                    long sc, int batch) {
+  if (m <= 0 || n <= 0 || batch <= 0) return;
+  rb_check(rocblas_dgemm_strided_batched((rocblas_handle)handle, ta ? rocblas_operation_transpose : rocblas_operation_none,
+                                         tb ? rocblas_operation_transpose : rocblas_operation_none, m, n, k, &alpha, A,
+                                         lda, sa, B, ldb, sb, &beta, C, ldc, sc, batch),
+           "rocblas_dgemm_strided_batched");
+}
+
 void GpuDense::syevd(int n, double* A, int lda, double* w, DevMem& work) {
   if (n <= 0) return;
   work.ensure(sizeof(double) * (size_t)n + 64);
@@ -136,6 +147,19 @@ void GpuDense::syevd(int n, double* A, int lda, double* w, DevMem& work) {
   rb_check(rocsolver_dsyevd((rocblas_handle)handle, rocblas_evect_original, rocblas_fill_upper, n, A, lda, w,
                             work.as<double>(), info),
            "rocsolver_dsyevd");
+}
+
+bool GpuDense::spd_inverse_upper(int n, double* A, int lda, DevMem& work) {
+  if (n <= 0) return true;
+  work.ensure(64);
+  int* info = work.as<int>();
+  rb_check(rocsolver_dpotrf((rocblas_handle)handle, rocblas_fill_upper, n, A, lda, info), "rocsolver_dpotrf");
+  int h = 0;
+  LRP_HIP(hipMemcpyAsync(&h, info, sizeof(int), hipMemcpyDeviceToHost, st_));
+  LRP_HIP(hipStreamSynchronize(st_));
+  if (h != 0) return false;
+  rb_check(rocsolver_dpotri((rocblas_handle)handle, rocblas_fill_upper, n, A, lda, info), "rocsolver_dpotri");
+  return true;
 }
 
 void GpuDense::dgmm_right(int m, int n, const double* A, int lda, const double* x, double* C, int ldc) {

@@ -80,14 +80,20 @@ class GpuDense {
   ~GpuDense();
   void gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda, const double* B, int ldb,
             double beta, double* C, int ldc);
+  // batch of C_b = alpha op(A_b) op(B_b) + beta C_b with constant strides (stride 0: shared operand)
+  void gemm_strided_batched(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda, long sa,
+                            const double* B, int ldb, long sb, double beta, double* C, int ldc, long sc, int batch);
   // A (n x n, upper triangle) -> eigenvectors in place, eigenvalues ascending in w (all device)
   void syevd(int n, double* A, int lda, double* w, DevMem& work);
+  // A (n x n SPD, upper triangle) -> upper triangle of A^{-1} (Cholesky); false if not positive definite
+  bool spd_inverse_upper(int n, double* A, int lda, DevMem& work);
   // C = A diag(x) (A, C: m x n device; x: n device)
   void dgmm_right(int m, int n, const double* A, int lda, const double* x, double* C, int ldc);
   void scal(int n, double alpha, double* x);
 
  private:
   void* handle = nullptr;
+  hipStream_t st_ = nullptr;
 };
 
 // A low-rank space-time vector X = A B^T with A on the device (nx x rank,
@@ -142,7 +148,11 @@ class Problem {
   void apply_op(int ncols, const double* X, double* Y, const std::vector<ShiftCoef>& ab,
                 const double* Z = nullptr, const std::vector<double>* zc = nullptr);
   // X ~ (a_j K + b_j M)^{-1} B by `cycles` V-cycles from zero
-  void mg_solve(int ncols, const double* B, double* X, const std::vector<ShiftCoef>& ab, int cycles);
+  // In LRPOST_MIXED mode the V-cycles run in float32: `cycles` of them per
+  // round, and `refine` further rounds each start from the float64 residual
+  // B - A X (iterative refinement); in float64 mode `refine` is ignored.
+  void mg_solve(int ncols, const double* B, double* X, const std::vector<ShiftCoef>& ab, int cycles,
+                int refine = 0);
   // C (host, m x q) = A^T B
   void gram(int m, const double* A, int q, const double* B, std::vector<double>& C);
   // C (device, m x q, leading dimension m) = A^T B
@@ -151,6 +161,8 @@ class Problem {
   void proj(int m, const double* A, const std::vector<double>& Q, int p, double* C, double beta);
   // C = beta C + A Q (Q device m x p, leading dimension ldq)
   void proj_dev(int m, const double* A, const double* Q, int ldq, int p, double* C, double beta);
+  // Y = L X for ncols nodal vectors, L = (alpha tau)^{-1/2} (K+M)^{-1/2} (symmetric root)
+  void prior_sqrt(int ncols, const double* X, double* Y);
   // symmetric eigenproblem of a host matrix (ascending), on the GPU above a small size
   void sym_eig(int n, const double* A, int lda, std::vector<double>& w, std::vector<double>& V);
   // thin SVD of a small host matrix; `accurate` asks for relative accuracy of
@@ -170,8 +182,8 @@ class Problem {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
   size_t prof_used = 0;
   double prof_bytes = 0.0;
-  void smooth_step(int nl, int ncols, const double* xc, const double* xp, double* xo, const double* b, long ld,
-                   const double* prm, int s);
+  template <typename T>
+  void smooth_step(int nl, int ncols, const T* xc, const T* xp, T* xo, const T* b, long ld, const double* prm, int s);
   void prof_read(int64_t* launches, double* ms, double* bytes);
 
   // ---- low-rank operations ---------------------------------------------
@@ -195,6 +207,8 @@ class Problem {
   int st_cycles = 0;
   int prior_cycles = 0;
   std::vector<double> poles;
+  // sine basis of K and M (device, n x n) and the per-mode weights of L (device, nx)
+  DevMem sine_, root_w_, sqrt_tmp_;
 
  private:
   DevMem mg_param_, mg_work_, mg_res_, gram_part_, gram_out_, proj_q_, op_w_;
@@ -203,7 +217,11 @@ class Problem {
   size_t staging_used_ = 0;
   std::vector<double> mg_param_h_, op_w_h_;
   std::vector<double> tmp_h_;
-  void vcycle_zero(int ncols, const double* B, double* X);
+  template <typename T>
+  void vcycle_zero(int ncols, const T* B, T* X);
+  // cycles V-cycles in float32 on nx x ncols float data (residual correction between cycles)
+  void mg_cycles_f32(int ncols, const float* B, float* X, const std::vector<ShiftCoef>& neg, int cycles);
+  DevMem mg_work_f_, mg_f_;
   void upload_mg_params(const std::vector<ShiftCoef>& ab);
   // space-time solver workspaces
   DevMem st_q_, st_w_, st_mw_, st_f_, st_kt_, st_small_, eig_work_;
@@ -218,8 +236,11 @@ struct EigResult {
   std::vector<double> lambda;
   std::vector<std::unique_ptr<LowRank>> vecs;
   int steps = 0;
+  double max_resid = -1.0;  // largest relative Ritz residual of the returned pairs
 };
 EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rtol);
+// Two-pass randomized eigensolver on the given probes (space-time vectors).
+EigResult randomized_eig(Problem* P, int k, const std::vector<const LowRank*>& probes);
 
 }  // namespace lrp
 

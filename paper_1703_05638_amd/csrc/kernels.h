@@ -28,25 +28,34 @@ void mg_coarse_lds(hipStream_t st, int n0, int nlev, int ncols, const T* B, long
                    const double* Pc, int nu1, int nu2);
 constexpr int kCoarseLdsMaxN = 31;
 
-int gram_chunks(long nrows, int m, int q);
-// C (device, m x q, double) = A^T B; part: device scratch of gram_chunks()*m*q doubles.
+int gram_chunks(long nrows, int m, int q);       // float instance (LDS kernel)
+int gram_chunks_mfma(long nrows, int m, int q);  // double instance (FP64 MFMA kernel)
+// C (device, m x q, double) = A^T B; part: device scratch of gram_chunks()*m*q
+// doubles (gram_chunks_mfma() for T = double).
 template <typename T>
 void gram(hipStream_t st, long nrows, int m, const T* A, long lda, int q, const T* B, long ldb, double* C,
           double* part);
-// C = beta*C + A Q  (Q: device m x p double, leading dim ldq)
+template <>
+void gram<double>(hipStream_t st, long nrows, int m, const double* A, long lda, int q, const double* B, long ldb,
+                  double* C, double* part);
+// C = beta*C + A Q  (Q: device m x p double, leading dim ldq; C must not overlap A)
 template <typename T>
 void proj(hipStream_t st, long nrows, int m, const T* A, long lda, const double* Q, int ldq, int p, T* C, long ldc,
           double beta);
+template <>
+void proj<double>(hipStream_t st, long nrows, int m, const double* A, long lda, const double* Q, int ldq, int p,
+                  double* C, long ldc, double beta);
 
 template <typename T>
 void mask_scale(hipStream_t st, long nx, int ncols, const T* X, long ldx, T* Y, long ldy, const uint8_t* mask,
                 double s);
 template <typename T>
 void axpby(hipStream_t st, long nx, int ncols, const T* X, long ldx, T* Y, long ldy, double a, double b);
+void scale_nodes(hipStream_t st, long nx, int ncols, double* X, long ldx, const double* w);
+void add_diag(hipStream_t st, int n, double* A, long lda, double v);
+void symmetrize_upper(hipStream_t st, int n, double* A, long lda);
 void d2f(hipStream_t st, long n, const double* x, float* y);
 void f2d(hipStream_t st, long n, const float* x, double* y);
-
-void time_recurrence(hipStream_t st, int q, int nt, const double* theta, const double* G, double* Z);
 
 void post_variance(hipStream_t st, long nx, int nt, int k, const int* seg, const double* dcoef, const double* A,
                    long lda, const double* Bt, int R, const double* dprior, double* D, long ldd);

@@ -146,50 +146,54 @@ template void mg_smooth_step<double>(hipStream_t, int, int, const double*, const
 template void mg_smooth_step<float>(hipStream_t, int, int, const float*, const float*, float*, const float*, long,
                                     const double*, int);
 
-// Fine residual r = b - A x evaluated at a fine node (0-based i, j).
-template <typename T>
-__device__ inline T fine_resid(int n, const T* __restrict__ x, const T* __restrict__ b, int i, int j, T wc, T we,
-                               T wk) {
-  if (i < 0 || j < 0 || i >= n || j >= n) return T(0);
-  auto at = [&](int ii, int jj) -> T { return (ii < 0 || jj < 0 || ii >= n || jj >= n) ? T(0) : x[(long)jj * n + ii]; };
-  const T ax = wc * at(i, j) + we * (at(i - 1, j) + at(i + 1, j) + at(i, j - 1) + at(i, j + 1)) +
-               wk * (at(i - 1, j - 1) + at(i + 1, j - 1) + at(i - 1, j + 1) + at(i + 1, j + 1));
-  return b[(long)j * n + i] - ax;
-}
-
 // Coarse right-hand side bc = P^T (b - A x): coarse node (I, J) sits on fine
 // node (2I+1, 2J+1) (0-based); bilinear-interpolation transpose weights
-// 1 (centre), 1/2 (edges), 1/4 (corners).
+// 1 (centre), 1/2 (edges), 1/4 (corners).  A workgroup covers 64 x 4 coarse
+// nodes: it stages the fine iterate of the 129 x 9 fine nodes they touch
+// (plus a one-node halo) in LDS with coalesced row loads, forms each fine
+// residual once, and restricts from LDS.
+constexpr int RCI = 64, RCJ = 4;                       // coarse tile
+constexpr int RFI = 2 * RCI + 1, RFJ = 2 * RCJ + 1;    // fine residual tile (129 x 9)
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_resid_restrict(int n, int nc, const T* __restrict__ X,
                                                         const T* __restrict__ B, long ld, T* __restrict__ Bc,
                                                         long ldc, const double* __restrict__ P) {
+  __shared__ T xs[RFJ + 2][RFI + 3];
+  __shared__ T rs[RFJ][RFI + 1];
   const int col = blockIdx.z;
-  const int I = blockIdx.x * 64 + threadIdx.x;
-  const int J = blockIdx.y * 4 + threadIdx.y;
-  if (I >= nc || J >= nc) return;
+  const int I0 = blockIdx.x * RCI, J0 = blockIdx.y * RCJ;
+  const int tid = threadIdx.y * 64 + threadIdx.x;
   const T wc = (T)P[kMgStride * col + 0], we = (T)P[kMgStride * col + 1], wk = (T)P[kMgStride * col + 2];
   const T* x = X ? X + (long)col * ld : nullptr;
   const T* b = B + (long)col * ld;
-  const int fi = 2 * I + 1, fj = 2 * J + 1;
-  T acc = T(0);
+  const int fi0 = 2 * I0, fj0 = 2 * J0;  // fine origin of the residual tile
   if (x) {
-#pragma unroll
-    for (int dj = -1; dj <= 1; ++dj)
-#pragma unroll
-      for (int di = -1; di <= 1; ++di) {
-        const T w = (di == 0 ? T(1) : T(0.5)) * (dj == 0 ? T(1) : T(0.5));
-        acc += w * fine_resid(n, x, b, fi + di, fj + dj, wc, we, wk);
-      }
-  } else {
-#pragma unroll
-    for (int dj = -1; dj <= 1; ++dj)
-#pragma unroll
-      for (int di = -1; di <= 1; ++di) {
-        const T w = (di == 0 ? T(1) : T(0.5)) * (dj == 0 ? T(1) : T(0.5));
-        acc += w * b[(long)(fj + dj) * n + (fi + di)];
-      }
+    for (int p = tid; p < (RFJ + 2) * (RFI + 2); p += 256) {
+      const int r = p / (RFI + 2), c = p % (RFI + 2);
+      const int fj = fj0 - 1 + r, fi = fi0 - 1 + c;
+      xs[r][c] = (fi >= 0 && fj >= 0 && fi < n && fj < n) ? x[(long)fj * n + fi] : T(0);
+    }
+    __syncthreads();
   }
+  for (int p = tid; p < RFJ * RFI; p += 256) {
+    const int r = p / RFI, c = p % RFI;
+    const int fj = fj0 + r, fi = fi0 + c;
+    T v = T(0);
+    if (fi < n && fj < n) {
+      v = b[(long)fj * n + fi];
+      if (x)
+        v -= wc * xs[r + 1][c + 1] + we * ((xs[r + 1][c] + xs[r + 1][c + 2]) + (xs[r][c + 1] + xs[r + 2][c + 1])) +
+             wk * ((xs[r][c] + xs[r][c + 2]) + (xs[r + 2][c] + xs[r + 2][c + 2]));
+    }
+    rs[r][c] = v;
+  }
+  __syncthreads();
+  const int I = I0 + threadIdx.x, J = J0 + threadIdx.y;
+  if (I >= nc || J >= nc) return;
+  const int r = 2 * threadIdx.y + 1, c = 2 * threadIdx.x + 1;
+  const T acc = rs[r][c] + T(0.5) * ((rs[r][c - 1] + rs[r][c + 1]) + (rs[r - 1][c] + rs[r + 1][c])) +
+                T(0.25) * ((rs[r - 1][c - 1] + rs[r - 1][c + 1]) + (rs[r + 1][c - 1] + rs[r + 1][c + 1]));
   Bc[(long)col * ldc + (long)J * nc + I] = acc;
 }
 
@@ -442,6 +446,85 @@ int gram_chunks(long nrows, int m, int q) {
   return (int)c;
 }
 
+// ---------------------------------------------------------------------------
+// FP64 Gram on the matrix cores.  Workgroup (tm, tq, chunk) accumulates a
+// 64 x 64 output tile over its chunk of rows.  Rows are staged through LDS
+// 32 at a time (coalesced: 32 consecutive lanes read 32 consecutive rows of
+// one column), stored [column][row] so that each MFMA operand is one LDS
+// read per lane.  Each wave owns a 32 x 32 quarter of the tile as 2 x 2
+// blocks of v_mfma_f64_16x16x4f64: for the 16 x 4 operand lane l holds
+// element (l % 16, l / 16), for the 4 x 16 operand element (l / 16, l % 16),
+// and the 16 x 16 result element (l / 16 + 4 v, l % 16) in slot v.
+// ---------------------------------------------------------------------------
+typedef double gram_d4 __attribute__((ext_vector_type(4)));
+constexpr int MT = 64;  // output tile edge
+constexpr int MK = 32;  // rows per LDS stage
+
+__global__ __launch_bounds__(256) void k_gram_mfma(long nrows, long rows_per_chunk, int m,
+                                                   const double* __restrict__ A, long lda, int q,
+                                                   const double* __restrict__ B, long ldb,
+                                                   double* __restrict__ part) {
+  __shared__ double As[MT][MK + 1];
+  __shared__ double Bs[MT][MK + 1];
+  const int tm = blockIdx.x, tq = blockIdx.y, chunk = blockIdx.z;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wq = wave >> 1;
+  const long r0 = (long)chunk * rows_per_chunk;
+  const long r1 = min(nrows, r0 + rows_per_chunk);
+  gram_d4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = gram_d4{0.0, 0.0, 0.0, 0.0};
+  const int lr = tid & 31, lc = tid >> 5;  // loader: row lr of columns lc, lc + 8, ...
+  for (long rb = r0; rb < r1; rb += MK) {
+    const long r = rb + lr;
+    const bool rin = r < r1;
+#pragma unroll
+    for (int u = 0; u < MT / 8; ++u) {
+      const int c = lc + 8 * u;
+      const int ca = tm * MT + c, cb = tq * MT + c;
+      As[c][lr] = (rin && ca < m) ? A[(long)ca * lda + r] : 0.0;
+      Bs[c][lr] = (rin && cb < q) ? B[(long)cb * ldb + r] : 0.0;
+    }
+    __syncthreads();
+    const int ci = lane & 15, ck = lane >> 4;
+#pragma unroll
+    for (int kk = 0; kk < MK; kk += 4) {
+      const double a0 = As[wm * 32 + ci][kk + ck], a1 = As[wm * 32 + 16 + ci][kk + ck];
+      const double b0 = Bs[wq * 32 + ci][kk + ck], b1 = Bs[wq * 32 + 16 + ci][kk + ck];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // partial layout: [chunk] column-major m x q
+  double* P = part + (long)chunk * m * q;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = tm * MT + wm * 32 + 16 * a + (lane >> 4) + 4 * v;
+        const int j = tq * MT + wq * 32 + 16 * b + (lane & 15);
+        if (i < m && j < q) P[(long)j * m + i] = acc[a][b][v];
+      }
+}
+
+int gram_chunks_mfma(long nrows, int m, int q) {
+  // about 1024 workgroups in stage 1, at least 1024 rows per chunk
+  const long tiles = (long)((m + MT - 1) / MT) * ((q + MT - 1) / MT);
+  long c = 1024 / (tiles > 0 ? tiles : 1);
+  const long cmax = (nrows + 1023) / 1024;
+  if (c > cmax) c = cmax;
+  if (c > 256) c = 256;
+  if (c < 1) c = 1;
+  return (int)c;
+}
+
 template <typename T>
 void gram(hipStream_t st, long nrows, int m, const T* A, long lda, int q, const T* B, long ldb, double* C,
           double* part) {
@@ -454,7 +537,18 @@ void gram(hipStream_t st, long nrows, int m, const T* A, long lda, int q, const 
   const long count = (long)m * q;
   hipLaunchKernelGGL(k_sum_partials, dim3((count + 255) / 256), dim3(256), 0, st, nchunk, count, part, C);
 }
-template void gram<double>(hipStream_t, long, int, const double*, long, int, const double*, long, double*, double*);
+template <>
+void gram<double>(hipStream_t st, long nrows, int m, const double* A, long lda, int q, const double* B, long ldb,
+                  double* C, double* part) {
+  if (m <= 0 || q <= 0) return;
+  const int nchunk = gram_chunks_mfma(nrows, m, q);
+  long rpc = (nrows + nchunk - 1) / nchunk;
+  rpc = ((rpc + MK - 1) / MK) * MK;
+  dim3 grd((m + MT - 1) / MT, (q + MT - 1) / MT, nchunk);
+  hipLaunchKernelGGL(k_gram_mfma, grd, dim3(256), 0, st, nrows, rpc, m, A, lda, q, B, ldb, part);
+  const long count = (long)m * q;
+  hipLaunchKernelGGL(k_sum_partials, dim3((count + 255) / 256), dim3(256), 0, st, nchunk, count, part, C);
+}
 template void gram<float>(hipStream_t, long, int, const float*, long, int, const float*, long, double*, double*);
 
 // ---------------------------------------------------------------------------
@@ -515,8 +609,81 @@ void proj(hipStream_t st, long nrows, int m, const T* A, long lda, const double*
   dim3 grd((nrows + 255) / 256, (p + PT - 1) / PT);
   hipLaunchKernelGGL((k_proj<T>), grd, dim3(256), 0, st, nrows, m, A, lda, Q, ldq, p, C, ldc, beta);
 }
-template void proj<double>(hipStream_t, long, int, const double*, long, const double*, int, int, double*, long,
-                           double);
+
+// FP64 projection on the matrix cores, computed as C^T = Q^T A^T so that the
+// 16 lanes of one result row of an MFMA block hold 16 consecutive rows of C
+// (coalesced stores).  Workgroup: 64 rows x 64 output columns; the inner
+// dimension m is staged through LDS 32 at a time, A as [k][row] and Q as
+// [k][column]; each wave owns 32 rows x 32 columns as 2 x 2 MFMA blocks.
+constexpr int PR = 64, PC = 64, PK = 32;
+
+__global__ __launch_bounds__(256) void k_proj_mfma(long nrows, int m, const double* __restrict__ A, long lda,
+                                                   const double* __restrict__ Q, int ldq, int p,
+                                                   double* __restrict__ C, long ldc, double beta) {
+  __shared__ double As[PK][PR + 1];
+  __shared__ double Qs[PK][PC + 1];
+  const long row0 = (long)blockIdx.x * PR;
+  const int col0 = blockIdx.y * PC;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1;
+  gram_d4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = gram_d4{0.0, 0.0, 0.0, 0.0};
+  const int ar = tid & 63, ak = tid >> 6;  // A loader: row ar, k = ak + 4u
+  const int qk = tid & 31, qc = tid >> 5;  // Q loader: k = qk, column qc + 8u
+  const long grow = row0 + ar;
+  for (int k0 = 0; k0 < m; k0 += PK) {
+#pragma unroll
+    for (int u = 0; u < PK / 4; ++u) {
+      const int k = ak + 4 * u;
+      As[k][ar] = (k0 + k < m && grow < nrows) ? A[(long)(k0 + k) * lda + grow] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PC / 8; ++u) {
+      const int c = qc + 8 * u;
+      Qs[qk][c] = (k0 + qk < m && col0 + c < p) ? Q[(long)(col0 + c) * ldq + k0 + qk] : 0.0;
+    }
+    __syncthreads();
+    const int ci = lane & 15, ck = lane >> 4;
+#pragma unroll
+    for (int kk = 0; kk < PK; kk += 4) {
+      const double q0 = Qs[kk + ck][wc * 32 + ci], q1 = Qs[kk + ck][wc * 32 + 16 + ci];
+      const double a0 = As[kk + ck][wr * 32 + ci], a1 = As[kk + ck][wr * 32 + 16 + ci];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(q0, a0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(q0, a1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(q1, a0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(q1, a1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = col0 + wc * 32 + 16 * a + (lane >> 4) + 4 * v;
+        const long r = row0 + wr * 32 + 16 * b + (lane & 15);
+        if (j < p && r < nrows) {
+          double* dst = C + (long)j * ldc + r;
+          *dst = beta == 0.0 ? acc[a][b][v] : beta * (*dst) + acc[a][b][v];
+        }
+      }
+}
+
+template <>
+void proj<double>(hipStream_t st, long nrows, int m, const double* A, long lda, const double* Q, int ldq, int p,
+                  double* C, long ldc, double beta) {
+  if (p <= 0) return;
+  if (m <= 0) {
+    if (beta == 0.0) axpby<double>(st, nrows, p, C, ldc, C, ldc, 0.0, 0.0);
+    return;
+  }
+  dim3 grd((nrows + PR - 1) / PR, (p + PC - 1) / PC);
+  hipLaunchKernelGGL(k_proj_mfma, grd, dim3(256), 0, st, nrows, m, A, lda, Q, ldq, p, C, ldc, beta);
+}
 template void proj<float>(hipStream_t, long, int, const float*, long, const double*, int, int, float*, long, double);
 
 // ---------------------------------------------------------------------------
@@ -540,6 +707,37 @@ void mask_scale(hipStream_t st, long nx, int ncols, const T* X, long ldx, T* Y, 
 }
 template void mask_scale<double>(hipStream_t, long, int, const double*, long, double*, long, const uint8_t*, double);
 template void mask_scale<float>(hipStream_t, long, int, const float*, long, float*, long, const uint8_t*, double);
+
+// X[:,c] = w .* X[:,c] (a per-node weight applied to every column)
+__global__ void k_scale_nodes(long nx, double* __restrict__ X, long ldx, const double* __restrict__ w) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long c = blockIdx.y;
+  if (idx >= nx) return;
+  X[c * ldx + idx] *= w[idx];
+}
+void scale_nodes(hipStream_t st, long nx, int ncols, double* X, long ldx, const double* w) {
+  if (ncols <= 0) return;
+  hipLaunchKernelGGL(k_scale_nodes, dim3((nx + 255) / 256, ncols), dim3(256), 0, st, nx, X, ldx, w);
+}
+
+// A[i, i] += v (i < n), and A[j, i] = A[i, j] for i < j: the upper triangle
+// copied to the lower one (column-major, leading dimension lda)
+__global__ void k_add_diag(int n, double* A, long lda, double v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) A[(long)i * lda + i] += v;
+}
+__global__ void k_symmetrize_upper(int n, double* A, long lda) {
+  const int i = blockIdx.x * 16 + threadIdx.x, j = blockIdx.y * 16 + threadIdx.y;
+  if (i < n && j < n && i > j) A[(long)j * lda + i] = A[(long)i * lda + j];
+}
+void add_diag(hipStream_t st, int n, double* A, long lda, double v) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_add_diag, dim3((n + 255) / 256), dim3(256), 0, st, n, A, lda, v);
+}
+void symmetrize_upper(hipStream_t st, int n, double* A, long lda) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_symmetrize_upper, dim3((n + 15) / 16, (n + 15) / 16), dim3(16, 16), 0, st, n, A, lda);
+}
 
 // Y = a X + b Y (column blocks)
 template <typename T>
@@ -572,28 +770,6 @@ void d2f(hipStream_t st, long n, const double* x, float* y) {
 }
 void f2d(hipStream_t st, long n, const float* x, double* y) {
   if (n > 0) hipLaunchKernelGGL(k_f2d, dim3((n + 255) / 256), dim3(256), 0, st, n, x, y);
-}
-
-// ---------------------------------------------------------------------------
-// Projected time stepping: for every projected spatial mode i (Q^T M Q = I,
-// Q^T tau K Q = E diag(theta) E^T) the implicit-Euler recurrence
-// (1 + theta_i) z_k = z_{k-1} + g_k, z_0 = 0.  G: nt x q (column i = mode i),
-// Z: q x nt.
-// ---------------------------------------------------------------------------
-__global__ void k_time_recurrence(int q, int nt, const double* __restrict__ theta, const double* __restrict__ G,
-                                  double* __restrict__ Z) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= q) return;
-  const double inv = 1.0 / (1.0 + theta[i]);
-  double z = 0.0;
-  for (int k = 0; k < nt; ++k) {
-    z = (z + G[(long)i * nt + k]) * inv;
-    Z[(long)k * q + i] = z;
-  }
-}
-void time_recurrence(hipStream_t st, int q, int nt, const double* theta, const double* G, double* Z) {
-  if (q <= 0) return;
-  hipLaunchKernelGGL(k_time_recurrence, dim3((q + 63) / 64), dim3(64), 0, st, q, nt, theta, G, Z);
 }
 
 // ---------------------------------------------------------------------------

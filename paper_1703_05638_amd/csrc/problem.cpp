@@ -265,12 +265,13 @@ void Problem::upload_mg_params(const std::vector<ShiftCoef>& ab) {
 // run inside a single kernel with all data in LDS.  Smoothing alternates
 // between the level's x and t buffers, writing each iterate over the one two
 // steps back, so that with an odd step count the result lands in x.
-void Problem::vcycle_zero(int ncols, const double* B, double* X) {
+template <typename T>
+void Problem::vcycle_zero(int ncols, const T* B, T* X) {
   const int L = (int)lv.size();
   const double* P = mg_param_.as<double>();
   auto prm = [&](int l) { return P + (size_t)l * ncols * kMgStride; };
   if (lds_level == 0) {
-    mg_coarse_lds<double>(st, lv[0].n, L, ncols, B, nx, X, nx, prm(0), kMgNu, kMgNu);
+    mg_coarse_lds<T>(st, lv[0].n, L, ncols, B, nx, X, nx, prm(0), kMgNu, kMgNu);
     return;
   }
   // workspace: per level l >= 1: x, b, t (nx_l * ncols each); level 0: t
@@ -280,8 +281,9 @@ void Problem::vcycle_zero(int ncols, const double* B, double* X) {
     off[l] = tot;
     tot += 3 * (size_t)lv[l].nx * ncols;
   }
-  mg_work_.ensure(sizeof(double) * tot);
-  double* base = mg_work_.as<double>();
+  DevMem& work = sizeof(T) == sizeof(double) ? mg_work_ : mg_work_f_;
+  work.ensure(sizeof(T) * tot);
+  T* base = work.as<T>();
   auto xw = [&](int l) { return base + off[l]; };
   auto bw = [&](int l) { return base + off[l] + (size_t)lv[l].nx * ncols; };
   auto tw = [&](int l) { return base + off[l] + 2 * (size_t)lv[l].nx * ncols; };
@@ -289,33 +291,33 @@ void Problem::vcycle_zero(int ncols, const double* B, double* X) {
   for (int l = 0; l < lds_level; ++l) {
     const int nl = lv[l].n;
     const long ldl = lv[l].nx;
-    double* x = l == 0 ? X : xw(l);
-    const double* b = l == 0 ? B : bw(l);
-    double* t = l == 0 ? base : tw(l);
+    T* x = l == 0 ? X : xw(l);
+    const T* b = l == 0 ? B : bw(l);
+    T* t = l == 0 ? base : tw(l);
     for (int s = 0; s < kMgNu; ++s) {
-      const double* xc = s == 0 ? nullptr : ((s % 2) ? x : t);
-      double* xo = (s % 2 == 0) ? x : t;
-      const double* xp = s <= 1 ? nullptr : xo;
-      smooth_step(nl, ncols, xc, xp, xo, b, ldl, prm(l), s);
+      const T* xc = s == 0 ? nullptr : ((s % 2) ? x : t);
+      T* xo = (s % 2 == 0) ? x : t;
+      const T* xp = s <= 1 ? nullptr : xo;
+      smooth_step<T>(nl, ncols, xc, xp, xo, b, ldl, prm(l), s);
     }
-    mg_resid_restrict<double>(st, nl, ncols, x, b, ldl, bw(l + 1), lv[l + 1].nx, prm(l));
+    mg_resid_restrict<T>(st, nl, ncols, x, b, ldl, bw(l + 1), lv[l + 1].nx, prm(l));
   }
   // coarse levels in LDS
-  mg_coarse_lds<double>(st, lv[lds_level].n, L - lds_level, ncols, bw(lds_level), lv[lds_level].nx, xw(lds_level),
+  mg_coarse_lds<T>(st, lv[lds_level].n, L - lds_level, ncols, bw(lds_level), lv[lds_level].nx, xw(lds_level),
                         lv[lds_level].nx, prm(lds_level), kMgNu, kMgNu);
   // up: t = x + P e, then post-smoothing from t, x_s in (s even ? t : x)
   for (int l = lds_level - 1; l >= 0; --l) {
     const int nl = lv[l].n;
     const long ldl = lv[l].nx;
-    double* x = l == 0 ? X : xw(l);
-    const double* b = l == 0 ? B : bw(l);
-    double* t = l == 0 ? base : tw(l);
-    mg_prolong_add<double>(st, nl, ncols, xw(l + 1), lv[l + 1].nx, x, t, ldl);
+    T* x = l == 0 ? X : xw(l);
+    const T* b = l == 0 ? B : bw(l);
+    T* t = l == 0 ? base : tw(l);
+    mg_prolong_add<T>(st, nl, ncols, xw(l + 1), lv[l + 1].nx, x, t, ldl);
     for (int s = 0; s < kMgNu; ++s) {
-      const double* xc = (s % 2 == 0) ? t : x;
-      double* xo = (s % 2 == 0) ? x : t;
-      const double* xp = s == 0 ? nullptr : xo;
-      smooth_step(nl, ncols, xc, xp, xo, b, ldl, prm(l), s);
+      const T* xc = (s % 2 == 0) ? t : x;
+      T* xo = (s % 2 == 0) ? x : t;
+      const T* xp = s == 0 ? nullptr : xo;
+      smooth_step<T>(nl, ncols, xc, xp, xo, b, ldl, prm(l), s);
     }
   }
 }
@@ -323,10 +325,11 @@ void Problem::vcycle_zero(int ncols, const double* B, double* X) {
 // One Chebyshev smoother step; with profiling on, bracketed by HIP events on
 // the problem's stream and credited with its algorithmic traffic: read xc,
 // xp and b once, write xo once (neighbour reads of xc are cache hits).
-void Problem::smooth_step(int nl, int ncols, const double* xc, const double* xp, double* xo, const double* b, long ld,
-                          const double* prm, int s) {
+template <typename T>
+void Problem::smooth_step(int nl, int ncols, const T* xc, const T* xp, T* xo, const T* b, long ld, const double* prm,
+                          int s) {
   if (!prof_on) {
-    mg_smooth_step<double>(st, nl, ncols, xc, xp, xo, b, ld, prm, s);
+    mg_smooth_step<T>(st, nl, ncols, xc, xp, xo, b, ld, prm, s);
     return;
   }
   if (prof_used == prof_ev.size()) {
@@ -337,10 +340,10 @@ void Problem::smooth_step(int nl, int ncols, const double* xc, const double* xp,
   }
   auto& ev = prof_ev[prof_used++];
   LRP_HIP(hipEventRecord(ev.first, st));
-  mg_smooth_step<double>(st, nl, ncols, xc, xp, xo, b, ld, prm, s);
+  mg_smooth_step<T>(st, nl, ncols, xc, xp, xo, b, ld, prm, s);
   LRP_HIP(hipEventRecord(ev.second, st));
   const int streams = 2 + (xc ? 1 : 0) + (xp ? 1 : 0);
-  prof_bytes += (double)streams * sizeof(double) * (double)nl * nl * ncols;
+  prof_bytes += (double)streams * sizeof(T) * (double)nl * nl * ncols;
 }
 
 void Problem::prof_read(int64_t* launches, double* ms, double* bytes) {
@@ -358,27 +361,71 @@ void Problem::prof_read(int64_t* launches, double* ms, double* bytes) {
   prof_bytes = 0.0;
 }
 
-void Problem::mg_solve(int ncols, const double* B, double* X, const std::vector<ShiftCoef>& ab_in, int cycles) {
+void Problem::mg_cycles_f32(int ncols, const float* B, float* X, const std::vector<ShiftCoef>& neg, int cycles) {
+  vcycle_zero<float>(ncols, B, X);
+  if (cycles <= 1) return;
+  const size_t blk = (size_t)nx * ncols;
+  float* R = mg_f_.as<float>() + 2 * blk;
+  float* E = R + blk;
+  op_w_h_.assign((size_t)4 * ncols, 0.0);
+  for (int c = 0; c < ncols; ++c) {
+    stencil_weights(neg[c].a, neg[c].b, h, &op_w_h_[(size_t)4 * c]);
+    op_w_h_[(size_t)4 * c + 3] = 1.0;
+  }
+  op_w_.ensure(sizeof(double) * op_w_h_.size());
+  to_device(op_w_.as<double>(), op_w_h_.data(), op_w_h_.size());
+  for (int cyc = 1; cyc < cycles; ++cyc) {
+    stencil<float>(st, n, ncols, X, nx, R, nx, B, nx, op_w_.as<double>());  // R = B - A X
+    vcycle_zero<float>(ncols, R, E);
+    axpby<float>(st, nx, ncols, E, nx, X, nx, 1.0, 1.0);
+  }
+}
+
+void Problem::mg_solve(int ncols, const double* B, double* X, const std::vector<ShiftCoef>& ab_in, int cycles,
+                       int refine) {
   if (ncols <= 0) return;
   std::vector<ShiftCoef> ab(ncols);
   for (int c = 0; c < ncols; ++c) ab[c] = ab_in.size() == 1 ? ab_in[0] : ab_in[c];
   upload_mg_params(ab);
-  vcycle_zero(ncols, B, X);
+  std::vector<ShiftCoef> neg(ncols);
+  for (int c = 0; c < ncols; ++c) neg[c] = {-ab[c].a, -ab[c].b};
+  std::vector<double> one(1, 1.0);
+  const size_t blk = (size_t)nx * ncols;
+  if (desc.precision == LRPOST_MIXED) {
+    // float32 V-cycles; each refinement round solves for the correction of
+    // the float64 residual and adds it in float64
+    mg_f_.ensure(sizeof(float) * 4 * blk);
+    float* Bf = mg_f_.as<float>();
+    float* Xf = Bf + blk;
+    d2f(st, (long)blk, B, Bf);
+    mg_cycles_f32(ncols, Bf, Xf, neg, cycles);
+    f2d(st, (long)blk, Xf, X);
+    if (refine > 0) {
+      mg_res_.ensure(sizeof(double) * blk);
+      double* R = mg_res_.as<double>();
+      for (int r = 0; r < refine; ++r) {
+        apply_op(ncols, X, R, neg, B, &one);  // R = B - A X in float64
+        d2f(st, (long)blk, R, Bf);
+        mg_cycles_f32(ncols, Bf, Xf, neg, cycles);
+        f2d(st, (long)blk, Xf, R);
+        axpby<double>(st, nx, ncols, R, nx, X, nx, 1.0, 1.0);
+      }
+    }
+    LRP_HIP(hipGetLastError());
+    return;
+  }
+  vcycle_zero<double>(ncols, B, X);
   if (cycles <= 1) {
     LRP_HIP(hipGetLastError());
     return;
   }
   // residual correction: X += V(B - A X)
-  const size_t blk = (size_t)nx * ncols;
   mg_res_.ensure(sizeof(double) * 2 * blk);
   double* R = mg_res_.as<double>();
   double* E = R + blk;
-  std::vector<ShiftCoef> neg(ncols);
-  for (int c = 0; c < ncols; ++c) neg[c] = {-ab[c].a, -ab[c].b};
-  std::vector<double> one(1, 1.0);
   for (int cyc = 1; cyc < cycles; ++cyc) {
     apply_op(ncols, X, R, neg, B, &one);
-    vcycle_zero(ncols, R, E);
+    vcycle_zero<double>(ncols, R, E);
     axpby<double>(st, nx, ncols, E, nx, X, nx, 1.0, 1.0);
   }
   LRP_HIP(hipGetLastError());
@@ -387,7 +434,7 @@ void Problem::mg_solve(int ncols, const double* B, double* X, const std::vector<
 void Problem::gram(int m, const double* A, int q, const double* B, std::vector<double>& C) {
   C.assign((size_t)m * q, 0.0);
   if (m <= 0 || q <= 0) return;
-  const int nchunk = gram_chunks(nx, m, q);
+  const int nchunk = gram_chunks_mfma(nx, m, q);
   gram_part_.ensure(sizeof(double) * (size_t)nchunk * m * q);
   gram_out_.ensure(sizeof(double) * (size_t)m * q);
   ::lrp::gram<double>(st, nx, m, A, nx, q, B, nx, gram_out_.as<double>(), gram_part_.as<double>());
@@ -405,7 +452,7 @@ void Problem::proj(int m, const double* A, const std::vector<double>& Q, int p, 
 
 void Problem::gram_dev(int m, const double* A, int q, const double* B, double* C) {
   if (m <= 0 || q <= 0) return;
-  const int nchunk = gram_chunks(nx, m, q);
+  const int nchunk = gram_chunks_mfma(nx, m, q);
   gram_part_.ensure(sizeof(double) * (size_t)nchunk * m * q);
   ::lrp::gram<double>(st, nx, m, A, nx, q, B, nx, C, gram_part_.as<double>());
   LRP_HIP(hipGetLastError());
@@ -415,6 +462,48 @@ void Problem::proj_dev(int m, const double* A, const double* Q, int ldq, int p, 
   if (p <= 0) return;
   ::lrp::proj<double>(st, nx, m, A, nx, Q, ldq, p, C, nx, beta);
   LRP_HIP(hipGetLastError());
+}
+
+// K and M are diagonalized by the two-dimensional discrete sine transform
+// S kron S with the orthonormal, symmetric DST-I matrix
+// S[i][p] = sqrt(2/(n+1)) sin((i+1)(p+1) pi/(n+1)).  With the 1D eigenvalues
+// k_p = (2/h)(1 - cos t_p) of K1 = tridiag(-1, 2, -1)/h and
+// m_p = (h/3)(2 + cos t_p) of M1 = (h/6) tridiag(1, 4, 1), t_p = (p+1) pi h,
+// mode (p, q) of K + M = K1 kron M1 + M1 kron K1 + M1 kron M1 has eigenvalue
+// k_p m_q + m_p k_q + m_p m_q.  The prior covariance's symmetric root
+// (alpha tau)^{-1/2} (K+M)^{-1/2} is then S2 diag(w) S2 with w the scaled
+// inverse square roots; on a nodal vector viewed as the n x n matrix
+// X[i, j] (x1 index i fastest) it is S (w .* (S X S)) S.
+void Problem::prior_sqrt(int ncols, const double* X, double* Y) {
+  if (ncols <= 0) return;
+  if (!sine_.p) {
+    std::vector<double> S((size_t)n * n), w(nx), k1(n), m1(n);
+    const double sc = std::sqrt(2.0 / (n + 1));
+    for (int p = 0; p < n; ++p) {
+      for (int i = 0; i < n; ++i) S[(size_t)p * n + i] = sc * std::sin(M_PI * (double)(i + 1) * (p + 1) / (n + 1));
+      const double c = std::cos(M_PI * (p + 1) * h);
+      k1[p] = 2.0 / h * (1.0 - c);
+      m1[p] = h / 3.0 * (2.0 + c);
+    }
+    const double s = 1.0 / std::sqrt(desc.alpha * tau);
+    for (int q = 0; q < n; ++q)
+      for (int p = 0; p < n; ++p) w[(size_t)q * n + p] = s / std::sqrt(k1[p] * m1[q] + m1[p] * k1[q] + m1[p] * m1[q]);
+    sine_.ensure(sizeof(double) * S.size());
+    root_w_.ensure(sizeof(double) * w.size());
+    to_device(sine_.as<double>(), S.data(), S.size());
+    to_device(root_w_.as<double>(), w.data(), w.size());
+  }
+  const double* S = sine_.as<double>();
+  sqrt_tmp_.ensure(sizeof(double) * (size_t)nx * ncols);
+  double* T = sqrt_tmp_.as<double>();
+  const long nn = (long)n * n;
+  // along x1: T = S X over all n * ncols lines; along x2: Y_c = T_c S per vector
+  dense->gemm(false, false, n, n * ncols, n, 1.0, S, n, X, n, 0.0, T, n);
+  dense->gemm_strided_batched(false, false, n, n, n, 1.0, T, n, nn, S, n, 0, 0.0, Y, n, nn, ncols);
+  scale_nodes(st, nx, ncols, Y, nx, root_w_.as<double>());
+  LRP_HIP(hipGetLastError());
+  dense->gemm_strided_batched(false, false, n, n, n, 1.0, Y, n, nn, S, n, 0, 0.0, T, n, nn, ncols);
+  dense->gemm(false, false, n, n * ncols, n, 1.0, S, n, T, n, 0.0, Y, n);
 }
 
 void Problem::sym_eig(int nn, const double* A, int lda, std::vector<double>& w, std::vector<double>& V) {
@@ -566,39 +655,46 @@ void Problem::spacetime_solve(const LowRank& F, LowRank& Y, bool adjoint) {
     double ref = 0.0;
     for (int c = 0; c < r1; ++c) ref = std::max(ref, Gw[(size_t)c * r1 + c]);
     if (!(ref > 0)) continue;
-    // block CGS2 against Q in the M inner product
-    for (int pass = 0; pass < 2 && q > 0; ++pass) {
-      if (pass > 0) apply_op(r1, W, MW, Mop);
-      gram(q, Q, r1, MW, C);
-      for (double& x : C) x = -x;
-      proj(q, Q, C, r1, W, 1.0);
-    }
-    // within the block: two eigen-based orthonormalization passes in the M
-    // inner product (SVQB, Stathopoulos and Wu 2002), dropping directions whose
-    // M-norm after the projection is below 1e-11 of the block's original
-    // scale (already in span(Q)).  A Gram-based Cholesky cannot tell such
+    // Block Gram-Schmidt against Q in the M inner product, twice, with the
+    // block normalized between the two sweeps: (1) project the raw block
+    // out of span(Q); (2) orthonormalize it by its Gram eigenpairs (SVQB,
+    // Stathopoulos and Wu 2002), dropping directions whose M-norm fell below
+    // 1e-11 of the block's original scale; (3) project the normalized block
+    // out of span(Q) again: a direction that kept little of its norm in (1)
+    // carries the rounding of that sweep magnified by the normalization,
+    // and this sweep removes it; (4) orthonormalize again, dropping
+    // directions that now keep less than 1e-4 of their norm (they were
+    // inside span(Q)).  A Gram-based Cholesky cannot tell nearly dependent
     // directions from rounding noise, so it is not used here.
-    int kcols = r1;
-    double* src = W;
-    for (int pass = 0; pass < 2; ++pass) {
-      apply_op(kcols, src, MW, Mop);
-      gram(kcols, src, kcols, MW, Gw);
-      wv.assign(kcols, 0.0);
-      Uv.assign((size_t)kcols * kcols, 0.0);
-      if (!syev(kcols, Gw.data(), kcols, wv.data(), Uv.data())) fail(LRPOST_EBREAKDOWN, "basis Gram eigensolve");
+    auto sweep = [&](int kc, double* X) {
+      if (q == 0 || kc == 0) return;
+      apply_op(kc, X, MW, Mop);
+      gram(q, Q, kc, MW, C);
+      for (double& x : C) x = -x;
+      proj(q, Q, C, kc, X, 1.0);
+    };
+    auto svqb = [&](int kc, const double* src, double* dst, double thresh) -> int {
+      apply_op(kc, src, MW, Mop);
+      gram(kc, src, kc, MW, Gw);
+      wv.assign(kc, 0.0);
+      Uv.assign((size_t)kc * kc, 0.0);
+      if (!syev(kc, Gw.data(), kc, wv.data(), Uv.data())) fail(LRPOST_EBREAKDOWN, "basis Gram eigensolve");
       std::vector<int> kk;
-      for (int j = kcols - 1; j >= 0; --j)
-        if (wv[j] > 1e-22 * ref) kk.push_back(j);
+      for (int j = kc - 1; j >= 0; --j)
+        if (wv[j] > thresh) kk.push_back(j);
       const int kn = (int)kk.size();
-      if (kn == 0) { kcols = 0; break; }
-      std::vector<double> Tm((size_t)kcols * kn);
+      if (kn == 0) return 0;
+      std::vector<double> Tm((size_t)kc * kn);
       for (int c = 0; c < kn; ++c)
-        for (int i = 0; i < kcols; ++i) Tm[(size_t)c * kcols + i] = Uv[(size_t)kk[c] * kcols + i] / std::sqrt(wv[kk[c]]);
-      double* dst = pass == 0 ? W2 : Q + (size_t)q * nx;
-      proj(kcols, src, Tm, kn, dst, 0.0);
-      src = dst;
-      kcols = kn;
-    }
+        for (int i = 0; i < kc; ++i) Tm[(size_t)c * kc + i] = Uv[(size_t)kk[c] * kc + i] / std::sqrt(wv[kk[c]]);
+      proj(kc, src, Tm, kn, dst, 0.0);
+      return kn;
+    };
+    sweep(r1, W);
+    int kcols = svqb(r1, W, W2, 1e-22 * ref);
+    if (kcols == 0) continue;
+    sweep(kcols, W2);
+    kcols = svqb(kcols, W2, Q + (size_t)q * nx, 1e-8);
     if (kcols == 0) continue;
     // extend Kt = Q^T tau K Q by the new columns (upper triangle suffices)
     double* Qn = Q + (size_t)q * nx;
@@ -615,24 +711,53 @@ void Problem::spacetime_solve(const LowRank& F, LowRank& Y, bool adjoint) {
     Y.resize(nx, nt, 0);
     return;
   }
-  // 3. projected problem on the device: Kt = E diag(theta) E^T
-  st_small_.ensure(sizeof(double) * ((size_t)q + (size_t)q * r1 * 2 + (size_t)nt * r1 + (size_t)nt * q * 3 +
-                                     (size_t)q * q + (size_t)nt * nt + 64));
-  double* theta = st_small_.as<double>();
-  double* S = theta + q;                    // q x r1 = Q^T Fb
-  double* Bh = S + (size_t)q * r1;          // q x r1 = E^T S
-  double* F2d = Bh + (size_t)q * r1;        // nt x r1
-  double* Gt = F2d + (size_t)nt * r1;       // nt x q
-  double* Z = Gt + (size_t)nt * q;          // q x nt
-  double* Zp = Z + (size_t)q * nt;          // q x nt = E Z
-  double* Gsm = Zp + (size_t)q * nt;        // Gram for the truncation (max(q, nt)^2)
-  dense->syevd(q, Kt, qmax, theta, eig_work_);
+  // 3. projected problem on the device.  With Q^T M Q = I each column obeys
+  // (I + Kt) z_k = z_{k-1} + g_k, g_k = S F2p^T e_k: a linear recurrence
+  // z_k = A z_{k-1} + A g_k with the constant matrix A = (I + Kt)^{-1}
+  // (Cholesky inverse).  It is evaluated by recursive doubling over time:
+  // after the level with stride d, X[:, k] = sum_{j < 2d, j <= k} A^j (A G)[:, k-j];
+  // the next level adds A^{2d} X[:, k - 2d].  The eigenvalues of A lie in
+  // (0, 1], so the powers stay bounded.
+  const int gmax = std::max(q, nt);
+  st_small_.ensure(sizeof(double) * ((size_t)q * r1 + (size_t)nt * r1 + 2 * (size_t)q * nt + 3 * (size_t)q * q +
+                                     (size_t)gmax * gmax + (size_t)gmax + 64));
+  double* S = st_small_.as<double>();       // q x r1 = Q^T Fb
+  double* F2d = S + (size_t)q * r1;         // nt x r1
+  double* X1 = F2d + (size_t)nt * r1;       // q x nt
+  double* X2 = X1 + (size_t)q * nt;         // q x nt
+  double* Ainv = X2 + (size_t)q * nt;       // q x q: I + Kt, then A = (I + Kt)^{-1}
+  double* P1 = Ainv + (size_t)q * q;        // q x q powers of A
+  double* P2 = P1 + (size_t)q * q;
+  double* Gsm = P2 + (size_t)q * q;         // Gram for the truncation (max(q, nt)^2)
+  double* Gt = Gsm + (size_t)gmax * gmax;   // max(q, nt) eigenvalues
+  LRP_HIP(hipMemcpy2DAsync(Ainv, sizeof(double) * q, Kt, sizeof(double) * qmax, sizeof(double) * q, q,
+                           hipMemcpyDeviceToDevice, st));
+  add_diag(st, q, Ainv, q, 1.0);
+  if (!dense->spd_inverse_upper(q, Ainv, q, eig_work_))
+    fail(LRPOST_EBREAKDOWN, "projected I + tau K is not positive definite");
+  symmetrize_upper(st, q, Ainv, q);
   gram_dev(q, Q, r1, Fb, S);
-  dense->gemm(true, false, q, r1, q, 1.0, Kt, qmax, S, q, 0.0, Bh, q);
   to_device(F2d, F2p.data(), (size_t)nt * r1);
-  dense->gemm(false, true, nt, q, r1, 1.0, F2d, nt, Bh, q, 0.0, Gt, nt);
-  time_recurrence(st, q, nt, theta, Gt, Z);
-  dense->gemm(false, false, q, nt, q, 1.0, Kt, qmax, Z, q, 0.0, Zp, q);
+  dense->gemm(false, true, q, nt, r1, 1.0, S, q, F2d, nt, 0.0, X2, q);        // G = S F2p^T
+  dense->gemm(false, false, q, nt, q, 1.0, Ainv, q, X2, q, 0.0, X1, q);       // A G
+  const double* Apow = Ainv;
+  int ldp = q;
+  double* cur = X1;
+  double* nxt = X2;
+  double* pw = P1;
+  for (int d = 1; d < nt; d *= 2) {
+    LRP_HIP(hipMemcpyAsync(nxt, cur, sizeof(double) * (size_t)q * nt, hipMemcpyDeviceToDevice, st));
+    dense->gemm(false, false, q, nt - d, q, 1.0, Apow, ldp, cur, q, 1.0, nxt + (size_t)d * q, q);
+    std::swap(cur, nxt);
+    if (2 * d < nt) {
+      dense->gemm(false, false, q, q, q, 1.0, Apow, ldp, Apow, ldp, 0.0, pw, q);
+      Apow = pw;
+      ldp = q;
+      pw = pw == P1 ? P2 : P1;
+    }
+  }
+  double* Zp = cur;  // q x nt: Y = Q Zp
+  double* Z = nxt;   // scratch (q x nt)
   // 4. truncation of Y = Q Zp (Q M-orthonormal: M-weighted Frobenius norm)
   const bool accurate = desc.trunc_tol < 1e-7;
   double tail = 0.0;
@@ -719,7 +844,10 @@ void Problem::hess_apply(const LowRank& x, LowRank& y, bool precond) {
       DevMem mp;
       mp.ensure(sizeof(double) * (size_t)nx * P.rank);
       apply_op(P.rank, P.a(), mp.as<double>(), {{0.0, 1.0}});
-      mg_solve(P.rank, mp.as<double>(), y.a(), {{1.0, 1.0}}, prior_cycles);
+      if (desc.precision == LRPOST_MIXED)  // float32 cycles, float64 refinement rounds
+        mg_solve(P.rank, mp.as<double>(), y.a(), {{1.0, 1.0}}, (prior_cycles + 1) / 2, desc.trunc_tol < 1e-7 ? 2 : 1);
+      else
+        mg_solve(P.rank, mp.as<double>(), y.a(), {{1.0, 1.0}}, prior_cycles);
       axpby<double>(st, nx, P.rank, y.a(), nx, y.a(), nx, 1.0 / desc.alpha, 0.0);
     } else {
       apply_op(P.rank, P.a(), y.a(), {{0.0, tau}});

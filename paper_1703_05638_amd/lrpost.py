@@ -49,7 +49,8 @@ class LowRankC(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("applies", ctypes.c_int64), ("last_rank_y", ctypes.c_int32), ("last_rank_p", ctypes.c_int32),
                 ("last_rank_out", ctypes.c_int32), ("last_basis", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("last_tail", ctypes.c_double), ("last_st_resid", ctypes.c_double)]
+                ("pad", ctypes.c_int32), ("last_tail", ctypes.c_double), ("last_st_resid", ctypes.c_double),
+                ("ritz_resid", ctypes.c_double)]
 
 
 _lib = None
@@ -78,6 +79,7 @@ def load(path: str = LIB_PATH):
         "lrpost_hess_apply_batch": (I, [P, I, ctypes.POINTER(LowRankC), ctypes.POINTER(LowRankC), I]),
         "lrpost_spacetime_solve": (I, [P, ctypes.POINTER(LowRankC), ctypes.POINTER(LowRankC), I]),
         "lrpost_eigensolve": (I, [P, I, I, I, ctypes.POINTER(P)]),
+        "lrpost_eigensolve_probes": (I, [P, I, I, ctypes.POINTER(LowRankC), ctypes.POINTER(P)]),
         "lrpost_eig_count": (I, [P]),
         "lrpost_eig_values": (I, [P, pd]),
         "lrpost_eig_vector": (I, [P, I, ctypes.POINTER(LowRankC)]),
@@ -86,7 +88,7 @@ def load(path: str = LIB_PATH):
         "lrpost_eigs_from_pairs": (I, [P, I, pd, ctypes.POINTER(LowRankC), ctypes.POINTER(P)]),
         "lrpost_post_variance": (I, [P, P, P, I]),
         "lrpost_prior_variance": (I, [P, pd]),
-        "lrpost_sample": (I, [P, P, I, pd, pd]),
+        "lrpost_sample": (I, [P, P, I, P, P, I]),
         "lrpost_get_stats": (I, [P, ctypes.POINTER(Stats)]),
         "lrpost_stencil_apply": (I, [P, I, P, P, P, pd]),
         "lrpost_mg_solve": (I, [P, I, P, P, pd, I]),
@@ -95,6 +97,11 @@ def load(path: str = LIB_PATH):
         "lrpost_set_log": (I, [P, I]),
         "lrpost_profile": (I, [P, I]),
         "lrpost_profile_read": (I, [P, ctypes.POINTER(ctypes.c_int64), pd, pd]),
+        "lrpost_server_create": (I, [ctypes.c_size_t, I, ctypes.POINTER(P)]),
+        "lrpost_server_submit": (I, [P, P, I, I, ctypes.POINTER(ctypes.c_uint64)]),
+        "lrpost_server_wait": (I, [P, ctypes.c_uint64, pd, I, pd, pd]),
+        "lrpost_server_info": (I, [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_size_t)]),
+        "lrpost_server_destroy": (I, [P]),
         "lrpost_last_error": (ctypes.c_char_p, []),
         "lrpost_version": (ctypes.c_char_p, []),
     }
@@ -125,6 +132,65 @@ def _hptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
+def _make_desc(desc, seed: int = 2, mg_levels: int = 0, stream_ptr=None) -> "Desc":
+    d = Desc()
+    d.N, d.nt, d.T, d.alpha, d.sigma = desc.N, desc.nt, desc.T, desc.alpha, desc.sigma
+    for i in range(4):
+        d.box[i] = desc.box[i]
+    d.trunc_tol, d.rank_cap = desc.trunc_tol, desc.rank_cap
+    d.precision = LRPOST_MIXED if getattr(desc, "precision", "fp64") == "mixed" else LRPOST_FP64
+    d.mg_levels, d.seed = mg_levels, seed
+    d.hip_stream = ctypes.c_void_p(stream_ptr)
+    return d
+
+
+class Server:
+    """Serving loop: posterior requests run concurrently on `workers` streams,
+    admitted against a device-memory budget (lrpost_server_*)."""
+
+    def __init__(self, hbm_budget_bytes: int, workers: int = 4):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.lrpost_server_create(ctypes.c_size_t(int(hbm_budget_bytes)), workers, ctypes.byref(h)))
+        self.h = h
+        self._sizes = {}
+
+    def submit(self, desc, k: int, want_diag: bool = True, seed: int = 2) -> int:
+        d = _make_desc(desc, seed)
+        t = ctypes.c_uint64()
+        _check(_lib.lrpost_server_submit(self.h, ctypes.byref(d), k, 1 if want_diag else 0, ctypes.byref(t)))
+        self._sizes[t.value] = ((desc.N - 1) ** 2, desc.nt, k, want_diag)
+        return t.value
+
+    def wait(self, ticket: int):
+        """(eigenvalues (k,), variance (nt, nx) or None, latency in s)."""
+        nx, nt, k, want = self._sizes.pop(ticket)
+        lam = np.zeros(k)
+        D = np.zeros((nt, nx)) if want else None
+        lat = ctypes.c_double()
+        _check(_lib.lrpost_server_wait(self.h, ctypes.c_uint64(ticket), _hptr(lam), k,
+                                       D.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if want else None,
+                                       ctypes.byref(lat)))
+        return lam, D, lat.value
+
+    def info(self):
+        pr = ctypes.c_int()
+        pb = ctypes.c_size_t()
+        _check(_lib.lrpost_server_info(self.h, ctypes.byref(pr), ctypes.byref(pb)))
+        return {"peak_running": pr.value, "peak_admitted_bytes": pb.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.lrpost_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Problem:
     """A posterior problem on the GPU.  `desc` has the fields of synthetic.ProblemDesc."""
 
@@ -134,14 +200,7 @@ class Problem:
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
-        d = Desc()
-        d.N, d.nt, d.T, d.alpha, d.sigma = desc.N, desc.nt, desc.T, desc.alpha, desc.sigma
-        for i in range(4):
-            d.box[i] = desc.box[i]
-        d.trunc_tol, d.rank_cap = desc.trunc_tol, desc.rank_cap
-        d.precision = LRPOST_MIXED if getattr(desc, "precision", "fp64") == "mixed" else LRPOST_FP64
-        d.mg_levels, d.seed = mg_levels, seed
-        d.hip_stream = ctypes.c_void_p(stream.cuda_stream)
+        d = _make_desc(desc, seed, mg_levels, stream.cuda_stream)
         self._d = d
         h = ctypes.c_void_p()
         _check(lib.lrpost_create(ctypes.byref(d), ctypes.byref(h)))
@@ -236,6 +295,18 @@ class Problem:
         _check(_lib.lrpost_eigensolve(self.h, k, method, oversample, ctypes.byref(e)))
         return Eigs(self, e)
 
+    def eigensolve_probes(self, k: int, probes) -> "Eigs":
+        """Randomized two-pass eigensolver on caller probes [(W1 (r, nx) CUDA, W2 (r, nt) host), ...]."""
+        arr = (LowRankC * len(probes))()
+        keep = []
+        for i, (W1, W2) in enumerate(probes):
+            x = self._lr_in(W1, W2)
+            keep.append(x)
+            arr[i] = x
+        e = ctypes.c_void_p()
+        _check(_lib.lrpost_eigensolve_probes(self.h, k, len(probes), arr, ctypes.byref(e)))
+        return Eigs(self, e)
+
     def eigs_from_pairs(self, lam, vecs) -> "Eigs":
         lam = np.ascontiguousarray(lam, dtype=np.float64)
         arr = (LowRankC * len(vecs))()
@@ -258,6 +329,26 @@ class Problem:
         D = np.zeros((self.nt, self.nx))
         _check(_lib.lrpost_post_variance(self.h, eigs.h, D.ctypes.data_as(ctypes.c_void_p), 0))
         return D
+
+    def sample(self, eigs: "Eigs", xi):
+        """Posterior samples for standard normal draws xi of shape (ns, nt, nx)
+        (row t of sample s = time step t).  A CUDA float64 tensor stays on the
+        device; a NumPy array goes through host memory.  Same shape returned."""
+        torch = _torch()
+        if torch is not None and isinstance(xi, torch.Tensor):
+            if xi.device.type != "cuda" or xi.dtype != torch.float64 or xi.dim() != 3:
+                raise ValueError("xi must be a CUDA float64 tensor (ns, nt, nx)")
+            xi = xi.contiguous()
+            out = torch.empty_like(xi)
+            _check(_lib.lrpost_sample(self.h, eigs.h, xi.shape[0], _dptr(xi), _dptr(out), 1))
+            return out
+        xi = np.ascontiguousarray(xi, dtype=np.float64)
+        if xi.ndim != 3:
+            raise ValueError("xi must have shape (ns, nt, nx)")
+        out = np.zeros_like(xi)
+        _check(_lib.lrpost_sample(self.h, eigs.h, xi.shape[0], xi.ctypes.data_as(ctypes.c_void_p),
+                                  out.ctypes.data_as(ctypes.c_void_p), 0))
+        return out
 
     def set_log(self, level: int):
         """Progress lines (JSON on stderr) from the eigensolvers when level > 0."""

@@ -1,0 +1,126 @@
+"""Summaries of rocprofv3 CSV output for the smoother kernel.
+
+Two modes, each printing a short text report:
+
+  python -m paper_1703_05638_amd.profile_summary stats DIR REGEX
+      kernel-trace statistics (``*_kernel_stats.csv``): the kernels by total
+      time and the line of the kernel matching REGEX.
+
+  python -m paper_1703_05638_amd.profile_summary traffic FETCH_DIR WRITE_DIR REGEX COPY_REGEX COPY_BYTES
+      counter collection (``*_counter_collection.csv``) of two runs, one with
+      FETCH_SIZE and one with WRITE_SIZE (KiB per dispatch).  A plain copy
+      kernel that moves COPY_BYTES in and COPY_BYTES out gives one scale
+      factor per counter (counter reading / true bytes); the matched kernel's
+      average readings per dispatch are divided by them.  The report records
+      a digest of the kernel's source so that a reader can tell when the
+      figure no longer describes the kernel.
+"""
+import csv
+import glob
+import hashlib
+import os
+import re
+import statistics
+import sys
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+
+
+def smoother_source_digest():
+    """sha256 of the Chebyshev smoother kernel and its launcher in kernels.hip."""
+    src = open(os.path.join(ROOT, "csrc", "kernels.hip")).read()
+    a = src.index("void k_cheb(")
+    b = src.index("template void mg_smooth_step<float>")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+
+
+def _rows(d, suffix):
+    files = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not files:
+        raise SystemExit("no *%s under %s" % (suffix, d))
+    out = []
+    for f in files:
+        with open(f, newline="") as fh:
+            out.extend(csv.DictReader(fh))
+    return out
+
+
+def stats(d, regex):
+    rows = _rows(d, "kernel_stats.csv")
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    pat = re.compile(regex)
+    print("%-60s %10s %14s %12s %7s" % ("kernel", "calls", "total_ms", "avg_us", "pct"))
+    for r in rows[:15]:
+        print("%-60s %10s %14.3f %12.3f %7.2f" % (r["Name"][:60], r["Calls"], float(r["TotalDurationNs"]) / 1e6,
+                                                  float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+    for r in rows:
+        if pat.search(r["Name"]):
+            print("matched: %s calls=%s avg_us=%.3f total_ms=%.3f" % (r["Name"], r["Calls"], float(r["AverageNs"]) / 1e3,
+                                                                      float(r["TotalDurationNs"]) / 1e6))
+
+
+def _per_dispatch(rows, regex, counter):
+    pat = re.compile(regex)
+    acc = {}
+    for r in rows:
+        if r["Counter_Name"] != counter or not pat.search(r["Kernel_Name"]):
+            continue
+        key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        acc[key] = acc.get(key, 0.0) + float(r["Counter_Value"])
+    return list(acc.values())
+
+
+def traffic(fetch_dir, write_dir, regex, copy_regex, copy_bytes):
+    fr = _rows(fetch_dir, "counter_collection.csv")
+    wr = _rows(write_dir, "counter_collection.csv")
+    kf = _per_dispatch(fr, regex, "FETCH_SIZE")
+    kw = _per_dispatch(wr, regex, "WRITE_SIZE")
+    cf = _per_dispatch(fr, copy_regex, "FETCH_SIZE")
+    cw = _per_dispatch(wr, copy_regex, "WRITE_SIZE")
+    if not (kf and kw and cf and cw):
+        raise SystemExit("missing dispatches: kernel %d/%d copy %d/%d" % (len(kf), len(kw), len(cf), len(cw)))
+    # each counter is scaled by what it reads for the copy (which moves
+    # copy_bytes in and copy_bytes out)
+    f_fetch = statistics.median(cf) * 1024.0 / copy_bytes
+    f_write = statistics.median(cw) * 1024.0 / copy_bytes
+    per_launch = (statistics.mean(kf) / f_fetch + statistics.mean(kw) / f_write) * 1024.0
+    print("kernel_regex: %s" % regex)
+    print("kernel_source_sha256_16: %s" % smoother_source_digest())
+    print("dispatches_fetch: %d" % len(kf))
+    print("dispatches_write: %d" % len(kw))
+    print("fetch_kib_per_dispatch_mean: %.3f" % statistics.mean(kf))
+    print("write_kib_per_dispatch_mean: %.3f" % statistics.mean(kw))
+    print("copy_regex: %s" % copy_regex)
+    print("copy_bytes_each_way: %d" % copy_bytes)
+    print("copy_fetch_kib_median: %.3f" % statistics.median(cf))
+    print("copy_write_kib_median: %.3f" % statistics.median(cw))
+    print("fetch_scale_factor: %.6f" % f_fetch)
+    print("write_scale_factor: %.6f" % f_write)
+    print("traffic_bytes_per_launch: %.1f" % per_launch)
+
+
+def read_traffic(path):
+    """traffic_bytes_per_launch from a committed report, or None when the report
+    is absent or the smoother source has changed since it was taken."""
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != smoother_source_digest():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+if __name__ == "__main__":
+    if len(sys.argv) >= 4 and sys.argv[1] == "stats":
+        stats(sys.argv[2], sys.argv[3])
+    elif len(sys.argv) >= 7 and sys.argv[1] == "traffic":
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], int(sys.argv[6]))
+    else:
+        raise SystemExit(__doc__)

@@ -225,3 +225,139 @@ def test_truncation_of_ill_conditioned_concatenation(lp):
     R1, R2 = truncate_dense(X, 1e-10)
     assert W1.shape[0] == R1.shape[1]
     assert np.linalg.norm(got - R1 @ R2.T) <= 1e-13 * np.linalg.norm(X) + 1e-12 * np.linalg.norm(R1 @ R2.T - X)
+
+
+def test_samples_match_oracle(lp):
+    """Posterior draws s = (I - V diag(p) V^T P) L xi for fixed xi against the
+    oracle, with the oracle's dense-pencil eigenpairs handed in through
+    eigs_from_pairs (so only the sampling map is compared).  Host and device
+    buffers both."""
+    from oracle import posterior
+    print("case samples N=16 nt=4", flush=True)
+    d = _desc(16, 4, tol=1e-12, cap=4)
+    ora = OP.from_desc(d)
+    lam, V = posterior.eig_dense(ora, 5)
+    prob = lp.Problem(d)
+    vecs = []
+    for i in range(len(lam)):
+        X = V[:, i].reshape((ora.nx, ora.nt), order="F")
+        U, s, Wt = np.linalg.svd(X, full_matrices=False)
+        vecs.append((_dev((U * s).T), Wt))
+    eig = prob.eigs_from_pairs(lam, vecs)
+    xi = synthetic.sample_normals(3, ora.nx, ora.nt)  # (ns, nx, nt)
+    ref = posterior.samples(ora, lam, V, xi)
+    xt = np.ascontiguousarray(np.transpose(xi, (0, 2, 1)))  # (ns, nt, nx)
+    got_h = prob.sample(eig, xt)
+    got_d = prob.sample(eig, _dev(xt)).cpu().numpy()
+    for got in (got_h, got_d):
+        err = np.abs(np.transpose(got, (0, 2, 1)) - ref).max() / np.abs(ref).max()
+        print("sample rel err %.3e" % err, flush=True)
+        assert err < 1e-12
+
+
+def test_prior_root_at_bench_size(lp):
+    """At N = 256, nt = 4: the sample map with no eigenpairs is the prior root L,
+    and L^T P L = I, i.e. alpha tau <L x, (K+M) L y> = <x, y> for every pair
+    (a property of the symmetric root that holds at any size)."""
+    print("case prior root N=256", flush=True)
+    d = _desc(256, 4, tol=1e-6, cap=8)
+    prob = lp.Problem(d)
+    eig = prob.eigs_from_pairs(np.zeros(0), [])
+    rng = np.random.default_rng(5)
+    xi = rng.standard_normal((2, d.nt, prob.nx))
+    L = prob.sample(eig, _dev(xi)).cpu().numpy()  # (2, nt, nx)
+    K, M = fem.assemble_kronecker(256)
+    at = d.alpha / d.nt
+    G = np.array([[at * np.sum(L[a] * ((K + M) @ L[b].T).T) for b in range(2)] for a in range(2)])
+    E = np.array([[np.sum(xi[a] * xi[b]) for b in range(2)] for a in range(2)])
+    print("L^T P L err %.3e" % (np.abs(G - E).max() / np.abs(E).max()), flush=True)
+    assert np.allclose(G, E, rtol=1e-11, atol=1e-11 * np.abs(E).max())
+
+
+def test_randomized_eigensolver_matches_oracle(lp):
+    """Two-pass randomized eigensolver on the same seeded low-rank probes as the
+    oracle (32 x 32 mesh, nt = 40, tol 1e-10): the top Ritz values agree to
+    1e-8 relative, and the Ritz residual certificate is small."""
+    from oracle.randomized import probes_from_factors, randomized_eig
+    print("case randomized N=32 nt=40", flush=True)
+    d = _desc(32, 40, tol=1e-10, cap=40)
+    ora = OP.from_desc(d)
+    G1, G2 = synthetic.probe_factors(ora.nx, ora.nt, count=16, rank=4)
+    theta_ref, _, res_ref = randomized_eig(ora, probes_from_factors(G1, G2), 10)
+    prob = lp.Problem(d)
+    probes = [(_dev(G1[j].T), G2[j].T / 2.0) for j in range(16)]  # G1 G2^T / sqrt(4)
+    eig = prob.eigensolve_probes(10, probes)
+    theta = eig.values()
+    rel = np.abs(theta - theta_ref) / theta_ref
+    st = prob.stats()
+    print("randomized rel err max %.3e, ritz resid gpu %.3e oracle %.3e" %
+          (rel.max(), st["ritz_resid"], (res_ref / theta_ref).max()), flush=True)
+    assert rel.max() < 1e-8
+    assert abs(st["ritz_resid"] - (res_ref / theta_ref).max()) < 1e-6
+
+
+def test_randomized_internal_probes_bound_lanczos(lp):
+    """LRPOST_RANDOMIZED with the library's own probes: Ritz values lie below the
+    converged Lanczos eigenvalues (Rayleigh-Ritz interlacing), and the leading
+    Ritz value is within its certified residual of the leading eigenvalue (for
+    a self-adjoint operator some eigenvalue lies within ||G x - theta x||_P of
+    theta; here the nearest one is lambda_1)."""
+    print("case randomized internal N=32 nt=40", flush=True)
+    d = _desc(32, 40, tol=1e-10, cap=40)
+    prob = lp.Problem(d)
+    lam = prob.eigensolve(10).values()
+    th = prob.eigensolve(10, method=lp.LRPOST_RANDOMIZED, oversample=10).values()
+    res = prob.stats()["ritz_resid"]
+    print("randomized vs lanczos:", th[:4], lam[:4], "max rel resid %.3e" % res, flush=True)
+    assert np.all(th <= lam * (1 + 1e-9))
+    assert abs(th[0] - lam[0]) <= res * th[0] * (1 + 1e-6)
+    assert abs(th[0] - lam[0]) < abs(th[0] - lam[1])
+
+
+def test_mixed_precision_within_1e5_of_oracle(lp, tiny_golden):
+    """LRPOST_MIXED at the 32 x 32 mesh, nt = 40: float32 multigrid (float64
+    refinement of the prior solve, float64 projections and truncations);
+    eigenvalues and the posterior variance within 1e-5 of the oracle."""
+    import dataclasses
+    print("case mixed tiny eigensolve", flush=True)
+    d = dataclasses.replace(synthetic.TINY_FP64, precision="mixed")
+    prob = lp.Problem(d)
+    eig = prob.eigensolve(d.k)
+    lam = eig.values()
+    ref = tiny_golden["lam"][: d.k]
+    rel = np.abs(lam - ref) / ref
+    D = prob.post_variance(eig).cpu().numpy()
+    relv = np.abs(D.T - tiny_golden["diag_k20"]) / np.abs(tiny_golden["diag_k20"])
+    print("mixed: eigenvalue rel err %.3e, variance rel err %.3e" % (rel.max(), relv.max()), flush=True)
+    assert rel.max() < 1e-5
+    assert relv.max() < 1e-5
+
+
+def test_server_results_alone_equal_in_the_mix(lp):
+    """Serving loop: six requests of different mesh and time sizes, priors,
+    noise levels and boxes submitted at once to four workers; every result
+    (eigenvalues and posterior variance) equals the same request solved alone
+    on a fresh problem to 1e-10 relative, and requests overlapped."""
+    import dataclasses
+    print("case server mix", flush=True)
+    base = synthetic.ProblemDesc(N=16, nt=8, trunc_tol=1e-10, rank_cap=16, k=6)
+    reqs = [dataclasses.replace(base, N=16, nt=8),
+            dataclasses.replace(base, N=32, nt=12, alpha=1e-3, box=(0.1, 0.6, 0.3, 0.9)),
+            dataclasses.replace(base, N=16, nt=16, sigma=1e-3),
+            dataclasses.replace(base, N=32, nt=8, box=(0.4, 0.9, 0.1, 0.5)),
+            dataclasses.replace(base, N=16, nt=12, alpha=1e-3, sigma=1e-3),
+            dataclasses.replace(base, N=32, nt=16)]
+    srv = lp.Server(hbm_budget_bytes=8 << 30, workers=4)
+    tickets = [srv.submit(d, d.k) for d in reqs]
+    mix = [srv.wait(t) for t in tickets]
+    info = srv.info()
+    srv.close()
+    print("server info", info, "latencies", [round(m[2], 3) for m in mix], flush=True)
+    assert info["peak_running"] >= 2
+    for d, (lam_mix, D_mix, _) in zip(reqs, mix):
+        prob = lp.Problem(d)
+        eig = prob.eigensolve(d.k)
+        lam = eig.values()
+        D = prob.post_variance(eig, on_device=False)
+        assert np.allclose(lam_mix, lam, rtol=1e-10, atol=0)
+        assert np.allclose(D_mix, D, rtol=1e-10, atol=0)
