@@ -115,10 +115,21 @@ int lrpost_hess_apply(lrpost_problem* p, const lrpost_lowrank* x, lrpost_lowrank
 int lrpost_hess_apply_batch(lrpost_problem* p, int nvec, const lrpost_lowrank* x, lrpost_lowrank* y, int which) {
   return guarded([&] {
     if (nvec < 0 || (nvec > 0 && (!x || !y))) fail(LRPOST_EINVAL, "bad batch");
+    if (which != LRPOST_MISFIT && which != LRPOST_PRECOND) fail(LRPOST_EINVAL, "which must be MISFIT or PRECOND");
+    Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
+    std::vector<LowRank> xs(nvec), ys(nvec);
+    std::vector<const LowRank*> px;
+    std::vector<LowRank*> py;
     for (int i = 0; i < nvec; ++i) {
-      const int rc = lrpost_hess_apply(p, x + i, y + i, which);
-      if (rc != LRPOST_OK) fail(rc, g_last_error);
+      check_lr(P, x + i, true);
+      if (y[i].nx != P->nx || y[i].nt != P->nt) fail(LRPOST_EINVAL, "output shape does not match the problem");
+      load_lr(P, x + i, xs[i]);
+      px.push_back(&xs[i]);
+      py.push_back(&ys[i]);
     }
+    P->hess_apply_batch(px, py, which == LRPOST_PRECOND);
+    for (int i = 0; i < nvec; ++i) store_lr(P, ys[i], y + i);
   });
 }
 

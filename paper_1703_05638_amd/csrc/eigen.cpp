@@ -507,17 +507,16 @@ EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rt
     const int j0 = block_start.back(), bj = block_size.back();
     // W = G V_j
     auto t0 = clk::now();
-    std::vector<LowRank> outs(bj);
+    std::vector<LowRank> outs(bj), xin(bj);
+    std::vector<const LowRank*> px;
+    std::vector<LowRank*> po;
     for (int i = 0; i < bj; ++i) {
-      LowRank x;
-      sb.materialize(sb.stored(j0 + i), x);
-      P->hess_apply(x, outs[i], true);
-      if (P->log_level > 1)
-        std::fprintf(stderr, "{\"apply\": %d, \"rank_in\": %d, \"rank_y\": %d, \"rank_p\": %d, \"rank_out\": %d, "
-                             "\"basis\": %d, \"tail\": %.3e}\n",
-                     j0 + i, x.rank, P->stats.last_rank_y, P->stats.last_rank_p, P->stats.last_rank_out,
-                     P->stats.last_basis, P->stats.last_tail);
+      sb.materialize(sb.stored(j0 + i), xin[i]);
+      px.push_back(&xin[i]);
+      po.push_back(&outs[i]);
     }
+    P->hess_apply_batch(px, po, true);
+    xin.clear();
     auto t1 = clk::now();
     t_apply += std::chrono::duration<double>(t1 - t0).count();
     std::vector<CVec> Wn;
@@ -664,12 +663,18 @@ EigResult randomized_eig(Problem* P, int k, const std::vector<const LowRank*>& p
     }
   };
   // pass one
+  // applies in batches of kBatch with fused multigrid solves
+  constexpr int kBatch = 8;
   std::vector<CVec> Y;
-  for (int j = 0; j < l; ++j) {
-    LowRank y;
-    P->hess_apply(*probes[j], y, true);
-    Y.push_back(sb.absorb(y, tol, cap));
-    if ((j + 1) % 8 == 0 || j + 1 == l) logline("pass1", j + 1);
+  for (int j0 = 0; j0 < l; j0 += kBatch) {
+    const int nbt = std::min(kBatch, l - j0);
+    std::vector<LowRank> ys(nbt);
+    std::vector<const LowRank*> px(probes.begin() + j0, probes.begin() + j0 + nbt);
+    std::vector<LowRank*> py;
+    for (auto& y : ys) py.push_back(&y);
+    P->hess_apply_batch(px, py, true);
+    for (auto& y : ys) Y.push_back(sb.absorb(y, tol, cap));
+    logline("pass1", j0 + nbt);
   }
   for (auto& y : Y) sb.append(y);
   std::vector<double> Gy((size_t)l * l);
@@ -697,12 +702,19 @@ EigResult randomized_eig(Problem* P, int k, const std::vector<const LowRank*>& p
   }
   // pass two
   std::vector<CVec> W;
-  for (int a = 0; a < m; ++a) {
-    LowRank q, w;
-    sb.materialize(Q[a], q);
-    P->hess_apply(q, w, true);
-    W.push_back(sb.absorb(w, tol, cap));
-    if ((a + 1) % 8 == 0 || a + 1 == m) logline("pass2", a + 1);
+  for (int a0 = 0; a0 < m; a0 += kBatch) {
+    const int nbt = std::min(kBatch, m - a0);
+    std::vector<LowRank> qs(nbt), ws(nbt);
+    std::vector<const LowRank*> pq;
+    std::vector<LowRank*> pw;
+    for (int a = 0; a < nbt; ++a) {
+      sb.materialize(Q[a0 + a], qs[a]);
+      pq.push_back(&qs[a]);
+      pw.push_back(&ws[a]);
+    }
+    P->hess_apply_batch(pq, pw, true);
+    for (auto& w : ws) W.push_back(sb.absorb(w, tol, cap));
+    logline("pass2", a0 + nbt);
   }
   // stored vectors: Y (0 .. l-1), Q (l .. l+m-1), W (l+m .. l+2m-1)
   for (auto& q : Q) sb.append(q);

@@ -105,6 +105,21 @@ size_t Pool::bytes_in_use() const { return impl_->in_use; }
 size_t Pool::peak_bytes() const { return impl_->peak; }
 
 // ---- rocBLAS / rocSOLVER ---------------------------------------------------
+// Calls of different problems (different handles and streams, from the
+// serving loop's worker threads) interfered here: rocSOLVER factorizations
+// that overlapped on the device came out wrong, and rocBLAS calls enqueued
+// from several threads at once changed results far beyond rounding.  So
+// every rocSOLVER call holds a process-wide lock until its stream has
+// drained (at most one runs at a time), and every rocBLAS call is enqueued
+// under a second process-wide lock (held only while the call is issued).
+static std::mutex g_solver_mu;
+static std::mutex g_blas_mu;
+struct SolverSection {
+  std::lock_guard<std::mutex> lk;
+  hipStream_t st;
+  explicit SolverSection(hipStream_t s) : lk(g_solver_mu), st(s) {}
+  ~SolverSection() { (void)hipStreamSynchronize(st); }
+};
 static void rb_check(rocblas_status s, const char* what) {
   if (s != rocblas_status_success) fail(LRPOST_EHIP, std::string(what) + " failed (rocblas status " + std::to_string((int)s) + ")");
 }
@@ -113,6 +128,8 @@ GpuDense::GpuDense(hipStream_t st) {
   rocblas_handle h;
   rb_check(rocblas_create_handle(&h), "rocblas_create_handle");
   rb_check(rocblas_set_stream(h, st), "rocblas_set_stream");
+  // no split-K GEMM solutions with atomic accumulation: reproducible results
+  rb_check(rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed), "rocblas_set_atomics_mode");
   handle = h;
   st_ = st;
 }
@@ -124,6 +141,7 @@ GpuDense::~GpuDense() {
 void GpuDense::gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda, const double* B,
                     int ldb, double beta, double* C, int ldc) {
   if (m <= 0 || n <= 0) return;
+  std::lock_guard<std::mutex> blas_lock(g_blas_mu);
   rb_check(rocblas_dgemm((rocblas_handle)handle, ta ? rocblas_operation_transpose : rocblas_operation_none,
                          tb ? rocblas_operation_transpose : rocblas_operation_none, m, n, k, &alpha, A, lda, B, ldb,
                          &beta, C, ldc),
@@ -134,6 +152,7 @@ void GpuDense::gemm_strided_batched(bool ta, bool tb, int m, int n, int k, doubl
                                     long sa, const double* B, int ldb, long sb, double beta, double* C, int ldc,
                                     long sc, int batch) {
   if (m <= 0 || n <= 0 || batch <= 0) return;
+  std::lock_guard<std::mutex> blas_lock(g_blas_mu);
   rb_check(rocblas_dgemm_strided_batched((rocblas_handle)handle, ta ? rocblas_operation_transpose : rocblas_operation_none,
                                          tb ? rocblas_operation_transpose : rocblas_operation_none, m, n, k, &alpha, A,
                                          lda, sa, B, ldb, sb, &beta, C, ldc, sc, batch),
@@ -144,6 +163,7 @@ void GpuDense::syevd(int n, double* A, int lda, double* w, DevMem& work) {
   if (n <= 0) return;
   work.ensure(sizeof(double) * (size_t)n + 64);
   int* info = reinterpret_cast<int*>(work.as<char>() + sizeof(double) * (size_t)n);
+  SolverSection section(st_);
   rb_check(rocsolver_dsyevd((rocblas_handle)handle, rocblas_evect_original, rocblas_fill_upper, n, A, lda, w,
                             work.as<double>(), info),
            "rocsolver_dsyevd");
@@ -153,6 +173,7 @@ bool GpuDense::spd_inverse_upper(int n, double* A, int lda, DevMem& work) {
   if (n <= 0) return true;
   work.ensure(64);
   int* info = work.as<int>();
+  SolverSection section(st_);
   rb_check(rocsolver_dpotrf((rocblas_handle)handle, rocblas_fill_upper, n, A, lda, info), "rocsolver_dpotrf");
   int h = 0;
   LRP_HIP(hipMemcpyAsync(&h, info, sizeof(int), hipMemcpyDeviceToHost, st_));
@@ -164,11 +185,13 @@ bool GpuDense::spd_inverse_upper(int n, double* A, int lda, DevMem& work) {
 
 void GpuDense::dgmm_right(int m, int n, const double* A, int lda, const double* x, double* C, int ldc) {
   if (m <= 0 || n <= 0) return;
+  std::lock_guard<std::mutex> blas_lock(g_blas_mu);
   rb_check(rocblas_ddgmm((rocblas_handle)handle, rocblas_side_right, m, n, A, lda, x, 1, C, ldc), "rocblas_ddgmm");
 }
 
 void GpuDense::scal(int n, double alpha, double* x) {
   if (n <= 0) return;
+  std::lock_guard<std::mutex> blas_lock(g_blas_mu);
   rb_check(rocblas_dscal((rocblas_handle)handle, n, &alpha, x, 1), "rocblas_dscal");
 }
 

@@ -189,6 +189,18 @@ class Problem {
   // ---- low-rank operations ---------------------------------------------
   // Solve tau K Y + M Y C^T = F (forward) or tau K Y + M Y C = F (adjoint).
   void spacetime_solve(const LowRank& F, LowRank& Y, bool adjoint);
+  // The same for several sources, with all pole solves in one multigrid solve.
+  void spacetime_solve_batch(const std::vector<const LowRank*>& F, const std::vector<LowRank*>& Y, bool adjoint);
+  // Hessian applies of several vectors with fused multigrid solves.
+  void hess_apply_batch(const std::vector<const LowRank*>& x, const std::vector<LowRank*>& y, bool precond);
+  struct StPrep {
+    int r1 = 0;
+    DevMem Fb;               // orthonormal spatial factor of the source (nx x r1)
+    std::vector<double> F2p; // its temporal factor (nt x r1), time-reversed for the adjoint
+  };
+  void st_prepare(const LowRank& F, bool adjoint, StPrep& pr);
+  double* st_pole_solves(const std::vector<const StPrep*>& prs);
+  void st_finish(const StPrep& pr, double* Wall, LowRank& Y, bool adjoint);
   // G x (precond) or H_mis x (misfit).
   void hess_apply(const LowRank& x, LowRank& y, bool precond);
   // Truncate in place; weight 0: Euclidean, 1: M, 2: K+M.  With ref_norm > 0
@@ -224,7 +236,7 @@ class Problem {
   DevMem mg_work_f_, mg_f_;
   void upload_mg_params(const std::vector<ShiftCoef>& ab);
   // space-time solver workspaces
-  DevMem st_q_, st_w_, st_mw_, st_f_, st_kt_, st_small_, eig_work_;
+  DevMem st_q_, st_w_, st_mw_, st_wall_, st_brep_, st_kt_, st_small_, eig_work_;
 };
 
 void smoother_interval(double a, double bh2, double* lo, double* hi);

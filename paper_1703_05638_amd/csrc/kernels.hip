@@ -515,12 +515,12 @@ __global__ __launch_bounds__(256) void k_gram_mfma(long nrows, long rows_per_chu
 }
 
 int gram_chunks_mfma(long nrows, int m, int q) {
-  // about 1024 workgroups in stage 1, at least 1024 rows per chunk
+  // about 2048 workgroups in stage 1 (8 per CU), at least 256 rows per chunk
   const long tiles = (long)((m + MT - 1) / MT) * ((q + MT - 1) / MT);
-  long c = 1024 / (tiles > 0 ? tiles : 1);
-  const long cmax = (nrows + 1023) / 1024;
+  long c = 2048 / (tiles > 0 ? tiles : 1);
+  const long cmax = (nrows + 255) / 256;
   if (c > cmax) c = cmax;
-  if (c > 256) c = 256;
+  if (c > 1024) c = 1024;
   if (c < 1) c = 1;
   return (int)c;
 }

@@ -583,14 +583,10 @@ void Problem::small_svd(int m, int nn, const double* A, int lda, bool accurate, 
 // The adjoint equation tau K Y + M Y C = F is the same problem with time
 // reversed on both sides.
 // ---------------------------------------------------------------------------
-void Problem::spacetime_solve(const LowRank& F, LowRank& Y, bool adjoint) {
+void Problem::st_prepare(const LowRank& F, bool adjoint, StPrep& pr) {
   const int rf0 = F.rank;
-  Y.nx = nx;
-  Y.nt = nt;
-  if (rf0 == 0) {
-    Y.resize(nx, nt, 0);
-    return;
-  }
+  pr.r1 = 0;
+  if (rf0 == 0) return;
   // 1. orthonormalize the source's spatial factor (eigen-based, drops null directions)
   std::vector<double> G, w(rf0), U((size_t)rf0 * rf0);
   gram(rf0, F.a(), rf0, F.a(), G);
@@ -600,11 +596,10 @@ void Problem::spacetime_solve(const LowRank& F, LowRank& Y, bool adjoint) {
   for (int j = rf0 - 1; j >= 0; --j)
     if (w[j] > 1e-26 * wmax && wmax > 0) keep.push_back(j);
   const int r1 = (int)keep.size();
-  if (r1 == 0) {
-    Y.resize(nx, nt, 0);
-    return;
-  }
-  std::vector<double> T1((size_t)rf0 * r1), F2p((size_t)nt * r1, 0.0);
+  if (r1 == 0) return;
+  std::vector<double> T1((size_t)rf0 * r1);
+  std::vector<double>& F2p = pr.F2p;
+  F2p.assign((size_t)nt * r1, 0.0);
   for (int c = 0; c < r1; ++c) {
     const int j = keep[c];
     const double sw = std::sqrt(w[j]);
@@ -616,31 +611,80 @@ void Problem::spacetime_solve(const LowRank& F, LowRank& Y, bool adjoint) {
       F2p[(size_t)c * nt + k] = s * sw;
     }
   }
-  st_f_.ensure(sizeof(double) * (size_t)nx * r1);
-  double* Fb = st_f_.as<double>();
-  proj(rf0, F.a(), T1, r1, Fb, 0.0);
+  pr.Fb.ensure(sizeof(double) * (size_t)nx * r1);
+  proj(rf0, F.a(), T1, r1, pr.Fb.as<double>(), 0.0);
+  pr.r1 = r1;
+}
 
-  // 2. spatial basis: all pole solves in one batched multigrid solve with
-  // per-column shifts, then block-by-block M-orthonormalization
+
+// Pole solves of a batch of prepared sources in one multigrid solve with
+// per-column shifts: Wall (nx x sum_j r1_j npol) holds, source after
+// source and pole after pole, (tau K + p_i M)^{-1} Fb_j.
+double* Problem::st_pole_solves(const std::vector<const StPrep*>& prs) {
+  const int npol = (int)poles.size();
+  long cols = 0;
+  for (auto* pr : prs) cols += (long)pr->r1 * npol;
+  if (cols == 0) return nullptr;
+  st_wall_.ensure(sizeof(double) * (size_t)nx * cols);
+  st_brep_.ensure(sizeof(double) * (size_t)nx * cols);
+  double* Wall = st_wall_.as<double>();
+  double* Brep = st_brep_.as<double>();
+  std::vector<ShiftCoef> ab((size_t)cols);
+  long off = 0;
+  for (auto* pr : prs)
+    for (int i = 0; i < npol; ++i) {
+      if (pr->r1 == 0) continue;
+      LRP_HIP(hipMemcpyAsync(Brep + (size_t)off * nx, pr->Fb.p, sizeof(double) * (size_t)nx * pr->r1,
+                             hipMemcpyDeviceToDevice, st));
+      for (int c = 0; c < pr->r1; ++c) ab[(size_t)off + c] = {tau, poles[i]};
+      off += pr->r1;
+    }
+  mg_solve((int)cols, Brep, Wall, ab, st_cycles);
+  return Wall;
+}
+
+void Problem::spacetime_solve(const LowRank& F, LowRank& Y, bool adjoint) {
+  spacetime_solve_batch({&F}, {&Y}, adjoint);
+}
+
+void Problem::spacetime_solve_batch(const std::vector<const LowRank*>& F, const std::vector<LowRank*>& Y,
+                                    bool adjoint) {
+  const int nb = (int)F.size();
+  std::vector<StPrep> prs(nb);
+  std::vector<const StPrep*> pp;
+  for (int j = 0; j < nb; ++j) {
+    st_prepare(*F[j], adjoint, prs[j]);
+    pp.push_back(&prs[j]);
+  }
+  double* Wall = st_pole_solves(pp);
+  long off = 0;
+  for (int j = 0; j < nb; ++j) {
+    st_finish(prs[j], Wall ? Wall + (size_t)off * nx : nullptr, *Y[j], adjoint);
+    off += (long)prs[j].r1 * (long)poles.size();
+  }
+}
+
+// Basis, projected problem and truncation of one prepared source whose pole
+// solves are in Wall (nx x r1 npol, overwritten).
+void Problem::st_finish(const StPrep& pr, double* Wall, LowRank& Y, bool adjoint) {
+  Y.nx = nx;
+  Y.nt = nt;
+  const int r1 = pr.r1;
+  if (r1 == 0) {
+    Y.resize(nx, nt, 0);
+    return;
+  }
+  const double* Fb = pr.Fb.as<double>();
+  const std::vector<double>& F2p = pr.F2p;
+  // 2. block-by-block M-orthonormalization of the pole solutions
   const int npol = (int)poles.size();
   const int qmax = r1 * npol;
   st_q_.ensure(sizeof(double) * (size_t)nx * qmax);
-  st_w_.ensure(sizeof(double) * (size_t)nx * qmax * 2 + sizeof(double) * (size_t)nx * r1);
+  st_w_.ensure(sizeof(double) * (size_t)nx * r1);
   st_mw_.ensure(sizeof(double) * (size_t)nx * std::max(r1, 1));
   double* Q = st_q_.as<double>();
-  double* Wall = st_w_.as<double>();
-  double* Brep = Wall + (size_t)nx * qmax;
-  double* W2 = Brep + (size_t)nx * qmax;
+  double* W2 = st_w_.as<double>();
   double* MW = st_mw_.as<double>();
-  {
-    std::vector<ShiftCoef> ab((size_t)qmax);
-    for (int i = 0; i < npol; ++i) {
-      LRP_HIP(hipMemcpyAsync(Brep + (size_t)i * r1 * nx, Fb, sizeof(double) * (size_t)nx * r1,
-                             hipMemcpyDeviceToDevice, st));
-      for (int c = 0; c < r1; ++c) ab[(size_t)i * r1 + c] = {tau, poles[i]};
-    }
-    mg_solve(qmax, Brep, Wall, ab, st_cycles);
-  }
   int q = 0;
   st_kt_.ensure(sizeof(double) * (size_t)qmax * qmax);
   double* Kt = st_kt_.as<double>();  // q x q projected tau K, leading dimension qmax (device)
@@ -819,42 +863,71 @@ void Problem::spacetime_solve(const LowRank& F, LowRank& Y, bool adjoint) {
 // G x = alpha^{-1} (K+M)^{-1} M P1 P2^T (precond) or H_mis x = tau M P1 P2^T (misfit),
 // with Y = forward solve of the source tau M X1 X2^T, Z = sigma^{-2} mask .* Y and
 // P the adjoint solve of Z (Sec. 6.1 eq. misfit).
-void Problem::hess_apply(const LowRank& x, LowRank& y, bool precond) {
-  stats.applies += 1;
-  y.nx = nx;
-  y.nt = nt;
-  if (x.rank == 0) {
-    y.resize(nx, nt, 0);
-    return;
+void Problem::hess_apply(const LowRank& x, LowRank& y, bool precond) { hess_apply_batch({&x}, {&y}, precond); }
+
+// Several applies with the multigrid work fused: the forward solves' pole
+// solves in one multigrid solve, the adjoint solves' in another, and the
+// prior solves of all outputs in a third.
+void Problem::hess_apply_batch(const std::vector<const LowRank*>& x, const std::vector<LowRank*>& y, bool precond) {
+  const int nb = (int)x.size();
+  stats.applies += nb;
+  std::vector<LowRank> F(nb), Yf(nb), Zs(nb), Pa(nb);
+  std::vector<const LowRank*> pF, pZ;
+  std::vector<LowRank*> pY, pP;
+  for (int j = 0; j < nb; ++j) {
+    F[j].resize(nx, nt, x[j]->rank);
+    if (x[j]->rank > 0) apply_op(x[j]->rank, x[j]->a(), F[j].a(), {{0.0, tau}});
+    F[j].B = x[j]->B;
+    pF.push_back(&F[j]);
+    pY.push_back(&Yf[j]);
   }
-  LowRank F, Yf, Zs, P;
-  F.resize(nx, nt, x.rank);
-  apply_op(x.rank, x.a(), F.a(), {{0.0, tau}});
-  F.B = x.B;
-  spacetime_solve(F, Yf, false);
-  stats.last_rank_y = Yf.rank;
-  Zs.resize(nx, nt, Yf.rank);
-  mask_scale<double>(st, nx, Yf.rank, Yf.a(), nx, Zs.a(), nx, mask.as<uint8_t>(), 1.0 / (desc.sigma * desc.sigma));
-  Zs.B = Yf.B;
-  spacetime_solve(Zs, P, true);
-  stats.last_rank_p = P.rank;
-  y.resize(nx, nt, P.rank);
-  if (P.rank > 0) {
-    if (precond) {
-      DevMem mp;
-      mp.ensure(sizeof(double) * (size_t)nx * P.rank);
-      apply_op(P.rank, P.a(), mp.as<double>(), {{0.0, 1.0}});
-      if (desc.precision == LRPOST_MIXED)  // float32 cycles, float64 refinement rounds
-        mg_solve(P.rank, mp.as<double>(), y.a(), {{1.0, 1.0}}, (prior_cycles + 1) / 2, desc.trunc_tol < 1e-7 ? 2 : 1);
-      else
-        mg_solve(P.rank, mp.as<double>(), y.a(), {{1.0, 1.0}}, prior_cycles);
-      axpby<double>(st, nx, P.rank, y.a(), nx, y.a(), nx, 1.0 / desc.alpha, 0.0);
-    } else {
-      apply_op(P.rank, P.a(), y.a(), {{0.0, tau}});
+  spacetime_solve_batch(pF, pY, false);
+  for (int j = 0; j < nb; ++j) {
+    stats.last_rank_y = Yf[j].rank;
+    Zs[j].resize(nx, nt, Yf[j].rank);
+    if (Yf[j].rank > 0)
+      mask_scale<double>(st, nx, Yf[j].rank, Yf[j].a(), nx, Zs[j].a(), nx, mask.as<uint8_t>(),
+                         1.0 / (desc.sigma * desc.sigma));
+    Zs[j].B = Yf[j].B;
+    pZ.push_back(&Zs[j]);
+    pP.push_back(&Pa[j]);
+  }
+  spacetime_solve_batch(pZ, pP, true);
+  int R = 0;
+  for (int j = 0; j < nb; ++j) R += Pa[j].rank;
+  DevMem mp, out;
+  if (R > 0 && precond) {
+    mp.ensure(sizeof(double) * (size_t)nx * R);
+    out.ensure(sizeof(double) * (size_t)nx * R);
+    int off = 0;
+    for (int j = 0; j < nb; ++j) {
+      if (Pa[j].rank > 0) apply_op(Pa[j].rank, Pa[j].a(), mp.as<double>() + (size_t)off * nx, {{0.0, 1.0}});
+      off += Pa[j].rank;
     }
-    y.B = P.B;
+    if (desc.precision == LRPOST_MIXED)  // float32 cycles, float64 refinement rounds
+      mg_solve(R, mp.as<double>(), out.as<double>(), {{1.0, 1.0}}, (prior_cycles + 1) / 2,
+               desc.trunc_tol < 1e-7 ? 2 : 1);
+    else
+      mg_solve(R, mp.as<double>(), out.as<double>(), {{1.0, 1.0}}, prior_cycles);
   }
-  stats.last_rank_out = y.rank;
+  int off = 0;
+  for (int j = 0; j < nb; ++j) {
+    LowRank& yj = *y[j];
+    const int r = Pa[j].rank;
+    stats.last_rank_p = r;
+    yj.nx = nx;
+    yj.nt = nt;
+    yj.resize(nx, nt, r);
+    if (r > 0) {
+      if (precond)
+        axpby<double>(st, nx, r, out.as<double>() + (size_t)off * nx, nx, yj.a(), nx, 1.0 / desc.alpha, 0.0);
+      else
+        apply_op(r, Pa[j].a(), yj.a(), {{0.0, tau}});
+      yj.B = Pa[j].B;
+    }
+    off += r;
+    stats.last_rank_out = r;
+  }
   sync();
 }
 

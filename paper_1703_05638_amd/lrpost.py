@@ -248,6 +248,21 @@ class Problem:
         r = y.rank
         return Y1[:r].clone(), Y2[:r].copy()
 
+    def hess_apply_batch(self, vecs, which: int = LRPOST_PRECOND):
+        """Applies to several low-rank vectors [(W1, W2), ...] with fused multigrid solves."""
+        n = len(vecs)
+        xs = (LowRankC * n)()
+        ys = (LowRankC * n)()
+        keep = []
+        for i, (W1, W2) in enumerate(vecs):
+            x = self._lr_in(W1, W2)
+            y, Y1, Y2 = self._lr_out(max(self.desc.rank_cap, 1))
+            keep.append((x, Y1, Y2))
+            xs[i] = x
+            ys[i] = y
+        _check(_lib.lrpost_hess_apply_batch(self.h, n, xs, ys, which))
+        return [(keep[i][1][:ys[i].rank].clone(), keep[i][2][:ys[i].rank].copy()) for i in range(n)]
+
     def spacetime_solve(self, W1, W2, adjoint: bool = False):
         x = self._lr_in(W1, W2)
         y, Y1, Y2 = self._lr_out(max(self.desc.rank_cap, 1))
