@@ -11,8 +11,14 @@ variance diag(Gamma_post,50) over all nx * nt space-time points.  Inputs are
 synthetic (seeded start block); they are generated inside the library and
 are resident in HBM when the timed region starts.
 
-value = Hessian applies completed in the timed steps / timed seconds.
+value = Hessian applies completed in the timed steps / timed seconds.  The
+default precision is mixed (float32 multigrid cycles with float64 iterative
+refinement of the prior solve; projections, truncations and the Lanczos
+matrix in float64); afterwards the same step runs in float64, and its
+throughput and the mixed result's relative error against it (eigenvalues and
+posterior variance) are reported under "fp64_reference".
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+[--precision mixed|fp64] [--serving R]
 """
 import argparse
 import json
@@ -27,7 +33,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 COPY_BYTES = 256 << 20  # calibration copy for the HBM byte counters, each way
-TRAFFIC_REPORT = os.path.join(ROOT, "profiles", "k_cheb_mesh256_nt200_traffic.txt")
+TRAFFIC_REPORTS = {"fp64": os.path.join(ROOT, "profiles", "k_cheb_mesh256_nt200_traffic.txt"),
+                   "mixed": os.path.join(ROOT, "profiles", "k_cheb_f32_mesh256_nt200_mixed_traffic.txt")}
 
 
 def cpu_baseline(desc, budget_s=20.0):
@@ -111,7 +118,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
+    ap.add_argument("--no-fp64-reference", action="store_true",
+                    help="in mixed precision, skip the float64 comparison step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving", type=int, default=0,
                     help="measure the serving loop on this many requests instead of the eigensolve step")
@@ -142,47 +151,63 @@ def main():
         torch.mul(src, 1.0, out=dst)
     torch.cuda.synchronize()
     del src, dst
-    desc = dataclasses.replace(synthetic.MESH256_NT200, precision=args.precision)
-    prob = lp.Problem(desc)
-    prob.set_log(1)
+    def run(precision, warmup, steps, profile):
+        desc = dataclasses.replace(synthetic.MESH256_NT200, precision=precision)
+        prob = lp.Problem(desc)
+        prob.set_log(1)
 
-    def step():
-        eig = prob.eigensolve(desc.k)
-        D = prob.post_variance(eig, on_device=True)
-        return eig, D
+        def step():
+            eig = prob.eigensolve(desc.k)
+            D = prob.post_variance(eig, on_device=True)
+            return eig, D
 
-    for w in range(args.warmup):
-        t0 = time.perf_counter()
-        eig, D = step()
-        del eig, D
-        print("warmup step %d done in %.1f s" % (w, time.perf_counter() - t0), file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    applies0 = prob.stats()["applies"]
-    prob.profile(True)
-    step_ms = []
-    lam = None
-    t_all = time.perf_counter()
-    for _ in range(args.steps):
-        t0 = time.perf_counter()
-        eig, D = step()
+        for w in range(warmup):
+            t0 = time.perf_counter()
+            eig, D = step()
+            del eig, D
+            print("%s warmup step %d done in %.1f s" % (precision, w, time.perf_counter() - t0), file=sys.stderr,
+                  flush=True)
         torch.cuda.synchronize()
-        step_ms.append((time.perf_counter() - t0) * 1e3)
-        lam = eig.values()
-        del eig, D
-        print("timed step done in %.1f s" % (step_ms[-1] / 1e3), file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_all
-    launches, kern_ms, kern_bytes = prob.profile_read()
-    prob.profile(False)
-    applies = prob.stats()["applies"] - applies0
-    st = prob.stats()
+        applies0 = prob.stats()["applies"]
+        if profile:
+            prob.profile(True)
+        step_ms = []
+        lam = D_last = None
+        t_all = time.perf_counter()
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            eig, D = step()
+            torch.cuda.synchronize()
+            step_ms.append((time.perf_counter() - t0) * 1e3)
+            lam = eig.values()
+            D_last = D
+            del eig
+            print("%s timed step done in %.1f s" % (precision, step_ms[-1] / 1e3), file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_all
+        prof = prob.profile_read() if profile else (0, 0.0, 0.0)
+        prob.profile(False)
+        res = {"desc": desc, "applies": prob.stats()["applies"] - applies0, "elapsed": elapsed, "step_ms": step_ms,
+               "lam": lam, "D": D_last, "prof": prof, "stats": prob.stats()}
+        del prob
+        return res
 
+    main_run = run(args.precision, args.warmup, args.steps, True)
+    desc = main_run["desc"]
+    launches, kern_ms, kern_bytes = main_run["prof"]
+    applies, elapsed, step_ms, lam, st = (main_run["applies"], main_run["elapsed"], main_run["step_ms"],
+                                          main_run["lam"], main_run["stats"])
+    ref = None
+    if args.precision == "mixed" and not args.no_fp64_reference:
+        # the same step in float64: its throughput, and the mixed result's error against it
+        ref = run("fp64", 0, 1, False)
     from paper_1703_05638_amd.profile_summary import read_traffic
 
-    traffic = read_traffic(TRAFFIC_REPORT)
+    traffic = read_traffic(TRAFFIC_REPORTS[args.precision])
     avg_ms = kern_ms / max(launches, 1)
     bytes_per_launch = kern_bytes / max(launches, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if launches else 0.0
+    kname = "k_cheb<double,4>" if args.precision == "fp64" else "k_cheb<float,4>"
     out = {
         "metric": "Hessian applies/s (fwd+adj space-time) + p50/p99 posterior latency @1e-5 rel",
         "value": applies / elapsed,
@@ -204,12 +229,21 @@ def main():
         "applies_per_step": applies / args.steps,
         "lanczos_block_steps": st["lanczos_steps"],
         "lambda_1_to_3": [float(x) for x in lam[:3]],
-        "roofline": {"kernel": "k_cheb<double,4> (multigrid Chebyshev smoother step)", "bound": "hbm",
+        "roofline": {"kernel": kname + " (multigrid Chebyshev smoother step)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "launches": launches, "avg_launch_us": avg_ms * 1e3,
                      "bytes_per_launch": bytes_per_launch},
     }
+    if ref is not None:
+        lam64 = ref["lam"]
+        D64 = ref["D"]
+        out["fp64_reference"] = {
+            "applies_per_s": ref["applies"] / ref["elapsed"],
+            "posterior_latency_ms": ref["step_ms"][0],
+            "lambda_max_rel_err": float(abs(lam - lam64).max() / abs(lam64).max()),
+            "variance_max_rel_err": float(((main_run["D"] - D64).abs() / D64.abs()).max().item()),
+        }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(desc)
     print(json.dumps(out))

@@ -4,6 +4,8 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <array>
+#include <map>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -224,6 +226,7 @@ class Problem {
 
  private:
   DevMem mg_param_, mg_work_, mg_res_, gram_part_, gram_out_, proj_q_, op_w_;
+  std::map<std::array<double, 3>, DevMem> op_w_cache_;  // weights of column-uniform operators
   static constexpr size_t kStagingBytes = size_t(32) << 20;
   void* staging_ = nullptr;
   size_t staging_used_ = 0;

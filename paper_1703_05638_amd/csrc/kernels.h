@@ -5,11 +5,12 @@
 
 namespace lrp {
 
-// Y[:,c] = W[4c]*centre + W[4c+1]*edges + W[4c+2]*corners of X[:,c] + W[4c+3]*Z[:,c]
-// (W: device, 4*ncols doubles; Z may be null).
+// Y[:,c] = w0*centre + w1*edges + w2*corners of X[:,c] + w3*Z[:,c] with
+// (w0..w3) = W[wstride*c .. +3] (W: device doubles; wstride 4: one set per
+// column, 0: one set for all; Z may be null).
 template <typename T>
 void stencil(hipStream_t st, int n, int ncols, const T* X, long ldx, T* Y, long ldy, const T* Z, long ldz,
-             const double* W);
+             const double* W, int wstride = 4);
 
 // Multigrid passes; P: device, kMgStride doubles per column:
 // {wc, we, wk, 0, alpha_0, beta_0/wc, alpha_1, beta_1/wc, ...} (Chebyshev steps).

@@ -23,16 +23,19 @@ namespace lrp {
 // Stencil: Y[:,c] = wc*x + we*(edges) + wk*(corners) + zc * Z[:,c]
 // Each thread owns one x1 index and walks S consecutive rows, keeping the
 // three rows it needs in registers; the x1 neighbours come from the
-// neighbouring lanes' loads through the L1 cache.
+// neighbouring lanes' loads through the L1 cache.  Column c's weights are
+// W[wstride * c .. + 3] (wstride 0: one set for all columns).
 // ---------------------------------------------------------------------------
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_stencil(int n, const T* __restrict__ X, long ldx, T* __restrict__ Y, long ldy,
-                                                 const T* __restrict__ Z, long ldz, const double* __restrict__ W) {
+                                                 const T* __restrict__ Z, long ldz, const double* __restrict__ W,
+                                                 int wstride) {
   const int col = blockIdx.z;
   const int i = blockIdx.x * 64 + threadIdx.x;
   const int j0 = (blockIdx.y * 4 + threadIdx.y) * S;
   if (i >= n || j0 >= n) return;
-  const T wc = (T)W[4 * col + 0], we = (T)W[4 * col + 1], wk = (T)W[4 * col + 2], zc = (T)W[4 * col + 3];
+  const double* w = W + (long)wstride * col;
+  const T wc = (T)w[0], we = (T)w[1], wk = (T)w[2], zc = (T)w[3];
   const T* x = X + (long)col * ldx;
   T* y = Y + (long)col * ldy;
   const T* z = Z ? Z + (long)col * ldz : nullptr;
@@ -62,17 +65,17 @@ __global__ __launch_bounds__(256) void k_stencil(int n, const T* __restrict__ X,
 
 template <typename T>
 void stencil(hipStream_t st, int n, int ncols, const T* X, long ldx, T* Y, long ldy, const T* Z, long ldz,
-             const double* W) {
+             const double* W, int wstride) {
   if (ncols <= 0 || n <= 0) return;
   constexpr int S = 8;
   dim3 blk(64, 4);
   dim3 grd((n + 63) / 64, (n + 4 * S - 1) / (4 * S), ncols);
-  hipLaunchKernelGGL((k_stencil<T, S>), grd, blk, 0, st, n, X, ldx, Y, ldy, Z, ldz, W);
+  hipLaunchKernelGGL((k_stencil<T, S>), grd, blk, 0, st, n, X, ldx, Y, ldy, Z, ldz, W, wstride);
 }
 template void stencil<double>(hipStream_t, int, int, const double*, long, double*, long, const double*, long,
-                              const double*);
+                              const double*, int);
 template void stencil<float>(hipStream_t, int, int, const float*, long, float*, long, const float*, long,
-                             const double*);
+                             const double*, int);
 
 // ---------------------------------------------------------------------------
 // Multigrid passes.  Per level and column the host provides kMgStride doubles
@@ -459,15 +462,20 @@ int gram_chunks(long nrows, int m, int q) {
 typedef double gram_d4 __attribute__((ext_vector_type(4)));
 constexpr int MT = 64;  // output tile edge
 constexpr int MK = 32;  // rows per LDS stage
+constexpr int MG = 2;   // row groups of 4 waves per workgroup
 
-__global__ __launch_bounds__(256) void k_gram_mfma(long nrows, long rows_per_chunk, int m,
-                                                   const double* __restrict__ A, long lda, int q,
-                                                   const double* __restrict__ B, long ldb,
-                                                   double* __restrict__ part) {
-  __shared__ double As[MT][MK + 1];
-  __shared__ double Bs[MT][MK + 1];
+// Two groups of four waves per workgroup take alternate 32-row stages of the
+// chunk, each with LDS tiles of its own; at the end the second group hands
+// its accumulators to the first through LDS.
+__global__ __launch_bounds__(256 * MG) void k_gram_mfma(long nrows, long rows_per_chunk, int m,
+                                                        const double* __restrict__ A, long lda, int q,
+                                                        const double* __restrict__ B, long ldb,
+                                                        double* __restrict__ part) {
+  __shared__ double As[MG][MT][MK + 1];
+  __shared__ double Bs[MG][MT][MK + 1];
   const int tm = blockIdx.x, tq = blockIdx.y, chunk = blockIdx.z;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int grp = threadIdx.x >> 8, tid = threadIdx.x & 255;
+  const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wq = wave >> 1;
   const long r0 = (long)chunk * rows_per_chunk;
   const long r1 = min(nrows, r0 + rows_per_chunk);
@@ -477,22 +485,28 @@ __global__ __launch_bounds__(256) void k_gram_mfma(long nrows, long rows_per_chu
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = gram_d4{0.0, 0.0, 0.0, 0.0};
   const int lr = tid & 31, lc = tid >> 5;  // loader: row lr of columns lc, lc + 8, ...
-  for (long rb = r0; rb < r1; rb += MK) {
+  double(*as)[MK + 1] = As[grp];
+  double(*bs)[MK + 1] = Bs[grp];
+  // every group runs the same number of stages (barriers are workgroup-wide)
+  const long nst = (r1 > r0) ? (r1 - r0 + MK - 1) / MK : 0;
+  const long nst_g = (nst + MG - 1) / MG;
+  for (long it = 0; it < nst_g; ++it) {
+    const long rb = r0 + (it * MG + grp) * MK;
     const long r = rb + lr;
     const bool rin = r < r1;
 #pragma unroll
     for (int u = 0; u < MT / 8; ++u) {
       const int c = lc + 8 * u;
       const int ca = tm * MT + c, cb = tq * MT + c;
-      As[c][lr] = (rin && ca < m) ? A[(long)ca * lda + r] : 0.0;
-      Bs[c][lr] = (rin && cb < q) ? B[(long)cb * ldb + r] : 0.0;
+      as[c][lr] = (rin && ca < m) ? A[(long)ca * lda + r] : 0.0;
+      bs[c][lr] = (rin && cb < q) ? B[(long)cb * ldb + r] : 0.0;
     }
     __syncthreads();
     const int ci = lane & 15, ck = lane >> 4;
 #pragma unroll
     for (int kk = 0; kk < MK; kk += 4) {
-      const double a0 = As[wm * 32 + ci][kk + ck], a1 = As[wm * 32 + 16 + ci][kk + ck];
-      const double b0 = Bs[wq * 32 + ci][kk + ck], b1 = Bs[wq * 32 + 16 + ci][kk + ck];
+      const double a0 = as[wm * 32 + ci][kk + ck], a1 = as[wm * 32 + 16 + ci][kk + ck];
+      const double b0 = bs[wq * 32 + ci][kk + ck], b1 = bs[wq * 32 + 16 + ci][kk + ck];
       acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
       acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
       acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
@@ -500,6 +514,18 @@ __global__ __launch_bounds__(256) void k_gram_mfma(long nrows, long rows_per_chu
     }
     __syncthreads();
   }
+  // group 1 passes its accumulators to group 0 through the (now idle) LDS tiles
+  double* red = &As[0][0][0];  // 256 threads x 16 values = 4096 doubles <= MG * MT * (MK + 1)
+  if (grp == 1) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[((a * 2 + b) * 4 + v) * 256 + tid] = acc[a][b][v];
+  }
+  __syncthreads();
+  if (grp != 0) return;
   // partial layout: [chunk] column-major m x q
   double* P = part + (long)chunk * m * q;
 #pragma unroll
@@ -510,17 +536,17 @@ __global__ __launch_bounds__(256) void k_gram_mfma(long nrows, long rows_per_chu
       for (int v = 0; v < 4; ++v) {
         const int i = tm * MT + wm * 32 + 16 * a + (lane >> 4) + 4 * v;
         const int j = tq * MT + wq * 32 + 16 * b + (lane & 15);
-        if (i < m && j < q) P[(long)j * m + i] = acc[a][b][v];
+        if (i < m && j < q) P[(long)j * m + i] = acc[a][b][v] + red[((a * 2 + b) * 4 + v) * 256 + tid];
       }
 }
 
 int gram_chunks_mfma(long nrows, int m, int q) {
-  // about 2048 workgroups in stage 1 (8 per CU), at least 256 rows per chunk
+  // about 512 workgroups of 8 waves in stage 1, at least 512 rows per chunk
   const long tiles = (long)((m + MT - 1) / MT) * ((q + MT - 1) / MT);
-  long c = 2048 / (tiles > 0 ? tiles : 1);
-  const long cmax = (nrows + 255) / 256;
+  long c = 512 / (tiles > 0 ? tiles : 1);
+  const long cmax = (nrows + 511) / 512;
   if (c > cmax) c = cmax;
-  if (c > 1024) c = 1024;
+  if (c > 512) c = 512;
   if (c < 1) c = 1;
   return (int)c;
 }
@@ -545,7 +571,7 @@ void gram<double>(hipStream_t st, long nrows, int m, const double* A, long lda, 
   long rpc = (nrows + nchunk - 1) / nchunk;
   rpc = ((rpc + MK - 1) / MK) * MK;
   dim3 grd((m + MT - 1) / MT, (q + MT - 1) / MT, nchunk);
-  hipLaunchKernelGGL(k_gram_mfma, grd, dim3(256), 0, st, nrows, rpc, m, A, lda, q, B, ldb, part);
+  hipLaunchKernelGGL(k_gram_mfma, grd, dim3(256 * MG), 0, st, nrows, rpc, m, A, lda, q, B, ldb, part);
   const long count = (long)m * q;
   hipLaunchKernelGGL(k_sum_partials, dim3((count + 255) / 256), dim3(256), 0, st, nchunk, count, part, C);
 }

@@ -227,6 +227,24 @@ void Problem::to_host(double* dst, const double* src, size_t count) {
 void Problem::apply_op(int ncols, const double* X, double* Y, const std::vector<ShiftCoef>& ab, const double* Z,
                        const std::vector<double>* zc) {
   if (ncols <= 0) return;
+  if (ab.size() == 1 && (!zc || zc->size() == 1)) {
+    // one operator for all columns: its weights are uploaded once per problem
+    const double c = zc ? (*zc)[0] : 0.0;
+    const std::array<double, 3> key{ab[0].a, ab[0].b, c};
+    auto it = op_w_cache_.find(key);
+    if (it == op_w_cache_.end()) {
+      double w[4];
+      stencil_weights(ab[0].a, ab[0].b, h, w);
+      w[3] = c;
+      DevMem d;
+      d.ensure(sizeof(double) * 4);
+      to_device(d.as<double>(), w, 4);
+      it = op_w_cache_.emplace(key, std::move(d)).first;
+    }
+    stencil<double>(st, n, ncols, X, nx, Y, nx, Z, nx, it->second.as<double>(), 0);
+    LRP_HIP(hipGetLastError());
+    return;
+  }
   op_w_h_.assign((size_t)4 * ncols, 0.0);
   for (int c = 0; c < ncols; ++c) {
     const ShiftCoef& s = ab.size() == 1 ? ab[0] : ab[c];
@@ -235,7 +253,7 @@ void Problem::apply_op(int ncols, const double* X, double* Y, const std::vector<
   }
   op_w_.ensure(sizeof(double) * op_w_h_.size());
   to_device(op_w_.as<double>(), op_w_h_.data(), op_w_h_.size());
-  stencil<double>(st, n, ncols, X, nx, Y, nx, Z, nx, op_w_.as<double>());
+  stencil<double>(st, n, ncols, X, nx, Y, nx, Z, nx, op_w_.as<double>(), 4);
   LRP_HIP(hipGetLastError());
 }
 
