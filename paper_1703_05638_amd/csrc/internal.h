@@ -239,7 +239,7 @@ class Problem {
   DevMem mg_work_f_, mg_f_;
   void upload_mg_params(const std::vector<ShiftCoef>& ab);
   // space-time solver workspaces
-  DevMem st_q_, st_w_, st_mw_, st_wall_, st_brep_, st_kt_, st_small_, eig_work_;
+  DevMem st_q_, st_w_, st_mw_, st_wall_, st_brep_, st_kt_, st_small_, st_c_, eig_work_;
 };
 
 void smoother_interval(double a, double bh2, double* lo, double* hi);

@@ -708,7 +708,7 @@ void Problem::st_finish(const StPrep& pr, double* Wall, LowRank& Y, bool adjoint
   double* Kt = st_kt_.as<double>();  // q x q projected tau K, leading dimension qmax (device)
   const std::vector<ShiftCoef> Mop{{0.0, 1.0}};
   const std::vector<ShiftCoef> Kop{{tau, 0.0}};
-  std::vector<double> C, Gw, wv, Uv;
+  std::vector<double> Gw, wv, Uv;
   for (int ip = 0; ip < npol; ++ip) {
     double* W = Wall + (size_t)ip * r1 * nx;
     // reference norms before orthogonalization
@@ -728,12 +728,13 @@ void Problem::st_finish(const StPrep& pr, double* Wall, LowRank& Y, bool adjoint
     // directions that now keep less than 1e-4 of their norm (they were
     // inside span(Q)).  A Gram-based Cholesky cannot tell nearly dependent
     // directions from rounding noise, so it is not used here.
-    auto sweep = [&](int kc, double* X) {
+    auto sweep = [&](int kc, double* X) {  // X -= Q (Q^T M X), all on the device
       if (q == 0 || kc == 0) return;
       apply_op(kc, X, MW, Mop);
-      gram(q, Q, kc, MW, C);
-      for (double& x : C) x = -x;
-      proj(q, Q, C, kc, X, 1.0);
+      st_c_.ensure(sizeof(double) * (size_t)q * kc);
+      gram_dev(q, Q, kc, MW, st_c_.as<double>());
+      dense->scal(q * kc, -1.0, st_c_.as<double>());
+      proj_dev(q, Q, st_c_.as<double>(), q, kc, X, 1.0);
     };
     auto svqb = [&](int kc, const double* src, double* dst, double thresh) -> int {
       apply_op(kc, src, MW, Mop);

@@ -395,3 +395,51 @@ def test_batched_applies_equal_single_applies(lp):
         print("batch vs single %.3e, vs oracle %.3e" % (e_single, e_ref), flush=True)
         assert e_single < 1e-12
         assert e_ref < 1e-8
+
+
+def test_bench_size_eigenpairs_certified_by_oracle(lp):
+    """The bench workload at full size (256 x 256 mesh, nt = 200, tol 1e-6,
+    k = 50, float64 and mixed): the oracle's exact float64 G is applied to the
+    GPU's leading, second and 50th eigenvectors one by one.  Their Rayleigh
+    quotients match the GPU eigenvalues to 1e-5 relative and the relative
+    residuals ||G v - lambda v||_P / lambda stay at the truncation level.
+    Sampled entries of diag(Gamma_post,50) equal dprior - sum_i d_i v_i^2
+    evaluated from the same eigenvectors."""
+    import dataclasses
+    print("case bench-size certificate", flush=True)
+    ora = OP.from_desc(synthetic.MESH256_NT200)
+    for precision in ("fp64", "mixed"):
+        d = dataclasses.replace(synthetic.MESH256_NT200, precision=precision)
+        prob = lp.Problem(d)
+        eig = prob.eigensolve(d.k)
+        lam = eig.values()
+        vecs = {}
+        for i in (0, 1, d.k - 1):
+            W1, W2 = eig.vector(i)
+            V = W1.cpu().numpy().T @ W2  # nx x nt
+            vecs[i] = V
+            GV = ora.G(V)
+            vv = ora.P_inner(V, V)
+            rho = ora.P_inner(V, GV) / vv
+            R = GV - lam[i] * V
+            res = np.sqrt(ora.P_inner(R, R) / vv) / lam[i]
+            print("%s pair %d: lambda %.10e rayleigh rel err %.3e residual %.3e" %
+                  (precision, i, lam[i], abs(rho - lam[i]) / lam[i], res), flush=True)
+            assert abs(rho - lam[i]) / lam[i] < 1e-5
+            assert res < 1e-3
+        # sampled variance entries against the formula with all 50 GPU eigenvectors
+        D = prob.post_variance(eig, on_device=False)  # (nt, nx)
+        rng = np.random.default_rng(7)
+        xs = rng.integers(0, prob.nx, 200)
+        ts = rng.integers(0, d.nt, 200)
+        acc = np.zeros(200)
+        for i in range(d.k):
+            W1, W2 = eig.vector(i)
+            A = W1.cpu().numpy().T  # nx x r
+            vals = np.einsum("sr,sr->s", A[xs], W2.T[ts])
+            acc += lam[i] / (1 + lam[i]) * vals ** 2
+        ref = prob.prior_variance()[xs] - acc
+        err = np.abs(D[ts, xs] - ref).max() / np.abs(ref).max()
+        print("%s sampled variance rel err %.3e" % (precision, err), flush=True)
+        assert err < 1e-12
+        del eig, prob
