@@ -107,18 +107,40 @@ size_t Pool::peak_bytes() const { return impl_->peak; }
 // ---- rocBLAS / rocSOLVER ---------------------------------------------------
 // Calls of different problems (different handles and streams, from the
 // serving loop's worker threads) interfered here: rocSOLVER factorizations
-// that overlapped on the device came out wrong, and rocBLAS calls enqueued
-// from several threads at once changed results far beyond rounding.  So
-// every rocSOLVER call holds a process-wide lock until its stream has
-// drained (at most one runs at a time), and every rocBLAS call is enqueued
-// under a second process-wide lock (held only while the call is issued).
+// that overlapped on the device came out wrong, and rocBLAS calls that were
+// enqueued, or ran on the device, at the same time as another stream's
+// changed results far beyond rounding.  So every rocBLAS and rocSOLVER call
+// is issued under one process-wide lock and, on the device, waits for the
+// previous such call if that was issued on another stream (an event chain:
+// the host does not block, and calls on one stream only keep their stream
+// order).  A rocSOLVER call in addition holds a second lock until its stream
+// has drained, so at most one runs at a time.
 static std::mutex g_solver_mu;
 static std::mutex g_blas_mu;
-struct SolverSection {
+constexpr int kMaxDevices = 64;
+static hipEvent_t g_blas_done[kMaxDevices] = {};     // end of the last call per device, any stream
+static hipStream_t g_blas_stream[kMaxDevices] = {};  // the stream that call was issued on
+
+struct BlasSection {
   std::lock_guard<std::mutex> lk;
   hipStream_t st;
-  explicit SolverSection(hipStream_t s) : lk(g_solver_mu), st(s) {}
-  ~SolverSection() { (void)hipStreamSynchronize(st); }
+  int dev = 0;
+  explicit BlasSection(hipStream_t s) : lk(g_blas_mu), st(s) {
+    LRP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) fail(LRPOST_EINVAL, "device ordinal out of range");
+    if (!g_blas_done[dev]) LRP_HIP(hipEventCreateWithFlags(&g_blas_done[dev], hipEventDisableTiming));
+    else if (g_blas_stream[dev] != st) LRP_HIP(hipStreamWaitEvent(st, g_blas_done[dev], 0));
+  }
+  ~BlasSection() {
+    (void)hipEventRecord(g_blas_done[dev], st);
+    g_blas_stream[dev] = st;
+  }
+};
+struct SolverSection {
+  std::lock_guard<std::mutex> lk;
+  BlasSection blas;
+  explicit SolverSection(hipStream_t s) : lk(g_solver_mu), blas(s) {}
+  ~SolverSection() { (void)hipStreamSynchronize(blas.st); }
 };
 static void rb_check(rocblas_status s, const char* what) {
   if (s != rocblas_status_success) fail(LRPOST_EHIP, std::string(what) + " failed (rocblas status " + std::to_string((int)s) + ")");
@@ -126,6 +148,7 @@ static void rb_check(rocblas_status s, const char* what) {
 
 GpuDense::GpuDense(hipStream_t st) {
   rocblas_handle h;
+  std::lock_guard<std::mutex> lk(g_blas_mu);
   rb_check(rocblas_create_handle(&h), "rocblas_create_handle");
   rb_check(rocblas_set_stream(h, st), "rocblas_set_stream");
   // no split-K GEMM solutions with atomic accumulation: reproducible results
@@ -135,13 +158,19 @@ GpuDense::GpuDense(hipStream_t st) {
 }
 
 GpuDense::~GpuDense() {
-  if (handle) rocblas_destroy_handle((rocblas_handle)handle);
+  if (!handle) return;
+  std::lock_guard<std::mutex> lk(g_blas_mu);
+  rocblas_destroy_handle((rocblas_handle)handle);
+  // the stream may be destroyed next and its handle value reused: make the
+  // next call on any stream wait for the chain again
+  for (auto& s : g_blas_stream)
+    if (s == st_) s = nullptr;
 }
 
 void GpuDense::gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda, const double* B,
                     int ldb, double beta, double* C, int ldc) {
   if (m <= 0 || n <= 0) return;
-  std::lock_guard<std::mutex> blas_lock(g_blas_mu);
+  BlasSection blas(st_);
   rb_check(rocblas_dgemm((rocblas_handle)handle, ta ? rocblas_operation_transpose : rocblas_operation_none,
                          tb ? rocblas_operation_transpose : rocblas_operation_none, m, n, k, &alpha, A, lda, B, ldb,
                          &beta, C, ldc),
@@ -152,7 +181,7 @@ void GpuDense::gemm_strided_batched(bool ta, bool tb, int m, int n, int k, doubl
                                     long sa, const double* B, int ldb, long sb, double beta, double* C, int ldc,
                                     long sc, int batch) {
   if (m <= 0 || n <= 0 || batch <= 0) return;
-  std::lock_guard<std::mutex> blas_lock(g_blas_mu);
+  BlasSection blas(st_);
   rb_check(rocblas_dgemm_strided_batched((rocblas_handle)handle, ta ? rocblas_operation_transpose : rocblas_operation_none,
                                          tb ? rocblas_operation_transpose : rocblas_operation_none, m, n, k, &alpha, A,
                                          lda, sa, B, ldb, sb, &beta, C, ldc, sc, batch),
@@ -185,13 +214,13 @@ bool GpuDense::spd_inverse_upper(int n, double* A, int lda, DevMem& work) {
 
 void GpuDense::dgmm_right(int m, int n, const double* A, int lda, const double* x, double* C, int ldc) {
   if (m <= 0 || n <= 0) return;
-  std::lock_guard<std::mutex> blas_lock(g_blas_mu);
+  BlasSection blas(st_);
   rb_check(rocblas_ddgmm((rocblas_handle)handle, rocblas_side_right, m, n, A, lda, x, 1, C, ldc), "rocblas_ddgmm");
 }
 
 void GpuDense::scal(int n, double alpha, double* x) {
   if (n <= 0) return;
-  std::lock_guard<std::mutex> blas_lock(g_blas_mu);
+  BlasSection blas(st_);
   rb_check(rocblas_dscal((rocblas_handle)handle, n, &alpha, x, 1), "rocblas_dscal");
 }
 
