@@ -33,8 +33,19 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 COPY_BYTES = 256 << 20  # calibration copy for the HBM byte counters, each way
-TRAFFIC_REPORTS = {"fp64": os.path.join(ROOT, "profiles", "k_cheb_mesh256_nt200_traffic.txt"),
-                   "mixed": os.path.join(ROOT, "profiles", "k_cheb_f32_mesh256_nt200_mixed_traffic.txt")}
+# Multigrid kernels timed with HIP events (kind as in the library's
+# LRPOST_KERNEL_*), their names, and the committed HBM-counter reports.
+KERNELS = {
+    0: ("k_cheb", "multigrid Chebyshev smoother step"),
+    1: ("k_mg_down", "level-fused pre-smoothing + residual + restriction"),
+    2: ("k_mg_up", "level-fused prolongation + post-smoothing"),
+}
+
+
+def traffic_report(kernel, precision):
+    tag = "f32_" if precision == "mixed" else ""
+    suffix = "_mixed" if precision == "mixed" else ""
+    return os.path.join(ROOT, "profiles", "%s_%smesh256_nt200%s_traffic.txt" % (kernel, tag, suffix))
 
 
 def cpu_baseline(desc, budget_s=20.0):
@@ -228,7 +239,7 @@ def main():
             print("%s timed step done in %.1f s" % (precision, step_ms[-1] / 1e3), file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_all
-        prof = prob.profile_read() if profile else (0, 0.0, 0.0)
+        prof = {k: prob.profile_read(k) for k in KERNELS} if profile else {}
         prob.profile(False)
         res = {"desc": desc, "applies": prob.stats()["applies"] - applies0, "elapsed": elapsed, "step_ms": step_ms,
                "lam": lam, "D": D_last, "prof": prof, "stats": prob.stats()}
@@ -237,7 +248,9 @@ def main():
 
     main_run = run(args.precision, args.warmup, args.steps, True)
     desc = main_run["desc"]
-    launches, kern_ms, kern_bytes = main_run["prof"]
+    # the multigrid kernel with the most device time in the timed steps
+    kind = max(main_run["prof"], key=lambda k: main_run["prof"][k][1])
+    launches, kern_ms, kern_bytes = main_run["prof"][kind]
     applies, elapsed, step_ms, lam, st = (main_run["applies"], main_run["elapsed"], main_run["step_ms"],
                                           main_run["lam"], main_run["stats"])
     ref = None
@@ -246,11 +259,15 @@ def main():
         ref = run("fp64", 0, 1, False)
     from paper_1703_05638_amd.profile_summary import read_traffic
 
-    traffic = read_traffic(TRAFFIC_REPORTS[args.precision])
+    kbase, kdesc = KERNELS[kind]
+    traffic = read_traffic(traffic_report(kbase, args.precision))
     avg_ms = kern_ms / max(launches, 1)
     bytes_per_launch = kern_bytes / max(launches, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if launches else 0.0
-    kname = "k_cheb<double,4>" if args.precision == "fp64" else "k_cheb<float,4>"
+    kname = kbase + ("<double>" if args.precision == "fp64" else "<float>")
+    others = {KERNELS[k][0]: {"launches": v[0], "total_ms": v[1],
+                              "achieved_GBs": (v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else 0.0}
+              for k, v in main_run["prof"].items() if k != kind and v[0] > 0}
     out = {
         "metric": "Hessian applies/s (fwd+adj space-time) + p50/p99 posterior latency @1e-5 rel",
         "value": applies / elapsed,
@@ -272,11 +289,12 @@ def main():
         "applies_per_step": applies / args.steps,
         "lanczos_block_steps": st["lanczos_steps"],
         "lambda_1_to_3": [float(x) for x in lam[:3]],
-        "roofline": {"kernel": kname + " (multigrid Chebyshev smoother step)", "bound": "hbm",
+        "roofline": {"kernel": "%s (%s)" % (kname, kdesc), "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "launches": launches, "avg_launch_us": avg_ms * 1e3,
-                     "bytes_per_launch": bytes_per_launch},
+                     "bytes_per_launch": bytes_per_launch, "total_ms": kern_ms,
+                     "other_multigrid_kernels": others},
     }
     if ref is not None:
         lam64 = ref["lam"]

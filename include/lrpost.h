@@ -181,14 +181,35 @@ int lrpost_get_stats(const lrpost_problem* p, lrpost_stats* s);
 int lrpost_set_log(lrpost_problem* p, int level);
 
 /* Kernel timing for measurement: while enabled, every launch of the
- * multigrid smoother kernel (the dominant kernel of the apply) is bracketed
- * by HIP events on the problem's stream, and its algorithmic traffic is
- * counted (read x_cur, x_prev and b once, write x_new once; float64).
- * lrpost_profile_read synchronizes, returns the launch count, the summed
- * kernel time in ms and the counted bytes since the last read, and resets
- * the counters. */
+ * multigrid kernels below is bracketed by HIP events on the problem's stream
+ * and credited with its algorithmic traffic in bytes (elements of the
+ * precision it runs in, float32 for the V-cycles of LRPOST_MIXED):
+ *   LRPOST_KERNEL_SMOOTHER_STEP  one Chebyshev step: read x_cur, x_prev and b
+ *                                once, write x_new once (absent operands are
+ *                                not counted);
+ *   LRPOST_KERNEL_MG_DOWN        level-fused pre-smoothing, residual and
+ *                                restriction: read b, write x and the coarse
+ *                                right-hand side;
+ *   LRPOST_KERNEL_MG_UP          level-fused prolongation and post-smoothing:
+ *                                read the pre-smoothed x, the coarse
+ *                                correction and b, write x.
+ * lrpost_profile_read synchronizes, returns for one kind the launch count, the
+ * summed kernel time in ms and the counted bytes since the last read, and
+ * resets that kind's counters. */
+enum {
+  LRPOST_KERNEL_SMOOTHER_STEP = 0,
+  LRPOST_KERNEL_MG_DOWN = 1,
+  LRPOST_KERNEL_MG_UP = 2
+};
 int lrpost_profile(lrpost_problem* p, int enable);
-int lrpost_profile_read(lrpost_problem* p, int64_t* launches, double* total_ms, double* bytes);
+int lrpost_profile_read(lrpost_problem* p, int kernel, int64_t* launches, double* total_ms, double* bytes);
+
+/* Multigrid kernel choice: on (the default) runs each V-cycle level on meshes
+ * of up to 1023 nodes per side as two level-fused kernels (pre-smoothing with
+ * residual and restriction; prolongation with post-smoothing), off as one
+ * kernel per smoother step, residual-restriction and prolongation.  Both
+ * compute the same iterates; finer meshes always take the per-step kernels. */
+int lrpost_set_mg_fused(lrpost_problem* p, int on);
 
 /* ---- building blocks, exported for kernel-level parity tests ----------
  * All pointers are DEVICE memory, float64, column-major with leading

@@ -405,17 +405,26 @@ int lrpost_profile(lrpost_problem* p, int enable) {
     PoolScope pool_scope(P->pool);
     P->sync();
     P->prof_on = enable != 0;
-    P->prof_used = 0;
-    P->prof_bytes = 0.0;
+    P->prof_reset();
   });
 }
 
-int lrpost_profile_read(lrpost_problem* p, int64_t* launches, double* total_ms, double* bytes) {
+int lrpost_profile_read(lrpost_problem* p, int kernel, int64_t* launches, double* total_ms, double* bytes) {
   return guarded([&] {
     Problem* P = impl(p);
     PoolScope pool_scope(P->pool);
     if (!launches || !total_ms || !bytes) fail(LRPOST_EINVAL, "null argument");
-    P->prof_read(launches, total_ms, bytes);
+    if (kernel < 0 || kernel > LRPOST_KERNEL_MG_UP) fail(LRPOST_EINVAL, "unknown kernel kind");
+    P->prof_read(kernel, launches, total_ms, bytes);
+  });
+}
+
+int lrpost_set_mg_fused(lrpost_problem* p, int on) {
+  return guarded([&] {
+    Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
+    P->sync();
+    P->mg_fused = on != 0;
   });
 }
 

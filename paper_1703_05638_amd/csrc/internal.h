@@ -179,14 +179,25 @@ class Problem {
   // progress lines (JSON, stderr) of the eigensolvers when > 0
   int log_level = 0;
 
-  // opt-in timing of the multigrid smoother kernel with HIP events
+  // opt-in timing of the multigrid kernels with HIP events, per kernel kind
+  // (LRPOST_KERNEL_*): every launch is bracketed by an event pair on the
+  // problem's stream and credited with its algorithmic bytes
+  struct ProfSlot {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t used = 0;
+    double bytes = 0.0;
+  };
   bool prof_on = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
-  size_t prof_used = 0;
-  double prof_bytes = 0.0;
+  std::array<ProfSlot, 3> prof_;
+  template <class Launch>
+  void timed(int kind, double bytes, Launch&& launch);
   template <typename T>
   void smooth_step(int nl, int ncols, const T* xc, const T* xp, T* xo, const T* b, long ld, const double* prm, int s);
-  void prof_read(int64_t* launches, double* ms, double* bytes);
+  void prof_reset();
+  void prof_read(int kind, int64_t* launches, double* ms, double* bytes);
+  // level-fused multigrid kernels on meshes with up to kMgFusedMaxN nodes per
+  // side (on by default; off selects the per-step kernels)
+  bool mg_fused = true;
 
   // ---- low-rank operations ---------------------------------------------
   // Solve tau K Y + M Y C^T = F (forward) or tau K Y + M Y C = F (adjoint).

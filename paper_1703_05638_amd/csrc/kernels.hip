@@ -246,6 +246,259 @@ template void mg_prolong_add<double>(hipStream_t, int, int, const double*, long,
 template void mg_prolong_add<float>(hipStream_t, int, int, const float*, long, const float*, float*, long);
 
 // ---------------------------------------------------------------------------
+// Level-fused multigrid passes for meshes of up to 1023 nodes per side.
+//
+// A workgroup of TW >= n + 1 threads owns a strip of S consecutive mesh rows
+// of one column over the full row width; thread i holds mesh column i of the
+// strip plus a halo of rows above and below in registers, so vertical
+// neighbours are register reads and only the left and right neighbours pass
+// through LDS (one exchange per smoother step).  Each Chebyshev step of the
+// smoother is recomputed on a halo one row narrower than the step before, so
+// that the strip needs no data from other strips between steps.  Per node and
+// step the arithmetic is the per-step kernels' (same operands, same order).
+//
+//   down:  x = NU smoother steps from zero for A x = b, and the coarse
+//          right-hand side bc = P^T (b - A x); reads b, writes x and bc.
+//   up:    t = xi + P e (bilinear prolongation of the coarse correction e),
+//          then NU smoother steps from t; reads xi, e, b, writes x.
+//
+// Workgroups are numbered so that consecutive strips of a column share an
+// XCD (hardware dispatch goes round robin over the 8 XCDs), keeping the halo
+// rows that neighbouring strips both read in one L2.
+// ---------------------------------------------------------------------------
+__device__ inline void strip_of(int nstrip, int& strip, int& col) {
+  const int w = blockIdx.x, g = gridDim.x;
+  const int full = g & ~7;
+  const int lw = w < full ? (w & 7) * (full >> 3) + (w >> 3) : w;
+  strip = lw % nstrip;
+  col = lw / nstrip;
+}
+
+// One smoother step on rows [lo, hi] of the register column:
+//   out = cur + al (cur - prv) + be (b - A cur),
+// with cur's rows [lo - 1, hi + 1] exchanged through LDS first.  Rows outside
+// the mesh (jb + r outside [0, n)) and columns i >= n are kept at zero.
+template <typename T, int TW, int R, int lo, int hi>
+__device__ inline void strip_step(const T (&cur)[R], const T (&prv)[R], T (&out)[R], const T (&b)[R], T* xs, int i,
+                                  int n, int jb, T wc, T we, T wk, T al, T be) {
+  constexpr int LP = TW + 2;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (r >= lo - 1 && r <= hi + 1) xs[r * LP + i + 1] = cur[r];
+  __syncthreads();
+  T hs[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (r >= lo - 1 && r <= hi + 1) hs[r] = xs[r * LP + i] + xs[r * LP + i + 2];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (r >= lo && r <= hi) {
+      const T m = cur[r];
+      const T ax = wc * m + we * (hs[r] + (cur[r - 1] + cur[r + 1])) + wk * (hs[r - 1] + hs[r + 1]);
+      const T v = m + al * (m - prv[r]) + be * (b[r] - ax);
+      const int j = jb + r;
+      out[r] = (i < n && j >= 0 && j < n) ? v : T(0);
+    }
+}
+
+template <typename T, int TW, int S, int NU>
+__global__ __launch_bounds__(TW) void k_mg_down(int n, int nstrip, const T* __restrict__ B, long ld,
+                                                T* __restrict__ Xo, T* __restrict__ Bc, long ldc,
+                                                const double* __restrict__ P) {
+  static_assert(NU == 3, "three smoother steps");
+  constexpr int R = S + 2 * NU + 1;  // rows j0 - NU .. j0 + S + NU
+  constexpr int LP = TW + 2;
+  __shared__ T xs[R * LP];
+  int strip, col;
+  strip_of(nstrip, strip, col);
+  const int i = threadIdx.x;
+  const int j0 = strip * S, jb = j0 - NU;
+  const double* pc = P + (long)col * kMgStride;
+  const T wc = (T)pc[0], we = (T)pc[1], wk = (T)pc[2];
+  for (int r = i; r < R; r += TW) {
+    xs[r * LP] = T(0);
+    xs[r * LP + TW + 1] = T(0);
+  }
+  const T* b = B + (long)col * ld;
+  T bv[R], x0[R], x1[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = jb + r;
+    bv[r] = (i < n && j >= 0 && j < n) ? b[(long)j * n + i] : T(0);
+  }
+  // step 0 from zero: x_1 = be_0 b
+  {
+    const T be = (T)pc[5];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      x1[r] = be * bv[r];
+      x0[r] = T(0);
+    }
+  }
+  // step s (1, 2) computes rows [s, R-1-s]
+  strip_step<T, TW, R, 1, R - 2>(x1, x0, x0, bv, xs, i, n, jb, wc, we, wk, (T)pc[6], (T)pc[7]);
+  strip_step<T, TW, R, 2, R - 3>(x0, x1, x1, bv, xs, i, n, jb, wc, we, wk, (T)pc[8], (T)pc[9]);
+  const T(&x)[R] = x1;
+  // owned rows
+  T* xo = Xo + (long)col * ld;
+#pragma unroll
+  for (int r = NU; r < NU + S; ++r) {
+    const int j = jb + r;
+    if (i < n && j < n) xo[(long)j * n + i] = x[r];
+  }
+  // residual on rows j0 .. j0 + S (local r = NU .. NU + S), then restriction
+  const int nc = (n - 1) / 2;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (r >= NU - 1 && r <= NU + S + 1) xs[r * LP + i + 1] = x[r];
+  __syncthreads();
+  T res[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (r >= NU && r <= NU + S) {
+      const T hm = xs[r * LP + i] + xs[r * LP + i + 2];
+      const T hu = xs[(r - 1) * LP + i] + xs[(r - 1) * LP + i + 2];
+      const T hd = xs[(r + 1) * LP + i] + xs[(r + 1) * LP + i + 2];
+      T v = bv[r];
+      v -= wc * x[r] + we * (hm + (x[r - 1] + x[r + 1])) + wk * (hu + hd);
+      res[r] = v;
+    }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (r >= NU && r <= NU + S) xs[(r - NU) * LP + i + 1] = (i < n) ? res[r] : T(0);
+  __syncthreads();
+  const int J0 = j0 / 2;
+  T* bc = Bc + (long)col * ldc;
+  for (int p = i; p < (S / 2) * nc; p += TW) {
+    const int Jl = p / nc, I = p - Jl * nc;
+    if (J0 + Jl >= nc) break;
+    const T* rs = xs + (2 * Jl + 1) * LP + 2 * I + 2;  // fine node (2I+1, 2J+1)
+    const T acc = rs[0] + T(0.5) * ((rs[-1] + rs[1]) + (rs[-LP] + rs[LP])) +
+                  T(0.25) * ((rs[-LP - 1] + rs[-LP + 1]) + (rs[LP - 1] + rs[LP + 1]));
+    bc[(long)(J0 + Jl) * nc + I] = acc;
+  }
+}
+
+template <typename T, int TW, int S, int NU>
+__global__ __launch_bounds__(TW) void k_mg_up(int n, int nstrip, const T* __restrict__ Xi, const T* __restrict__ E,
+                                              long ldc, const T* __restrict__ B, long ld, T* __restrict__ Xo,
+                                              const double* __restrict__ P) {
+  constexpr int R = S + 2 * NU;  // rows j0 - NU .. j0 + S + NU - 1
+  constexpr int LP = TW + 2;
+  constexpr int NCR = R / 2 + 1;  // coarse rows j0/2 - 2 + q, q < NCR
+  __shared__ T xs[R * LP];
+  static_assert(NU == 3, "three smoother steps; the coarse-row bookkeeping assumes a halo of three rows");
+  int strip, col;
+  strip_of(nstrip, strip, col);
+  const int i = threadIdx.x;
+  const int j0 = strip * S, jb = j0 - NU;
+  const int nc = (n - 1) / 2;
+  const double* pc = P + (long)col * kMgStride;
+  const T wc = (T)pc[0], we = (T)pc[1], wk = (T)pc[2];
+  for (int r = i; r < R; r += TW) {
+    xs[r * LP] = T(0);
+    xs[r * LP + TW + 1] = T(0);
+  }
+  const T* xi = Xi + (long)col * ld;
+  const T* b = B + (long)col * ld;
+  const T* e = E + (long)col * ldc;
+  // coarse columns feeding fine column i: odd i sits on coarse (i-1)/2; even i
+  // lies between i/2 - 1 and i/2
+  const bool io = i & 1;
+  const int ca = io ? (i - 1) >> 1 : (i >> 1) - 1, cb = i >> 1;
+  const int J0 = j0 / 2 - 2;  // j0 even, jb = j0 - 3 odd: row r is odd when r is even
+  T ea[NCR], eb[NCR];
+#pragma unroll
+  for (int q = 0; q < NCR; ++q) {
+    const int J = J0 + q;
+    const bool okj = J >= 0 && J < nc;
+    ea[q] = (okj && ca >= 0 && ca < nc) ? e[(long)J * nc + ca] : T(0);
+    eb[q] = (okj && !io && cb < nc) ? e[(long)J * nc + cb] : T(0);
+  }
+  T bv[R], x0[R], x1[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = jb + r;
+    const bool ok = i < n && j >= 0 && j < n;
+    T v;
+    if ((r & 1) == 0) {  // odd fine row j = 2J+1, J = J0 + r/2
+      const int q = r / 2;
+      v = io ? ea[q] : T(0.5) * (ea[q] + eb[q]);
+    } else {  // even fine row between coarse J0 + (r-1)/2 and the next
+      const int q = (r - 1) / 2;
+      v = io ? T(0.5) * (ea[q] + ea[q + 1]) : T(0.25) * (ea[q] + eb[q] + ea[q + 1] + eb[q + 1]);
+    }
+    x0[r] = ok ? xi[(long)j * n + i] + v : T(0);
+    bv[r] = ok && r >= 1 && r < R - 1 ? b[(long)j * n + i] : T(0);
+    x1[r] = T(0);
+  }
+  // step s (0, 1, 2) computes rows [s + 1, R - 2 - s]; step 0 has no previous iterate
+  strip_step<T, TW, R, 1, R - 2>(x0, x1, x1, bv, xs, i, n, jb, wc, we, wk, (T)pc[4], (T)pc[5]);
+  strip_step<T, TW, R, 2, R - 3>(x1, x0, x0, bv, xs, i, n, jb, wc, we, wk, (T)pc[6], (T)pc[7]);
+  strip_step<T, TW, R, 3, R - 4>(x0, x1, x1, bv, xs, i, n, jb, wc, we, wk, (T)pc[8], (T)pc[9]);
+  const T(&x)[R] = x1;
+  T* xo = Xo + (long)col * ld;
+#pragma unroll
+  for (int r = NU; r < NU + S; ++r) {
+    const int j = jb + r;
+    if (i < n && j < n) xo[(long)j * n + i] = x[r];
+  }
+}
+
+// Strip height per precision and row width: as tall as the register budget
+// of TW threads allows (the halo overhead is (2 NU + 1) / S).
+template <typename T, int TW>
+constexpr int strip_rows() {
+  return sizeof(T) == 4 ? 16 : (TW <= 512 ? 8 : 4);
+}
+
+template <typename T, int TW>
+static void launch_down(hipStream_t st, int n, int ncols, const T* B, long ld, T* X, T* Bc, long ldc,
+                        const double* P) {
+  constexpr int S = strip_rows<T, TW>();
+  const int nstrip = (n + S - 1) / S;
+  hipLaunchKernelGGL((k_mg_down<T, TW, S, kMgFusedNu>), dim3(nstrip * ncols), dim3(TW), 0, st, n, nstrip, B, ld, X,
+                     Bc, ldc, P);
+}
+
+template <typename T, int TW>
+static void launch_up(hipStream_t st, int n, int ncols, const T* Xi, const T* E, long ldc, const T* B, long ld,
+                      T* Xo, const double* P) {
+  constexpr int S = strip_rows<T, TW>();
+  const int nstrip = (n + S - 1) / S;
+  hipLaunchKernelGGL((k_mg_up<T, TW, S, kMgFusedNu>), dim3(nstrip * ncols), dim3(TW), 0, st, n, nstrip, Xi, E, ldc,
+                     B, ld, Xo, P);
+}
+
+template <typename T>
+void mg_down(hipStream_t st, int n, int ncols, const T* B, long ld, T* X, T* Bc, long ldc, const double* P) {
+  if (n < 64) launch_down<T, 64>(st, n, ncols, B, ld, X, Bc, ldc, P);
+  else if (n < 128) launch_down<T, 128>(st, n, ncols, B, ld, X, Bc, ldc, P);
+  else if (n < 256) launch_down<T, 256>(st, n, ncols, B, ld, X, Bc, ldc, P);
+  else if (n < 512) launch_down<T, 512>(st, n, ncols, B, ld, X, Bc, ldc, P);
+  else launch_down<T, 1024>(st, n, ncols, B, ld, X, Bc, ldc, P);
+}
+
+template <typename T>
+void mg_up(hipStream_t st, int n, int ncols, const T* Xi, const T* E, long ldc, const T* B, long ld, T* Xo,
+           const double* P) {
+  if (n < 64) launch_up<T, 64>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P);
+  else if (n < 128) launch_up<T, 128>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P);
+  else if (n < 256) launch_up<T, 256>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P);
+  else if (n < 512) launch_up<T, 512>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P);
+  else launch_up<T, 1024>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P);
+}
+template void mg_down<double>(hipStream_t, int, int, const double*, long, double*, double*, long, const double*);
+template void mg_down<float>(hipStream_t, int, int, const float*, long, float*, float*, long, const double*);
+template void mg_up<double>(hipStream_t, int, int, const double*, const double*, long, const double*, long, double*,
+                            const double*);
+template void mg_up<float>(hipStream_t, int, int, const float*, const float*, long, const float*, long, float*,
+                           const double*);
+
+// ---------------------------------------------------------------------------
 // Coarse levels in LDS: one workgroup per column runs a full V-cycle from the
 // level with n0 = nlds (<= 31) nodes per side down to a single node, entirely
 // in shared memory.  Pc holds per level (0 = the level entering LDS) and

@@ -201,10 +201,11 @@ Problem::Problem(const lrpost_problem_desc& d) : desc(d) {
 Problem::~Problem() {
   if (st) (void)hipStreamSynchronize(st);
   else (void)hipDeviceSynchronize();
-  for (auto& ev : prof_ev) {
-    (void)hipEventDestroy(ev.first);
-    (void)hipEventDestroy(ev.second);
-  }
+  for (auto& ps : prof_)
+    for (auto& ev : ps.ev) {
+      (void)hipEventDestroy(ev.first);
+      (void)hipEventDestroy(ev.second);
+    }
   if (staging_) (void)hipHostFree(staging_);
 }
 
@@ -320,6 +321,29 @@ void Problem::vcycle_zero(int ncols, const T* B, T* X) {
   auto xw = [&](int l) { return base + off[l]; };
   auto bw = [&](int l) { return base + off[l] + (size_t)lv[l].nx * ncols; };
   auto tw = [&](int l) { return base + off[l] + 2 * (size_t)lv[l].nx * ncols; };
+  if (mg_fused && lv[0].n <= kMgFusedMaxN) {
+    static_assert(kMgNu == kMgFusedNu, "fused kernels take the smoother's step count");
+    // down: level l pre-smoothes into its t buffer and writes the coarse
+    // right-hand side; up: x_l = smoothing from t_l + P x_{l+1}
+    for (int l = 0; l < lds_level; ++l) {
+      const int nl = lv[l].n, nc = lv[l + 1].n;
+      const T* b = l == 0 ? B : bw(l);
+      T* t = l == 0 ? base : tw(l);
+      timed(LRPOST_KERNEL_MG_DOWN, sizeof(T) * ((double)nl * nl * 2 + (double)nc * nc) * ncols,
+            [&] { mg_down<T>(st, nl, ncols, b, lv[l].nx, t, bw(l + 1), lv[l + 1].nx, prm(l)); });
+    }
+    mg_coarse_lds<T>(st, lv[lds_level].n, L - lds_level, ncols, bw(lds_level), lv[lds_level].nx, xw(lds_level),
+                     lv[lds_level].nx, prm(lds_level), kMgNu, kMgNu);
+    for (int l = lds_level - 1; l >= 0; --l) {
+      const int nl = lv[l].n, nc = lv[l + 1].n;
+      const T* b = l == 0 ? B : bw(l);
+      const T* t = l == 0 ? base : tw(l);
+      T* x = l == 0 ? X : xw(l);
+      timed(LRPOST_KERNEL_MG_UP, sizeof(T) * ((double)nl * nl * 3 + (double)nc * nc) * ncols,
+            [&] { mg_up<T>(st, nl, ncols, t, xw(l + 1), lv[l + 1].nx, b, lv[l].nx, x, prm(l)); });
+    }
+    return;
+  }
   // down: pre-smoothing from zero, x_s in (s odd ? x : t)
   for (int l = 0; l < lds_level; ++l) {
     const int nl = lv[l].n;
@@ -355,43 +379,57 @@ void Problem::vcycle_zero(int ncols, const T* B, T* X) {
   }
 }
 
-// One Chebyshev smoother step; with profiling on, bracketed by HIP events on
-// the problem's stream and credited with its algorithmic traffic: read xc,
-// xp and b once, write xo once (neighbour reads of xc are cache hits).
-template <typename T>
-void Problem::smooth_step(int nl, int ncols, const T* xc, const T* xp, T* xo, const T* b, long ld, const double* prm,
-                          int s) {
+template <class Launch>
+void Problem::timed(int kind, double bytes, Launch&& launch) {
   if (!prof_on) {
-    mg_smooth_step<T>(st, nl, ncols, xc, xp, xo, b, ld, prm, s);
+    launch();
     return;
   }
-  if (prof_used == prof_ev.size()) {
+  ProfSlot& ps = prof_[kind];
+  if (ps.used == ps.ev.size()) {
     hipEvent_t a, e;
     LRP_HIP(hipEventCreate(&a));
     LRP_HIP(hipEventCreate(&e));
-    prof_ev.push_back({a, e});
+    ps.ev.push_back({a, e});
   }
-  auto& ev = prof_ev[prof_used++];
+  auto& ev = ps.ev[ps.used++];
   LRP_HIP(hipEventRecord(ev.first, st));
-  mg_smooth_step<T>(st, nl, ncols, xc, xp, xo, b, ld, prm, s);
+  launch();
   LRP_HIP(hipEventRecord(ev.second, st));
-  const int streams = 2 + (xc ? 1 : 0) + (xp ? 1 : 0);
-  prof_bytes += (double)streams * sizeof(T) * (double)nl * nl * ncols;
+  ps.bytes += bytes;
 }
 
-void Problem::prof_read(int64_t* launches, double* ms, double* bytes) {
+// One Chebyshev smoother step, credited with its algorithmic traffic: read
+// xc, xp and b once, write xo once (neighbour reads of xc are cache hits).
+template <typename T>
+void Problem::smooth_step(int nl, int ncols, const T* xc, const T* xp, T* xo, const T* b, long ld, const double* prm,
+                          int s) {
+  const int streams = 2 + (xc ? 1 : 0) + (xp ? 1 : 0);
+  timed(LRPOST_KERNEL_SMOOTHER_STEP, (double)streams * sizeof(T) * (double)nl * nl * ncols,
+        [&] { mg_smooth_step<T>(st, nl, ncols, xc, xp, xo, b, ld, prm, s); });
+}
+
+void Problem::prof_reset() {
+  for (auto& ps : prof_) {
+    ps.used = 0;
+    ps.bytes = 0.0;
+  }
+}
+
+void Problem::prof_read(int kind, int64_t* launches, double* ms, double* bytes) {
   sync();
+  ProfSlot& ps = prof_[kind];
   double tot = 0.0;
-  for (size_t i = 0; i < prof_used; ++i) {
+  for (size_t i = 0; i < ps.used; ++i) {
     float t = 0.0f;
-    LRP_HIP(hipEventElapsedTime(&t, prof_ev[i].first, prof_ev[i].second));
+    LRP_HIP(hipEventElapsedTime(&t, ps.ev[i].first, ps.ev[i].second));
     tot += t;
   }
-  *launches = (int64_t)prof_used;
+  *launches = (int64_t)ps.used;
   *ms = tot;
-  *bytes = prof_bytes;
-  prof_used = 0;
-  prof_bytes = 0.0;
+  *bytes = ps.bytes;
+  ps.used = 0;
+  ps.bytes = 0.0;
 }
 
 void Problem::mg_cycles_f32(int ncols, const float* B, float* X, const std::vector<ShiftCoef>& neg, int cycles) {

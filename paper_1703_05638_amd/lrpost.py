@@ -23,6 +23,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "lrpost.h")
 LRPOST_FP64, LRPOST_MIXED = 0, 1
 LRPOST_MISFIT, LRPOST_PRECOND = 0, 1
 LRPOST_BLOCK_LANCZOS, LRPOST_RANDOMIZED = 0, 1
+LRPOST_KERNEL_SMOOTHER_STEP, LRPOST_KERNEL_MG_DOWN, LRPOST_KERNEL_MG_UP = 0, 1, 2
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "ENOCONV", -4: "EBREAKDOWN", -5: "EHIP"}
 
 
@@ -96,7 +97,8 @@ def load(path: str = LIB_PATH):
         "lrpost_truncate": (I, [P, ctypes.POINTER(LowRankC), D, I]),
         "lrpost_set_log": (I, [P, I]),
         "lrpost_profile": (I, [P, I]),
-        "lrpost_profile_read": (I, [P, ctypes.POINTER(ctypes.c_int64), pd, pd]),
+        "lrpost_profile_read": (I, [P, I, ctypes.POINTER(ctypes.c_int64), pd, pd]),
+        "lrpost_set_mg_fused": (I, [P, I]),
         "lrpost_server_create": (I, [ctypes.c_size_t, I, ctypes.POINTER(P)]),
         "lrpost_server_submit": (I, [P, P, I, I, ctypes.POINTER(ctypes.c_uint64)]),
         "lrpost_server_wait": (I, [P, ctypes.c_uint64, pd, I, pd, pd]),
@@ -370,16 +372,22 @@ class Problem:
         _check(_lib.lrpost_set_log(self.h, level))
 
     def profile(self, enable: bool):
-        """Turn event timing of the multigrid smoother kernel on or off."""
+        """Turn event timing of the multigrid kernels on or off."""
         _check(_lib.lrpost_profile(self.h, 1 if enable else 0))
 
-    def profile_read(self):
-        """(launches, kernel ms, algorithmic bytes) since the last read."""
+    def profile_read(self, kernel: int = None):
+        """(launches, kernel ms, algorithmic bytes) of one kernel kind
+        (LRPOST_KERNEL_*; default the level-fused up kernel) since the last read."""
         n = ctypes.c_int64()
         ms = ctypes.c_double()
         by = ctypes.c_double()
-        _check(_lib.lrpost_profile_read(self.h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+        k = LRPOST_KERNEL_MG_UP if kernel is None else kernel
+        _check(_lib.lrpost_profile_read(self.h, k, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
         return n.value, ms.value, by.value
+
+    def set_mg_fused(self, on: bool):
+        """Level-fused multigrid kernels (default) or one kernel per step."""
+        _check(_lib.lrpost_set_mg_fused(self.h, 1 if on else 0))
 
     def stats(self) -> dict:
         s = Stats()

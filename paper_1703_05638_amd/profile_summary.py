@@ -1,4 +1,4 @@
-"""Summaries of rocprofv3 CSV output for the smoother kernel.
+"""Summaries of rocprofv3 CSV output for the multigrid kernels.
 
 Two modes, each printing a short text report:
 
@@ -26,11 +26,24 @@ import sys
 ROOT = os.path.dirname(os.path.abspath(__file__))
 
 
-def smoother_source_digest():
-    """sha256 of the Chebyshev smoother kernel and its launcher in kernels.hip."""
+# source regions (first and last marker in kernels.hip) whose digest a
+# traffic report records, by the kernel-name prefix the report matches
+KERNEL_SOURCES = {
+    "k_cheb": ("void k_cheb(", "template void mg_smooth_step<float>"),
+    "k_mg": ("__device__ inline void strip_of(", "template void mg_up<float>"),
+}
+
+
+def _source_key(regex):
+    return "k_mg" if "k_mg" in regex else "k_cheb"
+
+
+def source_digest(key="k_cheb"):
+    """sha256 (16 hex digits) of a kernel's source region in kernels.hip."""
     src = open(os.path.join(ROOT, "csrc", "kernels.hip")).read()
-    a = src.index("void k_cheb(")
-    b = src.index("template void mg_smooth_step<float>")
+    first, last = KERNEL_SOURCES[key]
+    a = src.index(first)
+    b = src.index(last)
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
@@ -85,7 +98,7 @@ def traffic(fetch_dir, write_dir, regex, copy_regex, copy_bytes):
     f_write = statistics.median(cw) * 1024.0 / copy_bytes
     per_launch = (statistics.mean(kf) / f_fetch + statistics.mean(kw) / f_write) * 1024.0
     print("kernel_regex: %s" % regex)
-    print("kernel_source_sha256_16: %s" % smoother_source_digest())
+    print("kernel_source_sha256_16: %s" % source_digest(_source_key(regex)))
     print("dispatches_fetch: %d" % len(kf))
     print("dispatches_write: %d" % len(kw))
     print("fetch_kib_per_dispatch_mean: %.3f" % statistics.mean(kf))
@@ -101,7 +114,7 @@ def traffic(fetch_dir, write_dir, regex, copy_regex, copy_bytes):
 
 def read_traffic(path):
     """traffic_bytes_per_launch from a committed report, or None when the report
-    is absent or the smoother source has changed since it was taken."""
+    is absent or the kernel's source has changed since it was taken."""
     if not os.path.exists(path):
         return None
     vals = {}
@@ -109,7 +122,8 @@ def read_traffic(path):
         if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != smoother_source_digest():
+    key = _source_key(vals.get("kernel_regex", ""))
+    if vals.get("kernel_source_sha256_16") != source_digest(key):
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])

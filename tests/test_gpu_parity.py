@@ -78,6 +78,29 @@ def test_multigrid_solve_converges_to_direct_solve(lp, N):
     assert np.linalg.norm(X1[0] - ref0) / np.linalg.norm(ref0) < 0.2
 
 
+@pytest.mark.parametrize("N", [64, 128, 256, 512, 1024])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fused_multigrid_levels_equal_per_step_kernels(lp, N, precision):
+    """The level-fused V-cycle kernels against the per-step kernels (one
+    launch per smoother step, residual-restriction and prolongation): the same
+    iterates, so the same solve up to rounding; five columns of different
+    shifts make the workgroup count no multiple of eight."""
+    print("case mg fused vs per-step N=%d %s" % (N, precision), flush=True)
+    prob = lp.Problem(_desc(N, 4, precision=precision))
+    rng = np.random.default_rng(N)
+    B = _dev(rng.standard_normal((5, prob.nx)))
+    coef = np.array([[1.0, 1.0], [1.0 / 200, 1.0], [1e-3, 50.0], [1.0, 0.0], [0.3, 7.0]])
+    X_fused = prob.mg_solve(B, coef, 2).cpu().numpy()
+    prob.set_mg_fused(False)
+    X_step = prob.mg_solve(B, coef, 2).cpu().numpy()
+    prob.set_mg_fused(True)
+    X_again = prob.mg_solve(B, coef, 2).cpu().numpy()
+    err = np.abs(X_fused - X_step).max() / np.abs(X_step).max()
+    print("fused vs per-step max rel diff %.3e" % err, flush=True)
+    assert np.array_equal(X_fused, X_again)
+    assert err <= (1e-13 if precision == "fp64" else 1e-6), err
+
+
 def test_gram_matches_definition(lp):
     d = _desc(128, 4)
     prob = lp.Problem(d)
