@@ -19,6 +19,12 @@
 
 namespace lrp {
 
+// Fused multiply-add with one rounding, written out where the per-step and
+// the level-fused multigrid kernels must round identically (the compiler's
+// own contraction of a*b + c*d may pick either product).
+__device__ inline float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // ---------------------------------------------------------------------------
 // Stencil: Y[:,c] = wc*x + we*(edges) + wk*(corners) + zc * Z[:,c]
 // Each thread owns one x1 index and walks S consecutive rows, keeping the
@@ -89,6 +95,9 @@ template void stencil<float>(hipStream_t, int, int, const float*, long, float*, 
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_cheb(int n, const T* Xc, const T* Xp, T* Xo, const T* __restrict__ B,
                                               long ld, const double* __restrict__ P, int step) {
+  // only the explicit fmad() calls fuse: the per-step and level-fused
+  // kernels then round every node identically
+#pragma clang fp contract(off)
   const int col = blockIdx.z;
   const int i = blockIdx.x * 64 + threadIdx.x;
   const int j0 = (blockIdx.y * 4 + threadIdx.y) * S;
@@ -106,7 +115,7 @@ __global__ __launch_bounds__(256) void k_cheb(int n, const T* Xc, const T* Xp, T
       if (j >= n) break;
       const long idx = (long)j * n + i;
       const T prev = xp ? xp[idx] : T(0);
-      xo[idx] = -al * prev + be * b[idx];
+      xo[idx] = fmad(be, b[idx], -al * prev);
     }
     return;
   }
@@ -128,9 +137,9 @@ __global__ __launch_bounds__(256) void k_cheb(int n, const T* Xc, const T* Xp, T
     if (j >= n) break;
     row(j + 1, l2, m2, r2);
     const long idx = (long)j * n + i;
-    const T ax = wc * m1 + we * ((l1 + r1) + (m0 + m2)) + wk * ((l0 + r0) + (l2 + r2));
+    const T ax = fmad(wk, (l0 + r0) + (l2 + r2), fmad(we, (l1 + r1) + (m0 + m2), wc * m1));
     const T prev = xp ? xp[idx] : T(0);
-    xo[idx] = m1 + al * (m1 - prev) + be * (b[idx] - ax);
+    xo[idx] = fmad(be, b[idx] - ax, fmad(al, m1 - prev, m1));
     l0 = l1; m0 = m1; r0 = r1;
     l1 = l2; m1 = m2; r1 = r2;
   }
@@ -162,6 +171,9 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_resid_restrict(int n, int nc, const T* __restrict__ X,
                                                         const T* __restrict__ B, long ld, T* __restrict__ Bc,
                                                         long ldc, const double* __restrict__ P) {
+  // only the explicit fmad() calls fuse: the per-step and level-fused
+  // kernels then round every node identically
+#pragma clang fp contract(off)
   __shared__ T xs[RFJ + 2][RFI + 3];
   __shared__ T rs[RFJ][RFI + 1];
   const int col = blockIdx.z;
@@ -186,8 +198,9 @@ __global__ __launch_bounds__(256) void k_resid_restrict(int n, int nc, const T* 
     if (fi < n && fj < n) {
       v = b[(long)fj * n + fi];
       if (x)
-        v -= wc * xs[r + 1][c + 1] + we * ((xs[r + 1][c] + xs[r + 1][c + 2]) + (xs[r][c + 1] + xs[r + 2][c + 1])) +
-             wk * ((xs[r][c] + xs[r][c + 2]) + (xs[r + 2][c] + xs[r + 2][c + 2]));
+        v -= fmad(wk, (xs[r][c] + xs[r][c + 2]) + (xs[r + 2][c] + xs[r + 2][c + 2]),
+                  fmad(we, (xs[r + 1][c] + xs[r + 1][c + 2]) + (xs[r][c + 1] + xs[r + 2][c + 1]),
+                       wc * xs[r + 1][c + 1]));
     }
     rs[r][c] = v;
   }
@@ -217,6 +230,9 @@ template void mg_resid_restrict<float>(hipStream_t, int, int, const float*, cons
 template <typename T>
 __global__ __launch_bounds__(256) void k_prolong_add(int n, int nc, const T* __restrict__ E, long ldc,
                                                      const T* __restrict__ Xi, T* __restrict__ Xo, long ld) {
+  // only the explicit fmad() calls fuse: the per-step and level-fused
+  // kernels then round every node identically
+#pragma clang fp contract(off)
   const int col = blockIdx.z;
   const int i = blockIdx.x * 64 + threadIdx.x;
   const int j = blockIdx.y * 4 + threadIdx.y;
@@ -277,10 +293,15 @@ __device__ inline void strip_of(int nstrip, int& strip, int& col) {
 // One smoother step on rows [lo, hi] of the register column:
 //   out = cur + al (cur - prv) + be (b - A cur),
 // with cur's rows [lo - 1, hi + 1] exchanged through LDS first.  Rows outside
-// the mesh (jb + r outside [0, n)) and columns i >= n are kept at zero.
-template <typename T, int TW, int R, int lo, int hi>
+// the mesh (jb + r outside [0, n)) are kept at zero (INNER strips have every
+// row inside the mesh); so are columns i >= n, whose cur and prv are zero and
+// whose coefficients are taken as zero.
+template <typename T, int TW, int R, int lo, int hi, bool INNER>
 __device__ inline void strip_step(const T (&cur)[R], const T (&prv)[R], T (&out)[R], const T (&b)[R], T* xs, int i,
                                   int n, int jb, T wc, T we, T wk, T al, T be) {
+  // only the explicit fmad() calls fuse: the per-step and level-fused
+  // kernels then round every node identically
+#pragma clang fp contract(off)
   constexpr int LP = TW + 2;
   __syncthreads();
 #pragma unroll
@@ -291,61 +312,68 @@ __device__ inline void strip_step(const T (&cur)[R], const T (&prv)[R], T (&out)
 #pragma unroll
   for (int r = 0; r < R; ++r)
     if (r >= lo - 1 && r <= hi + 1) hs[r] = xs[r * LP + i] + xs[r * LP + i + 2];
+  const bool act = i < n;
+  const T alm = act ? al : T(0), bem = act ? be : T(0);
 #pragma unroll
   for (int r = 0; r < R; ++r)
     if (r >= lo && r <= hi) {
       const T m = cur[r];
-      const T ax = wc * m + we * (hs[r] + (cur[r - 1] + cur[r + 1])) + wk * (hs[r - 1] + hs[r + 1]);
-      const T v = m + al * (m - prv[r]) + be * (b[r] - ax);
+      const T ax = fmad(wk, hs[r - 1] + hs[r + 1], fmad(we, hs[r] + (cur[r - 1] + cur[r + 1]), wc * m));
+      const T v = fmad(bem, b[r] - ax, fmad(alm, m - prv[r], m));
       const int j = jb + r;
-      out[r] = (i < n && j >= 0 && j < n) ? v : T(0);
+      out[r] = (INNER || (j >= 0 && j < n)) ? v : T(0);
     }
 }
 
-template <typename T, int TW, int S, int NU>
-__global__ __launch_bounds__(TW) void k_mg_down(int n, int nstrip, const T* __restrict__ B, long ld,
-                                                T* __restrict__ Xo, T* __restrict__ Bc, long ldc,
-                                                const double* __restrict__ P) {
-  static_assert(NU == 3, "three smoother steps");
+// Row r of a strip's register column (mesh row jb + r, column i) of a
+// column-major n x n block: every load is unconditional, with the row index
+// clamped into the mesh, so that all of them are in flight at once; values
+// outside the mesh are zeroed after (in columns i >= n only when LANES).
+template <typename T, int R, bool INNER, bool LANES>
+__device__ inline void load_rows(const T* __restrict__ a, int n, int i, int jb, T (&v)[R], int r0 = 0,
+                                 int r1 = R) {
+  const unsigned ic = i < n ? i : n - 1;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (r < r0 || r >= r1) continue;
+    const int j = jb + r;
+    const int jc = INNER ? j : (j < 0 ? 0 : (j >= n ? n - 1 : j));
+    const T x = (a + (unsigned)(jc * n))[ic];
+    v[r] = ((!LANES || i < n) && (INNER || (j >= 0 && j < n))) ? x : T(0);
+  }
+}
+
+template <typename T, int TW, int S, int NU, bool INNER>
+__device__ inline void mg_down_body(T* xs, int n, int col, int strip, const T* __restrict__ B, long ld,
+                                    T* __restrict__ Xo, T* __restrict__ Bc, long ldc, const double* __restrict__ P) {
+  // only the explicit fmad() calls fuse: the per-step and level-fused
+  // kernels then round every node identically
+#pragma clang fp contract(off)
   constexpr int R = S + 2 * NU + 1;  // rows j0 - NU .. j0 + S + NU
   constexpr int LP = TW + 2;
-  __shared__ T xs[R * LP];
-  int strip, col;
-  strip_of(nstrip, strip, col);
   const int i = threadIdx.x;
   const int j0 = strip * S, jb = j0 - NU;
   const double* pc = P + (long)col * kMgStride;
   const T wc = (T)pc[0], we = (T)pc[1], wk = (T)pc[2];
-  for (int r = i; r < R; r += TW) {
-    xs[r * LP] = T(0);
-    xs[r * LP + TW + 1] = T(0);
-  }
-  const T* b = B + (long)col * ld;
   T bv[R], x0[R], x1[R];
+  load_rows<T, R, INNER, false>(B + (long)col * ld, n, i, jb, bv);
+  // step 0 from zero: x_1 = be_0 b (zero in columns i >= n)
+  const T be0 = i < n ? (T)pc[5] : T(0);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int j = jb + r;
-    bv[r] = (i < n && j >= 0 && j < n) ? b[(long)j * n + i] : T(0);
-  }
-  // step 0 from zero: x_1 = be_0 b
-  {
-    const T be = (T)pc[5];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      x1[r] = be * bv[r];
-      x0[r] = T(0);
-    }
+    x1[r] = be0 * bv[r];
+    x0[r] = T(0);
   }
   // step s (1, 2) computes rows [s, R-1-s]
-  strip_step<T, TW, R, 1, R - 2>(x1, x0, x0, bv, xs, i, n, jb, wc, we, wk, (T)pc[6], (T)pc[7]);
-  strip_step<T, TW, R, 2, R - 3>(x0, x1, x1, bv, xs, i, n, jb, wc, we, wk, (T)pc[8], (T)pc[9]);
+  strip_step<T, TW, R, 1, R - 2, INNER>(x1, x0, x0, bv, xs, i, n, jb, wc, we, wk, (T)pc[6], (T)pc[7]);
+  strip_step<T, TW, R, 2, R - 3, INNER>(x0, x1, x1, bv, xs, i, n, jb, wc, we, wk, (T)pc[8], (T)pc[9]);
   const T(&x)[R] = x1;
   // owned rows
   T* xo = Xo + (long)col * ld;
 #pragma unroll
   for (int r = NU; r < NU + S; ++r) {
     const int j = jb + r;
-    if (i < n && j < n) xo[(long)j * n + i] = x[r];
+    if (i < n && (INNER || j < n)) (xo + (unsigned)(j * n))[(unsigned)i] = x[r];
   }
   // residual on rows j0 .. j0 + S (local r = NU .. NU + S), then restriction
   const int nc = (n - 1) / 2;
@@ -362,13 +390,14 @@ __global__ __launch_bounds__(TW) void k_mg_down(int n, int nstrip, const T* __re
       const T hu = xs[(r - 1) * LP + i] + xs[(r - 1) * LP + i + 2];
       const T hd = xs[(r + 1) * LP + i] + xs[(r + 1) * LP + i + 2];
       T v = bv[r];
-      v -= wc * x[r] + we * (hm + (x[r - 1] + x[r + 1])) + wk * (hu + hd);
+      v -= fmad(wk, hu + hd, fmad(we, hm + (x[r - 1] + x[r + 1]), wc * x[r]));
       res[r] = v;
     }
   __syncthreads();
+  // (the restriction reads columns 0 .. n-1 only)
 #pragma unroll
   for (int r = 0; r < R; ++r)
-    if (r >= NU && r <= NU + S) xs[(r - NU) * LP + i + 1] = (i < n) ? res[r] : T(0);
+    if (r >= NU && r <= NU + S) xs[(r - NU) * LP + i + 1] = res[r];
   __syncthreads();
   const int J0 = j0 / 2;
   T* bc = Bc + (long)col * ldc;
@@ -383,46 +412,62 @@ __global__ __launch_bounds__(TW) void k_mg_down(int n, int nstrip, const T* __re
 }
 
 template <typename T, int TW, int S, int NU>
-__global__ __launch_bounds__(TW) void k_mg_up(int n, int nstrip, const T* __restrict__ Xi, const T* __restrict__ E,
-                                              long ldc, const T* __restrict__ B, long ld, T* __restrict__ Xo,
-                                              const double* __restrict__ P) {
-  constexpr int R = S + 2 * NU;  // rows j0 - NU .. j0 + S + NU - 1
+__global__ __launch_bounds__(TW) void k_mg_down(int n, int nstrip, const T* __restrict__ B, long ld,
+                                                T* __restrict__ Xo, T* __restrict__ Bc, long ldc,
+                                                const double* __restrict__ P) {
+  static_assert(NU == 3, "three smoother steps");
+  constexpr int R = S + 2 * NU + 1;
   constexpr int LP = TW + 2;
-  constexpr int NCR = R / 2 + 1;  // coarse rows j0/2 - 2 + q, q < NCR
   __shared__ T xs[R * LP];
-  static_assert(NU == 3, "three smoother steps; the coarse-row bookkeeping assumes a halo of three rows");
   int strip, col;
   strip_of(nstrip, strip, col);
+  for (int r = threadIdx.x; r < R; r += TW) {
+    xs[r * LP] = T(0);
+    xs[r * LP + TW + 1] = T(0);
+  }
+  const int jb = strip * S - NU;
+  if (jb >= 0 && jb + R <= n) mg_down_body<T, TW, S, NU, true>(xs, n, col, strip, B, ld, Xo, Bc, ldc, P);
+  else mg_down_body<T, TW, S, NU, false>(xs, n, col, strip, B, ld, Xo, Bc, ldc, P);
+}
+
+template <typename T, int TW, int S, int NU, bool INNER>
+__device__ inline void mg_up_body(T* xs, int n, int col, int strip, const T* __restrict__ Xi,
+                                  const T* __restrict__ E, long ldc, const T* __restrict__ B, long ld,
+                                  T* __restrict__ Xo, const double* __restrict__ P) {
+  // only the explicit fmad() calls fuse: the per-step and level-fused
+  // kernels then round every node identically
+#pragma clang fp contract(off)
+  constexpr int R = S + 2 * NU;  // rows j0 - NU .. j0 + S + NU - 1
+  constexpr int NCR = R / 2 + 1;  // coarse rows j0/2 - 2 + q, q < NCR
   const int i = threadIdx.x;
   const int j0 = strip * S, jb = j0 - NU;
   const int nc = (n - 1) / 2;
   const double* pc = P + (long)col * kMgStride;
   const T wc = (T)pc[0], we = (T)pc[1], wk = (T)pc[2];
-  for (int r = i; r < R; r += TW) {
-    xs[r * LP] = T(0);
-    xs[r * LP + TW + 1] = T(0);
-  }
-  const T* xi = Xi + (long)col * ld;
-  const T* b = B + (long)col * ld;
   const T* e = E + (long)col * ldc;
   // coarse columns feeding fine column i: odd i sits on coarse (i-1)/2; even i
   // lies between i/2 - 1 and i/2
   const bool io = i & 1;
   const int ca = io ? (i - 1) >> 1 : (i >> 1) - 1, cb = i >> 1;
   const int J0 = j0 / 2 - 2;  // j0 even, jb = j0 - 3 odd: row r is odd when r is even
+  const bool oka = ca >= 0 && ca < nc, okb = !io && cb < nc;
+  const unsigned cac = ca < 0 ? 0 : (ca >= nc ? nc - 1 : ca), cbc = cb >= nc ? nc - 1 : cb;
   T ea[NCR], eb[NCR];
 #pragma unroll
   for (int q = 0; q < NCR; ++q) {
     const int J = J0 + q;
     const bool okj = J >= 0 && J < nc;
-    ea[q] = (okj && ca >= 0 && ca < nc) ? e[(long)J * nc + ca] : T(0);
-    eb[q] = (okj && !io && cb < nc) ? e[(long)J * nc + cb] : T(0);
+    const int Jc = J < 0 ? 0 : (J >= nc ? nc - 1 : J);
+    const T* er = e + (unsigned)(Jc * nc);  // uniform row base
+    const T va = er[cac], vb = er[cbc];
+    ea[q] = (okj && oka) ? va : T(0);
+    eb[q] = (okj && okb) ? vb : T(0);
   }
   T bv[R], x0[R], x1[R];
+  load_rows<T, R, INNER, true>(Xi + (long)col * ld, n, i, jb, x0);
+  load_rows<T, R, INNER, false>(B + (long)col * ld, n, i, jb, bv, 1, R - 1);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int j = jb + r;
-    const bool ok = i < n && j >= 0 && j < n;
     T v;
     if ((r & 1) == 0) {  // odd fine row j = 2J+1, J = J0 + r/2
       const int q = r / 2;
@@ -431,21 +476,40 @@ __global__ __launch_bounds__(TW) void k_mg_up(int n, int nstrip, const T* __rest
       const int q = (r - 1) / 2;
       v = io ? T(0.5) * (ea[q] + ea[q + 1]) : T(0.25) * (ea[q] + eb[q] + ea[q + 1] + eb[q + 1]);
     }
-    x0[r] = ok ? xi[(long)j * n + i] + v : T(0);
-    bv[r] = ok && r >= 1 && r < R - 1 ? b[(long)j * n + i] : T(0);
+    const int j = jb + r;
+    x0[r] = (i < n && (INNER || (j >= 0 && j < n))) ? x0[r] + v : T(0);
     x1[r] = T(0);
   }
   // step s (0, 1, 2) computes rows [s + 1, R - 2 - s]; step 0 has no previous iterate
-  strip_step<T, TW, R, 1, R - 2>(x0, x1, x1, bv, xs, i, n, jb, wc, we, wk, (T)pc[4], (T)pc[5]);
-  strip_step<T, TW, R, 2, R - 3>(x1, x0, x0, bv, xs, i, n, jb, wc, we, wk, (T)pc[6], (T)pc[7]);
-  strip_step<T, TW, R, 3, R - 4>(x0, x1, x1, bv, xs, i, n, jb, wc, we, wk, (T)pc[8], (T)pc[9]);
+  strip_step<T, TW, R, 1, R - 2, INNER>(x0, x1, x1, bv, xs, i, n, jb, wc, we, wk, (T)pc[4], (T)pc[5]);
+  strip_step<T, TW, R, 2, R - 3, INNER>(x1, x0, x0, bv, xs, i, n, jb, wc, we, wk, (T)pc[6], (T)pc[7]);
+  strip_step<T, TW, R, 3, R - 4, INNER>(x0, x1, x1, bv, xs, i, n, jb, wc, we, wk, (T)pc[8], (T)pc[9]);
   const T(&x)[R] = x1;
   T* xo = Xo + (long)col * ld;
 #pragma unroll
   for (int r = NU; r < NU + S; ++r) {
     const int j = jb + r;
-    if (i < n && j < n) xo[(long)j * n + i] = x[r];
+    if (i < n && (INNER || j < n)) (xo + (unsigned)(j * n))[(unsigned)i] = x[r];
   }
+}
+
+template <typename T, int TW, int S, int NU>
+__global__ __launch_bounds__(TW) void k_mg_up(int n, int nstrip, const T* __restrict__ Xi, const T* __restrict__ E,
+                                              long ldc, const T* __restrict__ B, long ld, T* __restrict__ Xo,
+                                              const double* __restrict__ P) {
+  static_assert(NU == 3, "three smoother steps; the coarse-row bookkeeping assumes a halo of three rows");
+  constexpr int R = S + 2 * NU;
+  constexpr int LP = TW + 2;
+  __shared__ T xs[R * LP];
+  int strip, col;
+  strip_of(nstrip, strip, col);
+  for (int r = threadIdx.x; r < R; r += TW) {
+    xs[r * LP] = T(0);
+    xs[r * LP + TW + 1] = T(0);
+  }
+  const int jb = strip * S - NU;
+  if (jb >= 0 && jb + R <= n) mg_up_body<T, TW, S, NU, true>(xs, n, col, strip, Xi, E, ldc, B, ld, Xo, P);
+  else mg_up_body<T, TW, S, NU, false>(xs, n, col, strip, Xi, E, ldc, B, ld, Xo, P);
 }
 
 // Strip height per precision and row width: as tall as the register budget
