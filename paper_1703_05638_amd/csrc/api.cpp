@@ -299,7 +299,7 @@ int lrpost_post_variance(lrpost_problem* p, const lrpost_eigs* e, double* diag, 
     Bt.ensure(sizeof(double) * bt.size());
     P->to_device(Bt.as<double>(), bt.data(), bt.size());
     segd.ensure(sizeof(int) * seg.size());
-    LRP_HIP(hipMemcpyAsync(segd.p, seg.data(), sizeof(int) * seg.size(), hipMemcpyHostToDevice, P->st));
+    P->to_device_bytes(segd.p, seg.data(), sizeof(int) * seg.size());
     dco.ensure(sizeof(double) * dc.size());
     P->to_device(dco.as<double>(), dc.data(), dc.size());
     double* out = diag;
@@ -310,7 +310,7 @@ int lrpost_post_variance(lrpost_problem* p, const lrpost_eigs* e, double* diag, 
     post_variance(P->st, nx, nt, k, segd.as<int>(), dco.as<double>(), A.as<double>(), nx, Bt.as<double>(),
                   std::max(R, 1), P->dprior.as<double>(), out, nx);
     LRP_HIP(hipGetLastError());
-    if (!on_device) LRP_HIP(hipMemcpyAsync(diag, out, sizeof(double) * (size_t)nx * nt, hipMemcpyDeviceToHost, P->st));
+    if (!on_device) P->to_host(diag, out, (size_t)nx * nt);
     P->sync();
   });
 }
@@ -345,7 +345,7 @@ int lrpost_sample(lrpost_problem* p, const lrpost_eigs* e, int ns, const double*
     const double* X = xi;
     if (!on_device) {
       Xd.ensure(sizeof(double) * (size_t)nx * cols);
-      LRP_HIP(hipMemcpyAsync(Xd.p, xi, sizeof(double) * (size_t)nx * cols, hipMemcpyHostToDevice, P->st));
+      P->to_device(Xd.as<double>(), xi, (size_t)nx * cols);
       X = Xd.as<double>();
     }
     double* Lx = out;
@@ -389,8 +389,7 @@ int lrpost_sample(lrpost_problem* p, const lrpost_eigs* e, int ns, const double*
       P->dense->gemm(false, false, (int)nx, (int)cols, R, 1.0, A.as<double>(), (int)nx, Cm.as<double>(), R, 1.0, Lx,
                      (int)nx);
     }
-    if (!on_device)
-      LRP_HIP(hipMemcpyAsync(out, Lx, sizeof(double) * (size_t)nx * cols, hipMemcpyDeviceToHost, P->st));
+    if (!on_device) P->to_host(out, Lx, (size_t)nx * cols);
     P->sync();
   });
 }

@@ -267,9 +267,7 @@ class SharedBasis {
     double tail = 0.0;
     if (tol < 1e-7) {
       std::vector<double> Sh((size_t)rows * nt);
-      LRP_HIP(hipMemcpy2DAsync(Sh.data(), sizeof(double) * rows, S, sizeof(double) * lds, sizeof(double) * rows, nt,
-                               hipMemcpyDeviceToHost, P->st));
-      P->sync();
+      P->to_host_block(Sh.data(), S, rows, nt, lds);
       std::vector<double> Us, Vs;
       svd(rows, nt, Sh.data(), rows, sv, Us, Vs);
       r = truncation_rank(sv, tol, cap, &tail);
@@ -395,8 +393,7 @@ class SharedBasis {
     out.resize(nx, nt, v.r);
     if (v.r == 0) return;
     P->proj_dev(v.s, U.as<double>(), v.C.as<double>(), v.s, v.r, out.a(), 0.0);
-    LRP_HIP(hipMemcpyAsync(out.B.data(), v.B.p, sizeof(double) * (size_t)nt * v.r, hipMemcpyDeviceToHost, P->st));
-    P->sync();
+    P->to_host(out.B.data(), v.B.as<double>(), (size_t)nt * v.r);
   }
 
   CVec stored(int k) {

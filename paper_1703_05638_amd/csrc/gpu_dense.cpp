@@ -198,20 +198,6 @@ void GpuDense::syevd(int n, double* A, int lda, double* w, DevMem& work) {
            "rocsolver_dsyevd");
 }
 
-bool GpuDense::spd_inverse_upper(int n, double* A, int lda, DevMem& work) {
-  if (n <= 0) return true;
-  work.ensure(64);
-  int* info = work.as<int>();
-  SolverSection section(st_);
-  rb_check(rocsolver_dpotrf((rocblas_handle)handle, rocblas_fill_upper, n, A, lda, info), "rocsolver_dpotrf");
-  int h = 0;
-  LRP_HIP(hipMemcpyAsync(&h, info, sizeof(int), hipMemcpyDeviceToHost, st_));
-  LRP_HIP(hipStreamSynchronize(st_));
-  if (h != 0) return false;
-  rb_check(rocsolver_dpotri((rocblas_handle)handle, rocblas_fill_upper, n, A, lda, info), "rocsolver_dpotri");
-  return true;
-}
-
 void GpuDense::dgmm_right(int m, int n, const double* A, int lda, const double* x, double* C, int ldc) {
   if (m <= 0 || n <= 0) return;
   BlasSection blas(st_);

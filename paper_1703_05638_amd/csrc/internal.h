@@ -87,8 +87,6 @@ class GpuDense {
                             const double* B, int ldb, long sb, double beta, double* C, int ldc, long sc, int batch);
   // A (n x n, upper triangle) -> eigenvectors in place, eigenvalues ascending in w (all device)
   void syevd(int n, double* A, int lda, double* w, DevMem& work);
-  // A (n x n SPD, upper triangle) -> upper triangle of A^{-1} (Cholesky); false if not positive definite
-  bool spd_inverse_upper(int n, double* A, int lda, DevMem& work);
   // C = A diag(x) (A, C: m x n device; x: n device)
   void dgmm_right(int m, int n, const double* A, int lda, const double* x, double* C, int ldc);
   void scal(int n, double alpha, double* x);
@@ -141,9 +139,18 @@ class Problem {
   lrpost_stats stats{};
 
   // ---- small host/device transfers -------------------------------------
+  // Every host transfer goes through pinned buffers of the problem's own:
+  // the runtime stages pageable copies through buffers that all threads
+  // share, and problems served concurrently read back corrupted values
+  // through them.  to_host* return after the data has arrived.
   void sync();
   void to_host(double* dst, const double* src, size_t count);
   void to_device(double* dst, const double* src, size_t count);
+  void to_host_bytes(void* dst, const void* src, size_t bytes);
+  void to_device_bytes(void* dst, const void* src, size_t bytes);
+  // rows x cols block of doubles with leading dimension ld (device) into a
+  // contiguous host array (leading dimension rows)
+  void to_host_block(double* dst, const double* src, int rows, int cols, long ld);
 
   // ---- spatial building blocks (double) --------------------------------
   // Y = (a_j K + b_j M) X + c_j Z on the finest level
@@ -239,8 +246,12 @@ class Problem {
   DevMem mg_param_, mg_work_, mg_res_, gram_part_, gram_out_, proj_q_, op_w_;
   std::map<std::array<double, 3>, DevMem> op_w_cache_;  // weights of column-uniform operators
   static constexpr size_t kStagingBytes = size_t(32) << 20;
-  void* staging_ = nullptr;
+  static constexpr size_t kReadbackBytes = size_t(8) << 20;
+  void* staging_ = nullptr;   // pinned, host -> device, recycled at every sync
   size_t staging_used_ = 0;
+  void* readback_ = nullptr;  // pinned, device -> host
+  double ns_bound_ = 1.0;     // upper bound of the eigenvalues of the projected I + tau K
+  int ns_iters_ = 1;          // Newton-Schulz steps for its inverse
   std::vector<double> mg_param_h_, op_w_h_;
   std::vector<double> tmp_h_;
   template <typename T>

@@ -25,6 +25,18 @@ namespace lrp {
 __device__ inline float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ inline double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// Workgroup w of a launch over strips of columns -> (strip, column): the
+// hardware hands workgroups to the 8 XCDs round robin, so consecutive strips
+// of a column are given to workgroups 8 apart, which share an XCD and its L2
+// (neighbouring strips read each other's edge rows).
+__device__ inline void strip_of(int nstrip, int& strip, int& col) {
+  const int w = blockIdx.x, g = gridDim.x;
+  const int full = g & ~7;
+  const int lw = w < full ? (w & 7) * (full >> 3) + (w >> 3) : w;
+  strip = lw % nstrip;
+  col = lw / nstrip;
+}
+
 // ---------------------------------------------------------------------------
 // Stencil: Y[:,c] = wc*x + we*(edges) + wk*(corners) + zc * Z[:,c]
 // Each thread owns one x1 index and walks S consecutive rows, keeping the
@@ -69,10 +81,107 @@ __global__ __launch_bounds__(256) void k_stencil(int n, const T* __restrict__ X,
   }
 }
 
+// Strip form for meshes of up to 1024 nodes per side: a workgroup of TW >= n
+// threads owns S consecutive full mesh rows of one column (one contiguous
+// stretch of memory), thread i walks mesh column i down the strip with the
+// three rows it needs in registers, and its left and right neighbours come
+// from the same rows' cache lines.  Loads are unconditional (indices clamped
+// into the mesh, out-of-mesh values scaled to zero) so that they overlap;
+// strips that lie inside the mesh skip the row checks.  Consecutive strips of
+// a column share an XCD (see strip_of).
+template <typename T, int TW, int S, bool HASZ, bool INNER>
+__device__ inline void stencil_strip_body(int n, int strip, int col, const T* __restrict__ X, long ldx,
+                                          T* __restrict__ Y, long ldy, const T* __restrict__ Z, long ldz,
+                                          const double* __restrict__ W, int wstride) {
+  const int i = threadIdx.x;
+  const int j0 = strip * S;
+  const double* w = W + (long)wstride * col;
+  const T wc = (T)w[0], we = (T)w[1], wk = (T)w[2], zc = (T)w[3];
+  const T* x = X + (long)col * ldx;
+  T* y = Y + (long)col * ldy;
+  const unsigned ic = i < n ? i : n - 1, il = i > 0 ? (i < n ? i - 1 : n - 1) : 0, ir = i + 1 < n ? i + 1 : n - 1;
+  const T kl = i > 0 ? T(1) : T(0), kr = i + 1 < n ? T(1) : T(0);
+  auto row = [&](int j, T& l, T& m, T& r) {
+    const int jc = INNER ? j : (j < 0 ? 0 : (j >= n ? n - 1 : j));
+    const T* p = x + (unsigned)(jc * n);
+    const T kj = (INNER || (j >= 0 && j < n)) ? T(1) : T(0);
+    m = p[ic] * kj;
+    l = p[il] * (kl * kj);
+    r = p[ir] * (kr * kj);
+  };
+  T zv[S];
+  if (HASZ) {
+    const T* z = Z + (long)col * ldz;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int j = j0 + s;
+      const int jc = INNER ? j : (j >= n ? n - 1 : j);
+      zv[s] = (z + (unsigned)(jc * n))[ic];
+    }
+  }
+  T l0, m0, r0, l1, m1, r1, l2, m2, r2;
+  row(j0 - 1, l0, m0, r0);
+  row(j0, l1, m1, r1);
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int j = j0 + s;
+    row(j + 1, l2, m2, r2);
+    T v = wc * m1 + we * ((l1 + r1) + (m0 + m2)) + wk * ((l0 + r0) + (l2 + r2));
+    if (HASZ) v += zc * zv[s];
+    if (i < n && (INNER || j < n)) (y + (unsigned)(j * n))[(unsigned)i] = v;
+    l0 = l1; m0 = m1; r0 = r1;
+    l1 = l2; m1 = m2; r1 = r2;
+  }
+}
+
+template <typename T, int TW, int S, bool HASZ>
+__global__ __launch_bounds__(TW) void k_stencil_strip(int n, int nstrip, const T* __restrict__ X, long ldx,
+                                                      T* __restrict__ Y, long ldy, const T* __restrict__ Z,
+                                                      long ldz, const double* __restrict__ W, int wstride) {
+  int strip, col;
+  strip_of(nstrip, strip, col);
+  const int j0 = strip * S;
+  if (j0 >= 1 && j0 + S + 1 <= n)
+    stencil_strip_body<T, TW, S, HASZ, true>(n, strip, col, X, ldx, Y, ldy, Z, ldz, W, wstride);
+  else
+    stencil_strip_body<T, TW, S, HASZ, false>(n, strip, col, X, ldx, Y, ldy, Z, ldz, W, wstride);
+}
+
+template <typename T, int TW, int S>
+static void launch_stencil_strip(hipStream_t st, int n, int ncols, const T* X, long ldx, T* Y, long ldy, const T* Z,
+                                 long ldz, const double* W, int wstride) {
+  const int nstrip = (n + S - 1) / S;
+  if (Z)
+    hipLaunchKernelGGL((k_stencil_strip<T, TW, S, true>), dim3(nstrip * ncols), dim3(TW), 0, st, n, nstrip, X, ldx,
+                       Y, ldy, Z, ldz, W, wstride);
+  else
+    hipLaunchKernelGGL((k_stencil_strip<T, TW, S, false>), dim3(nstrip * ncols), dim3(TW), 0, st, n, nstrip, X,
+                       ldx, Y, ldy, Z, ldz, W, wstride);
+}
+
+template <typename T, int TW>
+static void stencil_strips(hipStream_t st, int n, int ncols, const T* X, long ldx, T* Y, long ldy, const T* Z,
+                           long ldz, const double* W, int wstride) {
+  // tall strips (less halo re-reading) when there are enough columns to
+  // give the chip a few thousand workgroups, short ones otherwise
+  const long want = 2048;
+  if ((long)((n + 31) / 32) * ncols >= want)
+    launch_stencil_strip<T, TW, 32>(st, n, ncols, X, ldx, Y, ldy, Z, ldz, W, wstride);
+  else if ((long)((n + 15) / 16) * ncols >= want)
+    launch_stencil_strip<T, TW, 16>(st, n, ncols, X, ldx, Y, ldy, Z, ldz, W, wstride);
+  else
+    launch_stencil_strip<T, TW, 8>(st, n, ncols, X, ldx, Y, ldy, Z, ldz, W, wstride);
+}
+
 template <typename T>
 void stencil(hipStream_t st, int n, int ncols, const T* X, long ldx, T* Y, long ldy, const T* Z, long ldz,
              const double* W, int wstride) {
   if (ncols <= 0 || n <= 0) return;
+  if (n <= 64) return stencil_strips<T, 64>(st, n, ncols, X, ldx, Y, ldy, Z, ldz, W, wstride);
+  if (n <= 128) return stencil_strips<T, 128>(st, n, ncols, X, ldx, Y, ldy, Z, ldz, W, wstride);
+  if (n <= 256) return stencil_strips<T, 256>(st, n, ncols, X, ldx, Y, ldy, Z, ldz, W, wstride);
+  if (n <= 512) return stencil_strips<T, 512>(st, n, ncols, X, ldx, Y, ldy, Z, ldz, W, wstride);
+  if (n <= 1024) return stencil_strips<T, 1024>(st, n, ncols, X, ldx, Y, ldy, Z, ldz, W, wstride);
   constexpr int S = 8;
   dim3 blk(64, 4);
   dim3 grd((n + 63) / 64, (n + 4 * S - 1) / (4 * S), ncols);
@@ -282,13 +391,6 @@ template void mg_prolong_add<float>(hipStream_t, int, int, const float*, long, c
 // XCD (hardware dispatch goes round robin over the 8 XCDs), keeping the halo
 // rows that neighbouring strips both read in one L2.
 // ---------------------------------------------------------------------------
-__device__ inline void strip_of(int nstrip, int& strip, int& col) {
-  const int w = blockIdx.x, g = gridDim.x;
-  const int full = g & ~7;
-  const int lw = w < full ? (w & 7) * (full >> 3) + (w >> 3) : w;
-  strip = lw % nstrip;
-  col = lw / nstrip;
-}
 
 // One smoother step on rows [lo, hi] of the register column:
 //   out = cur + al (cur - prv) + be (b - A cur),
@@ -332,6 +434,7 @@ __device__ inline void strip_step(const T (&cur)[R], const T (&prv)[R], T (&out)
 template <typename T, int R, bool INNER, bool LANES>
 __device__ inline void load_rows(const T* __restrict__ a, int n, int i, int jb, T (&v)[R], int r0 = 0,
                                  int r1 = R) {
+#pragma clang fp contract(off)
   const unsigned ic = i < n ? i : n - 1;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -339,7 +442,14 @@ __device__ inline void load_rows(const T* __restrict__ a, int n, int i, int jb, 
     const int j = jb + r;
     const int jc = INNER ? j : (j < 0 ? 0 : (j >= n ? n - 1 : j));
     const T x = (a + (unsigned)(jc * n))[ic];
-    v[r] = ((!LANES || i < n) && (INNER || (j >= 0 && j < n))) ? x : T(0);
+    if (!LANES && INNER) {
+      v[r] = x;
+    } else {
+      // scaled by 1 or 0 rather than selected: a select of a loaded value is
+      // compiled into a branch around the load, which serializes the loads
+      const bool keep = (!LANES || i < n) && (INNER || (j >= 0 && j < n));
+      v[r] = x * (keep ? T(1) : T(0));
+    }
   }
 }
 
@@ -460,8 +570,8 @@ __device__ inline void mg_up_body(T* xs, int n, int col, int strip, const T* __r
     const int Jc = J < 0 ? 0 : (J >= nc ? nc - 1 : J);
     const T* er = e + (unsigned)(Jc * nc);  // uniform row base
     const T va = er[cac], vb = er[cbc];
-    ea[q] = (okj && oka) ? va : T(0);
-    eb[q] = (okj && okb) ? vb : T(0);
+    ea[q] = va * ((okj && oka) ? T(1) : T(0));  // scaled, not selected (see load_rows)
+    eb[q] = vb * ((okj && okb) ? T(1) : T(0));
   }
   T bv[R], x0[R], x1[R];
   load_rows<T, R, INNER, true>(Xi + (long)col * ld, n, i, jb, x0);
@@ -807,18 +917,33 @@ __global__ __launch_bounds__(256 * MG) void k_gram_mfma(long nrows, long rows_pe
   // every group runs the same number of stages (barriers are workgroup-wide)
   const long nst = (r1 > r0) ? (r1 - r0 + MK - 1) / MK : 0;
   const long nst_g = (nst + MG - 1) / MG;
-  for (long it = 0; it < nst_g; ++it) {
-    const long rb = r0 + (it * MG + grp) * MK;
-    const long r = rb + lr;
+  // The next stage is fetched into registers while the matrix cores work on
+  // the current one.  Loads are unconditional (row and column indices clamped
+  // into range) so that all of a stage's loads are in flight together;
+  // out-of-range values are zeroed after.
+  double ra[MT / 8], rb[MT / 8];
+  auto fetch = [&](long it) {
+    const long r = r0 + (it * MG + grp) * MK + lr;
     const bool rin = r < r1;
+    const long rc = rin ? r : r1 - 1;
 #pragma unroll
     for (int u = 0; u < MT / 8; ++u) {
-      const int c = lc + 8 * u;
-      const int ca = tm * MT + c, cb = tq * MT + c;
-      as[c][lr] = (rin && ca < m) ? A[(long)ca * lda + r] : 0.0;
-      bs[c][lr] = (rin && cb < q) ? B[(long)cb * ldb + r] : 0.0;
+      const int ca = tm * MT + lc + 8 * u, cb = tq * MT + lc + 8 * u;
+      const double va = A[(long)(ca < m ? ca : m - 1) * lda + rc];
+      const double vb = B[(long)(cb < q ? cb : q - 1) * ldb + rc];
+      ra[u] = (rin && ca < m) ? va : 0.0;
+      rb[u] = (rin && cb < q) ? vb : 0.0;
+    }
+  };
+  if (nst_g > 0) fetch(0);
+  for (long it = 0; it < nst_g; ++it) {
+#pragma unroll
+    for (int u = 0; u < MT / 8; ++u) {
+      as[lc + 8 * u][lr] = ra[u];
+      bs[lc + 8 * u][lr] = rb[u];
     }
     __syncthreads();
+    if (it + 1 < nst_g) fetch(it + 1);
     const int ci = lane & 15, ck = lane >> 4;
 #pragma unroll
     for (int kk = 0; kk < MK; kk += 4) {
@@ -977,18 +1102,35 @@ __global__ __launch_bounds__(256) void k_proj_mfma(long nrows, int m, const doub
   const int ar = tid & 63, ak = tid >> 6;  // A loader: row ar, k = ak + 4u
   const int qk = tid & 31, qc = tid >> 5;  // Q loader: k = qk, column qc + 8u
   const long grow = row0 + ar;
-  for (int k0 = 0; k0 < m; k0 += PK) {
+  const long growc = grow < nrows ? grow : nrows - 1;
+  // The next k-stage is fetched into registers while the matrix cores work on
+  // the current one; loads are unconditional (indices clamped into range,
+  // out-of-range values zeroed after) so that a stage's loads overlap.
+  double ra[PK / 4], rq[PC / 8];
+  auto fetch = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < PK / 4; ++u) {
-      const int k = ak + 4 * u;
-      As[k][ar] = (k0 + k < m && grow < nrows) ? A[(long)(k0 + k) * lda + grow] : 0.0;
+      const int k = k0 + ak + 4 * u;
+      const double v = A[(long)(k < m ? k : m - 1) * lda + growc];
+      ra[u] = v * ((k < m && grow < nrows) ? 1.0 : 0.0);  // a select here becomes a branch per load
     }
+    const int kq = k0 + qk;
+    const int kqc = kq < m ? kq : m - 1;
 #pragma unroll
     for (int u = 0; u < PC / 8; ++u) {
-      const int c = qc + 8 * u;
-      Qs[qk][c] = (k0 + qk < m && col0 + c < p) ? Q[(long)(col0 + c) * ldq + k0 + qk] : 0.0;
+      const int c = col0 + qc + 8 * u;
+      const double v = Q[(long)(c < p ? c : p - 1) * ldq + kqc];
+      rq[u] = v * ((kq < m && c < p) ? 1.0 : 0.0);
     }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < m; k0 += PK) {
+#pragma unroll
+    for (int u = 0; u < PK / 4; ++u) As[ak + 4 * u][ar] = ra[u];
+#pragma unroll
+    for (int u = 0; u < PC / 8; ++u) Qs[qk][qc + 8 * u] = rq[u];
     __syncthreads();
+    if (k0 + PK < m) fetch(k0 + PK);
     const int ci = lane & 15, ck = lane >> 4;
 #pragma unroll
     for (int kk = 0; kk < PK; kk += 4) {
@@ -1001,6 +1143,21 @@ __global__ __launch_bounds__(256) void k_proj_mfma(long nrows, int m, const doub
     }
     __syncthreads();
   }
+  // beta != 0: every old value of C is read (from clamped addresses) before
+  // any store, so that the reads are in flight together
+  double old[2][2][4];
+  if (beta != 0.0) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = col0 + wc * 32 + 16 * a + (lane >> 4) + 4 * v;
+          const long r = row0 + wr * 32 + 16 * b + (lane & 15);
+          old[a][b][v] = C[(long)(j < p ? j : p - 1) * ldc + (r < nrows ? r : nrows - 1)];
+        }
+  }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -1009,10 +1166,8 @@ __global__ __launch_bounds__(256) void k_proj_mfma(long nrows, int m, const doub
       for (int v = 0; v < 4; ++v) {
         const int j = col0 + wc * 32 + 16 * a + (lane >> 4) + 4 * v;
         const long r = row0 + wr * 32 + 16 * b + (lane & 15);
-        if (j < p && r < nrows) {
-          double* dst = C + (long)j * ldc + r;
-          *dst = beta == 0.0 ? acc[a][b][v] : beta * (*dst) + acc[a][b][v];
-        }
+        if (j < p && r < nrows)
+          C[(long)j * ldc + r] = beta == 0.0 ? acc[a][b][v] : beta * old[a][b][v] + acc[a][b][v];
       }
 }
 

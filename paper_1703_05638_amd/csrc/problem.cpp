@@ -134,8 +134,8 @@ Problem::Problem(const lrpost_problem_desc& d) : desc(d) {
     }
   if (nobs == 0) fail(LRPOST_EINVAL, "observation box holds no mesh node");
   mask.ensure(nx);
-  LRP_HIP(hipMemcpyAsync(mask.p, mask_h.data(), nx, hipMemcpyHostToDevice, st));
-  LRP_HIP(hipStreamSynchronize(st));
+  to_device_bytes(mask.p, mask_h.data(), nx);
+  sync();
   // prior variance diag(P^{-1}) from the sine eigenpairs of K and M:
   // (K+M)^{-1} = sum_p phi_p phi_p^T / (kappa_p + mu_p), phi_p = s_i (x) s_j,
   // s_j(ii) = sqrt(2h) sin(ii j pi h), kappa = k_i m_j + m_i k_j, mu = m_i m_j.
@@ -165,8 +165,8 @@ Problem::Problem(const lrpost_problem_desc& d) : desc(d) {
       for (int ii = 0; ii < n; ++ii) dprior_h[(size_t)jj * n + ii] = s * D[(size_t)jj * n + ii];
   }
   dprior.ensure(sizeof(double) * nx);
-  LRP_HIP(hipMemcpyAsync(dprior.p, dprior_h.data(), sizeof(double) * nx, hipMemcpyHostToDevice, st));
-  LRP_HIP(hipStreamSynchronize(st));
+  to_device(dprior.as<double>(), dprior_h.data(), nx);
+  sync();
   // inner-solver settings from the truncation tolerance: poles of the spatial
   // rational Krylov basis log-spaced over the time-step scaled spectrum, and
   // enough V-cycles to resolve it.  For tolerances down to 1e-7 the poles
@@ -181,7 +181,15 @@ Problem::Problem(const lrpost_problem_desc& d) : desc(d) {
   st_cycles = std::max(3, (int)std::ceil((lt + 2.0) / 1.25));
   prior_cycles = std::max(4, (int)std::ceil((lt + 3.0) / 1.25));
   const double lam_min = 2.0 * M_PI * M_PI;
-  const double lam_max = 24.0 / (h * h);
+  const double lam_max = 24.0 / (h * h);  // bound of the element (K, M) eigenvalues, 2 x 12 / h^2
+  // Newton-Schulz inverse of the projected I + tau K (space-time finish):
+  // spectrum bound (with a margin for the rounding of the basis) and the
+  // number of steps that takes the error factor below 1e-18
+  ns_bound_ = 1.0 + 1.05 * tau * lam_max;
+  {
+    const double rho = (ns_bound_ - 1.0) / (ns_bound_ + 1.0);
+    ns_iters_ = std::max(1, (int)std::ceil(std::log2(std::log(1e-18) / std::log(rho))) + 1);
+  }
   const double plo = std::min(1e-2, 0.5 * tau * lam_min);
   const double phi = std::max(10.0 * plo, std::min(tau * lam_max, 1e4));
   if (lt <= 7.0) {
@@ -207,6 +215,7 @@ Problem::~Problem() {
       (void)hipEventDestroy(ev.second);
     }
   if (staging_) (void)hipHostFree(staging_);
+  if (readback_) (void)hipHostFree(readback_);
 }
 
 void Problem::sync() {
@@ -216,27 +225,63 @@ void Problem::sync() {
 
 // Host-to-device copies go through a pinned staging arena so that the host
 // source may be reused at once; the arena is recycled at every stream sync.
-void Problem::to_device(double* dst, const double* src, size_t count) {
-  const size_t bytes = sizeof(double) * count;
+void Problem::to_device_bytes(void* dst, const void* src, size_t bytes) {
   if (bytes == 0) return;
-  if (bytes > kStagingBytes) {
-    LRP_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+  if (!staging_) LRP_HIP(hipHostMalloc(&staging_, kStagingBytes, hipHostMallocDefault));
+  const char* s = static_cast<const char*>(src);
+  char* d = static_cast<char*>(dst);
+  while (bytes > 0) {
+    const size_t chunk = std::min(bytes, kStagingBytes);
+    if (staging_used_ + chunk > kStagingBytes) sync();
+    char* slot = static_cast<char*>(staging_) + staging_used_;
+    std::memcpy(slot, s, chunk);
+    staging_used_ += (chunk + 255) & ~size_t(255);
+    LRP_HIP(hipMemcpyAsync(d, slot, chunk, hipMemcpyHostToDevice, st));
+    s += chunk;
+    d += chunk;
+    bytes -= chunk;
+  }
+}
+
+void Problem::to_device(double* dst, const double* src, size_t count) {
+  to_device_bytes(dst, src, sizeof(double) * count);
+}
+
+void Problem::to_host_bytes(void* dst, const void* src, size_t bytes) {
+  if (bytes > 0 && !readback_) LRP_HIP(hipHostMalloc(&readback_, kReadbackBytes, hipHostMallocDefault));
+  const char* s = static_cast<const char*>(src);
+  char* d = static_cast<char*>(dst);
+  while (bytes > 0) {
+    const size_t chunk = std::min(bytes, kReadbackBytes);
+    LRP_HIP(hipMemcpyAsync(readback_, s, chunk, hipMemcpyDeviceToHost, st));
+    sync();
+    std::memcpy(d, readback_, chunk);
+    s += chunk;
+    d += chunk;
+    bytes -= chunk;
+  }
+  sync();
+}
+
+void Problem::to_host_block(double* dst, const double* src, int rows, int cols, long ld) {
+  if (rows <= 0 || cols <= 0) {
     sync();
     return;
   }
-  if (!staging_) {
-    LRP_HIP(hipHostMalloc(&staging_, kStagingBytes, hipHostMallocDefault));
+  if (ld == rows) return to_host(dst, src, (size_t)rows * cols);
+  if (!readback_) LRP_HIP(hipHostMalloc(&readback_, kReadbackBytes, hipHostMallocDefault));
+  const int per = (int)std::max<size_t>(1, kReadbackBytes / (sizeof(double) * rows));
+  for (int c0 = 0; c0 < cols; c0 += per) {
+    const int nc = std::min(per, cols - c0);
+    LRP_HIP(hipMemcpy2DAsync(readback_, sizeof(double) * rows, src + (size_t)c0 * ld, sizeof(double) * ld,
+                             sizeof(double) * rows, nc, hipMemcpyDeviceToHost, st));
+    sync();
+    std::memcpy(dst + (size_t)c0 * rows, readback_, sizeof(double) * rows * nc);
   }
-  if (staging_used_ + bytes > kStagingBytes) sync();
-  char* slot = static_cast<char*>(staging_) + staging_used_;
-  std::memcpy(slot, src, bytes);
-  staging_used_ += (bytes + 255) & ~size_t(255);
-  LRP_HIP(hipMemcpyAsync(dst, slot, bytes, hipMemcpyHostToDevice, st));
 }
 
 void Problem::to_host(double* dst, const double* src, size_t count) {
-  LRP_HIP(hipMemcpyAsync(dst, src, sizeof(double) * count, hipMemcpyDeviceToHost, st));
-  sync();
+  to_host_bytes(dst, src, sizeof(double) * count);
 }
 
 
@@ -593,9 +638,8 @@ void Problem::sym_eig(int nn, const double* A, int lda, std::vector<double>& w, 
   double* dw = dA + (size_t)nn * nn;
   to_device(dA, tmp.data(), tmp.size());
   dense->syevd(nn, dA, nn, dw, eig_work_);
-  LRP_HIP(hipMemcpyAsync(V.data(), dA, sizeof(double) * (size_t)nn * nn, hipMemcpyDeviceToHost, st));
-  LRP_HIP(hipMemcpyAsync(w.data(), dw, sizeof(double) * nn, hipMemcpyDeviceToHost, st));
-  sync();
+  to_host(V.data(), dA, (size_t)nn * nn);
+  to_host(w.data(), dw, nn);
 }
 
 void Problem::small_svd(int m, int nn, const double* A, int lda, bool accurate, std::vector<double>& s,
@@ -846,12 +890,33 @@ void Problem::st_finish(const StPrep& pr, double* Wall, LowRank& Y, bool adjoint
   double* P2 = P1 + (size_t)q * q;
   double* Gsm = P2 + (size_t)q * q;         // Gram for the truncation (max(q, nt)^2)
   double* Gt = Gsm + (size_t)gmax * gmax;   // max(q, nt) eigenvalues
-  LRP_HIP(hipMemcpy2DAsync(Ainv, sizeof(double) * q, Kt, sizeof(double) * qmax, sizeof(double) * q, q,
-                           hipMemcpyDeviceToDevice, st));
-  add_diag(st, q, Ainv, q, 1.0);
-  if (!dense->spd_inverse_upper(q, Ainv, q, eig_work_))
-    fail(LRPOST_EBREAKDOWN, "projected I + tau K is not positive definite");
-  symmetrize_upper(st, q, Ainv, q);
+  // A = (I + Kt)^{-1} by the Newton-Schulz iteration X <- 2X - X (I + Kt) X
+  // from X_0 = 2 / (1 + L) I: with Q M-orthonormal the eigenvalues of
+  // I + Kt lie in [1, L], L = 1 + tau lambda_max(M^{-1} K), so the error
+  // I - (I + Kt) X_j has spectral radius ((L - 1) / (L + 1))^(2^j) and the
+  // iteration count follows from L alone.  Only matrix products are used,
+  // which round identically on every run (a library Cholesky inverse did
+  // not when other work shared the device).
+  {
+    double* Apd = P1;  // I + Kt, full symmetric
+    double* T = P2;
+    double* Xa = Ainv;
+    double* Xn = Gsm;  // gmax^2 >= q^2
+    LRP_HIP(hipMemcpy2DAsync(Apd, sizeof(double) * q, Kt, sizeof(double) * qmax, sizeof(double) * q, q,
+                             hipMemcpyDeviceToDevice, st));
+    add_diag(st, q, Apd, q, 1.0);
+    symmetrize_upper(st, q, Apd, q);
+    LRP_HIP(hipMemsetAsync(Xa, 0, sizeof(double) * (size_t)q * q, st));
+    add_diag(st, q, Xa, q, 2.0 / (1.0 + ns_bound_));
+    for (int it = 0; it < ns_iters_; ++it) {
+      dense->gemm(false, false, q, q, q, 1.0, Apd, q, Xa, q, 0.0, T, q);  // T = (I + Kt) X
+      LRP_HIP(hipMemcpyAsync(Xn, Xa, sizeof(double) * (size_t)q * q, hipMemcpyDeviceToDevice, st));
+      dense->gemm(false, false, q, q, q, -1.0, Xa, q, T, q, 2.0, Xn, q);  // Xn = 2X - X T
+      std::swap(Xa, Xn);
+    }
+    if (Xa != Ainv)
+      LRP_HIP(hipMemcpyAsync(Ainv, Xa, sizeof(double) * (size_t)q * q, hipMemcpyDeviceToDevice, st));
+  }
   gram_dev(q, Q, r1, Fb, S);
   to_device(F2d, F2p.data(), (size_t)nt * r1);
   dense->gemm(false, true, q, nt, r1, 1.0, S, q, F2d, nt, 0.0, X2, q);        // G = S F2p^T
@@ -915,13 +980,13 @@ void Problem::st_finish(const StPrep& pr, double* Wall, LowRank& Y, bool adjoint
         double* Cm = Z;  // q x ry
         dense->gemm(false, false, q, ry, nt, 1.0, Zp, q, Ek, nt, 0.0, Cm, q);
         proj_dev(q, Q, Cm, q, ry, Y.a(), 0.0);
-        LRP_HIP(hipMemcpyAsync(B2.data(), Ek, sizeof(double) * (size_t)nt * ry, hipMemcpyDeviceToHost, st));
+        to_host(B2.data(), Ek, (size_t)nt * ry);
       } else {
         // Y = Q U_r (Zp^T U_r)^T
         double* Vt = Z;  // nt x ry
         dense->gemm(true, false, nt, ry, q, 1.0, Zp, q, Ek, q, 0.0, Vt, nt);
         proj_dev(q, Q, Ek, q, ry, Y.a(), 0.0);
-        LRP_HIP(hipMemcpyAsync(B2.data(), Vt, sizeof(double) * (size_t)nt * ry, hipMemcpyDeviceToHost, st));
+        to_host(B2.data(), Vt, (size_t)nt * ry);
       }
       sync();
       for (int c = 0; c < ry; ++c)

@@ -63,7 +63,7 @@ def stats(d, regex):
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     pat = re.compile(regex)
     print("%-60s %10s %14s %12s %7s" % ("kernel", "calls", "total_ms", "avg_us", "pct"))
-    for r in rows[:15]:
+    for r in rows[:25]:
         print("%-60s %10s %14.3f %12.3f %7.2f" % (r["Name"][:60], r["Calls"], float(r["TotalDurationNs"]) / 1e6,
                                                   float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
     for r in rows:
