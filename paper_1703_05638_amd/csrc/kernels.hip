@@ -857,12 +857,37 @@ __global__ __launch_bounds__(256) void k_gram_partial(long nrows, long rows_per_
     }
 }
 
-__global__ void k_sum_partials(int nchunk, long count, const double* __restrict__ part, double* __restrict__ C) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= count) return;
+// C[idx] = sum over chunks of part[chunk][idx].  A workgroup takes 64
+// consecutive outputs (coalesced reads) and spreads the chunks over 16 lanes
+// (chunk c to lane c % 16, each lane's loads independent of one another);
+// the 16 lane sums are combined through LDS in a fixed order, so the result
+// does not depend on scheduling.
+constexpr int SP_X = 64, SP_Y = 16;
+__global__ __launch_bounds__(SP_X * SP_Y) void k_sum_partials(int nchunk, long count, const double* __restrict__ part,
+                                                             double* __restrict__ C) {
+  __shared__ double red[SP_Y][SP_X + 1];
+  const int tx = threadIdx.x % SP_X, ty = threadIdx.x / SP_X;
+  const long idx = (long)blockIdx.x * SP_X + tx;
+  const long idc = idx < count ? idx : count - 1;
   double s = 0.0;
-  for (int c = 0; c < nchunk; ++c) s += part[(long)c * count + idx];
-  C[idx] = s;
+  int c = ty;
+  for (; c + 3 * SP_Y < nchunk; c += 4 * SP_Y) {
+    const double a0 = part[(long)c * count + idc], a1 = part[(long)(c + SP_Y) * count + idc];
+    const double a2 = part[(long)(c + 2 * SP_Y) * count + idc], a3 = part[(long)(c + 3 * SP_Y) * count + idc];
+    s += a0;
+    s += a1;
+    s += a2;
+    s += a3;
+  }
+  for (; c < nchunk; c += SP_Y) s += part[(long)c * count + idc];
+  red[ty][tx] = s;
+  __syncthreads();
+  if (ty == 0 && idx < count) {
+    double t = red[0][tx];
+#pragma unroll
+    for (int y = 1; y < SP_Y; ++y) t += red[y][tx];
+    C[idx] = t;
+  }
 }
 
 int gram_chunks(long nrows, int m, int q) {
@@ -1003,7 +1028,7 @@ void gram(hipStream_t st, long nrows, int m, const T* A, long lda, int q, const 
   dim3 grd((m + GT - 1) / GT, (q + GT - 1) / GT, nchunk);
   hipLaunchKernelGGL((k_gram_partial<T>), grd, dim3(256), 0, st, nrows, rpc, m, A, lda, q, B, ldb, part);
   const long count = (long)m * q;
-  hipLaunchKernelGGL(k_sum_partials, dim3((count + 255) / 256), dim3(256), 0, st, nchunk, count, part, C);
+  hipLaunchKernelGGL(k_sum_partials, dim3((count + SP_X - 1) / SP_X), dim3(SP_X * SP_Y), 0, st, nchunk, count, part, C);
 }
 template <>
 void gram<double>(hipStream_t st, long nrows, int m, const double* A, long lda, int q, const double* B, long ldb,
@@ -1015,7 +1040,7 @@ void gram<double>(hipStream_t st, long nrows, int m, const double* A, long lda, 
   dim3 grd((m + MT - 1) / MT, (q + MT - 1) / MT, nchunk);
   hipLaunchKernelGGL(k_gram_mfma, grd, dim3(256 * MG), 0, st, nrows, rpc, m, A, lda, q, B, ldb, part);
   const long count = (long)m * q;
-  hipLaunchKernelGGL(k_sum_partials, dim3((count + 255) / 256), dim3(256), 0, st, nchunk, count, part, C);
+  hipLaunchKernelGGL(k_sum_partials, dim3((count + SP_X - 1) / SP_X), dim3(SP_X * SP_Y), 0, st, nchunk, count, part, C);
 }
 template void gram<float>(hipStream_t, long, int, const float*, long, int, const float*, long, double*, double*);
 
