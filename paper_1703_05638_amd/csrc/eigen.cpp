@@ -259,51 +259,68 @@ class SharedBasis {
   // by one-sided Jacobi (relative accuracy of small singular values);
   // otherwise through the eigenpairs of S^T S on the device.
   CVec truncate_core(const double* S, int rows, int lds, double tol, int cap) {
-    CVec out;
-    out.s = rows;
-    if (rows == 0) return out;
+    return std::move(truncate_cores(S, 1, 0, rows, lds, tol, cap)[0]);
+  }
+
+  // The same for `count` cores S + b stride of one shape, with the
+  // eigenproblems of their Gram matrices solved as one batch.
+  std::vector<CVec> truncate_cores(const double* S, int count, long stride, int rows, int lds, double tol, int cap) {
+    std::vector<CVec> outs(count);
+    for (auto& o : outs) o.s = rows;
+    if (rows == 0 || count == 0) return outs;
     std::vector<double> sv;
-    int r = 0;
     double tail = 0.0;
     if (tol < 1e-7) {
-      std::vector<double> Sh((size_t)rows * nt);
-      P->to_host_block(Sh.data(), S, rows, nt, lds);
-      std::vector<double> Us, Vs;
-      svd(rows, nt, Sh.data(), rows, sv, Us, Vs);
-      r = truncation_rank(sv, tol, cap, &tail);
+      for (int b = 0; b < count; ++b) {
+        CVec& out = outs[b];
+        std::vector<double> Sh((size_t)rows * nt);
+        P->to_host_block(Sh.data(), S + b * stride, rows, nt, lds);
+        std::vector<double> Us, Vs;
+        svd(rows, nt, Sh.data(), rows, sv, Us, Vs);
+        const int r = truncation_rank(sv, tol, cap, &tail);
+        out.r = r;
+        out.C.ensure(sizeof(double) * (size_t)rows * std::max(r, 1));
+        out.B.ensure(sizeof(double) * (size_t)nt * std::max(r, 1));
+        if (r > 0) {
+          std::vector<double> Cm((size_t)rows * r);
+          for (int j = 0; j < r; ++j)
+            for (int i = 0; i < rows; ++i) Cm[(size_t)j * rows + i] = Us[(size_t)j * rows + i] * sv[j];
+          P->to_device(out.C.as<double>(), Cm.data(), Cm.size());
+          P->to_device(out.B.as<double>(), Vs.data(), (size_t)nt * r);
+        }
+      }
+      P->sync();
+      return outs;
+    }
+    const size_t gsz = (size_t)nt * nt;
+    work3.ensure(sizeof(double) * (gsz * count + (size_t)nt * count + 64));
+    double* Gt = work3.as<double>();
+    double* w = Gt + gsz * count;
+    if (count == 1)
+      P->dense->gemm(true, false, nt, nt, rows, 1.0, S, lds, S, lds, 0.0, Gt, nt);
+    else
+      P->dense->gemm_strided_batched(true, false, nt, nt, rows, 1.0, S, lds, stride, S, lds, stride, 0.0, Gt, nt,
+                                     (long)gsz, count);
+    P->dense->syevd_batched(nt, Gt, nt, (long)gsz, w, nt, count, wev);
+    std::vector<double> wh((size_t)nt * count);
+    P->to_host(wh.data(), w, wh.size());
+    for (int b = 0; b < count; ++b) {
+      CVec& out = outs[b];
+      sv.assign(nt, 0.0);
+      for (int c = 0; c < nt; ++c) sv[c] = std::sqrt(std::max(wh[(size_t)b * nt + nt - 1 - c], 0.0));
+      const int r = truncation_rank(sv, tol, cap, &tail);
       out.r = r;
       out.C.ensure(sizeof(double) * (size_t)rows * std::max(r, 1));
       out.B.ensure(sizeof(double) * (size_t)nt * std::max(r, 1));
       if (r > 0) {
-        std::vector<double> Cm((size_t)rows * r);
-        for (int j = 0; j < r; ++j)
-          for (int i = 0; i < rows; ++i) Cm[(size_t)j * rows + i] = Us[(size_t)j * rows + i] * sv[j];
-        P->to_device(out.C.as<double>(), Cm.data(), Cm.size());
-        P->to_device(out.B.as<double>(), Vs.data(), (size_t)nt * r);
+        // eigenvectors of the r largest eigenvalues
+        const double* Vr = Gt + gsz * b + (size_t)(nt - r) * nt;
+        P->dense->gemm(false, false, rows, r, nt, 1.0, S + b * stride, lds, Vr, nt, 0.0, out.C.as<double>(), rows);
+        LRP_HIP(hipMemcpyAsync(out.B.p, Vr, sizeof(double) * (size_t)nt * r, hipMemcpyDeviceToDevice, P->st));
       }
-      P->sync();
-      return out;
-    }
-    work3.ensure(sizeof(double) * ((size_t)nt * nt + nt + 64));
-    double* Gt = work3.as<double>();
-    double* w = Gt + (size_t)nt * nt;
-    P->dense->gemm(true, false, nt, nt, rows, 1.0, S, lds, S, lds, 0.0, Gt, nt);
-    P->dense->syevd(nt, Gt, nt, w, wev);
-    std::vector<double> wh(nt);
-    P->to_host(wh.data(), w, nt);
-    sv.assign(nt, 0.0);
-    for (int c = 0; c < nt; ++c) sv[c] = std::sqrt(std::max(wh[nt - 1 - c], 0.0));
-    r = truncation_rank(sv, tol, cap, &tail);
-    out.r = r;
-    out.C.ensure(sizeof(double) * (size_t)rows * std::max(r, 1));
-    out.B.ensure(sizeof(double) * (size_t)nt * std::max(r, 1));
-    if (r > 0) {
-      const double* Vr = Gt + (size_t)(nt - r) * nt;  // eigenvectors of the r largest eigenvalues
-      P->dense->gemm(false, false, rows, r, nt, 1.0, S, lds, Vr, nt, 0.0, out.C.as<double>(), rows);
-      LRP_HIP(hipMemcpyAsync(out.B.p, Vr, sizeof(double) * (size_t)nt * r, hipMemcpyDeviceToDevice, P->st));
     }
     P->sync();
-    return out;
+    return outs;
   }
 
   // Dense core S (s x nt) = sum_t tc[t] C_t B_t^T over temporaries plus
@@ -444,8 +461,10 @@ static std::vector<CVec> orthonormalize_block(SharedBasis& sb, std::vector<CVec>
   std::vector<CVec> out;
   std::vector<const CVec*> tv;
   for (auto& x : W) tv.push_back(&x);
+  // the kout new directions' cores are formed side by side and truncated as one batch
   DevMem Sbuf;
-  Sbuf.ensure(sizeof(double) * (size_t)std::max(sb.s, 1) * sb.nt);
+  const size_t slot = (size_t)std::max(sb.s, 1) * sb.nt;
+  Sbuf.ensure(sizeof(double) * slot * std::max(kout, 1));
   for (int c = 0; c < kout; ++c) {
     const int j = keep[c];
     const double sw = std::sqrt(w[j]);
@@ -454,8 +473,10 @@ static std::vector<CVec> orthonormalize_block(SharedBasis& sb, std::vector<CVec>
       coef[i] = U[(size_t)j * b + i] / sw;
       Rb[(size_t)i * kout + c] = U[(size_t)j * b + i] * sw;
     }
-    sb.combine(tv, coef, {}, Sbuf.as<double>());
-    CVec v = sb.truncate_core(Sbuf.as<double>(), sb.s, sb.s, tol, cap);
+    sb.combine(tv, coef, {}, Sbuf.as<double>() + c * slot);
+  }
+  auto vs = sb.truncate_cores(Sbuf.as<double>(), kout, (long)slot, sb.s, sb.s, tol, cap);
+  for (auto& v : vs) {
     const double nv = std::sqrt(std::max(sb.inner(v, v), 0.0));
     if (nv > 0) P->dense->scal(P->nt * v.r, 1.0 / nv, v.B.as<double>());
     out.push_back(std::move(v));
@@ -522,16 +543,23 @@ EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rt
     for (int i = 0; i < bj; ++i) Wn.push_back(sb.absorb(outs[i], tol, cap, false));
     outs.clear();
     // full re-orthogonalization, classical Gram-Schmidt twice, on the cores
+    // (the second pass forms the block's cores side by side and truncates
+    // them as one batch)
+    const size_t slot = (size_t)std::max(sb.s, 1) * nt;
     for (int pass = 0; pass < 2; ++pass) {
+      Sbuf.ensure(sizeof(double) * slot * (pass == 0 ? 1 : bj));
       for (int i = 0; i < bj; ++i) {
         std::vector<double> c = sb.inner_all(Wn[i]);
         const int m = sb.size();
         for (int kk = 0; kk < m; ++kk) T[(size_t)(j0 + i) * mmax + kk] += c[kk];
         for (double& x : c) x = -x;
-        Sbuf.ensure(sizeof(double) * (size_t)sb.s * nt);
-        sb.combine({&Wn[i]}, {1.0}, c, Sbuf.as<double>());
-        Wn[i] = pass == 0 ? sb.dense_core(Sbuf.as<double>(), sb.s)
-                          : sb.truncate_core(Sbuf.as<double>(), sb.s, sb.s, tol * 1e-1, cap);
+        double* Si = Sbuf.as<double>() + (pass == 0 ? 0 : i * slot);
+        sb.combine({&Wn[i]}, {1.0}, c, Si);
+        if (pass == 0) Wn[i] = sb.dense_core(Si, sb.s);
+      }
+      if (pass == 1) {
+        auto vs = sb.truncate_cores(Sbuf.as<double>(), bj, (long)slot, sb.s, sb.s, tol * 1e-1, cap);
+        for (int i = 0; i < bj; ++i) Wn[i] = std::move(vs[i]);
       }
     }
     const int m = sb.size();
@@ -613,19 +641,27 @@ EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rt
   // Ritz vectors of the k largest Ritz values
   const int m = m_conv;
   const int kk = std::min(k, m);
-  Sbuf.ensure(sizeof(double) * (size_t)sb.s * nt);
-  for (int s = 0; s < kk; ++s) {
-    const int col = m - 1 - s;
-    res.lambda.push_back(theta[col]);
-    std::vector<double> coef(sb.size(), 0.0);
-    for (int i = 0; i < m; ++i) coef[i] = Y[(size_t)col * m + i];
-    sb.combine({}, {}, coef, Sbuf.as<double>());
-    CVec v = sb.truncate_core(Sbuf.as<double>(), sb.s, sb.s, tol, cap);
-    const double nv = std::sqrt(std::max(sb.inner(v, v), 0.0));
-    if (nv > 0) P->dense->scal(nt * v.r, 1.0 / nv, v.B.as<double>());
-    auto out = std::make_unique<LowRank>();
-    sb.materialize(v, *out);
-    res.vecs.push_back(std::move(out));
+  // (formed kRitzBatch at a time and truncated as one batch)
+  constexpr int kRitzBatch = 8;
+  const size_t slot = (size_t)std::max(sb.s, 1) * nt;
+  Sbuf.ensure(sizeof(double) * slot * kRitzBatch);
+  for (int s0 = 0; s0 < kk; s0 += kRitzBatch) {
+    const int nb = std::min(kRitzBatch, kk - s0);
+    for (int s = s0; s < s0 + nb; ++s) {
+      const int col = m - 1 - s;
+      res.lambda.push_back(theta[col]);
+      std::vector<double> coef(sb.size(), 0.0);
+      for (int i = 0; i < m; ++i) coef[i] = Y[(size_t)col * m + i];
+      sb.combine({}, {}, coef, Sbuf.as<double>() + (s - s0) * slot);
+    }
+    auto vs = sb.truncate_cores(Sbuf.as<double>(), nb, (long)slot, sb.s, sb.s, tol, cap);
+    for (auto& v : vs) {
+      const double nv = std::sqrt(std::max(sb.inner(v, v), 0.0));
+      if (nv > 0) P->dense->scal(nt * v.r, 1.0 / nv, v.B.as<double>());
+      auto out = std::make_unique<LowRank>();
+      sb.materialize(v, *out);
+      res.vecs.push_back(std::move(out));
+    }
   }
   return res;
 }
@@ -688,14 +724,21 @@ EigResult randomized_eig(Problem* P, int k, const std::vector<const LowRank*>& p
     if (mu[l - 1] > 0 && mu[c] > 1e-14 * mu[l - 1]) keep.push_back(c);
   const int m = (int)keep.size();
   if (m == 0) fail(LRPOST_EBREAKDOWN, "the probes' images are zero");
+  // orthonormal basis vectors, kBatch cores at a time truncated as one batch
   DevMem Sbuf;
+  const size_t slot = (size_t)std::max(sb.s, 1) * nt;
+  Sbuf.ensure(sizeof(double) * slot * kBatch);
   std::vector<CVec> Q;
-  for (int c : keep) {
-    std::vector<double> coef(sb.size(), 0.0);
-    for (int j = 0; j < l; ++j) coef[j] = U[(size_t)c * l + j] / std::sqrt(mu[c]);
-    Sbuf.ensure(sizeof(double) * (size_t)sb.s * nt);
-    sb.combine({}, {}, coef, Sbuf.as<double>());
-    Q.push_back(sb.truncate_core(Sbuf.as<double>(), sb.s, sb.s, tol, cap));
+  for (int c0 = 0; c0 < m; c0 += kBatch) {
+    const int nb = std::min(kBatch, m - c0);
+    for (int q = 0; q < nb; ++q) {
+      const int c = keep[c0 + q];
+      std::vector<double> coef(sb.size(), 0.0);
+      for (int j = 0; j < l; ++j) coef[j] = U[(size_t)c * l + j] / std::sqrt(mu[c]);
+      sb.combine({}, {}, coef, Sbuf.as<double>() + q * slot);
+    }
+    auto vs = sb.truncate_cores(Sbuf.as<double>(), nb, (long)slot, sb.s, sb.s, tol, cap);
+    for (auto& v : vs) Q.push_back(std::move(v));
   }
   // pass two
   std::vector<CVec> W;
@@ -753,31 +796,39 @@ EigResult randomized_eig(Problem* P, int k, const std::vector<const LowRank*>& p
   EigResult res;
   res.steps = 2;
   double worst = 0.0;
-  for (int i = 0; i < kk; ++i) {
-    const int col = mq - 1 - i;
-    const double th = theta[col];
-    // coefficients on Q: c = B V[:, col]
-    std::vector<double> c(m, 0.0);
-    for (int a = 0; a < m; ++a)
-      for (int b = 0; b < mq; ++b) c[a] += Bm[(size_t)b * m + a] * V[(size_t)col * mq + b];
-    // residual ||sum c_a (W_a - theta Q_a)||_P^2 = c^T (GW - theta (T + T^T) + theta^2 MQ) c
-    double r2 = 0.0;
-    for (int b = 0; b < m; ++b)
+  // Ritz vectors, kBatch cores at a time truncated as one batch (the shared
+  // basis may have grown since the buffer was sized)
+  const size_t slot2 = (size_t)std::max(sb.s, 1) * nt;
+  Sbuf.ensure(sizeof(double) * slot2 * kBatch);
+  for (int i0 = 0; i0 < kk; i0 += kBatch) {
+    const int nb = std::min(kBatch, kk - i0);
+    for (int i = i0; i < i0 + nb; ++i) {
+      const int col = mq - 1 - i;
+      const double th = theta[col];
+      // coefficients on Q: c = B V[:, col]
+      std::vector<double> c(m, 0.0);
       for (int a = 0; a < m; ++a)
-        r2 += c[a] * c[b] * (GW[(size_t)b * m + a] - th * (T[(size_t)b * m + a] + T[(size_t)a * m + b]) +
-                             th * th * MQ[(size_t)b * m + a]);
-    worst = std::max(worst, std::sqrt(std::max(r2, 0.0)) / std::max(std::fabs(th), 1e-300));
-    std::vector<double> coef(sb.size(), 0.0);
-    for (int a = 0; a < m; ++a) coef[l + a] = c[a];
-    Sbuf.ensure(sizeof(double) * (size_t)sb.s * nt);
-    sb.combine({}, {}, coef, Sbuf.as<double>());
-    CVec v = sb.truncate_core(Sbuf.as<double>(), sb.s, sb.s, tol, cap);
-    const double nv = std::sqrt(std::max(sb.inner(v, v), 0.0));
-    if (nv > 0) P->dense->scal(nt * v.r, 1.0 / nv, v.B.as<double>());
-    auto out = std::make_unique<LowRank>();
-    sb.materialize(v, *out);
-    res.lambda.push_back(th);
-    res.vecs.push_back(std::move(out));
+        for (int b = 0; b < mq; ++b) c[a] += Bm[(size_t)b * m + a] * V[(size_t)col * mq + b];
+      // residual ||sum c_a (W_a - theta Q_a)||_P^2 = c^T (GW - theta (T + T^T) + theta^2 MQ) c
+      double r2 = 0.0;
+      for (int b = 0; b < m; ++b)
+        for (int a = 0; a < m; ++a)
+          r2 += c[a] * c[b] * (GW[(size_t)b * m + a] - th * (T[(size_t)b * m + a] + T[(size_t)a * m + b]) +
+                               th * th * MQ[(size_t)b * m + a]);
+      worst = std::max(worst, std::sqrt(std::max(r2, 0.0)) / std::max(std::fabs(th), 1e-300));
+      std::vector<double> coef(sb.size(), 0.0);
+      for (int a = 0; a < m; ++a) coef[l + a] = c[a];
+      sb.combine({}, {}, coef, Sbuf.as<double>() + (i - i0) * slot2);
+      res.lambda.push_back(th);
+    }
+    auto vs = sb.truncate_cores(Sbuf.as<double>(), nb, (long)slot2, sb.s, sb.s, tol, cap);
+    for (auto& v : vs) {
+      const double nv = std::sqrt(std::max(sb.inner(v, v), 0.0));
+      if (nv > 0) P->dense->scal(nt * v.r, 1.0 / nv, v.B.as<double>());
+      auto out = std::make_unique<LowRank>();
+      sb.materialize(v, *out);
+      res.vecs.push_back(std::move(out));
+    }
   }
   res.max_resid = worst;
   logline("done", kk);

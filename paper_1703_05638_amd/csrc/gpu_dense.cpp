@@ -198,6 +198,18 @@ void GpuDense::syevd(int n, double* A, int lda, double* w, DevMem& work) {
            "rocsolver_dsyevd");
 }
 
+void GpuDense::syevd_batched(int n, double* A, int lda, long strideA, double* w, long strideW, int batch,
+                             DevMem& work) {
+  if (n <= 0 || batch <= 0) return;
+  if (batch == 1) return syevd(n, A, lda, w, work);
+  work.ensure(sizeof(double) * (size_t)n * batch + sizeof(int) * (size_t)batch + 64);
+  int* info = reinterpret_cast<int*>(work.as<char>() + sizeof(double) * (size_t)n * batch);
+  SolverSection section(st_);
+  rb_check(rocsolver_dsyevd_strided_batched((rocblas_handle)handle, rocblas_evect_original, rocblas_fill_upper, n, A,
+                                            lda, strideA, w, strideW, work.as<double>(), n, info, batch),
+           "rocsolver_dsyevd_strided_batched");
+}
+
 void GpuDense::dgmm_right(int m, int n, const double* A, int lda, const double* x, double* C, int ldc) {
   if (m <= 0 || n <= 0) return;
   BlasSection blas(st_);

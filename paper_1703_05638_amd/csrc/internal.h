@@ -87,6 +87,9 @@ class GpuDense {
                             const double* B, int ldb, long sb, double beta, double* C, int ldc, long sc, int batch);
   // A (n x n, upper triangle) -> eigenvectors in place, eigenvalues ascending in w (all device)
   void syevd(int n, double* A, int lda, double* w, DevMem& work);
+  // the same for `batch` matrices A + b strideA (eigenvalues at w + b strideW);
+  // one batched solve costs about as much as one single solve
+  void syevd_batched(int n, double* A, int lda, long strideA, double* w, long strideW, int batch, DevMem& work);
   // C = A diag(x) (A, C: m x n device; x: n device)
   void dgmm_right(int m, int n, const double* A, int lda, const double* x, double* C, int ldc);
   void scal(int n, double alpha, double* x);
