@@ -223,7 +223,13 @@ class Problem {
   };
   void st_prepare(const LowRank& F, bool adjoint, StPrep& pr);
   double* st_pole_solves(const std::vector<const StPrep*>& prs);
-  void st_finish(const StPrep& pr, double* Wall, LowRank& Y, bool adjoint);
+  // per source: M-orthonormal basis Q (nx x q) and projected solution Zp (q x nt)
+  struct StFin {
+    int q = 0;
+    DevMem Q, Zp;
+  };
+  void st_project(const StPrep& pr, double* Wall, StFin& fin);
+  void st_truncate(std::vector<StFin>& fins, const std::vector<LowRank*>& Y, bool adjoint);
   // G x (precond) or H_mis x (misfit).
   void hess_apply(const LowRank& x, LowRank& y, bool precond);
   // Truncate in place; weight 0: Euclidean, 1: M, 2: K+M.  With ref_norm > 0
@@ -264,7 +270,7 @@ class Problem {
   DevMem mg_work_f_, mg_f_;
   void upload_mg_params(const std::vector<ShiftCoef>& ab);
   // space-time solver workspaces
-  DevMem st_q_, st_w_, st_mw_, st_wall_, st_brep_, st_kt_, st_small_, st_c_, eig_work_;
+  DevMem st_gram_, st_w_, st_mw_, st_wall_, st_brep_, st_kt_, st_small_, st_c_, eig_work_;
 };
 
 void smoother_interval(double a, double bh2, double* lo, double* hi);

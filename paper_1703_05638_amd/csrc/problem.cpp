@@ -772,32 +772,31 @@ void Problem::spacetime_solve_batch(const std::vector<const LowRank*>& F, const 
     pp.push_back(&prs[j]);
   }
   double* Wall = st_pole_solves(pp);
+  std::vector<StFin> fins(nb);
   long off = 0;
   for (int j = 0; j < nb; ++j) {
-    st_finish(prs[j], Wall ? Wall + (size_t)off * nx : nullptr, *Y[j], adjoint);
+    st_project(prs[j], Wall ? Wall + (size_t)off * nx : nullptr, fins[j]);
     off += (long)prs[j].r1 * (long)poles.size();
   }
+  st_truncate(fins, Y, adjoint);
 }
 
-// Basis, projected problem and truncation of one prepared source whose pole
-// solves are in Wall (nx x r1 npol, overwritten).
-void Problem::st_finish(const StPrep& pr, double* Wall, LowRank& Y, bool adjoint) {
-  Y.nx = nx;
-  Y.nt = nt;
+// Basis and projected problem of one prepared source whose pole solves are in
+// Wall (nx x r1 npol, overwritten): fin.Q (nx x q, M-orthonormal) and fin.Zp
+// (q x nt) with the space-time solution Q Zp.
+void Problem::st_project(const StPrep& pr, double* Wall, StFin& fin) {
+  fin.q = 0;
   const int r1 = pr.r1;
-  if (r1 == 0) {
-    Y.resize(nx, nt, 0);
-    return;
-  }
+  if (r1 == 0) return;
   const double* Fb = pr.Fb.as<double>();
   const std::vector<double>& F2p = pr.F2p;
   // 2. block-by-block M-orthonormalization of the pole solutions
   const int npol = (int)poles.size();
   const int qmax = r1 * npol;
-  st_q_.ensure(sizeof(double) * (size_t)nx * qmax);
+  fin.Q.ensure(sizeof(double) * (size_t)nx * qmax);
   st_w_.ensure(sizeof(double) * (size_t)nx * r1);
   st_mw_.ensure(sizeof(double) * (size_t)nx * std::max(r1, 1));
-  double* Q = st_q_.as<double>();
+  double* Q = fin.Q.as<double>();
   double* W2 = st_w_.as<double>();
   double* MW = st_mw_.as<double>();
   int q = 0;
@@ -867,14 +866,11 @@ void Problem::st_finish(const StPrep& pr, double* Wall, LowRank& Y, bool adjoint
     q += kcols;
   }
   stats.last_basis = q;
-  if (q == 0) {
-    Y.resize(nx, nt, 0);
-    return;
-  }
+  if (q == 0) return;
   // 3. projected problem on the device.  With Q^T M Q = I each column obeys
   // (I + Kt) z_k = z_{k-1} + g_k, g_k = S F2p^T e_k: a linear recurrence
   // z_k = A z_{k-1} + A g_k with the constant matrix A = (I + Kt)^{-1}
-  // (Cholesky inverse).  It is evaluated by recursive doubling over time:
+  // (computed below by Newton-Schulz).  It is evaluated by recursive doubling over time:
   // after the level with stride d, X[:, k] = sum_{j < 2d, j <= k} A^j (A G)[:, k-j];
   // the next level adds A^{2d} X[:, k - 2d].  The eigenvalues of A lie in
   // (0, 1], so the powers stay bounded.
@@ -937,61 +933,106 @@ void Problem::st_finish(const StPrep& pr, double* Wall, LowRank& Y, bool adjoint
       pw = pw == P1 ? P2 : P1;
     }
   }
-  double* Zp = cur;  // q x nt: Y = Q Zp
-  double* Z = nxt;   // scratch (q x nt)
-  // 4. truncation of Y = Q Zp (Q M-orthonormal: M-weighted Frobenius norm)
-  const bool accurate = desc.trunc_tol < 1e-7;
+  fin.q = q;
+  fin.Zp.ensure(sizeof(double) * (size_t)q * nt);
+  LRP_HIP(hipMemcpyAsync(fin.Zp.p, cur, sizeof(double) * (size_t)q * nt, hipMemcpyDeviceToDevice, st));
+}
+
+// Truncation of the projected solutions Y_j = Q_j Zp_j (Q_j M-orthonormal:
+// M-weighted Frobenius norm).  Below 1e-7 each Zp runs through the host
+// Jacobi SVD; otherwise the eigenpairs of the Gram matrices of the smaller
+// side are solved as one batch: Zp^T Zp (nt x nt) when nt is at most the
+// batch's largest q, else Zp Zp^T zero-padded to that q.
+void Problem::st_truncate(std::vector<StFin>& fins, const std::vector<LowRank*>& Y, bool adjoint) {
+  const int nb = (int)fins.size();
   double tail = 0.0;
-  int ry = 0;
-  if (accurate) {
-    std::vector<double> Zh((size_t)q * nt);
-    to_host(Zh.data(), Zp, Zh.size());
-    std::vector<double> s, Uz, Vz;
-    svd(q, nt, Zh.data(), q, s, Uz, Vz);
-    ry = truncation_rank(s, desc.trunc_tol, desc.rank_cap, &tail);
-    Y.resize(nx, nt, ry);
-    if (ry > 0) {
-      std::vector<double> Cm((size_t)q * ry);
-      for (int c = 0; c < ry; ++c)
-        for (int i = 0; i < q; ++i) Cm[(size_t)c * q + i] = Uz[(size_t)c * q + i] * s[c];
-      proj(q, Q, Cm, ry, Y.a(), 0.0);
-      for (int c = 0; c < ry; ++c)
-        for (int k = 0; k < nt; ++k) Y.B[(size_t)c * nt + (adjoint ? nt - 1 - k : k)] = Vz[(size_t)c * nt + k];
-    }
-  } else {
-    const bool right = nt <= q;  // Gram of the smaller side
-    const int g = right ? nt : q;
-    if (right) dense->gemm(true, false, nt, nt, q, 1.0, Zp, q, Zp, q, 0.0, Gsm, nt);
-    else dense->gemm(false, true, q, q, nt, 1.0, Zp, q, Zp, q, 0.0, Gsm, q);
-    double* wg = Gt;  // reuse: g values
-    dense->syevd(g, Gsm, g, wg, eig_work_);
-    std::vector<double> w(g);
-    to_host(w.data(), wg, g);
-    std::vector<double> s(g);
-    for (int c = 0; c < g; ++c) s[c] = std::sqrt(std::max(w[g - 1 - c], 0.0));
-    ry = truncation_rank(s, desc.trunc_tol, desc.rank_cap, &tail);
-    Y.resize(nx, nt, ry);
-    if (ry > 0) {
-      // eigenvectors of the kept directions are the last ry columns of Gsm
-      const double* Ek = Gsm + (size_t)(g - ry) * g;
-      std::vector<double> B2((size_t)nt * ry);
-      if (right) {
-        // Y = Q (Zp V_r) V_r^T
-        double* Cm = Z;  // q x ry
-        dense->gemm(false, false, q, ry, nt, 1.0, Zp, q, Ek, nt, 0.0, Cm, q);
-        proj_dev(q, Q, Cm, q, ry, Y.a(), 0.0);
-        to_host(B2.data(), Ek, (size_t)nt * ry);
-      } else {
-        // Y = Q U_r (Zp^T U_r)^T
-        double* Vt = Z;  // nt x ry
-        dense->gemm(true, false, nt, ry, q, 1.0, Zp, q, Ek, q, 0.0, Vt, nt);
-        proj_dev(q, Q, Ek, q, ry, Y.a(), 0.0);
-        to_host(B2.data(), Vt, (size_t)nt * ry);
+  auto store_B = [&](LowRank& y, const std::vector<double>& B2, int ry) {
+    for (int c = 0; c < ry; ++c)
+      for (int k = 0; k < nt; ++k) y.B[(size_t)c * nt + (adjoint ? nt - 1 - k : k)] = B2[(size_t)c * nt + k];
+  };
+  for (int j = 0; j < nb; ++j) {
+    Y[j]->nx = nx;
+    Y[j]->nt = nt;
+    if (fins[j].q == 0) Y[j]->resize(nx, nt, 0);
+  }
+  if (desc.trunc_tol < 1e-7) {
+    for (int j = 0; j < nb; ++j) {
+      const int q = fins[j].q;
+      if (q == 0) continue;
+      std::vector<double> Zh((size_t)q * nt);
+      to_host(Zh.data(), fins[j].Zp.as<double>(), Zh.size());
+      std::vector<double> sv, Uz, Vz;
+      svd(q, nt, Zh.data(), q, sv, Uz, Vz);
+      const int ry = truncation_rank(sv, desc.trunc_tol, desc.rank_cap, &tail);
+      Y[j]->resize(nx, nt, ry);
+      if (ry > 0) {
+        std::vector<double> Cm((size_t)q * ry);
+        for (int c = 0; c < ry; ++c)
+          for (int i = 0; i < q; ++i) Cm[(size_t)c * q + i] = Uz[(size_t)c * q + i] * sv[c];
+        proj(q, fins[j].Q.as<double>(), Cm, ry, Y[j]->a(), 0.0);
+        store_B(*Y[j], Vz, ry);
       }
-      sync();
-      for (int c = 0; c < ry; ++c)
-        for (int k = 0; k < nt; ++k) Y.B[(size_t)c * nt + (adjoint ? nt - 1 - k : k)] = B2[(size_t)c * nt + k];
     }
+    stats.last_tail = tail;
+    sync();
+    return;
+  }
+  std::vector<int> act;
+  int qb = 0;
+  for (int j = 0; j < nb; ++j)
+    if (fins[j].q > 0) {
+      act.push_back(j);
+      qb = std::max(qb, fins[j].q);
+    }
+  const int na = (int)act.size();
+  if (na == 0) {
+    sync();
+    return;
+  }
+  const bool right = nt <= qb;
+  const int g = right ? nt : qb;
+  const size_t gsz = (size_t)g * g;
+  st_gram_.ensure(sizeof(double) * (gsz * na + (size_t)g * na + 64));
+  double* G = st_gram_.as<double>();
+  double* wg = G + gsz * na;
+  if (!right) LRP_HIP(hipMemsetAsync(G, 0, sizeof(double) * gsz * na, st));
+  for (int a = 0; a < na; ++a) {
+    const StFin& f = fins[act[a]];
+    const double* Zp = f.Zp.as<double>();
+    if (right) dense->gemm(true, false, nt, nt, f.q, 1.0, Zp, f.q, Zp, f.q, 0.0, G + gsz * a, g);
+    else dense->gemm(false, true, f.q, f.q, nt, 1.0, Zp, f.q, Zp, f.q, 0.0, G + gsz * a, g);
+  }
+  dense->syevd_batched(g, G, g, (long)gsz, wg, g, na, eig_work_);
+  std::vector<double> w((size_t)g * na);
+  to_host(w.data(), wg, w.size());
+  for (int a = 0; a < na; ++a) {
+    const StFin& f = fins[act[a]];
+    LowRank& y = *Y[act[a]];
+    const int q = f.q;
+    const double* Zp = f.Zp.as<double>();
+    std::vector<double> sv(g);
+    for (int c = 0; c < g; ++c) sv[c] = std::sqrt(std::max(w[(size_t)a * g + g - 1 - c], 0.0));
+    const int ry = truncation_rank(sv, desc.trunc_tol, desc.rank_cap, &tail);
+    y.resize(nx, nt, ry);
+    if (ry == 0) continue;
+    // eigenvectors of the kept directions are the last ry columns
+    const double* Ek = G + gsz * a + (size_t)(g - ry) * g;
+    std::vector<double> B2((size_t)nt * ry);
+    st_c_.ensure(sizeof(double) * (size_t)std::max(q, nt) * ry);
+    if (right) {
+      // Y = Q (Zp V_r) V_r^T
+      double* Cm = st_c_.as<double>();  // q x ry
+      dense->gemm(false, false, q, ry, nt, 1.0, Zp, q, Ek, nt, 0.0, Cm, q);
+      proj_dev(q, f.Q.as<double>(), Cm, q, ry, y.a(), 0.0);
+      to_host(B2.data(), Ek, (size_t)nt * ry);
+    } else {
+      // Y = Q U_r (Zp^T U_r)^T, U_r the first q rows of the padded eigenvectors
+      double* Vt = st_c_.as<double>();  // nt x ry
+      dense->gemm(true, false, nt, ry, q, 1.0, Zp, q, Ek, g, 0.0, Vt, nt);
+      proj_dev(q, f.Q.as<double>(), Ek, g, ry, y.a(), 0.0);
+      to_host(B2.data(), Vt, (size_t)nt * ry);
+    }
+    store_B(y, B2, ry);
   }
   stats.last_tail = tail;
   sync();

@@ -51,14 +51,15 @@ struct Request {
   size_t peak_bytes = 0;
 };
 
-// Device-memory estimate of one request, in bytes: the rational Krylov basis
-// and its multigrid work (rank cap x poles x a few nodal vectors), the
-// shared Lanczos basis and the posterior variance.
+// Device-memory estimate of one request, in bytes: the rational Krylov pole
+// solutions and bases of a block of four applies with their multigrid work
+// (rank cap x poles x about ten nodal vectors), the shared Lanczos basis and
+// the posterior variance.
 size_t estimate_bytes(const lrpost_problem_desc& d, int k) {
   const double nx = (double)(d.N - 1) * (d.N - 1);
   const double lt = -std::log10(d.trunc_tol);
   const double poles = std::max(4.0, std::min(24.0, std::round(1.5 * lt) + 1.0));
-  const double cols = d.rank_cap * poles * 6.0 + 16.0 * (4.0 * k + 16.0) + 1024.0 + (double)d.nt;
+  const double cols = d.rank_cap * poles * 10.0 + 16.0 * (4.0 * k + 16.0) + 1024.0 + (double)d.nt;
   return (size_t)(8.0 * nx * cols * 2.0);
 }
 
