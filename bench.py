@@ -36,14 +36,18 @@ COPY_BYTES = 256 << 20  # calibration copy for the HBM byte counters, each way
 # Multigrid kernels timed with HIP events (kind as in the library's
 # LRPOST_KERNEL_*), their names, and the committed HBM-counter reports.
 KERNELS = {
-    0: ("k_cheb", "multigrid Chebyshev smoother step"),
-    1: ("k_mg_down", "level-fused pre-smoothing + residual + restriction"),
-    2: ("k_mg_up", "level-fused prolongation + post-smoothing"),
+    0: ("k_cheb", "multigrid Chebyshev smoother step", True),
+    1: ("k_mg_down", "level-fused pre-smoothing + residual + restriction", True),
+    2: ("k_mg_up", "level-fused prolongation + post-smoothing", True),
+    3: ("k_gram_mfma", "float64 matrix-core Gram A^T B, partial products", False),
 }
+MFMA_F64_PEAK_TFLOPS = 78.6  # MI355X published dense FP64 matrix throughput
 
 
 def traffic_report(kernel, precision):
-    tag = "f32_" if precision == "mixed" else ""
+    # the multigrid kernels run in float32 in mixed precision, the Gram always in float64
+    f32 = precision == "mixed" and KERNELS[[k for k in KERNELS if KERNELS[k][0] == kernel][0]][2]
+    tag = "f32_" if f32 else ""
     suffix = "_mixed" if precision == "mixed" else ""
     return os.path.join(ROOT, "profiles", "%s_%smesh256_nt200%s_traffic.txt" % (kernel, tag, suffix))
 
@@ -250,7 +254,7 @@ def main():
     desc = main_run["desc"]
     # the multigrid kernel with the most device time in the timed steps
     kind = max(main_run["prof"], key=lambda k: main_run["prof"][k][1])
-    launches, kern_ms, kern_bytes = main_run["prof"][kind]
+    launches, kern_ms, kern_bytes, kern_flops = main_run["prof"][kind]
     applies, elapsed, step_ms, lam, st = (main_run["applies"], main_run["elapsed"], main_run["step_ms"],
                                           main_run["lam"], main_run["stats"])
     ref = None
@@ -259,15 +263,29 @@ def main():
         ref = run("fp64", 0, 1, False)
     from paper_1703_05638_amd.profile_summary import read_traffic
 
-    kbase, kdesc = KERNELS[kind]
+    kbase, kdesc, mg_kernel = KERNELS[kind]
     traffic = read_traffic(traffic_report(kbase, args.precision))
     avg_ms = kern_ms / max(launches, 1)
     bytes_per_launch = kern_bytes / max(launches, 1)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if launches else 0.0
-    kname = kbase + ("<double>" if args.precision == "fp64" else "<float>")
+    flops_per_launch = kern_flops / max(launches, 1)
+    gbs = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if launches else 0.0
+    tflops = flops_per_launch / (avg_ms * 1e-3) / 1e12 if launches else 0.0
+    # the tighter of the two ceilings bounds the kernel
+    mfma_bound = kern_flops / (MFMA_F64_PEAK_TFLOPS * 1e12) > kern_bytes / (HBM_PEAK_GBS * 1e9)
+    if mg_kernel:
+        kname = kbase + ("<double>" if args.precision == "fp64" else "<float>")
+    else:
+        kname = kbase
     others = {KERNELS[k][0]: {"launches": v[0], "total_ms": v[1],
                               "achieved_GBs": (v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else 0.0}
               for k, v in main_run["prof"].items() if k != kind and v[0] > 0}
+    if mfma_bound:
+        roof = {"bound": "mfma", "achieved": tflops, "peak": MFMA_F64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": tflops / MFMA_F64_PEAK_TFLOPS, "achieved_GBs": gbs}
+    else:
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+        if kern_flops > 0:
+            roof["achieved_TFLOPs"] = tflops
     out = {
         "metric": "Hessian applies/s (fwd+adj space-time) + p50/p99 posterior latency @1e-5 rel",
         "value": applies / elapsed,
@@ -289,12 +307,10 @@ def main():
         "applies_per_step": applies / args.steps,
         "lanczos_block_steps": st["lanczos_steps"],
         "lambda_1_to_3": [float(x) for x in lam[:3]],
-        "roofline": {"kernel": "%s (%s)" % (kname, kdesc), "bound": "hbm",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "launches": launches, "avg_launch_us": avg_ms * 1e3,
-                     "bytes_per_launch": bytes_per_launch, "total_ms": kern_ms,
-                     "other_multigrid_kernels": others},
+        "roofline": dict({"kernel": "%s (%s)" % (kname, kdesc)}, **roof,
+                         **{"traffic": traffic, "launches": launches, "avg_launch_us": avg_ms * 1e3,
+                            "bytes_per_launch": bytes_per_launch, "flops_per_launch": flops_per_launch,
+                            "total_ms": kern_ms, "other_timed_kernels": others}),
     }
     if ref is not None:
         lam64 = ref["lam"]

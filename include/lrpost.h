@@ -192,17 +192,23 @@ int lrpost_set_log(lrpost_problem* p, int level);
  *                                right-hand side;
  *   LRPOST_KERNEL_MG_UP          level-fused prolongation and post-smoothing:
  *                                read the pre-smoothed x, the coarse
- *                                correction and b, write x.
+ *                                correction and b, write x;
+ *   LRPOST_KERNEL_GRAM           the matrix-core stage of the float64 Gram
+ *                                products A^T B (nx x m and nx x q operands):
+ *                                read A and B once, 2 m q nx flops.
  * lrpost_profile_read synchronizes, returns for one kind the launch count, the
- * summed kernel time in ms and the counted bytes since the last read, and
- * resets that kind's counters. */
+ * summed kernel time in ms, the counted bytes and (if flops is not NULL) the
+ * counted floating-point operations since the last read, and resets that
+ * kind's counters. */
 enum {
   LRPOST_KERNEL_SMOOTHER_STEP = 0,
   LRPOST_KERNEL_MG_DOWN = 1,
-  LRPOST_KERNEL_MG_UP = 2
+  LRPOST_KERNEL_MG_UP = 2,
+  LRPOST_KERNEL_GRAM = 3
 };
 int lrpost_profile(lrpost_problem* p, int enable);
-int lrpost_profile_read(lrpost_problem* p, int kernel, int64_t* launches, double* total_ms, double* bytes);
+int lrpost_profile_read(lrpost_problem* p, int kernel, int64_t* launches, double* total_ms, double* bytes,
+                        double* flops);
 
 /* Multigrid kernel choice: on (the default) runs each V-cycle level on meshes
  * of up to 1023 nodes per side as two level-fused kernels (pre-smoothing with

@@ -408,13 +408,14 @@ int lrpost_profile(lrpost_problem* p, int enable) {
   });
 }
 
-int lrpost_profile_read(lrpost_problem* p, int kernel, int64_t* launches, double* total_ms, double* bytes) {
+int lrpost_profile_read(lrpost_problem* p, int kernel, int64_t* launches, double* total_ms, double* bytes,
+                        double* flops) {
   return guarded([&] {
     Problem* P = impl(p);
     PoolScope pool_scope(P->pool);
     if (!launches || !total_ms || !bytes) fail(LRPOST_EINVAL, "null argument");
-    if (kernel < 0 || kernel > LRPOST_KERNEL_MG_UP) fail(LRPOST_EINVAL, "unknown kernel kind");
-    P->prof_read(kernel, launches, total_ms, bytes);
+    if (kernel < 0 || kernel > LRPOST_KERNEL_GRAM) fail(LRPOST_EINVAL, "unknown kernel kind");
+    P->prof_read(kernel, launches, total_ms, bytes, flops);
   });
 }
 

@@ -195,16 +195,16 @@ class Problem {
   struct ProfSlot {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     size_t used = 0;
-    double bytes = 0.0;
+    double bytes = 0.0, flops = 0.0;
   };
   bool prof_on = false;
-  std::array<ProfSlot, 3> prof_;
+  std::array<ProfSlot, 4> prof_;
   template <class Launch>
-  void timed(int kind, double bytes, Launch&& launch);
+  void timed(int kind, double bytes, Launch&& launch, double flops = 0.0);
   template <typename T>
   void smooth_step(int nl, int ncols, const T* xc, const T* xp, T* xo, const T* b, long ld, const double* prm, int s);
   void prof_reset();
-  void prof_read(int kind, int64_t* launches, double* ms, double* bytes);
+  void prof_read(int kind, int64_t* launches, double* ms, double* bytes, double* flops);
   // level-fused multigrid kernels on meshes with up to kMgFusedMaxN nodes per
   // side (on by default; off selects the per-step kernels)
   bool mg_fused = true;

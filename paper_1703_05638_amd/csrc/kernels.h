@@ -41,6 +41,11 @@ constexpr int kCoarseLdsMaxN = 31;
 
 int gram_chunks(long nrows, int m, int q);       // float instance (LDS kernel)
 int gram_chunks_mfma(long nrows, int m, int q);  // double instance (FP64 MFMA kernel)
+// the two stages of gram<double>: per-chunk partial products on the matrix
+// cores (part: gram_chunks_mfma() x m x q doubles), then their sum into C
+void gram_mfma_partials(hipStream_t st, long nrows, int m, const double* A, long lda, int q, const double* B,
+                        long ldb, double* part);
+void sum_partials(hipStream_t st, int nchunk, long count, const double* part, double* C);
 // C (device, m x q, double) = A^T B; part: device scratch of gram_chunks()*m*q
 // doubles (gram_chunks_mfma() for T = double).
 template <typename T>

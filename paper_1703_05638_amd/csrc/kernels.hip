@@ -1030,17 +1030,27 @@ void gram(hipStream_t st, long nrows, int m, const T* A, long lda, int q, const 
   const long count = (long)m * q;
   hipLaunchKernelGGL(k_sum_partials, dim3((count + SP_X - 1) / SP_X), dim3(SP_X * SP_Y), 0, st, nchunk, count, part, C);
 }
-template <>
-void gram<double>(hipStream_t st, long nrows, int m, const double* A, long lda, int q, const double* B, long ldb,
-                  double* C, double* part) {
+void gram_mfma_partials(hipStream_t st, long nrows, int m, const double* A, long lda, int q, const double* B,
+                        long ldb, double* part) {
   if (m <= 0 || q <= 0) return;
   const int nchunk = gram_chunks_mfma(nrows, m, q);
   long rpc = (nrows + nchunk - 1) / nchunk;
   rpc = ((rpc + MK - 1) / MK) * MK;
   dim3 grd((m + MT - 1) / MT, (q + MT - 1) / MT, nchunk);
   hipLaunchKernelGGL(k_gram_mfma, grd, dim3(256 * MG), 0, st, nrows, rpc, m, A, lda, q, B, ldb, part);
-  const long count = (long)m * q;
+}
+
+void sum_partials(hipStream_t st, int nchunk, long count, const double* part, double* C) {
+  if (count <= 0) return;
   hipLaunchKernelGGL(k_sum_partials, dim3((count + SP_X - 1) / SP_X), dim3(SP_X * SP_Y), 0, st, nchunk, count, part, C);
+}
+
+template <>
+void gram<double>(hipStream_t st, long nrows, int m, const double* A, long lda, int q, const double* B, long ldb,
+                  double* C, double* part) {
+  if (m <= 0 || q <= 0) return;
+  gram_mfma_partials(st, nrows, m, A, lda, q, B, ldb, part);
+  sum_partials(st, gram_chunks_mfma(nrows, m, q), (long)m * q, part, C);
 }
 template void gram<float>(hipStream_t, long, int, const float*, long, int, const float*, long, double*, double*);
 

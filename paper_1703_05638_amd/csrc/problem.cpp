@@ -425,7 +425,7 @@ void Problem::vcycle_zero(int ncols, const T* B, T* X) {
 }
 
 template <class Launch>
-void Problem::timed(int kind, double bytes, Launch&& launch) {
+void Problem::timed(int kind, double bytes, Launch&& launch, double flops) {
   if (!prof_on) {
     launch();
     return;
@@ -442,6 +442,7 @@ void Problem::timed(int kind, double bytes, Launch&& launch) {
   launch();
   LRP_HIP(hipEventRecord(ev.second, st));
   ps.bytes += bytes;
+  ps.flops += flops;
 }
 
 // One Chebyshev smoother step, credited with its algorithmic traffic: read
@@ -458,10 +459,11 @@ void Problem::prof_reset() {
   for (auto& ps : prof_) {
     ps.used = 0;
     ps.bytes = 0.0;
+    ps.flops = 0.0;
   }
 }
 
-void Problem::prof_read(int kind, int64_t* launches, double* ms, double* bytes) {
+void Problem::prof_read(int kind, int64_t* launches, double* ms, double* bytes, double* flops) {
   sync();
   ProfSlot& ps = prof_[kind];
   double tot = 0.0;
@@ -473,8 +475,10 @@ void Problem::prof_read(int kind, int64_t* launches, double* ms, double* bytes) 
   *launches = (int64_t)ps.used;
   *ms = tot;
   *bytes = ps.bytes;
+  if (flops) *flops = ps.flops;
   ps.used = 0;
   ps.bytes = 0.0;
+  ps.flops = 0.0;
 }
 
 void Problem::mg_cycles_f32(int ncols, const float* B, float* X, const std::vector<ShiftCoef>& neg, int cycles) {
@@ -550,11 +554,8 @@ void Problem::mg_solve(int ncols, const double* B, double* X, const std::vector<
 void Problem::gram(int m, const double* A, int q, const double* B, std::vector<double>& C) {
   C.assign((size_t)m * q, 0.0);
   if (m <= 0 || q <= 0) return;
-  const int nchunk = gram_chunks_mfma(nx, m, q);
-  gram_part_.ensure(sizeof(double) * (size_t)nchunk * m * q);
   gram_out_.ensure(sizeof(double) * (size_t)m * q);
-  ::lrp::gram<double>(st, nx, m, A, nx, q, B, nx, gram_out_.as<double>(), gram_part_.as<double>());
-  LRP_HIP(hipGetLastError());
+  gram_dev(m, A, q, B, gram_out_.as<double>());
   to_host(C.data(), gram_out_.as<double>(), (size_t)m * q);
 }
 
@@ -566,11 +567,16 @@ void Problem::proj(int m, const double* A, const std::vector<double>& Q, int p, 
   LRP_HIP(hipGetLastError());
 }
 
+// Stage 1 (the matrix-core kernel) is credited with reading A and B once and
+// with 2 m q nx flops.
 void Problem::gram_dev(int m, const double* A, int q, const double* B, double* C) {
   if (m <= 0 || q <= 0) return;
   const int nchunk = gram_chunks_mfma(nx, m, q);
   gram_part_.ensure(sizeof(double) * (size_t)nchunk * m * q);
-  ::lrp::gram<double>(st, nx, m, A, nx, q, B, nx, C, gram_part_.as<double>());
+  timed(LRPOST_KERNEL_GRAM, sizeof(double) * (double)(m + q) * nx,
+        [&] { gram_mfma_partials(st, nx, m, A, nx, q, B, nx, gram_part_.as<double>()); },
+        2.0 * m * q * (double)nx);
+  sum_partials(st, nchunk, (long)m * q, gram_part_.as<double>(), C);
   LRP_HIP(hipGetLastError());
 }
 

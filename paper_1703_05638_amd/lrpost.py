@@ -23,7 +23,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "lrpost.h")
 LRPOST_FP64, LRPOST_MIXED = 0, 1
 LRPOST_MISFIT, LRPOST_PRECOND = 0, 1
 LRPOST_BLOCK_LANCZOS, LRPOST_RANDOMIZED = 0, 1
-LRPOST_KERNEL_SMOOTHER_STEP, LRPOST_KERNEL_MG_DOWN, LRPOST_KERNEL_MG_UP = 0, 1, 2
+LRPOST_KERNEL_SMOOTHER_STEP, LRPOST_KERNEL_MG_DOWN, LRPOST_KERNEL_MG_UP, LRPOST_KERNEL_GRAM = 0, 1, 2, 3
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "ENOCONV", -4: "EBREAKDOWN", -5: "EHIP"}
 
 
@@ -97,7 +97,7 @@ def load(path: str = LIB_PATH):
         "lrpost_truncate": (I, [P, ctypes.POINTER(LowRankC), D, I]),
         "lrpost_set_log": (I, [P, I]),
         "lrpost_profile": (I, [P, I]),
-        "lrpost_profile_read": (I, [P, I, ctypes.POINTER(ctypes.c_int64), pd, pd]),
+        "lrpost_profile_read": (I, [P, I, ctypes.POINTER(ctypes.c_int64), pd, pd, pd]),
         "lrpost_set_mg_fused": (I, [P, I]),
         "lrpost_server_create": (I, [ctypes.c_size_t, I, ctypes.POINTER(P)]),
         "lrpost_server_submit": (I, [P, P, I, I, ctypes.POINTER(ctypes.c_uint64)]),
@@ -376,14 +376,16 @@ class Problem:
         _check(_lib.lrpost_profile(self.h, 1 if enable else 0))
 
     def profile_read(self, kernel: int = None):
-        """(launches, kernel ms, algorithmic bytes) of one kernel kind
+        """(launches, kernel ms, algorithmic bytes, flops) of one kernel kind
         (LRPOST_KERNEL_*; default the level-fused up kernel) since the last read."""
         n = ctypes.c_int64()
         ms = ctypes.c_double()
         by = ctypes.c_double()
+        fl = ctypes.c_double()
         k = LRPOST_KERNEL_MG_UP if kernel is None else kernel
-        _check(_lib.lrpost_profile_read(self.h, k, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
-        return n.value, ms.value, by.value
+        _check(_lib.lrpost_profile_read(self.h, k, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by),
+                                        ctypes.byref(fl)))
+        return n.value, ms.value, by.value, fl.value
 
     def set_mg_fused(self, on: bool):
         """Level-fused multigrid kernels (default) or one kernel per step."""

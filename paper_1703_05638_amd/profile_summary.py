@@ -31,11 +31,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = {
     "k_cheb": ("void k_cheb(", "template void mg_smooth_step<float>"),
     "k_mg": ("__device__ inline void strip_of(", "template void mg_up<float>"),
+    "k_gram": ("constexpr int MT = 64;", "void sum_partials("),
 }
 
 
 def _source_key(regex):
-    return "k_mg" if "k_mg" in regex else "k_cheb"
+    for key in ("k_gram", "k_mg"):
+        if key in regex:
+            return key
+    return "k_cheb"
 
 
 def source_digest(key="k_cheb"):
