@@ -223,12 +223,14 @@ class Problem {
   };
   void st_prepare(const LowRank& F, bool adjoint, StPrep& pr);
   double* st_pole_solves(const std::vector<const StPrep*>& prs);
-  // per source: M-orthonormal basis Q (nx x q) and projected solution Zp (q x nt)
+  // per source: M-orthonormal basis Q (nx x q) and projected solution Zp
+  // (q x nt); W2 and Kt are its working blocks while the basis is built
   struct StFin {
     int q = 0;
-    DevMem Q, Zp;
+    DevMem Q, Zp, W2, Kt;
   };
-  void st_project(const StPrep& pr, double* Wall, StFin& fin);
+  void st_project_batch(const std::vector<StPrep>& prs, double* Wall, std::vector<StFin>& fins);
+  void st_solve_projected(const StPrep& pr, int q, StFin& fin);
   void st_truncate(std::vector<StFin>& fins, const std::vector<LowRank*>& Y, bool adjoint);
   // G x (precond) or H_mis x (misfit).
   void hess_apply(const LowRank& x, LowRank& y, bool precond);
@@ -270,7 +272,7 @@ class Problem {
   DevMem mg_work_f_, mg_f_;
   void upload_mg_params(const std::vector<ShiftCoef>& ab);
   // space-time solver workspaces
-  DevMem st_gram_, st_w_, st_mw_, st_wall_, st_brep_, st_kt_, st_small_, st_c_, eig_work_;
+  DevMem st_gram_, st_g_, st_mw_, st_wall_, st_brep_, st_small_, st_c_, eig_work_;
 };
 
 void smoother_interval(double a, double bh2, double* lo, double* hi);

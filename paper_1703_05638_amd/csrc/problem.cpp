@@ -779,100 +779,152 @@ void Problem::spacetime_solve_batch(const std::vector<const LowRank*>& F, const 
   }
   double* Wall = st_pole_solves(pp);
   std::vector<StFin> fins(nb);
-  long off = 0;
-  for (int j = 0; j < nb; ++j) {
-    st_project(prs[j], Wall ? Wall + (size_t)off * nx : nullptr, fins[j]);
-    off += (long)prs[j].r1 * (long)poles.size();
-  }
+  st_project_batch(prs, Wall, fins);
   st_truncate(fins, Y, adjoint);
 }
 
 // Basis and projected problem of one prepared source whose pole solves are in
 // Wall (nx x r1 npol, overwritten): fin.Q (nx x q, M-orthonormal) and fin.Zp
 // (q x nt) with the space-time solution Q Zp.
-void Problem::st_project(const StPrep& pr, double* Wall, StFin& fin) {
-  fin.q = 0;
-  const int r1 = pr.r1;
-  if (r1 == 0) return;
-  const double* Fb = pr.Fb.as<double>();
-  const std::vector<double>& F2p = pr.F2p;
-  // 2. block-by-block M-orthonormalization of the pole solutions
+void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std::vector<StFin>& fins) {
+  // 2. block-by-block M-orthonormalization of the pole solutions.  Block
+  // Gram-Schmidt against Q in the M inner product, twice, with the block
+  // normalized between the two sweeps: (1) project the raw block out of
+  // span(Q); (2) orthonormalize it by its Gram eigenpairs (SVQB, Stathopoulos
+  // and Wu 2002), dropping directions whose M-norm fell below 1e-11 of the
+  // block's original scale; (3) project the normalized block out of span(Q)
+  // again: a direction that kept little of its norm in (1) carries the
+  // rounding of that sweep magnified by the normalization, and this sweep
+  // removes it; (4) orthonormalize again, dropping directions that now keep
+  // less than 1e-4 of their norm (they were inside span(Q)).  A Gram-based
+  // Cholesky cannot tell nearly dependent directions from rounding noise, so
+  // it is not used here.  The sources of the batch go through the pole blocks
+  // in lockstep, so that their small Gram matrices reach the host together:
+  // two round trips per pole block for the whole batch.  Each source's
+  // arithmetic is the same as on its own.
+  const int nb = (int)prs.size();
   const int npol = (int)poles.size();
-  const int qmax = r1 * npol;
-  fin.Q.ensure(sizeof(double) * (size_t)nx * qmax);
-  st_w_.ensure(sizeof(double) * (size_t)nx * r1);
-  st_mw_.ensure(sizeof(double) * (size_t)nx * std::max(r1, 1));
-  double* Q = fin.Q.as<double>();
-  double* W2 = st_w_.as<double>();
-  double* MW = st_mw_.as<double>();
-  int q = 0;
-  st_kt_.ensure(sizeof(double) * (size_t)qmax * qmax);
-  double* Kt = st_kt_.as<double>();  // q x q projected tau K, leading dimension qmax (device)
   const std::vector<ShiftCoef> Mop{{0.0, 1.0}};
   const std::vector<ShiftCoef> Kop{{tau, 0.0}};
-  std::vector<double> Gw, wv, Uv;
-  for (int ip = 0; ip < npol; ++ip) {
-    double* W = Wall + (size_t)ip * r1 * nx;
-    // reference norms before orthogonalization
-    apply_op(r1, W, MW, Mop);
-    gram(r1, W, r1, MW, Gw);
-    double ref = 0.0;
-    for (int c = 0; c < r1; ++c) ref = std::max(ref, Gw[(size_t)c * r1 + c]);
-    if (!(ref > 0)) continue;
-    // Block Gram-Schmidt against Q in the M inner product, twice, with the
-    // block normalized between the two sweeps: (1) project the raw block
-    // out of span(Q); (2) orthonormalize it by its Gram eigenpairs (SVQB,
-    // Stathopoulos and Wu 2002), dropping directions whose M-norm fell below
-    // 1e-11 of the block's original scale; (3) project the normalized block
-    // out of span(Q) again: a direction that kept little of its norm in (1)
-    // carries the rounding of that sweep magnified by the normalization,
-    // and this sweep removes it; (4) orthonormalize again, dropping
-    // directions that now keep less than 1e-4 of their norm (they were
-    // inside span(Q)).  A Gram-based Cholesky cannot tell nearly dependent
-    // directions from rounding noise, so it is not used here.
-    auto sweep = [&](int kc, double* X) {  // X -= Q (Q^T M X), all on the device
-      if (q == 0 || kc == 0) return;
-      apply_op(kc, X, MW, Mop);
-      st_c_.ensure(sizeof(double) * (size_t)q * kc);
-      gram_dev(q, Q, kc, MW, st_c_.as<double>());
-      dense->scal(q * kc, -1.0, st_c_.as<double>());
-      proj_dev(q, Q, st_c_.as<double>(), q, kc, X, 1.0);
-    };
-    auto svqb = [&](int kc, const double* src, double* dst, double thresh) -> int {
-      apply_op(kc, src, MW, Mop);
-      gram(kc, src, kc, MW, Gw);
-      wv.assign(kc, 0.0);
-      Uv.assign((size_t)kc * kc, 0.0);
-      if (!syev(kc, Gw.data(), kc, wv.data(), Uv.data())) fail(LRPOST_EBREAKDOWN, "basis Gram eigensolve");
-      std::vector<int> kk;
-      for (int j = kc - 1; j >= 0; --j)
-        if (wv[j] > thresh) kk.push_back(j);
-      const int kn = (int)kk.size();
-      if (kn == 0) return 0;
-      std::vector<double> Tm((size_t)kc * kn);
-      for (int c = 0; c < kn; ++c)
-        for (int i = 0; i < kc; ++i) Tm[(size_t)c * kc + i] = Uv[(size_t)kk[c] * kc + i] / std::sqrt(wv[kk[c]]);
-      proj(kc, src, Tm, kn, dst, 0.0);
-      return kn;
-    };
-    sweep(r1, W);
-    int kcols = svqb(r1, W, W2, 1e-22 * ref);
-    if (kcols == 0) continue;
-    sweep(kcols, W2);
-    kcols = svqb(kcols, W2, Q + (size_t)q * nx, 1e-8);
-    if (kcols == 0) continue;
-    // extend Kt = Q^T tau K Q by the new columns (upper triangle suffices)
-    double* Qn = Q + (size_t)q * nx;
-    apply_op(kcols, Qn, MW, Kop);
-    gram_out_.ensure(sizeof(double) * (size_t)(q + kcols) * kcols);
-    gram_dev(q + kcols, Q, kcols, MW, gram_out_.as<double>());
-    LRP_HIP(hipMemcpy2DAsync(Kt + (size_t)q * qmax, sizeof(double) * qmax, gram_out_.as<double>(),
-                             sizeof(double) * (q + kcols), sizeof(double) * (q + kcols), kcols,
-                             hipMemcpyDeviceToDevice, st));
-    q += kcols;
+  std::vector<double*> Wb(nb, nullptr);
+  std::vector<int> q(nb, 0);
+  int rmax = 0;
+  long off = 0;
+  for (int j = 0; j < nb; ++j) {
+    fins[j].q = 0;
+    const int r1 = prs[j].r1;
+    if (Wall) Wb[j] = Wall + (size_t)off * nx;
+    off += (long)r1 * npol;
+    rmax = std::max(rmax, r1);
+    if (r1 == 0) continue;
+    const int qmax = r1 * npol;
+    fins[j].Q.ensure(sizeof(double) * (size_t)nx * qmax);
+    fins[j].W2.ensure(sizeof(double) * (size_t)nx * r1);
+    fins[j].Kt.ensure(sizeof(double) * (size_t)qmax * qmax);  // q x q projected tau K, leading dimension qmax
   }
-  stats.last_basis = q;
-  if (q == 0) return;
+  if (rmax == 0) return;
+  st_mw_.ensure(sizeof(double) * (size_t)nx * rmax);
+  double* MW = st_mw_.as<double>();
+  const size_t gs = (size_t)rmax * rmax;  // one Gram slot; two per source
+  st_g_.ensure(sizeof(double) * gs * 2 * nb);
+  double* Gd = st_g_.as<double>();
+  std::vector<double> Gh(gs * 2 * nb);
+  auto slot = [&](int j, int k) { return (size_t)(2 * j + k) * gs; };
+  auto sweep = [&](int j, int kc, double* X) {  // X -= Q (Q^T M X), all on the device
+    if (q[j] == 0 || kc == 0) return;
+    const double* Q = fins[j].Q.as<double>();
+    apply_op(kc, X, MW, Mop);
+    st_c_.ensure(sizeof(double) * (size_t)q[j] * kc);
+    gram_dev(q[j], Q, kc, MW, st_c_.as<double>());
+    dense->scal(q[j] * kc, -1.0, st_c_.as<double>());
+    proj_dev(q[j], Q, st_c_.as<double>(), q[j], kc, X, 1.0);
+  };
+  // eigenpairs of a block's Gram G (kc x kc, host) above thresh -> the
+  // orthonormalizing transform Tm (kc x kn)
+  auto svqb_host = [&](int kc, const double* G, double thresh, std::vector<double>& Tm) -> int {
+    std::vector<double> Gw(G, G + (size_t)kc * kc), wv(kc, 0.0), Uv((size_t)kc * kc, 0.0);
+    if (!syev(kc, Gw.data(), kc, wv.data(), Uv.data())) fail(LRPOST_EBREAKDOWN, "basis Gram eigensolve");
+    std::vector<int> kk;
+    for (int i = kc - 1; i >= 0; --i)
+      if (wv[i] > thresh) kk.push_back(i);
+    const int kn = (int)kk.size();
+    Tm.assign((size_t)kc * std::max(kn, 1), 0.0);
+    for (int c = 0; c < kn; ++c)
+      for (int i = 0; i < kc; ++i) Tm[(size_t)c * kc + i] = Uv[(size_t)kk[c] * kc + i] / std::sqrt(wv[kk[c]]);
+    return kn;
+  };
+  std::vector<int> k1(nb, 0);
+  std::vector<double> Tm;
+  for (int ip = 0; ip < npol; ++ip) {
+    // stage 1: reference norms of the raw block, first sweep, Gram of the swept block
+    for (int j = 0; j < nb; ++j) {
+      const int r1 = prs[j].r1;
+      if (r1 == 0) continue;
+      double* W = Wb[j] + (size_t)ip * r1 * nx;
+      apply_op(r1, W, MW, Mop);
+      gram_dev(r1, W, r1, MW, Gd + slot(j, 0));
+      sweep(j, r1, W);
+      apply_op(r1, W, MW, Mop);
+      gram_dev(r1, W, r1, MW, Gd + slot(j, 1));
+    }
+    to_host(Gh.data(), Gd, Gh.size());
+    bool any = false;
+    for (int j = 0; j < nb; ++j) {
+      const int r1 = prs[j].r1;
+      k1[j] = 0;
+      if (r1 == 0) continue;
+      double ref = 0.0;
+      for (int c = 0; c < r1; ++c) ref = std::max(ref, Gh[slot(j, 0) + (size_t)c * r1 + c]);
+      if (!(ref > 0)) continue;
+      k1[j] = svqb_host(r1, Gh.data() + slot(j, 1), 1e-22 * ref, Tm);
+      if (k1[j] == 0) continue;
+      proj(r1, Wb[j] + (size_t)ip * r1 * nx, Tm, k1[j], fins[j].W2.as<double>(), 0.0);
+      any = true;
+    }
+    if (!any) continue;
+    // stage 2: second sweep of the normalized block and its Gram
+    for (int j = 0; j < nb; ++j) {
+      if (k1[j] == 0) continue;
+      double* W2 = fins[j].W2.as<double>();
+      sweep(j, k1[j], W2);
+      apply_op(k1[j], W2, MW, Mop);
+      gram_dev(k1[j], W2, k1[j], MW, Gd + slot(j, 0));
+    }
+    to_host(Gh.data(), Gd, Gh.size());
+    for (int j = 0; j < nb; ++j) {
+      if (k1[j] == 0) continue;
+      const int kcols = svqb_host(k1[j], Gh.data() + slot(j, 0), 1e-8, Tm);
+      if (kcols == 0) continue;
+      double* Q = fins[j].Q.as<double>();
+      double* Qn = Q + (size_t)q[j] * nx;
+      proj(k1[j], fins[j].W2.as<double>(), Tm, kcols, Qn, 0.0);
+      // extend Kt = Q^T tau K Q by the new columns (upper triangle suffices)
+      const int qmax = prs[j].r1 * npol;
+      apply_op(kcols, Qn, MW, Kop);
+      gram_out_.ensure(sizeof(double) * (size_t)(q[j] + kcols) * kcols);
+      gram_dev(q[j] + kcols, Q, kcols, MW, gram_out_.as<double>());
+      LRP_HIP(hipMemcpy2DAsync(fins[j].Kt.as<double>() + (size_t)q[j] * qmax, sizeof(double) * qmax,
+                               gram_out_.as<double>(), sizeof(double) * (q[j] + kcols), sizeof(double) * (q[j] + kcols),
+                               kcols, hipMemcpyDeviceToDevice, st));
+      q[j] += kcols;
+    }
+  }
+  for (int j = 0; j < nb; ++j) {
+    stats.last_basis = q[j];
+    if (q[j] > 0) st_solve_projected(prs[j], q[j], fins[j]);
+  }
+}
+
+// 3. Projected problem of one source on the device, given its basis
+// (fin.Q, q columns) and projected tau K (fin.Kt, leading dimension r1 npol):
+// fin.Zp (q x nt).
+void Problem::st_solve_projected(const StPrep& pr, int q, StFin& fin) {
+  const int r1 = pr.r1;
+  const int qmax = r1 * (int)poles.size();
+  const double* Fb = pr.Fb.as<double>();
+  const std::vector<double>& F2p = pr.F2p;
+  const double* Q = fin.Q.as<double>();
+  const double* Kt = fin.Kt.as<double>();
   // 3. projected problem on the device.  With Q^T M Q = I each column obeys
   // (I + Kt) z_k = z_{k-1} + g_k, g_k = S F2p^T e_k: a linear recurrence
   // z_k = A z_{k-1} + A g_k with the constant matrix A = (I + Kt)^{-1}
