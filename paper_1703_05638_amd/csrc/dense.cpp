@@ -56,6 +56,15 @@ void upper_inverse(int n, const double* R, double* Ri) {
   }
 }
 
+// sqrt(x^2 + z^2) without the cost of std::hypot unless a square could
+// overflow or underflow.
+static inline double fast_hypot(double x, double z) {
+  const double ax = std::fabs(x), az = std::fabs(z);
+  const double m = ax > az ? ax : az;
+  if (m < 1e-150 || m > 1e150) return std::hypot(x, z);
+  return std::sqrt(x * x + z * z);
+}
+
 // Householder reduction of symmetric A (n x n, both triangles stored) to
 // tridiagonal form A = Q T Q^T.  On return d (n) and e (n-1) hold T and Q is
 // written to Z (n x n).
@@ -66,9 +75,15 @@ static void tridiagonalize(int n, double* A, double* d, double* e, double* Z) {
   auto a = [&](int i, int j) -> double& { return A[(size_t)j * n + i]; };
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;  // length of x = A[k+1:, k]
-    double xnorm = 0.0;
-    for (int i = 0; i < m; ++i) xnorm = std::hypot(xnorm, a(k + 1 + i, k));
-    if (xnorm == 0.0) continue;
+    double amax = 0.0;
+    for (int i = 0; i < m; ++i) amax = std::max(amax, std::fabs(a(k + 1 + i, k)));
+    if (amax == 0.0) continue;
+    double ss = 0.0;  // scaled sum of squares
+    for (int i = 0; i < m; ++i) {
+      const double t = a(k + 1 + i, k) / amax;
+      ss += t * t;
+    }
+    const double xnorm = amax * std::sqrt(ss);
     const double x0 = a(k + 1, k);
     const double alpha = x0 >= 0 ? -xnorm : xnorm;  // new subdiagonal value
     for (int i = 0; i < m; ++i) v[i] = a(k + 1 + i, k);
@@ -93,12 +108,20 @@ static void tridiagonalize(int n, double* A, double* d, double* e, double* Z) {
     a(k + 1, k) = alpha;
     a(k, k + 1) = alpha;
     for (int i = 1; i < m; ++i) { a(k + 1 + i, k) = 0.0; a(k, k + 1 + i) = 0.0; }
-    // Z <- Z H with H = I - beta v v^T acting on columns k+1..n-1
-    for (int r = 0; r < n; ++r) {
-      double s = 0.0;
-      for (int i = 0; i < m; ++i) s += Z[(size_t)(k + 1 + i) * n + r] * v[i];
-      s *= beta;
-      for (int i = 0; i < m; ++i) Z[(size_t)(k + 1 + i) * n + r] -= s * v[i];
+    // Z <- Z H with H = I - beta v v^T acting on columns k+1..n-1 (row sums
+    // accumulated column by column: contiguous access)
+    std::vector<double>& zs = p;  // p is free again: zs[r] = beta sum_i Z[r, k+1+i] v[i]
+    zs.assign(n, 0.0);
+    for (int i = 0; i < m; ++i) {
+      const double vi = v[i];
+      const double* zc = Z + (size_t)(k + 1 + i) * n;
+      for (int r = 0; r < n; ++r) zs[r] += zc[r] * vi;
+    }
+    for (int r = 0; r < n; ++r) zs[r] *= beta;
+    for (int i = 0; i < m; ++i) {
+      const double vi = v[i];
+      double* zc = Z + (size_t)(k + 1 + i) * n;
+      for (int r = 0; r < n; ++r) zc[r] -= zs[r] * vi;
     }
   }
   for (int i = 0; i < n; ++i) d[i] = a(i, i);
@@ -128,7 +151,7 @@ static bool tridiagonal_qr(int n, double* d, double* e, double* Z) {
     double x = d[lo] - mu, z = e[lo];
     for (int k = lo; k < hi; ++k) {
       // rotation G in plane (k, k+1) with c*x - s*z = r, s*x + c*z = 0
-      const double r = std::hypot(x, z);
+      const double r = fast_hypot(x, z);
       double c = 1.0, s = 0.0;
       if (r != 0.0) { c = x / r; s = -z / r; }
       if (k > lo) e[k - 1] = r;

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 #include "internal.h"
 
@@ -786,6 +787,25 @@ void Problem::spacetime_solve_batch(const std::vector<const LowRank*>& F, const 
 // Basis and projected problem of one prepared source whose pole solves are in
 // Wall (nx x r1 npol, overwritten): fin.Q (nx x q, M-orthonormal) and fin.Zp
 // (q x nt) with the space-time solution Q Zp.
+// f(0) .. f(n-1) on up to kHostThreads host threads (pure host work only:
+// no HIP calls and no exceptions inside f).
+static constexpr int kHostThreads = 4;
+template <class F>
+static void host_parallel(int n, F&& f) {
+  if (n <= 1) {
+    for (int i = 0; i < n; ++i) f(i);
+    return;
+  }
+  const int nt = std::min(n, kHostThreads);
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t)
+    th.emplace_back([&, t] {
+      for (int i = t; i < n; i += nt) f(i);
+    });
+  for (int i = 0; i < n; i += nt) f(i);
+  for (auto& x : th) x.join();
+}
+
 void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std::vector<StFin>& fins) {
   // 2. block-by-block M-orthonormalization of the pole solutions.  Block
   // Gram-Schmidt against Q in the M inner product, twice, with the block
@@ -840,10 +860,11 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
     proj_dev(q[j], Q, st_c_.as<double>(), q[j], kc, X, 1.0);
   };
   // eigenpairs of a block's Gram G (kc x kc, host) above thresh -> the
-  // orthonormalizing transform Tm (kc x kn)
-  auto svqb_host = [&](int kc, const double* G, double thresh, std::vector<double>& Tm) -> int {
+  // orthonormalizing transform Tm (kc x kn); -1 if the eigensolve failed.
+  // Pure host arithmetic: the sources' solves run on parallel host threads.
+  auto svqb_host = [](int kc, const double* G, double thresh, std::vector<double>& Tm) -> int {
     std::vector<double> Gw(G, G + (size_t)kc * kc), wv(kc, 0.0), Uv((size_t)kc * kc, 0.0);
-    if (!syev(kc, Gw.data(), kc, wv.data(), Uv.data())) fail(LRPOST_EBREAKDOWN, "basis Gram eigensolve");
+    if (!syev(kc, Gw.data(), kc, wv.data(), Uv.data())) return -1;
     std::vector<int> kk;
     for (int i = kc - 1; i >= 0; --i)
       if (wv[i] > thresh) kk.push_back(i);
@@ -853,8 +874,9 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
       for (int i = 0; i < kc; ++i) Tm[(size_t)c * kc + i] = Uv[(size_t)kk[c] * kc + i] / std::sqrt(wv[kk[c]]);
     return kn;
   };
-  std::vector<int> k1(nb, 0);
-  std::vector<double> Tm;
+  std::vector<int> k1(nb, 0), k2(nb, 0);
+  std::vector<double> ref(nb, 0.0);
+  std::vector<std::vector<double>> Tm(nb);
   for (int ip = 0; ip < npol; ++ip) {
     // stage 1: reference norms of the raw block, first sweep, Gram of the swept block
     for (int j = 0; j < nb; ++j) {
@@ -868,17 +890,20 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
       gram_dev(r1, W, r1, MW, Gd + slot(j, 1));
     }
     to_host(Gh.data(), Gd, Gh.size());
-    bool any = false;
     for (int j = 0; j < nb; ++j) {
       const int r1 = prs[j].r1;
-      k1[j] = 0;
-      if (r1 == 0) continue;
-      double ref = 0.0;
-      for (int c = 0; c < r1; ++c) ref = std::max(ref, Gh[slot(j, 0) + (size_t)c * r1 + c]);
-      if (!(ref > 0)) continue;
-      k1[j] = svqb_host(r1, Gh.data() + slot(j, 1), 1e-22 * ref, Tm);
+      ref[j] = 0.0;
+      for (int c = 0; c < r1; ++c) ref[j] = std::max(ref[j], Gh[slot(j, 0) + (size_t)c * r1 + c]);
+    }
+    host_parallel(nb, [&](int j) {
+      k1[j] = (prs[j].r1 > 0 && ref[j] > 0) ? svqb_host(prs[j].r1, Gh.data() + slot(j, 1), 1e-22 * ref[j], Tm[j]) : 0;
+    });
+    bool any = false;
+    for (int j = 0; j < nb; ++j) {
+      if (k1[j] < 0) fail(LRPOST_EBREAKDOWN, "basis Gram eigensolve");
       if (k1[j] == 0) continue;
-      proj(r1, Wb[j] + (size_t)ip * r1 * nx, Tm, k1[j], fins[j].W2.as<double>(), 0.0);
+      const int r1 = prs[j].r1;
+      proj(r1, Wb[j] + (size_t)ip * r1 * nx, Tm[j], k1[j], fins[j].W2.as<double>(), 0.0);
       any = true;
     }
     if (!any) continue;
@@ -891,13 +916,14 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
       gram_dev(k1[j], W2, k1[j], MW, Gd + slot(j, 0));
     }
     to_host(Gh.data(), Gd, Gh.size());
+    host_parallel(nb, [&](int j) { k2[j] = k1[j] > 0 ? svqb_host(k1[j], Gh.data() + slot(j, 0), 1e-8, Tm[j]) : 0; });
     for (int j = 0; j < nb; ++j) {
-      if (k1[j] == 0) continue;
-      const int kcols = svqb_host(k1[j], Gh.data() + slot(j, 0), 1e-8, Tm);
+      if (k2[j] < 0) fail(LRPOST_EBREAKDOWN, "basis Gram eigensolve");
+      const int kcols = k2[j];
       if (kcols == 0) continue;
       double* Q = fins[j].Q.as<double>();
       double* Qn = Q + (size_t)q[j] * nx;
-      proj(k1[j], fins[j].W2.as<double>(), Tm, kcols, Qn, 0.0);
+      proj(k1[j], fins[j].W2.as<double>(), Tm[j], kcols, Qn, 0.0);
       // extend Kt = Q^T tau K Q by the new columns (upper triangle suffices)
       const int qmax = prs[j].r1 * npol;
       apply_op(kcols, Qn, MW, Kop);
