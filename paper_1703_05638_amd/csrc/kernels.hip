@@ -902,118 +902,124 @@ int gram_chunks(long nrows, int m, int q) {
 }
 
 // ---------------------------------------------------------------------------
-// FP64 Gram on the matrix cores.  Workgroup (tm, tq, chunk) accumulates a
-// 64 x 64 output tile over its chunk of rows.  Rows are staged through LDS
-// 32 at a time (coalesced: 32 consecutive lanes read 32 consecutive rows of
-// one column), stored [column][row] so that each MFMA operand is one LDS
-// read per lane.  Each wave owns a 32 x 32 quarter of the tile as 2 x 2
-// blocks of v_mfma_f64_16x16x4f64: for the 16 x 4 operand lane l holds
-// element (l % 16, l / 16), for the 4 x 16 operand element (l / 16, l % 16),
-// and the 16 x 16 result element (l / 16 + 4 v, l % 16) in slot v.
+// FP64 Gram on the matrix cores.  Workgroup (tm, tq, chunk), 8 waves,
+// accumulates a (64 BM) x 64 output tile over its chunk of rows; with
+// BM = 4 the tile covers m <= 256, so each operand of the usual tall-skinny
+// products is read from memory once.  Rows are staged through LDS 16 at a
+// time (coalesced: 16 consecutive lanes read 16 consecutive rows, 128 bytes,
+// of one column), stored [column][row] so that each MFMA operand is one LDS
+// read per lane; the next stage is fetched into registers while the matrix
+// cores work on the current one.  The waves form a 4 x 2 grid; each owns
+// (16 BM) x 32 of the tile as BM x 2 blocks of v_mfma_f64_16x16x4f64: for
+// the 16 x 4 operand lane l holds element (l % 16, l / 16), for the 4 x 16
+// operand element (l / 16, l % 16), and the 16 x 16 result element
+// (l / 16 + 4 v, l % 16) in slot v.
 // ---------------------------------------------------------------------------
 typedef double gram_d4 __attribute__((ext_vector_type(4)));
-constexpr int MT = 64;  // output tile edge
-constexpr int MK = 32;  // rows per LDS stage
-constexpr int MG = 2;   // row groups of 4 waves per workgroup
+constexpr int GQ = 64;   // output tile width (q direction)
+constexpr int GK = 16;   // rows per LDS stage
+constexpr int GTH = 512;  // threads per workgroup
 
-// Two groups of four waves per workgroup take alternate 32-row stages of the
-// chunk, each with LDS tiles of its own; at the end the second group hands
-// its accumulators to the first through LDS.
-__global__ __launch_bounds__(256 * MG) void k_gram_mfma(long nrows, long rows_per_chunk, int m,
-                                                        const double* __restrict__ A, long lda, int q,
-                                                        const double* __restrict__ B, long ldb,
-                                                        double* __restrict__ part) {
-  __shared__ double As[MG][MT][MK + 1];
-  __shared__ double Bs[MG][MT][MK + 1];
+template <int BM>
+__global__ __launch_bounds__(GTH) void k_gram_mfma(long nrows, long rows_per_chunk, int m,
+                                                   const double* __restrict__ A, long lda, int q,
+                                                   const double* __restrict__ B, long ldb,
+                                                   double* __restrict__ part) {
+  constexpr int GM = 64 * BM;                 // output tile height (m direction)
+  constexpr int NC = GM + GQ;                 // staged columns per row
+  constexpr int NU = NC / (GTH / GK);         // columns per loading thread
+  __shared__ double S[NC][GK + 1];            // [column][row]: A columns, then B columns
   const int tm = blockIdx.x, tq = blockIdx.y, chunk = blockIdx.z;
-  const int grp = threadIdx.x >> 8, tid = threadIdx.x & 255;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wq = wave >> 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 3, wq = wave >> 2;
   const long r0 = (long)chunk * rows_per_chunk;
   const long r1 = min(nrows, r0 + rows_per_chunk);
-  gram_d4 acc[2][2];
+  gram_d4 acc[BM][2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < BM; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = gram_d4{0.0, 0.0, 0.0, 0.0};
-  const int lr = tid & 31, lc = tid >> 5;  // loader: row lr of columns lc, lc + 8, ...
-  double(*as)[MK + 1] = As[grp];
-  double(*bs)[MK + 1] = Bs[grp];
-  // every group runs the same number of stages (barriers are workgroup-wide)
-  const long nst = (r1 > r0) ? (r1 - r0 + MK - 1) / MK : 0;
-  const long nst_g = (nst + MG - 1) / MG;
-  // The next stage is fetched into registers while the matrix cores work on
-  // the current one.  Loads are unconditional (row and column indices clamped
-  // into range) so that all of a stage's loads are in flight together;
-  // out-of-range values are zeroed after.
-  double ra[MT / 8], rb[MT / 8];
+  const int lr = tid & (GK - 1), lc = tid / GK;  // loader: row lr of columns lc, lc + 32, ...
+  const long nst = (r1 > r0) ? (r1 - r0 + GK - 1) / GK : 0;
+  // column pointers of this thread's staged columns (clamped into range) and
+  // whether they are real columns
+  const double* cp[NU];
+  bool cok[NU];
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int c = lc + (GTH / GK) * u;
+    if (c < GM) {
+      const int ca = tm * GM + c;
+      cok[u] = ca < m;
+      cp[u] = A + (long)(ca < m ? ca : m - 1) * lda;
+    } else {
+      const int cb = tq * GQ + (c - GM);
+      cok[u] = cb < q;
+      cp[u] = B + (long)(cb < q ? cb : q - 1) * ldb;
+    }
+  }
+  // loads are unconditional (row clamped into the chunk) so that a stage's
+  // loads are in flight together; out-of-range values are scaled to zero
+  // (a select of a loaded value is compiled into a branch around the load)
+  double rv[NU];
   auto fetch = [&](long it) {
-    const long r = r0 + (it * MG + grp) * MK + lr;
+    const long r = r0 + it * GK + lr;
     const bool rin = r < r1;
     const long rc = rin ? r : r1 - 1;
 #pragma unroll
-    for (int u = 0; u < MT / 8; ++u) {
-      const int ca = tm * MT + lc + 8 * u, cb = tq * MT + lc + 8 * u;
-      const double va = A[(long)(ca < m ? ca : m - 1) * lda + rc];
-      const double vb = B[(long)(cb < q ? cb : q - 1) * ldb + rc];
-      ra[u] = (rin && ca < m) ? va : 0.0;
-      rb[u] = (rin && cb < q) ? vb : 0.0;
+    for (int u = 0; u < NU; ++u) {
+      const double v = cp[u][rc];
+      rv[u] = v * ((rin && cok[u]) ? 1.0 : 0.0);
     }
   };
-  if (nst_g > 0) fetch(0);
-  for (long it = 0; it < nst_g; ++it) {
+  if (nst > 0) fetch(0);
+  const int ci = lane & 15, ck = lane >> 4;
+  for (long it = 0; it < nst; ++it) {
 #pragma unroll
-    for (int u = 0; u < MT / 8; ++u) {
-      as[lc + 8 * u][lr] = ra[u];
-      bs[lc + 8 * u][lr] = rb[u];
-    }
+    for (int u = 0; u < NU; ++u) S[lc + (GTH / GK) * u][lr] = rv[u];
     __syncthreads();
-    if (it + 1 < nst_g) fetch(it + 1);
-    const int ci = lane & 15, ck = lane >> 4;
+    if (it + 1 < nst) fetch(it + 1);
 #pragma unroll
-    for (int kk = 0; kk < MK; kk += 4) {
-      const double a0 = as[wm * 32 + ci][kk + ck], a1 = as[wm * 32 + 16 + ci][kk + ck];
-      const double b0 = bs[wq * 32 + ci][kk + ck], b1 = bs[wq * 32 + 16 + ci][kk + ck];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    for (int kk = 0; kk < GK; kk += 4) {
+      double bf[2];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bf[b] = S[GM + wq * 32 + 16 * b + ci][kk + ck];
+#pragma unroll
+      for (int a = 0; a < BM; ++a) {
+        const double af = S[wm * 16 * BM + 16 * a + ci][kk + ck];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf[b], acc[a][b], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
-  // group 1 passes its accumulators to group 0 through the (now idle) LDS tiles
-  double* red = &As[0][0][0];  // 256 threads x 16 values = 4096 doubles <= MG * MT * (MK + 1)
-  if (grp == 1) {
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) red[((a * 2 + b) * 4 + v) * 256 + tid] = acc[a][b][v];
-  }
-  __syncthreads();
-  if (grp != 0) return;
   // partial layout: [chunk] column-major m x q
   double* P = part + (long)chunk * m * q;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < BM; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = tm * MT + wm * 32 + 16 * a + (lane >> 4) + 4 * v;
-        const int j = tq * MT + wq * 32 + 16 * b + (lane & 15);
-        if (i < m && j < q) P[(long)j * m + i] = acc[a][b][v] + red[((a * 2 + b) * 4 + v) * 256 + tid];
+        const int i = tm * GM + wm * 16 * BM + 16 * a + (lane >> 4) + 4 * v;
+        const int j = tq * GQ + wq * 32 + 16 * b + (lane & 15);
+        if (i < m && j < q) P[(long)j * m + i] = acc[a][b][v];
       }
 }
 
+// tile height 64 BM: the smallest that covers m, at most 256
+static int gram_bm(int m) { return m <= 64 ? 1 : m <= 128 ? 2 : m <= 192 ? 3 : 4; }
+
 int gram_chunks_mfma(long nrows, int m, int q) {
-  // about 512 workgroups of 8 waves in stage 1, at least 512 rows per chunk
-  const long tiles = (long)((m + MT - 1) / MT) * ((q + MT - 1) / MT);
+  // about 512 workgroups, at least 128 rows per chunk, and per-chunk partial
+  // products of at most about 35% of the operand bytes
+  const int gm = 64 * gram_bm(m);
+  const long tiles = (long)((m + gm - 1) / gm) * ((q + GQ - 1) / GQ);
   long c = 512 / (tiles > 0 ? tiles : 1);
-  const long cmax = (nrows + 511) / 512;
-  if (c > cmax) c = cmax;
-  if (c > 512) c = 512;
+  const long cmax = (nrows + 127) / 128;
+  const long cpart = (long)(0.35 * (double)(m + q) * (double)nrows / ((double)m * q)) + 1;
+  c = std::min(c, std::min(cmax, cpart));
+  if (c > 1024) c = 1024;
   if (c < 1) c = 1;
   return (int)c;
 }
@@ -1030,14 +1036,21 @@ void gram(hipStream_t st, long nrows, int m, const T* A, long lda, int q, const 
   const long count = (long)m * q;
   hipLaunchKernelGGL(k_sum_partials, dim3((count + SP_X - 1) / SP_X), dim3(SP_X * SP_Y), 0, st, nchunk, count, part, C);
 }
+
 void gram_mfma_partials(hipStream_t st, long nrows, int m, const double* A, long lda, int q, const double* B,
                         long ldb, double* part) {
   if (m <= 0 || q <= 0) return;
   const int nchunk = gram_chunks_mfma(nrows, m, q);
   long rpc = (nrows + nchunk - 1) / nchunk;
-  rpc = ((rpc + MK - 1) / MK) * MK;
-  dim3 grd((m + MT - 1) / MT, (q + MT - 1) / MT, nchunk);
-  hipLaunchKernelGGL(k_gram_mfma, grd, dim3(256 * MG), 0, st, nrows, rpc, m, A, lda, q, B, ldb, part);
+  rpc = ((rpc + GK - 1) / GK) * GK;
+  const int bm = gram_bm(m), gm = 64 * bm;
+  dim3 grd((m + gm - 1) / gm, (q + GQ - 1) / GQ, nchunk);
+  switch (bm) {
+    case 1: hipLaunchKernelGGL((k_gram_mfma<1>), grd, dim3(GTH), 0, st, nrows, rpc, m, A, lda, q, B, ldb, part); break;
+    case 2: hipLaunchKernelGGL((k_gram_mfma<2>), grd, dim3(GTH), 0, st, nrows, rpc, m, A, lda, q, B, ldb, part); break;
+    case 3: hipLaunchKernelGGL((k_gram_mfma<3>), grd, dim3(GTH), 0, st, nrows, rpc, m, A, lda, q, B, ldb, part); break;
+    default: hipLaunchKernelGGL((k_gram_mfma<4>), grd, dim3(GTH), 0, st, nrows, rpc, m, A, lda, q, B, ldb, part);
+  }
 }
 
 void sum_partials(hipStream_t st, int nchunk, long count, const double* part, double* C) {

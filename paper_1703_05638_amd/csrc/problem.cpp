@@ -249,10 +249,14 @@ void Problem::to_device(double* dst, const double* src, size_t count) {
 }
 
 void Problem::to_host_bytes(void* dst, const void* src, size_t bytes) {
-  if (bytes > 0 && !readback_) LRP_HIP(hipHostMalloc(&readback_, kReadbackBytes, hipHostMallocDefault));
+  if (bytes == 0) {
+    sync();
+    return;
+  }
+  if (!readback_) LRP_HIP(hipHostMalloc(&readback_, kReadbackBytes, hipHostMallocDefault));
   const char* s = static_cast<const char*>(src);
   char* d = static_cast<char*>(dst);
-  while (bytes > 0) {
+  while (bytes > 0) {  // each chunk's sync also drains the stream
     const size_t chunk = std::min(bytes, kReadbackBytes);
     LRP_HIP(hipMemcpyAsync(readback_, s, chunk, hipMemcpyDeviceToHost, st));
     sync();
@@ -261,7 +265,6 @@ void Problem::to_host_bytes(void* dst, const void* src, size_t bytes) {
     d += chunk;
     bytes -= chunk;
   }
-  sync();
 }
 
 void Problem::to_host_block(double* dst, const double* src, int rows, int cols, long ld) {
@@ -1089,37 +1092,47 @@ void Problem::st_truncate(std::vector<StFin>& fins, const std::vector<LowRank*>&
   dense->syevd_batched(g, G, g, (long)gsz, wg, g, na, eig_work_);
   std::vector<double> w((size_t)g * na);
   to_host(w.data(), wg, w.size());
+  // ranks first, then the spatial factors on the device and all temporal
+  // factors gathered for one read-back
+  std::vector<int> ry(na), boff(na + 1, 0);
+  for (int a = 0; a < na; ++a) {
+    std::vector<double> sv(g);
+    for (int c = 0; c < g; ++c) sv[c] = std::sqrt(std::max(w[(size_t)a * g + g - 1 - c], 0.0));
+    ry[a] = truncation_rank(sv, desc.trunc_tol, desc.rank_cap, &tail);
+    boff[a + 1] = boff[a] + ry[a];
+  }
+  st_c_.ensure(sizeof(double) * std::max<size_t>(1, (size_t)nt * boff[na] + (size_t)qb * desc.rank_cap));
+  double* Bd = st_c_.as<double>();                 // nt x (sum of ranks): temporal factors
+  double* Cm = Bd + (size_t)nt * boff[na];         // q x ry scratch
   for (int a = 0; a < na; ++a) {
     const StFin& f = fins[act[a]];
     LowRank& y = *Y[act[a]];
-    const int q = f.q;
+    const int q = f.q, r = ry[a];
     const double* Zp = f.Zp.as<double>();
-    std::vector<double> sv(g);
-    for (int c = 0; c < g; ++c) sv[c] = std::sqrt(std::max(w[(size_t)a * g + g - 1 - c], 0.0));
-    const int ry = truncation_rank(sv, desc.trunc_tol, desc.rank_cap, &tail);
-    y.resize(nx, nt, ry);
-    if (ry == 0) continue;
-    // eigenvectors of the kept directions are the last ry columns
-    const double* Ek = G + gsz * a + (size_t)(g - ry) * g;
-    std::vector<double> B2((size_t)nt * ry);
-    st_c_.ensure(sizeof(double) * (size_t)std::max(q, nt) * ry);
+    y.resize(nx, nt, r);
+    if (r == 0) continue;
+    // eigenvectors of the kept directions are the last r columns
+    const double* Ek = G + gsz * a + (size_t)(g - r) * g;
+    double* Ba = Bd + (size_t)nt * boff[a];
     if (right) {
       // Y = Q (Zp V_r) V_r^T
-      double* Cm = st_c_.as<double>();  // q x ry
-      dense->gemm(false, false, q, ry, nt, 1.0, Zp, q, Ek, nt, 0.0, Cm, q);
-      proj_dev(q, f.Q.as<double>(), Cm, q, ry, y.a(), 0.0);
-      to_host(B2.data(), Ek, (size_t)nt * ry);
+      dense->gemm(false, false, q, r, nt, 1.0, Zp, q, Ek, nt, 0.0, Cm, q);
+      proj_dev(q, f.Q.as<double>(), Cm, q, r, y.a(), 0.0);
+      LRP_HIP(hipMemcpyAsync(Ba, Ek, sizeof(double) * (size_t)nt * r, hipMemcpyDeviceToDevice, st));
     } else {
       // Y = Q U_r (Zp^T U_r)^T, U_r the first q rows of the padded eigenvectors
-      double* Vt = st_c_.as<double>();  // nt x ry
-      dense->gemm(true, false, nt, ry, q, 1.0, Zp, q, Ek, g, 0.0, Vt, nt);
-      proj_dev(q, f.Q.as<double>(), Ek, g, ry, y.a(), 0.0);
-      to_host(B2.data(), Vt, (size_t)nt * ry);
+      dense->gemm(true, false, nt, r, q, 1.0, Zp, q, Ek, g, 0.0, Ba, nt);
+      proj_dev(q, f.Q.as<double>(), Ek, g, r, y.a(), 0.0);
     }
-    store_B(y, B2, ry);
+  }
+  std::vector<double> Bh((size_t)nt * boff[na]);
+  to_host(Bh.data(), Bd, Bh.size());
+  for (int a = 0; a < na; ++a) {
+    if (ry[a] == 0) continue;
+    std::vector<double> B2(Bh.begin() + (size_t)nt * boff[a], Bh.begin() + (size_t)nt * boff[a + 1]);
+    store_B(*Y[act[a]], B2, ry[a]);
   }
   stats.last_tail = tail;
-  sync();
 }
 
 // G x = alpha^{-1} (K+M)^{-1} M P1 P2^T (precond) or H_mis x = tau M P1 P2^T (misfit),

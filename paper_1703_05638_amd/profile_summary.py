@@ -31,7 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = {
     "k_cheb": ("void k_cheb(", "template void mg_smooth_step<float>"),
     "k_mg": ("__device__ inline void strip_of(", "template void mg_up<float>"),
-    "k_gram": ("constexpr int MT = 64;", "void sum_partials("),
+    "k_gram": ("// FP64 Gram on the matrix cores.", "void sum_partials("),
 }
 
 
