@@ -904,7 +904,7 @@ int gram_chunks(long nrows, int m, int q) {
 // ---------------------------------------------------------------------------
 // FP64 Gram on the matrix cores.  Workgroup (tm, tq, chunk), 8 waves,
 // accumulates a (64 BM) x 64 output tile over its chunk of rows; with
-// BM = 4 the tile covers m <= 256, so each operand of the usual tall-skinny
+// BM = 3 the tile covers m <= 192, so each operand of the usual tall-skinny
 // products is read from memory once.  Rows are staged through LDS 16 at a
 // time (coalesced: 16 consecutive lanes read 16 consecutive rows, 128 bytes,
 // of one column), stored [column][row] so that each MFMA operand is one LDS
@@ -1007,8 +1007,10 @@ __global__ __launch_bounds__(GTH) void k_gram_mfma(long nrows, long rows_per_chu
       }
 }
 
-// tile height 64 BM: the smallest that covers m, at most 256
-static int gram_bm(int m) { return m <= 64 ? 1 : m <= 128 ? 2 : m <= 192 ? 3 : 4; }
+// tile height 64 BM: the smallest that covers m, at most 192 (the 256-row
+// tile needs 146 registers per lane, which leaves one workgroup per CU; wider
+// products take several tiles)
+static int gram_bm(int m) { return m <= 64 ? 1 : m <= 128 ? 2 : 3; }
 
 int gram_chunks_mfma(long nrows, int m, int q) {
   // about 512 workgroups, at least 128 rows per chunk, and per-chunk partial
@@ -1048,8 +1050,7 @@ void gram_mfma_partials(hipStream_t st, long nrows, int m, const double* A, long
   switch (bm) {
     case 1: hipLaunchKernelGGL((k_gram_mfma<1>), grd, dim3(GTH), 0, st, nrows, rpc, m, A, lda, q, B, ldb, part); break;
     case 2: hipLaunchKernelGGL((k_gram_mfma<2>), grd, dim3(GTH), 0, st, nrows, rpc, m, A, lda, q, B, ldb, part); break;
-    case 3: hipLaunchKernelGGL((k_gram_mfma<3>), grd, dim3(GTH), 0, st, nrows, rpc, m, A, lda, q, B, ldb, part); break;
-    default: hipLaunchKernelGGL((k_gram_mfma<4>), grd, dim3(GTH), 0, st, nrows, rpc, m, A, lda, q, B, ldb, part);
+    default: hipLaunchKernelGGL((k_gram_mfma<3>), grd, dim3(GTH), 0, st, nrows, rpc, m, A, lda, q, B, ldb, part);
   }
 }
 
