@@ -266,7 +266,9 @@ class Problem {
   std::vector<double> mg_param_h_, op_w_h_;
   std::vector<double> tmp_h_;
   template <typename T>
-  void vcycle_zero(int ncols, const T* B, T* X);
+  void vcycle_zero(int ncols, const T* B, T* X, bool accumulate = false);  // accumulate: X += V(B), fused path only
+  // the V-cycle runs through the level-fused kernels (which can accumulate)
+  bool vcycle_fused() const { return mg_fused && lds_level > 0 && lv[0].n <= kMgFusedMaxN; }
   // cycles V-cycles in float32 on nx x ncols float data (residual correction between cycles)
   void mg_cycles_f32(int ncols, const float* B, float* X, const std::vector<ShiftCoef>& neg, int cycles);
   DevMem mg_work_f_, mg_f_;

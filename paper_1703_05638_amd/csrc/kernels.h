@@ -26,14 +26,14 @@ template <typename T>
 void mg_prolong_add(hipStream_t st, int n, int ncols, const T* E, long ldc, const T* Xi, T* Xo, long ld);
 // Level-fused passes for n <= kMgFusedMaxN with kMgFusedNu smoother steps:
 // down: X = smoothing from zero for A X = B, Bc = P^T (B - A X);
-// up: Xo = smoothing from Xi + P E.  Xo must not alias Xi.
+// up: Xo = smoothing from Xi + P E (acc: Xo += that).  Xo must not alias Xi.
 constexpr int kMgFusedNu = 3;
 constexpr int kMgFusedMaxN = 1023;
 template <typename T>
 void mg_down(hipStream_t st, int n, int ncols, const T* B, long ld, T* X, T* Bc, long ldc, const double* P);
 template <typename T>
 void mg_up(hipStream_t st, int n, int ncols, const T* Xi, const T* E, long ldc, const T* B, long ld, T* Xo,
-           const double* P);
+           const double* P, bool acc = false);
 template <typename T>
 void mg_coarse_lds(hipStream_t st, int n0, int nlev, int ncols, const T* B, long ldb, T* X, long ldx,
                    const double* Pc, int nu1, int nu2);

@@ -540,7 +540,7 @@ __global__ __launch_bounds__(TW) void k_mg_down(int n, int nstrip, const T* __re
   else mg_down_body<T, TW, S, NU, false>(xs, n, col, strip, B, ld, Xo, Bc, ldc, P);
 }
 
-template <typename T, int TW, int S, int NU, bool INNER>
+template <typename T, int TW, int S, int NU, bool INNER, bool ACC>
 __device__ inline void mg_up_body(T* xs, int n, int col, int strip, const T* __restrict__ Xi,
                                   const T* __restrict__ E, long ldc, const T* __restrict__ B, long ld,
                                   T* __restrict__ Xo, const double* __restrict__ P) {
@@ -596,6 +596,23 @@ __device__ inline void mg_up_body(T* xs, int n, int col, int strip, const T* __r
   strip_step<T, TW, R, 3, R - 4, INNER>(x0, x1, x1, bv, xs, i, n, jb, wc, we, wk, (T)pc[8], (T)pc[9]);
   const T(&x)[R] = x1;
   T* xo = Xo + (long)col * ld;
+  if (ACC) {
+    // Xo += x: all old values are read (clamped rows and columns) before any store
+    T old[S];
+    const unsigned ic = i < n ? i : n - 1;
+#pragma unroll
+    for (int r = NU; r < NU + S; ++r) {
+      const int j = jb + r;
+      const int jc = INNER ? j : (j >= n ? n - 1 : j);
+      old[r - NU] = (xo + (unsigned)(jc * n))[ic];
+    }
+#pragma unroll
+    for (int r = NU; r < NU + S; ++r) {
+      const int j = jb + r;
+      if (i < n && (INNER || j < n)) (xo + (unsigned)(j * n))[(unsigned)i] = old[r - NU] + x[r];
+    }
+    return;
+  }
 #pragma unroll
   for (int r = NU; r < NU + S; ++r) {
     const int j = jb + r;
@@ -603,7 +620,7 @@ __device__ inline void mg_up_body(T* xs, int n, int col, int strip, const T* __r
   }
 }
 
-template <typename T, int TW, int S, int NU>
+template <typename T, int TW, int S, int NU, bool ACC>
 __global__ __launch_bounds__(TW) void k_mg_up(int n, int nstrip, const T* __restrict__ Xi, const T* __restrict__ E,
                                               long ldc, const T* __restrict__ B, long ld, T* __restrict__ Xo,
                                               const double* __restrict__ P) {
@@ -618,8 +635,8 @@ __global__ __launch_bounds__(TW) void k_mg_up(int n, int nstrip, const T* __rest
     xs[r * LP + TW + 1] = T(0);
   }
   const int jb = strip * S - NU;
-  if (jb >= 0 && jb + R <= n) mg_up_body<T, TW, S, NU, true>(xs, n, col, strip, Xi, E, ldc, B, ld, Xo, P);
-  else mg_up_body<T, TW, S, NU, false>(xs, n, col, strip, Xi, E, ldc, B, ld, Xo, P);
+  if (jb >= 0 && jb + R <= n) mg_up_body<T, TW, S, NU, true, ACC>(xs, n, col, strip, Xi, E, ldc, B, ld, Xo, P);
+  else mg_up_body<T, TW, S, NU, false, ACC>(xs, n, col, strip, Xi, E, ldc, B, ld, Xo, P);
 }
 
 // Strip height per precision and row width: as tall as the register budget
@@ -640,11 +657,15 @@ static void launch_down(hipStream_t st, int n, int ncols, const T* B, long ld, T
 
 template <typename T, int TW>
 static void launch_up(hipStream_t st, int n, int ncols, const T* Xi, const T* E, long ldc, const T* B, long ld,
-                      T* Xo, const double* P) {
+                      T* Xo, const double* P, bool acc) {
   constexpr int S = strip_rows<T, TW>();
   const int nstrip = (n + S - 1) / S;
-  hipLaunchKernelGGL((k_mg_up<T, TW, S, kMgFusedNu>), dim3(nstrip * ncols), dim3(TW), 0, st, n, nstrip, Xi, E, ldc,
-                     B, ld, Xo, P);
+  if (acc)
+    hipLaunchKernelGGL((k_mg_up<T, TW, S, kMgFusedNu, true>), dim3(nstrip * ncols), dim3(TW), 0, st, n, nstrip, Xi,
+                       E, ldc, B, ld, Xo, P);
+  else
+    hipLaunchKernelGGL((k_mg_up<T, TW, S, kMgFusedNu, false>), dim3(nstrip * ncols), dim3(TW), 0, st, n, nstrip, Xi,
+                       E, ldc, B, ld, Xo, P);
 }
 
 template <typename T>
@@ -658,19 +679,19 @@ void mg_down(hipStream_t st, int n, int ncols, const T* B, long ld, T* X, T* Bc,
 
 template <typename T>
 void mg_up(hipStream_t st, int n, int ncols, const T* Xi, const T* E, long ldc, const T* B, long ld, T* Xo,
-           const double* P) {
-  if (n < 64) launch_up<T, 64>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P);
-  else if (n < 128) launch_up<T, 128>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P);
-  else if (n < 256) launch_up<T, 256>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P);
-  else if (n < 512) launch_up<T, 512>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P);
-  else launch_up<T, 1024>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P);
+           const double* P, bool acc) {
+  if (n < 64) launch_up<T, 64>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P, acc);
+  else if (n < 128) launch_up<T, 128>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P, acc);
+  else if (n < 256) launch_up<T, 256>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P, acc);
+  else if (n < 512) launch_up<T, 512>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P, acc);
+  else launch_up<T, 1024>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P, acc);
 }
 template void mg_down<double>(hipStream_t, int, int, const double*, long, double*, double*, long, const double*);
 template void mg_down<float>(hipStream_t, int, int, const float*, long, float*, float*, long, const double*);
 template void mg_up<double>(hipStream_t, int, int, const double*, const double*, long, const double*, long, double*,
-                            const double*);
+                            const double*, bool);
 template void mg_up<float>(hipStream_t, int, int, const float*, const float*, long, const float*, long, float*,
-                           const double*);
+                           const double*, bool);
 
 // ---------------------------------------------------------------------------
 // Coarse levels in LDS: one workgroup per column runs a full V-cycle from the

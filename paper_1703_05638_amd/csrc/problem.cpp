@@ -349,7 +349,7 @@ void Problem::upload_mg_params(const std::vector<ShiftCoef>& ab) {
 // between the level's x and t buffers, writing each iterate over the one two
 // steps back, so that with an odd step count the result lands in x.
 template <typename T>
-void Problem::vcycle_zero(int ncols, const T* B, T* X) {
+void Problem::vcycle_zero(int ncols, const T* B, T* X, bool accumulate) {
   const int L = (int)lv.size();
   const double* P = mg_param_.as<double>();
   auto prm = [&](int l) { return P + (size_t)l * ncols * kMgStride; };
@@ -370,7 +370,7 @@ void Problem::vcycle_zero(int ncols, const T* B, T* X) {
   auto xw = [&](int l) { return base + off[l]; };
   auto bw = [&](int l) { return base + off[l] + (size_t)lv[l].nx * ncols; };
   auto tw = [&](int l) { return base + off[l] + 2 * (size_t)lv[l].nx * ncols; };
-  if (mg_fused && lv[0].n <= kMgFusedMaxN) {
+  if (vcycle_fused()) {
     static_assert(kMgNu == kMgFusedNu, "fused kernels take the smoother's step count");
     // down: level l pre-smoothes into its t buffer and writes the coarse
     // right-hand side; up: x_l = smoothing from t_l + P x_{l+1}
@@ -388,8 +388,9 @@ void Problem::vcycle_zero(int ncols, const T* B, T* X) {
       const T* b = l == 0 ? B : bw(l);
       const T* t = l == 0 ? base : tw(l);
       T* x = l == 0 ? X : xw(l);
-      timed(LRPOST_KERNEL_MG_UP, sizeof(T) * ((double)nl * nl * 3 + (double)nc * nc) * ncols,
-            [&] { mg_up<T>(st, nl, ncols, t, xw(l + 1), lv[l + 1].nx, b, lv[l].nx, x, prm(l)); });
+      const bool acc = accumulate && l == 0;
+      timed(LRPOST_KERNEL_MG_UP, sizeof(T) * ((double)nl * nl * (acc ? 4 : 3) + (double)nc * nc) * ncols,
+            [&] { mg_up<T>(st, nl, ncols, t, xw(l + 1), lv[l + 1].nx, b, lv[l].nx, x, prm(l), acc); });
     }
     return;
   }
@@ -500,8 +501,12 @@ void Problem::mg_cycles_f32(int ncols, const float* B, float* X, const std::vect
   to_device(op_w_.as<double>(), op_w_h_.data(), op_w_h_.size());
   for (int cyc = 1; cyc < cycles; ++cyc) {
     stencil<float>(st, n, ncols, X, nx, R, nx, B, nx, op_w_.as<double>());  // R = B - A X
-    vcycle_zero<float>(ncols, R, E);
-    axpby<float>(st, nx, ncols, E, nx, X, nx, 1.0, 1.0);
+    if (vcycle_fused()) {
+      vcycle_zero<float>(ncols, R, X, true);  // X += V(R) in the finest up kernel
+    } else {
+      vcycle_zero<float>(ncols, R, E);
+      axpby<float>(st, nx, ncols, E, nx, X, nx, 1.0, 1.0);
+    }
   }
 }
 
@@ -549,8 +554,12 @@ void Problem::mg_solve(int ncols, const double* B, double* X, const std::vector<
   double* E = R + blk;
   for (int cyc = 1; cyc < cycles; ++cyc) {
     apply_op(ncols, X, R, neg, B, &one);
-    vcycle_zero<double>(ncols, R, E);
-    axpby<double>(st, nx, ncols, E, nx, X, nx, 1.0, 1.0);
+    if (vcycle_fused()) {
+      vcycle_zero<double>(ncols, R, X, true);  // X += V(R) in the finest up kernel
+    } else {
+      vcycle_zero<double>(ncols, R, E);
+      axpby<double>(st, nx, ncols, E, nx, X, nx, 1.0, 1.0);
+    }
   }
   LRP_HIP(hipGetLastError());
 }
@@ -973,7 +982,7 @@ void Problem::st_solve_projected(const StPrep& pr, int q, StFin& fin) {
   double* P2 = P1 + (size_t)q * q;
   double* Gsm = P2 + (size_t)q * q;         // Gram for the truncation (max(q, nt)^2)
   double* Gt = Gsm + (size_t)gmax * gmax;   // max(q, nt) eigenvalues
-  // A = (I + Kt)^{-1} by the Newton-Schulz iteration X <- 2X - X (I + Kt) X
+  // A = (I + Kt)^{-1} by the Newton-Schulz iteration X <- X (2I - (I + Kt) X)
   // from X_0 = 2 / (1 + L) I: with Q M-orthonormal the eigenvalues of
   // I + Kt lie in [1, L], L = 1 + tau lambda_max(M^{-1} K), so the error
   // I - (I + Kt) X_j has spectral radius ((L - 1) / (L + 1))^(2^j) and the
@@ -992,9 +1001,9 @@ void Problem::st_solve_projected(const StPrep& pr, int q, StFin& fin) {
     LRP_HIP(hipMemsetAsync(Xa, 0, sizeof(double) * (size_t)q * q, st));
     add_diag(st, q, Xa, q, 2.0 / (1.0 + ns_bound_));
     for (int it = 0; it < ns_iters_; ++it) {
-      dense->gemm(false, false, q, q, q, 1.0, Apd, q, Xa, q, 0.0, T, q);  // T = (I + Kt) X
-      LRP_HIP(hipMemcpyAsync(Xn, Xa, sizeof(double) * (size_t)q * q, hipMemcpyDeviceToDevice, st));
-      dense->gemm(false, false, q, q, q, -1.0, Xa, q, T, q, 2.0, Xn, q);  // Xn = 2X - X T
+      dense->gemm(false, false, q, q, q, -1.0, Apd, q, Xa, q, 0.0, T, q);  // T = 2I - (I + Kt) X
+      add_diag(st, q, T, q, 2.0);
+      dense->gemm(false, false, q, q, q, 1.0, Xa, q, T, q, 0.0, Xn, q);  // Xn = X T
       std::swap(Xa, Xn);
     }
     if (Xa != Ainv)
