@@ -875,6 +875,25 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
   // orthonormalizing transform Tm (kc x kn); -1 if the eigensolve failed.
   // Pure host arithmetic: the sources' solves run on parallel host threads.
   auto svqb_host = [](int kc, const double* G, double thresh, std::vector<double>& Tm) -> int {
+    // Fast path, Tm = R^{-1} from the Cholesky factor G = R^T R, taken when
+    // the block is safely full-rank and well conditioned: lambda_min(G) =
+    // 1 / ||R^{-1}||_2^2 >= 1 / ||R^{-1}||_F^2 = 1 / f, so f < 1 / (100 thresh)
+    // means every eigenvalue exceeds 100 thresh (the eigen-based transform
+    // would keep every column; W R^{-1} is an M-orthonormal basis of the same
+    // span), and f max_i G_ii < 1e12 bounds the condition number.  Otherwise
+    // the eigen-based transform below.
+    {
+      std::vector<double> R((size_t)kc * kc);
+      double gmax = 0.0;
+      for (int i = 0; i < kc; ++i) gmax = std::max(gmax, G[(size_t)i * kc + i]);
+      if (cholesky_upper(kc, G, kc, R.data())) {
+        Tm.assign((size_t)kc * kc, 0.0);
+        upper_inverse(kc, R.data(), Tm.data());
+        double f = 0.0;
+        for (double x : Tm) f += x * x;
+        if (std::isfinite(f) && 100.0 * thresh * f < 1.0 && f * gmax < 1e12) return kc;
+      }
+    }
     std::vector<double> Gw(G, G + (size_t)kc * kc), wv(kc, 0.0), Uv((size_t)kc * kc, 0.0);
     if (!syev(kc, Gw.data(), kc, wv.data(), Uv.data())) return -1;
     std::vector<int> kk;
