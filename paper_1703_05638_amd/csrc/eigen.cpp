@@ -19,6 +19,7 @@
 // spatial factors touch nx-sized data.
 #include <algorithm>
 #include <chrono>
+#include <optional>
 #include <cmath>
 #include <cstdio>
 #include <numeric>
@@ -69,6 +70,7 @@ class SharedBasis {
   int used = 0, all_cap = 0;
   std::vector<int> off, rk;
   DevMem work1, work2, work3, wev, eye, eye_nt;
+  DevMem ipw, ipo;  // inner products: Gram pairs, row-wise dot products
 
   int size() const { return (int)off.size(); }
 
@@ -257,7 +259,8 @@ class SharedBasis {
   // Truncate a dense core S (rows x nt, leading dimension lds) to rank <= cap
   // at relative Frobenius tolerance tol.  Below 1e-7 the SVD runs on the host
   // by one-sided Jacobi (relative accuracy of small singular values);
-  // otherwise through the eigenpairs of S^T S on the device.
+  // otherwise through the eigenpairs of the smaller of S S^T and S^T S on
+  // the device.
   CVec truncate_core(const double* S, int rows, int lds, double tol, int cap) {
     return std::move(truncate_cores(S, 1, 0, rows, lds, tol, cap)[0]);
   }
@@ -292,31 +295,42 @@ class SharedBasis {
       P->sync();
       return outs;
     }
-    const size_t gsz = (size_t)nt * nt;
-    work3.ensure(sizeof(double) * (gsz * count + (size_t)nt * count + 64));
+    // Gram matrix of the smaller side: S S^T (rows x rows) when rows < nt,
+    // else S^T S (nt x nt)
+    const bool left = rows < nt;
+    const int g = left ? rows : nt;
+    const size_t gsz = (size_t)g * g;
+    work3.ensure(sizeof(double) * (gsz * count + (size_t)g * count + 64));
     double* Gt = work3.as<double>();
     double* w = Gt + gsz * count;
-    if (count == 1)
-      P->dense->gemm(true, false, nt, nt, rows, 1.0, S, lds, S, lds, 0.0, Gt, nt);
-    else
-      P->dense->gemm_strided_batched(true, false, nt, nt, rows, 1.0, S, lds, stride, S, lds, stride, 0.0, Gt, nt,
+    if (left)
+      P->dense->gemm_strided_batched(false, true, rows, rows, nt, 1.0, S, lds, stride, S, lds, stride, 0.0, Gt, g,
                                      (long)gsz, count);
-    P->dense->syevd_batched(nt, Gt, nt, (long)gsz, w, nt, count, wev);
-    std::vector<double> wh((size_t)nt * count);
+    else
+      P->dense->gemm_strided_batched(true, false, nt, nt, rows, 1.0, S, lds, stride, S, lds, stride, 0.0, Gt, g,
+                                     (long)gsz, count);
+    P->dense->syevd_batched(g, Gt, g, (long)gsz, w, g, count, wev);
+    std::vector<double> wh((size_t)g * count);
     P->to_host(wh.data(), w, wh.size());
     for (int b = 0; b < count; ++b) {
       CVec& out = outs[b];
-      sv.assign(nt, 0.0);
-      for (int c = 0; c < nt; ++c) sv[c] = std::sqrt(std::max(wh[(size_t)b * nt + nt - 1 - c], 0.0));
+      sv.assign(g, 0.0);
+      for (int c = 0; c < g; ++c) sv[c] = std::sqrt(std::max(wh[(size_t)b * g + g - 1 - c], 0.0));
       const int r = truncation_rank(sv, tol, cap, &tail);
       out.r = r;
       out.C.ensure(sizeof(double) * (size_t)rows * std::max(r, 1));
       out.B.ensure(sizeof(double) * (size_t)nt * std::max(r, 1));
-      if (r > 0) {
-        // eigenvectors of the r largest eigenvalues
-        const double* Vr = Gt + gsz * b + (size_t)(nt - r) * nt;
-        P->dense->gemm(false, false, rows, r, nt, 1.0, S + b * stride, lds, Vr, nt, 0.0, out.C.as<double>(), rows);
-        LRP_HIP(hipMemcpyAsync(out.B.p, Vr, sizeof(double) * (size_t)nt * r, hipMemcpyDeviceToDevice, P->st));
+      if (r == 0) continue;
+      // eigenvectors of the r largest eigenvalues
+      const double* Er = Gt + gsz * b + (size_t)(g - r) * g;
+      if (left) {
+        // S ~ U_r U_r^T S: C = U_r, B = S^T U_r
+        LRP_HIP(hipMemcpyAsync(out.C.p, Er, sizeof(double) * (size_t)rows * r, hipMemcpyDeviceToDevice, P->st));
+        P->dense->gemm(true, false, nt, r, rows, 1.0, S + b * stride, lds, Er, g, 0.0, out.B.as<double>(), nt);
+      } else {
+        // S ~ S V_r V_r^T: C = S V_r, B = V_r
+        P->dense->gemm(false, false, rows, r, nt, 1.0, S + b * stride, lds, Er, g, 0.0, out.C.as<double>(), rows);
+        LRP_HIP(hipMemcpyAsync(out.B.p, Er, sizeof(double) * (size_t)nt * r, hipMemcpyDeviceToDevice, P->st));
       }
     }
     P->sync();
@@ -352,44 +366,94 @@ class SharedBasis {
     }
   }
 
-  // <v_k, x>_P for every stored vector k.
-  std::vector<double> inner_all(const CVec& x) {
-    std::vector<double> c(size(), 0.0);
-    if (x.r == 0 || used == 0) return c;
-    work3.ensure(sizeof(double) * (size_t)used * x.r * 2);
-    double* G1 = work3.as<double>();
-    double* G2 = G1 + (size_t)used * x.r;
-    const int sm = std::min(x.s, s);
-    P->dense->gemm(true, false, used, x.r, sm, 1.0, C_all.as<double>(), s_cap, x.C.as<double>(), x.s, 0.0, G1, used);
-    P->dense->gemm(true, false, used, x.r, nt, 1.0, B_all.as<double>(), nt, x.B.as<double>(), nt, 0.0, G2, used);
-    std::vector<double> h((size_t)used * x.r * 2);
-    P->to_host(h.data(), G1, h.size());
-    const size_t half = (size_t)used * x.r;
-    for (int k = 0; k < size(); ++k) {
-      double acc = 0.0;
-      for (int j = 0; j < x.r; ++j)
-        for (int c2 = 0; c2 < rk[k]; ++c2) {
-          const size_t idx = (size_t)j * used + off[k] + c2;
-          acc += h[idx] * h[half + idx];
-        }
-      c[k] = scale * acc;
+  // <v_k, x>_P for every stored vector k, for each x in xs, with one
+  // read-back.  With U (K+M)-orthonormal, <U C_k B_k^T, U C_x B_x^T>_P =
+  // scale * sum (C_k^T C_x) .* (B_k^T B_x): per x the products G1 = C_all^T C_x
+  // and G2 = B_all^T B_x (used x r) and their row-wise dot products (one value
+  // per stored column) on the device; on the host the sums over each stored
+  // vector's columns.
+  std::vector<std::vector<double>> inner_all_many(const std::vector<const CVec*>& xs) {
+    const int nxs = (int)xs.size();
+    std::vector<std::vector<double>> cs(nxs, std::vector<double>(size(), 0.0));
+    if (used == 0 || nxs == 0) return cs;
+    int rmax = 0;
+    for (const CVec* x : xs) rmax = std::max(rmax, x->r);
+    if (rmax == 0) return cs;
+    ipw.ensure(sizeof(double) * (size_t)used * rmax * 2);
+    ipo.ensure(sizeof(double) * (size_t)used * nxs);
+    double* G1 = ipw.as<double>();
+    double* G2 = G1 + (size_t)used * rmax;
+    double* h = ipo.as<double>();
+    for (int a = 0; a < nxs; ++a) {
+      const CVec& x = *xs[a];
+      if (x.r == 0) {
+        LRP_HIP(hipMemsetAsync(h + (size_t)a * used, 0, sizeof(double) * used, P->st));
+        continue;
+      }
+      const int sm = std::min(x.s, s);
+      P->dense->gemm(true, false, used, x.r, sm, 1.0, C_all.as<double>(), s_cap, x.C.as<double>(), x.s, 0.0, G1, used);
+      P->dense->gemm(true, false, used, x.r, nt, 1.0, B_all.as<double>(), nt, x.B.as<double>(), nt, 0.0, G2, used);
+      row_dot(P->st, used, x.r, G1, used, G2, used, h + (size_t)a * used);
     }
-    return c;
+    std::vector<double> hh((size_t)used * nxs);
+    P->to_host(hh.data(), h, hh.size());
+    for (int a = 0; a < nxs; ++a)
+      for (int k = 0; k < size(); ++k) {
+        double acc = 0.0;
+        for (int c2 = 0; c2 < rk[k]; ++c2) acc += hh[(size_t)a * used + off[k] + c2];
+        cs[a][k] = scale * acc;
+      }
+    return cs;
   }
+  std::vector<double> inner_all(const CVec& x) { return std::move(inner_all_many({&x})[0]); }
 
-  double inner(const CVec& x, const CVec& y) {
-    if (x.r == 0 || y.r == 0) return 0.0;
-    const int sm = std::min(x.s, y.s);
-    work3.ensure(sizeof(double) * (size_t)x.r * y.r * 2);
-    double* G1 = work3.as<double>();
-    double* G2 = G1 + (size_t)x.r * y.r;
-    P->dense->gemm(true, false, x.r, y.r, sm, 1.0, x.C.as<double>(), x.s, y.C.as<double>(), y.s, 0.0, G1, x.r);
-    P->dense->gemm(true, false, x.r, y.r, nt, 1.0, x.B.as<double>(), nt, y.B.as<double>(), nt, 0.0, G2, x.r);
-    std::vector<double> h((size_t)x.r * y.r * 2);
-    P->to_host(h.data(), G1, h.size());
-    double acc = 0.0;
-    for (size_t i = 0; i < (size_t)x.r * y.r; ++i) acc += h[i] * h[(size_t)x.r * y.r + i];
-    return scale * acc;
+  // <x, y>_P for each pair, with one read-back (row-wise dot products of
+  // x.C^T y.C and x.B^T y.B on the device, their sum on the host).
+  std::vector<double> inner_pairs(const std::vector<std::pair<const CVec*, const CVec*>>& pr) {
+    const int np = (int)pr.size();
+    std::vector<double> out(np, 0.0);
+    std::vector<size_t> ho(np + 1, 0);
+    size_t wmax = 0;
+    for (int a = 0; a < np; ++a) {
+      const CVec &x = *pr[a].first, &y = *pr[a].second;
+      const bool live = x.r > 0 && y.r > 0;
+      ho[a + 1] = ho[a] + (live ? x.r : 0);
+      if (live) wmax = std::max(wmax, (size_t)x.r * y.r);
+    }
+    if (ho[np] == 0) return out;
+    ipw.ensure(sizeof(double) * wmax * 2);
+    ipo.ensure(sizeof(double) * ho[np]);
+    double* G1 = ipw.as<double>();
+    double* G2 = G1 + wmax;
+    double* h = ipo.as<double>();
+    for (int a = 0; a < np; ++a) {
+      const CVec &x = *pr[a].first, &y = *pr[a].second;
+      if (ho[a + 1] == ho[a]) continue;
+      const int sm = std::min(x.s, y.s);
+      P->dense->gemm(true, false, x.r, y.r, sm, 1.0, x.C.as<double>(), x.s, y.C.as<double>(), y.s, 0.0, G1, x.r);
+      P->dense->gemm(true, false, x.r, y.r, nt, 1.0, x.B.as<double>(), nt, y.B.as<double>(), nt, 0.0, G2, x.r);
+      row_dot(P->st, x.r, y.r, G1, x.r, G2, x.r, h + ho[a]);
+    }
+    std::vector<double> hh(ho[np]);
+    P->to_host(hh.data(), h, hh.size());
+    for (int a = 0; a < np; ++a) {
+      double acc = 0.0;
+      for (size_t i = ho[a]; i < ho[a + 1]; ++i) acc += hh[i];
+      out[a] = scale * acc;
+    }
+    return out;
+  }
+  double inner(const CVec& x, const CVec& y) { return inner_pairs({{&x, &y}})[0]; }
+
+  // each core of vs scaled to unit P-norm (one read-back for all)
+  void normalize(std::vector<CVec>& vs) {
+    std::vector<std::pair<const CVec*, const CVec*>> pr;
+    for (auto& v : vs) pr.push_back({&v, &v});
+    const std::vector<double> n2 = inner_pairs(pr);
+    for (size_t i = 0; i < vs.size(); ++i) {
+      const double nv = std::sqrt(std::max(n2[i], 0.0));
+      if (nv > 0) P->dense->scal(nt * vs[i].r, 1.0 / nv, vs[i].B.as<double>());
+    }
   }
 
   void append(const CVec& v) {
@@ -439,12 +503,18 @@ static std::vector<CVec> orthonormalize_block(SharedBasis& sb, std::vector<CVec>
   Problem* P = sb.P;
   const int b = (int)W.size();
   std::vector<double> Gb((size_t)b * b);
-  for (int i = 0; i < b; ++i)
-    for (int l = i; l < b; ++l) {
-      const double g = sb.inner(W[i], W[l]);
-      Gb[(size_t)l * b + i] = g;
-      Gb[(size_t)i * b + l] = g;
-    }
+  {
+    std::vector<std::pair<const CVec*, const CVec*>> pr;
+    for (int i = 0; i < b; ++i)
+      for (int l = i; l < b; ++l) pr.push_back({&W[i], &W[l]});
+    const std::vector<double> g = sb.inner_pairs(pr);
+    size_t a = 0;
+    for (int i = 0; i < b; ++i)
+      for (int l = i; l < b; ++l, ++a) {
+        Gb[(size_t)l * b + i] = g[a];
+        Gb[(size_t)i * b + l] = g[a];
+      }
+  }
   std::vector<double> w(b), U((size_t)b * b);
   if (!syev(b, Gb.data(), b, w.data(), U.data())) fail(LRPOST_EBREAKDOWN, "block Gram eigensolve failed");
   const double wmax = std::max(w[b - 1], 0.0);
@@ -476,11 +546,8 @@ static std::vector<CVec> orthonormalize_block(SharedBasis& sb, std::vector<CVec>
     sb.combine(tv, coef, {}, Sbuf.as<double>() + c * slot);
   }
   auto vs = sb.truncate_cores(Sbuf.as<double>(), kout, (long)slot, sb.s, sb.s, tol, cap);
-  for (auto& v : vs) {
-    const double nv = std::sqrt(std::max(sb.inner(v, v), 0.0));
-    if (nv > 0) P->dense->scal(P->nt * v.r, 1.0 / nv, v.B.as<double>());
-    out.push_back(std::move(v));
-  }
+  sb.normalize(vs);
+  for (auto& v : vs) out.push_back(std::move(v));
   return out;
 }
 
@@ -493,6 +560,7 @@ EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rt
   SharedBasis sb(P, (int)s_reserve, std::max(max_vectors * cap / 2, 64));
   using clk = std::chrono::steady_clock;
   const auto t_start = clk::now();
+  P->phase_s.fill(0.0);
   double t_apply = 0.0, t_orth = 0.0;
   // seeded start block of rank-one vectors a_j (x) b_j
   std::vector<CVec> W;
@@ -528,52 +596,64 @@ EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rt
     std::vector<LowRank> outs(bj), xin(bj);
     std::vector<const LowRank*> px;
     std::vector<LowRank*> po;
-    for (int i = 0; i < bj; ++i) {
-      sb.materialize(sb.stored(j0 + i), xin[i]);
-      px.push_back(&xin[i]);
-      po.push_back(&outs[i]);
+    {
+      Problem::PhaseTimer pt(P, Problem::kPhMaterialize);
+      for (int i = 0; i < bj; ++i) {
+        sb.materialize(sb.stored(j0 + i), xin[i]);
+        px.push_back(&xin[i]);
+        po.push_back(&outs[i]);
+      }
     }
     P->hess_apply_batch(px, po, true);
     xin.clear();
     auto t1 = clk::now();
     t_apply += std::chrono::duration<double>(t1 - t0).count();
     std::vector<CVec> Wn;
-    // the apply outputs and the first sweep's results stay dense cores (no
-    // truncation); the second sweep's results are truncated
-    for (int i = 0; i < bj; ++i) Wn.push_back(sb.absorb(outs[i], tol, cap, false));
+    // the apply outputs and both sweeps' results stay dense cores (no
+    // truncation): the block orthonormalization below truncates the new
+    // directions once
+    {
+      Problem::PhaseTimer pt(P, Problem::kPhAbsorb);
+      for (int i = 0; i < bj; ++i) Wn.push_back(sb.absorb(outs[i], tol, cap, false));
+    }
     outs.clear();
+    std::optional<Problem::PhaseTimer> ptr(std::in_place, P, Problem::kPhReorth);
     // full re-orthogonalization, classical Gram-Schmidt twice, on the cores
-    // (the second pass forms the block's cores side by side and truncates
-    // them as one batch)
     const size_t slot = (size_t)std::max(sb.s, 1) * nt;
     for (int pass = 0; pass < 2; ++pass) {
-      Sbuf.ensure(sizeof(double) * slot * (pass == 0 ? 1 : bj));
+      Sbuf.ensure(sizeof(double) * slot);
+      std::vector<const CVec*> pw;
+      for (int i = 0; i < bj; ++i) pw.push_back(&Wn[i]);
+      std::vector<std::vector<double>> cs = sb.inner_all_many(pw);
       for (int i = 0; i < bj; ++i) {
-        std::vector<double> c = sb.inner_all(Wn[i]);
+        std::vector<double>& c = cs[i];
         const int m = sb.size();
         for (int kk = 0; kk < m; ++kk) T[(size_t)(j0 + i) * mmax + kk] += c[kk];
         for (double& x : c) x = -x;
-        double* Si = Sbuf.as<double>() + (pass == 0 ? 0 : i * slot);
-        sb.combine({&Wn[i]}, {1.0}, c, Si);
-        if (pass == 0) Wn[i] = sb.dense_core(Si, sb.s);
-      }
-      if (pass == 1) {
-        auto vs = sb.truncate_cores(Sbuf.as<double>(), bj, (long)slot, sb.s, sb.s, tol * 1e-1, cap);
-        for (int i = 0; i < bj; ++i) Wn[i] = std::move(vs[i]);
+        sb.combine({&Wn[i]}, {1.0}, c, Sbuf.as<double>());
+        Wn[i] = sb.dense_core(Sbuf.as<double>(), sb.s);
       }
     }
+    ptr.reset();
     const int m = sb.size();
     // Ritz values of the symmetrized projected matrix
     std::vector<double> Tm((size_t)m * m);
     for (int c = 0; c < m; ++c)
       for (int r = 0; r < m; ++r) Tm[(size_t)c * m + r] = 0.5 * (T[(size_t)c * mmax + r] + T[(size_t)r * mmax + c]);
-    P->sym_eig(m, Tm.data(), m, theta, Y);
+    {
+      Problem::PhaseTimer pt(P, Problem::kPhRitz);
+      P->sym_eig(m, Tm.data(), m, theta, Y);
+    }
     // next block and its coupling factor
     std::vector<double> Rn;
     int kn = 0;
     double theta_max = 0.0;
     for (double t : theta) theta_max = std::max(theta_max, std::fabs(t));
-    auto Vn = orthonormalize_block(sb, Wn, Rn, kn, tol, cap, 10.0 * tol * theta_max);
+    std::vector<CVec> Vn;
+    {
+      Problem::PhaseTimer pt(P, Problem::kPhOrthBlock);
+      Vn = orthonormalize_block(sb, Wn, Rn, kn, tol, cap, 10.0 * tol * theta_max);
+    }
     // residual estimates ||G x - theta x||_P = ||Rn * Y[last block, s]||
     bool done = m >= k;
     double worst = 0.0;
@@ -622,10 +702,14 @@ EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rt
       std::fprintf(stderr,
                    "{\"lanczos_step\": %d, \"vectors\": %d, \"basis_s\": %d, \"applies\": %lld, \"t_apply_s\": %.3f, "
                    "\"t_orth_s\": %.3f, \"t_total_s\": %.3f, \"worst_rel_resid\": %.3e, \"theta1\": %.10e, "
-                   "\"pool_in_use_mb\": %.1f, \"device_free_mb\": %.1f}\n",
+                   "\"pool_in_use_mb\": %.1f, \"device_free_mb\": %.1f, \"phases_s\": {\"prep\": %.3f, "
+                   "\"poles\": %.3f, \"project\": %.3f, \"proj_solve\": %.3f, \"trunc\": %.3f, \"prior\": %.3f, "
+                   "\"materialize\": %.3f, \"absorb\": %.3f, \"reorth\": %.3f, \"ritz\": %.3f, \"orth_block\": %.3f}}\n",
                    step, m, sb.s, (long long)P->stats.applies, t_apply, t_orth,
                    std::chrono::duration<double>(clk::now() - t_start).count(), worst, theta[m - 1],
-                   P->pool->bytes_in_use() / 1048576.0, fr / 1048576.0);
+                   P->pool->bytes_in_use() / 1048576.0, fr / 1048576.0, P->phase_s[0], P->phase_s[1], P->phase_s[2],
+                   P->phase_s[3], P->phase_s[4], P->phase_s[5], P->phase_s[6], P->phase_s[7], P->phase_s[8],
+                   P->phase_s[9], P->phase_s[10]);
       std::fflush(stderr);
     }
     if (done || kn == 0 || m + kn > mmax) break;
@@ -655,9 +739,8 @@ EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rt
       sb.combine({}, {}, coef, Sbuf.as<double>() + (s - s0) * slot);
     }
     auto vs = sb.truncate_cores(Sbuf.as<double>(), nb, (long)slot, sb.s, sb.s, tol, cap);
+    sb.normalize(vs);
     for (auto& v : vs) {
-      const double nv = std::sqrt(std::max(sb.inner(v, v), 0.0));
-      if (nv > 0) P->dense->scal(nt * v.r, 1.0 / nv, v.B.as<double>());
       auto out = std::make_unique<LowRank>();
       sb.materialize(v, *out);
       res.vecs.push_back(std::move(out));
@@ -711,9 +794,12 @@ EigResult randomized_eig(Problem* P, int k, const std::vector<const LowRank*>& p
   }
   for (auto& y : Y) sb.append(y);
   std::vector<double> Gy((size_t)l * l);
-  for (int j = 0; j < l; ++j) {
-    std::vector<double> c = sb.inner_all(Y[j]);
-    for (int i = 0; i < l; ++i) Gy[(size_t)j * l + i] = c[i];
+  {
+    std::vector<const CVec*> py;
+    for (auto& y : Y) py.push_back(&y);
+    const auto cs = sb.inner_all_many(py);
+    for (int j = 0; j < l; ++j)
+      for (int i = 0; i < l; ++i) Gy[(size_t)j * l + i] = cs[j][i];
   }
   for (int j = 0; j < l; ++j)
     for (int i = 0; i < j; ++i) Gy[(size_t)j * l + i] = Gy[(size_t)i * l + j] = 0.5 * (Gy[(size_t)j * l + i] + Gy[(size_t)i * l + j]);
@@ -760,9 +846,13 @@ EigResult randomized_eig(Problem* P, int k, const std::vector<const LowRank*>& p
   for (auto& q : Q) sb.append(q);
   for (auto& w : W) sb.append(w);
   std::vector<double> MQ((size_t)m * m), T((size_t)m * m), GW((size_t)m * m);
+  std::vector<const CVec*> pqw;
+  for (auto& q : Q) pqw.push_back(&q);
+  for (auto& w : W) pqw.push_back(&w);
+  const auto cqw = sb.inner_all_many(pqw);
   for (int b = 0; b < m; ++b) {
-    std::vector<double> cq = sb.inner_all(Q[b]);
-    std::vector<double> cw = sb.inner_all(W[b]);
+    const std::vector<double>& cq = cqw[b];
+    const std::vector<double>& cw = cqw[m + b];
     for (int a = 0; a < m; ++a) {
       MQ[(size_t)b * m + a] = cq[l + a];
       T[(size_t)b * m + a] = cw[l + a];
@@ -822,9 +912,8 @@ EigResult randomized_eig(Problem* P, int k, const std::vector<const LowRank*>& p
       res.lambda.push_back(th);
     }
     auto vs = sb.truncate_cores(Sbuf.as<double>(), nb, (long)slot2, sb.s, sb.s, tol, cap);
+    sb.normalize(vs);
     for (auto& v : vs) {
-      const double nv = std::sqrt(std::max(sb.inner(v, v), 0.0));
-      if (nv > 0) P->dense->scal(nt * v.r, 1.0 / nv, v.B.as<double>());
       auto out = std::make_unique<LowRank>();
       sb.materialize(v, *out);
       res.vecs.push_back(std::move(out));

@@ -5,6 +5,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <array>
+#include <chrono>
 #include <map>
 #include <memory>
 #include <stdexcept>
@@ -188,6 +189,27 @@ class Problem {
 
   // progress lines (JSON, stderr) of the eigensolvers when > 0
   int log_level = 0;
+
+  // host wall time per phase of a Hessian apply and of the Lanczos step,
+  // reported in the progress lines (a phase that ends in a read-back also
+  // carries the device time of the work it queued)
+  enum Phase {
+    kPhPrep, kPhPoles, kPhProject, kPhProjSolve, kPhTrunc, kPhPrior,
+    kPhMaterialize, kPhAbsorb, kPhReorth, kPhRitz, kPhOrthBlock, kPhCount
+  };
+  std::array<double, kPhCount> phase_s{};
+  // (log_level > 2 drains the stream at the end of every phase, so that each
+  // phase carries exactly its own device time)
+  struct PhaseTimer {
+    Problem* p;
+    double& acc;
+    std::chrono::steady_clock::time_point t0;
+    PhaseTimer(Problem* pr, Phase ph) : p(pr), acc(pr->phase_s[ph]), t0(std::chrono::steady_clock::now()) {}
+    ~PhaseTimer() {
+      if (p->log_level > 2) (void)hipStreamSynchronize(p->st);
+      acc += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+  };
 
   // opt-in timing of the multigrid kernels with HIP events, per kernel kind
   // (LRPOST_KERNEL_*): every launch is bracketed by an event pair on the

@@ -68,6 +68,8 @@ void mask_scale(hipStream_t st, long nx, int ncols, const T* X, long ldx, T* Y, 
 template <typename T>
 void axpby(hipStream_t st, long nx, int ncols, const T* X, long ldx, T* Y, long ldy, double a, double b);
 void scale_nodes(hipStream_t st, long nx, int ncols, double* X, long ldx, const double* w);
+// out[i] = sum_j A[i + j lda] B[i + j ldb], i < n, j < r (row-wise dot products)
+void row_dot(hipStream_t st, int n, int r, const double* A, long lda, const double* B, long ldb, double* out);
 void add_diag(hipStream_t st, int n, double* A, long lda, double v);
 void symmetrize_upper(hipStream_t st, int n, double* A, long lda);
 void d2f(hipStream_t st, long n, const double* x, float* y);

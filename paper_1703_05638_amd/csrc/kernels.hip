@@ -1298,6 +1298,21 @@ __global__ void k_symmetrize_upper(int n, double* A, long lda) {
   const int i = blockIdx.x * 16 + threadIdx.x, j = blockIdx.y * 16 + threadIdx.y;
   if (i < n && j < n && i > j) A[(long)j * lda + i] = A[(long)i * lda + j];
 }
+// out[i] = sum_j A[i + j lda] B[i + j ldb] for i < n, j < r: the row-wise
+// dot products of two column-major n x r matrices (one lane per row, j
+// ascending, so every run rounds alike)
+__global__ void k_row_dot(int n, int r, const double* __restrict__ A, long lda, const double* __restrict__ B,
+                          long ldb, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int j = 0; j < r; ++j) acc = fma(A[i + (long)j * lda], B[i + (long)j * ldb], acc);
+  out[i] = acc;
+}
+void row_dot(hipStream_t st, int n, int r, const double* A, long lda, const double* B, long ldb, double* out) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_row_dot, dim3((n + 255) / 256), dim3(256), 0, st, n, r, A, lda, B, ldb, out);
+}
 void add_diag(hipStream_t st, int n, double* A, long lda, double v) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_add_diag, dim3((n + 255) / 256), dim3(256), 0, st, n, A, lda, v);

@@ -786,13 +786,24 @@ void Problem::spacetime_solve_batch(const std::vector<const LowRank*>& F, const 
   const int nb = (int)F.size();
   std::vector<StPrep> prs(nb);
   std::vector<const StPrep*> pp;
-  for (int j = 0; j < nb; ++j) {
-    st_prepare(*F[j], adjoint, prs[j]);
-    pp.push_back(&prs[j]);
+  {
+    PhaseTimer pt(this, kPhPrep);
+    for (int j = 0; j < nb; ++j) {
+      st_prepare(*F[j], adjoint, prs[j]);
+      pp.push_back(&prs[j]);
+    }
   }
-  double* Wall = st_pole_solves(pp);
+  double* Wall;
+  {
+    PhaseTimer pt(this, kPhPoles);
+    Wall = st_pole_solves(pp);
+  }
   std::vector<StFin> fins(nb);
-  st_project_batch(prs, Wall, fins);
+  {
+    PhaseTimer pt(this, kPhProject);
+    st_project_batch(prs, Wall, fins);
+  }
+  PhaseTimer pt(this, kPhTrunc);
   st_truncate(fins, Y, adjoint);
 }
 
@@ -966,6 +977,7 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
       q[j] += kcols;
     }
   }
+  PhaseTimer pt(this, kPhProjSolve);
   for (int j = 0; j < nb; ++j) {
     stats.last_basis = q[j];
     if (q[j] > 0) st_solve_projected(prs[j], q[j], fins[j]);
@@ -1198,6 +1210,7 @@ void Problem::hess_apply_batch(const std::vector<const LowRank*>& x, const std::
   spacetime_solve_batch(pZ, pP, true);
   int R = 0;
   for (int j = 0; j < nb; ++j) R += Pa[j].rank;
+  PhaseTimer pt(this, kPhPrior);
   DevMem mp, out;
   if (R > 0 && precond) {
     mp.ensure(sizeof(double) * (size_t)nx * R);
