@@ -40,6 +40,7 @@ KERNELS = {
     1: ("k_mg_down", "level-fused pre-smoothing + residual + restriction", True),
     2: ("k_mg_up", "level-fused prolongation + post-smoothing", True),
     3: ("k_gram_mfma", "float64 matrix-core Gram A^T B, partial products", False),
+    4: ("k_proj_mfma", "float64 matrix-core projection C = beta C + A Q", False),
 }
 MFMA_F64_PEAK_TFLOPS = 78.6  # MI355X published dense FP64 matrix throughput
 

@@ -195,7 +195,11 @@ int lrpost_set_log(lrpost_problem* p, int level);
  *                                correction and b, write x;
  *   LRPOST_KERNEL_GRAM           the matrix-core stage of the float64 Gram
  *                                products A^T B (nx x m and nx x q operands):
- *                                read A and B once, 2 m q nx flops.
+ *                                read A and B once, 2 m q nx flops;
+ *   LRPOST_KERNEL_PROJ           the float64 matrix-core projection
+ *                                C = beta C + A Q (A nx x m, C nx x p): read A
+ *                                once, read C once when beta != 0, write C
+ *                                once, 2 m p nx flops.
  * lrpost_profile_read synchronizes, returns for one kind the launch count, the
  * summed kernel time in ms, the counted bytes and (if flops is not NULL) the
  * counted floating-point operations since the last read, and resets that
@@ -204,7 +208,8 @@ enum {
   LRPOST_KERNEL_SMOOTHER_STEP = 0,
   LRPOST_KERNEL_MG_DOWN = 1,
   LRPOST_KERNEL_MG_UP = 2,
-  LRPOST_KERNEL_GRAM = 3
+  LRPOST_KERNEL_GRAM = 3,
+  LRPOST_KERNEL_PROJ = 4
 };
 int lrpost_profile(lrpost_problem* p, int enable);
 int lrpost_profile_read(lrpost_problem* p, int kernel, int64_t* launches, double* total_ms, double* bytes,

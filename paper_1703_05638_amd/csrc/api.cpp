@@ -414,7 +414,7 @@ int lrpost_profile_read(lrpost_problem* p, int kernel, int64_t* launches, double
     Problem* P = impl(p);
     PoolScope pool_scope(P->pool);
     if (!launches || !total_ms || !bytes) fail(LRPOST_EINVAL, "null argument");
-    if (kernel < 0 || kernel > LRPOST_KERNEL_GRAM) fail(LRPOST_EINVAL, "unknown kernel kind");
+    if (kernel < 0 || kernel > LRPOST_KERNEL_PROJ) fail(LRPOST_EINVAL, "unknown kernel kind");
     P->prof_read(kernel, launches, total_ms, bytes, flops);
   });
 }

@@ -220,7 +220,7 @@ class Problem {
     double bytes = 0.0, flops = 0.0;
   };
   bool prof_on = false;
-  std::array<ProfSlot, 4> prof_;
+  std::array<ProfSlot, 5> prof_;
   template <class Launch>
   void timed(int kind, double bytes, Launch&& launch, double flops = 0.0);
   template <typename T>
@@ -252,7 +252,7 @@ class Problem {
     DevMem Q, Zp, W2, Kt;
   };
   void st_project_batch(const std::vector<StPrep>& prs, double* Wall, std::vector<StFin>& fins);
-  void st_solve_projected(const StPrep& pr, int q, StFin& fin);
+  void st_solve_projected(const std::vector<StPrep>& prs, const std::vector<int>& q, std::vector<StFin>& fins);
   void st_truncate(std::vector<StFin>& fins, const std::vector<LowRank*>& Y, bool adjoint);
   // G x (precond) or H_mis x (misfit).
   void hess_apply(const LowRank& x, LowRank& y, bool precond);

@@ -62,6 +62,36 @@ template <>
 void proj<double>(hipStream_t st, long nrows, int m, const double* A, long lda, const double* Q, int ldq, int p,
                   double* C, long ldc, double beta);
 
+// Several independent products C_g = beta Cin_g + alpha A_g Q_g (A_g nrows x m,
+// Q_g m x p, C_g nrows x p, Cin_g may be C_g) on the matrix cores, up to
+// kProjGroupMax per launch; each product is computed exactly as by proj.
+constexpr int kProjGroupMax = 8;
+struct ProjGroup {
+  const double* A;
+  const double* Q;
+  const double* Cin;
+  double* C;
+  long lda, ldc, nrows;
+  int ldq, m, p;
+};
+struct ProjGroups {
+  ProjGroup g[kProjGroupMax];
+};
+void proj_grouped(hipStream_t st, int count, const ProjGroup* groups, double alpha, double beta);
+// A_g[i, i] += v for i < n_g; dst_g = src_g (len_g doubles); count <= kProjGroupMax
+struct DiagGroups {
+  double* A[kProjGroupMax];
+  long lda[kProjGroupMax];
+  int n[kProjGroupMax];
+};
+void add_diag_grouped(hipStream_t st, const DiagGroups& gs, int count, double v);
+struct CopyGroups {
+  const double* src[kProjGroupMax];
+  double* dst[kProjGroupMax];
+  long len[kProjGroupMax];
+};
+void copy_grouped(hipStream_t st, const CopyGroups& gs, int count);
+
 template <typename T>
 void mask_scale(hipStream_t st, long nx, int ncols, const T* X, long ldx, T* Y, long ldy, const uint8_t* mask,
                 double s);

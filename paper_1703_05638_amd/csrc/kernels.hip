@@ -926,8 +926,8 @@ int gram_chunks(long nrows, int m, int q) {
 // FP64 Gram on the matrix cores.  Workgroup (tm, tq, chunk), 8 waves,
 // accumulates a (64 BM) x 64 output tile over its chunk of rows; with
 // BM = 3 the tile covers m <= 192, so each operand of the usual tall-skinny
-// products is read from memory once.  Rows are staged through LDS 16 at a
-// time (coalesced: 16 consecutive lanes read 16 consecutive rows, 128 bytes,
+// products is read from memory once.  Rows are staged through LDS 32 at a
+// time (coalesced: 32 consecutive lanes read 32 consecutive rows, 256 bytes,
 // of one column), stored [column][row] so that each MFMA operand is one LDS
 // read per lane; the next stage is fetched into registers while the matrix
 // cores work on the current one.  The waves form a 4 x 2 grid; each owns
@@ -938,7 +938,7 @@ int gram_chunks(long nrows, int m, int q) {
 // ---------------------------------------------------------------------------
 typedef double gram_d4 __attribute__((ext_vector_type(4)));
 constexpr int GQ = 64;   // output tile width (q direction)
-constexpr int GK = 16;   // rows per LDS stage
+constexpr int GK = 32;   // rows per LDS stage
 constexpr int GTH = 512;  // threads per workgroup
 
 template <int BM>
@@ -960,7 +960,7 @@ __global__ __launch_bounds__(GTH) void k_gram_mfma(long nrows, long rows_per_chu
   for (int a = 0; a < BM; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = gram_d4{0.0, 0.0, 0.0, 0.0};
-  const int lr = tid & (GK - 1), lc = tid / GK;  // loader: row lr of columns lc, lc + 32, ...
+  const int lr = tid & (GK - 1), lc = tid / GK;  // loader: row lr of columns lc, lc + GTH / GK, ...
   const long nst = (r1 > r0) ? (r1 - r0 + GK - 1) / GK : 0;
   // column pointers of this thread's staged columns (clamped into range) and
   // whether they are real columns
@@ -1034,11 +1034,13 @@ __global__ __launch_bounds__(GTH) void k_gram_mfma(long nrows, long rows_per_chu
 static int gram_bm(int m) { return m <= 64 ? 1 : m <= 128 ? 2 : 3; }
 
 int gram_chunks_mfma(long nrows, int m, int q) {
-  // about 512 workgroups, at least 128 rows per chunk, and per-chunk partial
-  // products of at most about 35% of the operand bytes
+  // about one workgroup per CU (longer chunks beat more, shorter ones: a
+  // chunk's stages are dependent round trips to memory), at least 128 rows
+  // per chunk, and per-chunk partial products of at most about 35% of the
+  // operand bytes
   const int gm = 64 * gram_bm(m);
   const long tiles = (long)((m + gm - 1) / gm) * ((q + GQ - 1) / GQ);
-  long c = 512 / (tiles > 0 ? tiles : 1);
+  long c = 256 / (tiles > 0 ? tiles : 1);
   const long cmax = (nrows + 127) / 128;
   const long cpart = (long)(0.35 * (double)(m + q) * (double)nrows / ((double)m * q)) + 1;
   c = std::min(c, std::min(cmax, cpart));
@@ -1155,13 +1157,13 @@ void proj(hipStream_t st, long nrows, int m, const T* A, long lda, const double*
 // [k][column]; each wave owns 32 rows x 32 columns as 2 x 2 MFMA blocks.
 constexpr int PR = 64, PC = 64, PK = 32;
 
-__global__ __launch_bounds__(256) void k_proj_mfma(long nrows, int m, const double* __restrict__ A, long lda,
-                                                   const double* __restrict__ Q, int ldq, int p,
-                                                   double* __restrict__ C, long ldc, double beta) {
+// One 64 x 64 tile (rows row0.., columns col0..) of C = beta Cin + alpha A Q,
+// for the whole workgroup (Cin may be C).
+__device__ __forceinline__ void proj_tile(long nrows, int m, const double* __restrict__ A, long lda,
+                                          const double* __restrict__ Q, int ldq, int p, const double* Cin,
+                                          double* C, long ldc, double alpha, double beta, long row0, int col0) {
   __shared__ double As[PK][PR + 1];
   __shared__ double Qs[PK][PC + 1];
-  const long row0 = (long)blockIdx.x * PR;
-  const int col0 = blockIdx.y * PC;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave & 1, wc = wave >> 1;
   gram_d4 acc[2][2];
@@ -1213,8 +1215,8 @@ __global__ __launch_bounds__(256) void k_proj_mfma(long nrows, int m, const doub
     }
     __syncthreads();
   }
-  // beta != 0: every old value of C is read (from clamped addresses) before
-  // any store, so that the reads are in flight together
+  // beta != 0: every old value is read (from clamped addresses) before any
+  // store, so that the reads are in flight together
   double old[2][2][4];
   if (beta != 0.0) {
 #pragma unroll
@@ -1225,7 +1227,7 @@ __global__ __launch_bounds__(256) void k_proj_mfma(long nrows, int m, const doub
         for (int v = 0; v < 4; ++v) {
           const int j = col0 + wc * 32 + 16 * a + (lane >> 4) + 4 * v;
           const long r = row0 + wr * 32 + 16 * b + (lane & 15);
-          old[a][b][v] = C[(long)(j < p ? j : p - 1) * ldc + (r < nrows ? r : nrows - 1)];
+          old[a][b][v] = Cin[(long)(j < p ? j : p - 1) * ldc + (r < nrows ? r : nrows - 1)];
         }
   }
 #pragma unroll
@@ -1236,9 +1238,70 @@ __global__ __launch_bounds__(256) void k_proj_mfma(long nrows, int m, const doub
       for (int v = 0; v < 4; ++v) {
         const int j = col0 + wc * 32 + 16 * a + (lane >> 4) + 4 * v;
         const long r = row0 + wr * 32 + 16 * b + (lane & 15);
-        if (j < p && r < nrows)
-          C[(long)j * ldc + r] = beta == 0.0 ? acc[a][b][v] : beta * old[a][b][v] + acc[a][b][v];
+        const double t = alpha * acc[a][b][v];
+        if (j < p && r < nrows) C[(long)j * ldc + r] = beta == 0.0 ? t : fma(beta, old[a][b][v], t);
       }
+}
+
+__global__ __launch_bounds__(256) void k_proj_mfma(long nrows, int m, const double* __restrict__ A, long lda,
+                                                   const double* __restrict__ Q, int ldq, int p,
+                                                   double* __restrict__ C, long ldc, double beta) {
+  proj_tile(nrows, m, A, lda, Q, ldq, p, C, C, ldc, 1.0, beta, (long)blockIdx.x * PR, blockIdx.y * PC);
+}
+
+// Several independent products C_g = beta Cin_g + alpha A_g Q_g in one launch
+// (blockIdx.z = g; tiles outside a product's shape return before any
+// barrier).  Each tile is computed exactly as by a launch of its own.
+__global__ __launch_bounds__(256) void k_proj_grouped(ProjGroups gs, double alpha, double beta) {
+  const ProjGroup& g = gs.g[blockIdx.z];
+  const long row0 = (long)blockIdx.x * PR;
+  const int col0 = blockIdx.y * PC;
+  if (row0 >= g.nrows || col0 >= g.p || g.m <= 0) return;
+  proj_tile(g.nrows, g.m, g.A, g.lda, g.Q, g.ldq, g.p, g.Cin, g.C, g.ldc, alpha, beta, row0, col0);
+}
+
+void proj_grouped(hipStream_t st, int count, const ProjGroup* groups, double alpha, double beta) {
+  for (int g0 = 0; g0 < count; g0 += kProjGroupMax) {
+    ProjGroups gs{};
+    const int n = std::min(kProjGroupMax, count - g0);
+    long rmax = 0;
+    int pmax = 0;
+    for (int i = 0; i < n; ++i) {
+      gs.g[i] = groups[g0 + i];
+      rmax = std::max(rmax, gs.g[i].nrows);
+      pmax = std::max(pmax, gs.g[i].p);
+    }
+    if (rmax <= 0 || pmax <= 0) continue;
+    dim3 grd((rmax + PR - 1) / PR, (pmax + PC - 1) / PC, n);
+    hipLaunchKernelGGL(k_proj_grouped, grd, dim3(256), 0, st, gs, alpha, beta);
+  }
+}
+
+// A_g[i, i] += v (i < n_g) and dst_g = src_g (len_g doubles) for several
+// matrices in one launch (blockIdx.y = g)
+__global__ void k_add_diag_grouped(DiagGroups gs, double v) {
+  const int g = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < gs.n[g]) gs.A[g][(long)i * gs.lda[g] + i] += v;
+}
+void add_diag_grouped(hipStream_t st, const DiagGroups& gs, int count, double v) {
+  int nmax = 0;
+  for (int g = 0; g < count; ++g) nmax = std::max(nmax, gs.n[g]);
+  if (nmax <= 0 || count <= 0) return;
+  hipLaunchKernelGGL(k_add_diag_grouped, dim3((nmax + 255) / 256, count), dim3(256), 0, st, gs, v);
+}
+__global__ void k_copy_grouped(CopyGroups gs) {
+  const int g = blockIdx.y;
+  const long n = gs.len[g];
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    gs.dst[g][i] = gs.src[g][i];
+}
+void copy_grouped(hipStream_t st, const CopyGroups& gs, int count) {
+  long nmax = 0;
+  for (int g = 0; g < count; ++g) nmax = std::max(nmax, gs.len[g]);
+  if (nmax <= 0 || count <= 0) return;
+  const long blocks = std::min<long>((nmax + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_copy_grouped, dim3((unsigned)blocks, count), dim3(256), 0, st, gs);
 }
 
 template <>

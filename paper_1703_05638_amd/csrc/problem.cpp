@@ -99,6 +99,16 @@ static void stencil_weights(double a, double b, double h, double* w) {
   w[2] = -a / 3.0 + b * h2 / 36.0;
 }
 
+// Newton-Schulz steps X <- X (2I - A X) from X_0 = 2 / (1 + L) I for an
+// SPD A with spectrum in [1, L]: the error I - A X_k has spectral radius
+// rho^(2^k), rho = (L - 1) / (L + 1); the count takes it below 1e-18 (plus
+// one step).
+static int ns_steps(double L) {
+  const double rho = (L - 1.0) / (L + 1.0);
+  if (!(rho > 0.0)) return 1;
+  return std::max(1, (int)std::ceil(std::log2(std::log(1e-18) / std::log(rho))) + 1);
+}
+
 Problem::Problem(const lrpost_problem_desc& d) : desc(d) {
   if (d.N < 4 || d.N > 4096 || (d.N & (d.N - 1)) != 0) fail(LRPOST_EINVAL, "N must be a power of two in [4, 4096]");
   if (d.nt < 1) fail(LRPOST_EINVAL, "nt must be >= 1");
@@ -187,10 +197,7 @@ Problem::Problem(const lrpost_problem_desc& d) : desc(d) {
   // spectrum bound (with a margin for the rounding of the basis) and the
   // number of steps that takes the error factor below 1e-18
   ns_bound_ = 1.0 + 1.05 * tau * lam_max;
-  {
-    const double rho = (ns_bound_ - 1.0) / (ns_bound_ + 1.0);
-    ns_iters_ = std::max(1, (int)std::ceil(std::log2(std::log(1e-18) / std::log(rho))) + 1);
-  }
+  ns_iters_ = ns_steps(ns_bound_);
   const double plo = std::min(1e-2, 0.5 * tau * lam_min);
   const double phi = std::max(10.0 * plo, std::min(tau * lam_max, 1e4));
   if (lt <= 7.0) {
@@ -595,7 +602,8 @@ void Problem::gram_dev(int m, const double* A, int q, const double* B, double* C
 
 void Problem::proj_dev(int m, const double* A, const double* Q, int ldq, int p, double* C, double beta) {
   if (p <= 0) return;
-  ::lrp::proj<double>(st, nx, m, A, nx, Q, ldq, p, C, nx, beta);
+  timed(LRPOST_KERNEL_PROJ, sizeof(double) * (double)(m + (beta != 0.0 ? 2 : 1) * p) * nx,
+        [&] { ::lrp::proj<double>(st, nx, m, A, nx, Q, ldq, p, C, nx, beta); }, 2.0 * m * p * (double)nx);
   LRP_HIP(hipGetLastError());
 }
 
@@ -873,10 +881,11 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
   double* Gd = st_g_.as<double>();
   std::vector<double> Gh(gs * 2 * nb);
   auto slot = [&](int j, int k) { return (size_t)(2 * j + k) * gs; };
-  auto sweep = [&](int j, int kc, double* X) {  // X -= Q (Q^T M X), all on the device
+  // X -= Q (Q^T M X), all on the device (mw_ready: MW already holds M X)
+  auto sweep = [&](int j, int kc, double* X, bool mw_ready) {
     if (q[j] == 0 || kc == 0) return;
     const double* Q = fins[j].Q.as<double>();
-    apply_op(kc, X, MW, Mop);
+    if (!mw_ready) apply_op(kc, X, MW, Mop);
     st_c_.ensure(sizeof(double) * (size_t)q[j] * kc);
     gram_dev(q[j], Q, kc, MW, st_c_.as<double>());
     dense->scal(q[j] * kc, -1.0, st_c_.as<double>());
@@ -927,7 +936,7 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
       double* W = Wb[j] + (size_t)ip * r1 * nx;
       apply_op(r1, W, MW, Mop);
       gram_dev(r1, W, r1, MW, Gd + slot(j, 0));
-      sweep(j, r1, W);
+      sweep(j, r1, W, true);
       apply_op(r1, W, MW, Mop);
       gram_dev(r1, W, r1, MW, Gd + slot(j, 1));
     }
@@ -953,7 +962,7 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
     for (int j = 0; j < nb; ++j) {
       if (k1[j] == 0) continue;
       double* W2 = fins[j].W2.as<double>();
-      sweep(j, k1[j], W2);
+      sweep(j, k1[j], W2, false);
       apply_op(k1[j], W2, MW, Mop);
       gram_dev(k1[j], W2, k1[j], MW, Gd + slot(j, 0));
     }
@@ -978,41 +987,60 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
     }
   }
   PhaseTimer pt(this, kPhProjSolve);
-  for (int j = 0; j < nb; ++j) {
-    stats.last_basis = q[j];
-    if (q[j] > 0) st_solve_projected(prs[j], q[j], fins[j]);
-  }
+  for (int j = 0; j < nb; ++j) stats.last_basis = q[j];
+  st_solve_projected(prs, q, fins);
 }
 
-// 3. Projected problem of one source on the device, given its basis
-// (fin.Q, q columns) and projected tau K (fin.Kt, leading dimension r1 npol):
-// fin.Zp (q x nt).
-void Problem::st_solve_projected(const StPrep& pr, int q, StFin& fin) {
-  const int r1 = pr.r1;
-  const int qmax = r1 * (int)poles.size();
-  const double* Fb = pr.Fb.as<double>();
-  const std::vector<double>& F2p = pr.F2p;
-  const double* Q = fin.Q.as<double>();
-  const double* Kt = fin.Kt.as<double>();
-  // 3. projected problem on the device.  With Q^T M Q = I each column obeys
-  // (I + Kt) z_k = z_{k-1} + g_k, g_k = S F2p^T e_k: a linear recurrence
-  // z_k = A z_{k-1} + A g_k with the constant matrix A = (I + Kt)^{-1}
-  // (computed below by Newton-Schulz).  It is evaluated by recursive doubling over time:
-  // after the level with stride d, X[:, k] = sum_{j < 2d, j <= k} A^j (A G)[:, k-j];
-  // the next level adds A^{2d} X[:, k - 2d].  The eigenvalues of A lie in
-  // (0, 1], so the powers stay bounded.
-  const int gmax = std::max(q, nt);
-  st_small_.ensure(sizeof(double) * ((size_t)q * r1 + (size_t)nt * r1 + 2 * (size_t)q * nt + 3 * (size_t)q * q +
-                                     (size_t)gmax * gmax + (size_t)gmax + 64));
-  double* S = st_small_.as<double>();       // q x r1 = Q^T Fb
-  double* F2d = S + (size_t)q * r1;         // nt x r1
-  double* X1 = F2d + (size_t)nt * r1;       // q x nt
-  double* X2 = X1 + (size_t)q * nt;         // q x nt
-  double* Ainv = X2 + (size_t)q * nt;       // q x q: I + Kt, then A = (I + Kt)^{-1}
-  double* P1 = Ainv + (size_t)q * q;        // q x q powers of A
-  double* P2 = P1 + (size_t)q * q;
-  double* Gsm = P2 + (size_t)q * q;         // Gram for the truncation (max(q, nt)^2)
-  double* Gt = Gsm + (size_t)gmax * gmax;   // max(q, nt) eigenvalues
+// 3. Projected problems of the sources of a batch on the device, given their
+// bases (fin.Q, q[j] columns) and projected tau K (fin.Kt, leading dimension
+// r1 npol): fin.Zp (q[j] x nt).  The small dense products of all sources run
+// as grouped matrix-core launches; each source's arithmetic is the same as
+// on its own.
+void Problem::st_solve_projected(const std::vector<StPrep>& prs, const std::vector<int>& q, std::vector<StFin>& fins) {
+  const int npol = (int)poles.size();
+  std::vector<int> act;
+  for (int j = 0; j < (int)prs.size(); ++j)
+    if (q[j] > 0) act.push_back(j);
+  const int na = (int)act.size();
+  if (na == 0) return;
+  // per source: S (q x r1) = Q^T Fb, F2t (r1 x nt) = F2p^T, X1 and X2 (q x nt),
+  // and four q x q matrices
+  std::vector<size_t> off(na + 1, 0);
+  for (int a = 0; a < na; ++a) {
+    const size_t qa = q[act[a]], r1 = prs[act[a]].r1;
+    off[a + 1] = off[a] + qa * r1 + r1 * nt + 2 * qa * nt + 4 * qa * qa;
+  }
+  st_small_.ensure(sizeof(double) * (off[na] + 64));
+  struct Bufs {
+    double *S, *F2t, *X1, *X2, *M[4];
+  };
+  std::vector<Bufs> bf(na);
+  for (int a = 0; a < na; ++a) {
+    const size_t qa = q[act[a]], r1 = prs[act[a]].r1;
+    double* p = st_small_.as<double>() + off[a];
+    bf[a].S = p;
+    bf[a].F2t = bf[a].S + qa * r1;
+    bf[a].X1 = bf[a].F2t + r1 * nt;
+    bf[a].X2 = bf[a].X1 + qa * nt;
+    for (int k = 0; k < 4; ++k) bf[a].M[k] = bf[a].X2 + qa * nt + (size_t)k * qa * qa;
+  }
+  auto grouped = [&](double alpha, double beta, auto&& set) {
+    std::vector<ProjGroup> g(na);
+    for (int a = 0; a < na; ++a) set(a, q[act[a]], g[a]);
+    proj_grouped(st, na, g.data(), alpha, beta);
+  };
+  auto diag = [&](std::vector<double*> A, double v) {
+    for (int a0 = 0; a0 < na; a0 += kProjGroupMax) {
+      DiagGroups dg{};
+      const int n = std::min(kProjGroupMax, na - a0);
+      for (int i = 0; i < n; ++i) {
+        dg.A[i] = A[a0 + i];
+        dg.lda[i] = q[act[a0 + i]];
+        dg.n[i] = q[act[a0 + i]];
+      }
+      add_diag_grouped(st, dg, n, v);
+    }
+  };
   // A = (I + Kt)^{-1} by the Newton-Schulz iteration X <- X (2I - (I + Kt) X)
   // from X_0 = 2 / (1 + L) I: with Q M-orthonormal the eigenvalues of
   // I + Kt lie in [1, L], L = 1 + tau lambda_max(M^{-1} K), so the error
@@ -1020,49 +1048,94 @@ void Problem::st_solve_projected(const StPrep& pr, int q, StFin& fin) {
   // iteration count follows from L alone.  Only matrix products are used,
   // which round identically on every run (a library Cholesky inverse did
   // not when other work shared the device).
-  {
-    double* Apd = P1;  // I + Kt, full symmetric
-    double* T = P2;
-    double* Xa = Ainv;
-    double* Xn = Gsm;  // gmax^2 >= q^2
-    LRP_HIP(hipMemcpy2DAsync(Apd, sizeof(double) * q, Kt, sizeof(double) * qmax, sizeof(double) * q, q,
-                             hipMemcpyDeviceToDevice, st));
-    add_diag(st, q, Apd, q, 1.0);
-    symmetrize_upper(st, q, Apd, q);
-    LRP_HIP(hipMemsetAsync(Xa, 0, sizeof(double) * (size_t)q * q, st));
-    add_diag(st, q, Xa, q, 2.0 / (1.0 + ns_bound_));
-    for (int it = 0; it < ns_iters_; ++it) {
-      dense->gemm(false, false, q, q, q, -1.0, Apd, q, Xa, q, 0.0, T, q);  // T = 2I - (I + Kt) X
-      add_diag(st, q, T, q, 2.0);
-      dense->gemm(false, false, q, q, q, 1.0, Xa, q, T, q, 0.0, Xn, q);  // Xn = X T
-      std::swap(Xa, Xn);
-    }
-    if (Xa != Ainv)
-      LRP_HIP(hipMemcpyAsync(Ainv, Xa, sizeof(double) * (size_t)q * q, hipMemcpyDeviceToDevice, st));
+  // M[0] = I + Kt (full symmetric), M[1] and M[2] the iterates, M[3] = T.
+  std::vector<double*> Apd(na), Xa(na), Xn(na), T(na);
+  for (int a = 0; a < na; ++a) {
+    const int j = act[a], qa = q[j];
+    const int qmax = prs[j].r1 * npol;
+    Apd[a] = bf[a].M[0];
+    Xa[a] = bf[a].M[1];
+    Xn[a] = bf[a].M[2];
+    T[a] = bf[a].M[3];
+    LRP_HIP(hipMemcpy2DAsync(Apd[a], sizeof(double) * qa, fins[j].Kt.as<double>(), sizeof(double) * qmax,
+                             sizeof(double) * qa, qa, hipMemcpyDeviceToDevice, st));
+    symmetrize_upper(st, qa, Apd[a], qa);
+    LRP_HIP(hipMemsetAsync(Xa[a], 0, sizeof(double) * (size_t)qa * qa, st));
   }
-  gram_dev(q, Q, r1, Fb, S);
-  to_device(F2d, F2p.data(), (size_t)nt * r1);
-  dense->gemm(false, true, q, nt, r1, 1.0, S, q, F2d, nt, 0.0, X2, q);        // G = S F2p^T
-  dense->gemm(false, false, q, nt, q, 1.0, Ainv, q, X2, q, 0.0, X1, q);       // A G
-  const double* Apow = Ainv;
-  int ldp = q;
-  double* cur = X1;
-  double* nxt = X2;
-  double* pw = P1;
+  diag(Apd, 1.0);
+  diag(Xa, 2.0 / (1.0 + ns_bound_));
+  for (int it = 0; it < ns_iters_; ++it) {
+    grouped(-1.0, 0.0, [&](int a, int qa, ProjGroup& g) {  // T = -(I + Kt) X
+      g = ProjGroup{Apd[a], Xa[a], T[a], T[a], qa, qa, qa, qa, qa, qa};
+    });
+    diag(T, 2.0);  // T = 2I - (I + Kt) X
+    grouped(1.0, 0.0, [&](int a, int qa, ProjGroup& g) {  // Xn = X T
+      g = ProjGroup{Xa[a], T[a], Xn[a], Xn[a], qa, qa, qa, qa, qa, qa};
+    });
+    std::swap(Xa, Xn);
+  }
+  // Xa = A; the other two q x q buffers hold its powers
+  std::vector<double*> P1(na), P2(na);
+  for (int a = 0; a < na; ++a) {
+    P1[a] = Apd[a];
+    P2[a] = T[a];
+  }
+  // With Q^T M Q = I each column obeys (I + Kt) z_k = z_{k-1} + g_k,
+  // g_k = S F2p^T e_k: a linear recurrence z_k = A z_{k-1} + A g_k with the
+  // constant matrix A, evaluated by recursive doubling over time: after the
+  // level with stride d, X[:, k] = sum_{j < 2d, j <= k} A^j (A G)[:, k-j]; the
+  // next level adds A^{2d} X[:, k - 2d].  The eigenvalues of A lie in (0, 1],
+  // so the powers stay bounded.
+  for (int a = 0; a < na; ++a) {
+    const int j = act[a], r1 = prs[j].r1;
+    gram_dev(q[j], fins[j].Q.as<double>(), r1, prs[j].Fb.as<double>(), bf[a].S);
+    std::vector<double>& ft = tmp_h_;
+    ft.resize((size_t)r1 * nt);
+    for (int t = 0; t < nt; ++t)
+      for (int i = 0; i < r1; ++i) ft[(size_t)t * r1 + i] = prs[j].F2p[(size_t)i * nt + t];
+    to_device(bf[a].F2t, ft.data(), ft.size());
+  }
+  grouped(1.0, 0.0, [&](int a, int qa, ProjGroup& g) {  // G = S F2p^T (in X2)
+    const int r1 = prs[act[a]].r1;
+    g = ProjGroup{bf[a].S, bf[a].F2t, bf[a].X2, bf[a].X2, qa, qa, qa, r1, r1, nt};
+  });
+  grouped(1.0, 0.0, [&](int a, int qa, ProjGroup& g) {  // X1 = A G
+    g = ProjGroup{Xa[a], bf[a].X2, bf[a].X1, bf[a].X1, qa, qa, qa, qa, qa, nt};
+  });
+  std::vector<double*> Apow = Xa, cur(na), nxt(na), pw = P1;
+  for (int a = 0; a < na; ++a) {
+    cur[a] = bf[a].X1;
+    nxt[a] = bf[a].X2;
+  }
   for (int d = 1; d < nt; d *= 2) {
-    LRP_HIP(hipMemcpyAsync(nxt, cur, sizeof(double) * (size_t)q * nt, hipMemcpyDeviceToDevice, st));
-    dense->gemm(false, false, q, nt - d, q, 1.0, Apow, ldp, cur, q, 1.0, nxt + (size_t)d * q, q);
+    for (int a0 = 0; a0 < na; a0 += kProjGroupMax) {
+      CopyGroups cg{};
+      const int n = std::min(kProjGroupMax, na - a0);
+      for (int i = 0; i < n; ++i) {
+        cg.src[i] = cur[a0 + i];
+        cg.dst[i] = nxt[a0 + i];
+        cg.len[i] = (long)q[act[a0 + i]] * nt;
+      }
+      copy_grouped(st, cg, n);
+    }
+    grouped(1.0, 1.0, [&](int a, int qa, ProjGroup& g) {  // nxt[:, d:] += A^d cur[:, :nt-d]
+      g = ProjGroup{Apow[a], cur[a], nxt[a] + (size_t)d * qa, nxt[a] + (size_t)d * qa, qa, qa, qa, qa, qa, nt - d};
+    });
     std::swap(cur, nxt);
     if (2 * d < nt) {
-      dense->gemm(false, false, q, q, q, 1.0, Apow, ldp, Apow, ldp, 0.0, pw, q);
+      grouped(1.0, 0.0, [&](int a, int qa, ProjGroup& g) {  // A^{2d} = A^d A^d
+        g = ProjGroup{Apow[a], Apow[a], pw[a], pw[a], qa, qa, qa, qa, qa, qa};
+      });
       Apow = pw;
-      ldp = q;
-      pw = pw == P1 ? P2 : P1;
+      pw = pw[0] == P1[0] ? P2 : P1;
     }
   }
-  fin.q = q;
-  fin.Zp.ensure(sizeof(double) * (size_t)q * nt);
-  LRP_HIP(hipMemcpyAsync(fin.Zp.p, cur, sizeof(double) * (size_t)q * nt, hipMemcpyDeviceToDevice, st));
+  for (int a = 0; a < na; ++a) {
+    const int j = act[a];
+    fins[j].q = q[j];
+    fins[j].Zp.ensure(sizeof(double) * (size_t)q[j] * nt);
+    LRP_HIP(hipMemcpyAsync(fins[j].Zp.p, cur[a], sizeof(double) * (size_t)q[j] * nt, hipMemcpyDeviceToDevice, st));
+  }
 }
 
 // Truncation of the projected solutions Y_j = Q_j Zp_j (Q_j M-orthonormal:

@@ -23,7 +23,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "lrpost.h")
 LRPOST_FP64, LRPOST_MIXED = 0, 1
 LRPOST_MISFIT, LRPOST_PRECOND = 0, 1
 LRPOST_BLOCK_LANCZOS, LRPOST_RANDOMIZED = 0, 1
-LRPOST_KERNEL_SMOOTHER_STEP, LRPOST_KERNEL_MG_DOWN, LRPOST_KERNEL_MG_UP, LRPOST_KERNEL_GRAM = 0, 1, 2, 3
+LRPOST_KERNEL_SMOOTHER_STEP, LRPOST_KERNEL_MG_DOWN, LRPOST_KERNEL_MG_UP, LRPOST_KERNEL_GRAM, LRPOST_KERNEL_PROJ = 0, 1, 2, 3, 4
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "ENOCONV", -4: "EBREAKDOWN", -5: "EHIP"}
 
 

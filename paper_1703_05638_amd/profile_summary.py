@@ -32,11 +32,12 @@ KERNEL_SOURCES = {
     "k_cheb": ("void k_cheb(", "template void mg_smooth_step<float>"),
     "k_mg": ("__device__ inline void strip_of(", "template void mg_up<float>"),
     "k_gram": ("// FP64 Gram on the matrix cores.", "void sum_partials("),
+    "k_proj": ("// FP64 projection on the matrix cores,", "template void proj<float>("),
 }
 
 
 def _source_key(regex):
-    for key in ("k_gram", "k_mg"):
+    for key in ("k_gram", "k_proj", "k_mg"):
         if key in regex:
             return key
     return "k_cheb"
