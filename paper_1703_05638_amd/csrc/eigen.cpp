@@ -149,11 +149,9 @@ class SharedBasis {
       if (pass > 0) P->apply_op(rw, R.as<double>(), KR.as<double>(), {{1.0, 1.0}});
       double* dst = pass == 0 ? G : G2;
       P->gram_dev(s0, U.as<double>(), rw, KR.as<double>(), dst);
-      P->dense->scal(s0 * rw, -1.0, dst);
-      P->proj_dev(s0, U.as<double>(), dst, s0, rw, R.as<double>(), 1.0);
+      P->proj_dev(s0, U.as<double>(), dst, s0, rw, R.as<double>(), 1.0, -1.0);
       if (pass > 0) axpby<double>(P->st, (long)s0 * rw, 1, G2, (long)s0 * rw, G, (long)s0 * rw, 1.0, 1.0);
     }
-    if (s0 > 0) P->dense->scal(s0 * rw, -1.0, G);
     // remainder R w.B^T: truncated relative to ||w||, (K+M)-orthonormal spatial factor
     LowRank rem;
     rem.nx = nx;
@@ -179,11 +177,9 @@ class SharedBasis {
         P->apply_op(rq, rem.a(), KR.as<double>(), {{1.0, 1.0}});
         double* dst = pass == 0 ? Cq : C2;
         P->gram_dev(s0, U.as<double>(), rq, KR.as<double>(), dst);
-        P->dense->scal(s0 * rq, -1.0, dst);
-        P->proj_dev(s0, U.as<double>(), dst, s0, rq, rem.a(), 1.0);
+        P->proj_dev(s0, U.as<double>(), dst, s0, rq, rem.a(), 1.0, -1.0);
         if (pass > 0) axpby<double>(P->st, (long)s0 * rq, 1, C2, (long)s0 * rq, Cq, (long)s0 * rq, 1.0, 1.0);
       }
-      P->dense->scal(s0 * rq, -1.0, Cq);
       P->apply_op(rq, rem.a(), KR.as<double>(), {{1.0, 1.0}});
       std::vector<double> Gq;
       P->gram(rq, rem.a(), rq, KR.as<double>(), Gq);

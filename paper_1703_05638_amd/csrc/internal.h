@@ -172,8 +172,8 @@ class Problem {
   void gram_dev(int m, const double* A, int q, const double* B, double* C);
   // C = beta C + A Q (Q host m x p)
   void proj(int m, const double* A, const std::vector<double>& Q, int p, double* C, double beta);
-  // C = beta C + A Q (Q device m x p, leading dimension ldq)
-  void proj_dev(int m, const double* A, const double* Q, int ldq, int p, double* C, double beta);
+  // C = beta C + alpha A Q (Q device m x p, leading dimension ldq)
+  void proj_dev(int m, const double* A, const double* Q, int ldq, int p, double* C, double beta, double alpha = 1.0);
   // Y = L X for ncols nodal vectors, L = (alpha tau)^{-1/2} (K+M)^{-1/2} (symmetric root)
   void prior_sqrt(int ncols, const double* X, double* Y);
   // symmetric eigenproblem of a host matrix (ascending), on the GPU above a small size

@@ -1243,7 +1243,9 @@ __device__ __forceinline__ void proj_tile(long nrows, int m, const double* __res
       }
 }
 
-__global__ __launch_bounds__(256) void k_proj_mfma(long nrows, int m, const double* __restrict__ A, long lda,
+// (four waves per SIMD: the 1017 row tiles of a 255 x 255 mesh then fit in
+// one round of 256 CUs x 4 workgroups)
+__global__ __launch_bounds__(256, 4) void k_proj_mfma(long nrows, int m, const double* __restrict__ A, long lda,
                                                    const double* __restrict__ Q, int ldq, int p,
                                                    double* __restrict__ C, long ldc, double beta) {
   proj_tile(nrows, m, A, lda, Q, ldq, p, C, C, ldc, 1.0, beta, (long)blockIdx.x * PR, blockIdx.y * PC);
@@ -1252,7 +1254,7 @@ __global__ __launch_bounds__(256) void k_proj_mfma(long nrows, int m, const doub
 // Several independent products C_g = beta Cin_g + alpha A_g Q_g in one launch
 // (blockIdx.z = g; tiles outside a product's shape return before any
 // barrier).  Each tile is computed exactly as by a launch of its own.
-__global__ __launch_bounds__(256) void k_proj_grouped(ProjGroups gs, double alpha, double beta) {
+__global__ __launch_bounds__(256, 4) void k_proj_grouped(ProjGroups gs, double alpha, double beta) {
   const ProjGroup& g = gs.g[blockIdx.z];
   const long row0 = (long)blockIdx.x * PR;
   const int col0 = blockIdx.y * PC;

@@ -600,10 +600,17 @@ void Problem::gram_dev(int m, const double* A, int q, const double* B, double* C
   LRP_HIP(hipGetLastError());
 }
 
-void Problem::proj_dev(int m, const double* A, const double* Q, int ldq, int p, double* C, double beta) {
+void Problem::proj_dev(int m, const double* A, const double* Q, int ldq, int p, double* C, double beta,
+                       double alpha) {
   if (p <= 0) return;
-  timed(LRPOST_KERNEL_PROJ, sizeof(double) * (double)(m + (beta != 0.0 ? 2 : 1) * p) * nx,
-        [&] { ::lrp::proj<double>(st, nx, m, A, nx, Q, ldq, p, C, nx, beta); }, 2.0 * m * p * (double)nx);
+  timed(LRPOST_KERNEL_PROJ, sizeof(double) * (double)(m + (beta != 0.0 ? 2 : 1) * p) * nx, [&] {
+    if (alpha == 1.0 || m <= 0) {
+      ::lrp::proj<double>(st, nx, m, A, nx, Q, ldq, p, C, nx, beta);
+    } else {
+      const ProjGroup g{A, Q, C, C, nx, nx, nx, ldq, m, p};
+      proj_grouped(st, 1, &g, alpha, beta);
+    }
+  }, 2.0 * m * p * (double)nx);
   LRP_HIP(hipGetLastError());
 }
 
@@ -888,8 +895,7 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
     if (!mw_ready) apply_op(kc, X, MW, Mop);
     st_c_.ensure(sizeof(double) * (size_t)q[j] * kc);
     gram_dev(q[j], Q, kc, MW, st_c_.as<double>());
-    dense->scal(q[j] * kc, -1.0, st_c_.as<double>());
-    proj_dev(q[j], Q, st_c_.as<double>(), q[j], kc, X, 1.0);
+    proj_dev(q[j], Q, st_c_.as<double>(), q[j], kc, X, 1.0, -1.0);
   };
   // eigenpairs of a block's Gram G (kc x kc, host) above thresh -> the
   // orthonormalizing transform Tm (kc x kn); -1 if the eigensolve failed.
