@@ -930,7 +930,7 @@ int gram_chunks(long nrows, int m, int q) {
 // time (coalesced: 32 consecutive lanes read 32 consecutive rows, 256 bytes,
 // of one column), stored [column][row] so that each MFMA operand is one LDS
 // read per lane; the next stage is fetched into registers while the matrix
-// cores work on the current one.  The waves form a 4 x 2 grid; each owns
+// cores work on the current one, and stored to the second LDS buffer.  The waves form a 4 x 2 grid; each owns
 // (16 BM) x 32 of the tile as BM x 2 blocks of v_mfma_f64_16x16x4f64: for
 // the 16 x 4 operand lane l holds element (l % 16, l / 16), for the 4 x 16
 // operand element (l / 16, l % 16), and the 16 x 16 result element
@@ -949,7 +949,7 @@ __global__ __launch_bounds__(GTH) void k_gram_mfma(long nrows, long rows_per_chu
   constexpr int GM = 64 * BM;                 // output tile height (m direction)
   constexpr int NC = GM + GQ;                 // staged columns per row
   constexpr int NU = NC / (GTH / GK);         // columns per loading thread
-  __shared__ double S[NC][GK + 1];            // [column][row]: A columns, then B columns
+  __shared__ double S[2][NC][GK + 1];         // two stages of [column][row]: A columns, then B columns
   const int tm = blockIdx.x, tq = blockIdx.y, chunk = blockIdx.z;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 3, wq = wave >> 2;
@@ -993,24 +993,33 @@ __global__ __launch_bounds__(GTH) void k_gram_mfma(long nrows, long rows_per_chu
       rv[u] = v * ((rin && cok[u]) ? 1.0 : 0.0);
     }
   };
-  if (nst > 0) fetch(0);
+  // stage it is read from buffer it % 2 while stage it + 1 arrives in
+  // registers and is then stored to the other buffer: one barrier per stage
   const int ci = lane & 15, ck = lane >> 4;
-  for (long it = 0; it < nst; ++it) {
+  if (nst > 0) {
+    fetch(0);
 #pragma unroll
-    for (int u = 0; u < NU; ++u) S[lc + (GTH / GK) * u][lr] = rv[u];
-    __syncthreads();
+    for (int u = 0; u < NU; ++u) S[0][lc + (GTH / GK) * u][lr] = rv[u];
+  }
+  __syncthreads();
+  for (long it = 0; it < nst; ++it) {
+    const int cb = (int)(it & 1);
     if (it + 1 < nst) fetch(it + 1);
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 4) {
       double bf[2];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bf[b] = S[GM + wq * 32 + 16 * b + ci][kk + ck];
+      for (int b = 0; b < 2; ++b) bf[b] = S[cb][GM + wq * 32 + 16 * b + ci][kk + ck];
 #pragma unroll
       for (int a = 0; a < BM; ++a) {
-        const double af = S[wm * 16 * BM + 16 * a + ci][kk + ck];
+        const double af = S[cb][wm * 16 * BM + 16 * a + ci][kk + ck];
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf[b], acc[a][b], 0, 0, 0);
       }
+    }
+    if (it + 1 < nst) {
+#pragma unroll
+      for (int u = 0; u < NU; ++u) S[cb ^ 1][lc + (GTH / GK) * u][lr] = rv[u];
     }
     __syncthreads();
   }
