@@ -170,6 +170,10 @@ class Problem {
   void gram(int m, const double* A, int q, const double* B, std::vector<double>& C);
   // C (device, m x q, leading dimension m) = A^T B
   void gram_dev(int m, const double* A, int q, const double* B, double* C);
+  // several device Gram products (nx rows; part is set here) in grouped launches
+  void gram_dev_grouped(std::vector<GramGroup>& gs);
+  // several device projections C_g = beta C_g + alpha A_g Q_g in grouped launches
+  void proj_dev_grouped(const std::vector<ProjGroup>& pg, double alpha, double beta);
   // C = beta C + A Q (Q host m x p)
   void proj(int m, const double* A, const std::vector<double>& Q, int p, double* C, double beta);
   // C = beta C + alpha A Q (Q device m x p, leading dimension ldq)
@@ -246,10 +250,10 @@ class Problem {
   void st_prepare(const LowRank& F, bool adjoint, StPrep& pr);
   double* st_pole_solves(const std::vector<const StPrep*>& prs);
   // per source: M-orthonormal basis Q (nx x q) and projected solution Zp
-  // (q x nt); W2 and Kt are its working blocks while the basis is built
+  // (q x nt); Kt (projected tau K) is built with the basis
   struct StFin {
     int q = 0;
-    DevMem Q, Zp, W2, Kt;
+    DevMem Q, Zp, Kt;
   };
   void st_project_batch(const std::vector<StPrep>& prs, double* Wall, std::vector<StFin>& fins);
   void st_solve_projected(const std::vector<StPrep>& prs, const std::vector<int>& q, std::vector<StFin>& fins);
@@ -296,7 +300,7 @@ class Problem {
   DevMem mg_work_f_, mg_f_;
   void upload_mg_params(const std::vector<ShiftCoef>& ab);
   // space-time solver workspaces
-  DevMem st_gram_, st_g_, st_mw_, st_wall_, st_brep_, st_small_, st_c_, eig_work_;
+  DevMem st_gram_, st_g_, st_mw_, st_w2_, st_tm_, st_wall_, st_brep_, st_small_, st_c_, eig_work_;
 };
 
 void smoother_interval(double a, double bh2, double* lo, double* hi);

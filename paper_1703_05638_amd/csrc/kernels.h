@@ -41,10 +41,40 @@ constexpr int kCoarseLdsMaxN = 31;
 
 int gram_chunks(long nrows, int m, int q);       // float instance (LDS kernel)
 int gram_chunks_mfma(long nrows, int m, int q);  // double instance (FP64 MFMA kernel)
-// the two stages of gram<double>: per-chunk partial products on the matrix
-// cores (part: gram_chunks_mfma() x m x q doubles), then their sum into C
-void gram_mfma_partials(hipStream_t st, long nrows, int m, const double* A, long lda, int q, const double* B,
-                        long ldb, double* part);
+// Products of one launch: up to kProjGroupMax Gram products, projections,
+// diagonal shifts or copies.
+constexpr int kProjGroupMax = 8;
+// One Gram product C = A^T B (A nrows x m, B nrows x q; C m x q with leading
+// dimension ldc) and its partial-product scratch (gram_part_doubles()).
+struct GramGroup {
+  const double* A;
+  const double* B;
+  double* part;
+  double* C;
+  long lda, ldb, ldc;
+  long rpc;    // rows per chunk, set by gram_mfma_partials
+  int m, q;
+  int nchunk;  // set by gram_mfma_partials
+};
+struct GramGroups {
+  GramGroup g[kProjGroupMax];
+  int nchunk_max;
+};
+struct SumGroup {
+  const double* part;
+  double* C;
+  long ldc;
+  int m, q, nchunk;
+};
+struct SumGroups {
+  SumGroup g[kProjGroupMax];
+};
+// the two stages of gram<double> for several products: per-chunk partial
+// products on the matrix cores (each product chunked by its own shape, so its
+// result does not depend on the others), then their sums into each C
+void gram_mfma_partials(hipStream_t st, long nrows, int count, GramGroup* groups);
+void sum_partials_grouped(hipStream_t st, int count, const GramGroup* groups);
+long gram_part_doubles(long nrows, int m, int q);
 void sum_partials(hipStream_t st, int nchunk, long count, const double* part, double* C);
 // C (device, m x q, double) = A^T B; part: device scratch of gram_chunks()*m*q
 // doubles (gram_chunks_mfma() for T = double).
@@ -65,7 +95,6 @@ void proj<double>(hipStream_t st, long nrows, int m, const double* A, long lda, 
 // Several independent products C_g = beta Cin_g + alpha A_g Q_g (A_g nrows x m,
 // Q_g m x p, C_g nrows x p, Cin_g may be C_g) on the matrix cores, up to
 // kProjGroupMax per launch; each product is computed exactly as by proj.
-constexpr int kProjGroupMax = 8;
 struct ProjGroup {
   const double* A;
   const double* Q;

@@ -942,15 +942,13 @@ constexpr int GK = 32;   // rows per LDS stage
 constexpr int GTH = 512;  // threads per workgroup
 
 template <int BM>
-__global__ __launch_bounds__(GTH) void k_gram_mfma(long nrows, long rows_per_chunk, int m,
-                                                   const double* __restrict__ A, long lda, int q,
-                                                   const double* __restrict__ B, long ldb,
-                                                   double* __restrict__ part) {
+__device__ __forceinline__ void gram_tile(long nrows, long rows_per_chunk, int m, const double* __restrict__ A,
+                                          long lda, int q, const double* __restrict__ B, long ldb,
+                                          double* __restrict__ part, int tm, int tq, int chunk) {
   constexpr int GM = 64 * BM;                 // output tile height (m direction)
   constexpr int NC = GM + GQ;                 // staged columns per row
   constexpr int NU = NC / (GTH / GK);         // columns per loading thread
   __shared__ double S[2][NC][GK + 1];         // two stages of [column][row]: A columns, then B columns
-  const int tm = blockIdx.x, tq = blockIdx.y, chunk = blockIdx.z;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 3, wq = wave >> 2;
   const long r0 = (long)chunk * rows_per_chunk;
@@ -1037,6 +1035,17 @@ __global__ __launch_bounds__(GTH) void k_gram_mfma(long nrows, long rows_per_chu
       }
 }
 
+// Several Gram products in one launch: blockIdx.z = group * nchunk_max +
+// chunk; each product keeps its own chunking (rows per chunk from its own
+// shape), so its partial sums are exactly those of a launch of its own.
+template <int BM>
+__global__ __launch_bounds__(GTH) void k_gram_mfma(long nrows, GramGroups gs) {
+  const int gi = blockIdx.z / gs.nchunk_max, chunk = blockIdx.z % gs.nchunk_max;
+  const GramGroup& g = gs.g[gi];
+  if (chunk >= g.nchunk || (int)blockIdx.x * 64 * BM >= g.m || (int)blockIdx.y * GQ >= g.q) return;
+  gram_tile<BM>(nrows, g.rpc, g.m, g.A, g.lda, g.q, g.B, g.ldb, g.part, blockIdx.x, blockIdx.y, chunk);
+}
+
 // tile height 64 BM: the smallest that covers m, at most 192 (the 256-row
 // tile needs 146 registers per lane, which leaves one workgroup per CU; wider
 // products take several tiles)
@@ -1071,18 +1080,30 @@ void gram(hipStream_t st, long nrows, int m, const T* A, long lda, int q, const 
   hipLaunchKernelGGL(k_sum_partials, dim3((count + SP_X - 1) / SP_X), dim3(SP_X * SP_Y), 0, st, nchunk, count, part, C);
 }
 
-void gram_mfma_partials(hipStream_t st, long nrows, int m, const double* A, long lda, int q, const double* B,
-                        long ldb, double* part) {
-  if (m <= 0 || q <= 0) return;
-  const int nchunk = gram_chunks_mfma(nrows, m, q);
-  long rpc = (nrows + nchunk - 1) / nchunk;
-  rpc = ((rpc + GK - 1) / GK) * GK;
-  const int bm = gram_bm(m), gm = 64 * bm;
-  dim3 grd((m + gm - 1) / gm, (q + GQ - 1) / GQ, nchunk);
-  switch (bm) {
-    case 1: hipLaunchKernelGGL((k_gram_mfma<1>), grd, dim3(GTH), 0, st, nrows, rpc, m, A, lda, q, B, ldb, part); break;
-    case 2: hipLaunchKernelGGL((k_gram_mfma<2>), grd, dim3(GTH), 0, st, nrows, rpc, m, A, lda, q, B, ldb, part); break;
-    default: hipLaunchKernelGGL((k_gram_mfma<3>), grd, dim3(GTH), 0, st, nrows, rpc, m, A, lda, q, B, ldb, part);
+void gram_mfma_partials(hipStream_t st, long nrows, int count, GramGroup* groups) {
+  for (int g0 = 0; g0 < count; g0 += kProjGroupMax) {
+    GramGroups gs{};
+    const int n = std::min(kProjGroupMax, count - g0);
+    int mmax = 0, qmax = 0, cmax = 1;
+    for (int i = 0; i < n; ++i) {
+      GramGroup& g = groups[g0 + i];
+      g.nchunk = (g.m > 0 && g.q > 0) ? gram_chunks_mfma(nrows, g.m, g.q) : 0;
+      long rpc = g.nchunk > 0 ? (nrows + g.nchunk - 1) / g.nchunk : 0;
+      g.rpc = ((rpc + GK - 1) / GK) * GK;
+      gs.g[i] = g;
+      mmax = std::max(mmax, g.m);
+      qmax = std::max(qmax, g.q);
+      cmax = std::max(cmax, g.nchunk);
+    }
+    if (mmax <= 0 || qmax <= 0) continue;
+    gs.nchunk_max = cmax;
+    const int bm = gram_bm(mmax), gm = 64 * bm;
+    dim3 grd((mmax + gm - 1) / gm, (qmax + GQ - 1) / GQ, n * cmax);
+    switch (bm) {
+      case 1: hipLaunchKernelGGL((k_gram_mfma<1>), grd, dim3(GTH), 0, st, nrows, gs); break;
+      case 2: hipLaunchKernelGGL((k_gram_mfma<2>), grd, dim3(GTH), 0, st, nrows, gs); break;
+      default: hipLaunchKernelGGL((k_gram_mfma<3>), grd, dim3(GTH), 0, st, nrows, gs);
+    }
   }
 }
 
@@ -1091,12 +1112,64 @@ void sum_partials(hipStream_t st, int nchunk, long count, const double* part, do
   hipLaunchKernelGGL(k_sum_partials, dim3((count + SP_X - 1) / SP_X), dim3(SP_X * SP_Y), 0, st, nchunk, count, part, C);
 }
 
+// C_g (m x q, leading dimension ldc) = the sum of the nchunk partial products,
+// for several products in one launch (blockIdx.y = g)
+__global__ __launch_bounds__(SP_X * SP_Y) void k_sum_partials_grouped(SumGroups gs) {
+  const SumGroup& g = gs.g[blockIdx.y];
+  const long count = (long)g.m * g.q;
+  if ((long)blockIdx.x * SP_X >= count) return;
+  __shared__ double red[SP_Y][SP_X + 1];
+  const int tx = threadIdx.x % SP_X, ty = threadIdx.x / SP_X;
+  const long idx = (long)blockIdx.x * SP_X + tx;
+  const long idc = idx < count ? idx : count - 1;
+  const double* __restrict__ part = g.part;
+  double s = 0.0;
+  int c = ty;
+  for (; c + 3 * SP_Y < g.nchunk; c += 4 * SP_Y) {
+    const double a0 = part[(long)c * count + idc], a1 = part[(long)(c + SP_Y) * count + idc];
+    const double a2 = part[(long)(c + 2 * SP_Y) * count + idc], a3 = part[(long)(c + 3 * SP_Y) * count + idc];
+    s += a0;
+    s += a1;
+    s += a2;
+    s += a3;
+  }
+  for (; c < g.nchunk; c += SP_Y) s += part[(long)c * count + idc];
+  red[ty][tx] = s;
+  __syncthreads();
+  if (ty == 0 && idx < count) {
+    double t = red[0][tx];
+#pragma unroll
+    for (int y = 1; y < SP_Y; ++y) t += red[y][tx];
+    g.C[(idx % g.m) + (idx / g.m) * g.ldc] = t;
+  }
+}
+
+void sum_partials_grouped(hipStream_t st, int count, const GramGroup* groups) {
+  for (int g0 = 0; g0 < count; g0 += kProjGroupMax) {
+    SumGroups gs{};
+    const int n = std::min(kProjGroupMax, count - g0);
+    long cmax = 0;
+    for (int i = 0; i < n; ++i) {
+      const GramGroup& g = groups[g0 + i];
+      gs.g[i] = SumGroup{g.part, g.C, g.ldc, g.m, g.q, g.nchunk};
+      if (g.nchunk > 0) cmax = std::max(cmax, (long)g.m * g.q);
+    }
+    if (cmax <= 0) continue;
+    hipLaunchKernelGGL(k_sum_partials_grouped, dim3((cmax + SP_X - 1) / SP_X, n), dim3(SP_X * SP_Y), 0, st, gs);
+  }
+}
+
+long gram_part_doubles(long nrows, int m, int q) {
+  return (m > 0 && q > 0) ? (long)gram_chunks_mfma(nrows, m, q) * m * q : 0;
+}
+
 template <>
 void gram<double>(hipStream_t st, long nrows, int m, const double* A, long lda, int q, const double* B, long ldb,
                   double* C, double* part) {
   if (m <= 0 || q <= 0) return;
-  gram_mfma_partials(st, nrows, m, A, lda, q, B, ldb, part);
-  sum_partials(st, gram_chunks_mfma(nrows, m, q), (long)m * q, part, C);
+  GramGroup g{A, B, part, C, lda, ldb, m, 0, m, q, 0};
+  gram_mfma_partials(st, nrows, 1, &g);
+  sum_partials_grouped(st, 1, &g);
 }
 template void gram<float>(hipStream_t, long, int, const float*, long, int, const float*, long, double*, double*);
 

@@ -591,12 +591,31 @@ void Problem::proj(int m, const double* A, const std::vector<double>& Q, int p, 
 // with 2 m q nx flops.
 void Problem::gram_dev(int m, const double* A, int q, const double* B, double* C) {
   if (m <= 0 || q <= 0) return;
-  const int nchunk = gram_chunks_mfma(nx, m, q);
-  gram_part_.ensure(sizeof(double) * (size_t)nchunk * m * q);
-  timed(LRPOST_KERNEL_GRAM, sizeof(double) * (double)(m + q) * nx,
-        [&] { gram_mfma_partials(st, nx, m, A, nx, q, B, nx, gram_part_.as<double>()); },
-        2.0 * m * q * (double)nx);
-  sum_partials(st, nchunk, (long)m * q, gram_part_.as<double>(), C);
+  std::vector<GramGroup> g{GramGroup{A, B, nullptr, C, nx, nx, m, 0, m, q, 0}};
+  gram_dev_grouped(g);
+}
+
+// Several Gram products A_g^T B_g (nx rows) with one launch per stage for up
+// to kProjGroupMax of them; each result is the one gram_dev gives.
+void Problem::gram_dev_grouped(std::vector<GramGroup>& gs) {
+  std::vector<size_t> off(gs.size() + 1, 0);
+  for (size_t i = 0; i < gs.size(); ++i) off[i + 1] = off[i] + (size_t)gram_part_doubles(nx, gs[i].m, gs[i].q);
+  if (off.back() == 0) return;
+  gram_part_.ensure(sizeof(double) * off.back());
+  for (size_t i = 0; i < gs.size(); ++i) gs[i].part = gram_part_.as<double>() + off[i];
+  for (size_t g0 = 0; g0 < gs.size(); g0 += kProjGroupMax) {
+    const int n = (int)std::min<size_t>(kProjGroupMax, gs.size() - g0);
+    double bytes = 0.0, flops = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const GramGroup& g = gs[g0 + i];
+      if (g.m <= 0 || g.q <= 0) continue;
+      bytes += sizeof(double) * (double)(g.m + g.q) * nx;
+      flops += 2.0 * g.m * g.q * (double)nx;
+    }
+    if (bytes == 0.0) continue;
+    timed(LRPOST_KERNEL_GRAM, bytes, [&] { gram_mfma_partials(st, nx, n, gs.data() + g0); }, flops);
+    sum_partials_grouped(st, n, gs.data() + g0);
+  }
   LRP_HIP(hipGetLastError());
 }
 
@@ -611,6 +630,22 @@ void Problem::proj_dev(int m, const double* A, const double* Q, int ldq, int p, 
       proj_grouped(st, 1, &g, alpha, beta);
     }
   }, 2.0 * m * p * (double)nx);
+  LRP_HIP(hipGetLastError());
+}
+
+// Several projections C_g = beta C_g + alpha A_g Q_g (nx rows), grouped
+// launches credited like proj_dev.
+void Problem::proj_dev_grouped(const std::vector<ProjGroup>& pg, double alpha, double beta) {
+  for (size_t g0 = 0; g0 < pg.size(); g0 += kProjGroupMax) {
+    const int n = (int)std::min<size_t>(kProjGroupMax, pg.size() - g0);
+    double bytes = 0.0, flops = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const ProjGroup& g = pg[g0 + i];
+      bytes += sizeof(double) * (double)(g.m + (beta != 0.0 ? 2 : 1) * g.p) * g.nrows;
+      flops += 2.0 * g.m * g.p * (double)g.nrows;
+    }
+    timed(LRPOST_KERNEL_PROJ, bytes, [&] { proj_grouped(st, n, pg.data() + g0, alpha, beta); }, flops);
+  }
   LRP_HIP(hipGetLastError());
 }
 
@@ -767,8 +802,8 @@ void Problem::st_prepare(const LowRank& F, bool adjoint, StPrep& pr) {
 
 
 // Pole solves of a batch of prepared sources in one multigrid solve with
-// per-column shifts: Wall (nx x sum_j r1_j npol) holds, source after
-// source and pole after pole, (tau K + p_i M)^{-1} Fb_j.
+// per-column shifts: Wall (nx x sum_j r1_j npol) holds, pole after pole and
+// source after source, (tau K + p_i M)^{-1} Fb_j.
 double* Problem::st_pole_solves(const std::vector<const StPrep*>& prs) {
   const int npol = (int)poles.size();
   long cols = 0;
@@ -778,16 +813,22 @@ double* Problem::st_pole_solves(const std::vector<const StPrep*>& prs) {
   st_brep_.ensure(sizeof(double) * (size_t)nx * cols);
   double* Wall = st_wall_.as<double>();
   double* Brep = st_brep_.as<double>();
+  // pole-major: the sources' columns for pole i are adjacent (block i of
+  // width sum r1), the first block assembled from the sources and copied on
   std::vector<ShiftCoef> ab((size_t)cols);
+  const long R1 = cols / npol;
   long off = 0;
-  for (auto* pr : prs)
-    for (int i = 0; i < npol; ++i) {
-      if (pr->r1 == 0) continue;
-      LRP_HIP(hipMemcpyAsync(Brep + (size_t)off * nx, pr->Fb.p, sizeof(double) * (size_t)nx * pr->r1,
-                             hipMemcpyDeviceToDevice, st));
-      for (int c = 0; c < pr->r1; ++c) ab[(size_t)off + c] = {tau, poles[i]};
-      off += pr->r1;
-    }
+  for (auto* pr : prs) {
+    if (pr->r1 == 0) continue;
+    LRP_HIP(hipMemcpyAsync(Brep + (size_t)off * nx, pr->Fb.p, sizeof(double) * (size_t)nx * pr->r1,
+                           hipMemcpyDeviceToDevice, st));
+    off += pr->r1;
+  }
+  for (int i = 1; i < npol; ++i)
+    LRP_HIP(hipMemcpyAsync(Brep + (size_t)i * R1 * nx, Brep, sizeof(double) * (size_t)nx * R1,
+                           hipMemcpyDeviceToDevice, st));
+  for (int i = 0; i < npol; ++i)
+    for (long c = 0; c < R1; ++c) ab[(size_t)i * R1 + c] = {tau, poles[i]};
   mg_solve((int)cols, Brep, Wall, ab, st_cycles);
   return Wall;
 }
@@ -857,45 +898,72 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
   // less than 1e-4 of their norm (they were inside span(Q)).  A Gram-based
   // Cholesky cannot tell nearly dependent directions from rounding noise, so
   // it is not used here.  The sources of the batch go through the pole blocks
-  // in lockstep, so that their small Gram matrices reach the host together:
-  // two round trips per pole block for the whole batch.  Each source's
+  // in lockstep: their small Gram matrices reach the host together (two round
+  // trips per pole block for the whole batch), the stencil products of their
+  // blocks are one launch (the blocks of one pole are adjacent columns), and
+  // their Gram products and projections are grouped launches.  Each source's
   // arithmetic is the same as on its own.
   const int nb = (int)prs.size();
   const int npol = (int)poles.size();
   const std::vector<ShiftCoef> Mop{{0.0, 1.0}};
   const std::vector<ShiftCoef> Kop{{tau, 0.0}};
-  std::vector<double*> Wb(nb, nullptr);
-  std::vector<int> q(nb, 0);
+  std::vector<int> q(nb, 0), pre(nb + 1, 0);
+  std::vector<size_t> coff(nb + 1, 0), toff(nb + 1, 0);
   int rmax = 0;
-  long off = 0;
   for (int j = 0; j < nb; ++j) {
     fins[j].q = 0;
     const int r1 = prs[j].r1;
-    if (Wall) Wb[j] = Wall + (size_t)off * nx;
-    off += (long)r1 * npol;
+    pre[j + 1] = pre[j] + r1;
+    coff[j + 1] = coff[j] + (size_t)r1 * npol * r1;  // sweep coefficients, at most qmax x r1
+    toff[j + 1] = toff[j] + (size_t)r1 * r1;         // orthonormalizing transforms
     rmax = std::max(rmax, r1);
     if (r1 == 0) continue;
     const int qmax = r1 * npol;
     fins[j].Q.ensure(sizeof(double) * (size_t)nx * qmax);
-    fins[j].W2.ensure(sizeof(double) * (size_t)nx * r1);
     fins[j].Kt.ensure(sizeof(double) * (size_t)qmax * qmax);  // q x q projected tau K, leading dimension qmax
   }
-  if (rmax == 0) return;
-  st_mw_.ensure(sizeof(double) * (size_t)nx * rmax);
-  double* MW = st_mw_.as<double>();
+  if (rmax == 0 || !Wall) return;
+  const int R1 = pre[nb];
+  // pole block ip of source j: Wall columns ip R1 + pre[j] ...
+  auto Wj = [&](int ip, int j) { return Wall + ((size_t)ip * R1 + pre[j]) * nx; };
+  st_mw_.ensure(sizeof(double) * (size_t)nx * R1);
+  st_w2_.ensure(sizeof(double) * (size_t)nx * R1);
+  st_c_.ensure(sizeof(double) * coff[nb]);
+  st_tm_.ensure(sizeof(double) * toff[nb]);
+  double* MW = st_mw_.as<double>();  // M (or tau K) times the blocks of all sources
+  double* W2 = st_w2_.as<double>();  // the normalized blocks, source after source
+  double* Cd = st_c_.as<double>();
+  double* Td = st_tm_.as<double>();
   const size_t gs = (size_t)rmax * rmax;  // one Gram slot; two per source
   st_g_.ensure(sizeof(double) * gs * 2 * nb);
   double* Gd = st_g_.as<double>();
-  std::vector<double> Gh(gs * 2 * nb);
+  std::vector<double> Gh(gs * 2 * nb), Th(toff[nb]);
   auto slot = [&](int j, int k) { return (size_t)(2 * j + k) * gs; };
-  // X -= Q (Q^T M X), all on the device (mw_ready: MW already holds M X)
-  auto sweep = [&](int j, int kc, double* X, bool mw_ready) {
-    if (q[j] == 0 || kc == 0) return;
-    const double* Q = fins[j].Q.as<double>();
-    if (!mw_ready) apply_op(kc, X, MW, Mop);
-    st_c_.ensure(sizeof(double) * (size_t)q[j] * kc);
-    gram_dev(q[j], Q, kc, MW, st_c_.as<double>());
-    proj_dev(q[j], Q, st_c_.as<double>(), q[j], kc, X, 1.0, -1.0);
+  auto gram_g = [&](const double* A, const double* B, double* C, int m, int qq, long ldc) {
+    return GramGroup{A, B, nullptr, C, nx, nx, ldc, 0, m, qq, 0};
+  };
+  auto proj_g = [&](const double* A, const double* Qm, int ldq, double* C, int m, int p) {
+    return ProjGroup{A, Qm, C, C, nx, nx, nx, ldq, m, p};
+  };
+  // the sweep X_j -= Q_j (Q_j^T M X_j) of every source with a basis (M X_j
+  // in MW at column mwc[j]); extra Gram products ride along in the launch
+  auto sweep = [&](const std::vector<int>& kc, const std::vector<double*>& X, const std::vector<int>& mwc,
+                   std::vector<GramGroup> gg) {
+    std::vector<ProjGroup> pg;
+    for (int j = 0; j < nb; ++j) {
+      if (q[j] == 0 || kc[j] == 0) continue;
+      const double* Q = fins[j].Q.as<double>();
+      gg.push_back(gram_g(Q, MW + (size_t)mwc[j] * nx, Cd + coff[j], q[j], kc[j], q[j]));
+      pg.push_back(proj_g(Q, Cd + coff[j], q[j], X[j], q[j], kc[j]));
+    }
+    gram_dev_grouped(gg);
+    proj_dev_grouped(pg, -1.0, 1.0);
+  };
+  // the host transforms Tm[j] (rows x cols[j]) to the device, one upload
+  auto upload = [&](const std::vector<std::vector<double>>& Tm, const std::vector<int>& cols) {
+    for (int j = 0; j < nb; ++j)
+      if (cols[j] > 0) std::copy(Tm[j].begin(), Tm[j].end(), Th.begin() + toff[j]);
+    to_device(Td, Th.data(), Th.size());
   };
   // eigenpairs of a block's Gram G (kc x kc, host) above thresh -> the
   // orthonormalizing transform Tm (kc x kn); -1 if the eigensolve failed.
@@ -931,21 +999,26 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
       for (int i = 0; i < kc; ++i) Tm[(size_t)c * kc + i] = Uv[(size_t)kk[c] * kc + i] / std::sqrt(wv[kk[c]]);
     return kn;
   };
-  std::vector<int> k1(nb, 0), k2(nb, 0);
+  std::vector<int> k1(nb, 0), k2(nb, 0), pre2(nb + 1, 0), mw1(nb), mw2(nb);
   std::vector<double> ref(nb, 0.0);
   std::vector<std::vector<double>> Tm(nb);
+  std::vector<double*> X1(nb), X2(nb);
+  for (int j = 0; j < nb; ++j) mw1[j] = pre[j];
   for (int ip = 0; ip < npol; ++ip) {
     // stage 1: reference norms of the raw block, first sweep, Gram of the swept block
+    std::vector<int> r1s(nb);
+    std::vector<GramGroup> g0, g1;
     for (int j = 0; j < nb; ++j) {
-      const int r1 = prs[j].r1;
-      if (r1 == 0) continue;
-      double* W = Wb[j] + (size_t)ip * r1 * nx;
-      apply_op(r1, W, MW, Mop);
-      gram_dev(r1, W, r1, MW, Gd + slot(j, 0));
-      sweep(j, r1, W, true);
-      apply_op(r1, W, MW, Mop);
-      gram_dev(r1, W, r1, MW, Gd + slot(j, 1));
+      r1s[j] = prs[j].r1;
+      X1[j] = Wj(ip, j);
+      if (r1s[j] == 0) continue;
+      g0.push_back(gram_g(X1[j], MW + (size_t)pre[j] * nx, Gd + slot(j, 0), r1s[j], r1s[j], r1s[j]));
+      g1.push_back(gram_g(X1[j], MW + (size_t)pre[j] * nx, Gd + slot(j, 1), r1s[j], r1s[j], r1s[j]));
     }
+    apply_op(R1, Wj(ip, 0), MW, Mop);
+    sweep(r1s, X1, mw1, g0);  // the raw Gram shares the launch of the sweep's products
+    apply_op(R1, Wj(ip, 0), MW, Mop);
+    gram_dev_grouped(g1);
     to_host(Gh.data(), Gd, Gh.size());
     for (int j = 0; j < nb; ++j) {
       const int r1 = prs[j].r1;
@@ -955,42 +1028,55 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
     host_parallel(nb, [&](int j) {
       k1[j] = (prs[j].r1 > 0 && ref[j] > 0) ? svqb_host(prs[j].r1, Gh.data() + slot(j, 1), 1e-22 * ref[j], Tm[j]) : 0;
     });
-    bool any = false;
     for (int j = 0; j < nb; ++j) {
       if (k1[j] < 0) fail(LRPOST_EBREAKDOWN, "basis Gram eigensolve");
-      if (k1[j] == 0) continue;
-      const int r1 = prs[j].r1;
-      proj(r1, Wb[j] + (size_t)ip * r1 * nx, Tm[j], k1[j], fins[j].W2.as<double>(), 0.0);
-      any = true;
+      pre2[j + 1] = pre2[j] + k1[j];
     }
-    if (!any) continue;
+    const int K1 = pre2[nb];
+    if (K1 == 0) continue;
+    upload(Tm, k1);
+    {
+      std::vector<ProjGroup> pg;
+      for (int j = 0; j < nb; ++j) {
+        X2[j] = W2 + (size_t)pre2[j] * nx;
+        mw2[j] = pre2[j];
+        if (k1[j] > 0) pg.push_back(proj_g(X1[j], Td + toff[j], prs[j].r1, X2[j], prs[j].r1, k1[j]));
+      }
+      proj_dev_grouped(pg, 1.0, 0.0);
+    }
     // stage 2: second sweep of the normalized block and its Gram
-    for (int j = 0; j < nb; ++j) {
-      if (k1[j] == 0) continue;
-      double* W2 = fins[j].W2.as<double>();
-      sweep(j, k1[j], W2, false);
-      apply_op(k1[j], W2, MW, Mop);
-      gram_dev(k1[j], W2, k1[j], MW, Gd + slot(j, 0));
-    }
+    std::vector<GramGroup> g2;
+    for (int j = 0; j < nb; ++j)
+      if (k1[j] > 0) g2.push_back(gram_g(X2[j], MW + (size_t)pre2[j] * nx, Gd + slot(j, 0), k1[j], k1[j], k1[j]));
+    apply_op(K1, W2, MW, Mop);
+    sweep(k1, X2, mw2, {});
+    apply_op(K1, W2, MW, Mop);
+    gram_dev_grouped(g2);
     to_host(Gh.data(), Gd, Gh.size());
     host_parallel(nb, [&](int j) { k2[j] = k1[j] > 0 ? svqb_host(k1[j], Gh.data() + slot(j, 0), 1e-8, Tm[j]) : 0; });
-    for (int j = 0; j < nb; ++j) {
+    for (int j = 0; j < nb; ++j)
       if (k2[j] < 0) fail(LRPOST_EBREAKDOWN, "basis Gram eigensolve");
+    upload(Tm, k2);
+    std::vector<ProjGroup> pg;
+    std::vector<GramGroup> gk;
+    for (int j = 0; j < nb; ++j) {
+      if (k2[j] == 0) continue;
+      double* Qn = fins[j].Q.as<double>() + (size_t)q[j] * nx;
+      pg.push_back(proj_g(X2[j], Td + toff[j], k1[j], Qn, k1[j], k2[j]));
+    }
+    proj_dev_grouped(pg, 1.0, 0.0);
+    // extend Kt = Q^T tau K Q by the new columns (upper triangle suffices)
+    for (int j = 0; j < nb; ++j) {
       const int kcols = k2[j];
       if (kcols == 0) continue;
       double* Q = fins[j].Q.as<double>();
-      double* Qn = Q + (size_t)q[j] * nx;
-      proj(k1[j], fins[j].W2.as<double>(), Tm[j], kcols, Qn, 0.0);
-      // extend Kt = Q^T tau K Q by the new columns (upper triangle suffices)
+      double* KQn = MW + (size_t)pre[j] * nx;
+      apply_op(kcols, Q + (size_t)q[j] * nx, KQn, Kop);
       const int qmax = prs[j].r1 * npol;
-      apply_op(kcols, Qn, MW, Kop);
-      gram_out_.ensure(sizeof(double) * (size_t)(q[j] + kcols) * kcols);
-      gram_dev(q[j] + kcols, Q, kcols, MW, gram_out_.as<double>());
-      LRP_HIP(hipMemcpy2DAsync(fins[j].Kt.as<double>() + (size_t)q[j] * qmax, sizeof(double) * qmax,
-                               gram_out_.as<double>(), sizeof(double) * (q[j] + kcols), sizeof(double) * (q[j] + kcols),
-                               kcols, hipMemcpyDeviceToDevice, st));
-      q[j] += kcols;
+      gk.push_back(gram_g(Q, KQn, fins[j].Kt.as<double>() + (size_t)q[j] * qmax, q[j] + kcols, kcols, qmax));
     }
+    gram_dev_grouped(gk);
+    for (int j = 0; j < nb; ++j) q[j] += k2[j];
   }
   PhaseTimer pt(this, kPhProjSolve);
   for (int j = 0; j < nb; ++j) stats.last_basis = q[j];
