@@ -247,7 +247,7 @@ class Problem {
     DevMem Fb;               // orthonormal spatial factor of the source (nx x r1)
     std::vector<double> F2p; // its temporal factor (nt x r1), time-reversed for the adjoint
   };
-  void st_prepare(const LowRank& F, bool adjoint, StPrep& pr);
+  void st_prepare(const std::vector<const LowRank*>& F, bool adjoint, std::vector<StPrep>& prs);
   double* st_pole_solves(const std::vector<const StPrep*>& prs);
   // per source: M-orthonormal basis Q (nx x q) and projected solution Zp
   // (q x nt); Kt (projected tau K) is built with the basis
@@ -300,7 +300,7 @@ class Problem {
   DevMem mg_work_f_, mg_f_;
   void upload_mg_params(const std::vector<ShiftCoef>& ab);
   // space-time solver workspaces
-  DevMem st_gram_, st_g_, st_mw_, st_w2_, st_tm_, st_wall_, st_brep_, st_small_, st_c_, eig_work_;
+  DevMem st_gram_, st_g_, st_mw_, st_w2_, st_tm_, st_prep_g_, st_prep_t_, st_wall_, st_brep_, st_small_, st_c_, eig_work_;
 };
 
 void smoother_interval(double a, double bh2, double* lo, double* hi);

@@ -109,6 +109,25 @@ static int ns_steps(double L) {
   return std::max(1, (int)std::ceil(std::log2(std::log(1e-18) / std::log(rho))) + 1);
 }
 
+// f(0) .. f(n-1) on up to kHostThreads host threads (pure host work only:
+// no HIP calls and no exceptions inside f).
+static constexpr int kHostThreads = 4;
+template <class F>
+static void host_parallel(int n, F&& f) {
+  if (n <= 1) {
+    for (int i = 0; i < n; ++i) f(i);
+    return;
+  }
+  const int nt = std::min(n, kHostThreads);
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t)
+    th.emplace_back([&, t] {
+      for (int i = t; i < n; i += nt) f(i);
+    });
+  for (int i = 0; i < n; i += nt) f(i);
+  for (auto& x : th) x.join();
+}
+
 Problem::Problem(const lrpost_problem_desc& d) : desc(d) {
   if (d.N < 4 || d.N > 4096 || (d.N & (d.N - 1)) != 0) fail(LRPOST_EINVAL, "N must be a power of two in [4, 4096]");
   if (d.nt < 1) fail(LRPOST_EINVAL, "nt must be >= 1");
@@ -767,37 +786,78 @@ void Problem::small_svd(int m, int nn, const double* A, int lda, bool accurate, 
 // The adjoint equation tau K Y + M Y C = F is the same problem with time
 // reversed on both sides.
 // ---------------------------------------------------------------------------
-void Problem::st_prepare(const LowRank& F, bool adjoint, StPrep& pr) {
-  const int rf0 = F.rank;
-  pr.r1 = 0;
-  if (rf0 == 0) return;
-  // 1. orthonormalize the source's spatial factor (eigen-based, drops null directions)
-  std::vector<double> G, w(rf0), U((size_t)rf0 * rf0);
-  gram(rf0, F.a(), rf0, F.a(), G);
-  if (!syev(rf0, G.data(), rf0, w.data(), U.data())) fail(LRPOST_EBREAKDOWN, "source Gram eigensolve failed");
-  const double wmax = std::max(w[rf0 - 1], 0.0);
-  std::vector<int> keep;
-  for (int j = rf0 - 1; j >= 0; --j)
-    if (w[j] > 1e-26 * wmax && wmax > 0) keep.push_back(j);
-  const int r1 = (int)keep.size();
-  if (r1 == 0) return;
-  std::vector<double> T1((size_t)rf0 * r1);
-  std::vector<double>& F2p = pr.F2p;
-  F2p.assign((size_t)nt * r1, 0.0);
-  for (int c = 0; c < r1; ++c) {
-    const int j = keep[c];
-    const double sw = std::sqrt(w[j]);
-    for (int i = 0; i < rf0; ++i) T1[(size_t)c * rf0 + i] = U[(size_t)j * rf0 + i] / sw;
-    for (int k = 0; k < nt; ++k) {
-      const int kk = adjoint ? nt - 1 - k : k;
-      double s = 0.0;
-      for (int i = 0; i < rf0; ++i) s += F.B[(size_t)i * nt + kk] * U[(size_t)j * rf0 + i];
-      F2p[(size_t)c * nt + k] = s * sw;
-    }
+void Problem::st_prepare(const std::vector<const LowRank*>& F, bool adjoint, std::vector<StPrep>& prs) {
+  // 1. orthonormalize each source's spatial factor (eigen-based, drops null
+  // directions); the Gram matrices of all sources are one grouped launch and
+  // one read-back, the transforms one grouped projection
+  const int nb = (int)F.size();
+  std::vector<size_t> goff(nb + 1, 0);
+  for (int j = 0; j < nb; ++j) {
+    prs[j].r1 = 0;
+    goff[j + 1] = goff[j] + (size_t)F[j]->rank * F[j]->rank;
   }
-  pr.Fb.ensure(sizeof(double) * (size_t)nx * r1);
-  proj(rf0, F.a(), T1, r1, pr.Fb.as<double>(), 0.0);
-  pr.r1 = r1;
+  if (goff[nb] == 0) return;
+  st_prep_g_.ensure(sizeof(double) * goff[nb]);
+  double* Gd = st_prep_g_.as<double>();
+  std::vector<GramGroup> gg;
+  for (int j = 0; j < nb; ++j) {
+    const int rf0 = F[j]->rank;
+    if (rf0 > 0) gg.push_back(GramGroup{F[j]->a(), F[j]->a(), nullptr, Gd + goff[j], nx, nx, rf0, 0, rf0, rf0, 0});
+  }
+  gram_dev_grouped(gg);
+  std::vector<double> Gh(goff[nb]);
+  to_host(Gh.data(), Gd, Gh.size());
+  std::vector<std::vector<double>> T1(nb);
+  std::vector<int> ok(nb, 1);
+  host_parallel(nb, [&](int j) {
+    const LowRank& f = *F[j];
+    const int rf0 = f.rank;
+    StPrep& pr = prs[j];
+    if (rf0 == 0) return;
+    std::vector<double> w(rf0), U((size_t)rf0 * rf0);
+    if (!syev(rf0, Gh.data() + goff[j], rf0, w.data(), U.data())) {
+      ok[j] = 0;
+      return;
+    }
+    const double wmax = std::max(w[rf0 - 1], 0.0);
+    std::vector<int> keep;
+    for (int c = rf0 - 1; c >= 0; --c)
+      if (w[c] > 1e-26 * wmax && wmax > 0) keep.push_back(c);
+    const int r1 = (int)keep.size();
+    if (r1 == 0) return;
+    T1[j].assign((size_t)rf0 * r1, 0.0);
+    std::vector<double>& F2p = pr.F2p;
+    F2p.assign((size_t)nt * r1, 0.0);
+    for (int c = 0; c < r1; ++c) {
+      const int e = keep[c];
+      const double sw = std::sqrt(w[e]);
+      for (int i = 0; i < rf0; ++i) T1[j][(size_t)c * rf0 + i] = U[(size_t)e * rf0 + i] / sw;
+      for (int k = 0; k < nt; ++k) {
+        const int kk = adjoint ? nt - 1 - k : k;
+        double acc = 0.0;
+        for (int i = 0; i < rf0; ++i) acc += f.B[(size_t)i * nt + kk] * U[(size_t)e * rf0 + i];
+        F2p[(size_t)c * nt + k] = acc * sw;
+      }
+    }
+    pr.r1 = r1;
+  });
+  for (int j = 0; j < nb; ++j)
+    if (!ok[j]) fail(LRPOST_EBREAKDOWN, "source Gram eigensolve failed");
+  std::vector<double> Th(goff[nb], 0.0);
+  std::vector<ProjGroup> pg;
+  for (int j = 0; j < nb; ++j)
+    if (prs[j].r1 > 0) std::copy(T1[j].begin(), T1[j].end(), Th.begin() + goff[j]);
+  st_prep_t_.ensure(sizeof(double) * goff[nb]);
+  to_device(st_prep_t_.as<double>(), Th.data(), Th.size());
+  for (int j = 0; j < nb; ++j) {
+    StPrep& pr = prs[j];
+    if (pr.r1 == 0) continue;
+    const int rf0 = F[j]->rank;
+    pr.Fb.ensure(sizeof(double) * (size_t)nx * pr.r1);
+    pg.push_back(ProjGroup{F[j]->a(), st_prep_t_.as<double>() + goff[j], pr.Fb.as<double>(), pr.Fb.as<double>(), nx, nx,
+                           nx, rf0, rf0, pr.r1});
+  }
+  proj_dev_grouped(pg, 1.0, 0.0);
 }
 
 
@@ -844,10 +904,8 @@ void Problem::spacetime_solve_batch(const std::vector<const LowRank*>& F, const 
   std::vector<const StPrep*> pp;
   {
     PhaseTimer pt(this, kPhPrep);
-    for (int j = 0; j < nb; ++j) {
-      st_prepare(*F[j], adjoint, prs[j]);
-      pp.push_back(&prs[j]);
-    }
+    st_prepare(F, adjoint, prs);
+    for (int j = 0; j < nb; ++j) pp.push_back(&prs[j]);
   }
   double* Wall;
   {
@@ -863,28 +921,9 @@ void Problem::spacetime_solve_batch(const std::vector<const LowRank*>& F, const 
   st_truncate(fins, Y, adjoint);
 }
 
-// Basis and projected problem of one prepared source whose pole solves are in
-// Wall (nx x r1 npol, overwritten): fin.Q (nx x q, M-orthonormal) and fin.Zp
-// (q x nt) with the space-time solution Q Zp.
-// f(0) .. f(n-1) on up to kHostThreads host threads (pure host work only:
-// no HIP calls and no exceptions inside f).
-static constexpr int kHostThreads = 4;
-template <class F>
-static void host_parallel(int n, F&& f) {
-  if (n <= 1) {
-    for (int i = 0; i < n; ++i) f(i);
-    return;
-  }
-  const int nt = std::min(n, kHostThreads);
-  std::vector<std::thread> th;
-  for (int t = 1; t < nt; ++t)
-    th.emplace_back([&, t] {
-      for (int i = t; i < n; i += nt) f(i);
-    });
-  for (int i = 0; i < n; i += nt) f(i);
-  for (auto& x : th) x.join();
-}
-
+// Bases and projected problems of a batch of prepared sources whose pole
+// solves are in Wall (pole-major, overwritten): per source fin.Q (nx x q,
+// M-orthonormal) and fin.Zp (q x nt) with the space-time solution Q Zp.
 void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std::vector<StFin>& fins) {
   // 2. block-by-block M-orthonormalization of the pole solutions.  Block
   // Gram-Schmidt against Q in the M inner product, twice, with the block
