@@ -960,35 +960,34 @@ __device__ __forceinline__ void gram_tile(long nrows, long rows_per_chunk, int m
     for (int b = 0; b < 2; ++b) acc[a][b] = gram_d4{0.0, 0.0, 0.0, 0.0};
   const int lr = tid & (GK - 1), lc = tid / GK;  // loader: row lr of columns lc, lc + GTH / GK, ...
   const long nst = (r1 > r0) ? (r1 - r0 + GK - 1) / GK : 0;
-  // column pointers of this thread's staged columns (clamped into range) and
-  // whether they are real columns
-  const double* cp[NU];
-  bool cok[NU];
+  // this thread's staged columns: u < NA are columns of A, the rest of B,
+  // each as an element offset from the tile's first column (clamped into
+  // range: a clamped column only feeds output rows or columns that are never
+  // written, so only rows outside the chunk need zeroing)
+  constexpr int NA = GM / (GTH / GK);
+  const double* __restrict__ At = A + (long)tm * GM * lda;
+  const double* __restrict__ Bt = B + (long)tq * GQ * ldb;
+  const int ma = m - 1 - tm * GM, qb = q - 1 - tq * GQ;
+  // (32-bit: at most 191 x 16.8e6 for the largest mesh, 4095^2 nodes)
+  unsigned co[NU];
 #pragma unroll
   for (int u = 0; u < NU; ++u) {
     const int c = lc + (GTH / GK) * u;
-    if (c < GM) {
-      const int ca = tm * GM + c;
-      cok[u] = ca < m;
-      cp[u] = A + (long)(ca < m ? ca : m - 1) * lda;
-    } else {
-      const int cb = tq * GQ + (c - GM);
-      cok[u] = cb < q;
-      cp[u] = B + (long)(cb < q ? cb : q - 1) * ldb;
-    }
+    co[u] = u < NA ? (unsigned)min(c, ma) * (unsigned)lda : (unsigned)min(c - GM, qb) * (unsigned)ldb;
   }
   // loads are unconditional (row clamped into the chunk) so that a stage's
-  // loads are in flight together; out-of-range values are scaled to zero
+  // loads are in flight together; rows outside the chunk are scaled to zero
   // (a select of a loaded value is compiled into a branch around the load)
   double rv[NU];
   auto fetch = [&](long it) {
     const long r = r0 + it * GK + lr;
     const bool rin = r < r1;
     const long rc = rin ? r : r1 - 1;
+    const double keep = rin ? 1.0 : 0.0;
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
-      const double v = cp[u][rc];
-      rv[u] = v * ((rin && cok[u]) ? 1.0 : 0.0);
+      const double v = (u < NA ? At : Bt)[(long)co[u] + rc];
+      rv[u] = v * keep;
     }
   };
   // stage it is read from buffer it % 2 while stage it + 1 arrives in
@@ -1446,19 +1445,34 @@ __global__ void k_symmetrize_upper(int n, double* A, long lda) {
   if (i < n && j < n && i > j) A[(long)j * lda + i] = A[(long)i * lda + j];
 }
 // out[i] = sum_j A[i + j lda] B[i + j ldb] for i < n, j < r: the row-wise
-// dot products of two column-major n x r matrices (one lane per row, j
-// ascending, so every run rounds alike)
-__global__ void k_row_dot(int n, int r, const double* __restrict__ A, long lda, const double* __restrict__ B,
-                          long ldb, double* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// dot products of two column-major n x r matrices.  A workgroup takes 64 rows;
+// its 16 waves each sum one sixteenth of the j range (ascending), and the 16
+// partial sums are combined in a fixed order, so every run rounds alike.
+constexpr int RD_ROWS = 64, RD_SEG = 16;
+__global__ __launch_bounds__(RD_ROWS * RD_SEG) void k_row_dot(int n, int r, const double* __restrict__ A, long lda,
+                                                            const double* __restrict__ B, long ldb,
+                                                            double* __restrict__ out) {
+  __shared__ double red[RD_SEG][RD_ROWS + 1];
+  const int tx = threadIdx.x % RD_ROWS, ty = threadIdx.x / RD_ROWS;
+  const int i = blockIdx.x * RD_ROWS + tx;
+  const int ic = i < n ? i : n - 1;
+  const int seg = (r + RD_SEG - 1) / RD_SEG;
+  const int j0 = ty * seg, j1 = min(r, j0 + seg);
   double acc = 0.0;
-  for (int j = 0; j < r; ++j) acc = fma(A[i + (long)j * lda], B[i + (long)j * ldb], acc);
-  out[i] = acc;
+  for (int j = j0; j < j1; ++j) acc = fma(A[ic + (long)j * lda], B[ic + (long)j * ldb], acc);
+  red[ty][tx] = acc;
+  __syncthreads();
+  if (ty == 0 && i < n) {
+    double t = red[0][tx];
+#pragma unroll
+    for (int y = 1; y < RD_SEG; ++y) t += red[y][tx];
+    out[i] = t;
+  }
 }
 void row_dot(hipStream_t st, int n, int r, const double* A, long lda, const double* B, long ldb, double* out) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_row_dot, dim3((n + 255) / 256), dim3(256), 0, st, n, r, A, lda, B, ldb, out);
+  hipLaunchKernelGGL(k_row_dot, dim3((n + RD_ROWS - 1) / RD_ROWS), dim3(RD_ROWS * RD_SEG), 0, st, n, r, A, lda, B, ldb,
+                     out);
 }
 void add_diag(hipStream_t st, int n, double* A, long lda, double v) {
   if (n <= 0) return;
