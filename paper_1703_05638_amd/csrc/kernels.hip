@@ -1048,7 +1048,7 @@ __global__ __launch_bounds__(GTH) void k_gram_mfma(long nrows, GramGroups gs) {
 // tile height 64 BM: the smallest that covers m, at most 192 (the 256-row
 // tile needs 146 registers per lane, which leaves one workgroup per CU; wider
 // products take several tiles)
-static int gram_bm(int m) { return m <= 64 ? 1 : m <= 128 ? 2 : 3; }
+int gram_bm(int m) { return m <= 64 ? 1 : m <= 128 ? 2 : 3; }
 
 int gram_chunks_mfma(long nrows, int m, int q) {
   // about one workgroup per CU (longer chunks beat more, shorter ones: a

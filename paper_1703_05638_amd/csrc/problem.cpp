@@ -615,25 +615,30 @@ void Problem::gram_dev(int m, const double* A, int q, const double* B, double* C
 }
 
 // Several Gram products A_g^T B_g (nx rows) with one launch per stage for up
-// to kProjGroupMax of them; each result is the one gram_dev gives.
+// to kProjGroupMax of them; each result is the one gram_dev gives.  Products
+// of different tile heights (64, 128 or 192 rows, from m) go to separate
+// launches, so that no product is computed with a taller tile than its own.
 void Problem::gram_dev_grouped(std::vector<GramGroup>& gs) {
   std::vector<size_t> off(gs.size() + 1, 0);
   for (size_t i = 0; i < gs.size(); ++i) off[i + 1] = off[i] + (size_t)gram_part_doubles(nx, gs[i].m, gs[i].q);
   if (off.back() == 0) return;
   gram_part_.ensure(sizeof(double) * off.back());
   for (size_t i = 0; i < gs.size(); ++i) gs[i].part = gram_part_.as<double>() + off[i];
-  for (size_t g0 = 0; g0 < gs.size(); g0 += kProjGroupMax) {
-    const int n = (int)std::min<size_t>(kProjGroupMax, gs.size() - g0);
-    double bytes = 0.0, flops = 0.0;
-    for (int i = 0; i < n; ++i) {
-      const GramGroup& g = gs[g0 + i];
-      if (g.m <= 0 || g.q <= 0) continue;
-      bytes += sizeof(double) * (double)(g.m + g.q) * nx;
-      flops += 2.0 * g.m * g.q * (double)nx;
+  for (int cls = 1; cls <= 3; ++cls) {
+    std::vector<GramGroup> gc;
+    for (const GramGroup& g : gs)
+      if (g.m > 0 && g.q > 0 && gram_bm(g.m) == cls) gc.push_back(g);
+    for (size_t g0 = 0; g0 < gc.size(); g0 += kProjGroupMax) {
+      const int n = (int)std::min<size_t>(kProjGroupMax, gc.size() - g0);
+      double bytes = 0.0, flops = 0.0;
+      for (int i = 0; i < n; ++i) {
+        const GramGroup& g = gc[g0 + i];
+        bytes += sizeof(double) * (double)(g.m + g.q) * nx;
+        flops += 2.0 * g.m * g.q * (double)nx;
+      }
+      timed(LRPOST_KERNEL_GRAM, bytes, [&] { gram_mfma_partials(st, nx, n, gc.data() + g0); }, flops);
+      sum_partials_grouped(st, n, gc.data() + g0);
     }
-    if (bytes == 0.0) continue;
-    timed(LRPOST_KERNEL_GRAM, bytes, [&] { gram_mfma_partials(st, nx, n, gs.data() + g0); }, flops);
-    sum_partials_grouped(st, n, gs.data() + g0);
   }
   LRP_HIP(hipGetLastError());
 }
