@@ -19,10 +19,10 @@
 // spatial factors touch nx-sized data.
 #include <algorithm>
 #include <chrono>
-#include <optional>
 #include <cmath>
 #include <cstdio>
 #include <numeric>
+#include <optional>
 
 #include "internal.h"
 
@@ -473,6 +473,32 @@ class SharedBasis {
     P->to_host(out.B.data(), v.B.as<double>(), (size_t)nt * v.r);
   }
 
+  // The stored vectors k0 .. k0 + count - 1 as low-rank vectors: spatial
+  // factors U C_k in one grouped projection, temporal factors (adjacent in
+  // B_all) in one read-back.
+  void materialize_block(int k0, int count, std::vector<LowRank>& outs) {
+    std::vector<ProjGroup> pg;
+    int cols = 0;
+    for (int i = 0; i < count; ++i) {
+      const int k = k0 + i;
+      outs[i].resize(nx, nt, rk[k]);
+      cols += rk[k];
+      if (rk[k] > 0)
+        pg.push_back(ProjGroup{U.as<double>(), C_all.as<double>() + (size_t)off[k] * s_cap, outs[i].a(), outs[i].a(),
+                               nx, nx, nx, s_cap, s, rk[k]});
+    }
+    if (cols == 0) return;
+    if (s > 0) P->proj_dev_grouped(pg, 1.0, 0.0);
+    std::vector<double> Bh((size_t)nt * cols);
+    P->to_host(Bh.data(), B_all.as<double>() + (size_t)off[k0] * nt, Bh.size());
+    size_t o = 0;
+    for (int i = 0; i < count; ++i) {
+      const size_t len = (size_t)nt * rk[k0 + i];
+      std::copy(Bh.begin() + o, Bh.begin() + o + len, outs[i].B.begin());
+      o += len;
+    }
+  }
+
   CVec stored(int k) {
     CVec v;
     v.s = s;
@@ -594,8 +620,8 @@ EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rt
     std::vector<LowRank*> po;
     {
       Problem::PhaseTimer pt(P, Problem::kPhMaterialize);
+      sb.materialize_block(j0, bj, xin);
       for (int i = 0; i < bj; ++i) {
-        sb.materialize(sb.stored(j0 + i), xin[i]);
         px.push_back(&xin[i]);
         po.push_back(&outs[i]);
       }

@@ -731,8 +731,11 @@ void Problem::sym_eig(int nn, const double* A, int lda, std::vector<double>& w, 
   double* dw = dA + (size_t)nn * nn;
   to_device(dA, tmp.data(), tmp.size());
   dense->syevd(nn, dA, nn, dw, eig_work_);
-  to_host(V.data(), dA, (size_t)nn * nn);
-  to_host(w.data(), dw, nn);
+  // eigenvectors and eigenvalues are adjacent on the device: one read-back
+  tmp.resize((size_t)nn * nn + nn);
+  to_host(tmp.data(), dA, tmp.size());
+  std::copy(tmp.begin(), tmp.begin() + (size_t)nn * nn, V.begin());
+  std::copy(tmp.begin() + (size_t)nn * nn, tmp.end(), w.begin());
 }
 
 void Problem::small_svd(int m, int nn, const double* A, int lda, bool accurate, std::vector<double>& s,
@@ -1339,20 +1342,31 @@ void Problem::st_truncate(std::vector<StFin>& fins, const std::vector<LowRank*>&
     else dense->gemm(false, true, f.q, f.q, nt, 1.0, Zp, f.q, Zp, f.q, 0.0, G + gsz * a, g);
   }
   dense->syevd_batched(g, G, g, (long)gsz, wg, g, na, eig_work_);
-  std::vector<double> w((size_t)g * na);
-  to_host(w.data(), wg, w.size());
-  // ranks first, then the spatial factors on the device and all temporal
-  // factors gathered for one read-back
-  std::vector<int> ry(na), boff(na + 1, 0);
+  // One read-back for the eigenvalues and, per source, the temporal factors
+  // of the rc = min(cap, g) leading directions (the kept ones are the last r
+  // of them once the ranks are known): the eigenvectors themselves when nt is
+  // the small side, else Zp^T U.
+  const int rc = desc.rank_cap > 0 ? std::min(desc.rank_cap, g) : g;
+  const size_t wlen = (size_t)g * na, clen = (size_t)nt * rc;
+  st_c_.ensure(sizeof(double) * (wlen + clen * na + (size_t)qb * rc + 64));
+  double* Rd = st_c_.as<double>();               // eigenvalues, then the candidate temporal factors
+  double* Cm = Rd + wlen + clen * na;            // q x r scratch
+  LRP_HIP(hipMemcpyAsync(Rd, wg, sizeof(double) * wlen, hipMemcpyDeviceToDevice, st));
+  for (int a = 0; a < na; ++a) {
+    const StFin& f = fins[act[a]];
+    const double* Ec = G + gsz * a + (size_t)(g - rc) * g;  // eigenvectors of the rc largest eigenvalues
+    double* Ba = Rd + wlen + clen * a;
+    if (right) LRP_HIP(hipMemcpyAsync(Ba, Ec, sizeof(double) * clen, hipMemcpyDeviceToDevice, st));
+    else dense->gemm(true, false, nt, rc, f.q, 1.0, f.Zp.as<double>(), f.q, Ec, g, 0.0, Ba, nt);
+  }
+  std::vector<double> Rh(wlen + clen * na);
+  to_host(Rh.data(), Rd, Rh.size());
+  std::vector<int> ry(na);
   for (int a = 0; a < na; ++a) {
     std::vector<double> sv(g);
-    for (int c = 0; c < g; ++c) sv[c] = std::sqrt(std::max(w[(size_t)a * g + g - 1 - c], 0.0));
+    for (int c = 0; c < g; ++c) sv[c] = std::sqrt(std::max(Rh[(size_t)a * g + g - 1 - c], 0.0));
     ry[a] = truncation_rank(sv, desc.trunc_tol, desc.rank_cap, &tail);
-    boff[a + 1] = boff[a] + ry[a];
   }
-  st_c_.ensure(sizeof(double) * std::max<size_t>(1, (size_t)nt * boff[na] + (size_t)qb * desc.rank_cap));
-  double* Bd = st_c_.as<double>();                 // nt x (sum of ranks): temporal factors
-  double* Cm = Bd + (size_t)nt * boff[na];         // q x ry scratch
   for (int a = 0; a < na; ++a) {
     const StFin& f = fins[act[a]];
     LowRank& y = *Y[act[a]];
@@ -1362,24 +1376,17 @@ void Problem::st_truncate(std::vector<StFin>& fins, const std::vector<LowRank*>&
     if (r == 0) continue;
     // eigenvectors of the kept directions are the last r columns
     const double* Ek = G + gsz * a + (size_t)(g - r) * g;
-    double* Ba = Bd + (size_t)nt * boff[a];
     if (right) {
       // Y = Q (Zp V_r) V_r^T
       dense->gemm(false, false, q, r, nt, 1.0, Zp, q, Ek, nt, 0.0, Cm, q);
       proj_dev(q, f.Q.as<double>(), Cm, q, r, y.a(), 0.0);
-      LRP_HIP(hipMemcpyAsync(Ba, Ek, sizeof(double) * (size_t)nt * r, hipMemcpyDeviceToDevice, st));
     } else {
       // Y = Q U_r (Zp^T U_r)^T, U_r the first q rows of the padded eigenvectors
-      dense->gemm(true, false, nt, r, q, 1.0, Zp, q, Ek, g, 0.0, Ba, nt);
       proj_dev(q, f.Q.as<double>(), Ek, g, r, y.a(), 0.0);
     }
-  }
-  std::vector<double> Bh((size_t)nt * boff[na]);
-  to_host(Bh.data(), Bd, Bh.size());
-  for (int a = 0; a < na; ++a) {
-    if (ry[a] == 0) continue;
-    std::vector<double> B2(Bh.begin() + (size_t)nt * boff[a], Bh.begin() + (size_t)nt * boff[a + 1]);
-    store_B(*Y[act[a]], B2, ry[a]);
+    const auto b0 = Rh.begin() + wlen + clen * a + (size_t)nt * (rc - r);
+    std::vector<double> B2(b0, b0 + (size_t)nt * r);
+    store_B(y, B2, r);
   }
   stats.last_tail = tail;
 }
