@@ -45,3 +45,16 @@ def test_committed_reports_name_their_kernels():
         text = open(os.path.join(prof, name)).read()
         assert "kernel_regex:" in text and "traffic_bytes_per_launch:" in text
         assert "rocprofv3 --pmc FETCH_SIZE" in text and "rocprofv3 --pmc WRITE_SIZE" in text
+
+
+def test_bench_kernel_table_matches_the_library_kinds():
+    import bench
+    from paper_1703_05638_amd import lrpost as lp
+
+    kinds = {lp.LRPOST_KERNEL_SMOOTHER_STEP: "k_cheb", lp.LRPOST_KERNEL_MG_DOWN: "k_mg_down",
+             lp.LRPOST_KERNEL_MG_UP: "k_mg_up", lp.LRPOST_KERNEL_GRAM: "k_gram_mfma",
+             lp.LRPOST_KERNEL_PROJ: "k_proj_mfma"}
+    assert {k: v[0] for k, v in bench.KERNELS.items()} == kinds
+    # the dominant kernel's committed traffic reports exist under the names the bench looks for
+    for name in ("k_gram_mfma", "k_mg_up", "k_mg_down"):
+        assert os.path.exists(bench.traffic_report(name, "mixed"))
