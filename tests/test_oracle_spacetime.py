@@ -56,3 +56,29 @@ def test_mask_is_closed_box():
     assert p.nobs == 17 * 17
     p2 = Problem(32, 2, box=(0.0, 1.0, 0.0, 1.0))
     assert p2.nobs == p2.nx
+
+
+def test_forward_source_solves_the_all_at_once_system():
+    """forward_source is the solve of Sec. 6.1 eq. st_pde with L = tau K and
+    C = I - S, for any right-hand side: checked against a sparse direct solve
+    of the Kronecker-form matrix (no time stepping), and against the
+    parameter-to-state map when the right-hand side is the source tau M U."""
+    p = Problem(7, 6, box=(0.2, 0.9, 0.1, 0.6))
+    Kst, Sst, _, _ = p.spacetime_matrices()
+    rng = _rng(23)
+    F = rng.standard_normal((p.nx, p.nt))
+    ref = spla.spsolve(Kst, F.reshape(-1, order="F")).reshape((p.nx, p.nt), order="F")
+    assert np.allclose(p.forward_source(F), ref, rtol=1e-13, atol=1e-14 * np.abs(ref).max())
+    U = rng.standard_normal((p.nx, p.nt))
+    assert np.allclose(p.forward_source(p.tau * (p.M @ U)), p.forward(U), rtol=1e-13, atol=1e-15)
+
+
+def test_adjoint_source_solves_the_transposed_system():
+    """adjoint_source solves (I kron tau K + C^T kron M) vec(P) = vec(Z): the
+    transpose of the all-at-once matrix (K and M are symmetric), checked by a
+    sparse direct solve with Kst^T."""
+    p = Problem(7, 5, box=(0.2, 0.9, 0.1, 0.6))
+    Kst, _, _, _ = p.spacetime_matrices()
+    Z = _rng(29).standard_normal((p.nx, p.nt))
+    ref = spla.spsolve(Kst.T.tocsc(), Z.reshape(-1, order="F")).reshape((p.nx, p.nt), order="F")
+    assert np.allclose(p.adjoint_source(Z), ref, rtol=1e-13, atol=1e-14 * np.abs(ref).max())
