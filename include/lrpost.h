@@ -76,8 +76,9 @@ typedef struct {
   double trunc_tol;   /* relative Frobenius truncation tolerance of factors, in (0, 1) */
   int32_t rank_cap;   /* maximal factor rank kept after truncation, >= 1 */
   int32_t precision;  /* LRPOST_FP64 or LRPOST_MIXED */
-  int32_t mg_levels;  /* 0 = coarsen down to a single node; otherwise the number of
-                         multigrid levels (the coarsest then gets a dense solve) */
+  int32_t mg_levels;  /* must be 0: the V-cycle always coarsens to levels of at most 31
+                         nodes per side, solved inside one workgroup (any other value
+                         is rejected with LRPOST_EINVAL) */
   uint64_t seed;      /* seed of the Lanczos start block */
   void* hip_stream;   /* hipStream_t to order work on, or NULL for the null stream */
 } lrpost_problem_desc;
@@ -97,10 +98,17 @@ typedef struct {
   int32_t last_rank_out;  /* rank of the last apply's output */
   int32_t last_basis;     /* spatial basis size of the last space-time solve */
   int32_t lanczos_steps;  /* block steps of the last eigensolve */
-  int32_t pad;
+  int32_t st_enrichments; /* space-time solve batches that needed the refined pole set */
   double last_tail;       /* relative tail dropped by the last truncation */
-  double last_st_resid;   /* relative residual of the last checked space-time solve (or -1) */
-  double ritz_resid;      /* largest ||G x - theta x||_P / theta over the pairs of the last eigensolve */
+  double last_st_resid;   /* largest relative residual ||tau K Y + M Y C^T - F||_F / ||F||_F
+                             (C for the adjoint) of the solutions of the last space-time
+                             solve batch, for the truncated factors returned (Sec. 6.1,
+                             eq. st_pde); -1 while the check is off or no solve ran */
+  double ritz_resid;      /* largest relative Ritz residual ESTIMATE of the last
+                             eigensolve: block Lanczos takes it from the coupling block of
+                             the recurrence, the randomized solver from the Grams of its
+                             two passes.  Neither includes the truncation of the Ritz
+                             vectors after the loop; lrpost_eig_residuals measures that */
 } lrpost_stats;
 
 /* Create a problem: validates the description, builds the multigrid
@@ -124,14 +132,42 @@ int lrpost_hess_apply_batch(lrpost_problem* p, int nvec, const lrpost_lowrank* x
 /* Low-rank space-time solve (Sec. 6.1 eq. st_pde with L = tau K):
  * forward (adjoint = 0):  tau K Y + M Y C^T = F1 F2^T  (time runs forward),
  * adjoint (adjoint = 1):  tau K Y + M Y C   = F1 F2^T  (time runs backward).
- * Output truncated at desc.trunc_tol in the M-weighted Frobenius norm. */
+ * Output truncated at desc.trunc_tol in the M-weighted Frobenius norm.
+ * Every space-time solve (also inside the Hessian applies) measures the
+ * relative residual of its truncated output (lrpost_stats.last_st_resid);
+ * above the check threshold the spatial basis is enriched once by a refined
+ * pole set, and a residual still above it returns LRPOST_ENOCONV (the
+ * residual monitor of the AMEn solver of Sec. 6.1). */
 int lrpost_spacetime_solve(lrpost_problem* p, const lrpost_lowrank* f, lrpost_lowrank* y, int adjoint);
+/* Residual check of the space-time solves: mode 0 off (last_st_resid = -1),
+ * 1 measure only, 2 (default) measure, enrich and fail as described above;
+ * rtol is the threshold on the relative residual (0: 100 trunc_tol).
+ * mode outside 0..2 or rtol < 0: LRPOST_EINVAL. */
+int lrpost_set_st_check(lrpost_problem* p, int mode, double rtol);
 
 /* Eigensolve for the k largest eigenpairs of G (Sec. 4 Algorithm 1, as block
  * Lanczos with full re-orthogonalization in the P inner product; or a
  * randomized two-pass range finder with k + oversample probes).  The result
- * handle owns device-resident eigenvector factors. */
+ * handle owns device-resident eigenvector factors.
+ * Convergence: every wanted pair must reach a relative Ritz residual
+ * estimate (lrpost_stats.ritz_resid) of at most rtol, by default
+ * max(1e-9, 0.1 trunc_tol) in FP64 and max(1e-7, 0.1 trunc_tol) mixed, block
+ * Lanczos within at most min(max(8k, 64), 800) vectors (lrpost_set_eig_limits
+ * overrides both).  Otherwise the call returns LRPOST_ENOCONV and *out STILL
+ * holds the pairs reached, which the caller reads and frees as usual. */
 int lrpost_eigensolve(lrpost_problem* p, int k, int method, int oversample, lrpost_eigs** out);
+/* Limits of lrpost_eigensolve / lrpost_eigensolve_probes on this problem:
+ * max_vectors caps the block-Lanczos basis (0: default), rtol the relative
+ * Ritz residual target (0: default).  Negative values: LRPOST_EINVAL. */
+int lrpost_set_eig_limits(lrpost_problem* p, int max_vectors, double rtol);
+/* Measured relative residuals ||G v_i - lambda_i v_i||_P / |lambda_i| of the
+ * k stored pairs of e (one extra Hessian apply per pair, batched four at a
+ * time; the residual's P-norm from a weighted Gram product of the low-rank
+ * concatenation [G v_i, v_i]).  e must come from p (else LRPOST_EINVAL);
+ * resid: caller-owned host array of k doubles.  The bound |lambda - theta|
+ * <= ||G v - theta v||_P of a P-normalized v certifies each eigenvalue up to
+ * the accuracy of the library's (truncated) apply. */
+int lrpost_eig_residuals(lrpost_problem* p, const lrpost_eigs* e, double* resid);
 /* The two-pass randomized eigensolver (method LRPOST_RANDOMIZED) on caller
  * probes: Y_j = G Omega_j, a P-orthonormal basis Q of range(Y) through the
  * Gram [<Y_i, Y_j>_P], T = Q^T P G Q from a second pass of applies, Ritz

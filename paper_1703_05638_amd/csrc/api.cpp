@@ -41,6 +41,20 @@ static Problem* impl(lrpost_problem* p) {
   return p->impl.get();
 }
 
+// The problem that created e, which must be p (when p is given) and still
+// alive; every stored vector must have that problem's shape.
+static Problem* owner_of(lrpost_problem* p, const lrpost_eigs* e) {
+  if (!e) fail(LRPOST_EINVAL, "null eigenpair handle");
+  if (e->owner_alive.expired() || !e->owner) fail(LRPOST_EINVAL, "the problem of this eigenpair handle was destroyed");
+  if (p && e->owner != p) fail(LRPOST_EINVAL, "eigenpair handle belongs to another problem");
+  Problem* P = e->owner->impl.get();
+  if (!P) fail(LRPOST_EINVAL, "null problem handle");
+  for (auto& v : e->vecs)
+    if (v->rank > 0 && (v->nx != P->nx || v->nt != P->nt))
+      fail(LRPOST_EINVAL, "eigenvector shape does not match the problem");
+  return P;
+}
+
 static void check_lr(const Problem* P, const lrpost_lowrank* x, bool need_data) {
   if (!x) fail(LRPOST_EINVAL, "null low-rank vector");
   if (x->nx != P->nx || x->nt != P->nt) fail(LRPOST_EINVAL, "low-rank vector shape does not match the problem");
@@ -150,6 +164,7 @@ static void finish_eigs(lrpost_problem* p, Problem* P, EigResult& r, lrpost_eigs
   P->stats.ritz_resid = r.max_resid;
   auto e = new lrpost_eigs();
   e->owner = p;
+  e->owner_alive = p->alive;
   e->lambda = r.lambda;
   e->vecs = std::move(r.vecs);
   *out = e;
@@ -162,14 +177,20 @@ int lrpost_eigensolve(lrpost_problem* p, int k, int method, int oversample, lrpo
     if (!out) fail(LRPOST_EINVAL, "null output");
     *out = nullptr;
     if (k < 1) fail(LRPOST_EINVAL, "k must be >= 1");
+    // Ritz residual target: the truncation tolerance bounds how far the
+    // residual of the truncated process can go down
+    const double rtol = P->eig_rtol > 0 ? P->eig_rtol
+                                        : std::max(P->desc.precision == LRPOST_FP64 ? 1e-9 : 1e-7,
+                                                   0.1 * P->desc.trunc_tol);
     if (method == LRPOST_BLOCK_LANCZOS) {
-      // Ritz residual target: the truncation tolerance bounds how far the
-      // residual of the truncated process can go down
-      const double rtol = std::max(P->desc.precision == LRPOST_FP64 ? 1e-9 : 1e-7, 0.1 * P->desc.trunc_tol);
       const int bsize = 4;
-      const int maxv = std::max(8 * k, 64);
-      EigResult r = block_lanczos(P, k, bsize, std::min(maxv, 800), rtol);
+      const int maxv = P->eig_max_vectors > 0 ? P->eig_max_vectors : std::min(std::max(8 * k, 64), 800);
+      EigResult r = block_lanczos(P, k, bsize, std::max(maxv, bsize), rtol);
       finish_eigs(p, P, r, out);
+      if (!r.converged)
+        fail(LRPOST_ENOCONV, "block Lanczos reached its limit of " + std::to_string(maxv) +
+                                 " vectors with a relative Ritz residual estimate of " +
+                                 std::to_string(r.max_resid) + " (target " + std::to_string(rtol) + ")");
       return;
     }
     if (method != LRPOST_RANDOMIZED) fail(LRPOST_EINVAL, "unsupported eigensolver method");
@@ -195,6 +216,9 @@ int lrpost_eigensolve(lrpost_problem* p, int k, int method, int oversample, lrpo
     for (auto& w : probes) pp.push_back(&w);
     EigResult r = randomized_eig(P, k, pp);
     finish_eigs(p, P, r, out);
+    if (!(r.max_resid <= rtol))
+      fail(LRPOST_ENOCONV, "randomized eigensolver: largest relative Ritz residual " + std::to_string(r.max_resid) +
+                               " above the target " + std::to_string(rtol));
   });
 }
 
@@ -216,6 +240,12 @@ int lrpost_eigensolve_probes(lrpost_problem* p, int k, int nprobe, const lrpost_
     for (auto& w : ws) pp.push_back(&w);
     EigResult r = randomized_eig(P, k, pp);
     finish_eigs(p, P, r, out);
+    const double rtol = P->eig_rtol > 0 ? P->eig_rtol
+                                        : std::max(P->desc.precision == LRPOST_FP64 ? 1e-9 : 1e-7,
+                                                   0.1 * P->desc.trunc_tol);
+    if (!(r.max_resid <= rtol))
+      fail(LRPOST_ENOCONV, "randomized eigensolver: largest relative Ritz residual " + std::to_string(r.max_resid) +
+                               " above the target " + std::to_string(rtol));
   });
 }
 
@@ -236,7 +266,7 @@ int lrpost_eig_vector_rank(const lrpost_eigs* e, int i) {
 int lrpost_eig_vector(const lrpost_eigs* e, int i, lrpost_lowrank* v) {
   return guarded([&] {
     if (!e || !v || i < 0 || i >= (int)e->vecs.size()) fail(LRPOST_EINVAL, "bad eigenvector index");
-    Problem* P = impl(e->owner);
+    Problem* P = owner_of(nullptr, e);
     PoolScope pool_scope(P->pool);
     if (v->nx != P->nx || v->nt != P->nt) fail(LRPOST_EINVAL, "output shape does not match the problem");
     store_lr(P, *e->vecs[i], v);
@@ -255,6 +285,7 @@ int lrpost_eigs_from_pairs(lrpost_problem* p, int k, const double* lambda, const
     if (!out || k < 0 || (k > 0 && (!lambda || !v))) fail(LRPOST_EINVAL, "bad arguments");
     auto e = new lrpost_eigs();
     e->owner = p;
+    e->owner_alive = p->alive;
     try {
       for (int i = 0; i < k; ++i) {
         check_lr(P, v + i, true);
@@ -278,6 +309,7 @@ int lrpost_post_variance(lrpost_problem* p, const lrpost_eigs* e, double* diag, 
     Problem* P = impl(p);
     PoolScope pool_scope(P->pool);
     if (!e || !diag) fail(LRPOST_EINVAL, "null argument");
+    (void)owner_of(p, e);
     const int k = (int)e->vecs.size();
     int R = 0;
     std::vector<int> seg{0};
@@ -331,6 +363,7 @@ int lrpost_sample(lrpost_problem* p, const lrpost_eigs* e, int ns, const double*
     Problem* P = impl(p);
     PoolScope pool_scope(P->pool);
     if (!e || !xi || !out) fail(LRPOST_EINVAL, "null argument");
+    (void)owner_of(p, e);
     if (ns < 0) fail(LRPOST_EINVAL, "ns must be >= 0");
     if (ns == 0) return;
     const int nt = P->nt;
@@ -391,6 +424,70 @@ int lrpost_sample(lrpost_problem* p, const lrpost_eigs* e, int ns, const double*
     }
     if (!on_device) P->to_host(out, Lx, (size_t)nx * cols);
     P->sync();
+  });
+}
+
+int lrpost_set_eig_limits(lrpost_problem* p, int max_vectors, double rtol) {
+  return guarded([&] {
+    Problem* P = impl(p);
+    if (max_vectors < 0 || !(rtol >= 0)) fail(LRPOST_EINVAL, "max_vectors and rtol must be >= 0");
+    P->eig_max_vectors = max_vectors;
+    P->eig_rtol = rtol;
+  });
+}
+
+// ||G v_i - lambda_i v_i||_P / |lambda_i| from applies of the library's G to
+// the stored vectors (a batch of four at a time): the residual is the
+// low-rank concatenation [A_g, A_v] [B_g, -lambda B_v]^T, its P-norm from one
+// weighted Gram product.
+int lrpost_eig_residuals(lrpost_problem* p, const lrpost_eigs* e, double* resid) {
+  return guarded([&] {
+    Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
+    if (!e || !resid) fail(LRPOST_EINVAL, "null argument");
+    (void)owner_of(p, e);
+    const int k = (int)e->vecs.size();
+    const long nx = P->nx;
+    const int nt = P->nt;
+    constexpr int kBatch = 4;
+    for (int i0 = 0; i0 < k; i0 += kBatch) {
+      const int nb = std::min(kBatch, k - i0);
+      std::vector<LowRank> outs(nb);
+      std::vector<const LowRank*> px;
+      std::vector<LowRank*> po;
+      for (int i = 0; i < nb; ++i) {
+        px.push_back(e->vecs[i0 + i].get());
+        po.push_back(&outs[i]);
+      }
+      P->hess_apply_batch(px, po, true);
+      for (int i = 0; i < nb; ++i) {
+        const LowRank& v = *e->vecs[i0 + i];
+        const LowRank& g = outs[i];
+        const double lam = e->lambda[i0 + i];
+        LowRank r;
+        r.resize(nx, nt, g.rank + v.rank);
+        if (g.rank > 0)
+          LRP_HIP(hipMemcpyAsync(r.a(), g.a(), sizeof(double) * nx * g.rank, hipMemcpyDeviceToDevice, P->st));
+        if (v.rank > 0)
+          LRP_HIP(hipMemcpyAsync(r.a() + (size_t)g.rank * nx, v.a(), sizeof(double) * nx * v.rank,
+                                 hipMemcpyDeviceToDevice, P->st));
+        std::copy(g.B.begin(), g.B.end(), r.B.begin());
+        for (size_t t = 0; t < v.B.size(); ++t) r.B[(size_t)g.rank * nt + t] = -lam * v.B[t];
+        const double r2 = r.rank > 0 ? P->p_inner(r, r) : 0.0;
+        resid[i0 + i] = std::sqrt(std::max(r2, 0.0)) / std::max(std::fabs(lam), 1e-300);
+      }
+    }
+    P->sync();
+  });
+}
+
+int lrpost_set_st_check(lrpost_problem* p, int mode, double rtol) {
+  return guarded([&] {
+    Problem* P = impl(p);
+    if (mode < 0 || mode > 2 || !(rtol >= 0)) fail(LRPOST_EINVAL, "mode must be 0..2 and rtol >= 0");
+    P->st_check = mode;
+    P->st_rtol = rtol;
+    if (mode == 0) P->stats.last_st_resid = -1.0;
   });
 }
 

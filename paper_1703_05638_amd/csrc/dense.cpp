@@ -283,35 +283,74 @@ void svd(int m, int n, const double* A, int lda, std::vector<double>& s, std::ve
   }
 }
 
+namespace {
+// four partial sums, so that the loops vectorize
+inline double dot4(const double* x, const double* y, int len) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int i = 0;
+  for (; i + 3 < len; i += 4) {
+    s0 += x[i] * y[i];
+    s1 += x[i + 1] * y[i + 1];
+    s2 += x[i + 2] * y[i + 2];
+    s3 += x[i + 3] * y[i + 3];
+  }
+  for (; i < len; ++i) s0 += x[i] * y[i];
+  return (s0 + s1) + (s2 + s3);
+}
+
+// Householder reflections of W (m x n, leading dimension m) in place: W
+// becomes R in its upper trapezoid; reflector k (I - beta_k v_k v_k^T, v_k of
+// length m - k) is kept in vs[k] when keep_v.
+void householder_reduce(int m, int n, std::vector<double>& W, std::vector<std::vector<double>>* vs,
+                        std::vector<double>& betas) {
+  const int K = std::min(m, n);
+  betas.assign(K, 0.0);
+  if (vs) vs->assign(K, {});
+  std::vector<double> v(m);
+  for (int k = 0; k < K; ++k) {
+    const int len = m - k;
+    double* wk = W.data() + (size_t)k * m + k;
+    double amax = 0.0;
+    for (int i = 0; i < len; ++i) amax = std::max(amax, std::fabs(wk[i]));
+    if (amax == 0.0) continue;
+    for (int i = 0; i < len; ++i) v[i] = wk[i] / amax;
+    const double xn = std::sqrt(dot4(v.data(), v.data(), len));
+    const double alpha = v[0] >= 0 ? -xn : xn;
+    v[0] -= alpha;
+    const double vv = dot4(v.data(), v.data(), len);
+    if (!(vv > 0.0)) continue;
+    const double beta = 2.0 / vv;
+    for (int j = k; j < n; ++j) {
+      double* wj = W.data() + (size_t)j * m + k;
+      const double sdot = beta * dot4(v.data(), wj, len);
+      for (int i = 0; i < len; ++i) wj[i] -= sdot * v[i];
+    }
+    betas[k] = beta;
+    if (vs) (*vs)[k].assign(v.begin(), v.begin() + len);
+  }
+}
+}  // namespace
+
+// R factor only (K x n upper trapezoidal, K = min(m, n)) of A = Q R; Q is not formed.
+void householder_r(int m, int n, const double* A, int lda, std::vector<double>& R) {
+  const int K = std::min(m, n);
+  std::vector<double> W((size_t)m * n), betas;
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < m; ++i) W[(size_t)j * m + i] = A[(size_t)j * lda + i];
+  householder_reduce(m, n, W, nullptr, betas);
+  R.assign((size_t)K * n, 0.0);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i <= std::min(j, K - 1); ++i) R[(size_t)j * K + i] = W[(size_t)j * m + i];
+}
+
 void householder_qr(int m, int n, const double* A, int lda, std::vector<double>& Q, std::vector<double>& R) {
   // A (m x n) = Q (m x K) R (K x n), K = min(m, n); R upper trapezoidal
   const int K = std::min(m, n);
-  std::vector<double> W((size_t)m * n);
+  std::vector<double> W((size_t)m * n), betas;
   for (int j = 0; j < n; ++j)
     for (int i = 0; i < m; ++i) W[(size_t)j * m + i] = A[(size_t)j * lda + i];
-  std::vector<std::vector<double>> vs(K);
-  std::vector<double> betas(K, 0.0);
-  for (int k = 0; k < K; ++k) {
-    double xn = 0.0;
-    for (int i = k; i < m; ++i) xn = std::hypot(xn, W[(size_t)k * m + i]);
-    std::vector<double> v(m - k);
-    for (int i = k; i < m; ++i) v[i - k] = W[(size_t)k * m + i];
-    const double alpha = v[0] >= 0 ? -xn : xn;
-    v[0] -= alpha;
-    double vv = 0.0;
-    for (double t : v) vv += t * t;
-    if (vv > 0.0) {
-      const double beta = 2.0 / vv;
-      for (int j = k; j < n; ++j) {
-        double sdot = 0.0;
-        for (int i = k; i < m; ++i) sdot += v[i - k] * W[(size_t)j * m + i];
-        sdot *= beta;
-        for (int i = k; i < m; ++i) W[(size_t)j * m + i] -= sdot * v[i - k];
-      }
-      betas[k] = beta;
-    }
-    vs[k] = std::move(v);
-  }
+  std::vector<std::vector<double>> vs;
+  householder_reduce(m, n, W, &vs, betas);
   R.assign((size_t)K * n, 0.0);
   for (int j = 0; j < n; ++j)
     for (int i = 0; i <= std::min(j, K - 1); ++i) R[(size_t)j * K + i] = W[(size_t)j * m + i];
@@ -320,11 +359,11 @@ void householder_qr(int m, int n, const double* A, int lda, std::vector<double>&
   for (int k = K - 1; k >= 0; --k) {
     if (betas[k] == 0.0) continue;
     const std::vector<double>& v = vs[k];
+    const int len = m - k;
     for (int j = 0; j < K; ++j) {
-      double sdot = 0.0;
-      for (int i = k; i < m; ++i) sdot += v[i - k] * Q[(size_t)j * m + i];
-      sdot *= betas[k];
-      for (int i = k; i < m; ++i) Q[(size_t)j * m + i] -= sdot * v[i - k];
+      double* qj = Q.data() + (size_t)j * m + k;
+      const double sdot = betas[k] * dot4(v.data(), qj, len);
+      for (int i = 0; i < len; ++i) qj[i] -= sdot * v[i];
     }
   }
 }

@@ -19,6 +19,7 @@ void svd(int m, int n, const double* A, int lda, std::vector<double>& s, std::ve
          std::vector<double>& V);
 // Householder QR A (m x n) = Q (m x K) R (K x n), K = min(m, n), R upper trapezoidal.
 void householder_qr(int m, int n, const double* A, int lda, std::vector<double>& Q, std::vector<double>& R);
+void householder_r(int m, int n, const double* A, int lda, std::vector<double>& R);
 // Smallest r with sqrt(sum_{i>=r} s_i^2) <= tol ||s||, capped at cap (cap < 0: none).
 int truncation_rank(const std::vector<double>& s, double tol, int cap, double* tail_out);
 

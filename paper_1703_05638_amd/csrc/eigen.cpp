@@ -734,6 +734,8 @@ EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rt
                    P->phase_s[9], P->phase_s[10]);
       std::fflush(stderr);
     }
+    // an empty next block means the Krylov space is invariant: its Ritz pairs are exact
+    res.converged = done || kn == 0;
     if (done || kn == 0 || m + kn > mmax) break;
     // coupling block below the diagonal: W_i = sum_l Vn_l Rn[l, i]
     for (int i = 0; i < bj; ++i)

@@ -193,6 +193,9 @@ class Problem {
 
   // progress lines (JSON, stderr) of the eigensolvers when > 0
   int log_level = 0;
+  // eigensolver limits (0: the defaults of lrpost_eigensolve)
+  int eig_max_vectors = 0;
+  double eig_rtol = 0.0;
 
   // host wall time per phase of a Hessian apply and of the Lanczos step,
   // reported in the progress lines (a phase that ends in a read-back also
@@ -258,6 +261,16 @@ class Problem {
   void st_project_batch(const std::vector<StPrep>& prs, double* Wall, std::vector<StFin>& fins);
   void st_solve_projected(const std::vector<StPrep>& prs, const std::vector<int>& q, std::vector<StFin>& fins);
   void st_truncate(std::vector<StFin>& fins, const std::vector<LowRank*>& Y, bool adjoint);
+  // prepare, pole solves, projection and truncation with the current poles
+  void st_solve_pass(const std::vector<const LowRank*>& F, const std::vector<LowRank*>& Y, bool adjoint);
+  // relative Frobenius residuals of eq. st_pde for the solutions Y_j of F_j
+  void st_residuals(const std::vector<const LowRank*>& F, const std::vector<const LowRank*>& Y, bool adjoint,
+                    std::vector<double>& rel);
+  // residual check of every space-time solve: 0 off, 1 measure (last_st_resid),
+  // 2 measure and, above st_rtol, enrich the basis by a refined pole set once,
+  // then fail with LRPOST_ENOCONV if the residual is still above st_rtol
+  int st_check = 1;
+  double st_rtol = 0.0;
   // G x (precond) or H_mis x (misfit).
   void hess_apply(const LowRank& x, LowRank& y, bool precond);
   // Truncate in place; weight 0: Euclidean, 1: M, 2: K+M.  With ref_norm > 0
@@ -300,6 +313,7 @@ class Problem {
   DevMem mg_work_f_, mg_f_;
   void upload_mg_params(const std::vector<ShiftCoef>& ab);
   // space-time solver workspaces
+  DevMem st_res_a_, st_res_b_, st_res_q_, st_res_g_;
   DevMem st_gram_, st_g_, st_mw_, st_w2_, st_tm_, st_prep_g_, st_prep_t_, st_wall_, st_brep_, st_small_, st_c_, eig_work_;
 };
 
@@ -312,7 +326,8 @@ struct EigResult {
   std::vector<double> lambda;
   std::vector<std::unique_ptr<LowRank>> vecs;
   int steps = 0;
-  double max_resid = -1.0;  // largest relative Ritz residual of the returned pairs
+  double max_resid = -1.0;  // largest relative Ritz residual estimate of the returned pairs
+  bool converged = true;    // every wanted pair met the residual target within the vector limit
 };
 EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rtol);
 // Two-pass randomized eigensolver on the given probes (space-time vectors).
@@ -322,10 +337,13 @@ EigResult randomized_eig(Problem* P, int k, const std::vector<const LowRank*>& p
 
 struct lrpost_problem {
   std::unique_ptr<lrp::Problem> impl;
+  // expires when the handle is destroyed; eigs handles keep a weak reference
+  std::shared_ptr<int> alive = std::make_shared<int>(0);
 };
 
 struct lrpost_eigs {
   lrpost_problem* owner = nullptr;
+  std::weak_ptr<int> owner_alive;
   std::vector<double> lambda;
   std::vector<std::unique_ptr<lrp::LowRank>> vecs;
 };

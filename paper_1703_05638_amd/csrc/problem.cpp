@@ -135,6 +135,8 @@ Problem::Problem(const lrpost_problem_desc& d) : desc(d) {
   if (!(d.trunc_tol > 0) || !(d.trunc_tol < 1)) fail(LRPOST_EINVAL, "trunc_tol must lie in (0, 1)");
   if (d.rank_cap < 1) fail(LRPOST_EINVAL, "rank_cap must be >= 1");
   if (d.precision != LRPOST_FP64 && d.precision != LRPOST_MIXED) fail(LRPOST_EINVAL, "unknown precision");
+  if (d.mg_levels != 0)
+    fail(LRPOST_EINVAL, "mg_levels must be 0: the multigrid hierarchy always coarsens to the LDS-resident levels");
   pool = std::make_shared<Pool>();
   PoolScope scope(pool);
   N = d.N;
@@ -905,8 +907,168 @@ void Problem::spacetime_solve(const LowRank& F, LowRank& Y, bool adjoint) {
   spacetime_solve_batch({&F}, {&Y}, adjoint);
 }
 
+// Space-time solves of a batch with the residual check of the AMEn solver
+// (Sec. 6.1): the relative residual of eq. st_pde is measured for every
+// truncated solution.  Where it exceeds st_rtol the spatial basis of that
+// source is enriched (a pole set refined by the geometric midpoints of
+// neighbouring poles and one more pole beyond each end) and the solve
+// repeated; a residual still above st_rtol ends in LRPOST_ENOCONV.
 void Problem::spacetime_solve_batch(const std::vector<const LowRank*>& F, const std::vector<LowRank*>& Y,
                                     bool adjoint) {
+  st_solve_pass(F, Y, adjoint);
+  if (st_check == 0) return;
+  const int nb = (int)F.size();
+  std::vector<const LowRank*> cy(Y.begin(), Y.end());
+  std::vector<double> rel;
+  st_residuals(F, cy, adjoint, rel);
+  double worst = 0.0;
+  for (double r : rel) worst = std::max(worst, r);
+  stats.last_st_resid = worst;
+  if (st_check < 2) return;
+  const double thr = st_rtol > 0 ? st_rtol : 100.0 * desc.trunc_tol;
+  std::vector<int> bad;
+  for (int j = 0; j < nb; ++j)
+    if (!(rel[j] <= thr)) bad.push_back(j);
+  if (bad.empty()) return;
+  ++stats.st_enrichments;
+  std::vector<double> fine;
+  const std::vector<double> base = poles;
+  const double ratio = base.size() > 1 ? std::sqrt(base[1] / base[0]) : 3.0;
+  fine.push_back(base.front() / ratio);
+  for (size_t i = 0; i < base.size(); ++i) {
+    fine.push_back(base[i]);
+    if (i + 1 < base.size()) fine.push_back(std::sqrt(base[i] * base[i + 1]));
+  }
+  fine.push_back(base.back() * ratio);
+  std::vector<const LowRank*> Fb;
+  std::vector<LowRank*> Yb;
+  for (int j : bad) {
+    Fb.push_back(F[j]);
+    Yb.push_back(Y[j]);
+  }
+  poles = fine;
+  try {
+    st_solve_pass(Fb, Yb, adjoint);
+  } catch (...) {
+    poles = base;
+    throw;
+  }
+  poles = base;
+  std::vector<const LowRank*> cyb(Yb.begin(), Yb.end());
+  st_residuals(Fb, cyb, adjoint, rel);
+  worst = 0.0;
+  for (double r : rel) worst = std::max(worst, r);
+  stats.last_st_resid = worst;
+  if (!(worst <= thr))
+    fail(LRPOST_ENOCONV, "space-time solve: relative residual " + std::to_string(worst) + " above " +
+                             std::to_string(thr) + " after enrichment");
+}
+
+// Relative residuals ||tau K Y + M Y D^T - F||_F / ||F||_F of the solutions
+// Y_j = Y1 Y2^T of sources F_j = F1 F2^T, with D = C (forward: y_k - y_{k-1})
+// or C^T (adjoint: y_k - y_{k+1}).  The residual is A B^T with
+// A = [tau K Y1, M Y1, F1] and B = [Y2, D Y2, -F2]; with the host QR
+// B = Q_B R_B its norm is ||A R_B^T||_F, formed on the device and summed
+// through a Gram product, so that the cancellation between the three terms
+// happens in the explicit sum and not between squared norms.
+void Problem::st_residuals(const std::vector<const LowRank*>& F, const std::vector<const LowRank*>& Y, bool adjoint,
+                           std::vector<double>& rel) {
+  const int nb = (int)F.size();
+  rel.assign(nb, 0.0);
+  std::vector<int> w(nb), c(nb), f(nb);
+  std::vector<size_t> aoff(nb + 1, 0), coff(nb + 1, 0), qoff(nb + 1, 0), goff(nb + 1, 0);
+  for (int j = 0; j < nb; ++j) {
+    f[j] = F[j]->rank;
+    w[j] = 2 * Y[j]->rank + f[j];
+    c[j] = std::min(nt, w[j]);
+    aoff[j + 1] = aoff[j] + (size_t)w[j];
+    coff[j + 1] = coff[j] + (size_t)c[j];
+    qoff[j + 1] = qoff[j] + (size_t)w[j] * c[j];
+    goff[j + 1] = goff[j] + (size_t)c[j] * c[j] + (size_t)f[j] * f[j];
+  }
+  if (aoff[nb] == 0) return;
+  st_res_a_.ensure(sizeof(double) * (size_t)nx * aoff[nb]);
+  st_res_b_.ensure(sizeof(double) * (size_t)nx * std::max<size_t>(coff[nb], 1));
+  st_res_q_.ensure(sizeof(double) * std::max<size_t>(qoff[nb], 1));
+  st_res_g_.ensure(sizeof(double) * std::max<size_t>(goff[nb], 1));
+  double* A = st_res_a_.as<double>();
+  double* Bd = st_res_b_.as<double>();
+  std::vector<double> Qh(std::max<size_t>(qoff[nb], 1), 0.0);
+  std::vector<std::vector<double>> F2g(nb);
+  std::vector<ProjGroup> pg;
+  std::vector<GramGroup> gg;
+  for (int j = 0; j < nb; ++j) {
+    const LowRank& y = *Y[j];
+    const LowRank& fs = *F[j];
+    const int r = y.rank;
+    double* Aj = A + aoff[j] * nx;
+    if (r > 0) {
+      apply_op(r, y.a(), Aj, {{tau, 0.0}});
+      apply_op(r, y.a(), Aj + (size_t)r * nx, {{0.0, 1.0}});
+    }
+    if (f[j] > 0)
+      LRP_HIP(hipMemcpyAsync(Aj + (size_t)2 * r * nx, fs.a(), sizeof(double) * nx * f[j], hipMemcpyDeviceToDevice, st));
+  }
+  // host side of every source on parallel threads (no HIP calls inside)
+  host_parallel(nb, [&](int j) {
+    const LowRank& y = *Y[j];
+    const LowRank& fs = *F[j];
+    const int r = y.rank;
+    // B = [Y2, D Y2, -F2] (nt x w) and its triangular factor
+    std::vector<double> B((size_t)nt * std::max(w[j], 1), 0.0);
+    for (int cc = 0; cc < r; ++cc)
+      for (int k = 0; k < nt; ++k) {
+        const double v = y.B[(size_t)cc * nt + k];
+        const int kn = adjoint ? k + 1 : k - 1;
+        const double prev = (kn >= 0 && kn < nt) ? y.B[(size_t)cc * nt + kn] : 0.0;
+        B[(size_t)cc * nt + k] = v;
+        B[(size_t)(r + cc) * nt + k] = v - prev;
+      }
+    for (int cc = 0; cc < f[j]; ++cc)
+      for (int k = 0; k < nt; ++k) B[(size_t)(2 * r + cc) * nt + k] = -fs.B[(size_t)cc * nt + k];
+    if (w[j] == 0) return;
+    std::vector<double> RB;
+    householder_r(nt, w[j], B.data(), nt, RB);
+    // R_B^T (w x c)
+    double* Rt = Qh.data() + qoff[j];
+    for (int jj = 0; jj < c[j]; ++jj)
+      for (int i = 0; i < w[j]; ++i) Rt[(size_t)jj * w[j] + i] = RB[(size_t)i * c[j] + jj];
+    // Gram of the source's temporal factor (host)
+    F2g[j].assign((size_t)f[j] * f[j], 0.0);
+    for (int a = 0; a < f[j]; ++a)
+      for (int b = 0; b < f[j]; ++b) {
+        double t = 0.0;
+        for (int k = 0; k < nt; ++k) t += fs.B[(size_t)a * nt + k] * fs.B[(size_t)b * nt + k];
+        F2g[j][(size_t)b * f[j] + a] = t;
+      }
+  });
+  to_device(st_res_q_.as<double>(), Qh.data(), Qh.size());
+  double* Gd = st_res_g_.as<double>();
+  for (int j = 0; j < nb; ++j) {
+    if (w[j] == 0) continue;
+    double* Cj = Bd + coff[j] * nx;
+    pg.push_back(ProjGroup{A + aoff[j] * nx, st_res_q_.as<double>() + qoff[j], Cj, Cj, nx, nx, nx, w[j], w[j], c[j]});
+    gg.push_back(GramGroup{Cj, Cj, nullptr, Gd + goff[j], nx, nx, c[j], 0, c[j], c[j], 0});
+    if (f[j] > 0) {
+      const double* F1 = A + (aoff[j] + (size_t)2 * Y[j]->rank) * nx;
+      gg.push_back(GramGroup{F1, F1, nullptr, Gd + goff[j] + (size_t)c[j] * c[j], nx, nx, f[j], 0, f[j], f[j], 0});
+    }
+  }
+  proj_dev_grouped(pg, 1.0, 0.0);
+  gram_dev_grouped(gg);
+  std::vector<double> Gh(goff[nb]);
+  to_host(Gh.data(), Gd, Gh.size());
+  for (int j = 0; j < nb; ++j) {
+    if (w[j] == 0) continue;
+    double r2 = 0.0, f2 = 0.0;
+    for (int i = 0; i < c[j]; ++i) r2 += Gh[goff[j] + (size_t)i * c[j] + i];
+    const double* G1 = Gh.data() + goff[j] + (size_t)c[j] * c[j];
+    for (size_t i = 0; i < (size_t)f[j] * f[j]; ++i) f2 += G1[i] * F2g[j][i];
+    rel[j] = f2 > 0 ? std::sqrt(std::max(r2, 0.0) / f2) : (r2 > 0 ? INFINITY : 0.0);
+  }
+}
+
+void Problem::st_solve_pass(const std::vector<const LowRank*>& F, const std::vector<LowRank*>& Y, bool adjoint) {
   const int nb = (int)F.size();
   std::vector<StPrep> prs(nb);
   std::vector<const StPrep*> pp;
@@ -1562,19 +1724,37 @@ void Problem::truncate(LowRank& x, double tol, int cap, int weight, double ref_n
     x.resize(nx, nt, 0);
     return;
   }
-  bool plain = chol_step(G, 0.0);
+  // Plain CholeskyQR2 when the first factor certifies the conditioning:
+  // ||R||_F ||R^{-1}||_F bounds cond_2(A') from above, and below 1e5 the
+  // second pass restores orthonormality to rounding level.  If a later
+  // Cholesky of the plain path still fails, the shifted path starts over
+  // from A' (still intact in qa: the plain path's first projection writes qb).
+  const std::vector<double> G0 = G;
+  auto cond_ok = [&]() {
+    double fr = 0.0, fi = 0.0;
+    for (int j = 0; j < kcur; ++j)
+      for (int i = 0; i <= j; ++i) {
+        fr += Rf[(size_t)j * kcur + i] * Rf[(size_t)j * kcur + i];
+        fi += T[(size_t)j * kcur + i] * T[(size_t)j * kcur + i];
+      }
+    return std::sqrt(fr * fi) < 1e5;
+  };
+  bool plain = chol_step(G, 0.0) && cond_ok();
   if (plain) {
-    double dmin = 1e300, dmax = 0.0;
-    for (int i = 0; i < kcur; ++i) {
-      dmin = std::min(dmin, Rf[(size_t)i * kcur + i]);
-      dmax = std::max(dmax, Rf[(size_t)i * kcur + i]);
+    accept(true);
+    kcur = kout;
+    gram_w(src, kcur, G);
+    if (!chol_step(G, 0.0)) {
+      plain = false;
+      src = qa.as<double>();
+      dst = qb.as<double>();
+      kcur = c;
+      G = G0;
+      RA.assign((size_t)c * c, 0.0);
+      for (int i = 0; i < c; ++i) RA[(size_t)i * c + i] = 1.0;
     }
-    plain = dmin >= 1e-5 * dmax;
   }
-  int remaining_chol;
-  if (plain) {
-    remaining_chol = 1;  // CholeskyQR2: this pass plus one more
-  } else {
+  if (!plain) {
     double shift = 11.0 * ((double)nx * kcur + (double)kcur * (kcur + 1)) * u * tr;
     int attempt = 0;
     while (!chol_step(G, shift)) {
@@ -1586,14 +1766,11 @@ void Problem::truncate(LowRank& x, double tol, int cap, int weight, double ref_n
     gram_w(src, kcur, G);
     eig_step(G);
     if (kout == 0) { x.resize(nx, nt, 0); return; }
-    remaining_chol = 1;
     // the eigen step is applied now; CholeskyQR2 follows
     accept(true);
     kcur = kout;
     gram_w(src, kcur, G);
     if (!chol_step(G, 0.0)) fail(LRPOST_EBREAKDOWN, "Cholesky failed after the eigen pass in truncation");
-  }
-  for (int k = 0; k < remaining_chol; ++k) {
     accept(true);
     kcur = kout;
     gram_w(src, kcur, G);

@@ -50,7 +50,7 @@ class LowRankC(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("applies", ctypes.c_int64), ("last_rank_y", ctypes.c_int32), ("last_rank_p", ctypes.c_int32),
                 ("last_rank_out", ctypes.c_int32), ("last_basis", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("last_tail", ctypes.c_double), ("last_st_resid", ctypes.c_double),
+                ("st_enrichments", ctypes.c_int32), ("last_tail", ctypes.c_double), ("last_st_resid", ctypes.c_double),
                 ("ritz_resid", ctypes.c_double)]
 
 
@@ -96,6 +96,9 @@ def load(path: str = LIB_PATH):
         "lrpost_gram": (I, [P, I, P, I, P, pd]),
         "lrpost_truncate": (I, [P, ctypes.POINTER(LowRankC), D, I]),
         "lrpost_set_log": (I, [P, I]),
+        "lrpost_set_eig_limits": (I, [P, I, D]),
+        "lrpost_eig_residuals": (I, [P, P, pd]),
+        "lrpost_set_st_check": (I, [P, I, D]),
         "lrpost_profile": (I, [P, I]),
         "lrpost_profile_read": (I, [P, I, ctypes.POINTER(ctypes.c_int64), pd, pd, pd]),
         "lrpost_set_mg_fused": (I, [P, I]),
@@ -307,12 +310,34 @@ class Problem:
         _check(_lib.lrpost_prior_variance(self.h, _hptr(out)))
         return out
 
-    def eigensolve(self, k: int, method: int = LRPOST_BLOCK_LANCZOS, oversample: int = 10) -> "Eigs":
+    def eigensolve(self, k: int, method: int = LRPOST_BLOCK_LANCZOS, oversample: int = 10,
+                   allow_unconverged: bool = False) -> "Eigs":
+        """k leading eigenpairs.  On LRPOST_ENOCONV the pairs reached are still
+        returned (with .converged False) when allow_unconverged, else it raises."""
         e = ctypes.c_void_p()
-        _check(_lib.lrpost_eigensolve(self.h, k, method, oversample, ctypes.byref(e)))
+        rc = _lib.lrpost_eigensolve(self.h, k, method, oversample, ctypes.byref(e))
+        return self._eigs_result(rc, e, allow_unconverged)
+
+    def _eigs_result(self, rc, e, allow_unconverged):
+        if rc == -3 and e.value:
+            out = Eigs(self, e)
+            out.converged = False
+            out.message = _lib.lrpost_last_error().decode()
+            if allow_unconverged:
+                return out
+            out.close()
+        _check(rc)
         return Eigs(self, e)
 
-    def eigensolve_probes(self, k: int, probes) -> "Eigs":
+    def set_eig_limits(self, max_vectors: int = 0, rtol: float = 0.0):
+        """Block-Lanczos vector limit and relative Ritz residual target (0: defaults)."""
+        _check(_lib.lrpost_set_eig_limits(self.h, int(max_vectors), float(rtol)))
+
+    def set_st_check(self, mode: int = 2, rtol: float = 0.0):
+        """Residual check of the space-time solves: 0 off, 1 measure, 2 measure and enrich."""
+        _check(_lib.lrpost_set_st_check(self.h, int(mode), float(rtol)))
+
+    def eigensolve_probes(self, k: int, probes, allow_unconverged: bool = False) -> "Eigs":
         """Randomized two-pass eigensolver on caller probes [(W1 (r, nx) CUDA, W2 (r, nt) host), ...]."""
         arr = (LowRankC * len(probes))()
         keep = []
@@ -321,8 +346,8 @@ class Problem:
             keep.append(x)
             arr[i] = x
         e = ctypes.c_void_p()
-        _check(_lib.lrpost_eigensolve_probes(self.h, k, len(probes), arr, ctypes.byref(e)))
-        return Eigs(self, e)
+        rc = _lib.lrpost_eigensolve_probes(self.h, k, len(probes), arr, ctypes.byref(e))
+        return self._eigs_result(rc, e, allow_unconverged)
 
     def eigs_from_pairs(self, lam, vecs) -> "Eigs":
         lam = np.ascontiguousarray(lam, dtype=np.float64)
@@ -394,13 +419,21 @@ class Problem:
     def stats(self) -> dict:
         s = Stats()
         _check(_lib.lrpost_get_stats(self.h, ctypes.byref(s)))
-        return {f: getattr(s, f) for f, _ in Stats._fields_ if f != "pad"}
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
 
 
 class Eigs:
     def __init__(self, prob: Problem, h):
         self.prob = prob
         self.h = h
+        self.converged = True
+        self.message = ""
+
+    def residuals(self) -> np.ndarray:
+        """Measured ||G v - lambda v||_P / |lambda| of every stored pair (one apply each)."""
+        out = np.zeros(len(self))
+        _check(_lib.lrpost_eig_residuals(self.prob.h, self.h, _hptr(out)))
+        return out
 
     def __len__(self):
         return _lib.lrpost_eig_count(self.h)

@@ -34,3 +34,22 @@ def test_error_path_without_gpu_work():
     rc = lib.lrpost_create(ctypes.byref(d), ctypes.byref(h))
     assert rc == -1
     assert b"power of two" in lib.lrpost_last_error()
+
+
+def test_rejections_before_device_work():
+    """mg_levels other than 0, null handles and negative limits are refused
+    with LRPOST_EINVAL before anything touches the device."""
+    if not os.path.exists(lp.LIB_PATH):
+        pytest.skip("library not built")
+    lib = lp.load()
+    d = lp.Desc()
+    d.N, d.nt, d.T, d.alpha, d.sigma = 32, 10, 1.0, 1e-2, 1e-2
+    d.box[0], d.box[1], d.box[2], d.box[3] = 0.25, 0.75, 0.25, 0.75
+    d.trunc_tol, d.rank_cap, d.mg_levels = 1e-6, 8, 4
+    h = ctypes.c_void_p()
+    assert lib.lrpost_create(ctypes.byref(d), ctypes.byref(h)) == -1
+    assert b"mg_levels" in lib.lrpost_last_error()
+    assert lib.lrpost_set_eig_limits(None, 8, 0.0) == -1
+    assert lib.lrpost_set_st_check(None, 1, 0.0) == -1
+    res = (ctypes.c_double * 1)()
+    assert lib.lrpost_eig_residuals(None, None, res) == -1

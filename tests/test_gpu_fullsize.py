@@ -1,0 +1,116 @@
+"""GPU parity at the bench sizes (256 x 256 mesh, nt = 200): the paths that
+only run above the coarse LDS level -- level-fused multigrid kernels, Gram
+tiles of every height, the full-size space-time solve -- against the oracle.
+
+Full observation (box = the whole square) has the closed-form spectrum of the
+separable pencil (Sec. 5): per sine mode p the time operator is the bidiagonal
+B_p = (1 + tau lambda_p) I - S, and the eigenvalues are
+tau / (sigma^2 alpha (kappa_p + mu_p) s_q(B_p)^2).  It holds at any size and
+so catches a missed or spurious eigenvalue of the full-size eigensolve.
+"""
+import dataclasses
+import os
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import synthetic  # noqa: E402
+from oracle import closed_forms, fem  # noqa: E402
+from oracle.spacetime import Problem as OP  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1703_05638_amd import lrpost
+    lrpost.load()
+    return lrpost
+
+
+def _dev(a):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("m,q", [(100, 64), (180, 180), (250, 61), (400, 135)])
+def test_gram_tiles_at_bench_size(lp, m, q):
+    """C = A^T B at nx = 65,025 for tile heights 2 and 3 (m = 100, 180) and the
+    multi-tile path (m = 250, 400), against the float64 definition."""
+    print("case gram nx=65025 m=%d q=%d" % (m, q), flush=True)
+    prob = lp.Problem(synthetic.ProblemDesc(N=256, nt=4, trunc_tol=1e-6, rank_cap=8))
+    rng = np.random.default_rng(m + 7 * q)
+    A = rng.standard_normal((m, prob.nx))
+    B = A[:q] if m == q else rng.standard_normal((q, prob.nx))
+    C = prob.gram(_dev(A), _dev(B))
+    ref = A @ B.T
+    err = np.abs(C - ref).max() / np.abs(ref).max()
+    print("gram max rel err %.3e" % err, flush=True)
+    assert err <= 1e-13
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_spacetime_solve_at_bench_size(lp, precision, adjoint):
+    """256 x 256 mesh, nt = 200, tol 1e-6: the low-rank solve against the
+    oracle's sparse-LU time stepping of eq. st_pde, both directions, both
+    precisions, with a rank-3 source of smooth time profiles."""
+    print("case spacetime N=256 nt=200 %s adjoint=%s" % (precision, adjoint), flush=True)
+    d = dataclasses.replace(synthetic.MESH256_NT200, precision=precision)
+    prob = lp.Problem(d)
+    ora = OP.from_desc(d)
+    rng = np.random.default_rng(256 + adjoint)
+    A = rng.standard_normal((prob.nx, 3))
+    B = np.cumsum(rng.standard_normal((d.nt, 3)), axis=0) / np.sqrt(d.nt)
+    F1 = ora.tau * (ora.M @ A)
+    Y1, Y2 = prob.spacetime_solve(_dev(F1.T), B.T, adjoint)
+    got = Y1.cpu().numpy().T @ Y2
+    F = F1 @ B.T
+    ref = ora.adjoint_source(F) if adjoint else ora.forward_source(F)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print("space-time solve N=256 rel err %.3e rank %d residual %.3e" %
+          (err, Y1.shape[0], prob.stats()["last_st_resid"]), flush=True)
+    assert err <= 20 * d.trunc_tol
+
+
+def _full_obs_top(N, nt, T, alpha, sigma, k):
+    """The k largest closed-form eigenvalues with full observation.  Modes are
+    taken in increasing lambda_p until the largest eigenvalue any further mode
+    can have, tau / (sigma^2 alpha (kappa+mu) (tau lambda_p)^2) (s_min(B_p) >=
+    tau lambda_p), falls below the k-th value found."""
+    _, kappa, mu = fem.modes_2d(N)
+    tau = T / nt
+    lam = (kappa / mu).ravel()
+    order = np.argsort(lam)
+    n = N - 1
+    vals = []
+    for idx in order:
+        i, j = idx // n + 1, idx % n + 1
+        bound = tau / (sigma ** 2 * alpha * (kappa.ravel()[idx] + mu.ravel()[idx]) * (tau * lam[idx]) ** 2)
+        if len(vals) >= k and bound < sorted(vals)[-k]:
+            break
+        ev, _ = closed_forms.full_obs_eigs(N, nt, T, alpha, sigma, modes=[(i, j)])
+        vals.extend(ev[:k])
+    return np.sort(np.asarray(vals))[::-1][:k]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_observation_spectrum_at_bench_size(lp, precision):
+    """Box = [0, 1]^2 at the bench size (N = 256, nt = 200, tol 1e-6, k = 50):
+    the GPU's 50 leading eigenvalues equal the closed form to 1e-5."""
+    print("case full observation N=256 nt=200 %s" % precision, flush=True)
+    d = dataclasses.replace(synthetic.MESH256_NT200, box=(0.0, 1.0, 0.0, 1.0), precision=precision)
+    ref = _full_obs_top(d.N, d.nt, d.T, d.alpha, d.sigma, d.k)
+    prob = lp.Problem(d)
+    lam = prob.eigensolve(d.k).values()
+    rel = np.abs(lam - ref) / ref
+    print("full observation top-%d max rel err %.3e (lambda_1 %.6e, lambda_50 %.6e)" %
+          (d.k, rel.max(), ref[0], ref[-1]), prob.stats(), flush=True)
+    assert rel.max() < 1e-5

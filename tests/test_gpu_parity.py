@@ -311,7 +311,7 @@ def test_randomized_eigensolver_matches_oracle(lp):
     theta_ref, _, res_ref = randomized_eig(ora, probes_from_factors(G1, G2), 10)
     prob = lp.Problem(d)
     probes = [(_dev(G1[j].T), G2[j].T / 2.0) for j in range(16)]  # G1 G2^T / sqrt(4)
-    eig = prob.eigensolve_probes(10, probes)
+    eig = prob.eigensolve_probes(10, probes, allow_unconverged=True)
     theta = eig.values()
     rel = np.abs(theta - theta_ref) / theta_ref
     st = prob.stats()
@@ -331,7 +331,7 @@ def test_randomized_internal_probes_bound_lanczos(lp):
     d = _desc(32, 40, tol=1e-10, cap=40)
     prob = lp.Problem(d)
     lam = prob.eigensolve(10).values()
-    th = prob.eigensolve(10, method=lp.LRPOST_RANDOMIZED, oversample=10).values()
+    th = prob.eigensolve(10, method=lp.LRPOST_RANDOMIZED, oversample=10, allow_unconverged=True).values()
     res = prob.stats()["ritz_resid"]
     print("randomized vs lanczos:", th[:4], lam[:4], "max rel resid %.3e" % res, flush=True)
     assert np.all(th <= lam * (1 + 1e-9))
@@ -362,8 +362,10 @@ def test_server_results_alone_equal_in_the_mix(lp):
     """Serving loop: nine requests of different mesh and time sizes, priors,
     noise levels, boxes and tolerances submitted at once to four workers;
     every result (eigenvalues and posterior variance) equals the same request
-    solved alone on a fresh problem within the float64 accuracy bar (1e-8
-    relative), and requests overlapped.  Two rounds of submissions."""
+    solved alone on a fresh problem bit for bit (the library's kernels use no
+    atomics and no scheduling-dependent reductions, and its dense library
+    calls are ordered across streams), and requests overlapped.  Two rounds of
+    submissions."""
     import dataclasses
     print("case server mix", flush=True)
     base = synthetic.ProblemDesc(N=16, nt=8, trunc_tol=1e-10, rank_cap=16, k=6)
@@ -396,8 +398,8 @@ def test_server_results_alone_equal_in_the_mix(lp):
             lam_mix, D_mix, _ = m[i]
             print("alone vs mix: eigenvalues %.3e, variance %.3e" % (np.abs(lam_mix - lam).max() / np.abs(lam).max(),
                                                                  np.abs(D_mix - D).max() / np.abs(D).max()), flush=True)
-            assert np.allclose(lam_mix, lam, rtol=1e-8, atol=0)
-            assert np.allclose(D_mix, D, rtol=1e-8, atol=0)
+            assert np.array_equal(lam_mix, lam)
+            assert np.array_equal(D_mix, D)
 
 
 def test_batched_applies_equal_single_applies(lp):
@@ -426,8 +428,10 @@ def test_bench_size_eigenpairs_certified_by_oracle(lp):
     """The bench workload at full size (256 x 256 mesh, nt = 200, tol 1e-6,
     k = 50, float64 and mixed): the oracle's exact float64 G is applied to the
     GPU's leading, second and 50th eigenvectors one by one.  Their Rayleigh
-    quotients match the GPU eigenvalues to 1e-5 relative and the relative
-    residuals ||G v - lambda v||_P / lambda stay at the truncation level.
+    quotients match the GPU eigenvalues to 1e-5 relative, the relative
+    residuals ||G v - lambda v||_P / lambda stay at the truncation level
+    (below 2e-4), and the library's own measured residuals
+    (lrpost_eig_residuals, with its truncated apply) agree with them.
     Sampled entries of diag(Gamma_post,50) equal dprior - sum_i d_i v_i^2
     evaluated from the same eigenvectors."""
     import dataclasses
@@ -438,6 +442,7 @@ def test_bench_size_eigenpairs_certified_by_oracle(lp):
         prob = lp.Problem(d)
         eig = prob.eigensolve(d.k)
         lam = eig.values()
+        res_lib = eig.residuals()
         vecs = {}
         for i in (0, 1, d.k - 1):
             W1, W2 = eig.vector(i)
@@ -448,10 +453,11 @@ def test_bench_size_eigenpairs_certified_by_oracle(lp):
             rho = ora.P_inner(V, GV) / vv
             R = GV - lam[i] * V
             res = np.sqrt(ora.P_inner(R, R) / vv) / lam[i]
-            print("%s pair %d: lambda %.10e rayleigh rel err %.3e residual %.3e" %
-                  (precision, i, lam[i], abs(rho - lam[i]) / lam[i], res), flush=True)
+            print("%s pair %d: lambda %.10e rayleigh rel err %.3e residual %.3e (library %.3e)" %
+                  (precision, i, lam[i], abs(rho - lam[i]) / lam[i], res, res_lib[i]), flush=True)
             assert abs(rho - lam[i]) / lam[i] < 1e-5
-            assert res < 1e-3
+            assert res < 2e-4
+            assert abs(res_lib[i] - res) <= 0.25 * res + 5 * d.trunc_tol
         # sampled variance entries against the formula with all 50 GPU eigenvectors
         D = prob.post_variance(eig, on_device=False)  # (nt, nx)
         rng = np.random.default_rng(7)
