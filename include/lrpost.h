@@ -271,6 +271,20 @@ int lrpost_stencil_apply(lrpost_problem* p, int ncols, const double* X, double* 
 int lrpost_mg_solve(lrpost_problem* p, int ncols, const double* B, double* X, const double* coef, int cycles);
 /* C = A^T B  (A: nx x m, B: nx x q, C: host m x q column-major). */
 int lrpost_gram(lrpost_problem* p, int m, const double* A, int q, const double* B, double* C_host);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the Gram
+ * product of lrpost_gram, C = A^T B, with C in DEVICE memory (m x q,
+ * column-major, leading dimension m, caller-owned) instead of host memory.
+ * Its partial products go to a static scratch array of 64 MiB per device
+ * (resolved when the first problem is created on that device and held until
+ * the process ends); the call allocates and frees nothing and does not
+ * synchronize: the work is enqueued on p's stream and C is complete when the
+ * stream reaches it.  Every call on one device shares that array, so calls
+ * whose work overlaps on one device (two streams, two threads) race; calls
+ * ordered on one stream do not.  Returns LRPOST_EINVAL when the product needs
+ * more than the array holds (e.g. m = q = 4096 on a 32 x 32 mesh); the same
+ * kernels and chunking as lrpost_gram give the same bits. */
+int lrpost_gram_noalloc(lrpost_problem* p, int m, const double* A, int q, const double* B, double* C_dev);
 /* Truncate X = W1 W2^T in place to tolerance tol (<= 0: desc.trunc_tol) and
  * rank <= cap; weighted = 1 measures in the M-norm in space. */
 int lrpost_truncate(lrpost_problem* p, lrpost_lowrank* x, double tol, int weighted);

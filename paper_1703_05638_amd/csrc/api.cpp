@@ -93,6 +93,8 @@ int lrpost_create(const lrpost_problem_desc* desc, lrpost_problem** out) {
     auto h = new lrpost_problem();
     try {
       h->impl = std::make_unique<Problem>(*desc);
+      // resolve the static Gram scratch of this device (lrpost_gram_noalloc)
+      if (!gram_scratch_setup()) fail(LRPOST_EHIP, "hipGetSymbolAddress of the Gram scratch failed");
     } catch (...) {
       delete h;
       throw;
@@ -562,6 +564,29 @@ int lrpost_gram(lrpost_problem* p, int m, const double* A, int q, const double* 
     std::vector<double> C;
     P->gram(m, A, q, B, C);
     if (!C.empty()) std::memcpy(C_host, C.data(), sizeof(double) * C.size());
+  });
+}
+
+// C = A^T B with the partial products in the static per-device scratch: no
+// allocation, no synchronization (the result is complete when p's stream
+// reaches it).  Same kernels and chunking as lrpost_gram.
+int lrpost_gram_noalloc(lrpost_problem* p, int m, const double* A, int q, const double* B, double* C_dev) {
+  return guarded([&] {
+    Problem* P = impl(p);
+    if (m < 0 || q < 0 || (m > 0 && q > 0 && (!A || !B || !C_dev))) fail(LRPOST_EINVAL, "bad arguments");
+    if (m == 0 || q == 0) return;
+    const long need = gram_part_doubles(P->nx, m, q);
+    if (need > kGramScratchDoubles)
+      fail(LRPOST_EINVAL, "Gram of " + std::to_string(m) + " x " + std::to_string(q) + " needs " +
+                              std::to_string(need * 8) + " bytes of scratch, above the static " +
+                              std::to_string(kGramScratchDoubles * 8));
+    double* scratch = gram_scratch_device();
+    if (!scratch) scratch = gram_scratch_setup();
+    if (!scratch) fail(LRPOST_EHIP, "hipGetSymbolAddress of the Gram scratch failed");
+    GramGroup g{A, B, scratch, C_dev, P->nx, P->nx, m, 0, m, q, 0};
+    gram_mfma_partials(P->st, P->nx, 1, &g);
+    sum_partials_grouped(P->st, 1, &g);
+    LRP_HIP(hipGetLastError());
   });
 }
 

@@ -139,4 +139,14 @@ void f2d(hipStream_t st, long n, const float* x, double* y);
 void post_variance(hipStream_t st, long nx, int nt, int k, const int* seg, const double* dcoef, const double* A,
                    long lda, const double* Bt, int R, const double* dprior, double* D, long ldd);
 
+// Static partial-product scratch of the Gram products for callers that cannot
+// allocate: kGramScratchDoubles doubles per device, held until the process
+// ends.  gram_scratch_setup() resolves the array's address on the current
+// device (once per device, later calls return the cached address; nullptr on
+// a HIP error); gram_scratch_device() returns it for the current device, or
+// nullptr before setup there.
+constexpr long kGramScratchDoubles = long(8) << 20;  // 64 MiB
+double* gram_scratch_setup();
+double* gram_scratch_device();
+
 }  // namespace lrp

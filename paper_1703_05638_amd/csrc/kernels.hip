@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "kernels.h"
 
 namespace lrp {
@@ -1156,6 +1158,36 @@ void sum_partials_grouped(hipStream_t st, int count, const GramGroup* groups) {
     if (cmax <= 0) continue;
     hipLaunchKernelGGL(k_sum_partials_grouped, dim3((cmax + SP_X - 1) / SP_X, n), dim3(SP_X * SP_Y), 0, st, gs);
   }
+}
+
+// The scratch array itself.  Host code never passes its name to a kernel:
+// the name is a host-side stand-in, and only the address from
+// hipGetSymbolAddress (one per device) is device memory.
+static __device__ __align__(256) double scratch[kGramScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+double* gram_scratch_setup() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+
+double* gram_scratch_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[dev];
 }
 
 long gram_part_doubles(long nrows, int m, int q) {

@@ -94,6 +94,7 @@ def load(path: str = LIB_PATH):
         "lrpost_stencil_apply": (I, [P, I, P, P, P, pd]),
         "lrpost_mg_solve": (I, [P, I, P, P, pd, I]),
         "lrpost_gram": (I, [P, I, P, I, P, pd]),
+        "lrpost_gram_noalloc": (I, [P, I, P, I, P, P]),
         "lrpost_truncate": (I, [P, ctypes.POINTER(LowRankC), D, I]),
         "lrpost_set_log": (I, [P, I]),
         "lrpost_set_eig_limits": (I, [P, I, D]),
@@ -304,6 +305,14 @@ class Problem:
         C = np.zeros((q, m))  # column-major m x q == row-major q x m
         _check(_lib.lrpost_gram(self.h, m, _dptr(A), q, _dptr(B), _hptr(C)))
         return C.T.copy()
+
+    def gram_noalloc(self, A, B, C):
+        """C (q, m) float64 CUDA, caller-allocated: C^T = A^T B enqueued on the
+        problem's stream with the library's static scratch (no allocation, no sync)."""
+        m, q = A.shape[0], B.shape[0]
+        assert tuple(C.shape) == (q, m) and C.is_contiguous()
+        _check(_lib.lrpost_gram_noalloc(self.h, m, _dptr(A), q, _dptr(B), _dptr(C)))
+        return C
 
     def prior_variance(self):
         out = np.zeros(self.nx)
