@@ -21,6 +21,9 @@ paper (or of the reading stated in its docstring), in float64:
                  Sec. 4 Algorithm 1 with modified Gram-Schmidt
   closed_forms   spectra known in closed form (Sec. 5 and its space-time SVD
                  argument) used as pins
+  mean           the posterior mean / MAP point (Sec. 2 eq. map1): normal
+                 equations, data-space form, and the fully observed closed
+                 form mode by mode
 
 Functions whose results have no independent pin say "parity unpinned" in
 their docstring.
