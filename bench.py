@@ -1,24 +1,30 @@
-"""Benchmark: Hessian applies per second during a full low-rank posterior
-computation on one MI355X.
+"""Benchmark: Hessian applies per second on the largest single-GPU workload.
 
-A step is one pass of the whole hot path on the 256 x 256 mesh, nt = 200
-workload (alpha = sigma = 1e-2, observation box [0.25, 0.75]^2, truncation
-tolerance 1e-6, factor rank <= 64): block-Lanczos eigensolve for the 50
-leading eigenpairs of the prior-preconditioned misfit Hessian (every Krylov
-vector a low-rank space-time vector, every apply a forward and an adjoint
-low-rank space-time solve plus a prior solve) followed by the posterior
-variance diag(Gamma_post,50) over all nx * nt space-time points.  Inputs are
-synthetic (seeded start block); they are generated inside the library and
-are resident in HBM when the timed region starts.
+Headline workload (mesh1024_nt1000): the 1024 x 1024 mesh (nx = 1,046,529
+interior nodes), nt = 1000 implicit-Euler steps, alpha = sigma = 1e-2,
+observation box [0.25, 0.75]^2, truncation tolerance 1e-6, factor rank <= 128,
+mixed precision (float32 stencil and multigrid, float64 refinement,
+projections, truncations and Lanczos matrix).  A step is one pass of the hot
+path over it: block-Lanczos iterations for the k = 100 leading eigenpairs of
+the prior-preconditioned misfit Hessian, stopped at a fixed budget of Krylov
+vectors (--vectors, default 40, i.e. 10 block steps of 4 applies; every
+Krylov vector a low-rank space-time vector, every apply a forward and an
+adjoint low-rank space-time solve plus a prior solve), then the Ritz pairs
+reached and the posterior variance diag(Gamma_post) over all nx * nt = 1.05e9
+space-time points from them.  A full 100-pair posterior at this size takes
+several minutes, so the step budget is in vectors; value counts the applies
+completed.  Inputs are synthetic (seeded start block), generated inside the
+library and resident in HBM when the timed region starts.
 
-value = Hessian applies completed in the timed steps / timed seconds.  The
-default precision is mixed (float32 multigrid cycles with float64 iterative
-refinement of the prior solve; projections, truncations and the Lanczos
-matrix in float64); afterwards the same step runs in float64, and its
-throughput and the mixed result's relative error against it (eigenvalues and
-posterior variance) are reported under "fp64_reference".
+value = Hessian applies completed in the timed steps / timed seconds.  After
+the mixed steps the same step runs in float64; its throughput and the mixed
+result's relative error against it (Ritz values and posterior variance) are
+reported under "fp64_reference".  "mesh256_posterior" reports a complete
+50-pair posterior on the 256 x 256 mesh, nt = 200 workload (applies/s and the
+posterior latency).  "cpu_baseline" times the float64 oracle's apply on a
+bounded sample of the headline workload.
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-[--precision mixed|fp64] [--serving R]
+[--precision mixed|fp64] [--vectors V] [--serving R] [--randomized]
 """
 import argparse
 import json
@@ -41,40 +47,46 @@ KERNELS = {
     2: ("k_mg_up", "level-fused prolongation + post-smoothing", True),
     3: ("k_gram_mfma", "float64 matrix-core Gram A^T B, partial products", False),
     4: ("k_proj_mfma", "float64 matrix-core projection C = beta C + A Q", False),
+    5: ("k_stencil_strip", "Q1 stencil SpMM a K x + b M x (+ c z), all columns per launch", True),
 }
 MFMA_F64_PEAK_TFLOPS = 78.6  # MI355X published dense FP64 matrix throughput
 
 
-def traffic_report(kernel, precision):
+def traffic_report(kernel, precision, workload):
     # the multigrid kernels run in float32 in mixed precision, the Gram always in float64
     f32 = precision == "mixed" and KERNELS[[k for k in KERNELS if KERNELS[k][0] == kernel][0]][2]
     tag = "f32_" if f32 else ""
     suffix = "_mixed" if precision == "mixed" else ""
-    return os.path.join(ROOT, "profiles", "%s_%smesh256_nt200%s_traffic.txt" % (kernel, tag, suffix))
+    return os.path.join(ROOT, "profiles", "%s_%s%s%s_traffic.txt" % (kernel, tag, workload, suffix))
 
 
-def cpu_baseline(desc, budget_s=20.0):
-    """The FP64 oracle's Hessian apply (implicit-Euler time stepping with a
-    sparse LU of M + tau K) on the same workload, timed on the host."""
+def cpu_baseline(desc, sample_steps=16):
+    """The FP64 oracle's Hessian apply G (implicit-Euler time stepping with a
+    sparse LU of M + tau K, observation, backward adjoint stepping, sparse-LU
+    prior solve) on the headline mesh and time step, timed on the host over
+    the first sample_steps of the nt time steps (the per-step work does not
+    depend on the step) and scaled by nt / sample_steps.  The LU factors are
+    computed before the timed region."""
+    import dataclasses
+
     import numpy as np
     from oracle.spacetime import Problem as OracleProblem
 
-    ora = OracleProblem.from_desc(desc)
+    short = dataclasses.replace(desc, nt=sample_steps, T=desc.T * sample_steps / desc.nt)
+    ora = OracleProblem.from_desc(short)
     rng = np.random.default_rng(1)
     A = rng.standard_normal((ora.nx, 20))
     B = np.cumsum(rng.standard_normal((ora.nt, 20)), axis=0) / np.sqrt(ora.nt)
     X = A @ B.T
     t0 = time.perf_counter()
-    n = 0
-    while True:
-        ora.G(X)
-        n += 1
-        if time.perf_counter() - t0 > budget_s / 2 or n >= 3:
-            break
+    ora.G(X)
     dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "Hessian applies/s", "cores": 1, "kind": "oracle",
-            "sample": "%d full FP64 G-applies on a rank-20 space-time input, 256x256 mesh, nt=200 "
-                      "(SuperLU factor reused; single-threaded)" % n}
+    per_apply = dt * desc.nt / sample_steps
+    return {"value": 1.0 / per_apply, "unit": "Hessian applies/s", "cores": 1, "kind": "oracle",
+            "sample": "one full FP64 G-apply of the oracle on a rank-20 space-time input over the first %d of "
+                      "the %d time steps (same %dx%d mesh and tau), %.1f s, scaled by %d; SuperLU factors "
+                      "built beforehand, single-threaded" % (sample_steps, desc.nt, desc.N, desc.N, dt,
+                                                             desc.nt // sample_steps)}
 
 
 def serving(args):
@@ -132,9 +144,12 @@ def serving(args):
 def randomized(args):
     """The randomized two-pass eigensolver on the 512 x 512 mesh, nt = 500
     workload (alpha = 1e-3, sigma = 5e-3, tol 1e-6, rank <= 32): 64 + 10
-    Gaussian probes of rank 32 drawn by the library, probes applied 8 at a time
-    with fused multigrid solves, mixed precision.  Reports probe applies per
-    second, the top eigenvalues and the Ritz residual certificate."""
+    Gaussian probes of rank 32 drawn by the library (the same probes in every
+    run: a counter-based generator of the problem's seed), applied in batched
+    passes as large as device memory allows, mixed precision.  Reports probe
+    applies per second, the top eigenvalues and the Ritz residual estimate,
+    and, unless --no-fp64-reference, the same solve in float64 on the same
+    probes with the mixed result's relative error of the top 64 Ritz values."""
     import dataclasses
 
     import torch
@@ -144,27 +159,40 @@ def randomized(args):
 
     lp.load()
     torch.cuda.set_device(0)
-    desc = dataclasses.replace(synthetic.MESH512_NT500_PROBES, precision=args.precision)
-    prob = lp.Problem(desc)
-    prob.set_log(1)
-    a0 = prob.stats()["applies"]
-    t0 = time.perf_counter()
-    eig = prob.eigensolve(synthetic.PROBE_COUNT, method=lp.LRPOST_RANDOMIZED, oversample=synthetic.PROBE_OVERSAMPLE,
-                          allow_unconverged=True)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    st = prob.stats()
-    lam = eig.values()
+
+    def solve(precision):
+        desc = dataclasses.replace(synthetic.MESH512_NT500_PROBES, precision=precision)
+        prob = lp.Problem(desc)
+        prob.set_log(1)
+        a0 = prob.stats()["applies"]
+        t0 = time.perf_counter()
+        eig = prob.eigensolve(synthetic.PROBE_COUNT, method=lp.LRPOST_RANDOMIZED,
+                              oversample=synthetic.PROBE_OVERSAMPLE, allow_unconverged=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = prob.stats()
+        lam = eig.values()
+        del eig, prob
+        return desc, dt, st, st["applies"] - a0, lam
+
+    desc, dt, st, applies, lam = solve(args.precision)
     out = {
         "metric": "probe Hessian applies/s (randomized two-pass eigensolver)",
-        "value": (st["applies"] - a0) / dt, "unit": "Hessian applies/s", "n_gpus": 1, "higher_is_better": True,
+        "value": applies / dt, "unit": "Hessian applies/s", "n_gpus": 1, "higher_is_better": True,
         "data": "synthetic", "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "config": {"workload": "mesh512_nt500_probes74_rank32", "N": desc.N, "nt": desc.nt, "nx": (desc.N - 1) ** 2,
                    "probes": synthetic.PROBE_COUNT + synthetic.PROBE_OVERSAMPLE, "probe_rank": 32, "k": synthetic.PROBE_COUNT,
                    "trunc_tol": desc.trunc_tol, "rank_cap": desc.rank_cap, "precision": args.precision},
-        "seconds": dt, "applies": st["applies"] - a0, "lambda_1_to_3": [float(x) for x in lam[:3]],
-        "lambda_64": float(lam[-1]), "max_rel_ritz_residual": st["ritz_resid"],
+        "seconds": dt, "applies": applies, "lambda_1_to_3": [float(x) for x in lam[:3]],
+        "lambda_64": float(lam[-1]), "max_rel_ritz_residual_estimate": st["ritz_resid"],
+        "spacetime_check": {"enriched_batches": st["st_enrichments"], "unresolved_batches": st["st_unresolved"]},
     }
+    if args.precision == "mixed" and not args.no_fp64_reference:
+        _, dt64, _, applies64, lam64 = solve("fp64")
+        n = min(len(lam), len(lam64))
+        rel = abs(lam[:n] - lam64[:n]) / abs(lam64[:n])
+        out["fp64_reference"] = {"applies_per_s": applies64 / dt64, "seconds": dt64,
+                                 "top64_max_rel_err": float(rel.max()), "top10_max_rel_err": float(rel[:10].max())}
     print(json.dumps(out))
 
 
@@ -177,6 +205,10 @@ def main():
     ap.add_argument("--no-fp64-reference", action="store_true",
                     help="in mixed precision, skip the float64 comparison step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-posterior", action="store_true",
+                    help="skip the complete 256 x 256 posterior reported beside the headline")
+    ap.add_argument("--vectors", type=int, default=40,
+                    help="Krylov vectors per headline step (block-Lanczos budget)")
     ap.add_argument("--serving", type=int, default=0,
                     help="measure the serving loop on this many requests instead of the eigensolve step")
     ap.add_argument("--workers", type=int, default=4)
@@ -204,20 +236,23 @@ def main():
     lp.load()
     torch.cuda.set_device(0)
     # A plain elementwise copy of known size (8-byte elements, read once and
-    # written once): its FETCH_SIZE / WRITE_SIZE counters scale the smoother's.
+    # written once): its FETCH_SIZE / WRITE_SIZE counters scale the kernels'.
     src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
         torch.mul(src, 1.0, out=dst)
     torch.cuda.synchronize()
     del src, dst
-    def run(precision, warmup, steps, profile):
-        desc = dataclasses.replace(synthetic.MESH256_NT200, precision=precision)
+
+    def run(base, precision, warmup, steps, profile, vectors):
+        desc = dataclasses.replace(base, precision=precision)
         prob = lp.Problem(desc)
         prob.set_log(1)
+        if vectors:
+            prob.set_eig_limits(max_vectors=vectors)
 
         def step():
-            eig = prob.eigensolve(desc.k)
+            eig = prob.eigensolve(desc.k, allow_unconverged=vectors > 0)
             D = prob.post_variance(eig, on_device=True)
             return eig, D
 
@@ -236,6 +271,7 @@ def main():
         t_all = time.perf_counter()
         for _ in range(steps):
             t0 = time.perf_counter()
+            D_last = None
             eig, D = step()
             torch.cuda.synchronize()
             step_ms.append((time.perf_counter() - t0) * 1e3)
@@ -252,21 +288,35 @@ def main():
         del prob
         return res
 
-    main_run = run(args.precision, args.warmup, args.steps, True)
+    head = synthetic.MESH1024_NT1000
+    workload = "mesh1024_nt1000"
+    main_run = run(head, args.precision, args.warmup, args.steps, True, args.vectors)
     desc = main_run["desc"]
-    # the multigrid kernel with the most device time in the timed steps
+    # the timed kernel kind with the most device time in the timed steps
     kind = max(main_run["prof"], key=lambda k: main_run["prof"][k][1])
     launches, kern_ms, kern_bytes, kern_flops = main_run["prof"][kind]
     applies, elapsed, step_ms, lam, st = (main_run["applies"], main_run["elapsed"], main_run["step_ms"],
                                           main_run["lam"], main_run["stats"])
     ref = None
+    fp64_ref = None
     if args.precision == "mixed" and not args.no_fp64_reference:
         # the same step in float64: its throughput, and the mixed result's error against it
-        ref = run("fp64", 0, 1, False)
+        D_mixed = main_run["D"]
+        main_run["D"] = None
+        ref = run(head, "fp64", 0, 1, False, args.vectors)
+        lam64, D64 = ref["lam"], ref["D"]
+        fp64_ref = {
+            "applies_per_s": ref["applies"] / ref["elapsed"],
+            "step_ms": ref["step_ms"][0],
+            "ritz_values_max_rel_err": float(abs(lam - lam64).max() / abs(lam64).max()),
+            "variance_max_rel_err": float(((D_mixed - D64).abs() / D64.abs()).max().item()),
+        }
+        del D_mixed, D64, ref
+        torch.cuda.empty_cache()
     from paper_1703_05638_amd.profile_summary import read_traffic
 
     kbase, kdesc, mg_kernel = KERNELS[kind]
-    traffic = read_traffic(traffic_report(kbase, args.precision))
+    traffic = read_traffic(traffic_report(kbase, args.precision, workload))
     avg_ms = kern_ms / max(launches, 1)
     bytes_per_launch = kern_bytes / max(launches, 1)
     flops_per_launch = kern_flops / max(launches, 1)
@@ -279,7 +329,8 @@ def main():
     else:
         kname = kbase
     others = {KERNELS[k][0]: {"launches": v[0], "total_ms": v[1],
-                              "achieved_GBs": (v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else 0.0}
+                              "achieved_GBs": (v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else 0.0,
+                              "achieved_TFLOPs": (v[3] / (v[1] * 1e-3) / 1e12) if v[1] > 0 else 0.0}
               for k, v in main_run["prof"].items() if k != kind and v[0] > 0}
     if mfma_bound:
         roof = {"bound": "mfma", "achieved": tflops, "peak": MFMA_F64_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -301,28 +352,35 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "mesh256_nt200_lanczos50", "N": desc.N, "nt": desc.nt, "nx": (desc.N - 1) ** 2,
-                   "k": desc.k, "trunc_tol": desc.trunc_tol, "rank_cap": desc.rank_cap,
-                   "alpha": desc.alpha, "sigma": desc.sigma, "precision": args.precision},
-        "posterior_latency_ms": {"p50": statistics.median(step_ms),
-                                 "p99": sorted(step_ms)[min(len(step_ms) - 1, int(0.99 * len(step_ms)))]},
+        "config": {"workload": "%s_lanczos%dvec" % (workload, args.vectors), "N": desc.N, "nt": desc.nt,
+                   "nx": (desc.N - 1) ** 2, "k": desc.k, "krylov_vectors_per_step": args.vectors,
+                   "trunc_tol": desc.trunc_tol, "rank_cap": desc.rank_cap, "alpha": desc.alpha, "sigma": desc.sigma,
+                   "precision": args.precision},
+        "step_latency_ms": {"p50": statistics.median(step_ms),
+                            "p99": sorted(step_ms)[min(len(step_ms) - 1, int(0.99 * len(step_ms)))]},
         "applies_per_step": applies / args.steps,
         "lanczos_block_steps": st["lanczos_steps"],
-        "lambda_1_to_3": [float(x) for x in lam[:3]],
+        "ritz_values_1_to_3": [float(x) for x in lam[:3]],
+        "ritz_resid_estimate": st["ritz_resid"],
+        "spacetime_check": {"last_resid": st["last_st_resid"], "last_precond_resid": st["last_st_presid"],
+                            "enriched_batches": st["st_enrichments"], "unresolved_batches": st["st_unresolved"]},
         "roofline": dict({"kernel": "%s (%s)" % (kname, kdesc)}, **roof,
                          **{"traffic": traffic, "launches": launches, "avg_launch_us": avg_ms * 1e3,
                             "bytes_per_launch": bytes_per_launch, "flops_per_launch": flops_per_launch,
                             "total_ms": kern_ms, "other_timed_kernels": others}),
     }
-    if ref is not None:
-        lam64 = ref["lam"]
-        D64 = ref["D"]
-        out["fp64_reference"] = {
-            "applies_per_s": ref["applies"] / ref["elapsed"],
-            "posterior_latency_ms": ref["step_ms"][0],
-            "lambda_max_rel_err": float(abs(lam - lam64).max() / abs(lam64).max()),
-            "variance_max_rel_err": float(((main_run["D"] - D64).abs() / D64.abs()).max().item()),
-        }
+    if fp64_ref is not None:
+        out["fp64_reference"] = fp64_ref
+    del main_run
+    torch.cuda.empty_cache()
+    if not args.no_posterior:
+        # a complete posterior (50 pairs, converged) on the 256 x 256 mesh, nt = 200
+        post = run(synthetic.MESH256_NT200, args.precision, 1, 1, False, 0)
+        out["mesh256_posterior"] = {
+            "workload": "mesh256_nt200_lanczos50", "applies_per_s": post["applies"] / post["elapsed"],
+            "posterior_latency_ms": post["step_ms"][0], "applies": post["applies"],
+            "lanczos_block_steps": post["stats"]["lanczos_steps"], "ritz_resid_estimate": post["stats"]["ritz_resid"]}
+        del post
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(desc)
     print(json.dumps(out))

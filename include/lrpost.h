@@ -33,8 +33,10 @@
  * thread-local message describing the last failure on the calling thread.
  *
  * Concurrency: one problem handle must not be used by two threads at once.
- * Work is ordered on the HIP stream given in the description (or the null
- * stream); every entry point returns after its results are complete.
+ * Work is ordered on the HIP stream given in the description; without one,
+ * on a blocking stream the problem creates (ordered after earlier work of
+ * the null stream, like every blocking stream).  Every entry point except
+ * lrpost_gram_noalloc returns after its results are complete.
  */
 #ifndef LRPOST_H
 #define LRPOST_H
@@ -80,7 +82,7 @@ typedef struct {
                          nodes per side, solved inside one workgroup (any other value
                          is rejected with LRPOST_EINVAL) */
   uint64_t seed;      /* seed of the Lanczos start block */
-  void* hip_stream;   /* hipStream_t to order work on, or NULL for the null stream */
+  void* hip_stream;   /* hipStream_t to order work on, or NULL for a blocking stream of the problem's own */
 } lrpost_problem_desc;
 
 /* A low-rank space-time vector X = W1 W2^T (see the header comment for memory). */
@@ -98,12 +100,19 @@ typedef struct {
   int32_t last_rank_out;  /* rank of the last apply's output */
   int32_t last_basis;     /* spatial basis size of the last space-time solve */
   int32_t lanczos_steps;  /* block steps of the last eigensolve */
-  int32_t st_enrichments; /* space-time solve batches that needed the refined pole set */
+  int32_t st_enrichments; /* space-time solve batches that needed the enriched pole set */
+  int32_t st_unresolved;  /* of those, batches still above the threshold after enrichment */
+  int32_t reserved;
   double last_tail;       /* relative tail dropped by the last truncation */
   double last_st_resid;   /* largest relative residual ||tau K Y + M Y C^T - F||_F / ||F||_F
                              (C for the adjoint) of the solutions of the last space-time
                              solve batch, for the truncated factors returned (Sec. 6.1,
                              eq. st_pde); -1 while the check is off or no solve ran */
+  double last_st_presid;  /* the same residual preconditioned by two multigrid V-cycles of
+                             M + tau K per time step, relative to the same preconditioned
+                             source (the block-diagonal preconditioner of Sec. 6.1,
+                             eq. pre_1): it tracks the relative error of the solution and is
+                             what the check of lrpost_set_st_check compares */
   double ritz_resid;      /* largest relative Ritz residual ESTIMATE of the last
                              eigensolve: block Lanczos takes it from the coupling block of
                              the recurrence, the randomized solver from the Grams of its
@@ -134,15 +143,21 @@ int lrpost_hess_apply_batch(lrpost_problem* p, int nvec, const lrpost_lowrank* x
  * adjoint (adjoint = 1):  tau K Y + M Y C   = F1 F2^T  (time runs backward).
  * Output truncated at desc.trunc_tol in the M-weighted Frobenius norm.
  * Every space-time solve (also inside the Hessian applies) measures the
- * relative residual of its truncated output (lrpost_stats.last_st_resid);
- * above the check threshold the spatial basis is enriched once by a refined
- * pole set, and a residual still above it returns LRPOST_ENOCONV (the
- * residual monitor of the AMEn solver of Sec. 6.1). */
+ * relative residual of its truncated output (lrpost_stats.last_st_resid) and
+ * the residual preconditioned by M + tau K (last_st_presid); above the check
+ * threshold the spatial basis is enriched once by a refined and extended pole
+ * set (the residual monitor and basis enrichment of the AMEn solver of
+ * Sec. 6.1).  A solve still above it is counted in st_unresolved, and in the
+ * strict check mode returns LRPOST_ENOCONV. */
 int lrpost_spacetime_solve(lrpost_problem* p, const lrpost_lowrank* f, lrpost_lowrank* y, int adjoint);
-/* Residual check of the space-time solves: mode 0 off (last_st_resid = -1),
- * 1 measure only, 2 (default) measure, enrich and fail as described above;
- * rtol is the threshold on the relative residual (0: 100 trunc_tol).
- * mode outside 0..2 or rtol < 0: LRPOST_EINVAL. */
+/* Residual check of the space-time solves: mode 0 off (last_st_resid =
+ * last_st_presid = -1), 1 measure only, 2 (default) measure and enrich, 3
+ * (strict) measure, enrich and return LRPOST_ENOCONV when a solve stays
+ * above the threshold; rtol is the threshold on the preconditioned relative
+ * residual (0: 50 trunc_tol, and at least 1e-4 with LRPOST_MIXED, whose
+ * float32 multigrid bounds the attainable value).  Enrichment: the pole set refined by the
+ * geometric midpoints of neighbouring poles and extended at the original
+ * spacing up to min(24 tau / h^2, 1e4).  mode outside 0..3 or rtol < 0: LRPOST_EINVAL. */
 int lrpost_set_st_check(lrpost_problem* p, int mode, double rtol);
 
 /* Eigensolve for the k largest eigenpairs of G (Sec. 4 Algorithm 1, as block
@@ -192,6 +207,30 @@ int lrpost_eigs_free(lrpost_eigs* e);
 int lrpost_eigs_from_pairs(lrpost_problem* p, int k, const double* lambda, const lrpost_lowrank* v,
                            lrpost_eigs** out);
 
+/* Number of observed nodes (the interior nodes inside the closed box), or -1
+ * for a null handle. */
+int lrpost_obs_count(const lrpost_problem* p);
+/* Posterior mean, which for this linear-Gaussian problem is the MAP point of
+ * Sec. 2 (eq. map1 and the minimization after it, with zero prior and noise
+ * means): the solution of (H_mis + P) u = sigma^{-2} F^T y.  Solved as
+ * (G + I) u = P^{-1} sigma^{-2} F^T y in the P inner product by block
+ * Lanczos with full re-orthogonalization started from the right-hand side
+ * (the Lanczos form of conjugate gradients; block size 4, three seeded
+ * start vectors beside the right-hand side), every Krylov vector a low-rank
+ * space-time vector.  y_obs: host, nobs x nt column-major (nobs =
+ * lrpost_obs_count, observed nodes in increasing node order, column k the
+ * observations at t_{k+1}), caller-owned, read only.  max_vectors caps the
+ * Krylov vectors (0: 800); rtol is the target of the relative residual
+ * estimate ||(G + I) u - rhs||_P / ||rhs||_P (0: max(1e-7, 1e3 trunc_tol)).
+ * The apply's truncation error bounds the attainable accuracy (it enters as
+ * about trunc_tol times the largest eigenvalue of G relative to the shift
+ * 1), so meaningful means need tight tolerances.  mean: output (cap columns,
+ * rank set); rel_resid (may be NULL): the final estimate.  Returns
+ * LRPOST_ENOCONV, with mean and rel_resid still written, when the target is
+ * not met within max_vectors. */
+int lrpost_posterior_mean(lrpost_problem* p, const double* y_obs, int max_vectors, double rtol, lrpost_lowrank* mean,
+                          double* rel_resid);
+
 /* diag(Gamma_post,k) = diag(P^{-1}) - sum_i d_i v_i^2, d_i = lambda_i/(1+lambda_i)
  * (Sec. 2, Sherman-Morrison-Woodbury step), as an nx x nt array
  * (column-major, caller-owned; `on_device` says whether diag is device memory). */
@@ -235,7 +274,11 @@ int lrpost_set_log(lrpost_problem* p, int level);
  *   LRPOST_KERNEL_PROJ           the float64 matrix-core projection
  *                                C = beta C + A Q (A nx x m, C nx x p): read A
  *                                once, read C once when beta != 0, write C
- *                                once, 2 m p nx flops.
+ *                                once, 2 m p nx flops;
+ *   LRPOST_KERNEL_STENCIL        the Q1 stencil Y = a K X + b M X (+ c Z) on
+ *                                the finest mesh (the operator applies and
+ *                                the residuals of the multigrid correction
+ *                                cycles): read X (and Z) once, write Y once.
  * lrpost_profile_read synchronizes, returns for one kind the launch count, the
  * summed kernel time in ms, the counted bytes and (if flops is not NULL) the
  * counted floating-point operations since the last read, and resets that
@@ -245,7 +288,8 @@ enum {
   LRPOST_KERNEL_MG_DOWN = 1,
   LRPOST_KERNEL_MG_UP = 2,
   LRPOST_KERNEL_GRAM = 3,
-  LRPOST_KERNEL_PROJ = 4
+  LRPOST_KERNEL_PROJ = 4,
+  LRPOST_KERNEL_STENCIL = 5
 };
 int lrpost_profile(lrpost_problem* p, int enable);
 int lrpost_profile_read(lrpost_problem* p, int kernel, int64_t* launches, double* total_ms, double* bytes,
@@ -257,6 +301,41 @@ int lrpost_profile_read(lrpost_problem* p, int kernel, int64_t* launches, double
  * kernel per smoother step, residual-restriction and prolongation.  Both
  * compute the same iterates; finer meshes always take the per-step kernels. */
 int lrpost_set_mg_fused(lrpost_problem* p, int on);
+
+/* Autotuned tile shape of the Q1 stencil kernel: the strip height (8, 16 or
+ * 32 mesh rows per workgroup) of every shape class -- precision, mesh side,
+ * column count rounded up to a power of two, with or without the added term
+ * -- is chosen by timing the three heights on the class's first launch (the
+ * fastest is kept for the process).  Every height computes every node with
+ * the same operations, so results do not depend on the choice.
+ * lrpost_set_autotune(0) uses a fixed rule (tall strips when there are
+ * enough columns for a few thousand workgroups) for classes not yet timed.
+ * lrpost_autotune_report writes the table (one text line per class: its
+ * choice and the three times) into buf (len bytes, NUL-terminated,
+ * truncated to fit) and returns the full length. */
+int lrpost_set_autotune(int on);
+int lrpost_autotune_report(char* buf, size_t len);
+
+/* Batch size of the randomized eigensolver's probe applies: n > 0 applies
+ * at most n probes per batched pass (one multigrid solve for all their pole
+ * solves); 0 (the default) takes as many as fit in half of the device memory
+ * that was free when the problem was created, by an estimate of 56 bytes per
+ * node, pole and probe column in mixed precision (about 38 rank-32 probes per
+ * pass on the 512 x 512, nt = 500 workload).  Results do not depend on the
+ * batch size.  n < 0: LRPOST_EINVAL. */
+int lrpost_set_apply_batch(lrpost_problem* p, int n);
+
+/* HIP graphs of the multigrid V-cycles: with on (the default) every V-cycle
+ * launch sequence (the level kernels down, the LDS coarse solve, the level
+ * kernels up) is captured once per precision, column count and buffers into
+ * a HIP graph on the problem's stream and replayed from then on, one graph
+ * launch in place of 2L + 1 kernel launches; off launches the kernels one by
+ * one (and frees the captured graphs).  Both give the same bits.  Runs with
+ * kernel timing enabled (lrpost_profile) launch directly.
+ * lrpost_graph_info returns the number of graphs captured and of graph
+ * launches since the problem was created. */
+int lrpost_set_graphs(lrpost_problem* p, int on);
+int lrpost_graph_info(const lrpost_problem* p, int64_t* captured, int64_t* launches);
 
 /* ---- building blocks, exported for kernel-level parity tests ----------
  * All pointers are DEVICE memory, float64, column-major with leading

@@ -251,6 +251,43 @@ int lrpost_eigensolve_probes(lrpost_problem* p, int k, int nprobe, const lrpost_
   });
 }
 
+int lrpost_obs_count(const lrpost_problem* p) { return (p && p->impl) ? p->impl->nobs : -1; }
+
+// Posterior mean: the block-Lanczos (conjugate-gradient) solve of
+// (G + I) u = P^{-1} sigma^{-2} F^T y in the P inner product, which is the
+// normal-equation system (H_mis + P) u = sigma^{-2} F^T y divided by P.
+int lrpost_posterior_mean(lrpost_problem* p, const double* y_obs, int max_vectors, double rtol, lrpost_lowrank* mean,
+                          double* rel_resid) {
+  return guarded([&] {
+    Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
+    if (!y_obs || !mean) fail(LRPOST_EINVAL, "null argument");
+    if (max_vectors < 0 || !(rtol >= 0)) fail(LRPOST_EINVAL, "max_vectors and rtol must be >= 0");
+    if (mean->nx != P->nx || mean->nt != P->nt) fail(LRPOST_EINVAL, "output shape does not match the problem");
+    LowRank c;
+    P->data_rhs(y_obs, c);
+    if (c.rank == 0) {
+      mean->rank = 0;
+      if (rel_resid) *rel_resid = 0.0;
+      return;
+    }
+    LanczosSolve lin;
+    lin.rhs = &c;
+    lin.shift = 1.0;
+    lin.rtol = rtol > 0 ? rtol : std::max(1e-7, 1e3 * P->desc.trunc_tol);
+    const int maxv = max_vectors > 0 ? max_vectors : 800;
+    block_lanczos(P, 1, 4, std::max(maxv, 8), 0.0, &lin);
+    store_lr(P, *lin.x, mean);
+    if (rel_resid) *rel_resid = lin.resid;
+    if (!lin.converged) {
+      char msg[160];
+      std::snprintf(msg, sizeof msg, "posterior mean: relative residual estimate %.3e above %.3e after %d block steps",
+                    lin.resid, lin.rtol, lin.steps);
+      fail(LRPOST_ENOCONV, msg);
+    }
+  });
+}
+
 int lrpost_eig_count(const lrpost_eigs* e) { return e ? (int)e->lambda.size() : 0; }
 
 int lrpost_eig_values(const lrpost_eigs* e, double* lambda) {
@@ -486,10 +523,10 @@ int lrpost_eig_residuals(lrpost_problem* p, const lrpost_eigs* e, double* resid)
 int lrpost_set_st_check(lrpost_problem* p, int mode, double rtol) {
   return guarded([&] {
     Problem* P = impl(p);
-    if (mode < 0 || mode > 2 || !(rtol >= 0)) fail(LRPOST_EINVAL, "mode must be 0..2 and rtol >= 0");
+    if (mode < 0 || mode > 3 || !(rtol >= 0)) fail(LRPOST_EINVAL, "mode must be 0..3 and rtol >= 0");
     P->st_check = mode;
     P->st_rtol = rtol;
-    if (mode == 0) P->stats.last_st_resid = -1.0;
+    if (mode == 0) P->stats.last_st_resid = P->stats.last_st_presid = -1.0;
   });
 }
 
@@ -513,7 +550,7 @@ int lrpost_profile_read(lrpost_problem* p, int kernel, int64_t* launches, double
     Problem* P = impl(p);
     PoolScope pool_scope(P->pool);
     if (!launches || !total_ms || !bytes) fail(LRPOST_EINVAL, "null argument");
-    if (kernel < 0 || kernel > LRPOST_KERNEL_PROJ) fail(LRPOST_EINVAL, "unknown kernel kind");
+    if (kernel < 0 || kernel > LRPOST_KERNEL_STENCIL) fail(LRPOST_EINVAL, "unknown kernel kind");
     P->prof_read(kernel, launches, total_ms, bytes, flops);
   });
 }
@@ -524,6 +561,46 @@ int lrpost_set_mg_fused(lrpost_problem* p, int on) {
     PoolScope pool_scope(P->pool);
     P->sync();
     P->mg_fused = on != 0;
+  });
+}
+
+int lrpost_set_autotune(int on) {
+  return guarded([&] { set_stencil_autotune(on != 0); });
+}
+
+int lrpost_autotune_report(char* buf, size_t len) {
+  const std::string rep = stencil_autotune_report();
+  if (buf && len > 0) {
+    const size_t n = std::min(len - 1, rep.size());
+    std::memcpy(buf, rep.data(), n);
+    buf[n] = 0;
+  }
+  return (int)rep.size();
+}
+
+int lrpost_set_apply_batch(lrpost_problem* p, int n) {
+  return guarded([&] {
+    Problem* P = impl(p);
+    if (n < 0) fail(LRPOST_EINVAL, "n must be >= 0");
+    P->apply_batch_max = n;
+  });
+}
+
+int lrpost_set_graphs(lrpost_problem* p, int on) {
+  return guarded([&] {
+    Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
+    P->sync();
+    P->use_graphs = on != 0;
+    if (!P->use_graphs) P->drop_graphs();
+  });
+}
+
+int lrpost_graph_info(const lrpost_problem* p, int64_t* captured, int64_t* launches) {
+  return guarded([&] {
+    if (!p || !p->impl || !captured || !launches) fail(LRPOST_EINVAL, "null argument");
+    *captured = p->impl->stats_graphs_captured;
+    *launches = p->impl->stats_graph_launches;
   });
 }
 

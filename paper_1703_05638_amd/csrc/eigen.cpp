@@ -573,22 +573,27 @@ static std::vector<CVec> orthonormalize_block(SharedBasis& sb, std::vector<CVec>
   return out;
 }
 
-EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rtol) {
+EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rtol, LanczosSolve* lin) {
   const int nt = P->nt;
   const long nx = P->nx;
   const double tol = P->desc.trunc_tol;
   const int cap = P->desc.rank_cap;
-  const long s_reserve = std::min<long>(nx, (long)std::min(max_vectors, 4 * k + 16) * 16 + 64);
+  const long s_reserve = std::min<long>(nx, (long)std::min(max_vectors, lin ? max_vectors : 4 * k + 16) * 16 + 64);
   SharedBasis sb(P, (int)s_reserve, std::max(max_vectors * cap / 2, 64));
   using clk = std::chrono::steady_clock;
   const auto t_start = clk::now();
   P->phase_s.fill(0.0);
   double t_apply = 0.0, t_orth = 0.0;
-  // seeded start block of rank-one vectors a_j (x) b_j
+  // seeded start block of rank-one vectors a_j (x) b_j (in the linear-solve
+  // mode the right-hand side first, then bsize - 1 of them)
   std::vector<CVec> W;
+  if (lin) {
+    if (!lin->rhs || lin->rhs->rank == 0) fail(LRPOST_EINVAL, "zero right-hand side");
+    W.push_back(sb.absorb(*lin->rhs, tol, cap));
+  }
   {
     std::vector<double> ha((size_t)nx);
-    for (int j = 0; j < bsize; ++j) {
+    for (int j = lin ? 1 : 0; j < bsize; ++j) {
       LowRank v;
       v.resize(nx, nt, 1);
       for (long i = 0; i < nx; ++i) ha[i] = normal_draw(P->desc.seed, 2 * j, i);
@@ -602,6 +607,19 @@ EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rt
   int kb = 0;
   auto V = orthonormalize_block(sb, W, Rb, kb, tol, cap, 0.0);
   if (kb == 0) fail(LRPOST_EBREAKDOWN, "start block is zero");
+  // linear-solve mode: the right-hand side in the P-orthonormal basis (its
+  // coefficients on the first block; zero on every later vector)
+  std::vector<double> g0;
+  double gnorm = 0.0;
+  if (lin) {
+    g0.assign(kb, 0.0);
+    for (int c = 0; c < kb; ++c) {
+      g0[c] = Rb[c];  // W_0 = sum_c V_c Rb[c, 0]
+      gnorm += g0[c] * g0[c];
+    }
+    gnorm = std::sqrt(gnorm);
+  }
+  std::vector<double> zsol;
   std::vector<int> block_start{0}, block_size{kb};
   for (auto& v : V) sb.append(v);
   const int mmax = max_vectors;
@@ -674,12 +692,36 @@ EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rt
     std::vector<CVec> Vn;
     {
       Problem::PhaseTimer pt(P, Problem::kPhOrthBlock);
-      Vn = orthonormalize_block(sb, Wn, Rn, kn, tol, cap, 10.0 * tol * theta_max);
+      // new directions at the apply's truncation level are noise: for the
+      // eigenproblem that level is tol times the largest Ritz value; for the
+      // shifted linear system the components at the shift's scale matter
+      const double drop = lin ? 10.0 * tol * lin->shift : 10.0 * tol * theta_max;
+      Vn = orthonormalize_block(sb, Wn, Rn, kn, tol, cap, drop);
     }
     // residual estimates ||G x - theta x||_P = ||Rn * Y[last block, s]||
     bool done = m >= k;
     double worst = 0.0;
-    for (int s = 0; s < std::min(k, m); ++s) {
+    if (lin) {
+      // Galerkin solution of (G + shift I) x = rhs on the basis:
+      // z = Y diag(1 / (theta + shift)) Y^T g, with residual
+      // ||(G + shift I) V z - rhs||_P = ||Rn z[last block]||
+      zsol.assign(m, 0.0);
+      for (int c = 0; c < m; ++c) {
+        double t = 0.0;
+        for (int i = 0; i < (int)g0.size(); ++i) t += Y[(size_t)c * m + i] * g0[i];
+        t /= theta[c] + lin->shift;
+        for (int i = 0; i < m; ++i) zsol[i] += Y[(size_t)c * m + i] * t;
+      }
+      double r2 = 0.0;
+      for (int l = 0; l < kn; ++l) {
+        double t = 0.0;
+        for (int i = 0; i < bj; ++i) t += Rn[(size_t)i * kn + l] * zsol[j0 + i];
+        r2 += t * t;
+      }
+      worst = std::sqrt(r2) / std::max(gnorm, 1e-300);
+      done = worst <= lin->rtol;
+    }
+    for (int s = 0; s < (lin ? 0 : std::min(k, m)); ++s) {
       const int col = m - 1 - s;  // descending order
       double r2 = 0.0;
       for (int l = 0; l < kn; ++l) {
@@ -746,6 +788,21 @@ EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rt
   }
   P->stats.lanczos_steps = res.steps;
   res.max_resid = last_worst;
+  if (lin) {
+    // the solution V z, formed on the cores and truncated once
+    lin->resid = last_worst;
+    lin->steps = res.steps;
+    lin->converged = res.converged;
+    const size_t slot = (size_t)std::max(sb.s, 1) * nt;
+    Sbuf.ensure(sizeof(double) * slot);
+    std::vector<double> coef(sb.size(), 0.0);
+    for (int i = 0; i < (int)zsol.size() && i < sb.size(); ++i) coef[i] = zsol[i];
+    sb.combine({}, {}, coef, Sbuf.as<double>());
+    auto vs = sb.truncate_cores(Sbuf.as<double>(), 1, (long)slot, sb.s, sb.s, tol, cap);
+    lin->x = std::make_unique<LowRank>();
+    sb.materialize(vs[0], *lin->x);
+    return res;
+  }
   // Ritz vectors of the k largest Ritz values
   const int m = m_conv;
   const int kk = std::min(k, m);
@@ -802,12 +859,16 @@ EigResult randomized_eig(Problem* P, int k, const std::vector<const LowRank*>& p
       std::fflush(stderr);
     }
   };
-  // pass one
-  // applies in batches of kBatch with fused multigrid solves
+  // pass one: the probes applied in batches as large as device memory
+  // allows (one multigrid solve for the pole solves of a whole batch);
+  // cores are formed and truncated kBatch at a time
   constexpr int kBatch = 8;
+  int rmax = 1;
+  for (auto* w : probes) rmax = std::max(rmax, w->rank);
+  const int abatch = P->apply_batch_limit(rmax, l);
   std::vector<CVec> Y;
-  for (int j0 = 0; j0 < l; j0 += kBatch) {
-    const int nbt = std::min(kBatch, l - j0);
+  for (int j0 = 0; j0 < l; j0 += abatch) {
+    const int nbt = std::min(abatch, l - j0);
     std::vector<LowRank> ys(nbt);
     std::vector<const LowRank*> px(probes.begin() + j0, probes.begin() + j0 + nbt);
     std::vector<LowRank*> py;
@@ -852,8 +913,9 @@ EigResult randomized_eig(Problem* P, int k, const std::vector<const LowRank*>& p
   }
   // pass two
   std::vector<CVec> W;
-  for (int a0 = 0; a0 < m; a0 += kBatch) {
-    const int nbt = std::min(kBatch, m - a0);
+  const int abatch2 = P->apply_batch_limit(cap, m);
+  for (int a0 = 0; a0 < m; a0 += abatch2) {
+    const int nbt = std::min(abatch2, m - a0);
     std::vector<LowRank> qs(nbt), ws(nbt);
     std::vector<const LowRank*> pq;
     std::vector<LowRank*> pw;

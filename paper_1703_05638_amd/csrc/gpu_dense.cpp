@@ -6,6 +6,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <map>
 #include <cstring>
 #include <mutex>
 
@@ -14,13 +15,15 @@
 namespace lrp {
 
 // ---- caching allocator ---------------------------------------------------
-// Blocks are rounded up to a power of two (at least 4 KiB) and kept in
-// per-size free lists.  A pool belongs to one problem, whose work is ordered
+// Blocks up to 256 MiB are rounded up to a power of two (at least 4 KiB);
+// larger ones to a multiple of 256 MiB, so that the multi-GB pole-solve
+// blocks of the finest meshes waste at most 256 MiB each.  Free blocks wait
+// in per-size lists.  A pool belongs to one problem, whose work is ordered
 // on one stream, so a block freed by one operation can be handed to the next
 // without waiting: any reuse is ordered after the earlier use on that stream.
 struct Pool::Impl {
   std::mutex mu;
-  std::vector<std::vector<void*>> free_lists = std::vector<std::vector<void*>>(64);
+  std::map<size_t, std::vector<void*>> free_lists;
   size_t cached = 0, in_use = 0, peak = 0;
 };
 
@@ -28,27 +31,26 @@ Pool::Pool() : impl_(new Impl) {}
 Pool::~Pool() {
   (void)hipDeviceSynchronize();
   for (auto& fl : impl_->free_lists)
-    for (void* p : fl) (void)hipFree(p);
+    for (void* p : fl.second) (void)hipFree(p);
   delete impl_;
 }
 
-static int bucket_of(size_t bytes, size_t* rounded) {
+static size_t rounded_size(size_t bytes) {
+  constexpr size_t kLarge = size_t(256) << 20;
+  if (bytes > kLarge) return (bytes + kLarge - 1) / kLarge * kLarge;
   size_t s = 4096;
-  int b = 12;
-  while (s < bytes) { s <<= 1; ++b; }
-  *rounded = s;
-  return b;
+  while (s < bytes) s <<= 1;
+  return s;
 }
 
 void* Pool::alloc(size_t bytes, size_t* got) {
-  size_t r;
-  const int b = bucket_of(bytes, &r);
+  const size_t r = rounded_size(bytes);
   {
     std::lock_guard<std::mutex> lk(impl_->mu);
-    auto& fl = impl_->free_lists[b];
-    if (!fl.empty()) {
-      void* p = fl.back();
-      fl.pop_back();
+    auto it = impl_->free_lists.find(r);
+    if (it != impl_->free_lists.end() && !it->second.empty()) {
+      void* p = it->second.back();
+      it->second.pop_back();
       impl_->cached -= r;
       impl_->in_use += r;
       impl_->peak = std::max(impl_->peak, impl_->in_use);
@@ -77,10 +79,9 @@ void* Pool::alloc(size_t bytes, size_t* got) {
 
 void Pool::release(void* p, size_t bytes) {
   if (!p) return;
-  size_t r;
-  const int b = bucket_of(bytes, &r);
+  const size_t r = rounded_size(bytes);
   std::lock_guard<std::mutex> lk(impl_->mu);
-  impl_->free_lists[b].push_back(p);
+  impl_->free_lists[r].push_back(p);
   impl_->cached += r;
   impl_->in_use -= r;
 }
@@ -90,8 +91,8 @@ void Pool::trim() {
   {
     std::lock_guard<std::mutex> lk(impl_->mu);
     for (auto& fl : impl_->free_lists) {
-      drop.insert(drop.end(), fl.begin(), fl.end());
-      fl.clear();
+      drop.insert(drop.end(), fl.second.begin(), fl.second.end());
+      fl.second.clear();
     }
     impl_->cached = 0;
   }

@@ -10,6 +10,7 @@
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/lrpost.h"
@@ -227,7 +228,7 @@ class Problem {
     double bytes = 0.0, flops = 0.0;
   };
   bool prof_on = false;
-  std::array<ProfSlot, 5> prof_;
+  std::array<ProfSlot, 6> prof_;
   template <class Launch>
   void timed(int kind, double bytes, Launch&& launch, double flops = 0.0);
   template <typename T>
@@ -237,6 +238,12 @@ class Problem {
   // level-fused multigrid kernels on meshes with up to kMgFusedMaxN nodes per
   // side (on by default; off selects the per-step kernels)
   bool mg_fused = true;
+  // V-cycles replayed from captured HIP graphs (on by default; needs a
+  // non-null stream)
+  bool use_graphs = true;
+  hipStream_t own_stream_ = nullptr;  // created when the description names no stream
+  int64_t stats_graphs_captured = 0, stats_graph_launches = 0;
+  void drop_graphs();
 
   // ---- low-rank operations ---------------------------------------------
   // Solve tau K Y + M Y C^T = F (forward) or tau K Y + M Y C = F (adjoint).
@@ -264,12 +271,14 @@ class Problem {
   // prepare, pole solves, projection and truncation with the current poles
   void st_solve_pass(const std::vector<const LowRank*>& F, const std::vector<LowRank*>& Y, bool adjoint);
   // relative Frobenius residuals of eq. st_pde for the solutions Y_j of F_j
+  // and of the same residuals preconditioned by two V-cycles of M + tau K
   void st_residuals(const std::vector<const LowRank*>& F, const std::vector<const LowRank*>& Y, bool adjoint,
-                    std::vector<double>& rel);
-  // residual check of every space-time solve: 0 off, 1 measure (last_st_resid),
-  // 2 measure and, above st_rtol, enrich the basis by a refined pole set once,
-  // then fail with LRPOST_ENOCONV if the residual is still above st_rtol
-  int st_check = 1;
+                    std::vector<double>& rel, std::vector<double>& prel);
+  // residual check of every space-time solve: 0 off, 1 measure (last_st_resid,
+  // last_st_presid), 2 measure and, with the preconditioned residual above
+  // the threshold, enrich the basis once (st_unresolved counts solves still
+  // above it), 3 as 2 but fail with LRPOST_ENOCONV when still above it
+  int st_check = 2;
   double st_rtol = 0.0;
   // G x (precond) or H_mis x (misfit).
   void hess_apply(const LowRank& x, LowRank& y, bool precond);
@@ -280,6 +289,18 @@ class Problem {
   void truncate(LowRank& x, double tol, int cap, int weight, double ref_norm = 0.0, bool orth_spatial = false);
   // P inner product alpha tau <X, (I kron (K+M)) Y>.
   double p_inner(const LowRank& x, const LowRank& y);
+  // how many applies of inputs of rank <= r fit in one batch (at most want):
+  // per input, the pole solves and spatial basis of its forward solve take
+  // about r * (poles) nx doubles several times over; batches use at most
+  // half of the device memory free when the problem was created, or the
+  // limit set by lrpost_set_apply_batch
+  int apply_batch_limit(int r, int want) const;
+  int apply_batch_max = 0;
+  size_t free_at_create = 0;
+  // P^{-1} sigma^{-2} F^T y for observations y (nobs x nt, host, column-major;
+  // the observed nodes in increasing node order): the right-hand side of the
+  // normal equations of the posterior mean, divided by P.
+  void data_rhs(const double* y, LowRank& c);
   // sum_i c_i x_i as a truncated low-rank vector (P-weighted truncation).
   void lincomb(const std::vector<const LowRank*>& xs, const std::vector<double>& c, LowRank& out, double tol,
                int cap);
@@ -306,6 +327,25 @@ class Problem {
   std::vector<double> tmp_h_;
   template <typename T>
   void vcycle_zero(int ncols, const T* B, T* X, bool accumulate = false);  // accumulate: X += V(B), fused path only
+  template <typename T>
+  void vcycle_launch(int ncols, const T* B, T* X, bool accumulate, const std::vector<size_t>& off);
+  // HIP graphs of V-cycle launch sequences, one per precision, shape and buffers
+  struct GraphKey {
+    size_t elem;
+    int ncols;
+    const void *B, *X, *work, *prm;
+    int acc, fused;
+    bool operator<(const GraphKey& o) const;
+  };
+  struct GraphEntry {
+    hipGraphExec_t exec;
+    uint64_t serial;
+  };
+  static constexpr size_t kMaxGraphs = 64;
+  std::map<GraphKey, GraphEntry> graphs_;
+  uint64_t graph_serial_ = 0;
+  template <class Launch>
+  void run_graph(const GraphKey& key, Launch&& launch);
   // the V-cycle runs through the level-fused kernels (which can accumulate)
   bool vcycle_fused() const { return mg_fused && lds_level > 0 && lv[0].n <= kMgFusedMaxN; }
   // cycles V-cycles in float32 on nx x ncols float data (residual correction between cycles)
@@ -313,7 +353,7 @@ class Problem {
   DevMem mg_work_f_, mg_f_;
   void upload_mg_params(const std::vector<ShiftCoef>& ab);
   // space-time solver workspaces
-  DevMem st_res_a_, st_res_b_, st_res_q_, st_res_g_;
+  DevMem st_res_a_, st_res_b_, st_res_q_, st_res_g_, st_res_p_, st_res_h_;
   DevMem st_gram_, st_g_, st_mw_, st_w2_, st_tm_, st_prep_g_, st_prep_t_, st_wall_, st_brep_, st_small_, st_c_, eig_work_;
 };
 
@@ -329,7 +369,20 @@ struct EigResult {
   double max_resid = -1.0;  // largest relative Ritz residual estimate of the returned pairs
   bool converged = true;    // every wanted pair met the residual target within the vector limit
 };
-EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rtol);
+// Linear-solve mode of the block Lanczos process: (G + shift I) x = rhs in
+// the P inner product (G is P-self-adjoint), solved by the Galerkin condition
+// on the block Krylov space started from rhs (the Lanczos form of conjugate
+// gradients, with full re-orthogonalization).
+struct LanczosSolve {
+  const LowRank* rhs = nullptr;
+  double shift = 1.0;
+  double rtol = 1e-8;           // stop at ||residual||_P <= rtol ||rhs||_P (recurrence estimate)
+  std::unique_ptr<LowRank> x;   // the solution
+  double resid = -1.0;
+  int steps = 0;
+  bool converged = false;
+};
+EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rtol, LanczosSolve* lin = nullptr);
 // Two-pass randomized eigensolver on the given probes (space-time vectors).
 EigResult randomized_eig(Problem* P, int k, const std::vector<const LowRank*>& probes);
 

@@ -1,6 +1,8 @@
 // Launch wrappers for the device kernels (all asynchronous on the given stream).
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <string>
 #include <stdint.h>
 
 namespace lrp {
@@ -145,6 +147,9 @@ void post_variance(hipStream_t st, long nx, int nt, int k, const int* seg, const
 // device (once per device, later calls return the cached address; nullptr on
 // a HIP error); gram_scratch_device() returns it for the current device, or
 // nullptr before setup there.
+// Stencil strip-height autotuner: switch, and its table as text lines.
+void set_stencil_autotune(bool on);
+std::string stencil_autotune_report();
 constexpr long kGramScratchDoubles = long(8) << 20;  // 64 MiB
 double* gram_scratch_setup();
 double* gram_scratch_device();

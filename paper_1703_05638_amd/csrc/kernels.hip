@@ -15,7 +15,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstdio>
+#include <map>
 #include <mutex>
+#include <string>
+#include <tuple>
 
 #include "kernels.h"
 
@@ -161,18 +165,112 @@ static void launch_stencil_strip(hipStream_t st, int n, int ncols, const T* X, l
                        ldx, Y, ldy, Z, ldz, W, wstride);
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner of the stencil strip height S (8, 16 or 32 mesh rows per
+// workgroup).  Every node is computed by the same operations whatever S is,
+// so the choice changes timing only, never results.  The first launch of a
+// shape class -- precision, thread count, mesh side, column count rounded to
+// a power of two, with or without the added term -- times each height over
+// three launches (events on the caller's stream, after one untimed launch)
+// and keeps the fastest for the process; later launches of the class use it.
+// Launches whose output aliases an input, or that are being captured into a
+// graph, use the rule below without timing: tall strips (less halo
+// re-reading) when there are enough columns for a few thousand workgroups.
+// ---------------------------------------------------------------------------
+namespace {
+struct TuneKey {
+  int elem, tw, n, cls, hasz;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(elem, tw, n, cls, hasz) < std::tie(o.elem, o.tw, o.n, o.cls, o.hasz);
+  }
+};
+struct TuneEntry {
+  int S;
+  float us[3];  // per launch, S = 8, 16, 32
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneEntry> g_tune;
+bool g_tune_on = true;
+constexpr int kTuneS[3] = {8, 16, 32};
+}  // namespace
+
+void set_stencil_autotune(bool on) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_on = on;
+}
+
+std::string stencil_autotune_report() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  std::string out;
+  char line[256];
+  for (const auto& kv : g_tune) {
+    const TuneKey& k = kv.first;
+    const TuneEntry& e = kv.second;
+    std::snprintf(line, sizeof line,
+                  "stencil %s threads=%d n=%d cols<=%d %s: S=%d (us per launch: S8 %.1f, S16 %.1f, S32 %.1f)\n",
+                  k.elem == 8 ? "float64" : "float32", k.tw, k.n, 1 << k.cls, k.hasz ? "with z" : "no z", e.S,
+                  e.us[0], e.us[1], e.us[2]);
+    out += line;
+  }
+  return out;
+}
+
+template <typename T, int TW>
+static void launch_stencil_s(int S, hipStream_t st, int n, int ncols, const T* X, long ldx, T* Y, long ldy,
+                             const T* Z, long ldz, const double* W, int wstride) {
+  if (S == 32) launch_stencil_strip<T, TW, 32>(st, n, ncols, X, ldx, Y, ldy, Z, ldz, W, wstride);
+  else if (S == 16) launch_stencil_strip<T, TW, 16>(st, n, ncols, X, ldx, Y, ldy, Z, ldz, W, wstride);
+  else launch_stencil_strip<T, TW, 8>(st, n, ncols, X, ldx, Y, ldy, Z, ldz, W, wstride);
+}
+
 template <typename T, int TW>
 static void stencil_strips(hipStream_t st, int n, int ncols, const T* X, long ldx, T* Y, long ldy, const T* Z,
                            long ldz, const double* W, int wstride) {
-  // tall strips (less halo re-reading) when there are enough columns to
-  // give the chip a few thousand workgroups, short ones otherwise
   const long want = 2048;
-  if ((long)((n + 31) / 32) * ncols >= want)
-    launch_stencil_strip<T, TW, 32>(st, n, ncols, X, ldx, Y, ldy, Z, ldz, W, wstride);
-  else if ((long)((n + 15) / 16) * ncols >= want)
-    launch_stencil_strip<T, TW, 16>(st, n, ncols, X, ldx, Y, ldy, Z, ldz, W, wstride);
-  else
-    launch_stencil_strip<T, TW, 8>(st, n, ncols, X, ldx, Y, ldy, Z, ldz, W, wstride);
+  const int rule = (long)((n + 31) / 32) * ncols >= want ? 32 : (long)((n + 15) / 16) * ncols >= want ? 16 : 8;
+  int cls = 0;
+  while ((1 << cls) < ncols) ++cls;
+  const TuneKey key{(int)sizeof(T), TW, n, cls, Z ? 1 : 0};
+  int S = rule;
+  bool tune = false;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) S = it->second.S;
+    else tune = g_tune_on;
+  }
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (tune && (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)) tune = false;
+  if (tune && ((const void*)Y == (const void*)X || (Z && (const void*)Y == (const void*)Z))) tune = false;
+  if (!tune) {
+    launch_stencil_s<T, TW>(S, st, n, ncols, X, ldx, Y, ldy, Z, ldz, W, wstride);
+    return;
+  }
+  TuneEntry e{rule, {0.f, 0.f, 0.f}};
+  hipEvent_t a = nullptr, b = nullptr;
+  bool ok = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
+  float best = 0.f;
+  for (int v = 0; v < 3 && ok; ++v) {
+    launch_stencil_s<T, TW>(kTuneS[v], st, n, ncols, X, ldx, Y, ldy, Z, ldz, W, wstride);
+    ok = hipEventRecord(a, st) == hipSuccess;
+    for (int r = 0; r < 3; ++r) launch_stencil_s<T, TW>(kTuneS[v], st, n, ncols, X, ldx, Y, ldy, Z, ldz, W, wstride);
+    float ms = 0.f;
+    ok = ok && hipEventRecord(b, st) == hipSuccess && hipEventSynchronize(b) == hipSuccess &&
+         hipEventElapsedTime(&ms, a, b) == hipSuccess;
+    e.us[v] = 1000.f * ms / 3.f;
+    if (ok && (v == 0 || e.us[v] < best)) {
+      best = e.us[v];
+      e.S = kTuneS[v];
+    }
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (!ok) e.S = rule;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.emplace(key, e);
+  }
+  // the output of the last timed launch is already the result
 }
 
 template <typename T>

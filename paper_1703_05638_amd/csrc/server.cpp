@@ -122,6 +122,10 @@ struct lrpost_server {
     lrpost_problem* p = nullptr;
     lrpost_eigs* e = nullptr;
     int rc = lrpost_create(&d, &p);
+    // V-cycles launched kernel by kernel: a graph capture on one worker's
+    // stream while another worker issues its ordered dense-library calls was
+    // reported by the runtime as a stream-capture isolation error
+    if (rc == LRPOST_OK) rc = lrpost_set_graphs(p, 0);
     if (rc == LRPOST_OK) rc = lrpost_eigensolve(p, rq->k, LRPOST_BLOCK_LANCZOS, 0, &e);
     if (rc == LRPOST_OK) {
       const int kk = lrpost_eig_count(e);

@@ -24,6 +24,7 @@ LRPOST_FP64, LRPOST_MIXED = 0, 1
 LRPOST_MISFIT, LRPOST_PRECOND = 0, 1
 LRPOST_BLOCK_LANCZOS, LRPOST_RANDOMIZED = 0, 1
 LRPOST_KERNEL_SMOOTHER_STEP, LRPOST_KERNEL_MG_DOWN, LRPOST_KERNEL_MG_UP, LRPOST_KERNEL_GRAM, LRPOST_KERNEL_PROJ = 0, 1, 2, 3, 4
+LRPOST_KERNEL_STENCIL = 5
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "ENOCONV", -4: "EBREAKDOWN", -5: "EHIP"}
 
 
@@ -50,8 +51,9 @@ class LowRankC(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("applies", ctypes.c_int64), ("last_rank_y", ctypes.c_int32), ("last_rank_p", ctypes.c_int32),
                 ("last_rank_out", ctypes.c_int32), ("last_basis", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32),
-                ("st_enrichments", ctypes.c_int32), ("last_tail", ctypes.c_double), ("last_st_resid", ctypes.c_double),
-                ("ritz_resid", ctypes.c_double)]
+                ("st_enrichments", ctypes.c_int32), ("st_unresolved", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("last_tail", ctypes.c_double), ("last_st_resid", ctypes.c_double),
+                ("last_st_presid", ctypes.c_double), ("ritz_resid", ctypes.c_double)]
 
 
 _lib = None
@@ -97,12 +99,19 @@ def load(path: str = LIB_PATH):
         "lrpost_gram_noalloc": (I, [P, I, P, I, P, P]),
         "lrpost_truncate": (I, [P, ctypes.POINTER(LowRankC), D, I]),
         "lrpost_set_log": (I, [P, I]),
+        "lrpost_obs_count": (I, [P]),
+        "lrpost_posterior_mean": (I, [P, pd, I, D, ctypes.POINTER(LowRankC), pd]),
         "lrpost_set_eig_limits": (I, [P, I, D]),
         "lrpost_eig_residuals": (I, [P, P, pd]),
         "lrpost_set_st_check": (I, [P, I, D]),
         "lrpost_profile": (I, [P, I]),
         "lrpost_profile_read": (I, [P, I, ctypes.POINTER(ctypes.c_int64), pd, pd, pd]),
         "lrpost_set_mg_fused": (I, [P, I]),
+        "lrpost_set_graphs": (I, [P, I]),
+        "lrpost_set_apply_batch": (I, [P, I]),
+        "lrpost_set_autotune": (I, [I]),
+        "lrpost_autotune_report": (I, [ctypes.c_char_p, ctypes.c_size_t]),
+        "lrpost_graph_info": (I, [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
         "lrpost_server_create": (I, [ctypes.c_size_t, I, ctypes.POINTER(P)]),
         "lrpost_server_submit": (I, [P, P, I, I, ctypes.POINTER(ctypes.c_uint64)]),
         "lrpost_server_wait": (I, [P, ctypes.c_uint64, pd, I, pd, pd]),
@@ -148,6 +157,20 @@ def _make_desc(desc, seed: int = 2, mg_levels: int = 0, stream_ptr=None) -> "Des
     d.mg_levels, d.seed = mg_levels, seed
     d.hip_stream = ctypes.c_void_p(stream_ptr)
     return d
+
+
+def autotune_report() -> str:
+    """The stencil strip-height autotuner's table (one line per shape class)."""
+    lib = load()
+    n = lib.lrpost_autotune_report(None, 0)
+    buf = ctypes.create_string_buffer(n + 1)
+    lib.lrpost_autotune_report(buf, n + 1)
+    return buf.value.decode()
+
+
+def set_autotune(on: bool):
+    """Time the stencil strip heights on each new shape class (default) or use the fixed rule."""
+    _check(load().lrpost_set_autotune(1 if on else 0))
 
 
 class Server:
@@ -203,10 +226,10 @@ class Problem:
     def __init__(self, desc, seed: int = 2, mg_levels: int = 0, stream=None):
         torch = _torch()
         lib = load()
-        if stream is None:
-            stream = torch.cuda.current_stream()
+        # without a stream the library works on a blocking stream of its own,
+        # which is ordered after the work queued on torch's (null) default stream
         self.stream = stream
-        d = _make_desc(desc, seed, mg_levels, stream.cuda_stream)
+        d = _make_desc(desc, seed, mg_levels, stream.cuda_stream if stream is not None else None)
         self._d = d
         h = ctypes.c_void_p()
         _check(lib.lrpost_create(ctypes.byref(d), ctypes.byref(h)))
@@ -343,7 +366,7 @@ class Problem:
         _check(_lib.lrpost_set_eig_limits(self.h, int(max_vectors), float(rtol)))
 
     def set_st_check(self, mode: int = 2, rtol: float = 0.0):
-        """Residual check of the space-time solves: 0 off, 1 measure, 2 measure and enrich."""
+        """Residual check of the space-time solves: 0 off, 1 measure, 2 measure and enrich, 3 strict."""
         _check(_lib.lrpost_set_st_check(self.h, int(mode), float(rtol)))
 
     def eigensolve_probes(self, k: int, probes, allow_unconverged: bool = False) -> "Eigs":
@@ -369,6 +392,22 @@ class Problem:
         e = ctypes.c_void_p()
         _check(_lib.lrpost_eigs_from_pairs(self.h, len(vecs), _hptr(lam), arr, ctypes.byref(e)))
         return Eigs(self, e)
+
+    def obs_count(self) -> int:
+        return _lib.lrpost_obs_count(self.h)
+
+    def posterior_mean(self, y_obs, max_vectors: int = 0, rtol: float = 0.0, allow_unconverged: bool = False):
+        """Posterior mean for observations y_obs (nobs, nt): (W1 (r, nx) CUDA, W2 (r, nt), residual estimate)."""
+        y = np.asfortranarray(np.asarray(y_obs, dtype=np.float64))
+        assert y.shape == (self.obs_count(), self.nt)
+        out, W1, W2 = self._lr_out(max(self.desc.rank_cap, 1))
+        res = ctypes.c_double()
+        rc = _lib.lrpost_posterior_mean(self.h, _hptr(y), int(max_vectors), float(rtol), ctypes.byref(out),
+                                        ctypes.byref(res))
+        if not (rc == -3 and allow_unconverged):
+            _check(rc)
+        r = out.rank
+        return W1[:r].clone(), W2[:r].copy(), res.value
 
     def post_variance(self, eigs: "Eigs", on_device: bool = True):
         """diag(Gamma_post,k) as an (nt, nx) array (row t = time step t)."""
@@ -425,10 +464,25 @@ class Problem:
         """Level-fused multigrid kernels (default) or one kernel per step."""
         _check(_lib.lrpost_set_mg_fused(self.h, 1 if on else 0))
 
+    def set_apply_batch(self, n: int):
+        """Probe applies per batched pass of the randomized eigensolver (0: as many as fit)."""
+        _check(_lib.lrpost_set_apply_batch(self.h, int(n)))
+
+    def set_graphs(self, on: bool):
+        """V-cycles replayed from captured HIP graphs (default) or launched kernel by kernel."""
+        _check(_lib.lrpost_set_graphs(self.h, 1 if on else 0))
+
+    def graph_info(self):
+        """(graphs captured, graph launches) since creation."""
+        a = ctypes.c_int64()
+        b = ctypes.c_int64()
+        _check(_lib.lrpost_graph_info(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
     def stats(self) -> dict:
         s = Stats()
         _check(_lib.lrpost_get_stats(self.h, ctypes.byref(s)))
-        return {f: getattr(s, f) for f, _ in Stats._fields_}
+        return {f: getattr(s, f) for f, _ in Stats._fields_ if f != "reserved"}
 
 
 class Eigs:

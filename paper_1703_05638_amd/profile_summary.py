@@ -1,4 +1,4 @@
-"""Summaries of rocprofv3 CSV output for the multigrid kernels.
+"""Summaries of rocprofv3 CSV output for the library's kernels.
 
 Two modes, each printing a short text report:
 
@@ -33,11 +33,12 @@ KERNEL_SOURCES = {
     "k_mg": ("__device__ inline void strip_of(", "template void mg_up<float>"),
     "k_gram": ("// FP64 Gram on the matrix cores.", "void sum_partials("),
     "k_proj": ("// FP64 projection on the matrix cores,", "template void proj<float>("),
+    "k_stencil": ("__device__ inline void stencil_strip_body", "// Autotuner of the stencil strip height"),
 }
 
 
 def _source_key(regex):
-    for key in ("k_gram", "k_proj", "k_mg"):
+    for key in ("k_gram", "k_proj", "k_mg", "k_stencil"):
         if key in regex:
             return key
     return "k_cheb"
