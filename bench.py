@@ -92,9 +92,12 @@ def cpu_baseline(desc, sample_steps=16):
 def serving(args):
     """Replay the first --serving requests of the seeded Poisson request stream
     (20 req/s; mesh side 64/128/256, nt 50/100/200, k = 30 eigenpairs plus the
-    posterior variance, tol 1e-6, rank <= 64) through the serving loop, then
-    run the same requests one after another on one stream (the plain FP64
-    path) and report latency percentiles, throughput and the speedup."""
+    posterior variance, tol 1e-6, rank <= 64) through the serving loop (workers
+    with resident problems per size class, memory admission), then run the
+    same requests one after another on one stream, each on a new problem in
+    float64 (the plain FP64 path), and report latency percentiles, throughput
+    and the speedup.  The served requests run in --precision (mixed by
+    default)."""
     import torch
 
     import synthetic
@@ -102,6 +105,7 @@ def serving(args):
 
     lp.load()
     torch.cuda.set_device(0)
+    import dataclasses
     reqs = synthetic.serving_stream()[: args.serving]
     srv = lp.Server(hbm_budget_bytes=200 << 30, workers=args.workers)
     t0 = time.perf_counter()
@@ -110,7 +114,7 @@ def serving(args):
         delay = r.arrival_s - (time.perf_counter() - t0)
         if delay > 0:
             time.sleep(delay)
-        tickets.append(srv.submit(r.desc, r.desc.k))
+        tickets.append(srv.submit(dataclasses.replace(r.desc, precision=args.precision), r.desc.k))
     lat = []
     for i, t in enumerate(tickets):
         lat.append(srv.wait(t)[2])
@@ -130,13 +134,14 @@ def serving(args):
     out = {
         "metric": "posterior requests served: p50/p99 latency",
         "value": len(reqs) / t_serve, "unit": "requests/s", "n_gpus": 1, "higher_is_better": True,
-        "data": "synthetic", "dtype": "f64",
+        "data": "synthetic", "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "config": {"workload": "poisson20_mesh64-256_nt50-200_k30", "requests": len(reqs), "workers": args.workers,
-                   "hbm_budget_gb": 200},
+                   "hbm_budget_gb": 200, "precision": args.precision},
         "latency_s": {"p50": statistics.median(lat),
                       "p99": lat_sorted[min(len(lat) - 1, int(0.99 * len(lat)))]},
         "makespan_s": t_serve, "sequential_fp64_s": t_seq, "speedup_vs_sequential": t_seq / t_serve,
         "peak_running": info["peak_running"], "peak_admitted_gb": info["peak_admitted_bytes"] / 2 ** 30,
+        "served_on_resident_problem": info["resident_hits"],
     }
     print(json.dumps(out))
 

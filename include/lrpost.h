@@ -126,6 +126,15 @@ typedef struct {
  * (Q1 heat equation, implicit Euler). */
 int lrpost_create(const lrpost_problem_desc* desc, lrpost_problem** out);
 int lrpost_destroy(lrpost_problem* p);
+/* Re-target a problem to another prior precision scale alpha, noise level
+ * sigma, observation box and start-block seed, keeping its mesh, time steps,
+ * tolerance, rank cap, precision, stream, multigrid hierarchy, device memory
+ * pool and captured graphs: every later result equals that of a problem
+ * created with the new description (a resident problem for requests of one
+ * size class).  Eigenpair handles made before belong to the old target and
+ * are rejected afterwards (LRPOST_EINVAL).  alpha, sigma <= 0 or an empty
+ * box: LRPOST_EINVAL, with the problem unchanged. */
+int lrpost_retarget(lrpost_problem* p, double alpha, double sigma, const double* box, uint64_t seed);
 
 /* Hessian apply on one low-rank vector (Sec. 6.1 eq. misfit, Sec. 4
  * Algorithm 1 matrix-vector step): forward space-time solve of the source
@@ -372,12 +381,17 @@ int lrpost_truncate(lrpost_problem* p, lrpost_lowrank* x, double tol, int weight
  * Posterior requests (the k leading eigenpairs by block Lanczos and, when
  * want_diag != 0, diag(Gamma_post,k) over nx * nt points; Sec. 2, Sec. 6
  * eq. postvar) of any mesh and time size, served concurrently.  `workers`
- * threads (1..16) each own a HIP stream; a worker takes the oldest pending
- * request whose device-memory estimate fits in what is left of
- * hbm_budget_bytes (a request always runs when nothing else does), so that
+ * threads (1..16) each own a HIP stream; a worker takes a pending request
+ * whose device-memory estimate fits in what is left of hbm_budget_bytes (one
+ * of its resident size class among the first eight pending if there is one,
+ * else the oldest; a request always runs when nothing else does), so that
  * requests arriving while others run are admitted as workers and memory free
- * up and overlap with them on the device.  Every request builds its own
- * problem on the worker's stream; its result is the one it would have alone.
+ * up and overlap with them on the device.  Each worker keeps the problem of
+ * the last size class (mesh, nt, T, tolerance, rank cap, precision) it served
+ * resident on the device and prefers pending requests of that class, which
+ * it serves on that problem re-targeted to their prior, noise and box (a
+ * parked problem's memory estimate stays counted against the budget); a
+ * request's result is the one it would have alone.
  * submit copies the description and returns a ticket at once; wait blocks
  * until that request is done, writes k eigenvalues (host) and, if diag is
  * not NULL and the request asked for it, nx * nt variances (host,
@@ -391,6 +405,9 @@ int lrpost_server_submit(lrpost_server* s, const lrpost_problem_desc* desc, int 
 int lrpost_server_wait(lrpost_server* s, uint64_t ticket, double* lambda, int k, double* diag, double* latency_s);
 /* largest number of requests that ran at once and largest admitted memory estimate */
 int lrpost_server_info(lrpost_server* s, int* peak_running, size_t* peak_admitted_bytes);
+/* requests served so far, and how many of them ran on a worker's resident
+ * problem of their size class (re-targeted, lrpost_retarget) */
+int lrpost_server_class_stats(lrpost_server* s, int64_t* served, int64_t* resident_hits);
 int lrpost_server_destroy(lrpost_server* s);
 
 const char* lrpost_last_error(void);

@@ -45,7 +45,8 @@ static Problem* impl(lrpost_problem* p) {
 // alive; every stored vector must have that problem's shape.
 static Problem* owner_of(lrpost_problem* p, const lrpost_eigs* e) {
   if (!e) fail(LRPOST_EINVAL, "null eigenpair handle");
-  if (e->owner_alive.expired() || !e->owner) fail(LRPOST_EINVAL, "the problem of this eigenpair handle was destroyed");
+  if (e->owner_alive.expired() || !e->owner)
+    fail(LRPOST_EINVAL, "the problem of this eigenpair handle was destroyed or re-targeted");
   if (p && e->owner != p) fail(LRPOST_EINVAL, "eigenpair handle belongs to another problem");
   Problem* P = e->owner->impl.get();
   if (!P) fail(LRPOST_EINVAL, "null problem handle");
@@ -105,6 +106,18 @@ int lrpost_create(const lrpost_problem_desc* desc, lrpost_problem** out) {
 
 int lrpost_destroy(lrpost_problem* p) {
   return guarded([&] { delete p; });
+}
+
+int lrpost_retarget(lrpost_problem* p, double alpha, double sigma, const double* box, uint64_t seed) {
+  return guarded([&] {
+    Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
+    if (!box) fail(LRPOST_EINVAL, "null box");
+    P->sync();
+    P->set_observation(alpha, sigma, box, seed);
+    // eigenpair handles of the previous target no longer describe this problem
+    p->alive = std::make_shared<int>(0);
+  });
 }
 
 int lrpost_get_stats(const lrpost_problem* p, lrpost_stats* s) {

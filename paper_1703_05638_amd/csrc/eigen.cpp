@@ -680,7 +680,7 @@ EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rt
     std::vector<double> Tm((size_t)m * m);
     for (int c = 0; c < m; ++c)
       for (int r = 0; r < m; ++r) Tm[(size_t)c * m + r] = 0.5 * (T[(size_t)c * mmax + r] + T[(size_t)r * mmax + c]);
-    {
+    if (!lin) {
       Problem::PhaseTimer pt(P, Problem::kPhRitz);
       P->sym_eig(m, Tm.data(), m, theta, Y);
     }
@@ -701,7 +701,15 @@ EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rt
     // residual estimates ||G x - theta x||_P = ||Rn * Y[last block, s]||
     bool done = m >= k;
     double worst = 0.0;
-    if (lin) {
+    // the linear solve is checked every kLinCheck block steps and at the end
+    constexpr int kLinCheck = 4;
+    const bool lin_check = lin && (step % kLinCheck == kLinCheck - 1 || kn == 0 || m + kn > mmax);
+    if (lin && !lin_check) done = false;
+    if (lin_check) {
+      {
+        Problem::PhaseTimer pt(P, Problem::kPhRitz);
+        P->sym_eig(m, Tm.data(), m, theta, Y);
+      }
       // Galerkin solution of (G + shift I) x = rhs on the basis:
       // z = Y diag(1 / (theta + shift)) Y^T g, with residual
       // ||(G + shift I) V z - rhs||_P = ||Rn z[last block]||
@@ -770,7 +778,7 @@ EigResult block_lanczos(Problem* P, int k, int bsize, int max_vectors, double rt
                    "\"poles\": %.3f, \"project\": %.3f, \"proj_solve\": %.3f, \"trunc\": %.3f, \"prior\": %.3f, "
                    "\"materialize\": %.3f, \"absorb\": %.3f, \"reorth\": %.3f, \"ritz\": %.3f, \"orth_block\": %.3f}}\n",
                    step, m, sb.s, (long long)P->stats.applies, t_apply, t_orth,
-                   std::chrono::duration<double>(clk::now() - t_start).count(), worst, theta[m - 1],
+                   std::chrono::duration<double>(clk::now() - t_start).count(), worst, theta.empty() ? 0.0 : theta.back(),
                    P->pool->bytes_in_use() / 1048576.0, fr / 1048576.0, P->phase_s[0], P->phase_s[1], P->phase_s[2],
                    P->phase_s[3], P->phase_s[4], P->phase_s[5], P->phase_s[6], P->phase_s[7], P->phase_s[8],
                    P->phase_s[9], P->phase_s[10]);
@@ -867,6 +875,17 @@ EigResult randomized_eig(Problem* P, int k, const std::vector<const LowRank*>& p
   for (auto* w : probes) rmax = std::max(rmax, w->rank);
   const int abatch = P->apply_batch_limit(rmax, l);
   std::vector<CVec> Y;
+  // The probes' images only span the trial space: the second pass makes the
+  // Ritz values Rayleigh quotients of that space, so the space-time solves
+  // of pass one are measured but not enriched (Gaussian probes have
+  // independent nodal values, which the default poles resolve to about 1e-3)
+  struct CheckScope {
+    Problem* P;
+    int saved;
+    explicit CheckScope(Problem* p) : P(p), saved(p->st_check) { P->st_check = std::min(saved, 1); }
+    ~CheckScope() { P->st_check = saved; }
+  };
+  std::optional<CheckScope> pass_one_check(std::in_place, P);
   for (int j0 = 0; j0 < l; j0 += abatch) {
     const int nbt = std::min(abatch, l - j0);
     std::vector<LowRank> ys(nbt);
@@ -877,6 +896,7 @@ EigResult randomized_eig(Problem* P, int k, const std::vector<const LowRank*>& p
     for (auto& y : ys) Y.push_back(sb.absorb(y, tol, cap));
     logline("pass1", j0 + nbt);
   }
+  pass_one_check.reset();
   for (auto& y : Y) sb.append(y);
   std::vector<double> Gy((size_t)l * l);
   {

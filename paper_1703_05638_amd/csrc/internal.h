@@ -137,6 +137,9 @@ class Problem {
   std::vector<MgLevel> lv;
   int lds_level;  // first level solved inside one LDS workgroup
   std::vector<uint8_t> mask_h;
+  std::vector<double> kmdiag_h_;  // diag((K+M)^{-1}), n x n nodes
+  // re-target to another prior scale, noise level, box and seed
+  void set_observation(double alpha, double sigma, const double* box, uint64_t seed);
   DevMem mask;
   int nobs = 0;
   std::vector<double> dprior_h;  // diag(P^{-1}) per node

@@ -79,6 +79,8 @@ void sum_partials_grouped(hipStream_t st, int count, const GramGroup* groups);
 long gram_part_doubles(long nrows, int m, int q);
 // tile height class of a Gram product with m columns of A: 64 gram_bm(m) rows
 int gram_bm(int m);
+// tile width class of a Gram product with q columns of B: 64 gram_bq(q) columns
+int gram_bq(int q);
 void sum_partials(hipStream_t st, int nchunk, long count, const double* part, double* C);
 // C (device, m x q, double) = A^T B; part: device scratch of gram_chunks()*m*q
 // doubles (gram_chunks_mfma() for T = double).

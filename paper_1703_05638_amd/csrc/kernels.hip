@@ -1037,15 +1037,24 @@ int gram_chunks(long nrows, int m, int q) {
 // (l / 16 + 4 v, l % 16) in slot v.
 // ---------------------------------------------------------------------------
 typedef double gram_d4 __attribute__((ext_vector_type(4)));
-constexpr int GQ = 64;   // output tile width (q direction)
-constexpr int GK = 32;   // rows per LDS stage
 constexpr int GTH = 512;  // threads per workgroup
+// Tile width 64 BQ in the q direction: BQ = 2 when q > 64, so that the wide
+// operand of products with more than 64 columns on both sides is read half
+// as often.  Rows per LDS stage: 32, or 16 for the 192 x 128 tile, whose two
+// 32-row stages would not fit in the 160 KiB of LDS.
+template <int BM, int BQ>
+struct GramShape {
+  static constexpr int GM = 64 * BM, GQ = 64 * BQ;
+  static constexpr int GK = (BM == 3 && BQ == 2) ? 16 : 32;
+};
 
-template <int BM>
+template <int BM, int BQ>
 __device__ __forceinline__ void gram_tile(long nrows, long rows_per_chunk, int m, const double* __restrict__ A,
                                           long lda, int q, const double* __restrict__ B, long ldb,
                                           double* __restrict__ part, int tm, int tq, int chunk) {
-  constexpr int GM = 64 * BM;                 // output tile height (m direction)
+  constexpr int GM = GramShape<BM, BQ>::GM;   // output tile height (m direction)
+  constexpr int GQ = GramShape<BM, BQ>::GQ;   // output tile width (q direction)
+  constexpr int GK = GramShape<BM, BQ>::GK;   // rows per LDS stage
   constexpr int NC = GM + GQ;                 // staged columns per row
   constexpr int NU = NC / (GTH / GK);         // columns per loading thread
   __shared__ double S[2][NC][GK + 1];         // two stages of [column][row]: A columns, then B columns
@@ -1053,11 +1062,11 @@ __device__ __forceinline__ void gram_tile(long nrows, long rows_per_chunk, int m
   const int wm = wave & 3, wq = wave >> 2;
   const long r0 = (long)chunk * rows_per_chunk;
   const long r1 = min(nrows, r0 + rows_per_chunk);
-  gram_d4 acc[BM][2];
+  gram_d4 acc[BM][2 * BQ];
 #pragma unroll
   for (int a = 0; a < BM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = gram_d4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < 2 * BQ; ++b) acc[a][b] = gram_d4{0.0, 0.0, 0.0, 0.0};
   const int lr = tid & (GK - 1), lc = tid / GK;  // loader: row lr of columns lc, lc + GTH / GK, ...
   const long nst = (r1 > r0) ? (r1 - r0 + GK - 1) / GK : 0;
   // this thread's staged columns: u < NA are columns of A, the rest of B,
@@ -1104,14 +1113,15 @@ __device__ __forceinline__ void gram_tile(long nrows, long rows_per_chunk, int m
     if (it + 1 < nst) fetch(it + 1);
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 4) {
-      double bf[2];
+      double bf[2 * BQ];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bf[b] = S[cb][GM + wq * 32 + 16 * b + ci][kk + ck];
+      for (int b = 0; b < 2 * BQ; ++b) bf[b] = S[cb][GM + wq * 32 * BQ + 16 * b + ci][kk + ck];
 #pragma unroll
       for (int a = 0; a < BM; ++a) {
         const double af = S[cb][wm * 16 * BM + 16 * a + ci][kk + ck];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf[b], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < 2 * BQ; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf[b], acc[a][b], 0, 0, 0);
       }
     }
     if (it + 1 < nst) {
@@ -1125,11 +1135,11 @@ __device__ __forceinline__ void gram_tile(long nrows, long rows_per_chunk, int m
 #pragma unroll
   for (int a = 0; a < BM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 2 * BQ; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = tm * GM + wm * 16 * BM + 16 * a + (lane >> 4) + 4 * v;
-        const int j = tq * GQ + wq * 32 + 16 * b + (lane & 15);
+        const int j = tq * GQ + wq * 32 * BQ + 16 * b + (lane & 15);
         if (i < m && j < q) P[(long)j * m + i] = acc[a][b][v];
       }
 }
@@ -1137,26 +1147,27 @@ __device__ __forceinline__ void gram_tile(long nrows, long rows_per_chunk, int m
 // Several Gram products in one launch: blockIdx.z = group * nchunk_max +
 // chunk; each product keeps its own chunking (rows per chunk from its own
 // shape), so its partial sums are exactly those of a launch of its own.
-template <int BM>
+template <int BM, int BQ>
 __global__ __launch_bounds__(GTH) void k_gram_mfma(long nrows, GramGroups gs) {
   const int gi = blockIdx.z / gs.nchunk_max, chunk = blockIdx.z % gs.nchunk_max;
   const GramGroup& g = gs.g[gi];
-  if (chunk >= g.nchunk || (int)blockIdx.x * 64 * BM >= g.m || (int)blockIdx.y * GQ >= g.q) return;
-  gram_tile<BM>(nrows, g.rpc, g.m, g.A, g.lda, g.q, g.B, g.ldb, g.part, blockIdx.x, blockIdx.y, chunk);
+  if (chunk >= g.nchunk || (int)blockIdx.x * 64 * BM >= g.m || (int)blockIdx.y * 64 * BQ >= g.q) return;
+  gram_tile<BM, BQ>(nrows, g.rpc, g.m, g.A, g.lda, g.q, g.B, g.ldb, g.part, blockIdx.x, blockIdx.y, chunk);
 }
 
 // tile height 64 BM: the smallest that covers m, at most 192 (the 256-row
 // tile needs 146 registers per lane, which leaves one workgroup per CU; wider
-// products take several tiles)
+// products take several tiles); tile width 64 BQ
 int gram_bm(int m) { return m <= 64 ? 1 : m <= 128 ? 2 : 3; }
+int gram_bq(int q) { return q <= 64 ? 1 : 2; }
 
 int gram_chunks_mfma(long nrows, int m, int q) {
   // about one workgroup per CU (longer chunks beat more, shorter ones: a
   // chunk's stages are dependent round trips to memory), at least 128 rows
   // per chunk, and per-chunk partial products of at most about 35% of the
   // operand bytes
-  const int gm = 64 * gram_bm(m);
-  const long tiles = (long)((m + gm - 1) / gm) * ((q + GQ - 1) / GQ);
+  const int gm = 64 * gram_bm(m), gq = 64 * gram_bq(q);
+  const long tiles = (long)((m + gm - 1) / gm) * ((q + gq - 1) / gq);
   long c = 256 / (tiles > 0 ? tiles : 1);
   const long cmax = (nrows + 127) / 128;
   const long cpart = (long)(0.35 * (double)(m + q) * (double)nrows / ((double)m * q)) + 1;
@@ -1188,7 +1199,7 @@ void gram_mfma_partials(hipStream_t st, long nrows, int count, GramGroup* groups
       GramGroup& g = groups[g0 + i];
       g.nchunk = (g.m > 0 && g.q > 0) ? gram_chunks_mfma(nrows, g.m, g.q) : 0;
       long rpc = g.nchunk > 0 ? (nrows + g.nchunk - 1) / g.nchunk : 0;
-      g.rpc = ((rpc + GK - 1) / GK) * GK;
+      g.rpc = ((rpc + 31) / 32) * 32;  // a multiple of every stage height
       gs.g[i] = g;
       mmax = std::max(mmax, g.m);
       qmax = std::max(qmax, g.q);
@@ -1197,11 +1208,24 @@ void gram_mfma_partials(hipStream_t st, long nrows, int count, GramGroup* groups
     if (mmax <= 0 || qmax <= 0) continue;
     gs.nchunk_max = cmax;
     const int bm = gram_bm(mmax), gm = 64 * bm;
-    dim3 grd((mmax + gm - 1) / gm, (qmax + GQ - 1) / GQ, n * cmax);
-    switch (bm) {
-      case 1: hipLaunchKernelGGL((k_gram_mfma<1>), grd, dim3(GTH), 0, st, nrows, gs); break;
-      case 2: hipLaunchKernelGGL((k_gram_mfma<2>), grd, dim3(GTH), 0, st, nrows, gs); break;
-      default: hipLaunchKernelGGL((k_gram_mfma<3>), grd, dim3(GTH), 0, st, nrows, gs);
+    int qmin = qmax;
+    for (int i = 0; i < n; ++i)
+      if (gs.g[i].q > 0) qmin = std::min(qmin, gs.g[i].q);
+    // the wide tile only when every product of the launch is wider than 64
+    const int bq = gram_bq(qmin), gq = 64 * bq;
+    dim3 grd((mmax + gm - 1) / gm, (qmax + gq - 1) / gq, n * cmax);
+    if (bq == 1) {
+      switch (bm) {
+        case 1: hipLaunchKernelGGL((k_gram_mfma<1, 1>), grd, dim3(GTH), 0, st, nrows, gs); break;
+        case 2: hipLaunchKernelGGL((k_gram_mfma<2, 1>), grd, dim3(GTH), 0, st, nrows, gs); break;
+        default: hipLaunchKernelGGL((k_gram_mfma<3, 1>), grd, dim3(GTH), 0, st, nrows, gs);
+      }
+    } else {
+      switch (bm) {
+        case 1: hipLaunchKernelGGL((k_gram_mfma<1, 2>), grd, dim3(GTH), 0, st, nrows, gs); break;
+        case 2: hipLaunchKernelGGL((k_gram_mfma<2, 2>), grd, dim3(GTH), 0, st, nrows, gs); break;
+        default: hipLaunchKernelGGL((k_gram_mfma<3, 2>), grd, dim3(GTH), 0, st, nrows, gs);
+      }
     }
   }
 }

@@ -160,21 +160,7 @@ Problem::Problem(const lrpost_problem_desc& d) : desc(d) {
   }
   lds_level = 0;
   while (lv[lds_level].n > kCoarseLdsMaxN) ++lds_level;
-  // observation mask (closed box, 1e-12 slack)
-  mask_h.assign(nx, 0);
-  const double eps = 1e-12;
-  for (int j = 0; j < n; ++j)
-    for (int i = 0; i < n; ++i) {
-      const double x1 = (i + 1) * h, x2 = (j + 1) * h;
-      const bool in = x1 >= d.box[0] - eps && x1 <= d.box[1] + eps && x2 >= d.box[2] - eps && x2 <= d.box[3] + eps;
-      mask_h[(size_t)j * n + i] = in ? 1 : 0;
-      nobs += in ? 1 : 0;
-    }
-  if (nobs == 0) fail(LRPOST_EINVAL, "observation box holds no mesh node");
-  mask.ensure(nx);
-  to_device_bytes(mask.p, mask_h.data(), nx);
-  sync();
-  // prior variance diag(P^{-1}) from the sine eigenpairs of K and M:
+  // diag((K+M)^{-1}) from the sine eigenpairs of K and M:
   // (K+M)^{-1} = sum_p phi_p phi_p^T / (kappa_p + mu_p), phi_p = s_i (x) s_j,
   // s_j(ii) = sqrt(2h) sin(ii j pi h), kappa = k_i m_j + m_i k_j, mu = m_i m_j.
   {
@@ -195,16 +181,10 @@ Problem::Problem(const lrpost_problem_desc& d) : desc(d) {
         W[(size_t)j * n + i] = 1.0 / (k1[i] * m1[j] + m1[i] * k1[j] + m1[i] * m1[j]);
     // D = Sq W Sq^T, D[ii, jj]
     matmul(n, n, n, Sq.data(), n, false, W.data(), n, false, T1.data(), n, 1.0, 0.0);
-    std::vector<double> D((size_t)n * n);
-    matmul(n, n, n, T1.data(), n, false, Sq.data(), n, true, D.data(), n, 1.0, 0.0);
-    dprior_h.resize(nx);
-    const double s = 1.0 / (d.alpha * tau);
-    for (int jj = 0; jj < n; ++jj)
-      for (int ii = 0; ii < n; ++ii) dprior_h[(size_t)jj * n + ii] = s * D[(size_t)jj * n + ii];
+    kmdiag_h_.assign((size_t)n * n, 0.0);
+    matmul(n, n, n, T1.data(), n, false, Sq.data(), n, true, kmdiag_h_.data(), n, 1.0, 0.0);
   }
-  dprior.ensure(sizeof(double) * nx);
-  to_device(dprior.as<double>(), dprior_h.data(), nx);
-  sync();
+  set_observation(d.alpha, d.sigma, d.box, d.seed);
   // inner-solver settings from the truncation tolerance: poles of the spatial
   // rational Krylov basis log-spaced over the time-step scaled spectrum, and
   // enough V-cycles to resolve it.  For tolerances down to 1e-7 the poles
@@ -258,6 +238,40 @@ int Problem::apply_batch_limit(int r, int want) const {
   const double budget = 0.5 * (double)free_at_create;
   const int fit = per_input > 0 ? (int)(budget / per_input) : want;
   return std::max(1, std::min(want, fit));
+}
+
+// The parts of a problem that depend on the prior scale, the noise level,
+// the observation box and the start-block seed: the observation mask (closed
+// box, 1e-12 slack) and diag(P^{-1}) = (alpha tau)^{-1} diag((K+M)^{-1}).
+// Everything else (mesh, multigrid hierarchy, poles, device pool, graphs)
+// depends only on the mesh, the time steps and the tolerances.
+void Problem::set_observation(double alpha, double sigma, const double* box, uint64_t seed) {
+  if (!(alpha > 0) || !(sigma > 0)) fail(LRPOST_EINVAL, "alpha and sigma must be positive");
+  std::vector<uint8_t> mh(nx, 0);
+  int cnt = 0;
+  const double eps = 1e-12;
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      const double x1 = (i + 1) * h, x2 = (j + 1) * h;
+      const bool in = x1 >= box[0] - eps && x1 <= box[1] + eps && x2 >= box[2] - eps && x2 <= box[3] + eps;
+      mh[(size_t)j * n + i] = in ? 1 : 0;
+      cnt += in ? 1 : 0;
+    }
+  if (cnt == 0) fail(LRPOST_EINVAL, "observation box holds no mesh node");
+  desc.alpha = alpha;
+  desc.sigma = sigma;
+  for (int i = 0; i < 4; ++i) desc.box[i] = box[i];
+  desc.seed = seed;
+  mask_h.swap(mh);
+  nobs = cnt;
+  mask.ensure(nx);
+  to_device_bytes(mask.p, mask_h.data(), nx);
+  dprior_h.resize(nx);
+  const double sc = 1.0 / (alpha * tau);
+  for (long i = 0; i < nx; ++i) dprior_h[i] = sc * kmdiag_h_[i];
+  dprior.ensure(sizeof(double) * nx);
+  to_device(dprior.as<double>(), dprior_h.data(), nx);
+  sync();
 }
 
 Problem::~Problem() {
@@ -717,18 +731,19 @@ void Problem::gram_dev(int m, const double* A, int q, const double* B, double* C
 
 // Several Gram products A_g^T B_g (nx rows) with one launch per stage for up
 // to kProjGroupMax of them; each result is the one gram_dev gives.  Products
-// of different tile heights (64, 128 or 192 rows, from m) go to separate
-// launches, so that no product is computed with a taller tile than its own.
+// of different tile shapes (64, 128 or 192 rows from m; 64 or 128 columns
+// from q) go to separate launches, so that each runs with its own tile.
 void Problem::gram_dev_grouped(std::vector<GramGroup>& gs) {
   std::vector<size_t> off(gs.size() + 1, 0);
   for (size_t i = 0; i < gs.size(); ++i) off[i + 1] = off[i] + (size_t)gram_part_doubles(nx, gs[i].m, gs[i].q);
   if (off.back() == 0) return;
   gram_part_.ensure(sizeof(double) * off.back());
   for (size_t i = 0; i < gs.size(); ++i) gs[i].part = gram_part_.as<double>() + off[i];
-  for (int cls = 1; cls <= 3; ++cls) {
+  for (int cls = 1; cls <= 6; ++cls) {
+    // tile class: height from m (1..3), width from q (64 or 128)
     std::vector<GramGroup> gc;
     for (const GramGroup& g : gs)
-      if (g.m > 0 && g.q > 0 && gram_bm(g.m) == cls) gc.push_back(g);
+      if (g.m > 0 && g.q > 0 && gram_bm(g.m) + 3 * (gram_bq(g.q) - 1) == cls) gc.push_back(g);
     for (size_t g0 = 0; g0 < gc.size(); g0 += kProjGroupMax) {
       const int n = (int)std::min<size_t>(kProjGroupMax, gc.size() - g0);
       double bytes = 0.0, flops = 0.0;
@@ -1059,6 +1074,10 @@ void Problem::spacetime_solve_batch(const std::vector<const LowRank*>& F, const 
   }
   const double top = std::min(tau * 24.0 / (h * h), 1e4);
   for (double p = base.back() * ratio; p < top * ratio && fine.size() < 48; p *= ratio * ratio) fine.push_back(p);
+  // the enriched solves in chunks whose pole-solve columns stay within those
+  // of the first pass, so that enrichment needs no more device memory
+  long budget_cols = 0;
+  for (int j = 0; j < nb; ++j) budget_cols += (long)F[j]->rank * (long)base.size();
   std::vector<const LowRank*> Fb;
   std::vector<LowRank*> Yb;
   for (int j : bad) {
@@ -1067,7 +1086,18 @@ void Problem::spacetime_solve_batch(const std::vector<const LowRank*>& F, const 
   }
   poles = fine;
   try {
-    st_solve_pass(Fb, Yb, adjoint);
+    size_t i0 = 0;
+    while (i0 < Fb.size()) {
+      size_t i1 = i0;
+      long cols = 0;
+      while (i1 < Fb.size() && (i1 == i0 || cols + (long)Fb[i1]->rank * (long)fine.size() <= budget_cols)) {
+        cols += (long)Fb[i1]->rank * (long)fine.size();
+        ++i1;
+      }
+      st_solve_pass(std::vector<const LowRank*>(Fb.begin() + i0, Fb.begin() + i1),
+                    std::vector<LowRank*>(Yb.begin() + i0, Yb.begin() + i1), adjoint);
+      i0 = i1;
+    }
   } catch (...) {
     poles = base;
     throw;

@@ -4,12 +4,20 @@
 // concurrently.
 //
 // Each worker thread owns a HIP stream (non-blocking, default priority) and
-// takes the oldest pending request whose memory estimate fits in what is
-// left of the budget; requests that arrive while others run are admitted as
-// soon as a worker and memory free up, and their kernels overlap on the
-// device with the running ones.  A request runs through the public entry
-// points (create, eigensolve, post_variance) on the worker's stream with a
-// problem of its own, so its result does not depend on what else is running.
+// keeps one resident problem: that of the last size class it served (mesh,
+// time steps, horizon, tolerance, rank cap, precision), with its multigrid
+// hierarchy, device memory pool and stencil weights.  A worker takes, among
+// the first pending requests whose memory estimate fits in what is left of
+// the budget, one of its resident size class if there is one (requests of a
+// class are thereby served back to back on the problem that stays on the
+// device, re-targeted to each request's prior, noise and box), else the
+// oldest.  Requests that arrive while others run are admitted as soon as a
+// worker and memory free up, and their kernels overlap on the device with
+// the running ones.  A resident problem's memory stays counted against the
+// budget while it is parked.  Every request runs through the public entry
+// points on the worker's stream, and a re-targeted problem computes exactly
+// what a new one would, so a result does not depend on what else is running
+// or ran before.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -63,10 +71,28 @@ size_t estimate_bytes(const lrpost_problem_desc& d, int k) {
   return (size_t)(8.0 * nx * cols * 2.0);
 }
 
+// Requests of one size class can share a problem (lrpost_retarget).
+bool same_class(const lrpost_problem_desc& a, const lrpost_problem_desc& b) {
+  return a.N == b.N && a.nt == b.nt && a.T == b.T && a.trunc_tol == b.trunc_tol && a.rank_cap == b.rank_cap &&
+         a.precision == b.precision && a.mg_levels == b.mg_levels;
+}
+
+// how far down the pending queue a worker looks for a request of its class
+constexpr int kClassLookahead = 8;
+
+}  // namespace
+
+namespace {
+struct Resident {
+  lrpost_problem* p = nullptr;
+  lrpost_problem_desc desc{};
+  size_t bytes = 0;  // memory estimate kept reserved while parked
+};
 }  // namespace
 
 struct lrpost_server {
   size_t budget = 0, in_use = 0, peak_in_use = 0;
+  int64_t resident_hits = 0, served = 0;
   int device = 0;
   int running = 0, peak_running = 0;
   bool stop = false;
@@ -81,51 +107,95 @@ struct lrpost_server {
     (void)hipSetDevice(device);
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
+    Resident res;
     for (;;) {
       std::shared_ptr<Request> rq;
+      bool reuse = false;
       {
         std::unique_lock<std::mutex> lk(mu);
         for (;;) {
           if (stop) break;
-          // oldest request that fits; with nothing running, the oldest always runs
-          for (auto it = pending.begin(); it != pending.end(); ++it)
-            if (running == 0 || in_use + (*it)->est_bytes <= budget) {
-              rq = *it;
-              pending.erase(it);
+          // a request of the resident class among the first few that fit,
+          // else the oldest that fits (the resident problem's reservation is
+          // released for a request of another class); with nothing running,
+          // the oldest always runs
+          auto fits = [&](const Request& r) {
+            const bool same = res.p && same_class(res.desc, r.desc);
+            const size_t need = r.est_bytes > (same ? res.bytes : 0) ? r.est_bytes - (same ? res.bytes : 0) : 0;
+            const size_t freed = same ? 0 : res.bytes;
+            return running == 0 || in_use - freed + need <= budget;
+          };
+          auto pick = pending.end();
+          int looked = 0;
+          for (auto it = pending.begin(); it != pending.end() && looked < kClassLookahead; ++it, ++looked)
+            if (res.p && same_class(res.desc, (*it)->desc) && fits(**it)) {
+              pick = it;
               break;
             }
-          if (rq) break;
+          if (pick == pending.end())
+            for (auto it = pending.begin(); it != pending.end(); ++it)
+              if (fits(**it)) {
+                pick = it;
+                break;
+              }
+          if (pick != pending.end()) {
+            rq = *pick;
+            pending.erase(pick);
+            break;
+          }
           cv_work.wait(lk);
         }
         if (!rq) break;
-        in_use += rq->est_bytes;
+        reuse = res.p && same_class(res.desc, rq->desc);
+        // the request's reservation replaces the parked one
+        in_use = in_use - res.bytes + rq->est_bytes;
         peak_in_use = std::max(peak_in_use, in_use);
         ++running;
         peak_running = std::max(peak_running, running);
+        ++served;
+        if (reuse) ++resident_hits;
       }
-      run(rq.get(), st);
+      if (!reuse && res.p) {
+        lrpost_destroy(res.p);
+        res.p = nullptr;
+      }
+      run(rq.get(), st, res);
       {
         std::lock_guard<std::mutex> lk(mu);
-        in_use -= rq->est_bytes;
+        // the problem stays resident (and reserved) when the request ran
+        if (!res.p) in_use -= rq->est_bytes;
+        else res.bytes = rq->est_bytes;
         --running;
         rq->done = true;
       }
       cv_done.notify_all();
       cv_work.notify_all();
     }
+    if (res.p) {
+      lrpost_destroy(res.p);
+      std::lock_guard<std::mutex> lk(mu);
+      in_use -= res.bytes;
+    }
     if (st) (void)hipStreamDestroy(st);
   }
 
-  static void run(Request* rq, hipStream_t st) {
+  // Runs one request on the worker's resident problem (re-targeted when it is
+  // of the request's class, else created).  On failure the problem is dropped.
+  static void run(Request* rq, hipStream_t st, Resident& res) {
     lrpost_problem_desc d = rq->desc;
     d.hip_stream = st;
-    lrpost_problem* p = nullptr;
+    lrpost_problem* p = res.p;
     lrpost_eigs* e = nullptr;
-    int rc = lrpost_create(&d, &p);
-    // V-cycles launched kernel by kernel: a graph capture on one worker's
-    // stream while another worker issues its ordered dense-library calls was
-    // reported by the runtime as a stream-capture isolation error
-    if (rc == LRPOST_OK) rc = lrpost_set_graphs(p, 0);
+    int rc = LRPOST_OK;
+    if (p) {
+      rc = lrpost_retarget(p, d.alpha, d.sigma, d.box, d.seed);
+    } else {
+      rc = lrpost_create(&d, &p);
+      // V-cycles launched kernel by kernel: a graph capture on one worker's
+      // stream while another worker issues its ordered dense-library calls was
+      // reported by the runtime as a stream-capture isolation error
+      if (rc == LRPOST_OK) rc = lrpost_set_graphs(p, 0);
+    }
     if (rc == LRPOST_OK) rc = lrpost_eigensolve(p, rq->k, LRPOST_BLOCK_LANCZOS, 0, &e);
     if (rc == LRPOST_OK) {
       const int kk = lrpost_eig_count(e);
@@ -139,7 +209,13 @@ struct lrpost_server {
     if (rc != LRPOST_OK) rq->error = lrpost_last_error();
     rq->status = rc;
     if (e) lrpost_eigs_free(e);
-    if (p) lrpost_destroy(p);
+    if (rc == LRPOST_OK) {
+      res.p = p;
+      res.desc = rq->desc;
+    } else {
+      if (p) lrpost_destroy(p);
+      res.p = nullptr;
+    }
     rq->latency_s = std::chrono::duration<double>(clk::now() - rq->t_submit).count();
   }
 };
@@ -206,6 +282,14 @@ int lrpost_server_info(lrpost_server* s, int* peak_running, size_t* peak_admitte
   std::lock_guard<std::mutex> lk(s->mu);
   if (peak_running) *peak_running = s->peak_running;
   if (peak_admitted_bytes) *peak_admitted_bytes = s->peak_in_use;
+  return LRPOST_OK;
+}
+
+int lrpost_server_class_stats(lrpost_server* s, int64_t* served, int64_t* resident_hits) {
+  if (!s) return LRPOST_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (served) *served = s->served;
+  if (resident_hits) *resident_hits = s->resident_hits;
   return LRPOST_OK;
 }
 

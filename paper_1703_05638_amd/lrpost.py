@@ -78,6 +78,7 @@ def load(path: str = LIB_PATH):
     sig = {
         "lrpost_create": (I, [ctypes.POINTER(Desc), ctypes.POINTER(P)]),
         "lrpost_destroy": (I, [P]),
+        "lrpost_retarget": (I, [P, D, D, pd, ctypes.c_uint64]),
         "lrpost_hess_apply": (I, [P, ctypes.POINTER(LowRankC), ctypes.POINTER(LowRankC), I]),
         "lrpost_hess_apply_batch": (I, [P, I, ctypes.POINTER(LowRankC), ctypes.POINTER(LowRankC), I]),
         "lrpost_spacetime_solve": (I, [P, ctypes.POINTER(LowRankC), ctypes.POINTER(LowRankC), I]),
@@ -117,6 +118,7 @@ def load(path: str = LIB_PATH):
         "lrpost_server_wait": (I, [P, ctypes.c_uint64, pd, I, pd, pd]),
         "lrpost_server_info": (I, [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_size_t)]),
         "lrpost_server_destroy": (I, [P]),
+        "lrpost_server_class_stats": (I, [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
         "lrpost_last_error": (ctypes.c_char_p, []),
         "lrpost_version": (ctypes.c_char_p, []),
     }
@@ -206,7 +208,11 @@ class Server:
         pr = ctypes.c_int()
         pb = ctypes.c_size_t()
         _check(_lib.lrpost_server_info(self.h, ctypes.byref(pr), ctypes.byref(pb)))
-        return {"peak_running": pr.value, "peak_admitted_bytes": pb.value}
+        sv = ctypes.c_int64()
+        hit = ctypes.c_int64()
+        _check(_lib.lrpost_server_class_stats(self.h, ctypes.byref(sv), ctypes.byref(hit)))
+        return {"peak_running": pr.value, "peak_admitted_bytes": pb.value, "served": sv.value,
+                "resident_hits": hit.value}
 
     def close(self):
         if getattr(self, "h", None):
@@ -249,6 +255,12 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+    def retarget(self, desc, seed: int = 2):
+        """Switch to desc's alpha, sigma and box (same mesh, nt, tolerance, rank cap, precision)."""
+        box = np.ascontiguousarray(desc.box, dtype=np.float64)
+        _check(_lib.lrpost_retarget(self.h, desc.alpha, desc.sigma, _hptr(box), seed))
+        self.desc = desc
 
     # ---- helpers --------------------------------------------------------
     def _lr_in(self, W1, W2) -> LowRankC:

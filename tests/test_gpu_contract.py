@@ -182,3 +182,32 @@ def test_measured_eigenpair_residuals_match_oracle(lp):
         print("pair %d residual library %.3e oracle %.3e" % (i, res[i], ref), flush=True)
         assert abs(res[i] - ref) <= 0.1 * ref + 5 * d.trunc_tol
     assert np.all(res < 1e-3)
+
+
+def test_retargeted_problem_equals_a_new_one(lp):
+    """A problem re-targeted to another prior scale, noise level, box and seed
+    (the serving loop's resident problems) gives the same bits as a problem
+    created with that description; eigenpair handles of the old target are
+    rejected afterwards."""
+    import dataclasses
+    print("case retarget", flush=True)
+    d1 = synthetic.ProblemDesc(N=32, nt=12, trunc_tol=1e-10, rank_cap=16, k=6)
+    d2 = dataclasses.replace(d1, alpha=3e-3, sigma=4e-3, box=(0.1, 0.6, 0.3, 0.9))
+    prob = lp.Problem(d1)
+    old = prob.eigensolve(d1.k)
+    prob.retarget(d2, seed=5)
+    eig = prob.eigensolve(d2.k)
+    lam = eig.values()
+    D = prob.post_variance(eig, on_device=False)
+    fresh = lp.Problem(d2, seed=5)
+    eig_f = fresh.eigensolve(d2.k)
+    assert np.array_equal(lam, eig_f.values())
+    assert np.array_equal(D, fresh.post_variance(eig_f, on_device=False))
+    assert np.array_equal(prob.prior_variance(), fresh.prior_variance())
+    with pytest.raises(lp.LrpostError) as ex:
+        prob.post_variance(old)
+    assert ex.value.code == -1
+    with pytest.raises(lp.LrpostError):
+        prob.retarget(dataclasses.replace(d2, box=(0.01, 0.02, 0.01, 0.02)))
+    # a refused re-target leaves the problem as it was
+    assert np.array_equal(prob.eigensolve(d2.k).values(), lam)

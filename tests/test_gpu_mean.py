@@ -65,10 +65,12 @@ def test_posterior_mean_tiny_workload_matches_golden(lp):
     g = np.load(os.path.join(ROOT, "tests", "golden", "tiny_mean_oracle.npz"))
     d = dataclasses.replace(synthetic.TINY_FP64, trunc_tol=1e-12)
     prob = lp.Problem(d)
-    W1, W2, res = prob.posterior_mean(g["y_obs"], rtol=1e-9, allow_unconverged=True)
+    W1, W2, res = prob.posterior_mean(g["y_obs"], max_vectors=1600, rtol=1e-9, allow_unconverged=True)
     err = _rel_err(W1, W2, g["mean"])
     print("tiny mean rel err %.3e, residual estimate %.3e, rank %d, steps %d" %
           (err, res, W1.shape[0], prob.stats()["lanczos_steps"]), flush=True)
+    # conjugate gradients on G + I, whose spectrum spans 3.5e6 down to 0, gain
+    # accuracy slowly: 800 Krylov vectors leave 1.4e-4, the bound below is for 1600
     assert err < 1e-4
 
 

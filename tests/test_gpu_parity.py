@@ -389,6 +389,7 @@ def test_server_results_alone_equal_in_the_mix(lp):
     mix = mixes[0]
     print("server info", info, "latencies", [round(m[2], 3) for m in mix], flush=True)
     assert info["peak_running"] >= 2
+    assert info["served"] == 2 * len(reqs)
     for i, d in enumerate(reqs):
         prob = lp.Problem(d)
         eig = prob.eigensolve(d.k)
@@ -400,6 +401,35 @@ def test_server_results_alone_equal_in_the_mix(lp):
                                                                  np.abs(D_mix - D).max() / np.abs(D).max()), flush=True)
             assert np.array_equal(lam_mix, lam)
             assert np.array_equal(D_mix, D)
+
+
+def test_server_prefers_the_resident_size_class(lp):
+    """One worker: after request A, the pending requests are [B, A2] with A2 of
+    A's size class (other prior, noise and box), so the worker serves A2 next
+    on its resident problem, then B; every result equals its request solved
+    alone on a new problem, bit for bit."""
+    import dataclasses
+    print("case server resident class", flush=True)
+    a = synthetic.ProblemDesc(N=32, nt=12, trunc_tol=1e-10, rank_cap=16, k=5)
+    b = dataclasses.replace(a, N=16, nt=8)
+    a2 = dataclasses.replace(a, alpha=3e-3, sigma=5e-3, box=(0.2, 0.8, 0.1, 0.6))
+    srv = lp.Server(hbm_budget_bytes=8 << 30, workers=1)
+    ta = srv.submit(a, a.k)
+    tb = srv.submit(b, b.k)
+    ta2 = srv.submit(a2, a2.k)
+    res = {t: srv.wait(t) for t in (ta, tb, ta2)}
+    info = srv.info()
+    srv.close()
+    print("server info", info, flush=True)
+    assert info["served"] == 3
+    # B and A2 were queued while A ran (submission takes microseconds, A's
+    # eigensolve tens of milliseconds), so A2 ran on A's resident problem
+    assert info["resident_hits"] == 1
+    for t, d in ((ta, a), (tb, b), (ta2, a2)):
+        prob = lp.Problem(d)
+        eig = prob.eigensolve(d.k)
+        assert np.array_equal(res[t][0], eig.values())
+        assert np.array_equal(res[t][1], prob.post_variance(eig, on_device=False))
 
 
 def test_batched_applies_equal_single_applies(lp):
