@@ -39,17 +39,24 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 COPY_BYTES = 256 << 20  # calibration copy for the HBM byte counters, each way
-# Multigrid kernels timed with HIP events (kind as in the library's
-# LRPOST_KERNEL_*), their names, and the committed HBM-counter reports.
+# Kernels timed with HIP events (kind as in the library's LRPOST_KERNEL_*):
+# name, description, whether the name takes the precision of the V-cycles
+# (float32 in mixed precision), and the matrix-core peak of the kernel's
+# contraction dtype in TFLOP/s (None: no contraction).
+MFMA_F64_PEAK_TFLOPS = 78.6   # MI355X published dense FP64 matrix throughput
+MFMA_F32_PEAK_TFLOPS = 157.3  # MI355X published dense FP32 matrix throughput
 KERNELS = {
-    0: ("k_cheb", "multigrid Chebyshev smoother step", True),
-    1: ("k_mg_down", "level-fused pre-smoothing + residual + restriction", True),
-    2: ("k_mg_up", "level-fused prolongation + post-smoothing", True),
-    3: ("k_gram_mfma", "float64 matrix-core Gram A^T B, partial products", False),
-    4: ("k_proj_mfma", "float64 matrix-core projection C = beta C + A Q", False),
-    5: ("k_stencil_strip", "Q1 stencil SpMM a K x + b M x (+ c z), all columns per launch", True),
+    0: ("k_cheb", "multigrid Chebyshev smoother step", True, None),
+    1: ("k_mg_down", "level-fused pre-smoothing + residual + restriction", True, None),
+    2: ("k_mg_up", "level-fused prolongation + post-smoothing", True, None),
+    3: ("k_gram_mfma", "float64 matrix-core Gram A^T B, partial products", False, MFMA_F64_PEAK_TFLOPS),
+    4: ("k_proj_mfma", "float64 matrix-core projection C = beta C + A Q", False, MFMA_F64_PEAK_TFLOPS),
+    5: ("k_stencil_strip", "Q1 stencil SpMM a K x + b M x (+ c z), all columns per launch", True, None),
+    6: ("k_gram_f32", "float32 matrix-core Gram A^T B (first Gram-Schmidt sweep), partial products", False,
+        MFMA_F32_PEAK_TFLOPS),
+    7: ("k_proj_grouped_f32", "float32 matrix-core projection (first Gram-Schmidt sweep)", False,
+        MFMA_F32_PEAK_TFLOPS),
 }
-MFMA_F64_PEAK_TFLOPS = 78.6  # MI355X published dense FP64 matrix throughput
 
 
 def traffic_report(kernel, precision, workload):
@@ -320,7 +327,7 @@ def main():
         torch.cuda.empty_cache()
     from paper_1703_05638_amd.profile_summary import read_traffic
 
-    kbase, kdesc, mg_kernel = KERNELS[kind]
+    kbase, kdesc, mg_kernel, _ = KERNELS[kind]
     traffic = read_traffic(traffic_report(kbase, args.precision, workload))
     avg_ms = kern_ms / max(launches, 1)
     bytes_per_launch = kern_bytes / max(launches, 1)
@@ -328,7 +335,8 @@ def main():
     gbs = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if launches else 0.0
     tflops = flops_per_launch / (avg_ms * 1e-3) / 1e12 if launches else 0.0
     # the tighter of the two ceilings bounds the kernel
-    mfma_bound = kern_flops / (MFMA_F64_PEAK_TFLOPS * 1e12) > kern_bytes / (HBM_PEAK_GBS * 1e9)
+    mfma_peak = KERNELS[kind][3]
+    mfma_bound = mfma_peak is not None and kern_flops / (mfma_peak * 1e12) > kern_bytes / (HBM_PEAK_GBS * 1e9)
     if mg_kernel:
         kname = kbase + ("<double>" if args.precision == "fp64" else "<float>")
     else:
@@ -338,8 +346,8 @@ def main():
                               "achieved_TFLOPs": (v[3] / (v[1] * 1e-3) / 1e12) if v[1] > 0 else 0.0}
               for k, v in main_run["prof"].items() if k != kind and v[0] > 0}
     if mfma_bound:
-        roof = {"bound": "mfma", "achieved": tflops, "peak": MFMA_F64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": tflops / MFMA_F64_PEAK_TFLOPS, "achieved_GBs": gbs}
+        roof = {"bound": "mfma", "achieved": tflops, "peak": mfma_peak, "unit": "TFLOP/s",
+                "frac": tflops / mfma_peak, "achieved_GBs": gbs}
     else:
         roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
         if kern_flops > 0:

@@ -288,6 +288,12 @@ int lrpost_set_log(lrpost_problem* p, int level);
  *                                the finest mesh (the operator applies and
  *                                the residuals of the multigrid correction
  *                                cycles): read X (and Z) once, write Y once.
+ *   LRPOST_KERNEL_GRAM32,        the same Gram products and projections on
+ *   LRPOST_KERNEL_PROJ32         the float32 matrix cores (the first
+ *                                Gram-Schmidt sweep of the mixed-precision
+ *                                basis building): the basis operand A is read
+ *                                as float32 (4 bytes per element), the others
+ *                                as for the float64 kinds.
  * lrpost_profile_read synchronizes, returns for one kind the launch count, the
  * summed kernel time in ms, the counted bytes and (if flops is not NULL) the
  * counted floating-point operations since the last read, and resets that
@@ -298,7 +304,9 @@ enum {
   LRPOST_KERNEL_MG_UP = 2,
   LRPOST_KERNEL_GRAM = 3,
   LRPOST_KERNEL_PROJ = 4,
-  LRPOST_KERNEL_STENCIL = 5
+  LRPOST_KERNEL_STENCIL = 5,
+  LRPOST_KERNEL_GRAM32 = 6,
+  LRPOST_KERNEL_PROJ32 = 7
 };
 int lrpost_profile(lrpost_problem* p, int enable);
 int lrpost_profile_read(lrpost_problem* p, int kernel, int64_t* launches, double* total_ms, double* bytes,
@@ -346,6 +354,15 @@ int lrpost_set_apply_batch(lrpost_problem* p, int n);
 int lrpost_set_graphs(lrpost_problem* p, int on);
 int lrpost_graph_info(const lrpost_problem* p, int64_t* captured, int64_t* launches);
 
+/* Device memory kept for reuse: a problem's allocator caches the blocks its
+ * calls free (results stay valid; the cache only speeds up the next call).
+ * lrpost_release_cache waits for the problem's stream, returns every cached
+ * block to the device and stores the bytes released in *released_bytes (if
+ * not NULL).  Call it before allocating large buffers elsewhere on the same
+ * device (the binding does so when a device allocation of its own fails).
+ * Buffers held by live eigenpair handles are not cached and stay valid. */
+int lrpost_release_cache(lrpost_problem* p, uint64_t* released_bytes);
+
 /* ---- building blocks, exported for kernel-level parity tests ----------
  * All pointers are DEVICE memory, float64, column-major with leading
  * dimension nx (the problem's nx). */
@@ -359,6 +376,20 @@ int lrpost_stencil_apply(lrpost_problem* p, int ncols, const double* X, double* 
 int lrpost_mg_solve(lrpost_problem* p, int ncols, const double* B, double* X, const double* coef, int cycles);
 /* C = A^T B  (A: nx x m, B: nx x q, C: host m x q column-major). */
 int lrpost_gram(lrpost_problem* p, int m, const double* A, int q, const double* B, double* C_host);
+/* C = A^T B like lrpost_gram, with A (nx x m) in float32 DEVICE memory and
+ * B (nx x q) float64: the float32 matrix-core kernel of the first
+ * Gram-Schmidt sweep of mixed precision (B rounded to float32 as it is
+ * staged, float32 accumulation within a row chunk, float64 across chunks);
+ * C host, m x q column-major. */
+int lrpost_gram_f32(lrpost_problem* p, int m, const float* A, int q, const double* B, double* C_host);
+/* Mixed precision only: the first of the two Gram-Schmidt sweeps that build
+ * the rational Krylov basis of every space-time solve runs on the float32
+ * matrix cores against a float32 copy of the basis (fp32_first != 0, the
+ * default), or in float64 like the second.  The second sweep is float64
+ * either way; it removes what the first leaves (Sec. 4's re-orthogonalization
+ * done twice). */
+int lrpost_set_sweep_precision(lrpost_problem* p, int fp32_first);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the Gram
  * product of lrpost_gram, C = A^T B, with C in DEVICE memory (m x q,

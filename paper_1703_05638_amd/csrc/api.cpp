@@ -563,7 +563,7 @@ int lrpost_profile_read(lrpost_problem* p, int kernel, int64_t* launches, double
     Problem* P = impl(p);
     PoolScope pool_scope(P->pool);
     if (!launches || !total_ms || !bytes) fail(LRPOST_EINVAL, "null argument");
-    if (kernel < 0 || kernel > LRPOST_KERNEL_STENCIL) fail(LRPOST_EINVAL, "unknown kernel kind");
+    if (kernel < 0 || kernel > LRPOST_KERNEL_PROJ32) fail(LRPOST_EINVAL, "unknown kernel kind");
     P->prof_read(kernel, launches, total_ms, bytes, flops);
   });
 }
@@ -606,6 +606,15 @@ int lrpost_set_graphs(lrpost_problem* p, int on) {
     P->sync();
     P->use_graphs = on != 0;
     if (!P->use_graphs) P->drop_graphs();
+  });
+}
+
+int lrpost_release_cache(lrpost_problem* p, uint64_t* released_bytes) {
+  return guarded([&] {
+    Problem* P = impl(p);
+    P->sync();
+    const size_t b = P->pool->trim();
+    if (released_bytes) *released_bytes = (uint64_t)b;
   });
 }
 
@@ -654,6 +663,30 @@ int lrpost_gram(lrpost_problem* p, int m, const double* A, int q, const double* 
     std::vector<double> C;
     P->gram(m, A, q, B, C);
     if (!C.empty()) std::memcpy(C_host, C.data(), sizeof(double) * C.size());
+  });
+}
+
+int lrpost_set_sweep_precision(lrpost_problem* p, int fp32_first) {
+  return guarded([&] {
+    Problem* P = impl(p);
+    P->sync();
+    P->sweep_f32 = fp32_first != 0;
+  });
+}
+
+// C = A^T B with A in float32 on the float32 matrix cores (the kernel of the
+// first Gram-Schmidt sweep in mixed precision); C to host.
+int lrpost_gram_f32(lrpost_problem* p, int m, const float* A, int q, const double* B, double* C_host) {
+  return guarded([&] {
+    Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
+    if (m < 0 || q < 0 || (m > 0 && q > 0 && (!A || !B || !C_host))) fail(LRPOST_EINVAL, "bad arguments");
+    if (m == 0 || q == 0) return;
+    DevMem Cd;
+    Cd.ensure(sizeof(double) * (size_t)m * q);
+    std::vector<GramGroup> g{GramGroup{nullptr, B, nullptr, Cd.as<double>(), P->nx, P->nx, m, 0, m, q, 0, A}};
+    P->gram_dev_grouped(g);
+    P->to_host(C_host, Cd.as<double>(), (size_t)m * q);
   });
 }
 

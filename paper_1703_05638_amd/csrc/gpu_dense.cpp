@@ -86,20 +86,23 @@ void Pool::release(void* p, size_t bytes) {
   impl_->in_use -= r;
 }
 
-void Pool::trim() {
+size_t Pool::trim() {
   std::vector<void*> drop;
+  size_t bytes = 0;
   {
     std::lock_guard<std::mutex> lk(impl_->mu);
     for (auto& fl : impl_->free_lists) {
       drop.insert(drop.end(), fl.second.begin(), fl.second.end());
       fl.second.clear();
     }
+    bytes = impl_->cached;
     impl_->cached = 0;
   }
   if (!drop.empty()) {
     (void)hipDeviceSynchronize();
     for (void* p : drop) (void)hipFree(p);
   }
+  return bytes;
 }
 
 size_t Pool::bytes_in_use() const { return impl_->in_use; }

@@ -39,7 +39,7 @@ class Pool {
   ~Pool();
   void* alloc(size_t bytes, size_t* got);
   void release(void* p, size_t bytes);
-  void trim();
+  size_t trim();  // frees the cached blocks, returns their bytes
   size_t bytes_in_use() const;
   size_t peak_bytes() const;
 
@@ -231,7 +231,7 @@ class Problem {
     double bytes = 0.0, flops = 0.0;
   };
   bool prof_on = false;
-  std::array<ProfSlot, 6> prof_;
+  std::array<ProfSlot, 8> prof_;
   template <class Launch>
   void timed(int kind, double bytes, Launch&& launch, double flops = 0.0);
   template <typename T>
@@ -267,7 +267,11 @@ class Problem {
   struct StFin {
     int q = 0;
     DevMem Q, Zp, Kt;
+    DevMem Q32;  // float32 copy of Q for the first Gram-Schmidt sweep (mixed precision)
   };
+  // mixed precision: the first Gram-Schmidt sweep of the basis building on
+  // the float32 matrix cores (the second stays float64)
+  bool sweep_f32 = true;
   void st_project_batch(const std::vector<StPrep>& prs, double* Wall, std::vector<StFin>& fins);
   void st_solve_projected(const std::vector<StPrep>& prs, const std::vector<int>& q, std::vector<StFin>& fins);
   void st_truncate(std::vector<StFin>& fins, const std::vector<LowRank*>& Y, bool adjoint);

@@ -57,6 +57,10 @@ struct GramGroup {
   long rpc;    // rows per chunk, set by gram_mfma_partials
   int m, q;
   int nchunk;  // set by gram_mfma_partials
+  // when set, A is read from this float32 copy instead (B still float64) and
+  // the product runs on the float32 matrix cores with float32 accumulation
+  // within a chunk (partial sums across chunks in float64)
+  const float* A32 = nullptr;
 };
 struct GramGroups {
   GramGroup g[kProjGroupMax];
@@ -108,6 +112,9 @@ struct ProjGroup {
   double* C;
   long lda, ldc, nrows;
   int ldq, m, p;
+  // when set, A is read from this float32 copy and A Q runs on the float32
+  // matrix cores (Q rounded to float32); the update of C stays float64
+  const float* A32 = nullptr;
 };
 struct ProjGroups {
   ProjGroup g[kProjGroupMax];

@@ -1155,6 +1155,109 @@ __global__ __launch_bounds__(GTH) void k_gram_mfma(long nrows, GramGroups gs) {
   gram_tile<BM, BQ>(nrows, g.rpc, g.m, g.A, g.lda, g.q, g.B, g.ldb, g.part, blockIdx.x, blockIdx.y, chunk);
 }
 
+// ---------------------------------------------------------------------------
+// The same tiles on the float32 matrix cores (v_mfma_f32_16x16x4f32) for the
+// first Gram-Schmidt sweep of the mixed-precision basis building: A is a
+// float32 copy of the basis, B is float64 and rounded to float32 as it is
+// staged, a chunk accumulates in float32 (the partial products of the chunks
+// are summed in float64).  LDS holds float32, so 32-row stages fit for every
+// tile shape.  Operand lane layout as for the float64 instruction; result
+// element (kF32Row(l, v), l % 16) in slot v.
+// ---------------------------------------------------------------------------
+typedef float gram_f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ int kF32Row(int lane, int v) { return 4 * (lane >> 4) + v; }
+
+template <int BM, int BQ>
+__device__ __forceinline__ void gram_tile_f32(long nrows, long rows_per_chunk, int m, const float* __restrict__ A,
+                                              long lda, int q, const double* __restrict__ B, long ldb,
+                                              double* __restrict__ part, int tm, int tq, int chunk) {
+  constexpr int GM = 64 * BM, GQ = 64 * BQ, GK = 32;
+  constexpr int NC = GM + GQ;
+  constexpr int NU = NC / (GTH / GK);
+  constexpr int NA = GM / (GTH / GK);
+  __shared__ float S[2][NC][GK + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 3, wq = wave >> 2;
+  const long r0 = (long)chunk * rows_per_chunk;
+  const long r1 = min(nrows, r0 + rows_per_chunk);
+  gram_f4 acc[BM][2 * BQ];
+#pragma unroll
+  for (int a = 0; a < BM; ++a)
+#pragma unroll
+    for (int b = 0; b < 2 * BQ; ++b) acc[a][b] = gram_f4{0.f, 0.f, 0.f, 0.f};
+  const int lr = tid & (GK - 1), lc = tid / GK;
+  const long nst = (r1 > r0) ? (r1 - r0 + GK - 1) / GK : 0;
+  const float* __restrict__ At = A + (long)tm * GM * lda;
+  const double* __restrict__ Bt = B + (long)tq * GQ * ldb;
+  const int ma = m - 1 - tm * GM, qb = q - 1 - tq * GQ;
+  unsigned co[NU];
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int c = lc + (GTH / GK) * u;
+    co[u] = u < NA ? (unsigned)min(c, ma) * (unsigned)lda : (unsigned)min(c - GM, qb) * (unsigned)ldb;
+  }
+  float rv[NU];
+  auto fetch = [&](long it) {
+    const long r = r0 + it * GK + lr;
+    const bool rin = r < r1;
+    const long rc = rin ? r : r1 - 1;
+    const float keep = rin ? 1.f : 0.f;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const float v = u < NA ? At[(long)co[u] + rc] : (float)Bt[(long)co[u] + rc];
+      rv[u] = v * keep;
+    }
+  };
+  const int ci = lane & 15, ck = lane >> 4;
+  if (nst > 0) {
+    fetch(0);
+#pragma unroll
+    for (int u = 0; u < NU; ++u) S[0][lc + (GTH / GK) * u][lr] = rv[u];
+  }
+  __syncthreads();
+  for (long it = 0; it < nst; ++it) {
+    const int cb = (int)(it & 1);
+    if (it + 1 < nst) fetch(it + 1);
+#pragma unroll
+    for (int kk = 0; kk < GK; kk += 4) {
+      float bf[2 * BQ];
+#pragma unroll
+      for (int b = 0; b < 2 * BQ; ++b) bf[b] = S[cb][GM + wq * 32 * BQ + 16 * b + ci][kk + ck];
+#pragma unroll
+      for (int a = 0; a < BM; ++a) {
+        const float af = S[cb][wm * 16 * BM + 16 * a + ci][kk + ck];
+#pragma unroll
+        for (int b = 0; b < 2 * BQ; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bf[b], acc[a][b], 0, 0, 0);
+      }
+    }
+    if (it + 1 < nst) {
+#pragma unroll
+      for (int u = 0; u < NU; ++u) S[cb ^ 1][lc + (GTH / GK) * u][lr] = rv[u];
+    }
+    __syncthreads();
+  }
+  double* P = part + (long)chunk * m * q;
+#pragma unroll
+  for (int a = 0; a < BM; ++a)
+#pragma unroll
+    for (int b = 0; b < 2 * BQ; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = tm * GM + wm * 16 * BM + 16 * a + kF32Row(lane, v);
+        const int j = tq * GQ + wq * 32 * BQ + 16 * b + (lane & 15);
+        if (i < m && j < q) P[(long)j * m + i] = (double)acc[a][b][v];
+      }
+}
+
+template <int BM, int BQ>
+__global__ __launch_bounds__(GTH) void k_gram_f32(long nrows, GramGroups gs) {
+  const int gi = blockIdx.z / gs.nchunk_max, chunk = blockIdx.z % gs.nchunk_max;
+  const GramGroup& g = gs.g[gi];
+  if (chunk >= g.nchunk || (int)blockIdx.x * 64 * BM >= g.m || (int)blockIdx.y * 64 * BQ >= g.q) return;
+  gram_tile_f32<BM, BQ>(nrows, g.rpc, g.m, g.A32, g.lda, g.q, g.B, g.ldb, g.part, blockIdx.x, blockIdx.y, chunk);
+}
+
 // tile height 64 BM: the smallest that covers m, at most 192 (the 256-row
 // tile needs 146 registers per lane, which leaves one workgroup per CU; wider
 // products take several tiles); tile width 64 BQ
@@ -1214,6 +1317,22 @@ void gram_mfma_partials(hipStream_t st, long nrows, int count, GramGroup* groups
     // the wide tile only when every product of the launch is wider than 64
     const int bq = gram_bq(qmin), gq = 64 * bq;
     dim3 grd((mmax + gm - 1) / gm, (qmax + gq - 1) / gq, n * cmax);
+    if (gs.g[0].A32) {  // a launch is all float32 or all float64 (the caller groups them)
+      if (bq == 1) {
+        switch (bm) {
+          case 1: hipLaunchKernelGGL((k_gram_f32<1, 1>), grd, dim3(GTH), 0, st, nrows, gs); break;
+          case 2: hipLaunchKernelGGL((k_gram_f32<2, 1>), grd, dim3(GTH), 0, st, nrows, gs); break;
+          default: hipLaunchKernelGGL((k_gram_f32<3, 1>), grd, dim3(GTH), 0, st, nrows, gs);
+        }
+      } else {
+        switch (bm) {
+          case 1: hipLaunchKernelGGL((k_gram_f32<1, 2>), grd, dim3(GTH), 0, st, nrows, gs); break;
+          case 2: hipLaunchKernelGGL((k_gram_f32<2, 2>), grd, dim3(GTH), 0, st, nrows, gs); break;
+          default: hipLaunchKernelGGL((k_gram_f32<3, 2>), grd, dim3(GTH), 0, st, nrows, gs);
+        }
+      }
+      continue;
+    }
     if (bq == 1) {
       switch (bm) {
         case 1: hipLaunchKernelGGL((k_gram_mfma<1, 1>), grd, dim3(GTH), 0, st, nrows, gs); break;
@@ -1497,6 +1616,96 @@ __global__ __launch_bounds__(256, 4) void k_proj_grouped(ProjGroups gs, double a
   proj_tile(g.nrows, g.m, g.A, g.lda, g.Q, g.ldq, g.p, g.Cin, g.C, g.ldc, alpha, beta, row0, col0);
 }
 
+// The projection tile on the float32 matrix cores for the first Gram-Schmidt
+// sweep: A from its float32 copy, Q rounded to float32 as it is staged, A Q
+// accumulated in float32, the update C = beta Cin + alpha (A Q) in float64.
+__device__ __forceinline__ void proj_tile_f32(long nrows, int m, const float* __restrict__ A, long lda,
+                                              const double* __restrict__ Q, int ldq, int p, const double* Cin,
+                                              double* C, long ldc, double alpha, double beta, long row0, int col0) {
+  __shared__ float As[PK][PR + 1];
+  __shared__ float Qs[PK][PC + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1;
+  gram_f4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = gram_f4{0.f, 0.f, 0.f, 0.f};
+  const int ar = tid & 63, ak = tid >> 6;
+  const int qk = tid & 31, qc = tid >> 5;
+  const long grow = row0 + ar;
+  const long growc = grow < nrows ? grow : nrows - 1;
+  float ra[PK / 4], rq[PC / 8];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < PK / 4; ++u) {
+      const int k = k0 + ak + 4 * u;
+      const float v = A[(long)(k < m ? k : m - 1) * lda + growc];
+      ra[u] = v * ((k < m && grow < nrows) ? 1.f : 0.f);
+    }
+    const int kq = k0 + qk;
+    const int kqc = kq < m ? kq : m - 1;
+#pragma unroll
+    for (int u = 0; u < PC / 8; ++u) {
+      const int c = col0 + qc + 8 * u;
+      const float v = (float)Q[(long)(c < p ? c : p - 1) * ldq + kqc];
+      rq[u] = v * ((kq < m && c < p) ? 1.f : 0.f);
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < m; k0 += PK) {
+#pragma unroll
+    for (int u = 0; u < PK / 4; ++u) As[ak + 4 * u][ar] = ra[u];
+#pragma unroll
+    for (int u = 0; u < PC / 8; ++u) Qs[qk][qc + 8 * u] = rq[u];
+    __syncthreads();
+    if (k0 + PK < m) fetch(k0 + PK);
+    const int ci = lane & 15, ck = lane >> 4;
+#pragma unroll
+    for (int kk = 0; kk < PK; kk += 4) {
+      const float q0 = Qs[kk + ck][wc * 32 + ci], q1 = Qs[kk + ck][wc * 32 + 16 + ci];
+      const float a0 = As[kk + ck][wr * 32 + ci], a1 = As[kk + ck][wr * 32 + 16 + ci];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(q0, a0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(q0, a1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(q1, a0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(q1, a1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double old[2][2][4];
+  if (beta != 0.0) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = col0 + wc * 32 + 16 * a + kF32Row(lane, v);
+          const long r = row0 + wr * 32 + 16 * b + (lane & 15);
+          old[a][b][v] = Cin[(long)(j < p ? j : p - 1) * ldc + (r < nrows ? r : nrows - 1)];
+        }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = col0 + wc * 32 + 16 * a + kF32Row(lane, v);
+        const long r = row0 + wr * 32 + 16 * b + (lane & 15);
+        const double t = alpha * (double)acc[a][b][v];
+        if (j < p && r < nrows) C[(long)j * ldc + r] = beta == 0.0 ? t : fma(beta, old[a][b][v], t);
+      }
+}
+
+__global__ __launch_bounds__(256, 4) void k_proj_grouped_f32(ProjGroups gs, double alpha, double beta) {
+  const ProjGroup& g = gs.g[blockIdx.z];
+  const long row0 = (long)blockIdx.x * PR;
+  const int col0 = blockIdx.y * PC;
+  if (row0 >= g.nrows || col0 >= g.p || g.m <= 0) return;
+  proj_tile_f32(g.nrows, g.m, g.A32, g.lda, g.Q, g.ldq, g.p, g.Cin, g.C, g.ldc, alpha, beta, row0, col0);
+}
+
 void proj_grouped(hipStream_t st, int count, const ProjGroup* groups, double alpha, double beta) {
   for (int g0 = 0; g0 < count; g0 += kProjGroupMax) {
     ProjGroups gs{};
@@ -1510,7 +1719,10 @@ void proj_grouped(hipStream_t st, int count, const ProjGroup* groups, double alp
     }
     if (rmax <= 0 || pmax <= 0) continue;
     dim3 grd((rmax + PR - 1) / PR, (pmax + PC - 1) / PC, n);
-    hipLaunchKernelGGL(k_proj_grouped, grd, dim3(256), 0, st, gs, alpha, beta);
+    if (gs.g[0].A32)  // a launch is all float32 or all float64 (the caller groups them)
+      hipLaunchKernelGGL(k_proj_grouped_f32, grd, dim3(256), 0, st, gs, alpha, beta);
+    else
+      hipLaunchKernelGGL(k_proj_grouped, grd, dim3(256), 0, st, gs, alpha, beta);
   }
 }
 

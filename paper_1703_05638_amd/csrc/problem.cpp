@@ -739,20 +739,22 @@ void Problem::gram_dev_grouped(std::vector<GramGroup>& gs) {
   if (off.back() == 0) return;
   gram_part_.ensure(sizeof(double) * off.back());
   for (size_t i = 0; i < gs.size(); ++i) gs[i].part = gram_part_.as<double>() + off[i];
-  for (int cls = 1; cls <= 6; ++cls) {
-    // tile class: height from m (1..3), width from q (64 or 128)
+  for (int cls = 1; cls <= 12; ++cls) {
+    // tile class: height from m (1..3), width from q (64 or 128), float64 or
+    // float32 operands (one kernel per launch)
     std::vector<GramGroup> gc;
     for (const GramGroup& g : gs)
-      if (g.m > 0 && g.q > 0 && gram_bm(g.m) + 3 * (gram_bq(g.q) - 1) == cls) gc.push_back(g);
+      if (g.m > 0 && g.q > 0 && gram_bm(g.m) + 3 * (gram_bq(g.q) - 1) + 6 * (g.A32 ? 1 : 0) == cls) gc.push_back(g);
     for (size_t g0 = 0; g0 < gc.size(); g0 += kProjGroupMax) {
       const int n = (int)std::min<size_t>(kProjGroupMax, gc.size() - g0);
       double bytes = 0.0, flops = 0.0;
       for (int i = 0; i < n; ++i) {
         const GramGroup& g = gc[g0 + i];
-        bytes += sizeof(double) * (double)(g.m + g.q) * nx;
+        bytes += ((g.A32 ? sizeof(float) : sizeof(double)) * (double)g.m + sizeof(double) * (double)g.q) * nx;
         flops += 2.0 * g.m * g.q * (double)nx;
       }
-      timed(LRPOST_KERNEL_GRAM, bytes, [&] { gram_mfma_partials(st, nx, n, gc.data() + g0); }, flops);
+      timed(gc[g0].A32 ? LRPOST_KERNEL_GRAM32 : LRPOST_KERNEL_GRAM, bytes,
+            [&] { gram_mfma_partials(st, nx, n, gc.data() + g0); }, flops);
       sum_partials_grouped(st, n, gc.data() + g0);
     }
   }
@@ -775,16 +777,24 @@ void Problem::proj_dev(int m, const double* A, const double* Q, int ldq, int p, 
 
 // Several projections C_g = beta C_g + alpha A_g Q_g (nx rows), grouped
 // launches credited like proj_dev.
-void Problem::proj_dev_grouped(const std::vector<ProjGroup>& pg, double alpha, double beta) {
-  for (size_t g0 = 0; g0 < pg.size(); g0 += kProjGroupMax) {
-    const int n = (int)std::min<size_t>(kProjGroupMax, pg.size() - g0);
-    double bytes = 0.0, flops = 0.0;
-    for (int i = 0; i < n; ++i) {
-      const ProjGroup& g = pg[g0 + i];
-      bytes += sizeof(double) * (double)(g.m + (beta != 0.0 ? 2 : 1) * g.p) * g.nrows;
-      flops += 2.0 * g.m * g.p * (double)g.nrows;
+void Problem::proj_dev_grouped(const std::vector<ProjGroup>& pg_all, double alpha, double beta) {
+  // float64 and float32-operand products in separate launches
+  for (int f32 = 0; f32 < 2; ++f32) {
+    std::vector<ProjGroup> pg;
+    for (const ProjGroup& g : pg_all)
+      if ((g.A32 != nullptr) == (f32 == 1)) pg.push_back(g);
+    for (size_t g0 = 0; g0 < pg.size(); g0 += kProjGroupMax) {
+      const int n = (int)std::min<size_t>(kProjGroupMax, pg.size() - g0);
+      double bytes = 0.0, flops = 0.0;
+      for (int i = 0; i < n; ++i) {
+        const ProjGroup& g = pg[g0 + i];
+        bytes += ((g.A32 ? sizeof(float) : sizeof(double)) * (double)g.m +
+                  sizeof(double) * (double)((beta != 0.0 ? 2 : 1) * g.p)) * g.nrows;
+        flops += 2.0 * g.m * g.p * (double)g.nrows;
+      }
+      timed(f32 ? LRPOST_KERNEL_PROJ32 : LRPOST_KERNEL_PROJ, bytes,
+            [&] { proj_grouped(st, n, pg.data() + g0, alpha, beta); }, flops);
     }
-    timed(LRPOST_KERNEL_PROJ, bytes, [&] { proj_grouped(st, n, pg.data() + g0, alpha, beta); }, flops);
   }
   LRP_HIP(hipGetLastError());
 }
@@ -1317,6 +1327,7 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
     if (r1 == 0) continue;
     const int qmax = r1 * npol;
     fins[j].Q.ensure(sizeof(double) * (size_t)nx * qmax);
+    if (desc.precision == LRPOST_MIXED && sweep_f32) fins[j].Q32.ensure(sizeof(float) * (size_t)nx * qmax);
     fins[j].Kt.ensure(sizeof(double) * (size_t)qmax * qmax);  // q x q projected tau K, leading dimension qmax
   }
   if (rmax == 0 || !Wall) return;
@@ -1344,14 +1355,21 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
   };
   // the sweep X_j -= Q_j (Q_j^T M X_j) of every source with a basis (M X_j
   // in MW at column mwc[j]); extra Gram products ride along in the launch
+  // (in mixed precision the first sweep reads the float32 copy of Q and runs
+  // on the float32 matrix cores: its coefficients are accurate to about 1e-6
+  // of the block, and the second, float64 sweep removes what it leaves)
+  const bool f32_sweep = desc.precision == LRPOST_MIXED && sweep_f32;
   auto sweep = [&](const std::vector<int>& kc, const std::vector<double*>& X, const std::vector<int>& mwc,
-                   std::vector<GramGroup> gg) {
+                   std::vector<GramGroup> gg, bool first) {
     std::vector<ProjGroup> pg;
     for (int j = 0; j < nb; ++j) {
       if (q[j] == 0 || kc[j] == 0) continue;
       const double* Q = fins[j].Q.as<double>();
-      gg.push_back(gram_g(Q, MW + (size_t)mwc[j] * nx, Cd + coff[j], q[j], kc[j], q[j]));
-      pg.push_back(proj_g(Q, Cd + coff[j], q[j], X[j], q[j], kc[j]));
+      GramGroup g = gram_g(Q, MW + (size_t)mwc[j] * nx, Cd + coff[j], q[j], kc[j], q[j]);
+      ProjGroup pj = proj_g(Q, Cd + coff[j], q[j], X[j], q[j], kc[j]);
+      if (first && f32_sweep) g.A32 = pj.A32 = fins[j].Q32.as<float>();
+      gg.push_back(g);
+      pg.push_back(pj);
     }
     gram_dev_grouped(gg);
     proj_dev_grouped(pg, -1.0, 1.0);
@@ -1413,7 +1431,7 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
       g1.push_back(gram_g(X1[j], MW + (size_t)pre[j] * nx, Gd + slot(j, 1), r1s[j], r1s[j], r1s[j]));
     }
     apply_op(R1, Wj(ip, 0), MW, Mop);
-    sweep(r1s, X1, mw1, g0);  // the raw Gram shares the launch of the sweep's products
+    sweep(r1s, X1, mw1, g0, true);  // the raw Gram shares the launch of the sweep's float64 products
     apply_op(R1, Wj(ip, 0), MW, Mop);
     gram_dev_grouped(g1);
     to_host(Gh.data(), Gd, Gh.size());
@@ -1446,7 +1464,7 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
     for (int j = 0; j < nb; ++j)
       if (k1[j] > 0) g2.push_back(gram_g(X2[j], MW + (size_t)pre2[j] * nx, Gd + slot(j, 0), k1[j], k1[j], k1[j]));
     apply_op(K1, W2, MW, Mop);
-    sweep(k1, X2, mw2, {});
+    sweep(k1, X2, mw2, {}, false);
     apply_op(K1, W2, MW, Mop);
     gram_dev_grouped(g2);
     to_host(Gh.data(), Gd, Gh.size());
@@ -1473,6 +1491,11 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
       gk.push_back(gram_g(Q, KQn, fins[j].Kt.as<double>() + (size_t)q[j] * qmax, q[j] + kcols, kcols, qmax));
     }
     gram_dev_grouped(gk);
+    if (f32_sweep)
+      for (int j = 0; j < nb; ++j)
+        if (k2[j] > 0)
+          d2f(st, (long)nx * k2[j], fins[j].Q.as<double>() + (size_t)q[j] * nx,
+              fins[j].Q32.as<float>() + (size_t)q[j] * nx);
     for (int j = 0; j < nb; ++j) q[j] += k2[j];
   }
   PhaseTimer pt(this, kPhProjSolve);

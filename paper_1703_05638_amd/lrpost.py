@@ -25,6 +25,8 @@ LRPOST_MISFIT, LRPOST_PRECOND = 0, 1
 LRPOST_BLOCK_LANCZOS, LRPOST_RANDOMIZED = 0, 1
 LRPOST_KERNEL_SMOOTHER_STEP, LRPOST_KERNEL_MG_DOWN, LRPOST_KERNEL_MG_UP, LRPOST_KERNEL_GRAM, LRPOST_KERNEL_PROJ = 0, 1, 2, 3, 4
 LRPOST_KERNEL_STENCIL = 5
+LRPOST_KERNEL_GRAM32 = 6
+LRPOST_KERNEL_PROJ32 = 7
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "ENOCONV", -4: "EBREAKDOWN", -5: "EHIP"}
 
 
@@ -98,6 +100,8 @@ def load(path: str = LIB_PATH):
         "lrpost_mg_solve": (I, [P, I, P, P, pd, I]),
         "lrpost_gram": (I, [P, I, P, I, P, pd]),
         "lrpost_gram_noalloc": (I, [P, I, P, I, P, P]),
+        "lrpost_gram_f32": (I, [P, I, P, I, P, pd]),
+        "lrpost_set_sweep_precision": (I, [P, I]),
         "lrpost_truncate": (I, [P, ctypes.POINTER(LowRankC), D, I]),
         "lrpost_set_log": (I, [P, I]),
         "lrpost_obs_count": (I, [P]),
@@ -109,6 +113,7 @@ def load(path: str = LIB_PATH):
         "lrpost_profile_read": (I, [P, I, ctypes.POINTER(ctypes.c_int64), pd, pd, pd]),
         "lrpost_set_mg_fused": (I, [P, I]),
         "lrpost_set_graphs": (I, [P, I]),
+        "lrpost_release_cache": (I, [P, ctypes.POINTER(ctypes.c_uint64)]),
         "lrpost_set_apply_batch": (I, [P, I]),
         "lrpost_set_autotune": (I, [I]),
         "lrpost_autotune_report": (I, [ctypes.c_char_p, ctypes.c_size_t]),
@@ -273,10 +278,25 @@ class Problem:
         x._keep = (W1, W2)
         return x
 
-    def _lr_out(self, cap: int) -> Tuple[LowRankC, object, np.ndarray]:
+    def _device_empty(self, shape, like=None):
+        """A float64 CUDA tensor; when the device is full, the problem's cached
+        blocks are released and the allocation tried once more."""
         torch = _torch()
+
+        def make():
+            if like is not None:
+                return torch.empty_like(like)
+            return torch.empty(shape, dtype=torch.float64, device="cuda")
+
+        try:
+            return make()
+        except torch.OutOfMemoryError:
+            self.release_cache()
+            return make()
+
+    def _lr_out(self, cap: int) -> Tuple[LowRankC, object, np.ndarray]:
         cap = max(int(cap), 1)
-        W1 = torch.empty((cap, self.nx), dtype=torch.float64, device="cuda")
+        W1 = self._device_empty((cap, self.nx))
         W2 = np.zeros((cap, self.nt))
         y = LowRankC(self.nx, self.nt, 0, cap, ctypes.c_void_p(W1.data_ptr()), W2.ctypes.data_as(ctypes.c_void_p))
         return y, W1, W2
@@ -340,6 +360,17 @@ class Problem:
         C = np.zeros((q, m))  # column-major m x q == row-major q x m
         _check(_lib.lrpost_gram(self.h, m, _dptr(A), q, _dptr(B), _hptr(C)))
         return C.T.copy()
+
+    def gram_f32(self, A32, B):
+        """C = A^T B with A (m, nx) float32 CUDA, B (q, nx) float64 CUDA, on the float32 matrix cores."""
+        m, q = A32.shape[0], B.shape[0]
+        C = np.zeros((q, m))
+        _check(_lib.lrpost_gram_f32(self.h, m, _dptr(A32), q, _dptr(B), _hptr(C)))
+        return C.T.copy()
+
+    def set_sweep_precision(self, fp32_first: bool):
+        """Mixed precision: first Gram-Schmidt sweep of the basis building on float32 matrix cores (default)."""
+        _check(_lib.lrpost_set_sweep_precision(self.h, 1 if fp32_first else 0))
 
     def gram_noalloc(self, A, B, C):
         """C (q, m) float64 CUDA, caller-allocated: C^T = A^T B enqueued on the
@@ -425,7 +456,7 @@ class Problem:
         """diag(Gamma_post,k) as an (nt, nx) array (row t = time step t)."""
         torch = _torch()
         if on_device:
-            D = torch.empty((self.nt, self.nx), dtype=torch.float64, device="cuda")
+            D = self._device_empty((self.nt, self.nx))
             _check(_lib.lrpost_post_variance(self.h, eigs.h, _dptr(D), 1))
             return D
         D = np.zeros((self.nt, self.nx))
@@ -441,7 +472,7 @@ class Problem:
             if xi.device.type != "cuda" or xi.dtype != torch.float64 or xi.dim() != 3:
                 raise ValueError("xi must be a CUDA float64 tensor (ns, nt, nx)")
             xi = xi.contiguous()
-            out = torch.empty_like(xi)
+            out = self._device_empty(None, like=xi)
             _check(_lib.lrpost_sample(self.h, eigs.h, xi.shape[0], _dptr(xi), _dptr(out), 1))
             return out
         xi = np.ascontiguousarray(xi, dtype=np.float64)
@@ -483,6 +514,12 @@ class Problem:
     def set_graphs(self, on: bool):
         """V-cycles replayed from captured HIP graphs (default) or launched kernel by kernel."""
         _check(_lib.lrpost_set_graphs(self.h, 1 if on else 0))
+
+    def release_cache(self) -> int:
+        """Return the problem's cached device blocks to the device; bytes released."""
+        b = ctypes.c_uint64()
+        _check(_lib.lrpost_release_cache(self.h, ctypes.byref(b)))
+        return b.value
 
     def graph_info(self):
         """(graphs captured, graph launches) since creation."""

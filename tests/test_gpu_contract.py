@@ -211,3 +211,16 @@ def test_retargeted_problem_equals_a_new_one(lp):
         prob.retarget(dataclasses.replace(d2, box=(0.01, 0.02, 0.01, 0.02)))
     # a refused re-target leaves the problem as it was
     assert np.array_equal(prob.eigensolve(d2.k).values(), lam)
+
+
+@pytest.mark.gpu
+def test_release_cache_keeps_results(lp):
+    """Releasing the allocator's cached blocks between calls changes no bits."""
+    print("case release cache", flush=True)
+    d = synthetic.ProblemDesc(N=32, nt=12, trunc_tol=1e-10, rank_cap=16, k=6)
+    prob = lp.Problem(d)
+    lam = prob.eigensolve(d.k).values()
+    released = prob.release_cache()
+    assert released > 0
+    assert prob.release_cache() == 0
+    assert np.array_equal(prob.eigensolve(d.k).values(), lam)

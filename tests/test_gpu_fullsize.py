@@ -139,3 +139,22 @@ def test_full_observation_spectrum_at_bench_size(lp, precision):
     print("full observation top-%d max rel err %.3e (lambda_1 %.6e, lambda_50 %.6e)" %
           (d.k, rel.max(), ref[0], ref[-1]), prob.stats(), flush=True)
     assert rel.max() < 1e-5
+
+
+@pytest.mark.parametrize("m,q", [(37, 12), (100, 64), (180, 70), (250, 135)])
+def test_gram_f32_at_bench_size(lp, m, q):
+    """The float32 matrix-core Gram of the first Gram-Schmidt sweep (A float32,
+    B float64 rounded to float32 as staged, float32 accumulation within a
+    chunk): against the float64 product of the same float32 A, to float32
+    accuracy (relative to the largest entry)."""
+    import torch
+    print("case gram f32 nx=65025 m=%d q=%d" % (m, q), flush=True)
+    prob = lp.Problem(synthetic.ProblemDesc(N=256, nt=4, trunc_tol=1e-6, rank_cap=8))
+    rng = np.random.default_rng(3 * m + q)
+    A = rng.standard_normal((m, prob.nx)).astype(np.float32)
+    B = rng.standard_normal((q, prob.nx))
+    C = prob.gram_f32(torch.tensor(A, device="cuda"), _dev(B))
+    ref = A.astype(np.float64) @ B.T
+    err = np.abs(C - ref).max() / np.abs(ref).max()
+    print("gram f32 max rel err %.3e" % err, flush=True)
+    assert err <= 2e-5

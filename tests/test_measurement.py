@@ -53,7 +53,8 @@ def test_bench_kernel_table_matches_the_library_kinds():
 
     kinds = {lp.LRPOST_KERNEL_SMOOTHER_STEP: "k_cheb", lp.LRPOST_KERNEL_MG_DOWN: "k_mg_down",
              lp.LRPOST_KERNEL_MG_UP: "k_mg_up", lp.LRPOST_KERNEL_GRAM: "k_gram_mfma",
-             lp.LRPOST_KERNEL_PROJ: "k_proj_mfma", lp.LRPOST_KERNEL_STENCIL: "k_stencil_strip"}
+             lp.LRPOST_KERNEL_PROJ: "k_proj_mfma", lp.LRPOST_KERNEL_STENCIL: "k_stencil_strip",
+             lp.LRPOST_KERNEL_GRAM32: "k_gram_f32", lp.LRPOST_KERNEL_PROJ32: "k_proj_grouped_f32"}
     assert {k: v[0] for k, v in bench.KERNELS.items()} == kinds
     # the dominant kernel's committed traffic reports exist under the names the bench looks for
     for name in ("k_gram_mfma", "k_mg_up", "k_mg_down"):
