@@ -197,7 +197,8 @@ def randomized(args):
                    "trunc_tol": desc.trunc_tol, "rank_cap": desc.rank_cap, "precision": args.precision},
         "seconds": dt, "applies": applies, "lambda_1_to_3": [float(x) for x in lam[:3]],
         "lambda_64": float(lam[-1]), "max_rel_ritz_residual_estimate": st["ritz_resid"],
-        "spacetime_check": {"enriched_batches": st["st_enrichments"], "unresolved_batches": st["st_unresolved"]},
+        "spacetime_check": {"enriched_batches": st["st_enrichments"], "unresolved_batches": st["st_unresolved"],
+                            "direct_second_grams": st["st_direct_grams"]},
     }
     if args.precision == "mixed" and not args.no_fp64_reference:
         _, dt64, _, applies64, lam64 = solve("fp64")
@@ -275,7 +276,8 @@ def main():
             print("%s warmup step %d done in %.1f s" % (precision, w, time.perf_counter() - t0), file=sys.stderr,
                   flush=True)
         torch.cuda.synchronize()
-        applies0 = prob.stats()["applies"]
+        st0 = prob.stats()
+        applies0 = st0["applies"]
         if profile:
             prob.profile(True)
         step_ms = []
@@ -295,8 +297,12 @@ def main():
         elapsed = time.perf_counter() - t_all
         prof = {k: prob.profile_read(k) for k in KERNELS} if profile else {}
         prob.profile(False)
-        res = {"desc": desc, "applies": prob.stats()["applies"] - applies0, "elapsed": elapsed, "step_ms": step_ms,
-               "lam": lam, "D": D_last, "prof": prof, "stats": prob.stats()}
+        st1 = prob.stats()
+        res = {"desc": desc, "applies": st1["applies"] - applies0, "elapsed": elapsed, "step_ms": step_ms,
+               "lam": lam, "D": D_last, "prof": prof, "stats": st1,
+               "pool": {"device_allocations": st1["pool_mallocs"] - st0["pool_mallocs"],
+                        "cache_releases": st1["pool_trims"] - st0["pool_trims"],
+                        "host_seconds": st1["pool_malloc_s"] - st0["pool_malloc_s"]}}
         del prob
         return res
 
@@ -376,7 +382,9 @@ def main():
         "ritz_values_1_to_3": [float(x) for x in lam[:3]],
         "ritz_resid_estimate": st["ritz_resid"],
         "spacetime_check": {"last_resid": st["last_st_resid"], "last_precond_resid": st["last_st_presid"],
-                            "enriched_batches": st["st_enrichments"], "unresolved_batches": st["st_unresolved"]},
+                            "enriched_batches": st["st_enrichments"], "unresolved_batches": st["st_unresolved"],
+                            "direct_second_grams": st["st_direct_grams"]},
+        "device_pool_in_timed_steps": main_run["pool"],
         "roofline": dict({"kernel": "%s (%s)" % (kname, kdesc)}, **roof,
                          **{"traffic": traffic, "launches": launches, "avg_launch_us": avg_ms * 1e3,
                             "bytes_per_launch": bytes_per_launch, "flops_per_launch": flops_per_launch,

@@ -102,7 +102,8 @@ typedef struct {
   int32_t lanczos_steps;  /* block steps of the last eigensolve */
   int32_t st_enrichments; /* space-time solve batches that needed the enriched pole set */
   int32_t st_unresolved;  /* of those, batches still above the threshold after enrichment */
-  int32_t reserved;
+  int32_t st_direct_grams; /* pole blocks (per source) whose swept block needed its own Gram
+                             in the second orthogonalization sweep (see the space-time solve) */
   double last_tail;       /* relative tail dropped by the last truncation */
   double last_st_resid;   /* largest relative residual ||tau K Y + M Y C^T - F||_F / ||F||_F
                              (C for the adjoint) of the solutions of the last space-time
@@ -118,6 +119,9 @@ typedef struct {
                              the recurrence, the randomized solver from the Grams of its
                              two passes.  Neither includes the truncation of the Ritz
                              vectors after the loop; lrpost_eig_residuals measures that */
+  int64_t pool_mallocs;   /* device allocations the problem's caching pool made since creation */
+  int64_t pool_trims;     /* times the pool released its cached blocks to satisfy one */
+  double pool_malloc_s;   /* host seconds spent in those allocations and releases */
 } lrpost_stats;
 
 /* Create a problem: validates the description, builds the multigrid

@@ -124,6 +124,7 @@ int lrpost_get_stats(const lrpost_problem* p, lrpost_stats* s) {
   return guarded([&] {
     if (!p || !p->impl || !s) fail(LRPOST_EINVAL, "null argument");
     *s = p->impl->stats;
+    p->impl->pool->counters(&s->pool_mallocs, &s->pool_trims, &s->pool_malloc_s);
   });
 }
 
@@ -613,6 +614,7 @@ int lrpost_release_cache(lrpost_problem* p, uint64_t* released_bytes) {
   return guarded([&] {
     Problem* P = impl(p);
     P->sync();
+    P->fin_keep_.clear();  // the kept basis buffers go back to the pool first
     const size_t b = P->pool->trim();
     if (released_bytes) *released_bytes = (uint64_t)b;
   });

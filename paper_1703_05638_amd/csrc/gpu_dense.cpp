@@ -6,6 +6,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <chrono>
 #include <map>
 #include <cstring>
 #include <mutex>
@@ -25,6 +26,8 @@ struct Pool::Impl {
   std::mutex mu;
   std::map<size_t, std::vector<void*>> free_lists;
   size_t cached = 0, in_use = 0, peak = 0;
+  int64_t mallocs = 0, trims = 0;
+  double malloc_s = 0.0;
 };
 
 Pool::Pool() : impl_(new Impl) {}
@@ -59,18 +62,25 @@ void* Pool::alloc(size_t bytes, size_t* got) {
     }
   }
   void* p = nullptr;
+  const auto t0 = std::chrono::steady_clock::now();
+  bool trimmed = false;
   hipError_t e = hipMalloc(&p, r);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     // release cached blocks and retry once
     trim();
+    trimmed = true;
     e = hipMalloc(&p, r);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       fail(LRPOST_ENOMEM, "device allocation of " + std::to_string(r) + " bytes failed");
     }
   }
+  const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   std::lock_guard<std::mutex> lk(impl_->mu);
+  ++impl_->mallocs;
+  impl_->trims += trimmed ? 1 : 0;
+  impl_->malloc_s += dt;
   impl_->in_use += r;
   impl_->peak = std::max(impl_->peak, impl_->in_use);
   *got = r;
@@ -106,6 +116,12 @@ size_t Pool::trim() {
 }
 
 size_t Pool::bytes_in_use() const { return impl_->in_use; }
+void Pool::counters(int64_t* mallocs, int64_t* trims, double* seconds) const {
+  std::lock_guard<std::mutex> lk(impl_->mu);
+  *mallocs = impl_->mallocs;
+  *trims = impl_->trims;
+  *seconds = impl_->malloc_s;
+}
 size_t Pool::peak_bytes() const { return impl_->peak; }
 
 // ---- rocBLAS / rocSOLVER ---------------------------------------------------

@@ -42,6 +42,9 @@ class Pool {
   size_t trim();  // frees the cached blocks, returns their bytes
   size_t bytes_in_use() const;
   size_t peak_bytes() const;
+  // device allocations made, cache releases forced by a failed allocation,
+  // and the host seconds spent in both
+  void counters(int64_t* mallocs, int64_t* trims, double* seconds) const;
 
  private:
   struct Impl;
@@ -272,6 +275,7 @@ class Problem {
   // mixed precision: the first Gram-Schmidt sweep of the basis building on
   // the float32 matrix cores (the second stays float64)
   bool sweep_f32 = true;
+  std::vector<StFin> fin_keep_;  // basis buffers kept between batches (st_solve_pass)
   void st_project_batch(const std::vector<StPrep>& prs, double* Wall, std::vector<StFin>& fins);
   void st_solve_projected(const std::vector<StPrep>& prs, const std::vector<int>& q, std::vector<StFin>& fins);
   void st_truncate(std::vector<StFin>& fins, const std::vector<LowRank*>& Y, bool adjoint);

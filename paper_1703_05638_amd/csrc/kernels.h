@@ -61,7 +61,21 @@ struct GramGroup {
   // the product runs on the float32 matrix cores with float32 accumulation
   // within a chunk (partial sums across chunks in float64)
   const float* A32 = nullptr;
+  // when m2 > 0, the last m2 of the m columns of A are read from A2 (leading
+  // dimension lda): C = [A | A2]^T B, rows m - m2 .. m - 1 from A2 (float64
+  // products only)
+  const double* A2 = nullptr;
+  int m2 = 0;
 };
+// column sums of squares out_g[c] = sum_i C_g[i + c ld_g]^2 (i < rows_g,
+// c < cols_g) for several small matrices in one launch, in a fixed order
+struct ColGroup {
+  const double* C;
+  double* out;
+  long ld;
+  int rows, cols;
+};
+void col_sqnorms(hipStream_t st, int count, const ColGroup* groups);
 struct GramGroups {
   GramGroup g[kProjGroupMax];
   int nchunk_max;
@@ -115,6 +129,9 @@ struct ProjGroup {
   // when set, A is read from this float32 copy and A Q runs on the float32
   // matrix cores (Q rounded to float32); the update of C stays float64
   const float* A32 = nullptr;
+  // when set (float64 products), C is also written rounded to float32 here
+  // (leading dimension ldc)
+  float* C32 = nullptr;
 };
 struct ProjGroups {
   ProjGroup g[kProjGroupMax];

@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <map>
 #include <mutex>
+#include <stdexcept>
 #include <string>
 #include <tuple>
 
@@ -473,34 +474,38 @@ template void mg_prolong_add<float>(hipStream_t, int, int, const float*, long, c
 // ---------------------------------------------------------------------------
 // Level-fused multigrid passes for meshes of up to 1023 nodes per side.
 //
-// A workgroup of TW >= n + 1 threads owns a strip of S consecutive mesh rows
-// of one column over the full row width; thread i holds mesh column i of the
-// strip plus a halo of rows above and below in registers, so vertical
-// neighbours are register reads and only the left and right neighbours pass
-// through LDS (one exchange per smoother step).  Each Chebyshev step of the
-// smoother is recomputed on a halo one row narrower than the step before, so
-// that the strip needs no data from other strips between steps.  Per node and
-// step the arithmetic is the per-step kernels' (same operands, same order).
+// A workgroup owns a strip of S consecutive mesh rows of one column, over the
+// full row width (TW >= n + 1 threads, thread i holding mesh column i) or over
+// a tile of TW - 2H columns plus H halo columns on each side (thread i holding
+// mesh column c0 + i).  Each thread keeps its mesh column of the strip plus a
+// halo of rows above and below in registers, so vertical neighbours are
+// register reads and only the left and right neighbours pass through LDS (one
+// exchange per smoother step).  Each Chebyshev step of the smoother is
+// recomputed on a halo one row (and, in tiles, one column) narrower than the
+// step before, so that the strip needs no data from other workgroups between
+// steps.  Per node and step the arithmetic is the per-step kernels' (same
+// operands, same order), so tiles and whole rows give the same bits.
 //
 //   down:  x = NU smoother steps from zero for A x = b, and the coarse
 //          right-hand side bc = P^T (b - A x); reads b, writes x and bc.
 //   up:    t = xi + P e (bilinear prolongation of the coarse correction e),
 //          then NU smoother steps from t; reads xi, e, b, writes x.
 //
-// Workgroups are numbered so that consecutive strips of a column share an
-// XCD (hardware dispatch goes round robin over the 8 XCDs), keeping the halo
-// rows that neighbouring strips both read in one L2.
+// Workgroups are numbered so that consecutive tiles and strips of a column
+// share an XCD (hardware dispatch goes round robin over the 8 XCDs), keeping
+// the halo rows and columns that neighbouring workgroups both read in one L2.
 // ---------------------------------------------------------------------------
 
 // One smoother step on rows [lo, hi] of the register column:
 //   out = cur + al (cur - prv) + be (b - A cur),
 // with cur's rows [lo - 1, hi + 1] exchanged through LDS first.  Rows outside
 // the mesh (jb + r outside [0, n)) are kept at zero (INNER strips have every
-// row inside the mesh); so are columns i >= n, whose cur and prv are zero and
-// whose coefficients are taken as zero.
+// row inside the mesh); so are the lanes whose mesh column lies outside it
+// (inm false), whose cur and prv are zero and whose coefficients are taken as
+// zero.  Lane i sits at LDS column i + 1; columns 0 and TW + 1 hold zeros.
 template <typename T, int TW, int R, int lo, int hi, bool INNER>
-__device__ inline void strip_step(const T (&cur)[R], const T (&prv)[R], T (&out)[R], const T (&b)[R], T* xs, int i,
-                                  int n, int jb, T wc, T we, T wk, T al, T be) {
+__device__ __forceinline__ void strip_step(const T (&cur)[R], const T (&prv)[R], T (&out)[R], const T (&b)[R], T* xs, int i,
+                                  bool inm, int n, int jb, T wc, T we, T wk, T al, T be) {
   // only the explicit fmad() calls fuse: the per-step and level-fused
   // kernels then round every node identically
 #pragma clang fp contract(off)
@@ -514,8 +519,7 @@ __device__ inline void strip_step(const T (&cur)[R], const T (&prv)[R], T (&out)
 #pragma unroll
   for (int r = 0; r < R; ++r)
     if (r >= lo - 1 && r <= hi + 1) hs[r] = xs[r * LP + i] + xs[r * LP + i + 2];
-  const bool act = i < n;
-  const T alm = act ? al : T(0), bem = act ? be : T(0);
+  const T alm = inm ? al : T(0), bem = inm ? be : T(0);
 #pragma unroll
   for (int r = 0; r < R; ++r)
     if (r >= lo && r <= hi) {
@@ -527,15 +531,16 @@ __device__ inline void strip_step(const T (&cur)[R], const T (&prv)[R], T (&out)
     }
 }
 
-// Row r of a strip's register column (mesh row jb + r, column i) of a
-// column-major n x n block: every load is unconditional, with the row index
-// clamped into the mesh, so that all of them are in flight at once; values
-// outside the mesh are zeroed after (in columns i >= n only when LANES).
+// Row r of a strip's register column (mesh row jb + r, mesh column c) of a
+// column-major n x n block: every load is unconditional, with the row and
+// column indices clamped into the mesh, so that all of them are in flight at
+// once; values outside the mesh are zeroed after (in columns outside 0..n-1
+// only when LANES).
 template <typename T, int R, bool INNER, bool LANES>
-__device__ inline void load_rows(const T* __restrict__ a, int n, int i, int jb, T (&v)[R], int r0 = 0,
+__device__ __forceinline__ void load_rows(const T* __restrict__ a, int n, int c, int jb, T (&v)[R], int r0 = 0,
                                  int r1 = R) {
 #pragma clang fp contract(off)
-  const unsigned ic = i < n ? i : n - 1;
+  const unsigned ic = c < 0 ? 0 : (c < n ? c : n - 1);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     if (r < r0 || r >= r1) continue;
@@ -547,43 +552,46 @@ __device__ inline void load_rows(const T* __restrict__ a, int n, int i, int jb, 
     } else {
       // scaled by 1 or 0 rather than selected: a select of a loaded value is
       // compiled into a branch around the load, which serializes the loads
-      const bool keep = (!LANES || i < n) && (INNER || (j >= 0 && j < n));
+      const bool keep = (!LANES || (c >= 0 && c < n)) && (INNER || (j >= 0 && j < n));
       v[r] = x * (keep ? T(1) : T(0));
     }
   }
 }
 
 template <typename T, int TW, int S, int NU, bool INNER>
-__device__ inline void mg_down_body(T* xs, int n, int col, int strip, const T* __restrict__ B, long ld,
-                                    T* __restrict__ Xo, T* __restrict__ Bc, long ldc, const double* __restrict__ P) {
+__device__ __forceinline__ void mg_down_body(T* xs, int n, int col, int strip, int c0, int own_lo, int own_hi, int I0, int ncw,
+                                    const T* __restrict__ B, long ld, T* __restrict__ Xo, T* __restrict__ Bc,
+                                    long ldc, const double* __restrict__ P) {
   // only the explicit fmad() calls fuse: the per-step and level-fused
   // kernels then round every node identically
 #pragma clang fp contract(off)
   constexpr int R = S + 2 * NU + 1;  // rows j0 - NU .. j0 + S + NU
   constexpr int LP = TW + 2;
-  const int i = threadIdx.x;
+  const int i = threadIdx.x, c = c0 + i;
+  const bool inm = c >= 0 && c < n;
   const int j0 = strip * S, jb = j0 - NU;
   const double* pc = P + (long)col * kMgStride;
   const T wc = (T)pc[0], we = (T)pc[1], wk = (T)pc[2];
   T bv[R], x0[R], x1[R];
-  load_rows<T, R, INNER, false>(B + (long)col * ld, n, i, jb, bv);
-  // step 0 from zero: x_1 = be_0 b (zero in columns i >= n)
-  const T be0 = i < n ? (T)pc[5] : T(0);
+  load_rows<T, R, INNER, false>(B + (long)col * ld, n, c, jb, bv);
+  // step 0 from zero: x_1 = be_0 b (zero outside the mesh)
+  const T be0 = inm ? (T)pc[5] : T(0);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     x1[r] = be0 * bv[r];
     x0[r] = T(0);
   }
   // step s (1, 2) computes rows [s, R-1-s]
-  strip_step<T, TW, R, 1, R - 2, INNER>(x1, x0, x0, bv, xs, i, n, jb, wc, we, wk, (T)pc[6], (T)pc[7]);
-  strip_step<T, TW, R, 2, R - 3, INNER>(x0, x1, x1, bv, xs, i, n, jb, wc, we, wk, (T)pc[8], (T)pc[9]);
+  strip_step<T, TW, R, 1, R - 2, INNER>(x1, x0, x0, bv, xs, i, inm, n, jb, wc, we, wk, (T)pc[6], (T)pc[7]);
+  strip_step<T, TW, R, 2, R - 3, INNER>(x0, x1, x1, bv, xs, i, inm, n, jb, wc, we, wk, (T)pc[8], (T)pc[9]);
   const T(&x)[R] = x1;
-  // owned rows
+  // owned rows of the owned mesh columns
   T* xo = Xo + (long)col * ld;
+  const bool own = i >= own_lo && i < own_hi && c < n;
 #pragma unroll
   for (int r = NU; r < NU + S; ++r) {
     const int j = jb + r;
-    if (i < n && (INNER || j < n)) (xo + (unsigned)(j * n))[(unsigned)i] = x[r];
+    if (own && (INNER || j < n)) (xo + (unsigned)(j * n))[(unsigned)c] = x[r];
   }
   // residual on rows j0 .. j0 + S (local r = NU .. NU + S), then restriction
   const int nc = (n - 1) / 2;
@@ -604,64 +612,101 @@ __device__ inline void mg_down_body(T* xs, int n, int col, int strip, const T* _
       res[r] = v;
     }
   __syncthreads();
-  // (the restriction reads columns 0 .. n-1 only)
 #pragma unroll
   for (int r = 0; r < R; ++r)
     if (r >= NU && r <= NU + S) xs[(r - NU) * LP + i + 1] = res[r];
   __syncthreads();
+  // coarse nodes I0 .. I0 + ncw - 1 of coarse rows J0 .. J0 + S/2 - 1: the
+  // fine centre 2I + 1 and its neighbours are mesh columns inside
+  // [c0 + own_lo, c0 + own_hi], where the residual is exact
   const int J0 = j0 / 2;
   T* bc = Bc + (long)col * ldc;
-  for (int p = i; p < (S / 2) * nc; p += TW) {
-    const int Jl = p / nc, I = p - Jl * nc;
+  for (int p = i; p < (S / 2) * ncw; p += TW) {
+    const int Jl = p / ncw, I = I0 + (p - Jl * ncw);
     if (J0 + Jl >= nc) break;
-    const T* rs = xs + (2 * Jl + 1) * LP + 2 * I + 2;  // fine node (2I+1, 2J+1)
+    if (I >= nc) continue;
+    const T* rs = xs + (2 * Jl + 1) * LP + (2 * I + 1 - c0) + 1;  // fine node (2I+1, 2J+1)
     const T acc = rs[0] + T(0.5) * ((rs[-1] + rs[1]) + (rs[-LP] + rs[LP])) +
                   T(0.25) * ((rs[-LP - 1] + rs[-LP + 1]) + (rs[LP - 1] + rs[LP + 1]));
     bc[(long)(J0 + Jl) * nc + I] = acc;
   }
 }
 
-template <typename T, int TW, int S, int NU>
-__global__ __launch_bounds__(TW) void k_mg_down(int n, int nstrip, const T* __restrict__ B, long ld,
+// Halo columns of the tiled passes: the down pass needs its smoothed iterate
+// one column beyond the residual it restricts, which needs one column beyond
+// the owned coarse nodes' fine neighbours (2 steps + 1 + 1); the up pass its
+// three smoother steps.
+constexpr int kDownHalo = 4, kUpHalo = 3;
+
+// Workgroup -> (strip, tile, column): the tiles of a strip, then the strips,
+// then the columns, in XCD-grouped order (strip_of).
+__device__ inline void tile_of(int nstrip, int ntile, int& strip, int& tile, int& col) {
+  int st;
+  strip_of(nstrip * ntile, st, col);
+  strip = st / ntile;
+  tile = st - strip * ntile;
+}
+
+// TILED false: one workgroup covers a whole mesh row (TW >= n + 1); true:
+// tiles of TW - 2 H owned mesh columns with H halo columns each side.
+// at least four waves per SIMD in float32 (at most 128 registers per lane;
+// three in float64, whose strips need more): several workgroups per compute
+// unit overlap one's loads with another's smoothing
+template <typename T>
+constexpr int mg_min_waves() {
+  return sizeof(T) == 4 ? 4 : 3;
+}
+
+template <typename T, int TW, int S, int NU, bool TILED>
+__global__ __launch_bounds__(TW, mg_min_waves<T>()) void k_mg_down(int n, int nstrip, int ntile, const T* __restrict__ B, long ld,
                                                 T* __restrict__ Xo, T* __restrict__ Bc, long ldc,
                                                 const double* __restrict__ P) {
   static_assert(NU == 3, "three smoother steps");
   constexpr int R = S + 2 * NU + 1;
   constexpr int LP = TW + 2;
+  constexpr int H = TILED ? kDownHalo : 0, W = TW - 2 * H;
+  static_assert(W % 2 == 0, "owned tile width must be even (coarse nodes align with tiles)");
   __shared__ T xs[R * LP];
-  int strip, col;
-  strip_of(nstrip, strip, col);
+  int strip, tile, col;
+  tile_of(nstrip, ntile, strip, tile, col);
   for (int r = threadIdx.x; r < R; r += TW) {
     xs[r * LP] = T(0);
     xs[r * LP + TW + 1] = T(0);
   }
+  const int c0 = tile * W - H;
+  const int I0 = TILED ? tile * (W / 2) : 0, ncw = TILED ? W / 2 : (n - 1) / 2;
   const int jb = strip * S - NU;
-  if (jb >= 0 && jb + R <= n) mg_down_body<T, TW, S, NU, true>(xs, n, col, strip, B, ld, Xo, Bc, ldc, P);
-  else mg_down_body<T, TW, S, NU, false>(xs, n, col, strip, B, ld, Xo, Bc, ldc, P);
+  if (jb >= 0 && jb + R <= n)
+    mg_down_body<T, TW, S, NU, true>(xs, n, col, strip, c0, H, H + W, I0, ncw, B, ld, Xo, Bc, ldc, P);
+  else
+    mg_down_body<T, TW, S, NU, false>(xs, n, col, strip, c0, H, H + W, I0, ncw, B, ld, Xo, Bc, ldc, P);
 }
 
 template <typename T, int TW, int S, int NU, bool INNER, bool ACC>
-__device__ inline void mg_up_body(T* xs, int n, int col, int strip, const T* __restrict__ Xi,
-                                  const T* __restrict__ E, long ldc, const T* __restrict__ B, long ld,
-                                  T* __restrict__ Xo, const double* __restrict__ P) {
+__device__ __forceinline__ void mg_up_body(T* xs, int n, int col, int strip, int c0, int own_lo, int own_hi,
+                                  const T* __restrict__ Xi, const T* __restrict__ E, long ldc,
+                                  const T* __restrict__ B, long ld, T* __restrict__ Xo,
+                                  const double* __restrict__ P) {
   // only the explicit fmad() calls fuse: the per-step and level-fused
   // kernels then round every node identically
 #pragma clang fp contract(off)
   constexpr int R = S + 2 * NU;  // rows j0 - NU .. j0 + S + NU - 1
   constexpr int NCR = R / 2 + 1;  // coarse rows j0/2 - 2 + q, q < NCR
-  const int i = threadIdx.x;
+  const int i = threadIdx.x, c = c0 + i;
+  const bool inm = c >= 0 && c < n;
   const int j0 = strip * S, jb = j0 - NU;
   const int nc = (n - 1) / 2;
   const double* pc = P + (long)col * kMgStride;
   const T wc = (T)pc[0], we = (T)pc[1], wk = (T)pc[2];
   const T* e = E + (long)col * ldc;
-  // coarse columns feeding fine column i: odd i sits on coarse (i-1)/2; even i
-  // lies between i/2 - 1 and i/2
-  const bool io = i & 1;
-  const int ca = io ? (i - 1) >> 1 : (i >> 1) - 1, cb = i >> 1;
+  // coarse columns feeding fine column c: odd c sits on coarse (c-1)/2; even c
+  // lies between c/2 - 1 and c/2 (lanes outside the mesh read clamped
+  // addresses and are zeroed below)
+  const bool io = c & 1;
+  const int ca = io ? (c - 1) >> 1 : (c >> 1) - 1, cb = c >> 1;
   const int J0 = j0 / 2 - 2;  // j0 even, jb = j0 - 3 odd: row r is odd when r is even
-  const bool oka = ca >= 0 && ca < nc, okb = !io && cb < nc;
-  const unsigned cac = ca < 0 ? 0 : (ca >= nc ? nc - 1 : ca), cbc = cb >= nc ? nc - 1 : cb;
+  const bool oka = ca >= 0 && ca < nc, okb = !io && cb >= 0 && cb < nc;
+  const unsigned cac = ca < 0 ? 0 : (ca >= nc ? nc - 1 : ca), cbc = cb < 0 ? 0 : (cb >= nc ? nc - 1 : cb);
   T ea[NCR], eb[NCR];
 #pragma unroll
   for (int q = 0; q < NCR; ++q) {
@@ -674,8 +719,8 @@ __device__ inline void mg_up_body(T* xs, int n, int col, int strip, const T* __r
     eb[q] = vb * ((okj && okb) ? T(1) : T(0));
   }
   T bv[R], x0[R], x1[R];
-  load_rows<T, R, INNER, true>(Xi + (long)col * ld, n, i, jb, x0);
-  load_rows<T, R, INNER, false>(B + (long)col * ld, n, i, jb, bv, 1, R - 1);
+  load_rows<T, R, INNER, true>(Xi + (long)col * ld, n, c, jb, x0);
+  load_rows<T, R, INNER, false>(B + (long)col * ld, n, c, jb, bv, 1, R - 1);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     T v;
@@ -687,19 +732,20 @@ __device__ inline void mg_up_body(T* xs, int n, int col, int strip, const T* __r
       v = io ? T(0.5) * (ea[q] + ea[q + 1]) : T(0.25) * (ea[q] + eb[q] + ea[q + 1] + eb[q + 1]);
     }
     const int j = jb + r;
-    x0[r] = (i < n && (INNER || (j >= 0 && j < n))) ? x0[r] + v : T(0);
+    x0[r] = (inm && (INNER || (j >= 0 && j < n))) ? x0[r] + v : T(0);
     x1[r] = T(0);
   }
   // step s (0, 1, 2) computes rows [s + 1, R - 2 - s]; step 0 has no previous iterate
-  strip_step<T, TW, R, 1, R - 2, INNER>(x0, x1, x1, bv, xs, i, n, jb, wc, we, wk, (T)pc[4], (T)pc[5]);
-  strip_step<T, TW, R, 2, R - 3, INNER>(x1, x0, x0, bv, xs, i, n, jb, wc, we, wk, (T)pc[6], (T)pc[7]);
-  strip_step<T, TW, R, 3, R - 4, INNER>(x0, x1, x1, bv, xs, i, n, jb, wc, we, wk, (T)pc[8], (T)pc[9]);
+  strip_step<T, TW, R, 1, R - 2, INNER>(x0, x1, x1, bv, xs, i, inm, n, jb, wc, we, wk, (T)pc[4], (T)pc[5]);
+  strip_step<T, TW, R, 2, R - 3, INNER>(x1, x0, x0, bv, xs, i, inm, n, jb, wc, we, wk, (T)pc[6], (T)pc[7]);
+  strip_step<T, TW, R, 3, R - 4, INNER>(x0, x1, x1, bv, xs, i, inm, n, jb, wc, we, wk, (T)pc[8], (T)pc[9]);
   const T(&x)[R] = x1;
   T* xo = Xo + (long)col * ld;
+  const bool own = i >= own_lo && i < own_hi && c < n;
   if (ACC) {
     // Xo += x: all old values are read (clamped rows and columns) before any store
     T old[S];
-    const unsigned ic = i < n ? i : n - 1;
+    const unsigned ic = c < 0 ? 0 : (c < n ? c : n - 1);
 #pragma unroll
     for (int r = NU; r < NU + S; ++r) {
       const int j = jb + r;
@@ -709,34 +755,38 @@ __device__ inline void mg_up_body(T* xs, int n, int col, int strip, const T* __r
 #pragma unroll
     for (int r = NU; r < NU + S; ++r) {
       const int j = jb + r;
-      if (i < n && (INNER || j < n)) (xo + (unsigned)(j * n))[(unsigned)i] = old[r - NU] + x[r];
+      if (own && (INNER || j < n)) (xo + (unsigned)(j * n))[(unsigned)c] = old[r - NU] + x[r];
     }
     return;
   }
 #pragma unroll
   for (int r = NU; r < NU + S; ++r) {
     const int j = jb + r;
-    if (i < n && (INNER || j < n)) (xo + (unsigned)(j * n))[(unsigned)i] = x[r];
+    if (own && (INNER || j < n)) (xo + (unsigned)(j * n))[(unsigned)c] = x[r];
   }
 }
 
-template <typename T, int TW, int S, int NU, bool ACC>
-__global__ __launch_bounds__(TW) void k_mg_up(int n, int nstrip, const T* __restrict__ Xi, const T* __restrict__ E,
-                                              long ldc, const T* __restrict__ B, long ld, T* __restrict__ Xo,
-                                              const double* __restrict__ P) {
+template <typename T, int TW, int S, int NU, bool ACC, bool TILED>
+__global__ __launch_bounds__(TW, mg_min_waves<T>()) void k_mg_up(int n, int nstrip, int ntile, const T* __restrict__ Xi,
+                                              const T* __restrict__ E, long ldc, const T* __restrict__ B, long ld,
+                                              T* __restrict__ Xo, const double* __restrict__ P) {
   static_assert(NU == 3, "three smoother steps; the coarse-row bookkeeping assumes a halo of three rows");
   constexpr int R = S + 2 * NU;
   constexpr int LP = TW + 2;
+  constexpr int H = TILED ? kUpHalo : 0, W = TW - 2 * H;
   __shared__ T xs[R * LP];
-  int strip, col;
-  strip_of(nstrip, strip, col);
+  int strip, tile, col;
+  tile_of(nstrip, ntile, strip, tile, col);
   for (int r = threadIdx.x; r < R; r += TW) {
     xs[r * LP] = T(0);
     xs[r * LP + TW + 1] = T(0);
   }
+  const int c0 = tile * W - H;
   const int jb = strip * S - NU;
-  if (jb >= 0 && jb + R <= n) mg_up_body<T, TW, S, NU, true, ACC>(xs, n, col, strip, Xi, E, ldc, B, ld, Xo, P);
-  else mg_up_body<T, TW, S, NU, false, ACC>(xs, n, col, strip, Xi, E, ldc, B, ld, Xo, P);
+  if (jb >= 0 && jb + R <= n)
+    mg_up_body<T, TW, S, NU, true, ACC>(xs, n, col, strip, c0, H, H + W, Xi, E, ldc, B, ld, Xo, P);
+  else
+    mg_up_body<T, TW, S, NU, false, ACC>(xs, n, col, strip, c0, H, H + W, Xi, E, ldc, B, ld, Xo, P);
 }
 
 // Strip height per precision and row width: as tall as the register budget
@@ -746,45 +796,54 @@ constexpr int strip_rows() {
   return sizeof(T) == 4 ? 16 : (TW <= 512 ? 8 : 4);
 }
 
-template <typename T, int TW>
+// Meshes of at least kMgTileMinN nodes per side run the tiled passes with
+// workgroups of kMgTileTW threads: a whole-row workgroup of 512 or 1024
+// threads holds its strip in LDS and registers alone on its compute unit, so
+// its loads and its smoother steps alternate instead of overlapping; tiles of
+// kMgTileTW columns let several workgroups share a compute unit.  192 threads
+// cover the 1023- and 511-node rows with the least recomputed halo (6 and 3
+// tiles, 1.13 times the row), against 1.25 and 1.5 times for 256.
+constexpr int kMgTileMinN = 256, kMgTileTW = 192;
+
+template <typename T, int TW, bool TILED>
 static void launch_down(hipStream_t st, int n, int ncols, const T* B, long ld, T* X, T* Bc, long ldc,
                         const double* P) {
-  constexpr int S = strip_rows<T, TW>();
-  const int nstrip = (n + S - 1) / S;
-  hipLaunchKernelGGL((k_mg_down<T, TW, S, kMgFusedNu>), dim3(nstrip * ncols), dim3(TW), 0, st, n, nstrip, B, ld, X,
-                     Bc, ldc, P);
+  constexpr int S = strip_rows<T, TILED ? 512 : TW>();
+  constexpr int W = TW - 2 * (TILED ? kDownHalo : 0);
+  const int nstrip = (n + S - 1) / S, ntile = TILED ? (n + W - 1) / W : 1;
+  hipLaunchKernelGGL((k_mg_down<T, TW, S, kMgFusedNu, TILED>), dim3(nstrip * ntile * ncols), dim3(TW), 0, st, n,
+                     nstrip, ntile, B, ld, X, Bc, ldc, P);
 }
 
-template <typename T, int TW>
+template <typename T, int TW, bool TILED>
 static void launch_up(hipStream_t st, int n, int ncols, const T* Xi, const T* E, long ldc, const T* B, long ld,
                       T* Xo, const double* P, bool acc) {
-  constexpr int S = strip_rows<T, TW>();
-  const int nstrip = (n + S - 1) / S;
+  constexpr int S = strip_rows<T, TILED ? 512 : TW>();
+  constexpr int W = TW - 2 * (TILED ? kUpHalo : 0);
+  const int nstrip = (n + S - 1) / S, ntile = TILED ? (n + W - 1) / W : 1;
   if (acc)
-    hipLaunchKernelGGL((k_mg_up<T, TW, S, kMgFusedNu, true>), dim3(nstrip * ncols), dim3(TW), 0, st, n, nstrip, Xi,
-                       E, ldc, B, ld, Xo, P);
+    hipLaunchKernelGGL((k_mg_up<T, TW, S, kMgFusedNu, true, TILED>), dim3(nstrip * ntile * ncols), dim3(TW), 0, st,
+                       n, nstrip, ntile, Xi, E, ldc, B, ld, Xo, P);
   else
-    hipLaunchKernelGGL((k_mg_up<T, TW, S, kMgFusedNu, false>), dim3(nstrip * ncols), dim3(TW), 0, st, n, nstrip, Xi,
-                       E, ldc, B, ld, Xo, P);
+    hipLaunchKernelGGL((k_mg_up<T, TW, S, kMgFusedNu, false, TILED>), dim3(nstrip * ntile * ncols), dim3(TW), 0, st,
+                       n, nstrip, ntile, Xi, E, ldc, B, ld, Xo, P);
 }
 
 template <typename T>
 void mg_down(hipStream_t st, int n, int ncols, const T* B, long ld, T* X, T* Bc, long ldc, const double* P) {
-  if (n < 64) launch_down<T, 64>(st, n, ncols, B, ld, X, Bc, ldc, P);
-  else if (n < 128) launch_down<T, 128>(st, n, ncols, B, ld, X, Bc, ldc, P);
-  else if (n < 256) launch_down<T, 256>(st, n, ncols, B, ld, X, Bc, ldc, P);
-  else if (n < 512) launch_down<T, 512>(st, n, ncols, B, ld, X, Bc, ldc, P);
-  else launch_down<T, 1024>(st, n, ncols, B, ld, X, Bc, ldc, P);
+  if (n < 64) launch_down<T, 64, false>(st, n, ncols, B, ld, X, Bc, ldc, P);
+  else if (n < 128) launch_down<T, 128, false>(st, n, ncols, B, ld, X, Bc, ldc, P);
+  else if (n < kMgTileMinN) launch_down<T, 256, false>(st, n, ncols, B, ld, X, Bc, ldc, P);
+  else launch_down<T, kMgTileTW, true>(st, n, ncols, B, ld, X, Bc, ldc, P);
 }
 
 template <typename T>
 void mg_up(hipStream_t st, int n, int ncols, const T* Xi, const T* E, long ldc, const T* B, long ld, T* Xo,
            const double* P, bool acc) {
-  if (n < 64) launch_up<T, 64>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P, acc);
-  else if (n < 128) launch_up<T, 128>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P, acc);
-  else if (n < 256) launch_up<T, 256>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P, acc);
-  else if (n < 512) launch_up<T, 512>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P, acc);
-  else launch_up<T, 1024>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P, acc);
+  if (n < 64) launch_up<T, 64, false>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P, acc);
+  else if (n < 128) launch_up<T, 128, false>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P, acc);
+  else if (n < kMgTileMinN) launch_up<T, 256, false>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P, acc);
+  else launch_up<T, kMgTileTW, true>(st, n, ncols, Xi, E, ldc, B, ld, Xo, P, acc);
 }
 template void mg_down<double>(hipStream_t, int, int, const double*, long, double*, double*, long, const double*);
 template void mg_down<float>(hipStream_t, int, int, const float*, long, float*, float*, long, const double*);
@@ -1040,18 +1099,26 @@ typedef double gram_d4 __attribute__((ext_vector_type(4)));
 constexpr int GTH = 512;  // threads per workgroup
 // Tile width 64 BQ in the q direction: BQ = 2 when q > 64, so that the wide
 // operand of products with more than 64 columns on both sides is read half
-// as often.  Rows per LDS stage: 32, or 16 for the 192 x 128 tile, whose two
-// 32-row stages would not fit in the 160 KiB of LDS.
+// as often.  Two stages are in flight while one is multiplied (AHEAD), each
+// in a register set of NC / (GTH / GK) values per thread, with GK = 32 rows
+// per LDS stage, or 16 for the 128 x 128 tile, whose accumulators leave room
+// for two register sets only that short (at most 256 registers per lane at
+// two waves per SIMD).  The 192 x 128 tile keeps one stage in flight (two
+// sets spill even at 8 rows) and 16 rows per stage (two 32-row stages would
+// not fit in the 160 KiB of LDS).
 template <int BM, int BQ>
 struct GramShape {
   static constexpr int GM = 64 * BM, GQ = 64 * BQ;
-  static constexpr int GK = (BM == 3 && BQ == 2) ? 16 : 32;
+  static constexpr int GK = (BQ == 2 && BM >= 2) ? 16 : 32;
+  static constexpr int AHEAD = (BM == 3 && BQ == 2) ? 1 : 2;
 };
 
 template <int BM, int BQ>
 __device__ __forceinline__ void gram_tile(long nrows, long rows_per_chunk, int m, const double* __restrict__ A,
                                           long lda, int q, const double* __restrict__ B, long ldb,
-                                          double* __restrict__ part, int tm, int tq, int chunk) {
+                                          double* __restrict__ part, int tm, int tq, int chunk, int row0,
+                                          int ldp) {
+  // (m columns of A starting at output row row0 of the ldp x q partials)
   constexpr int GM = GramShape<BM, BQ>::GM;   // output tile height (m direction)
   constexpr int GQ = GramShape<BM, BQ>::GQ;   // output tile width (q direction)
   constexpr int GK = GramShape<BM, BQ>::GK;   // rows per LDS stage
@@ -1086,31 +1153,21 @@ __device__ __forceinline__ void gram_tile(long nrows, long rows_per_chunk, int m
   }
   // loads are unconditional (row clamped into the chunk) so that a stage's
   // loads are in flight together; rows outside the chunk are scaled to zero
-  // (a select of a loaded value is compiled into a branch around the load)
-  double rv[NU];
-  auto fetch = [&](long it) {
+  // as they are stored to LDS (a select of a loaded value is compiled into a
+  // branch around the load)
+  auto fetch = [&](long it, double (&rv)[NU]) {
     const long r = r0 + it * GK + lr;
-    const bool rin = r < r1;
-    const long rc = rin ? r : r1 - 1;
-    const double keep = rin ? 1.0 : 0.0;
+    const long rc = r < r1 ? r : r1 - 1;
 #pragma unroll
-    for (int u = 0; u < NU; ++u) {
-      const double v = (u < NA ? At : Bt)[(long)co[u] + rc];
-      rv[u] = v * keep;
-    }
+    for (int u = 0; u < NU; ++u) rv[u] = (u < NA ? At : Bt)[(long)co[u] + rc];
   };
-  // stage it is read from buffer it % 2 while stage it + 1 arrives in
-  // registers and is then stored to the other buffer: one barrier per stage
-  const int ci = lane & 15, ck = lane >> 4;
-  if (nst > 0) {
-    fetch(0);
+  auto stage = [&](long it, const double (&rv)[NU], int buf) {
+    const double keep = r0 + it * GK + lr < r1 ? 1.0 : 0.0;
 #pragma unroll
-    for (int u = 0; u < NU; ++u) S[0][lc + (GTH / GK) * u][lr] = rv[u];
-  }
-  __syncthreads();
-  for (long it = 0; it < nst; ++it) {
-    const int cb = (int)(it & 1);
-    if (it + 1 < nst) fetch(it + 1);
+    for (int u = 0; u < NU; ++u) S[buf][lc + (GTH / GK) * u][lr] = rv[u] * keep;
+  };
+  const int ci = lane & 15, ck = lane >> 4;
+  auto mma = [&](int cb) {
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 4) {
       double bf[2 * BQ];
@@ -1124,14 +1181,50 @@ __device__ __forceinline__ void gram_tile(long nrows, long rows_per_chunk, int m
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf[b], acc[a][b], 0, 0, 0);
       }
     }
-    if (it + 1 < nst) {
-#pragma unroll
-      for (int u = 0; u < NU; ++u) S[cb ^ 1][lc + (GTH / GK) * u][lr] = rv[u];
+  };
+  // AHEAD = 2: while stage it is multiplied out of LDS buffer
+  // it % 2, stage it + 1 is arriving in one register set (issued one stage
+  // earlier) and stage it + 2 is issued into the other; after the products,
+  // stage it + 1 goes to the other LDS buffer (its readers, stage it - 1,
+  // passed the previous barrier): one barrier per stage
+  if constexpr (GramShape<BM, BQ>::AHEAD == 2) {
+    double ra[NU], rb[NU];
+    if (nst > 0) {
+      fetch(0, ra);
+      stage(0, ra, 0);
+    }
+    if (nst > 1) fetch(1, rb);
+    __syncthreads();
+    for (long it = 0; it < nst; it += 2) {
+      if (it + 2 < nst) fetch(it + 2, ra);
+      mma(0);
+      if (it + 1 < nst) stage(it + 1, rb, 1);
+      __syncthreads();
+      if (it + 1 >= nst) break;
+      if (it + 3 < nst) fetch(it + 3, rb);
+      mma(1);
+      if (it + 2 < nst) stage(it + 2, ra, 0);
+      __syncthreads();
+    }
+  } else {
+    // one stage in flight: stage it + 1 arrives in registers while stage it
+    // is multiplied, then goes to the other LDS buffer
+    double rv[NU];
+    if (nst > 0) {
+      fetch(0, rv);
+      stage(0, rv, 0);
     }
     __syncthreads();
+    for (long it = 0; it < nst; ++it) {
+      const int cb = (int)(it & 1);
+      if (it + 1 < nst) fetch(it + 1, rv);
+      mma(cb);
+      if (it + 1 < nst) stage(it + 1, rv, cb ^ 1);
+      __syncthreads();
+    }
   }
-  // partial layout: [chunk] column-major m x q
-  double* P = part + (long)chunk * m * q;
+  // partial layout: [chunk] column-major ldp x q
+  double* P = part + (long)chunk * ldp * q + row0;
 #pragma unroll
   for (int a = 0; a < BM; ++a)
 #pragma unroll
@@ -1140,19 +1233,32 @@ __device__ __forceinline__ void gram_tile(long nrows, long rows_per_chunk, int m
       for (int v = 0; v < 4; ++v) {
         const int i = tm * GM + wm * 16 * BM + 16 * a + (lane >> 4) + 4 * v;
         const int j = tq * GQ + wq * 32 * BQ + 16 * b + (lane & 15);
-        if (i < m && j < q) P[(long)j * m + i] = acc[a][b][v];
+        if (i < m && j < q) P[(long)j * ldp + i] = acc[a][b][v];
       }
 }
 
 // Several Gram products in one launch: blockIdx.z = group * nchunk_max +
 // chunk; each product keeps its own chunking (rows per chunk from its own
 // shape), so its partial sums are exactly those of a launch of its own.
+//
+// A product with a second segment (m2 > 0) takes ceil((m - m2) / 64 BM) row
+// tiles over A, then ceil(m2 / 64 BM) over A2, each tile in one segment.
 template <int BM, int BQ>
 __global__ __launch_bounds__(GTH) void k_gram_mfma(long nrows, GramGroups gs) {
   const int gi = blockIdx.z / gs.nchunk_max, chunk = blockIdx.z % gs.nchunk_max;
   const GramGroup& g = gs.g[gi];
-  if (chunk >= g.nchunk || (int)blockIdx.x * 64 * BM >= g.m || (int)blockIdx.y * 64 * BQ >= g.q) return;
-  gram_tile<BM, BQ>(nrows, g.rpc, g.m, g.A, g.lda, g.q, g.B, g.ldb, g.part, blockIdx.x, blockIdx.y, chunk);
+  constexpr int GM = 64 * BM;
+  const int m1 = g.m - g.m2, t1 = (m1 + GM - 1) / GM;
+  int tm = blockIdx.x, mseg = m1, row0 = 0;
+  const double* A = g.A;
+  if (tm >= t1) {
+    tm -= t1;
+    mseg = g.m2;
+    row0 = m1;
+    A = g.A2;
+  }
+  if (chunk >= g.nchunk || tm * GM >= mseg || (int)blockIdx.y * 64 * BQ >= g.q) return;
+  gram_tile<BM, BQ>(nrows, g.rpc, mseg, A, g.lda, g.q, g.B, g.ldb, g.part, tm, blockIdx.y, chunk, row0, g.m);
 }
 
 // ---------------------------------------------------------------------------
@@ -1196,28 +1302,20 @@ __device__ __forceinline__ void gram_tile_f32(long nrows, long rows_per_chunk, i
     const int c = lc + (GTH / GK) * u;
     co[u] = u < NA ? (unsigned)min(c, ma) * (unsigned)lda : (unsigned)min(c - GM, qb) * (unsigned)ldb;
   }
-  float rv[NU];
-  auto fetch = [&](long it) {
+  // loads as in gram_tile (rows outside the chunk zeroed as they are staged)
+  auto fetch = [&](long it, float (&rv)[NU]) {
     const long r = r0 + it * GK + lr;
-    const bool rin = r < r1;
-    const long rc = rin ? r : r1 - 1;
-    const float keep = rin ? 1.f : 0.f;
+    const long rc = r < r1 ? r : r1 - 1;
 #pragma unroll
-    for (int u = 0; u < NU; ++u) {
-      const float v = u < NA ? At[(long)co[u] + rc] : (float)Bt[(long)co[u] + rc];
-      rv[u] = v * keep;
-    }
+    for (int u = 0; u < NU; ++u) rv[u] = u < NA ? At[(long)co[u] + rc] : (float)Bt[(long)co[u] + rc];
+  };
+  auto stage = [&](long it, const float (&rv)[NU], int buf) {
+    const float keep = r0 + it * GK + lr < r1 ? 1.f : 0.f;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) S[buf][lc + (GTH / GK) * u][lr] = rv[u] * keep;
   };
   const int ci = lane & 15, ck = lane >> 4;
-  if (nst > 0) {
-    fetch(0);
-#pragma unroll
-    for (int u = 0; u < NU; ++u) S[0][lc + (GTH / GK) * u][lr] = rv[u];
-  }
-  __syncthreads();
-  for (long it = 0; it < nst; ++it) {
-    const int cb = (int)(it & 1);
-    if (it + 1 < nst) fetch(it + 1);
+  auto mma = [&](int cb) {
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 4) {
       float bf[2 * BQ];
@@ -1231,10 +1329,20 @@ __device__ __forceinline__ void gram_tile_f32(long nrows, long rows_per_chunk, i
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bf[b], acc[a][b], 0, 0, 0);
       }
     }
-    if (it + 1 < nst) {
-#pragma unroll
-      for (int u = 0; u < NU; ++u) S[cb ^ 1][lc + (GTH / GK) * u][lr] = rv[u];
-    }
+  };
+  // one stage in flight (a second register set costs more in occupancy
+  // than it gains for these tiles)
+  float rv[NU];
+  if (nst > 0) {
+    fetch(0, rv);
+    stage(0, rv, 0);
+  }
+  __syncthreads();
+  for (long it = 0; it < nst; ++it) {
+    const int cb = (int)(it & 1);
+    if (it + 1 < nst) fetch(it + 1, rv);
+    mma(cb);
+    if (it + 1 < nst) stage(it + 1, rv, cb ^ 1);
     __syncthreads();
   }
   double* P = part + (long)chunk * m * q;
@@ -1300,6 +1408,8 @@ void gram_mfma_partials(hipStream_t st, long nrows, int count, GramGroup* groups
     int mmax = 0, qmax = 0, cmax = 1;
     for (int i = 0; i < n; ++i) {
       GramGroup& g = groups[g0 + i];
+      if (g.m2 < 0 || g.m2 > g.m || (g.m2 > 0 && (!g.A2 || g.A32)))
+        throw std::invalid_argument("gram: invalid second segment");
       g.nchunk = (g.m > 0 && g.q > 0) ? gram_chunks_mfma(nrows, g.m, g.q) : 0;
       long rpc = g.nchunk > 0 ? (nrows + g.nchunk - 1) / g.nchunk : 0;
       g.rpc = ((rpc + 31) / 32) * 32;  // a multiple of every stage height
@@ -1316,7 +1426,12 @@ void gram_mfma_partials(hipStream_t st, long nrows, int count, GramGroup* groups
       if (gs.g[i].q > 0) qmin = std::min(qmin, gs.g[i].q);
     // the wide tile only when every product of the launch is wider than 64
     const int bq = gram_bq(qmin), gq = 64 * bq;
-    dim3 grd((mmax + gm - 1) / gm, (qmax + gq - 1) / gq, n * cmax);
+    int tmax = 0;  // row tiles: each segment of a product starts a tile
+    for (int i = 0; i < n; ++i) {
+      const GramGroup& g = gs.g[i];
+      tmax = std::max(tmax, (g.m - g.m2 + gm - 1) / gm + (g.m2 + gm - 1) / gm);
+    }
+    dim3 grd(tmax, (qmax + gq - 1) / gq, n * cmax);
     if (gs.g[0].A32) {  // a launch is all float32 or all float64 (the caller groups them)
       if (bq == 1) {
         switch (bm) {
@@ -1398,6 +1513,42 @@ void sum_partials_grouped(hipStream_t st, int count, const GramGroup* groups) {
     }
     if (cmax <= 0) continue;
     hipLaunchKernelGGL(k_sum_partials_grouped, dim3((cmax + SP_X - 1) / SP_X, n), dim3(SP_X * SP_Y), 0, st, gs);
+  }
+}
+
+// Column sums of squares of small matrices: one workgroup per column and
+// matrix (blockIdx.y), strided partial sums and a fixed-order tree.
+struct ColGroups {
+  ColGroup g[kProjGroupMax];
+};
+__global__ __launch_bounds__(256) void k_col_sqnorms(ColGroups gs) {
+  const ColGroup& g = gs.g[blockIdx.y];
+  const int c = blockIdx.x;
+  if (c >= g.cols) return;
+  __shared__ double red[256];
+  const double* col = g.C + (long)c * g.ld;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < g.rows; i += 256) acc = fma(col[i], col[i], acc);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) g.out[c] = red[0];
+}
+
+void col_sqnorms(hipStream_t st, int count, const ColGroup* groups) {
+  for (int g0 = 0; g0 < count; g0 += kProjGroupMax) {
+    ColGroups gs{};
+    const int n = std::min(kProjGroupMax, count - g0);
+    int cmax = 0;
+    for (int i = 0; i < n; ++i) {
+      gs.g[i] = groups[g0 + i];
+      cmax = std::max(cmax, gs.g[i].cols);
+    }
+    if (cmax <= 0) continue;
+    hipLaunchKernelGGL(k_col_sqnorms, dim3(cmax, n), dim3(256), 0, st, gs);
   }
 }
 
@@ -1515,7 +1666,8 @@ constexpr int PR = 64, PC = 64, PK = 32;
 // for the whole workgroup (Cin may be C).
 __device__ __forceinline__ void proj_tile(long nrows, int m, const double* __restrict__ A, long lda,
                                           const double* __restrict__ Q, int ldq, int p, const double* Cin,
-                                          double* C, long ldc, double alpha, double beta, long row0, int col0) {
+                                          double* C, long ldc, double alpha, double beta, long row0, int col0,
+                                          float* C32 = nullptr) {
   __shared__ double As[PK][PR + 1];
   __shared__ double Qs[PK][PC + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1593,7 +1745,11 @@ __device__ __forceinline__ void proj_tile(long nrows, int m, const double* __res
         const int j = col0 + wc * 32 + 16 * a + (lane >> 4) + 4 * v;
         const long r = row0 + wr * 32 + 16 * b + (lane & 15);
         const double t = alpha * acc[a][b][v];
-        if (j < p && r < nrows) C[(long)j * ldc + r] = beta == 0.0 ? t : fma(beta, old[a][b][v], t);
+        const double y = beta == 0.0 ? t : fma(beta, old[a][b][v], t);
+        if (j < p && r < nrows) {
+          C[(long)j * ldc + r] = y;
+          if (C32) C32[(long)j * ldc + r] = (float)y;
+        }
       }
 }
 
@@ -1613,7 +1769,7 @@ __global__ __launch_bounds__(256, 4) void k_proj_grouped(ProjGroups gs, double a
   const long row0 = (long)blockIdx.x * PR;
   const int col0 = blockIdx.y * PC;
   if (row0 >= g.nrows || col0 >= g.p || g.m <= 0) return;
-  proj_tile(g.nrows, g.m, g.A, g.lda, g.Q, g.ldq, g.p, g.Cin, g.C, g.ldc, alpha, beta, row0, col0);
+  proj_tile(g.nrows, g.m, g.A, g.lda, g.Q, g.ldq, g.p, g.Cin, g.C, g.ldc, alpha, beta, row0, col0, g.C32);
 }
 
 // The projection tile on the float32 matrix cores for the first Gram-Schmidt

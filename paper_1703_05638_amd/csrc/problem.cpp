@@ -1280,13 +1280,21 @@ void Problem::st_solve_pass(const std::vector<const LowRank*>& F, const std::vec
     PhaseTimer pt(this, kPhPoles);
     Wall = st_pole_solves(pp);
   }
+  // the bases of the batch's sources reuse the buffers of the previous batch
+  // (grown as needed): their sizes follow the sources' ranks, and allocating
+  // them per batch left the caching pool with blocks of many sizes
   std::vector<StFin> fins(nb);
+  for (int j = 0; j < nb && j < (int)fin_keep_.size(); ++j) fins[j] = std::move(fin_keep_[j]);
   {
     PhaseTimer pt(this, kPhProject);
     st_project_batch(prs, Wall, fins);
   }
-  PhaseTimer pt(this, kPhTrunc);
-  st_truncate(fins, Y, adjoint);
+  {
+    PhaseTimer pt(this, kPhTrunc);
+    st_truncate(fins, Y, adjoint);
+  }
+  if ((int)fin_keep_.size() < nb) fin_keep_.resize(nb);
+  for (int j = 0; j < nb; ++j) fin_keep_[j] = std::move(fins[j]);
 }
 
 // Bases and projected problems of a batch of prepared sources whose pole
@@ -1414,31 +1422,48 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
       for (int i = 0; i < kc; ++i) Tm[(size_t)c * kc + i] = Uv[(size_t)kk[c] * kc + i] / std::sqrt(wv[kk[c]]);
     return kn;
   };
+  // Tm = R^{-1} from the Cholesky factor G = R^T R when every eigenvalue of G
+  // is above min_eig (lambda_min >= 1 / ||R^{-1}||_F^2); false otherwise
+  auto chol_transform = [](int kc, const double* G, double min_eig, std::vector<double>& Tm) -> bool {
+    std::vector<double> R((size_t)kc * kc);
+    if (!cholesky_upper(kc, G, kc, R.data())) return false;
+    Tm.assign((size_t)kc * kc, 0.0);
+    upper_inverse(kc, R.data(), Tm.data());
+    double f = 0.0;
+    for (double x : Tm) f += x * x;
+    return std::isfinite(f) && f * min_eig < 1.0;
+  };
   std::vector<int> k1(nb, 0), k2(nb, 0), pre2(nb + 1, 0), mw1(nb), mw2(nb);
   std::vector<double> ref(nb, 0.0);
   std::vector<std::vector<double>> Tm(nb);
   std::vector<double*> X1(nb), X2(nb);
   for (int j = 0; j < nb; ++j) mw1[j] = pre[j];
   for (int ip = 0; ip < npol; ++ip) {
-    // stage 1: reference norms of the raw block, first sweep, Gram of the swept block
+    // stage 1: first sweep, Gram of the swept block; the reference scale of
+    // the raw block is its largest squared M-norm, ||X_c||_M^2 = ||C_c||^2 +
+    // ||X'_c||_M^2 with C the sweep's coefficients (Q is M-orthonormal), so it
+    // needs no Gram of the raw block
     std::vector<int> r1s(nb);
-    std::vector<GramGroup> g0, g1;
+    std::vector<GramGroup> g1;
+    std::vector<ColGroup> cn;
     for (int j = 0; j < nb; ++j) {
       r1s[j] = prs[j].r1;
       X1[j] = Wj(ip, j);
       if (r1s[j] == 0) continue;
-      g0.push_back(gram_g(X1[j], MW + (size_t)pre[j] * nx, Gd + slot(j, 0), r1s[j], r1s[j], r1s[j]));
       g1.push_back(gram_g(X1[j], MW + (size_t)pre[j] * nx, Gd + slot(j, 1), r1s[j], r1s[j], r1s[j]));
+      if (q[j] > 0) cn.push_back(ColGroup{Cd + coff[j], Gd + slot(j, 0), q[j], q[j], r1s[j]});
     }
     apply_op(R1, Wj(ip, 0), MW, Mop);
-    sweep(r1s, X1, mw1, g0, true);  // the raw Gram shares the launch of the sweep's float64 products
+    sweep(r1s, X1, mw1, {}, true);
+    col_sqnorms(st, (int)cn.size(), cn.data());
     apply_op(R1, Wj(ip, 0), MW, Mop);
     gram_dev_grouped(g1);
     to_host(Gh.data(), Gd, Gh.size());
     for (int j = 0; j < nb; ++j) {
       const int r1 = prs[j].r1;
       ref[j] = 0.0;
-      for (int c = 0; c < r1; ++c) ref[j] = std::max(ref[j], Gh[slot(j, 0) + (size_t)c * r1 + c]);
+      for (int c = 0; c < r1; ++c)
+        ref[j] = std::max(ref[j], (q[j] > 0 ? Gh[slot(j, 0) + c] : 0.0) + Gh[slot(j, 1) + (size_t)c * r1 + c]);
     }
     host_parallel(nb, [&](int j) {
       k1[j] = (prs[j].r1 > 0 && ref[j] > 0) ? svqb_host(prs[j].r1, Gh.data() + slot(j, 1), 1e-22 * ref[j], Tm[j]) : 0;
@@ -1459,16 +1484,72 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
       }
       proj_dev_grouped(pg, 1.0, 0.0);
     }
-    // stage 2: second sweep of the normalized block and its Gram
-    std::vector<GramGroup> g2;
-    for (int j = 0; j < nb; ++j)
-      if (k1[j] > 0) g2.push_back(gram_g(X2[j], MW + (size_t)pre2[j] * nx, Gd + slot(j, 0), k1[j], k1[j], k1[j]));
+    // stage 2: second sweep of the normalized block X.  Its Gram rides along
+    // with the sweep's product, [Q | X]^T M X = [C; G], and the Gram of the
+    // swept block is G - C^T C (Pythagoras; C is small after the first
+    // sweep).  That form is used when its Cholesky factor shows every
+    // eigenvalue above 1e-4, where its absolute rounding (1e-16 of ||G||) is
+    // at most 1e-12 relative; otherwise the source's swept block gets its own
+    // M product and Gram, as computed directly they round relative to the
+    // small directions.  Each source decides on its own numbers.
     apply_op(K1, W2, MW, Mop);
-    sweep(k1, X2, mw2, {}, false);
-    apply_op(K1, W2, MW, Mop);
-    gram_dev_grouped(g2);
+    {
+      std::vector<GramGroup> gg;
+      std::vector<ProjGroup> pg;
+      for (int j = 0; j < nb; ++j) {
+        if (k1[j] == 0) continue;
+        const int mq = q[j] + k1[j];
+        GramGroup g = gram_g(fins[j].Q.as<double>(), MW + (size_t)pre2[j] * nx, Cd + coff[j], mq, k1[j], mq);
+        if (q[j] > 0) {
+          g.A2 = X2[j];
+          g.m2 = k1[j];
+          pg.push_back(proj_g(fins[j].Q.as<double>(), Cd + coff[j], mq, X2[j], q[j], k1[j]));
+        } else {
+          g.A = X2[j];
+        }
+        gg.push_back(g);
+      }
+      gram_dev_grouped(gg);
+      proj_dev_grouped(pg, -1.0, 1.0);
+    }
+    for (int j = 0; j < nb; ++j) {
+      if (k1[j] == 0) continue;
+      const int mq = q[j] + k1[j];
+      LRP_HIP(hipMemcpy2DAsync(Gd + slot(j, 0), sizeof(double) * k1[j], Cd + coff[j] + q[j], sizeof(double) * mq,
+                               sizeof(double) * k1[j], k1[j], hipMemcpyDeviceToDevice, st));
+      if (q[j] > 0)
+        dense->gemm(true, false, k1[j], k1[j], q[j], 1.0, Cd + coff[j], mq, Cd + coff[j], mq, 0.0, Gd + slot(j, 1),
+                    k1[j]);
+    }
     to_host(Gh.data(), Gd, Gh.size());
-    host_parallel(nb, [&](int j) { k2[j] = k1[j] > 0 ? svqb_host(k1[j], Gh.data() + slot(j, 0), 1e-8, Tm[j]) : 0; });
+    std::vector<int> direct(nb, 0);
+    host_parallel(nb, [&](int j) {
+      k2[j] = 0;
+      if (k1[j] == 0) return;
+      const int kc = k1[j];
+      double* G = Gh.data() + slot(j, 0);
+      if (q[j] > 0) {
+        const double* CC = Gh.data() + slot(j, 1);
+        for (size_t e = 0; e < (size_t)kc * kc; ++e) G[e] -= CC[e];
+      }
+      k2[j] = chol_transform(kc, G, 1e-4, Tm[j]) ? kc : -1;
+      if (k2[j] < 0) direct[j] = 1;
+    });
+    stats.st_direct_grams += (int32_t)std::count(direct.begin(), direct.end(), 1);
+    if (std::count(direct.begin(), direct.end(), 1) > 0) {
+      std::vector<GramGroup> g2;
+      for (int j = 0; j < nb; ++j) {
+        if (!direct[j]) continue;
+        double* MX = MW + (size_t)pre2[j] * nx;
+        apply_op(k1[j], X2[j], MX, Mop);
+        g2.push_back(gram_g(X2[j], MX, Gd + slot(j, 0), k1[j], k1[j], k1[j]));
+      }
+      gram_dev_grouped(g2);
+      to_host(Gh.data(), Gd, Gh.size());
+      host_parallel(nb, [&](int j) {
+        if (direct[j]) k2[j] = svqb_host(k1[j], Gh.data() + slot(j, 0), 1e-8, Tm[j]);
+      });
+    }
     for (int j = 0; j < nb; ++j)
       if (k2[j] < 0) fail(LRPOST_EBREAKDOWN, "basis Gram eigensolve");
     upload(Tm, k2);
@@ -1478,6 +1559,8 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
       if (k2[j] == 0) continue;
       double* Qn = fins[j].Q.as<double>() + (size_t)q[j] * nx;
       pg.push_back(proj_g(X2[j], Td + toff[j], k1[j], Qn, k1[j], k2[j]));
+      // the float32 copy of the new columns for the next first sweeps
+      if (f32_sweep) pg.back().C32 = fins[j].Q32.as<float>() + (size_t)q[j] * nx;
     }
     proj_dev_grouped(pg, 1.0, 0.0);
     // extend Kt = Q^T tau K Q by the new columns (upper triangle suffices)
@@ -1491,11 +1574,6 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
       gk.push_back(gram_g(Q, KQn, fins[j].Kt.as<double>() + (size_t)q[j] * qmax, q[j] + kcols, kcols, qmax));
     }
     gram_dev_grouped(gk);
-    if (f32_sweep)
-      for (int j = 0; j < nb; ++j)
-        if (k2[j] > 0)
-          d2f(st, (long)nx * k2[j], fins[j].Q.as<double>() + (size_t)q[j] * nx,
-              fins[j].Q32.as<float>() + (size_t)q[j] * nx);
     for (int j = 0; j < nb; ++j) q[j] += k2[j];
   }
   PhaseTimer pt(this, kPhProjSolve);

@@ -54,8 +54,9 @@ class Stats(ctypes.Structure):
     _fields_ = [("applies", ctypes.c_int64), ("last_rank_y", ctypes.c_int32), ("last_rank_p", ctypes.c_int32),
                 ("last_rank_out", ctypes.c_int32), ("last_basis", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32),
                 ("st_enrichments", ctypes.c_int32), ("st_unresolved", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("last_tail", ctypes.c_double), ("last_st_resid", ctypes.c_double),
-                ("last_st_presid", ctypes.c_double), ("ritz_resid", ctypes.c_double)]
+                ("st_direct_grams", ctypes.c_int32), ("last_tail", ctypes.c_double), ("last_st_resid", ctypes.c_double),
+                ("last_st_presid", ctypes.c_double), ("ritz_resid", ctypes.c_double),
+                ("pool_mallocs", ctypes.c_int64), ("pool_trims", ctypes.c_int64), ("pool_malloc_s", ctypes.c_double)]
 
 
 _lib = None
@@ -531,7 +532,7 @@ class Problem:
     def stats(self) -> dict:
         s = Stats()
         _check(_lib.lrpost_get_stats(self.h, ctypes.byref(s)))
-        return {f: getattr(s, f) for f, _ in Stats._fields_ if f != "reserved"}
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
 
 
 class Eigs:

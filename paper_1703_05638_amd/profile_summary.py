@@ -6,6 +6,15 @@ Two modes, each printing a short text report:
       kernel-trace statistics (``*_kernel_stats.csv``): the kernels by total
       time and the line of the kernel matching REGEX.
 
+  python -m paper_1703_05638_amd.profile_summary busy DIR MARKER_REGEX
+      kernel trace (``*_kernel_trace.csv``): the run cut into windows that
+      end where a kernel matching MARKER_REGEX ends (one per bench step
+      when the marker runs once per step); per window the wall time, the
+      time at least one kernel ran (union of the kernel intervals, all
+      queues), and the idle gaps longer than 50 us by count and sum; then,
+      over all windows after the first, the kernels that most often end
+      right before such a gap (what the device waited after).
+
   python -m paper_1703_05638_amd.profile_summary traffic FETCH_DIR WRITE_DIR REGEX COPY_REGEX COPY_BYTES
       counter collection (``*_counter_collection.csv``) of two runs, one with
       FETCH_SIZE and one with WRITE_SIZE (KiB per dispatch).  A plain copy
@@ -78,6 +87,61 @@ def stats(d, regex):
                                                                       float(r["TotalDurationNs"]) / 1e6))
 
 
+def _col(row, *names):
+    for n in names:
+        if n in row:
+            return row[n]
+    raise KeyError(names[0])
+
+
+def busy(d, marker):
+    rows = _rows(d, "kernel_trace.csv")
+    ks = []
+    for r in rows:
+        name = _col(r, "Kernel_Name", "KernelName", "Name")
+        ks.append((int(_col(r, "Start_Timestamp", "BeginNs", "Start")), int(_col(r, "End_Timestamp", "EndNs", "End")),
+                   name))
+    ks.sort()
+    pat = re.compile(marker)
+    cuts = sorted(e for b, e, n in ks if pat.search(n))
+    if not ks:
+        raise SystemExit("empty kernel trace")
+    edges = [ks[0][0]] + cuts
+    print("%-8s %12s %12s %8s %9s %12s %12s" % ("window", "wall_ms", "busy_ms", "busy", "kernels", "gaps>50us",
+                                                 "gap_sum_ms"))
+    after = {}
+    for w in range(len(edges) - 1):
+        lo, hi = edges[w], edges[w + 1]
+        inside = [(max(b, lo), min(e, hi), n) for b, e, n in ks if e > lo and b < hi]
+        busy_ns, cur_b, cur_e, cur_n, ngap, gap_ns = 0, None, None, "", 0, 0
+        for b, e, n in inside:
+            if cur_e is None or b > cur_e:
+                if cur_e is not None:
+                    busy_ns += cur_e - cur_b
+                    if b - cur_e > 50000:
+                        ngap += 1
+                        gap_ns += b - cur_e
+                        if w > 0:
+                            key = cur_n.split("(")[0][:70]
+                            c, t = after.get(key, (0, 0))
+                            after[key] = (c + 1, t + b - cur_e)
+                cur_b, cur_e, cur_n = b, e, n
+            else:
+                if e >= cur_e:
+                    cur_n = n
+                cur_e = max(cur_e, e)
+        if cur_e is not None:
+            busy_ns += cur_e - cur_b
+        wall = hi - lo
+        print("%-8d %12.1f %12.1f %8.3f %9d %12d %12.1f" % (w, wall / 1e6, busy_ns / 1e6, busy_ns / max(wall, 1),
+                                                          len(inside), ngap, gap_ns / 1e6))
+    if after:
+        print("gaps > 50 us after windows 1.. by the kernel ending before them:")
+        print("%-72s %8s %12s" % ("kernel", "gaps", "sum_ms"))
+        for key, (c, t) in sorted(after.items(), key=lambda kv: -kv[1][1])[:12]:
+            print("%-72s %8d %12.1f" % (key, c, t / 1e6))
+
+
 def _per_dispatch(rows, regex, counter):
     pat = re.compile(regex)
     acc = {}
@@ -140,6 +204,8 @@ def read_traffic(path):
 if __name__ == "__main__":
     if len(sys.argv) >= 4 and sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3])
+    elif len(sys.argv) >= 4 and sys.argv[1] == "busy":
+        busy(sys.argv[2], sys.argv[3])
     elif len(sys.argv) >= 7 and sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], int(sys.argv[6]))
     else:
