@@ -7,6 +7,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <cstring>
 #include <mutex>
@@ -78,6 +80,16 @@ void* Pool::alloc(size_t bytes, size_t* got) {
   }
   const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   std::lock_guard<std::mutex> lk(impl_->mu);
+  // allocation trace for tuning the pool: LRPOST_POOL_LOG=1 prints every
+  // device allocation (bytes, cached and in-use bytes, whether the cache was
+  // released first, host seconds)
+  static const bool log = [] {
+    const char* e = std::getenv("LRPOST_POOL_LOG");
+    return e && e[0] == '1';
+  }();
+  if (log)
+    std::fprintf(stderr, "pool malloc %zu cached %zu in_use %zu trim %d s %.4f\n", r, impl_->cached, impl_->in_use,
+                 trimmed ? 1 : 0, dt);
   ++impl_->mallocs;
   impl_->trims += trimmed ? 1 : 0;
   impl_->malloc_s += dt;

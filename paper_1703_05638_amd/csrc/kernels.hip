@@ -1096,21 +1096,26 @@ int gram_chunks(long nrows, int m, int q) {
 // (l / 16 + 4 v, l % 16) in slot v.
 // ---------------------------------------------------------------------------
 typedef double gram_d4 __attribute__((ext_vector_type(4)));
-constexpr int GTH = 512;  // threads per workgroup
+constexpr int GTH = 512;  // threads per workgroup of the 64-wide and float32 tiles
 // Tile width 64 BQ in the q direction: BQ = 2 when q > 64, so that the wide
 // operand of products with more than 64 columns on both sides is read half
-// as often.  Two stages are in flight while one is multiplied (AHEAD), each
-// in a register set of NC / (GTH / GK) values per thread, with GK = 32 rows
-// per LDS stage, or 16 for the 128 x 128 tile, whose accumulators leave room
-// for two register sets only that short (at most 256 registers per lane at
-// two waves per SIMD).  The 192 x 128 tile keeps one stage in flight (two
-// sets spill even at 8 rows) and 16 rows per stage (two 32-row stages would
-// not fit in the 160 KiB of LDS).
+// as often.  Stages of GK rows go through two LDS buffers; AHEAD stages are in
+// flight in registers (NC / (TH / GK) values per thread and set) while the
+// matrix cores work on the buffered one.  GK = 32, or 16 for the 192-row
+// tiles and the 128 x 128 tile (their two 32-row buffers would crowd or
+// overflow the 160 KiB of LDS, and shorter stages keep two register sets
+// within 128 registers per lane).
 template <int BM, int BQ>
 struct GramShape {
   static constexpr int GM = 64 * BM, GQ = 64 * BQ;
-  static constexpr int GK = (BQ == 2 && BM >= 2) ? 16 : 32;
+  static constexpr int GK = ((BQ == 2 && BM >= 2) || BM == 3) ? 16 : 32;
+  // waves in the q direction (4 in m): all tiles but the 64 x 64 one run 16
+  // waves of 16 BM x 16 BQ output each, whose small accumulator sets leave
+  // room for four waves per SIMD (128 registers per lane) and, except in the
+  // 192 x 128 tile, for two register sets in flight
   static constexpr int AHEAD = (BM == 3 && BQ == 2) ? 1 : 2;
+  static constexpr int WQ = (BQ == 2 || BM >= 2) ? 4 : 2;
+  static constexpr int TH = 256 * WQ;  // threads per workgroup
 };
 
 template <int BM, int BQ>
@@ -1122,25 +1127,29 @@ __device__ __forceinline__ void gram_tile(long nrows, long rows_per_chunk, int m
   constexpr int GM = GramShape<BM, BQ>::GM;   // output tile height (m direction)
   constexpr int GQ = GramShape<BM, BQ>::GQ;   // output tile width (q direction)
   constexpr int GK = GramShape<BM, BQ>::GK;   // rows per LDS stage
+  constexpr int TH = GramShape<BM, BQ>::TH;   // threads
+  constexpr int WQ = GramShape<BM, BQ>::WQ;   // waves in the q direction
+  constexpr int BW = 4 * BQ / WQ;             // 16-wide output blocks per wave in q
   constexpr int NC = GM + GQ;                 // staged columns per row
-  constexpr int NU = NC / (GTH / GK);         // columns per loading thread
+  constexpr int NU = NC / (TH / GK);          // columns per loading thread
+  static_assert(NC % (TH / GK) == 0 && GM % (TH / GK) == 0, "loader layout");
   __shared__ double S[2][NC][GK + 1];         // two stages of [column][row]: A columns, then B columns
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 3, wq = wave >> 2;
   const long r0 = (long)chunk * rows_per_chunk;
   const long r1 = min(nrows, r0 + rows_per_chunk);
-  gram_d4 acc[BM][2 * BQ];
+  gram_d4 acc[BM][BW];
 #pragma unroll
   for (int a = 0; a < BM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2 * BQ; ++b) acc[a][b] = gram_d4{0.0, 0.0, 0.0, 0.0};
-  const int lr = tid & (GK - 1), lc = tid / GK;  // loader: row lr of columns lc, lc + GTH / GK, ...
+    for (int b = 0; b < BW; ++b) acc[a][b] = gram_d4{0.0, 0.0, 0.0, 0.0};
+  const int lr = tid & (GK - 1), lc = tid / GK;  // loader: row lr of columns lc, lc + TH / GK, ...
   const long nst = (r1 > r0) ? (r1 - r0 + GK - 1) / GK : 0;
   // this thread's staged columns: u < NA are columns of A, the rest of B,
   // each as an element offset from the tile's first column (clamped into
   // range: a clamped column only feeds output rows or columns that are never
   // written, so only rows outside the chunk need zeroing)
-  constexpr int NA = GM / (GTH / GK);
+  constexpr int NA = GM / (TH / GK);
   const double* __restrict__ At = A + (long)tm * GM * lda;
   const double* __restrict__ Bt = B + (long)tq * GQ * ldb;
   const int ma = m - 1 - tm * GM, qb = q - 1 - tq * GQ;
@@ -1148,7 +1157,7 @@ __device__ __forceinline__ void gram_tile(long nrows, long rows_per_chunk, int m
   unsigned co[NU];
 #pragma unroll
   for (int u = 0; u < NU; ++u) {
-    const int c = lc + (GTH / GK) * u;
+    const int c = lc + (TH / GK) * u;
     co[u] = u < NA ? (unsigned)min(c, ma) * (unsigned)lda : (unsigned)min(c - GM, qb) * (unsigned)ldb;
   }
   // loads are unconditional (row clamped into the chunk) so that a stage's
@@ -1164,20 +1173,20 @@ __device__ __forceinline__ void gram_tile(long nrows, long rows_per_chunk, int m
   auto stage = [&](long it, const double (&rv)[NU], int buf) {
     const double keep = r0 + it * GK + lr < r1 ? 1.0 : 0.0;
 #pragma unroll
-    for (int u = 0; u < NU; ++u) S[buf][lc + (GTH / GK) * u][lr] = rv[u] * keep;
+    for (int u = 0; u < NU; ++u) S[buf][lc + (TH / GK) * u][lr] = rv[u] * keep;
   };
   const int ci = lane & 15, ck = lane >> 4;
   auto mma = [&](int cb) {
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 4) {
-      double bf[2 * BQ];
+      double bf[BW];
 #pragma unroll
-      for (int b = 0; b < 2 * BQ; ++b) bf[b] = S[cb][GM + wq * 32 * BQ + 16 * b + ci][kk + ck];
+      for (int b = 0; b < BW; ++b) bf[b] = S[cb][GM + wq * 16 * BW + 16 * b + ci][kk + ck];
 #pragma unroll
       for (int a = 0; a < BM; ++a) {
         const double af = S[cb][wm * 16 * BM + 16 * a + ci][kk + ck];
 #pragma unroll
-        for (int b = 0; b < 2 * BQ; ++b)
+        for (int b = 0; b < BW; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf[b], acc[a][b], 0, 0, 0);
       }
     }
@@ -1228,11 +1237,11 @@ __device__ __forceinline__ void gram_tile(long nrows, long rows_per_chunk, int m
 #pragma unroll
   for (int a = 0; a < BM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2 * BQ; ++b)
+    for (int b = 0; b < BW; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = tm * GM + wm * 16 * BM + 16 * a + (lane >> 4) + 4 * v;
-        const int j = tq * GQ + wq * 32 * BQ + 16 * b + (lane & 15);
+        const int j = tq * GQ + wq * 16 * BW + 16 * b + (lane & 15);
         if (i < m && j < q) P[(long)j * ldp + i] = acc[a][b][v];
       }
 }
@@ -1244,7 +1253,7 @@ __device__ __forceinline__ void gram_tile(long nrows, long rows_per_chunk, int m
 // A product with a second segment (m2 > 0) takes ceil((m - m2) / 64 BM) row
 // tiles over A, then ceil(m2 / 64 BM) over A2, each tile in one segment.
 template <int BM, int BQ>
-__global__ __launch_bounds__(GTH) void k_gram_mfma(long nrows, GramGroups gs) {
+__global__ __launch_bounds__((GramShape<BM, BQ>::TH)) void k_gram_mfma(long nrows, GramGroups gs) {
   const int gi = blockIdx.z / gs.nchunk_max, chunk = blockIdx.z % gs.nchunk_max;
   const GramGroup& g = gs.g[gi];
   constexpr int GM = 64 * BM;
@@ -1450,15 +1459,15 @@ void gram_mfma_partials(hipStream_t st, long nrows, int count, GramGroup* groups
     }
     if (bq == 1) {
       switch (bm) {
-        case 1: hipLaunchKernelGGL((k_gram_mfma<1, 1>), grd, dim3(GTH), 0, st, nrows, gs); break;
-        case 2: hipLaunchKernelGGL((k_gram_mfma<2, 1>), grd, dim3(GTH), 0, st, nrows, gs); break;
-        default: hipLaunchKernelGGL((k_gram_mfma<3, 1>), grd, dim3(GTH), 0, st, nrows, gs);
+        case 1: hipLaunchKernelGGL((k_gram_mfma<1, 1>), grd, dim3(GramShape<1, 1>::TH), 0, st, nrows, gs); break;
+        case 2: hipLaunchKernelGGL((k_gram_mfma<2, 1>), grd, dim3(GramShape<2, 1>::TH), 0, st, nrows, gs); break;
+        default: hipLaunchKernelGGL((k_gram_mfma<3, 1>), grd, dim3(GramShape<3, 1>::TH), 0, st, nrows, gs);
       }
     } else {
       switch (bm) {
-        case 1: hipLaunchKernelGGL((k_gram_mfma<1, 2>), grd, dim3(GTH), 0, st, nrows, gs); break;
-        case 2: hipLaunchKernelGGL((k_gram_mfma<2, 2>), grd, dim3(GTH), 0, st, nrows, gs); break;
-        default: hipLaunchKernelGGL((k_gram_mfma<3, 2>), grd, dim3(GTH), 0, st, nrows, gs);
+        case 1: hipLaunchKernelGGL((k_gram_mfma<1, 2>), grd, dim3(GramShape<1, 2>::TH), 0, st, nrows, gs); break;
+        case 2: hipLaunchKernelGGL((k_gram_mfma<2, 2>), grd, dim3(GramShape<2, 2>::TH), 0, st, nrows, gs); break;
+        default: hipLaunchKernelGGL((k_gram_mfma<3, 2>), grd, dim3(GramShape<3, 2>::TH), 0, st, nrows, gs);
       }
     }
   }

@@ -1491,11 +1491,13 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
     // eigenvalue above 1e-4, where its absolute rounding (1e-16 of ||G||) is
     // at most 1e-12 relative; otherwise the source's swept block gets its own
     // M product and Gram, as computed directly they round relative to the
-    // small directions.  Each source decides on its own numbers.
+    // small directions.  Each source decides on its own numbers.  In mixed
+    // precision the projection X -= Q C of this sweep reads the float32 copy
+    // of Q when every column of C is below 1e-5 (its rounding, 1e-7 of
+    // ||Q C||, is then below 1e-12 of the normalized block).
     apply_op(K1, W2, MW, Mop);
     {
       std::vector<GramGroup> gg;
-      std::vector<ProjGroup> pg;
       for (int j = 0; j < nb; ++j) {
         if (k1[j] == 0) continue;
         const int mq = q[j] + k1[j];
@@ -1503,14 +1505,12 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
         if (q[j] > 0) {
           g.A2 = X2[j];
           g.m2 = k1[j];
-          pg.push_back(proj_g(fins[j].Q.as<double>(), Cd + coff[j], mq, X2[j], q[j], k1[j]));
         } else {
           g.A = X2[j];
         }
         gg.push_back(g);
       }
       gram_dev_grouped(gg);
-      proj_dev_grouped(pg, -1.0, 1.0);
     }
     for (int j = 0; j < nb; ++j) {
       if (k1[j] == 0) continue;
@@ -1522,6 +1522,22 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
                     k1[j]);
     }
     to_host(Gh.data(), Gd, Gh.size());
+    {
+      std::vector<ProjGroup> pg;
+      for (int j = 0; j < nb; ++j) {
+        if (k1[j] == 0 || q[j] == 0) continue;
+        const int mq = q[j] + k1[j];
+        ProjGroup pj = proj_g(fins[j].Q.as<double>(), Cd + coff[j], mq, X2[j], q[j], k1[j]);
+        if (f32_sweep) {
+          const double* CC = Gh.data() + slot(j, 1);
+          double cmax = 0.0;
+          for (int c = 0; c < k1[j]; ++c) cmax = std::max(cmax, CC[(size_t)c * k1[j] + c]);
+          if (cmax < 1e-10) pj.A32 = fins[j].Q32.as<float>();
+        }
+        pg.push_back(pj);
+      }
+      proj_dev_grouped(pg, -1.0, 1.0);
+    }
     std::vector<int> direct(nb, 0);
     host_parallel(nb, [&](int j) {
       k2[j] = 0;

@@ -158,3 +158,30 @@ def test_gram_f32_at_bench_size(lp, m, q):
     err = np.abs(C - ref).max() / np.abs(ref).max()
     print("gram f32 max rel err %.3e" % err, flush=True)
     assert err <= 2e-5
+
+
+@pytest.mark.gpu
+def test_server_alone_equals_mix_on_the_request_stream(lp):
+    """The serving loop on the first eight requests of the seeded request
+    stream (meshes 64..256, nt 50..200, 30 eigenpairs and the variance,
+    mixed precision), all submitted at once to four workers: every served
+    result equals the same request solved alone on a fresh problem bit for
+    bit."""
+    import dataclasses
+    reqs = [dataclasses.replace(r.desc, precision="mixed") for r in synthetic.serving_stream()[:8]]
+    print("case server stream sizes", [(d.N, d.nt) for d in reqs], flush=True)
+    srv = lp.Server(hbm_budget_bytes=100 << 30, workers=4)
+    tickets = [srv.submit(d, d.k) for d in reqs]
+    mix = [srv.wait(t) for t in tickets]
+    info = srv.info()
+    srv.close()
+    print("server info", info, flush=True)
+    assert info["served"] == len(reqs)
+    for i, d in enumerate(reqs):
+        prob = lp.Problem(d)
+        eig = prob.eigensolve(d.k, allow_unconverged=True)
+        lam = eig.values()
+        D = prob.post_variance(eig, on_device=False)
+        lam_mix, D_mix, _ = mix[i]
+        assert np.array_equal(lam_mix, lam), i
+        assert np.array_equal(D_mix, D), i
