@@ -1082,18 +1082,18 @@ int gram_chunks(long nrows, int m, int q) {
 }
 
 // ---------------------------------------------------------------------------
-// FP64 Gram on the matrix cores.  Workgroup (tm, tq, chunk), 8 waves,
-// accumulates a (64 BM) x 64 output tile over its chunk of rows; with
-// BM = 3 the tile covers m <= 192, so each operand of the usual tall-skinny
-// products is read from memory once.  Rows are staged through LDS 32 at a
-// time (coalesced: 32 consecutive lanes read 32 consecutive rows, 256 bytes,
-// of one column), stored [column][row] so that each MFMA operand is one LDS
-// read per lane; the next stage is fetched into registers while the matrix
-// cores work on the current one, and stored to the second LDS buffer.  The waves form a 4 x 2 grid; each owns
-// (16 BM) x 32 of the tile as BM x 2 blocks of v_mfma_f64_16x16x4f64: for
-// the 16 x 4 operand lane l holds element (l % 16, l / 16), for the 4 x 16
-// operand element (l / 16, l % 16), and the 16 x 16 result element
-// (l / 16 + 4 v, l % 16) in slot v.
+// FP64 Gram on the matrix cores.  Workgroup (tm, tq, chunk) accumulates a
+// (64 BM) x (64 BQ) output tile over its chunk of rows; with BM = 3 the tile
+// covers m <= 192, so each operand of the usual tall-skinny products is read
+// from memory once.  Rows are staged through LDS GK at a time (coalesced:
+// consecutive lanes read consecutive rows of one column), stored
+// [column][row] so that each MFMA operand is one LDS read per lane; the next
+// stages are fetched into registers while the matrix cores work on the
+// current one, and stored to the second LDS buffer.  The waves form a 4 x WQ
+// grid (8 or 16 waves); each owns (16 BM) x (64 BQ / WQ) of the tile as
+// blocks of v_mfma_f64_16x16x4f64: for the 16 x 4 operand lane l holds
+// element (l % 16, l / 16), for the 4 x 16 operand element (l / 16, l % 16),
+// and the 16 x 16 result element (l / 16 + 4 v, l % 16) in slot v.
 // ---------------------------------------------------------------------------
 typedef double gram_d4 __attribute__((ext_vector_type(4)));
 constexpr int GTH = 512;  // threads per workgroup of the 64-wide and float32 tiles
