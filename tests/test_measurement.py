@@ -58,4 +58,4 @@ def test_bench_kernel_table_matches_the_library_kinds():
     assert {k: v[0] for k, v in bench.KERNELS.items()} == kinds
     # the dominant kernel's committed traffic reports exist under the names the bench looks for
     for name in ("k_gram_mfma", "k_mg_up", "k_mg_down"):
-        assert os.path.exists(bench.traffic_report(name, "mixed", "mesh256_nt200"))
+        assert os.path.exists(bench.traffic_report(name, "mixed", "mesh1024_nt1000"))
