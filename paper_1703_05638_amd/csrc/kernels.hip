@@ -1667,8 +1667,9 @@ void proj(hipStream_t st, long nrows, int m, const T* A, long lda, const double*
 // FP64 projection on the matrix cores, computed as C^T = Q^T A^T so that the
 // 16 lanes of one result row of an MFMA block hold 16 consecutive rows of C
 // (coalesced stores).  Workgroup: 64 rows x 64 output columns; the inner
-// dimension m is staged through LDS 32 at a time, A as [k][row] and Q as
-// [k][column]; each wave owns 32 rows x 32 columns as 2 x 2 MFMA blocks.
+// dimension m is staged through two LDS buffers 16 at a time, A as [k][row]
+// and Q as [k][column]; each wave owns 32 rows x 32 columns as 2 x 2 MFMA
+// blocks.
 constexpr int PR = 64, PC = 64, PK = 32;
 
 // One 64 x 64 tile (rows row0.., columns col0..) of C = beta Cin + alpha A Q,
@@ -1677,8 +1678,12 @@ __device__ __forceinline__ void proj_tile(long nrows, int m, const double* __res
                                           const double* __restrict__ Q, int ldq, int p, const double* Cin,
                                           double* C, long ldc, double alpha, double beta, long row0, int col0,
                                           float* C32 = nullptr) {
-  __shared__ double As[PK][PR + 1];
-  __shared__ double Qs[PK][PC + 1];
+  // two LDS buffers of PJK rows of k: while the matrix cores work on one, the
+  // next stage arrives in registers and is stored to the other (one barrier
+  // per stage)
+  constexpr int PJK = PK / 2;
+  __shared__ double As[2][PJK][PR + 1];
+  __shared__ double Qs[2][PJK][PC + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave & 1, wc = wave >> 1;
   gram_d4 acc[2][2];
@@ -1687,16 +1692,15 @@ __device__ __forceinline__ void proj_tile(long nrows, int m, const double* __res
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = gram_d4{0.0, 0.0, 0.0, 0.0};
   const int ar = tid & 63, ak = tid >> 6;  // A loader: row ar, k = ak + 4u
-  const int qk = tid & 31, qc = tid >> 5;  // Q loader: k = qk, column qc + 8u
+  const int qk = tid & 15, qc = tid >> 4;  // Q loader: k = qk, column qc + 16u
   const long grow = row0 + ar;
   const long growc = grow < nrows ? grow : nrows - 1;
-  // The next k-stage is fetched into registers while the matrix cores work on
-  // the current one; loads are unconditional (indices clamped into range,
-  // out-of-range values zeroed after) so that a stage's loads overlap.
-  double ra[PK / 4], rq[PC / 8];
+  // loads are unconditional (indices clamped into range, out-of-range values
+  // zeroed after) so that a stage's loads overlap
+  double ra[PJK / 4], rq[PC / 16];
   auto fetch = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < PK / 4; ++u) {
+    for (int u = 0; u < PJK / 4; ++u) {
       const int k = k0 + ak + 4 * u;
       const double v = A[(long)(k < m ? k : m - 1) * lda + growc];
       ra[u] = v * ((k < m && grow < nrows) ? 1.0 : 0.0);  // a select here becomes a branch per load
@@ -1704,30 +1708,38 @@ __device__ __forceinline__ void proj_tile(long nrows, int m, const double* __res
     const int kq = k0 + qk;
     const int kqc = kq < m ? kq : m - 1;
 #pragma unroll
-    for (int u = 0; u < PC / 8; ++u) {
-      const int c = col0 + qc + 8 * u;
+    for (int u = 0; u < PC / 16; ++u) {
+      const int c = col0 + qc + 16 * u;
       const double v = Q[(long)(c < p ? c : p - 1) * ldq + kqc];
       rq[u] = v * ((kq < m && c < p) ? 1.0 : 0.0);
     }
   };
-  fetch(0);
-  for (int k0 = 0; k0 < m; k0 += PK) {
+  auto stage = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < PK / 4; ++u) As[ak + 4 * u][ar] = ra[u];
+    for (int u = 0; u < PJK / 4; ++u) As[buf][ak + 4 * u][ar] = ra[u];
 #pragma unroll
-    for (int u = 0; u < PC / 8; ++u) Qs[qk][qc + 8 * u] = rq[u];
-    __syncthreads();
-    if (k0 + PK < m) fetch(k0 + PK);
-    const int ci = lane & 15, ck = lane >> 4;
+    for (int u = 0; u < PC / 16; ++u) Qs[buf][qk][qc + 16 * u] = rq[u];
+  };
+  const int ci = lane & 15, ck = lane >> 4;
+  const int nst = (m + PJK - 1) / PJK;
+  if (nst > 0) {
+    fetch(0);
+    stage(0);
+  }
+  __syncthreads();
+  for (int s = 0; s < nst; ++s) {
+    const int cb = s & 1;
+    if (s + 1 < nst) fetch((s + 1) * PJK);
 #pragma unroll
-    for (int kk = 0; kk < PK; kk += 4) {
-      const double q0 = Qs[kk + ck][wc * 32 + ci], q1 = Qs[kk + ck][wc * 32 + 16 + ci];
-      const double a0 = As[kk + ck][wr * 32 + ci], a1 = As[kk + ck][wr * 32 + 16 + ci];
+    for (int kk = 0; kk < PJK; kk += 4) {
+      const double q0 = Qs[cb][kk + ck][wc * 32 + ci], q1 = Qs[cb][kk + ck][wc * 32 + 16 + ci];
+      const double a0 = As[cb][kk + ck][wr * 32 + ci], a1 = As[cb][kk + ck][wr * 32 + 16 + ci];
       acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(q0, a0, acc[0][0], 0, 0, 0);
       acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(q0, a1, acc[0][1], 0, 0, 0);
       acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(q1, a0, acc[1][0], 0, 0, 0);
       acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(q1, a1, acc[1][1], 0, 0, 0);
     }
+    if (s + 1 < nst) stage(cb ^ 1);
     __syncthreads();
   }
   // beta != 0: every old value is read (from clamped addresses) before any
