@@ -24,6 +24,10 @@ paper (or of the reading stated in its docstring), in float64:
   mean           the posterior mean / MAP point (Sec. 2 eq. map1): normal
                  equations, data-space form, and the fully observed closed
                  form mode by mode
+  initial        the paper's own experiment setting (Sec. 6, Sec. 6.2): the
+                 initial condition as the parameter, nine sensors, prior
+                 covariance c I; its Hessian, eigenpairs and posterior
+                 variance, pinned by a closed form and an all-at-once route
 
 Functions whose results have no independent pin say "parity unpinned" in
 their docstring.
