@@ -358,6 +358,55 @@ int lrpost_set_apply_batch(lrpost_problem* p, int n);
 int lrpost_set_graphs(lrpost_problem* p, int on);
 int lrpost_graph_info(const lrpost_problem* p, int64_t* captured, int64_t* launches);
 
+/* ---- the initial-condition problem of the paper's experiments ----------
+ * Sec. 6 (eqs. pde, obj, dis_obj, postvar, misfit) and Sec. 6.2: the unknown
+ * is the initial state u = y(0), one value per interior node (node index
+ * j n + i, x1 fastest); the state follows the source-free heat equation
+ * from it on the problem's mesh and time steps, (M + tau K) y_1 = M u,
+ * (M + tau K) y_k = M y_{k-1}, i.e. the space-time system of eq. st_pde with
+ * right-hand side (M u) e_1^T; the observations are the problem's observed
+ * nodes at t_1..t_nt with noise sigma^2 I (sigma from the description), and
+ * the prior covariance is prior_var * I (the paper's experiments: 10 I with
+ * sigma^-2 = 1e4 / prior_var).  The prior-preconditioned misfit Hessian of
+ * eq. misfit is then G = prior_var sigma^-2 C^T K^-T B^T B K^-1 C with
+ * C = e_1 kron M, a symmetric operator on nodal vectors.  The space-time
+ * solves inside are the low-rank solver of lrpost_spacetime_solve, so the
+ * accuracy follows the description's trunc_tol.  Each call is independent:
+ * nothing of it is stored in the problem. */
+
+/* Observed nodes from a mask: mask[i] != 0 for each observed interior node
+ * (host, nx bytes, caller-owned).  Replaces the observation box of the
+ * description for every later call (the space-time source problem uses it
+ * too); eigenpair handles made before are rejected afterwards.  An all-zero
+ * mask: LRPOST_EINVAL. */
+int lrpost_set_obs_mask(lrpost_problem* p, const uint8_t* mask);
+
+/* Y = G U for nvec initial states: U and Y are nx x nvec column-major device
+ * buffers (caller-owned, distinct).  prior_var <= 0 or a null buffer with
+ * nvec > 0: LRPOST_EINVAL. */
+int lrpost_ic_apply(lrpost_problem* p, double prior_var, int nvec, const double* U, double* Y);
+
+/* The k leading eigenpairs of G (Sec. 4, Algorithm 1 for the self-adjoint G:
+ * block Krylov steps of 4 applies with full re-orthogonalization by
+ * classical Gram-Schmidt twice, and Rayleigh-Ritz on the whole basis).
+ * values: host, k doubles, descending.  vectors: device, nx x k
+ * column-major, Euclidean-orthonormal (caller-owned).  Stops when every
+ * wanted pair has ||G x - theta x|| <= rtol theta (rtol <= 0: max(1e-9,
+ * 0.1 trunc_tol), in mixed precision max(1e-7, 0.1 trunc_tol)), or when
+ * another block would pass max_vectors basis vectors (<= 0: max(8k, 40));
+ * then LRPOST_ENOCONV, with the Ritz pairs reached written all the same.
+ * used_vectors (may be NULL) receives the basis size. */
+int lrpost_ic_eigensolve(lrpost_problem* p, double prior_var, int k, int max_vectors, double rtol, double* values,
+                         double* vectors, int* used_vectors);
+
+/* Posterior variance diag(prior_var (I + G)^-1) from k eigenpairs of G
+ * (eq. postvar with the Sherman-Morrison-Woodbury update):
+ * out[i] = prior_var - prior_var sum_j values[j] / (1 + values[j]) vectors[i, j]^2.
+ * values host (k), vectors device (nx x k), out nx doubles on the device
+ * (on_device != 0) or on the host. */
+int lrpost_ic_post_variance(lrpost_problem* p, double prior_var, int k, const double* values, const double* vectors,
+                            double* out, int on_device);
+
 /* Device memory kept for reuse: a problem's allocator caches the blocks its
  * calls free (results stay valid; the cache only speeds up the next call).
  * lrpost_release_cache waits for the problem's stream, returns every cached

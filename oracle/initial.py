@@ -19,7 +19,8 @@ Readings of points the paper leaves open (they are listed with the design):
   * the prior covariance is Gamma_prior = c I (the paper's experiments take
     c = 10, with beta_noise = 1e4 beta_prior = 1e4 / c);
   * the nine sensors of area 1/256 "uniformly distributed" are the closed
-    squares of side 1/16 centred at (i/4, j/4), i, j = 1, 2, 3.
+    squares of side 1/16 centred at (i/4, j/4), i, j = 1, 2, 3 (the input
+    module's default sensor layout).
 
 The misfit Hessian is H = sigma^-2 C^T K_st^-T B^T B K_st^-1 C (eq. postvar
 without its prior term), the prior-preconditioned operator of eq. misfit is
@@ -32,25 +33,9 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
+from synthetic import sensor_mask  # the sensor layout: an input shared with the library's tests
+
 from . import fem
-
-
-def sensor_mask(N: int, centers=None, side: float = 1.0 / 16.0) -> np.ndarray:
-    """Interior nodes inside the closed axis-aligned squares of the given side
-    centred at `centers` (default: the nine points (i/4, j/4), i, j = 1..3).
-    Node index j n + i holds (x1, x2) = ((i+1) h, (j+1) h), x1 fastest."""
-    if centers is None:
-        centers = [(a / 4.0, b / 4.0) for b in (1, 2, 3) for a in (1, 2, 3)]
-    n = N - 1
-    h = 1.0 / N
-    g = np.arange(1, N) * h
-    x1 = np.tile(g, n)
-    x2 = np.repeat(g, n)
-    eps = 1e-12
-    mask = np.zeros(n * n, dtype=bool)
-    for c1, c2 in centers:
-        mask |= (np.abs(x1 - c1) <= side / 2 + eps) & (np.abs(x2 - c2) <= side / 2 + eps)
-    return mask
 
 
 class ICProblem:
@@ -137,6 +122,13 @@ class ICProblem:
         if k is not None:
             w, V = w[:k], V[:, :k]
         return w, V
+
+    def eig_arpack(self, k, tol=1e-12):
+        """k leading eigenpairs of G by ARPACK (scipy's eigsh) on the matrix-free apply, descending."""
+        op = spla.LinearOperator((self.nx, self.nx), matvec=self.G, dtype=np.float64)
+        w, V = spla.eigsh(op, k=k, which="LA", tol=tol, v0=np.ones(self.nx))
+        order = np.argsort(w)[::-1]
+        return w[order], V[:, order]
 
     def post_var_lowrank(self, lam, V):
         """diag of c (I + G)^{-1} from k eigenpairs of G (Sherman-Morrison-Woodbury):

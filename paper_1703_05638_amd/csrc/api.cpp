@@ -2,6 +2,7 @@
 // all exceptions and turns them into a return code plus a thread-local
 // message.
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 
@@ -607,6 +608,66 @@ int lrpost_set_graphs(lrpost_problem* p, int on) {
     P->sync();
     P->use_graphs = on != 0;
     if (!P->use_graphs) P->drop_graphs();
+  });
+}
+
+int lrpost_set_obs_mask(lrpost_problem* p, const uint8_t* mask) {
+  return guarded([&] {
+    Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
+    if (!mask) fail(LRPOST_EINVAL, "null mask");
+    P->sync();
+    P->set_obs_mask(mask);
+    p->alive = std::make_shared<int>(0);  // eigenpairs of the old operator are stale
+  });
+}
+
+int lrpost_ic_apply(lrpost_problem* p, double prior_var, int nvec, const double* U, double* Y) {
+  return guarded([&] {
+    Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
+    if (!(prior_var > 0.0)) fail(LRPOST_EINVAL, "prior variance must be positive");
+    if (nvec < 0) fail(LRPOST_EINVAL, "negative vector count");
+    if (nvec > 0 && (!U || !Y)) fail(LRPOST_EINVAL, "null vector buffer");
+    P->ic_apply(nvec, U, Y, prior_var);
+  });
+}
+
+int lrpost_ic_eigensolve(lrpost_problem* p, double prior_var, int k, int max_vectors, double rtol, double* values,
+                         double* vectors, int* used_vectors) {
+  int rc = LRPOST_OK;
+  const int g = guarded([&] {
+    Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
+    if (!(prior_var > 0.0)) fail(LRPOST_EINVAL, "prior variance must be positive");
+    if (k < 1 || k > P->nx) fail(LRPOST_EINVAL, "k out of range");
+    if (!values || !vectors) fail(LRPOST_EINVAL, "null output buffer");
+    if (!P->ic_eigensolve(prior_var, k, max_vectors, rtol, values, vectors, used_vectors)) {
+      rc = LRPOST_ENOCONV;
+      char msg[160];
+      std::snprintf(msg, sizeof msg, "initial-condition eigensolve stopped at its vector limit; worst relative Ritz residual %.3e",
+                    P->stats.ritz_resid);
+      fail(LRPOST_ENOCONV, msg);
+    }
+  });
+  return g != LRPOST_OK ? g : rc;
+}
+
+int lrpost_ic_post_variance(lrpost_problem* p, double prior_var, int k, const double* values, const double* vectors,
+                            double* out, int on_device) {
+  return guarded([&] {
+    Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
+    if (!(prior_var > 0.0)) fail(LRPOST_EINVAL, "prior variance must be positive");
+    if (k < 0 || (k > 0 && (!values || !vectors)) || !out) fail(LRPOST_EINVAL, "null or invalid argument");
+    if (on_device) {
+      P->ic_post_variance(prior_var, k, values, vectors, out);
+    } else {
+      DevMem d;
+      d.ensure(sizeof(double) * P->nx);
+      P->ic_post_variance(prior_var, k, values, vectors, d.as<double>());
+      P->to_host(out, d.as<double>(), P->nx);
+    }
   });
 }
 

@@ -256,6 +256,14 @@ class Problem {
   void spacetime_solve(const LowRank& F, LowRank& Y, bool adjoint);
   // The same for several sources, with all pole solves in one multigrid solve.
   void spacetime_solve_batch(const std::vector<const LowRank*>& F, const std::vector<LowRank*>& Y, bool adjoint);
+  // the initial-condition problem (ic.cpp): observed nodes from a mask, the
+  // prior-preconditioned misfit Hessian G = c sigma^-2 C^T K^-T B^T B K^-1 C
+  // on initial states (C = e_1 kron M), its leading eigenpairs and the
+  // posterior variance c (I + G)^-1
+  void set_obs_mask(const uint8_t* m);
+  void ic_apply(int nvec, const double* U, double* Y, double c);
+  bool ic_eigensolve(double c, int k, int max_vectors, double rtol, double* values, double* vectors, int* used);
+  void ic_post_variance(double c, int k, const double* values, const double* vectors, double* out);
   // Hessian applies of several vectors with fused multigrid solves.
   void hess_apply_batch(const std::vector<const LowRank*>& x, const std::vector<LowRank*>& y, bool precond);
   struct StPrep {

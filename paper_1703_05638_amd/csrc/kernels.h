@@ -76,6 +76,9 @@ struct ColGroup {
   int rows, cols;
 };
 void col_sqnorms(hipStream_t st, int count, const ColGroup* groups);
+// out[i] = c - c sum_j w[j] V[i + j ldv]^2 (i < nx, j < k): the posterior
+// variance of the initial-condition problem from k eigenpairs, w = lam/(1+lam)
+void ic_post_var(hipStream_t st, long nx, int k, const double* V, long ldv, const double* w, double c, double* out);
 struct GramGroups {
   GramGroup g[kProjGroupMax];
   int nchunk_max;

@@ -1561,6 +1561,25 @@ void col_sqnorms(hipStream_t st, int count, const ColGroup* groups) {
   }
 }
 
+// Posterior variance of the initial-condition problem, one thread per node
+// (columns of V read coalesced, the k terms summed in order).
+__global__ __launch_bounds__(256) void k_ic_post_var(long nx, int k, const double* __restrict__ V, long ldv,
+                                                     const double* __restrict__ w, double c, double* __restrict__ out) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nx) return;
+  double acc = 0.0;
+  for (int j = 0; j < k; ++j) {
+    const double v = V[i + (long)j * ldv];
+    acc = fma(w[j] * v, v, acc);
+  }
+  out[i] = c - c * acc;
+}
+
+void ic_post_var(hipStream_t st, long nx, int k, const double* V, long ldv, const double* w, double c, double* out) {
+  if (nx <= 0) return;
+  hipLaunchKernelGGL(k_ic_post_var, dim3((nx + 255) / 256), dim3(256), 0, st, nx, k, V, ldv, w, c, out);
+}
+
 // The scratch array itself.  Host code never passes its name to a kernel:
 // the name is a host-side stand-in, and only the address from
 // hipGetSymbolAddress (one per device) is device memory.

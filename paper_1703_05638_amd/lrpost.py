@@ -115,6 +115,10 @@ def load(path: str = LIB_PATH):
         "lrpost_set_mg_fused": (I, [P, I]),
         "lrpost_set_graphs": (I, [P, I]),
         "lrpost_release_cache": (I, [P, ctypes.POINTER(ctypes.c_uint64)]),
+        "lrpost_set_obs_mask": (I, [P, ctypes.c_void_p]),
+        "lrpost_ic_apply": (I, [P, D, I, P, P]),
+        "lrpost_ic_eigensolve": (I, [P, D, I, I, D, pd, P, ctypes.POINTER(ctypes.c_int)]),
+        "lrpost_ic_post_variance": (I, [P, D, I, pd, P, P, I]),
         "lrpost_set_apply_batch": (I, [P, I]),
         "lrpost_set_autotune": (I, [I]),
         "lrpost_autotune_report": (I, [ctypes.c_char_p, ctypes.c_size_t]),
@@ -439,6 +443,49 @@ class Problem:
 
     def obs_count(self) -> int:
         return _lib.lrpost_obs_count(self.h)
+
+    # ---- the initial-condition problem --------------------------------
+    def set_obs_mask(self, mask):
+        """Observed interior nodes from a boolean mask of length nx (node j n + i, x1 fastest)."""
+        m = np.ascontiguousarray(np.asarray(mask, dtype=bool).astype(np.uint8))
+        assert m.shape == (self.nx,)
+        _check(_lib.lrpost_set_obs_mask(self.h, m.ctypes.data_as(ctypes.c_void_p)))
+
+    def ic_apply(self, U, prior_var: float):
+        """G U for initial states U: CUDA float64 (nvec, nx) -> (nvec, nx)."""
+        torch = _torch()
+        assert U.dtype == torch.float64 and U.is_cuda and U.dim() == 2 and U.shape[1] == self.nx
+        U = U.contiguous()
+        Y = self._device_empty(None, like=U)
+        _check(_lib.lrpost_ic_apply(self.h, float(prior_var), int(U.shape[0]), _dptr(U), _dptr(Y)))
+        return Y
+
+    def ic_eigensolve(self, k: int, prior_var: float, max_vectors: int = 0, rtol: float = 0.0,
+                      allow_unconverged: bool = False):
+        """k leading eigenpairs of G: (values (k,) descending, vectors CUDA (k, nx), basis size)."""
+        vals = np.zeros(int(k))
+        V = self._device_empty((int(k), self.nx))
+        used = ctypes.c_int()
+        rc = _lib.lrpost_ic_eigensolve(self.h, float(prior_var), int(k), int(max_vectors), float(rtol), _hptr(vals),
+                                       _dptr(V), ctypes.byref(used))
+        if not (rc == -3 and allow_unconverged):
+            _check(rc)
+        return vals, V, used.value
+
+    def ic_post_variance(self, values, vectors, prior_var: float, on_device: bool = True):
+        """diag(prior_var (I + G)^{-1}) from eigenpairs (values (k,), vectors CUDA (k, nx))."""
+        vals = np.ascontiguousarray(np.asarray(values, dtype=np.float64))
+        k = int(vals.size)
+        vectors = vectors.contiguous()
+        assert tuple(vectors.shape) == (k, self.nx)
+        if on_device:
+            out = self._device_empty((self.nx,))
+            _check(_lib.lrpost_ic_post_variance(self.h, float(prior_var), k, _hptr(vals), _dptr(vectors), _dptr(out), 1))
+            return out
+        out = np.zeros(self.nx)
+        _check(_lib.lrpost_ic_post_variance(self.h, float(prior_var), k, _hptr(vals), _dptr(vectors),
+                                            out.ctypes.data_as(ctypes.c_void_p), 0))
+        return out
 
     def posterior_mean(self, y_obs, max_vectors: int = 0, rtol: float = 0.0, allow_unconverged: bool = False):
         """Posterior mean for observations y_obs (nobs, nt): (W1 (r, nx) CUDA, W2 (r, nt), residual estimate)."""

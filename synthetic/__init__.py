@@ -78,6 +78,22 @@ def node_coords(N: int) -> Tuple[np.ndarray, np.ndarray]:
     return x1, x2
 
 
+def sensor_mask(N: int, centers=None, side: float = 1.0 / 16.0) -> np.ndarray:
+    """Observed interior nodes of a sensor layout: the nodes inside closed
+    axis-aligned squares of the given side centred at `centers` (default: the
+    paper's nine sensors of area 1/256 spread uniformly, side 1/16 at the
+    points (i/4, j/4), i, j = 1..3).  Node index j n + i holds ((i+1) h,
+    (j+1) h), x1 fastest.  Layout only; no arithmetic of the method."""
+    if centers is None:
+        centers = [(a / 4.0, b / 4.0) for b in (1, 2, 3) for a in (1, 2, 3)]
+    x1, x2 = node_coords(N)
+    eps = 1e-12
+    mask = np.zeros(x1.size, dtype=bool)
+    for c1, c2 in centers:
+        mask |= (np.abs(x1 - c1) <= side / 2 + eps) & (np.abs(x2 - c2) <= side / 2 + eps)
+    return mask
+
+
 def u_true(desc: ProblemDesc) -> np.ndarray:
     """sin(pi x1) sin(pi x2) exp(-t_k) plus seeded N(0, 0.1^2) noise, shape (nx, nt)."""
     x1, x2 = node_coords(desc.N)

@@ -10,7 +10,8 @@ import scipy.sparse.linalg as spla
 sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 
 from oracle import fem  # noqa: E402
-from oracle.initial import ICProblem, full_obs_ic_eigs, sensor_mask  # noqa: E402
+from oracle.initial import ICProblem, full_obs_ic_eigs  # noqa: E402
+from synthetic import sensor_mask  # noqa: E402
 
 
 def test_full_observation_spectrum_closed_form():
@@ -77,3 +78,10 @@ def test_closed_form_uses_the_sine_basis():
     rho = mu[1, 2] / (mu[1, 2] + p.tau * kappa[1, 2])
     y1 = p.forward(v)[:, 0]
     assert np.allclose(y1, rho * v, atol=1e-13)
+
+
+def test_arpack_route_equals_dense_eigensolve():
+    p = ICProblem(16, 6, sigma=0.03, prior_var=10.0)
+    w, _ = p.eig(8)
+    wa, _ = p.eig_arpack(8)
+    assert np.allclose(wa, w, rtol=1e-9)
