@@ -387,12 +387,14 @@ int lrpost_set_obs_mask(lrpost_problem* p, const uint8_t* mask);
 int lrpost_ic_apply(lrpost_problem* p, double prior_var, int nvec, const double* U, double* Y);
 
 /* The k leading eigenpairs of G (Sec. 4, Algorithm 1 for the self-adjoint G:
- * block Krylov steps of 4 applies with full re-orthogonalization by
+ * block Krylov steps of 4 applies (8 when k >= 32) with full re-orthogonalization by
  * classical Gram-Schmidt twice, and Rayleigh-Ritz on the whole basis).
  * values: host, k doubles, descending.  vectors: device, nx x k
  * column-major, Euclidean-orthonormal (caller-owned).  Stops when every
- * wanted pair has ||G x - theta x|| <= rtol theta (rtol <= 0: max(1e-9,
- * 0.1 trunc_tol), in mixed precision max(1e-7, 0.1 trunc_tol)), or when
+ * wanted pair has ||G x - theta x|| <= rtol theta_1 (theta_1 the largest
+ * Ritz value, the norm of G: every apply carries the truncation error of its
+ * space-time solves relative to the whole operator; rtol <= 0: max(1e-8,
+ * 0.1 trunc_tol), in mixed precision max(1e-6, 0.1 trunc_tol)), or when
  * another block would pass max_vectors basis vectors (<= 0: max(8k, 40));
  * then LRPOST_ENOCONV, with the Ritz pairs reached written all the same.
  * used_vectors (may be NULL) receives the basis size. */
