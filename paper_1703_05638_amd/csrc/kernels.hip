@@ -1700,8 +1700,9 @@ __device__ __forceinline__ void proj_tile(long nrows, int m, const double* __res
   // two LDS buffers of PJK rows of k: while the matrix cores work on one, the
   // next stage arrives in registers and is stored to the other (one barrier
   // per stage)
-  // (rows padded by one double: 0.77 bank conflicts per LDS read at the
-  // 1024^2 workload; a padding of 16 measured 16.6 and a slower kernel)
+  // (rows padded by one double: 0.77 bank conflicts per LDS instruction at
+  // the 1024^2 workload, the same with the stages stored [row][k]; a padding
+  // of 16 measured 16.6 and a slower kernel)
   constexpr int PJK = PK / 2;
   __shared__ double As[2][PJK][PR + 1];
   __shared__ double Qs[2][PJK][PC + 1];
