@@ -28,6 +28,9 @@ paper (or of the reading stated in its docstring), in float64:
                  initial condition as the parameter, nine sensors, prior
                  covariance c I; its Hessian, eigenpairs and posterior
                  variance, pinned by a closed form and an all-at-once route
+  convdiff       the SUPG convection-diffusion operator of Sec. 6.3 (element
+                 loop with Gauss quadrature, Peclet rule) and the
+                 initial-condition problem on it, with transposed adjoint steps
 
 Functions whose results have no independent pin say "parity unpinned" in
 their docstring.

@@ -12,6 +12,10 @@ the boundary, Q1 in space and implicit Euler in time:
 which is the all-at-once system K_st vec(Y) = C u with K_st = I kron tau K +
 C_t kron M (C_t = I - S, S the sub-diagonal shift) and C = e_1 kron M.
 
+Another spatial operator L may take the place of K (the convection-diffusion
+operator of Sec. 6.3, which is not symmetric): the forward steps then solve
+(M + tau L) y_k = M y_{k-1} and the adjoint steps the transposed system.
+
 Readings of points the paper leaves open (they are listed with the design):
   * observations are nodal values at the nodes inside the sensor regions, at
     every step t_1..t_nt, with noise covariance sigma^2 I (the paper's noise
@@ -42,23 +46,30 @@ class ICProblem:
     """Operators of one initial-condition problem.  States are (nx, nt) arrays,
     column k at time t_{k+1}; parameters are nodal vectors (nx,)."""
 
-    def __init__(self, N, nt, T=1.0, sigma=1e-2, prior_var=10.0, mask=None):
+    def __init__(self, N, nt, T=1.0, sigma=1e-2, prior_var=10.0, mask=None, L=None):
         self.N, self.nt, self.T = int(N), int(nt), float(T)
         self.sigma, self.c = float(sigma), float(prior_var)
         self.n = self.N - 1
         self.nx = self.n * self.n
         self.tau = self.T / self.nt
         self.K, self.M = fem.assemble_kronecker(self.N)
+        # the spatial operator: the Laplacian's stiffness K, or another one
+        # (the convection-diffusion operator of Sec. 6.3, not symmetric)
+        self.L = self.K if L is None else sp.csr_matrix(L)
         self.mask = sensor_mask(self.N) if mask is None else np.asarray(mask, dtype=bool)
         self.obs_idx = np.nonzero(self.mask)[0]
-        self._lu = spla.splu((self.M + self.tau * self.K).tocsc())
+        self._lu = spla.splu((self.M + self.tau * self.L).tocsc())
 
     def step_solve(self, b):
-        """(M + tau K)^{-1} b."""
+        """(M + tau L)^{-1} b."""
         return self._lu.solve(np.asarray(b, dtype=np.float64))
 
+    def step_solve_t(self, b):
+        """(M + tau L)^{-T} b (the adjoint step)."""
+        return self._lu.solve(np.asarray(b, dtype=np.float64), trans="T")
+
     def forward(self, u):
-        """Y = K_st^{-1} C u by implicit-Euler time stepping from y_0 = u."""
+        """Y = K_st^{-1} C u by implicit-Euler time stepping from y_0 = u: (M + tau L) y_k = M y_{k-1}."""
         Y = np.zeros((self.nx, self.nt))
         y = np.asarray(u, dtype=np.float64)
         for k in range(self.nt):
@@ -67,12 +78,12 @@ class ICProblem:
         return Y
 
     def adjoint(self, Z):
-        """P = K_st^{-T} vec(Z): backward in time, (M + tau K) p_k = M p_{k+1} + z_k, p_{nt+1} = 0."""
+        """P = K_st^{-T} vec(Z): backward in time, (M + tau L)^T p_k = M p_{k+1} + z_k, p_{nt+1} = 0."""
         Z = np.asarray(Z, dtype=np.float64)
         P = np.zeros((self.nx, self.nt))
         p = np.zeros(self.nx)
         for k in range(self.nt - 1, -1, -1):
-            p = self.step_solve(self.M @ p + Z[:, k])
+            p = self.step_solve_t(self.M @ p + Z[:, k])
             P[:, k] = p
         return P
 
@@ -105,7 +116,7 @@ class ICProblem:
         (a route independent of the time stepping above)."""
         nt, nx = self.nt, self.nx
         Ct = sp.eye(nt) - sp.eye(nt, k=-1)
-        Kst = (sp.kron(sp.eye(nt), self.tau * self.K) + sp.kron(Ct, self.M)).tocsc()
+        Kst = (sp.kron(sp.eye(nt), self.tau * self.L) + sp.kron(Ct, self.M)).tocsc()
         e1 = np.zeros((nt, 1))
         e1[0, 0] = 1.0
         Cm = sp.kron(sp.csr_matrix(e1), self.M).tocsc()
