@@ -298,6 +298,16 @@ int lrpost_set_log(lrpost_problem* p, int level);
  *                                basis building): the basis operand A is read
  *                                as float32 (4 bytes per element), the others
  *                                as for the float64 kinds.
+ *   LRPOST_KERNEL_SINE           the sine transform along x1 of the
+ *                                convection-diffusion solves (a dense product
+ *                                with the n x n sine matrix on the float64
+ *                                matrix cores): read X once, write Y once,
+ *                                2 n flops per node;
+ *   LRPOST_KERNEL_TRIDIAG        the tridiagonal systems along x2 of those
+ *                                solves: the right-hand side read once, the
+ *                                eliminated values and multipliers written
+ *                                and read back once, the solution written:
+ *                                five float64 streams per node.
  * lrpost_profile_read synchronizes, returns for one kind the launch count, the
  * summed kernel time in ms, the counted bytes and (if flops is not NULL) the
  * counted floating-point operations since the last read, and resets that
@@ -310,7 +320,9 @@ enum {
   LRPOST_KERNEL_PROJ = 4,
   LRPOST_KERNEL_STENCIL = 5,
   LRPOST_KERNEL_GRAM32 = 6,
-  LRPOST_KERNEL_PROJ32 = 7
+  LRPOST_KERNEL_PROJ32 = 7,
+  LRPOST_KERNEL_SINE = 8,
+  LRPOST_KERNEL_TRIDIAG = 9
 };
 int lrpost_profile(lrpost_problem* p, int enable);
 int lrpost_profile_read(lrpost_problem* p, int kernel, int64_t* launches, double* total_ms, double* bytes,
@@ -408,6 +420,41 @@ int lrpost_ic_eigensolve(lrpost_problem* p, double prior_var, int k, int max_vec
  * (on_device != 0) or on the host. */
 int lrpost_ic_post_variance(lrpost_problem* p, double prior_var, int k, const double* values, const double* vectors,
                             double* out, int on_device);
+
+/* ---- the convection-diffusion operator (Sec. 6.3) ------------------------
+ * L = -nu Laplace + w . grad with the wind w = (0, wind) along x2,
+ * discretized by SUPG bilinear elements on the problem's mesh (homogeneous
+ * Dirichlet conditions).  For bilinear elements the stabilized operator is
+ * nu K + wind N + delta wind^2 S: N the convection matrix (w . grad phi_j,
+ * phi_i)/wind, S the streamline matrix (d phi_j/dx2, d phi_i/dx2); the time
+ * derivative keeps the mass matrix M (eq. st_pde with L in place of K).
+ *
+ * lrpost_set_convection switches the spatial operator of
+ * lrpost_spacetime_solve and of the initial-condition problem (lrpost_ic_*)
+ * to L: forward solves use L, adjoint solves L^T (eq. postvar's K^-T), so G
+ * stays symmetric.  nu > 0 sets it; delta < 0 takes the element Peclet rule
+ * (delta = h / (2|wind|) (1 - 1/Pe) for Pe = |wind| h / (2 nu) > 1, else 0),
+ * delta >= 0 is used as given (below the rule the shifted solves lose their
+ * stability guarantee); nu <= 0 returns to the heat operator K.  While L is
+ * set, the calls of the space-time source problem (hess_apply*,
+ * eigensolve*, eig_residuals, posterior_mean) return LRPOST_EINVAL.
+ * Non-finite parameters: LRPOST_EINVAL.  The shifted solves (tau L + p M) of
+ * the rational Krylov basis are exact: a sine transform along x1 (where the
+ * operator is symmetric), one tridiagonal system along x2 per sine mode, and
+ * the inverse transform. */
+int lrpost_set_convection(lrpost_problem* p, double nu, double wind, double delta);
+/* Building blocks for kernel-level parity tests (DEVICE float64 buffers, nx x
+ * ncols column-major, leading dimension nx; coef: host, 2 ncols doubles
+ * (a_j, b_j)):
+ *   apply: Y[:,j] = (a_j L + b_j M) X[:,j]  (transpose != 0: L^T);
+ *   solve: X[:,j] = (a_j L + b_j M)^{-1} B[:,j] (transpose != 0: L^T), with
+ *          a_j, b_j >= 0 and a_j + b_j > 0 (LRPOST_EINVAL otherwise); B may
+ *          equal X.
+ * LRPOST_EINVAL without a convection operator set. */
+int lrpost_convdiff_apply(lrpost_problem* p, int ncols, const double* X, double* Y, const double* coef,
+                          int transpose);
+int lrpost_convdiff_solve(lrpost_problem* p, int ncols, const double* B, double* X, const double* coef,
+                          int transpose);
 
 /* Device memory kept for reuse: a problem's allocator caches the blocks its
  * calls free (results stay valid; the cache only speeds up the next call).

@@ -42,6 +42,14 @@ static Problem* impl(lrpost_problem* p) {
   return p->impl.get();
 }
 
+// The space-time source problem (prior P = alpha tau (I kron (K + M))) is
+// built on the heat operator; with a convection operator set, only the
+// space-time solve and the initial-condition problem are defined.
+static void require_heat(const Problem* P) {
+  if (P->cd_on)
+    fail(LRPOST_EINVAL, "a convection operator is set: only the space-time solve and the initial-condition problem use it");
+}
+
 // The problem that created e, which must be p (when p is given) and still
 // alive; every stored vector must have that problem's shape.
 static Problem* owner_of(lrpost_problem* p, const lrpost_eigs* e) {
@@ -132,6 +140,7 @@ int lrpost_get_stats(const lrpost_problem* p, lrpost_stats* s) {
 int lrpost_hess_apply(lrpost_problem* p, const lrpost_lowrank* x, lrpost_lowrank* y, int which) {
   return guarded([&] {
     Problem* P = impl(p);
+    require_heat(P);
     PoolScope pool_scope(P->pool);
     check_lr(P, x, true);
     if (!y || y->nx != P->nx || y->nt != P->nt) fail(LRPOST_EINVAL, "output shape does not match the problem");
@@ -148,6 +157,7 @@ int lrpost_hess_apply_batch(lrpost_problem* p, int nvec, const lrpost_lowrank* x
     if (nvec < 0 || (nvec > 0 && (!x || !y))) fail(LRPOST_EINVAL, "bad batch");
     if (which != LRPOST_MISFIT && which != LRPOST_PRECOND) fail(LRPOST_EINVAL, "which must be MISFIT or PRECOND");
     Problem* P = impl(p);
+    require_heat(P);
     PoolScope pool_scope(P->pool);
     std::vector<LowRank> xs(nvec), ys(nvec);
     std::vector<const LowRank*> px;
@@ -190,6 +200,7 @@ static void finish_eigs(lrpost_problem* p, Problem* P, EigResult& r, lrpost_eigs
 int lrpost_eigensolve(lrpost_problem* p, int k, int method, int oversample, lrpost_eigs** out) {
   return guarded([&] {
     Problem* P = impl(p);
+    require_heat(P);
     PoolScope pool_scope(P->pool);
     if (!out) fail(LRPOST_EINVAL, "null output");
     *out = nullptr;
@@ -243,6 +254,7 @@ int lrpost_eigensolve_probes(lrpost_problem* p, int k, int nprobe, const lrpost_
                              lrpost_eigs** out) {
   return guarded([&] {
     Problem* P = impl(p);
+    require_heat(P);
     PoolScope pool_scope(P->pool);
     if (!out || !probes) fail(LRPOST_EINVAL, "null argument");
     *out = nullptr;
@@ -275,6 +287,7 @@ int lrpost_posterior_mean(lrpost_problem* p, const double* y_obs, int max_vector
                           double* rel_resid) {
   return guarded([&] {
     Problem* P = impl(p);
+    require_heat(P);
     PoolScope pool_scope(P->pool);
     if (!y_obs || !mean) fail(LRPOST_EINVAL, "null argument");
     if (max_vectors < 0 || !(rtol >= 0)) fail(LRPOST_EINVAL, "max_vectors and rtol must be >= 0");
@@ -497,6 +510,7 @@ int lrpost_set_eig_limits(lrpost_problem* p, int max_vectors, double rtol) {
 int lrpost_eig_residuals(lrpost_problem* p, const lrpost_eigs* e, double* resid) {
   return guarded([&] {
     Problem* P = impl(p);
+    require_heat(P);
     PoolScope pool_scope(P->pool);
     if (!e || !resid) fail(LRPOST_EINVAL, "null argument");
     (void)owner_of(p, e);
@@ -565,7 +579,7 @@ int lrpost_profile_read(lrpost_problem* p, int kernel, int64_t* launches, double
     Problem* P = impl(p);
     PoolScope pool_scope(P->pool);
     if (!launches || !total_ms || !bytes) fail(LRPOST_EINVAL, "null argument");
-    if (kernel < 0 || kernel > LRPOST_KERNEL_PROJ32) fail(LRPOST_EINVAL, "unknown kernel kind");
+    if (kernel < 0 || kernel > LRPOST_KERNEL_TRIDIAG) fail(LRPOST_EINVAL, "unknown kernel kind");
     P->prof_read(kernel, launches, total_ms, bytes, flops);
   });
 }
@@ -668,6 +682,46 @@ int lrpost_ic_post_variance(lrpost_problem* p, double prior_var, int k, const do
       P->ic_post_variance(prior_var, k, values, vectors, d.as<double>());
       P->to_host(out, d.as<double>(), P->nx);
     }
+  });
+}
+
+int lrpost_set_convection(lrpost_problem* p, double nu, double wind, double delta) {
+  return guarded([&] {
+    Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
+    P->set_convection(nu, wind, delta);
+  });
+}
+
+static void cd_coefs(const Problem* P, int ncols, const void* A, const void* B, const double* coef,
+                     std::vector<ShiftCoef>& ab) {
+  if (!P->cd_on) fail(LRPOST_EINVAL, "no convection operator set");
+  if (ncols < 0 || (ncols > 0 && (!A || !B || !coef))) fail(LRPOST_EINVAL, "bad arguments");
+  ab.resize(ncols);
+  for (int c = 0; c < ncols; ++c) ab[c] = {coef[2 * c], coef[2 * c + 1]};
+}
+
+int lrpost_convdiff_apply(lrpost_problem* p, int ncols, const double* X, double* Y, const double* coef,
+                          int transpose) {
+  return guarded([&] {
+    Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
+    std::vector<ShiftCoef> ab;
+    cd_coefs(P, ncols, X, Y, coef, ab);
+    P->cd_apply(ncols, X, Y, ab, transpose ? -1 : 1);
+    P->sync();
+  });
+}
+
+int lrpost_convdiff_solve(lrpost_problem* p, int ncols, const double* B, double* X, const double* coef,
+                          int transpose) {
+  return guarded([&] {
+    Problem* P = impl(p);
+    PoolScope pool_scope(P->pool);
+    std::vector<ShiftCoef> ab;
+    cd_coefs(P, ncols, B, X, coef, ab);
+    P->cd_solve(ncols, B, X, ab, transpose ? -1 : 1);
+    P->sync();
   });
 }
 

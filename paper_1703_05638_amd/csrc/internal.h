@@ -234,7 +234,7 @@ class Problem {
     double bytes = 0.0, flops = 0.0;
   };
   bool prof_on = false;
-  std::array<ProfSlot, 8> prof_;
+  std::array<ProfSlot, 10> prof_;
   template <class Launch>
   void timed(int kind, double bytes, Launch&& launch, double flops = 0.0);
   template <typename T>
@@ -261,6 +261,26 @@ class Problem {
   // on initial states (C = e_1 kron M), its leading eigenpairs and the
   // posterior variance c (I + G)^-1
   void set_obs_mask(const uint8_t* m);
+  // ---- convection-diffusion operator (convdiff.cpp) ----------------------
+  // With cd_on the space-time solves use the SUPG operator
+  // L = nu K + w N + delta w^2 S (wind (0, w) along x2, Sec. 6.3) in place of
+  // K: L in forward solves, L^T in adjoint ones (cd_sign -1).  Its shifted
+  // solves are exact (sine transform along x1, tridiagonal systems along x2).
+  bool cd_on = false;
+  double cd_nu = 0.0, cd_w = 0.0, cd_delta = 0.0;
+  int cd_sign = 1;
+  // nu <= 0: back to the heat operator K
+  void set_convection(double nu, double w, double delta);
+  // Y = (a_j L + b_j M) X (sign -1: a_j L^T + b_j M)
+  void cd_apply(int ncols, const double* X, double* Y, const std::vector<ShiftCoef>& ab, int sign);
+  // X = (a_j L + b_j M)^{-1} B (sign -1: transposed), a_j, b_j >= 0, a_j + b_j > 0
+  void cd_solve(int ncols, const double* B, double* X, const std::vector<ShiftCoef>& ab, int sign);
+  // the space-time solver's spatial operator (tau L, tau L^T or tau K) and
+  // its shifted solves (exact, or `cycles` V-cycles for K)
+  void st_apply(int ncols, const double* X, double* Y, const std::vector<ShiftCoef>& ab);
+  void st_spatial_solve(int ncols, const double* B, double* X, const std::vector<ShiftCoef>& ab, int cycles);
+  // poles and Newton-Schulz bound from the spectrum of the operator's symmetric part
+  void init_st_poles(double lam_min, double lam_max);
   void ic_apply(int nvec, const double* U, double* Y, double c);
   bool ic_eigensolve(double c, int k, int max_vectors, double rtol, double* values, double* vectors, int* used);
   void ic_post_variance(double c, int k, const double* values, const double* vectors, double* out);
@@ -342,6 +362,15 @@ class Problem {
   void* readback_ = nullptr;  // pinned, device -> host
   double ns_bound_ = 1.0;     // upper bound of the eigenvalues of the projected I + tau K
   int ns_iters_ = 1;          // Newton-Schulz steps for its inverse
+  double pole_lam_max_ = 0.0; // top of the spatial spectrum (enrichment poles)
+  // convection-diffusion: Newton-Schulz start X_0 = cd_ns_alpha_ I and steps;
+  // sine matrix (n x n), sine-mode mass and stiffness eigenvalues (n), the
+  // per-column shifts and stencil weights, the transform buffer, and the
+  // buffer of tau L Q for the projected operator
+  double cd_ns_alpha_ = 1.0;
+  int cd_ns_iters_ = 1;
+  DevMem cd_S_, cd_mu_, cd_kap_, cd_ab_, cd_wt_, cd_tmp_, st_lq_;
+  std::vector<double> cd_mu_h_, cd_kap_h_;
   std::vector<double> mg_param_h_, op_w_h_;
   std::vector<double> tmp_h_;
   template <typename T>
@@ -375,6 +404,28 @@ class Problem {
   DevMem st_res_a_, st_res_b_, st_res_q_, st_res_g_, st_res_p_, st_res_h_;
   DevMem st_gram_, st_g_, st_mw_, st_w2_, st_tm_, st_prep_g_, st_prep_t_, st_wall_, st_brep_, st_small_, st_c_, eig_work_;
 };
+
+// kernel launches bracketed by event pairs while timing is on (LRPOST_KERNEL_*)
+template <class Launch>
+inline void Problem::timed(int kind, double bytes, Launch&& launch, double flops) {
+  if (!prof_on) {
+    launch();
+    return;
+  }
+  ProfSlot& ps = prof_[kind];
+  if (ps.used == ps.ev.size()) {
+    hipEvent_t a, e;
+    LRP_HIP(hipEventCreate(&a));
+    LRP_HIP(hipEventCreate(&e));
+    ps.ev.push_back({a, e});
+  }
+  auto& ev = ps.ev[ps.used++];
+  LRP_HIP(hipEventRecord(ev.first, st));
+  launch();
+  LRP_HIP(hipEventRecord(ev.second, st));
+  ps.bytes += bytes;
+  ps.flops += flops;
+}
 
 void smoother_interval(double a, double bh2, double* lo, double* hi);
 void chebyshev_coefs(double lo, double hi, int nu, double* alpha, double* beta);

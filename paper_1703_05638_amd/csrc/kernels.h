@@ -183,4 +183,22 @@ constexpr long kGramScratchDoubles = long(8) << 20;  // 64 MiB
 double* gram_scratch_setup();
 double* gram_scratch_device();
 
+// Convection-diffusion with the wind along x2 (tensor mesh, x1 fastest).
+// Y[:,c] = the 9-point stencil with weights W[wstride c .. + 5] = (centre,
+// side) of the rows j - 1, j, j + 1 (symmetric along x1).
+void cd_stencil(hipStream_t st, int n, int ncols, const double* X, long ldx, double* Y, long ldy, const double* W,
+                int wstride);
+// Y = X transformed along x1 by the n x n sine matrix S (device, symmetric,
+// orthonormal) for every mesh row of ncols columns; X and Y distinct.
+void sine_x1(hipStream_t st, int n, int ncols, const double* X, long ldx, double* Y, long ldy, const double* S);
+// scalars of the x2 systems: D/h, s w / 2 (s = +1 for L, -1 for L^T), nu, h/6
+struct CdCoef {
+  double Dh, sw2, nu, h6;
+};
+// In place along x2 for every (column, sine mode): the tridiagonal system of
+// mode j of column c with shift (a, b) = ab[2c..] (device), sine-mode mass
+// and stiffness eigenvalues mu, kap (device, n); CP: scratch of R's shape.
+void tridiag_x2(hipStream_t st, int n, int ncols, double* R, long ldr, double* CP, long ldc, const double* ab,
+                const double* mu, const double* kap, const CdCoef& k);
+
 }  // namespace lrp

@@ -2141,4 +2141,254 @@ void post_variance(hipStream_t st, long nx, int nt, int k, const int* seg, const
   hipLaunchKernelGGL(k_post_var, grd, dim3(256), 0, st, nx, nt, k, seg, dcoef, A, lda, Bt, R, dprior, D, ldd);
 }
 
+// ---------------------------------------------------------------------------
+// Convection-diffusion with the wind along x2 (Sec. 6.3): the SUPG operator
+// on the tensor mesh is L = D K1 (x) M1 + nu M1 (x) K1 + w C1 (x) M1 (first
+// factor along x2, D = nu + delta w^2), so a L + b M is symmetric along x1
+// and its x1 factors are diagonal in the sine basis.  Solves transform along
+// x1, solve one tridiagonal system along x2 per sine mode, and transform
+// back (fast diagonalization).
+// ---------------------------------------------------------------------------
+
+// Y[:,c] = sum over the 3 x 3 block of W_c[d2][|d1|] x(i + d1, j + d2): six
+// weights per column (centre and side of the rows j - 1, j, j + 1), since
+// the operator is symmetric along x1 but not along x2.
+template <int S>
+__global__ __launch_bounds__(256) void k_cd_stencil(int n, const double* __restrict__ X, long ldx,
+                                                    double* __restrict__ Y, long ldy, const double* __restrict__ W,
+                                                    int wstride) {
+  const int col = blockIdx.z;
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int j0 = (blockIdx.y * 4 + threadIdx.y) * S;
+  if (i >= n || j0 >= n) return;
+  const double* w = W + (long)wstride * col;
+  const double c0 = w[0], s0 = w[1], c1 = w[2], s1 = w[3], c2 = w[4], s2 = w[5];
+  const double* x = X + (long)col * ldx;
+  double* y = Y + (long)col * ldy;
+  const bool hl = i > 0, hr = i + 1 < n;
+  auto row = [&](int j, double& m, double& lr) {
+    if (j < 0 || j >= n) {
+      m = lr = 0.0;
+      return;
+    }
+    const double* p = x + (long)j * n + i;
+    m = p[0];
+    lr = (hl ? p[-1] : 0.0) + (hr ? p[1] : 0.0);
+  };
+  double m0, e0, m1, e1, m2, e2;
+  row(j0 - 1, m0, e0);
+  row(j0, m1, e1);
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int j = j0 + s;
+    if (j >= n) break;
+    row(j + 1, m2, e2);
+    y[(long)j * n + i] = (c0 * m0 + s0 * e0) + (c1 * m1 + s1 * e1) + (c2 * m2 + s2 * e2);
+    m0 = m1; e0 = e1;
+    m1 = m2; e1 = e2;
+  }
+}
+
+void cd_stencil(hipStream_t st, int n, int ncols, const double* X, long ldx, double* Y, long ldy, const double* W,
+                int wstride) {
+  if (ncols <= 0 || n <= 0) return;
+  constexpr int S = 8;
+  dim3 blk(64, 4), grd((n + 63) / 64, (n + 4 * S - 1) / (4 * S), ncols);
+  hipLaunchKernelGGL(k_cd_stencil<S>, grd, blk, 0, st, n, X, ldx, Y, ldy, W, wstride);
+}
+
+// Sine transform along x1 of every mesh row of ncols columns: Y[l][j] =
+// sum_i X[l][i] S[i][j] for the lines l = (column c, row i2) at c ld + i2 n,
+// with S the n x n orthonormal sine matrix (symmetric, its own inverse).  A
+// dense product on the float64 matrix cores: 64 lines x 64 modes per
+// workgroup, the k dimension staged through two LDS buffers of 16 (one
+// barrier per stage).  X and Y must not overlap.
+constexpr int SX_L = 64, SX_M = 64, SX_K = 16;
+
+__global__ __launch_bounds__(256, 4) void k_sine_x1(int n, long nlines, const double* __restrict__ X, long ldx,
+                                                     double* __restrict__ Y, long ldy,
+                                                     const double* __restrict__ S) {
+  __shared__ double As[2][SX_K][SX_L + 1];
+  __shared__ double Ss[2][SX_K][SX_M + 1];
+  const long l0 = (long)blockIdx.x * SX_L;
+  const int j0 = blockIdx.y * SX_M;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1;
+  // A loader: k = tid & 15 of the lines (tid >> 4) + 16 u (16 lanes read 16
+  // consecutive doubles of one line); S loader: mode tid & 63 of the k rows
+  // (tid >> 6) + 4 u
+  const int ak = tid & 15, al = tid >> 4;
+  const int sj = tid & 63, sk = tid >> 6;
+  const double* arow[4];
+  double aval[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const long l = l0 + al + 16 * u;
+    const long lc = l < nlines ? l : nlines - 1;
+    arow[u] = X + (lc / n) * ldx + (lc % n) * (long)n;
+    aval[u] = l < nlines ? 1.0 : 0.0;
+  }
+  const int jj = j0 + sj;
+  const int jjc = jj < n ? jj : n - 1;
+  const double sval = jj < n ? 1.0 : 0.0;
+  double ra[4], rs[4];
+  auto fetch = [&](int k0) {
+    const int k = k0 + ak;
+    const int kc = k < n ? k : n - 1;
+    const double kv = k < n ? 1.0 : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) ra[u] = arow[u][kc] * (aval[u] * kv);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int ks = k0 + sk + 4 * u;
+      const int ksc = ks < n ? ks : n - 1;
+      rs[u] = S[(long)ksc * n + jjc] * (ks < n ? sval : 0.0);
+    }
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) As[buf][ak][al + 16 * u] = ra[u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) Ss[buf][sk + 4 * u][sj] = rs[u];
+  };
+  gram_d4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = gram_d4{0.0, 0.0, 0.0, 0.0};
+  const int ci = lane & 15, ck = lane >> 4;
+  const int nst = (n + SX_K - 1) / SX_K;
+  fetch(0);
+  stage(0);
+  __syncthreads();
+  for (int s = 0; s < nst; ++s) {
+    const int cb = s & 1;
+    if (s + 1 < nst) fetch((s + 1) * SX_K);
+#pragma unroll
+    for (int kk = 0; kk < SX_K; kk += 4) {
+      const double a0 = As[cb][kk + ck][wr * 32 + ci], a1 = As[cb][kk + ck][wr * 32 + 16 + ci];
+      const double b0 = Ss[cb][kk + ck][wc * 32 + ci], b1 = Ss[cb][kk + ck][wc * 32 + 16 + ci];
+      // first operand: lines, second: modes (the result's lane & 15 index,
+      // contiguous in Y)
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    if (s + 1 < nst) stage(cb ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const long l = l0 + wr * 32 + 16 * a + (lane >> 4) + 4 * v;
+        const int j = j0 + wc * 32 + 16 * b + (lane & 15);
+        if (l < nlines && j < n) Y[(l / n) * ldy + (l % n) * (long)n + j] = acc[a][b][v];
+      }
+}
+
+void sine_x1(hipStream_t st, int n, int ncols, const double* X, long ldx, double* Y, long ldy, const double* S) {
+  if (ncols <= 0 || n <= 0) return;
+  const long nlines = (long)ncols * n;
+  dim3 grd((unsigned)((nlines + SX_L - 1) / SX_L), (n + SX_M - 1) / SX_M);
+  hipLaunchKernelGGL(k_sine_x1, grd, dim3(256), 0, st, n, nlines, X, ldx, Y, ldy, S);
+}
+
+// One tridiagonal system along x2 per (column c, sine mode j), solved in
+// place in R by elimination without pivoting (the systems are strictly
+// diagonally dominant: the streamwise part D K1 + s w C1 has non-positive
+// off-diagonals and zero row sums when D >= h |w| / 2, which the Peclet rule
+// gives, and the mass part adds a strict margin).  Mode j of column c with
+// shift (a, b) = ab[2c..]: alpha = a mu_j, g = a nu kappa_j + b mu_j,
+//   sub = -alpha (D/h + s w/2) + g h/6, diag = 2 alpha D/h + 4 g h/6,
+//   sup = -alpha (D/h - s w/2) + g h/6.
+// CP (same layout as R) receives the eliminated super-diagonal.  One thread
+// per system, consecutive threads on consecutive modes (one contiguous row
+// segment per step); loads run a chunk ahead of the arithmetic.
+constexpr int TD_U = 8;
+
+__global__ __launch_bounds__(256) void k_tridiag_x2(int n, long nsys, double* __restrict__ R, long ldr,
+                                                    double* __restrict__ CP, long ldc,
+                                                    const double* __restrict__ ab, const double* __restrict__ mu,
+                                                    const double* __restrict__ kap, CdCoef k) {
+  const long g = (long)blockIdx.x * 256 + threadIdx.x;
+  if (g >= nsys) return;
+  const int c = (int)(g / n), j = (int)(g % n);
+  const double a = ab[2 * c], b = ab[2 * c + 1];
+  const double al = a * mu[j], gm = a * k.nu * kap[j] + b * mu[j];
+  const double sub = -al * (k.Dh + k.sw2) + gm * k.h6;
+  const double dia = 2.0 * al * k.Dh + 4.0 * gm * k.h6;
+  const double sup = -al * (k.Dh - k.sw2) + gm * k.h6;
+  double* r = R + (long)c * ldr + j;
+  double* cp = CP + (long)c * ldc + j;
+  const long sn = n;
+  // forward elimination: c'_i = sup / (diag - sub c'_{i-1}),
+  // d'_i = (r_i - sub d'_{i-1}) / (diag - sub c'_{i-1})
+  double cur[TD_U], nxt[TD_U];
+#pragma unroll
+  for (int u = 0; u < TD_U; ++u) cur[u] = r[(long)(u < n ? u : n - 1) * sn];
+  double cprev = 0.0, dprev = 0.0;
+  for (int i0 = 0; i0 < n; i0 += TD_U) {
+#pragma unroll
+    for (int u = 0; u < TD_U; ++u) {
+      const int i = i0 + TD_U + u;
+      nxt[u] = r[(long)(i < n ? i : n - 1) * sn];
+    }
+#pragma unroll
+    for (int u = 0; u < TD_U; ++u) {
+      const int i = i0 + u;
+      if (i < n) {
+        const double m = 1.0 / (dia - sub * cprev);
+        cprev = sup * m;
+        dprev = (cur[u] - sub * dprev) * m;
+        cp[(long)i * sn] = cprev;
+        r[(long)i * sn] = dprev;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < TD_U; ++u) cur[u] = nxt[u];
+  }
+  // back substitution z_i = d'_i - c'_i z_{i+1} (z_{n-1} = d'_{n-1} is in
+  // place), chunks of rows below i loaded ahead
+  double z = dprev;
+  double dc[TD_U], cc[TD_U], dn[TD_U], cn[TD_U];
+  auto load = [&](int top, double* dd, double* cv) {
+#pragma unroll
+    for (int u = 0; u < TD_U; ++u) {
+      const int i = top - u;
+      const long ic = (long)(i >= 0 ? i : 0) * sn;
+      dd[u] = r[ic];
+      cv[u] = cp[ic];
+    }
+  };
+  load(n - 2, dc, cc);
+  for (int top = n - 2; top >= 0; top -= TD_U) {
+    load(top - TD_U, dn, cn);
+#pragma unroll
+    for (int u = 0; u < TD_U; ++u) {
+      const int i = top - u;
+      if (i >= 0) {
+        z = dc[u] - cc[u] * z;
+        r[(long)i * sn] = z;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < TD_U; ++u) {
+      dc[u] = dn[u];
+      cc[u] = cn[u];
+    }
+  }
+}
+
+void tridiag_x2(hipStream_t st, int n, int ncols, double* R, long ldr, double* CP, long ldc, const double* ab,
+                const double* mu, const double* kap, const CdCoef& k) {
+  if (ncols <= 0 || n <= 0) return;
+  const long nsys = (long)ncols * n;
+  hipLaunchKernelGGL(k_tridiag_x2, dim3((unsigned)((nsys + 255) / 256)), dim3(256), 0, st, n, nsys, R, ldr, CP, ldc,
+                     ab, mu, kap, k);
+}
+
 }  // namespace lrp

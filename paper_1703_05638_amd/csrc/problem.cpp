@@ -185,21 +185,33 @@ Problem::Problem(const lrpost_problem_desc& d) : desc(d) {
     matmul(n, n, n, T1.data(), n, false, Sq.data(), n, true, kmdiag_h_.data(), n, 1.0, 0.0);
   }
   set_observation(d.alpha, d.sigma, d.box, d.seed);
-  // inner-solver settings from the truncation tolerance: poles of the spatial
-  // rational Krylov basis log-spaced over the time-step scaled spectrum, and
-  // enough V-cycles to resolve it.  For tolerances down to 1e-7 the poles
-  // cover [0.3 tau lambda_min, 10]: modes with tau lambda beyond about 10
-  // respond to the source within one step and need no poles of their own, and
-  // this placement reaches the tolerance with fewer poles than spreading them
-  // over the whole spectrum (measured on rough random sources at 64^2 and
-  // 128^2 meshes with nt = 200).
   const double lt = -std::log10(d.trunc_tol);
-  st_poles = std::max(4, std::min(24, (int)std::lround(1.5 * lt) + 1));
   // the Chebyshev-smoothed V-cycle contracts the error by about 0.05 per cycle
   st_cycles = std::max(3, (int)std::ceil((lt + 2.0) / 1.25));
   prior_cycles = std::max(4, (int)std::ceil((lt + 3.0) / 1.25));
-  const double lam_min = 2.0 * M_PI * M_PI;
-  const double lam_max = 24.0 / (h * h);  // bound of the element (K, M) eigenvalues, 2 x 12 / h^2
+  // the spectrum of M^{-1} K lies in [2 pi^2, 24 / h^2) (element bound 2 x 12 / h^2)
+  init_st_poles(2.0 * M_PI * M_PI, 24.0 / (h * h));
+  stats.last_st_resid = -1.0;
+  stats.last_st_presid = -1.0;
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) == hipSuccess) free_at_create = fr;
+  else (void)hipGetLastError();
+}
+
+// Inner-solver settings of the space-time solves from the truncation
+// tolerance and the spectrum [lam_min, lam_max] of the symmetric part of
+// M^{-1} times the spatial operator: poles of the spatial rational Krylov
+// basis log-spaced over the time-step scaled spectrum, and the Newton-Schulz
+// bound of the projected I + tau K.  For tolerances down to 1e-7 the poles
+// cover [0.3 tau lambda_min, 10]: modes with tau lambda beyond about 10
+// respond to the source within one step and need no poles of their own, and
+// this placement reaches the tolerance with fewer poles than spreading them
+// over the whole spectrum (measured on rough random sources at 64^2 and
+// 128^2 meshes with nt = 200).
+void Problem::init_st_poles(double lam_min, double lam_max) {
+  const double lt = -std::log10(desc.trunc_tol);
+  st_poles = std::max(4, std::min(24, (int)std::lround(1.5 * lt) + 1));
+  pole_lam_max_ = lam_max;
   // Newton-Schulz inverse of the projected I + tau K (space-time finish):
   // spectrum bound (with a margin for the rounding of the basis) and the
   // number of steps that takes the error factor below 1e-18
@@ -218,11 +230,6 @@ Problem::Problem(const lrpost_problem_desc& d) : desc(d) {
     for (int i = 0; i < st_poles; ++i)
       poles[i] = plo * std::pow(phi / plo, st_poles == 1 ? 0.0 : (double)i / (st_poles - 1));
   }
-  stats.last_st_resid = -1.0;
-  stats.last_st_presid = -1.0;
-  size_t fr = 0, tot = 0;
-  if (hipMemGetInfo(&fr, &tot) == hipSuccess) free_at_create = fr;
-  else (void)hipGetLastError();
 }
 
 int Problem::apply_batch_limit(int r, int want) const {
@@ -567,26 +574,6 @@ void Problem::vcycle_launch(int ncols, const T* B, T* X, bool accumulate, const 
   }
 }
 
-template <class Launch>
-void Problem::timed(int kind, double bytes, Launch&& launch, double flops) {
-  if (!prof_on) {
-    launch();
-    return;
-  }
-  ProfSlot& ps = prof_[kind];
-  if (ps.used == ps.ev.size()) {
-    hipEvent_t a, e;
-    LRP_HIP(hipEventCreate(&a));
-    LRP_HIP(hipEventCreate(&e));
-    ps.ev.push_back({a, e});
-  }
-  auto& ev = ps.ev[ps.used++];
-  LRP_HIP(hipEventRecord(ev.first, st));
-  launch();
-  LRP_HIP(hipEventRecord(ev.second, st));
-  ps.bytes += bytes;
-  ps.flops += flops;
-}
 
 // One Chebyshev smoother step, credited with its algorithmic traffic: read
 // xc, xp and b once, write xo once (neighbour reads of xc are cache hits).
@@ -1023,7 +1010,7 @@ double* Problem::st_pole_solves(const std::vector<const StPrep*>& prs) {
                            hipMemcpyDeviceToDevice, st));
   for (int i = 0; i < npol; ++i)
     for (long c = 0; c < R1; ++c) ab[(size_t)i * R1 + c] = {tau, poles[i]};
-  mg_solve((int)cols, Brep, Wall, ab, st_cycles);
+  st_spatial_solve((int)cols, Brep, Wall, ab, st_cycles);
   return Wall;
 }
 
@@ -1049,6 +1036,7 @@ void Problem::spacetime_solve(const LowRank& F, LowRank& Y, bool adjoint) {
 // values).
 void Problem::spacetime_solve_batch(const std::vector<const LowRank*>& F, const std::vector<LowRank*>& Y,
                                     bool adjoint) {
+  cd_sign = adjoint ? -1 : 1;  // the adjoint solves carry the transposed spatial operator
   st_solve_pass(F, Y, adjoint);
   if (st_check == 0) return;
   const int nb = (int)F.size();
@@ -1082,7 +1070,7 @@ void Problem::spacetime_solve_batch(const std::vector<const LowRank*>& F, const 
     fine.push_back(base[i]);
     if (i + 1 < base.size()) fine.push_back(std::sqrt(base[i] * base[i + 1]));
   }
-  const double top = std::min(tau * 24.0 / (h * h), 1e4);
+  const double top = std::min(tau * pole_lam_max_, 1e4);
   for (double p = base.back() * ratio; p < top * ratio && fine.size() < 48; p *= ratio * ratio) fine.push_back(p);
   // the enriched solves in chunks whose pole-solve columns stay within those
   // of the first pass, so that enrichment needs no more device memory
@@ -1166,7 +1154,7 @@ void Problem::st_residuals(const std::vector<const LowRank*>& F, const std::vect
     const int r = y.rank;
     double* Aj = A + aoff[j] * nx;
     if (r > 0) {
-      apply_op(r, y.a(), Aj, {{tau, 0.0}});
+      st_apply(r, y.a(), Aj, {{tau, 0.0}});
       apply_op(r, y.a(), Aj + (size_t)r * nx, {{0.0, 1.0}});
     }
     if (f[j] > 0)
@@ -1234,7 +1222,7 @@ void Problem::st_residuals(const std::vector<const LowRank*>& F, const std::vect
       LRP_HIP(hipMemcpyAsync(Pin + (poff[j] + c[j]) * nx, A + (aoff[j] + (size_t)2 * Y[j]->rank) * nx,
                              sizeof(double) * nx * f[j], hipMemcpyDeviceToDevice, st));
   }
-  if (poff[nb] > 0) mg_solve((int)poff[nb], Pin, Pout, {{tau, 1.0}}, 2);
+  if (poff[nb] > 0) st_spatial_solve((int)poff[nb], Pin, Pout, {{tau, 1.0}}, 2);
   std::vector<size_t> hoff(nb + 1, 0);
   for (int j = 0; j < nb; ++j) hoff[j + 1] = hoff[j] + (size_t)c[j] * c[j] + (size_t)f[j] * f[j];
   st_res_h_.ensure(sizeof(double) * std::max<size_t>(hoff[nb], 1));
@@ -1579,8 +1567,9 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
       if (f32_sweep) pg.back().C32 = fins[j].Q32.as<float>() + (size_t)q[j] * nx;
     }
     proj_dev_grouped(pg, 1.0, 0.0);
-    // extend Kt = Q^T tau K Q by the new columns (upper triangle suffices)
-    for (int j = 0; j < nb; ++j) {
+    // extend Kt = Q^T tau K Q by the new columns (upper triangle suffices;
+    // the convection-diffusion operator forms its full Kt after the loop)
+    for (int j = 0; j < nb && !cd_on; ++j) {
       const int kcols = k2[j];
       if (kcols == 0) continue;
       double* Q = fins[j].Q.as<double>();
@@ -1591,6 +1580,19 @@ void Problem::st_project_batch(const std::vector<StPrep>& prs, double* Wall, std
     }
     gram_dev_grouped(gk);
     for (int j = 0; j < nb; ++j) q[j] += k2[j];
+  }
+  if (cd_on) {
+    // a projected operator that is not symmetric: Kt = Q^T (tau L) Q in full
+    // (L^T in adjoint solves), one source after another through one buffer
+    for (int j = 0; j < nb; ++j) {
+      if (q[j] == 0) continue;
+      st_lq_.ensure(sizeof(double) * (size_t)nx * q[j]);
+      const double* Q = fins[j].Q.as<double>();
+      st_apply(q[j], Q, st_lq_.as<double>(), Kop);
+      std::vector<GramGroup> gk{gram_g(Q, st_lq_.as<double>(), fins[j].Kt.as<double>(), q[j], q[j],
+                                       prs[j].r1 * npol)};
+      gram_dev_grouped(gk);
+    }
   }
   PhaseTimer pt(this, kPhProjSolve);
   for (int j = 0; j < nb; ++j) stats.last_basis = q[j];
@@ -1665,12 +1667,15 @@ void Problem::st_solve_projected(const std::vector<StPrep>& prs, const std::vect
     T[a] = bf[a].M[3];
     LRP_HIP(hipMemcpy2DAsync(Apd[a], sizeof(double) * qa, fins[j].Kt.as<double>(), sizeof(double) * qmax,
                              sizeof(double) * qa, qa, hipMemcpyDeviceToDevice, st));
-    symmetrize_upper(st, qa, Apd[a], qa);
+    if (!cd_on) symmetrize_upper(st, qa, Apd[a], qa);
     LRP_HIP(hipMemsetAsync(Xa[a], 0, sizeof(double) * (size_t)qa * qa, st));
   }
   diag(Apd, 1.0);
-  diag(Xa, 2.0 / (1.0 + ns_bound_));
-  for (int it = 0; it < ns_iters_; ++it) {
+  // the convection-diffusion operator: X_0 = cd_ns_alpha_ I and a step count
+  // from the field of values of I + Kt (set_convection)
+  diag(Xa, cd_on ? cd_ns_alpha_ : 2.0 / (1.0 + ns_bound_));
+  const int ns_steps_now = cd_on ? cd_ns_iters_ : ns_iters_;
+  for (int it = 0; it < ns_steps_now; ++it) {
     grouped(-1.0, 0.0, [&](int a, int qa, ProjGroup& g) {  // T = -(I + Kt) X
       g = ProjGroup{Apd[a], Xa[a], T[a], T[a], qa, qa, qa, qa, qa, qa};
     });

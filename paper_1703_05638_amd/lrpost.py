@@ -27,6 +27,7 @@ LRPOST_KERNEL_SMOOTHER_STEP, LRPOST_KERNEL_MG_DOWN, LRPOST_KERNEL_MG_UP, LRPOST_
 LRPOST_KERNEL_STENCIL = 5
 LRPOST_KERNEL_GRAM32 = 6
 LRPOST_KERNEL_PROJ32 = 7
+LRPOST_KERNEL_SINE, LRPOST_KERNEL_TRIDIAG = 8, 9
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "ENOCONV", -4: "EBREAKDOWN", -5: "EHIP"}
 
 
@@ -119,6 +120,9 @@ def load(path: str = LIB_PATH):
         "lrpost_ic_apply": (I, [P, D, I, P, P]),
         "lrpost_ic_eigensolve": (I, [P, D, I, I, D, pd, P, ctypes.POINTER(ctypes.c_int)]),
         "lrpost_ic_post_variance": (I, [P, D, I, pd, P, P, I]),
+        "lrpost_set_convection": (I, [P, D, D, D]),
+        "lrpost_convdiff_apply": (I, [P, I, P, P, pd, I]),
+        "lrpost_convdiff_solve": (I, [P, I, P, P, pd, I]),
         "lrpost_set_apply_batch": (I, [P, I]),
         "lrpost_set_autotune": (I, [I]),
         "lrpost_autotune_report": (I, [ctypes.c_char_p, ctypes.c_size_t]),
@@ -450,6 +454,29 @@ class Problem:
         m = np.ascontiguousarray(np.asarray(mask, dtype=bool).astype(np.uint8))
         assert m.shape == (self.nx,)
         _check(_lib.lrpost_set_obs_mask(self.h, m.ctypes.data_as(ctypes.c_void_p)))
+
+    def set_convection(self, nu: float, wind: float = 1.0, delta: float = -1.0):
+        """Spatial operator -nu Laplace + (0, wind) . grad (SUPG; delta < 0: Peclet rule) for the
+        space-time solves and the initial-condition problem; nu <= 0: back to the heat operator."""
+        _check(_lib.lrpost_set_convection(self.h, float(nu), float(wind), float(delta)))
+
+    def _cd_call(self, fn, X, coef, transpose):
+        torch = _torch()
+        assert X.dtype == torch.float64 and X.is_cuda and X.dim() == 2 and X.shape[1] == self.nx
+        X = X.contiguous()
+        c = np.ascontiguousarray(np.asarray(coef, dtype=np.float64).reshape(-1))
+        assert c.size == 2 * X.shape[0]
+        Y = self._device_empty(None, like=X)
+        _check(fn(self.h, int(X.shape[0]), _dptr(X), _dptr(Y), _hptr(c), int(bool(transpose))))
+        return Y
+
+    def convdiff_apply(self, X, coef, transpose: bool = False):
+        """(a_j L + b_j M) X_j (L^T with transpose) for CUDA float64 X (ncols, nx); coef (ncols, 2)."""
+        return self._cd_call(_lib.lrpost_convdiff_apply, X, coef, transpose)
+
+    def convdiff_solve(self, B, coef, transpose: bool = False):
+        """(a_j L + b_j M)^{-1} B_j (exact; L^T with transpose) for CUDA float64 B (ncols, nx)."""
+        return self._cd_call(_lib.lrpost_convdiff_solve, B, coef, transpose)
 
     def ic_apply(self, U, prior_var: float):
         """G U for initial states U: CUDA float64 (nvec, nx) -> (nvec, nx)."""
