@@ -1767,13 +1767,24 @@ void Problem::st_truncate(std::vector<StFin>& fins, const std::vector<LowRank*>&
     if (fins[j].q == 0) Y[j]->resize(nx, nt, 0);
   }
   if (desc.trunc_tol < 1e-7) {
+    // every source's Zp to the host, their SVDs on parallel host threads
+    // (pure host arithmetic), then the truncated products source by source
+    std::vector<std::vector<double>> Zhs(nb), svs(nb), Uzs(nb), Vzs(nb);
     for (int j = 0; j < nb; ++j) {
       const int q = fins[j].q;
       if (q == 0) continue;
-      std::vector<double> Zh((size_t)q * nt);
-      to_host(Zh.data(), fins[j].Zp.as<double>(), Zh.size());
-      std::vector<double> sv, Uz, Vz;
-      svd(q, nt, Zh.data(), q, sv, Uz, Vz);
+      Zhs[j].resize((size_t)q * nt);
+      to_host(Zhs[j].data(), fins[j].Zp.as<double>(), Zhs[j].size());
+    }
+    host_parallel(nb, [&](int j) {
+      if (fins[j].q > 0) svd(fins[j].q, nt, Zhs[j].data(), fins[j].q, svs[j], Uzs[j], Vzs[j]);
+    });
+    for (int j = 0; j < nb; ++j) {
+      const int q = fins[j].q;
+      if (q == 0) continue;
+      const std::vector<double>& sv = svs[j];
+      const std::vector<double>& Uz = Uzs[j];
+      const std::vector<double>& Vz = Vzs[j];
       const int ry = truncation_rank(sv, desc.trunc_tol, desc.rank_cap, &tail);
       Y[j]->resize(nx, nt, ry);
       if (ry > 0) {
