@@ -307,7 +307,7 @@ int lrpost_set_log(lrpost_problem* p, int level);
  *                                solves: the right-hand side read once, the
  *                                eliminated values and multipliers written
  *                                and read back once, the solution written:
- *                                five float64 streams per node.
+ *                                six float64 streams per node.
  * lrpost_profile_read synchronizes, returns for one kind the launch count, the
  * summed kernel time in ms, the counted bytes and (if flops is not NULL) the
  * counted floating-point operations since the last read, and resets that

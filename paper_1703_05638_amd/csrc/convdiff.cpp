@@ -68,12 +68,17 @@ void Problem::set_convection(double nu, double w, double delta) {
   // Spectrum of the symmetric part of M^{-1} L: D (M1^{-1} K1) along x2 plus
   // nu (M1^{-1} K1) along x1, so within [(D + nu) kappa_1 / mu_1, (D + nu) 12 / h^2);
   // the skew part w C1 (x) M1 has ||M^{-1/2} (C1 (x) M1) M^{-1/2}|| <=
-  // ||C1|| / lambda_min(M1) < 3 / h.  Poles over the larger of the two scales.
+  // ||C1|| / lambda_min(M1) < 3 / h.  Poles over the larger of the two
+  // scales, twice as many as for the heat operator: transport keeps the
+  // space-time solutions' rank higher (at 32^2, nt = 90 a rank-one initial
+  // state gives rank 21 at 1e-8 against 11 for the heat equation), and a
+  // rank-one source gets one basis column per pole (measured: 13 poles leave
+  // a relative error of 1.4e-3, 26 poles 5e-6)
   const double D = nu + delta * w * w;
   const double lam_min = (D + nu) * cd_kap_h_[0] / cd_mu_h_[0];
   const double lam_sym = (D + nu) * 12.0 / (h * h);
   const double skew = 3.0 * std::abs(w) / h;
-  init_st_poles(lam_min, std::max(lam_sym, skew));
+  init_st_poles(lam_min, std::max(lam_sym, skew), 2.0);
   // Newton-Schulz for the projected A = I + Kt, Kt = Q^T tau L Q with Q
   // M-orthonormal: the field of values of A lies in the rectangle
   // [1, 1 + s] x i[-b, b], s = tau lam_sym, b = tau skew (5% margin for the
@@ -147,7 +152,7 @@ void Problem::cd_solve(int ncols, const double* B, double* X, const std::vector<
   // B -> T (sine modes along x1), the x2 systems in place in T with X as the
   // elimination scratch, T -> X (the sine matrix is its own inverse)
   timed(LRPOST_KERNEL_SINE, sbytes, [&] { sine_x1(st, n, ncols, B, nx, T, nx, cd_S_.as<double>()); }, sflops);
-  timed(LRPOST_KERNEL_TRIDIAG, sizeof(double) * 5.0 * (double)nx * ncols, [&] {
+  timed(LRPOST_KERNEL_TRIDIAG, sizeof(double) * 6.0 * (double)nx * ncols, [&] {
     tridiag_x2(st, n, ncols, T, nx, X, nx, cd_ab_.as<double>(), cd_mu_.as<double>(), cd_kap_.as<double>(), k);
   });
   timed(LRPOST_KERNEL_SINE, sbytes, [&] { sine_x1(st, n, ncols, T, nx, X, nx, cd_S_.as<double>()); }, sflops);

@@ -225,8 +225,12 @@ bool Problem::ic_eigensolve(double c, int k, int max_vectors, double rtol, doubl
     stats.ritz_resid = worst;
     converged = kk == k && worst <= rtol;
     if (log_level > 0)
-      std::fprintf(stderr, "{\"ic_step\": %d, \"vectors\": %d, \"theta1\": %.10e, \"worst_rel_resid\": %.3e}\n",
-                   m / kBlock, m, theta.empty() ? 0.0 : theta[0], worst);
+      std::fprintf(stderr,
+                   "{\"ic_step\": %d, \"vectors\": %d, \"theta1\": %.10e, \"worst_rel_resid\": %.3e, "
+                   "\"phase_s\": {\"prep\": %.4f, \"poles\": %.4f, \"project\": %.4f, \"projsolve\": %.4f, "
+                   "\"trunc\": %.4f, \"check\": %.4f}}\n",
+                   m / kBlock, m, theta.empty() ? 0.0 : theta[0], worst, phase_s[kPhPrep], phase_s[kPhPoles],
+                   phase_s[kPhProject], phase_s[kPhProjSolve], phase_s[kPhTrunc], phase_s[kPhCheck]);
     if (converged || m + kBlock > maxv) break;
     // next block from G applied to the most recent one
     LRP_HIP(hipMemcpyAsync(W.as<double>(), GVp + (size_t)last * nx, sizeof(double) * (size_t)nx * (m - last),

@@ -209,7 +209,7 @@ class Problem {
   // carries the device time of the work it queued)
   enum Phase {
     kPhPrep, kPhPoles, kPhProject, kPhProjSolve, kPhTrunc, kPhPrior,
-    kPhMaterialize, kPhAbsorb, kPhReorth, kPhRitz, kPhOrthBlock, kPhCount
+    kPhMaterialize, kPhAbsorb, kPhReorth, kPhRitz, kPhOrthBlock, kPhCheck, kPhCount
   };
   std::array<double, kPhCount> phase_s{};
   // (log_level > 2 drains the stream at the end of every phase, so that each
@@ -279,8 +279,9 @@ class Problem {
   // its shifted solves (exact, or `cycles` V-cycles for K)
   void st_apply(int ncols, const double* X, double* Y, const std::vector<ShiftCoef>& ab);
   void st_spatial_solve(int ncols, const double* B, double* X, const std::vector<ShiftCoef>& ab, int cycles);
-  // poles and Newton-Schulz bound from the spectrum of the operator's symmetric part
-  void init_st_poles(double lam_min, double lam_max);
+  // poles and Newton-Schulz bound from the spectrum of the operator's
+  // symmetric part; count_scale multiplies the number of poles
+  void init_st_poles(double lam_min, double lam_max, double count_scale = 1.0);
   void ic_apply(int nvec, const double* U, double* Y, double c);
   bool ic_eigensolve(double c, int k, int max_vectors, double rtol, double* values, double* vectors, int* used);
   void ic_post_variance(double c, int k, const double* values, const double* vectors, double* out);

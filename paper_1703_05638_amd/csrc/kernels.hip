@@ -2202,16 +2202,21 @@ void cd_stencil(hipStream_t st, int n, int ncols, const double* X, long ldx, dou
 // with S the n x n orthonormal sine matrix (symmetric, its own inverse).  A
 // dense product on the float64 matrix cores: 64 lines x 64 modes per
 // workgroup, the k dimension staged through two LDS buffers of 16 (one
-// barrier per stage).  X and Y must not overlap.
+// barrier per stage).  The mode tiles of one line tile run on one XCD,
+// dispatched one after another (workgroups 8 apart), so that its lines come
+// from that XCD's L2 after the first.  X and Y must not overlap.
 constexpr int SX_L = 64, SX_M = 64, SX_K = 16;
 
-__global__ __launch_bounds__(256, 4) void k_sine_x1(int n, long nlines, const double* __restrict__ X, long ldx,
-                                                     double* __restrict__ Y, long ldy,
+__global__ __launch_bounds__(256, 4) void k_sine_x1(int n, long nlines, int nmt, const double* __restrict__ X,
+                                                     long ldx, double* __restrict__ Y, long ldy,
                                                      const double* __restrict__ S) {
   __shared__ double As[2][SX_K][SX_L + 1];
   __shared__ double Ss[2][SX_K][SX_M + 1];
-  const long l0 = (long)blockIdx.x * SX_L;
-  const int j0 = blockIdx.y * SX_M;
+  const long w = blockIdx.x, g = gridDim.x;
+  const long full = g & ~7L;
+  const long lw = w < full ? (w & 7) * (full >> 3) + (w >> 3) : w;
+  const long l0 = (lw / nmt) * SX_L;
+  const int j0 = (int)(lw % nmt) * SX_M;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave & 1, wc = wave >> 1;
   // A loader: k = tid & 15 of the lines (tid >> 4) + 16 u (16 lanes read 16
@@ -2293,8 +2298,9 @@ __global__ __launch_bounds__(256, 4) void k_sine_x1(int n, long nlines, const do
 void sine_x1(hipStream_t st, int n, int ncols, const double* X, long ldx, double* Y, long ldy, const double* S) {
   if (ncols <= 0 || n <= 0) return;
   const long nlines = (long)ncols * n;
-  dim3 grd((unsigned)((nlines + SX_L - 1) / SX_L), (n + SX_M - 1) / SX_M);
-  hipLaunchKernelGGL(k_sine_x1, grd, dim3(256), 0, st, n, nlines, X, ldx, Y, ldy, S);
+  const int nmt = (n + SX_M - 1) / SX_M;
+  const long nwg = (nlines + SX_L - 1) / SX_L * nmt;
+  hipLaunchKernelGGL(k_sine_x1, dim3((unsigned)nwg), dim3(256), 0, st, n, nlines, nmt, X, ldx, Y, ldy, S);
 }
 
 // One tridiagonal system along x2 per (column c, sine mode j), solved in

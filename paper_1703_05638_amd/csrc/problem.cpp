@@ -111,7 +111,7 @@ static int ns_steps(double L) {
 
 // f(0) .. f(n-1) on up to kHostThreads host threads (pure host work only:
 // no HIP calls and no exceptions inside f).
-static constexpr int kHostThreads = 4;
+static constexpr int kHostThreads = 8;
 template <class F>
 static void host_parallel(int n, F&& f) {
   if (n <= 1) {
@@ -207,10 +207,10 @@ Problem::Problem(const lrpost_problem_desc& d) : desc(d) {
 // respond to the source within one step and need no poles of their own, and
 // this placement reaches the tolerance with fewer poles than spreading them
 // over the whole spectrum (measured on rough random sources at 64^2 and
-// 128^2 meshes with nt = 200).
-void Problem::init_st_poles(double lam_min, double lam_max) {
+// 128^2 meshes with nt = 200).  count_scale multiplies the pole count.
+void Problem::init_st_poles(double lam_min, double lam_max, double count_scale) {
   const double lt = -std::log10(desc.trunc_tol);
-  st_poles = std::max(4, std::min(24, (int)std::lround(1.5 * lt) + 1));
+  st_poles = std::max(4, (int)std::lround(count_scale * std::min(24, (int)std::lround(1.5 * lt) + 1)));
   pole_lam_max_ = lam_max;
   // Newton-Schulz inverse of the projected I + tau K (space-time finish):
   // spectrum bound (with a margin for the rounding of the basis) and the
@@ -220,7 +220,7 @@ void Problem::init_st_poles(double lam_min, double lam_max) {
   const double plo = std::min(1e-2, 0.5 * tau * lam_min);
   const double phi = std::max(10.0 * plo, std::min(tau * lam_max, 1e4));
   if (lt <= 7.0) {
-    st_poles = std::max(4, (int)std::lround(1.2 * lt) + 1);
+    st_poles = std::max(4, (int)std::lround(count_scale * ((int)std::lround(1.2 * lt) + 1)));
     const double lo = 0.3 * tau * lam_min;
     const double hi = std::max(10.0 * lo, std::min(tau * lam_max, 10.0));
     poles.resize(st_poles);
@@ -1042,7 +1042,10 @@ void Problem::spacetime_solve_batch(const std::vector<const LowRank*>& F, const 
   const int nb = (int)F.size();
   std::vector<const LowRank*> cy(Y.begin(), Y.end());
   std::vector<double> rel, prel;
-  st_residuals(F, cy, adjoint, rel, prel);
+  {
+    PhaseTimer pt(this, kPhCheck);
+    st_residuals(F, cy, adjoint, rel, prel);
+  }
   auto record = [&]() {
     double w = 0.0, wp = 0.0;
     for (size_t j = 0; j < rel.size(); ++j) {
@@ -1102,7 +1105,10 @@ void Problem::spacetime_solve_batch(const std::vector<const LowRank*>& F, const 
   }
   poles = base;
   std::vector<const LowRank*> cyb(Yb.begin(), Yb.end());
-  st_residuals(Fb, cyb, adjoint, rel, prel);
+  {
+    PhaseTimer pt(this, kPhCheck);
+    st_residuals(Fb, cyb, adjoint, rel, prel);
+  }
   const double worst = record();
   if (worst <= thr) return;
   ++stats.st_unresolved;

@@ -43,6 +43,7 @@ KERNEL_SOURCES = {
     "k_gram": ("// FP64 Gram on the matrix cores.", "void sum_partials("),
     "k_proj": ("// FP64 projection on the matrix cores,", "template void proj<float>("),
     "k_stencil": ("__device__ inline void stencil_strip_body", "// Autotuner of the stencil strip height"),
+    "k_cd": ("// Convection-diffusion with the wind along x2 (Sec. 6.3)", "void tridiag_x2(hipStream_t st"),
 }
 
 
@@ -50,6 +51,8 @@ def _source_key(regex):
     for key in ("k_gram", "k_proj", "k_mg", "k_stencil"):
         if key in regex:
             return key
+    if any(k in regex for k in ("k_sine", "k_tridiag", "k_cd_")):
+        return "k_cd"
     return "k_cheb"
 
 

@@ -32,6 +32,7 @@ def test_digest_keys_follow_the_kernel_regex():
     assert ps._source_key("k_proj_mfma") == "k_proj"
     assert ps._source_key("k_mg_up<float") == "k_mg"
     assert ps._source_key("k_cheb<float") == "k_cheb"
+    assert ps._source_key("k_sine_x1") == ps._source_key("k_tridiag_x2") == "k_cd"
     # the multigrid kernels share one region, so both reports follow it
     assert ps.source_digest("k_mg") == ps.source_digest(ps._source_key("k_mg_down<float"))
 
