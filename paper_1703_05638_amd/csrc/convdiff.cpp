@@ -21,6 +21,7 @@ void Problem::set_convection(double nu, double w, double delta) {
   if (!(nu > 0.0)) {
     cd_on = false;
     cd_nu = cd_w = cd_delta = 0.0;
+    poles_low_.clear();
     init_st_poles(2.0 * M_PI * M_PI, 24.0 / (h * h));
     return;
   }
@@ -69,16 +70,22 @@ void Problem::set_convection(double nu, double w, double delta) {
   // nu (M1^{-1} K1) along x1, so within [(D + nu) kappa_1 / mu_1, (D + nu) 12 / h^2);
   // the skew part w C1 (x) M1 has ||M^{-1/2} (C1 (x) M1) M^{-1/2}|| <=
   // ||C1|| / lambda_min(M1) < 3 / h.  Poles over the larger of the two
-  // scales, twice as many as for the heat operator: transport keeps the
-  // space-time solutions' rank higher (at 32^2, nt = 90 a rank-one initial
-  // state gives rank 21 at 1e-8 against 11 for the heat equation), and a
-  // rank-one source gets one basis column per pole (measured: 13 poles leave
-  // a relative error of 1.4e-3, 26 poles 5e-6)
+  // scales, more than for the heat operator: transport keeps the space-time
+  // solutions' rank higher (at 32^2, nt = 90 a rank-one initial state gives
+  // rank 21 at 1e-8 against 11 for the heat equation), and a source of rank
+  // one gets one basis column per pole.  Measured in a CPU emulation of the
+  // solver at 32^2, nu = 1e-3 and 1e-2, nt = 90, tol 1e-8: rank-one sources
+  // keep a relative error of 2e-3 with the heat operator's 13 poles, 5e-6
+  // with 26 and 3-4e-7 with 52; the adjoint sources (rank 20-30) 3e-6 with
+  // 13 and 3e-8 with 20.  So sources of rank <= 2 take four times the heat
+  // operator's count, the others one and a half times.
   const double D = nu + delta * w * w;
   const double lam_min = (D + nu) * cd_kap_h_[0] / cd_mu_h_[0];
   const double lam_sym = (D + nu) * 12.0 / (h * h);
   const double skew = 3.0 * std::abs(w) / h;
-  init_st_poles(lam_min, std::max(lam_sym, skew), 2.0);
+  init_st_poles(lam_min, std::max(lam_sym, skew), 4.0);
+  poles_low_ = poles;
+  init_st_poles(lam_min, std::max(lam_sym, skew), 1.5);
   // Newton-Schulz for the projected A = I + Kt, Kt = Q^T tau L Q with Q
   // M-orthonormal: the field of values of A lies in the rectangle
   // [1, 1 + s] x i[-b, b], s = tau lam_sym, b = tau skew (5% margin for the

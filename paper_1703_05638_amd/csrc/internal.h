@@ -256,6 +256,7 @@ class Problem {
   void spacetime_solve(const LowRank& F, LowRank& Y, bool adjoint);
   // The same for several sources, with all pole solves in one multigrid solve.
   void spacetime_solve_batch(const std::vector<const LowRank*>& F, const std::vector<LowRank*>& Y, bool adjoint);
+  void st_solve_group(const std::vector<const LowRank*>& F, const std::vector<LowRank*>& Y, bool adjoint);
   // the initial-condition problem (ic.cpp): observed nodes from a mask, the
   // prior-preconditioned misfit Hessian G = c sigma^-2 C^T K^-T B^T B K^-1 C
   // on initial states (C = e_1 kron M), its leading eigenpairs and the
@@ -368,6 +369,8 @@ class Problem {
   // sine matrix (n x n), sine-mode mass and stiffness eigenvalues (n), the
   // per-column shifts and stencil weights, the transform buffer, and the
   // buffer of tau L Q for the projected operator
+  // a larger pole set for sources of rank <= 2 (empty: the base set for all)
+  std::vector<double> poles_low_;
   double cd_ns_alpha_ = 1.0;
   int cd_ns_iters_ = 1;
   DevMem cd_S_, cd_mu_, cd_kap_, cd_ab_, cd_wt_, cd_tmp_, st_lq_;

@@ -1037,6 +1037,41 @@ void Problem::spacetime_solve(const LowRank& F, LowRank& Y, bool adjoint) {
 void Problem::spacetime_solve_batch(const std::vector<const LowRank*>& F, const std::vector<LowRank*>& Y,
                                     bool adjoint) {
   cd_sign = adjoint ? -1 : 1;  // the adjoint solves carry the transposed spatial operator
+  if (poles_low_.empty()) {
+    st_solve_group(F, Y, adjoint);
+    return;
+  }
+  // sources of rank at most 2 (one basis column per pole and source column)
+  // are solved with the larger pole set of low-rank sources, the others with
+  // the base set; each source's result depends on its own rank only
+  std::vector<const LowRank*> Fl, Fh;
+  std::vector<LowRank*> Yl, Yh;
+  for (size_t j = 0; j < F.size(); ++j) {
+    if (F[j]->rank <= 2) {
+      Fl.push_back(F[j]);
+      Yl.push_back(Y[j]);
+    } else {
+      Fh.push_back(F[j]);
+      Yh.push_back(Y[j]);
+    }
+  }
+  if (!Fl.empty()) {
+    const std::vector<double> base = poles;
+    poles = poles_low_;
+    try {
+      st_solve_group(Fl, Yl, adjoint);
+    } catch (...) {
+      poles = base;
+      throw;
+    }
+    poles = base;
+  }
+  if (!Fh.empty()) st_solve_group(Fh, Yh, adjoint);
+}
+
+// One group of sources with the current pole set: a pass, then the residual
+// check and at most one enrichment (see spacetime_solve_batch).
+void Problem::st_solve_group(const std::vector<const LowRank*>& F, const std::vector<LowRank*>& Y, bool adjoint) {
   st_solve_pass(F, Y, adjoint);
   if (st_check == 0) return;
   const int nb = (int)F.size();
