@@ -77,6 +77,18 @@ class ICProblem:
             Y[:, k] = y
         return Y
 
+    def forward_source(self, F):
+        """Y = K_st^{-1} vec(F) for a space-time source F (nx, nt): forward in
+        time, (M + tau L) y_k = M y_{k-1} + f_k, y_0 = 0 (eq. st_pde with a
+        general right-hand side)."""
+        F = np.asarray(F, dtype=np.float64)
+        Y = np.zeros((self.nx, self.nt))
+        y = np.zeros(self.nx)
+        for k in range(self.nt):
+            y = self.step_solve(self.M @ y + F[:, k])
+            Y[:, k] = y
+        return Y
+
     def adjoint(self, Z):
         """P = K_st^{-T} vec(Z): backward in time, (M + tau L)^T p_k = M p_{k+1} + z_k, p_{nt+1} = 0."""
         Z = np.asarray(Z, dtype=np.float64)

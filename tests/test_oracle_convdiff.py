@@ -131,3 +131,19 @@ def test_woodbury_variance_with_convection():
     p = cd_ic_problem(8, 6, 1e-3)
     lam, V = p.eig()
     assert np.allclose(p.post_var_lowrank(lam, V), p.post_var_exact(), rtol=1e-10, atol=1e-12)
+
+
+def test_source_solves_equal_the_all_at_once_system():
+    """Forward steps with a general source, and the transposed adjoint steps,
+    equal sparse solves with K_st = I kron tau L + C_t kron M and its
+    transpose (eq. st_pde)."""
+    import scipy.sparse.linalg as spla
+    p = cd_ic_problem(10, 6, 1e-3)
+    rng = np.random.default_rng(11)
+    F = rng.standard_normal((p.nx, p.nt))
+    Ct = sp.eye(p.nt) - sp.eye(p.nt, k=-1)
+    Kst = (sp.kron(sp.eye(p.nt), p.tau * p.L) + sp.kron(Ct, p.M)).tocsc()
+    fwd = spla.spsolve(Kst, F.T.reshape(-1)).reshape(p.nt, p.nx).T
+    adj = spla.spsolve(Kst.T.tocsc(), F.T.reshape(-1)).reshape(p.nt, p.nx).T
+    assert np.abs(p.forward_source(F) - fwd).max() <= 1e-12 * np.abs(fwd).max()
+    assert np.abs(p.adjoint(F) - adj).max() <= 1e-12 * np.abs(adj).max()
