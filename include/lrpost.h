@@ -443,6 +443,17 @@ int lrpost_ic_post_variance(lrpost_problem* p, double prior_var, int k, const do
  * operator is symmetric), one tridiagonal system along x2 per sine mode, and
  * the inverse transform. */
 int lrpost_set_convection(lrpost_problem* p, double nu, double wind, double delta);
+/* Host settings of the convection-diffusion operator for a mesh of N cells
+ * per side and nt steps over [0, T] (no problem, no device work): out[0]
+ * delta (the Peclet rule when delta < 0), out[1], out[2] the rectangle
+ * [1, out[1]] x i[-out[2], out[2]] that holds the field of values of every
+ * projected I + tau Q^T L Q with Q^T M Q = I, out[3] the Newton-Schulz start
+ * alpha (X_0 = alpha I), out[4] the bound r < 1 of the numerical radius of
+ * I - alpha (I + tau Q^T L Q), out[5] the step count (2 r^(2^k) <= 1e-18),
+ * out[6] the lower spectral bound of the symmetric part of M^{-1} L.
+ * out: host, 7 doubles.  N < 2, nt < 1, T <= 0, nu <= 0 or non-finite
+ * values: LRPOST_EINVAL. */
+int lrpost_convdiff_params(int N, int nt, double T, double nu, double wind, double delta, double* out);
 /* Building blocks for kernel-level parity tests (DEVICE float64 buffers, nx x
  * ncols column-major, leading dimension nx; coef: host, 2 ncols doubles
  * (a_j, b_j)):

@@ -685,6 +685,17 @@ int lrpost_ic_post_variance(lrpost_problem* p, double prior_var, int k, const do
   });
 }
 
+int lrpost_convdiff_params(int N, int nt, double T, double nu, double wind, double delta, double* out) {
+  return guarded([&] {
+    if (N < 2 || nt < 1 || !(T > 0.0) || !(nu > 0.0) || !std::isfinite(T) || !std::isfinite(nu) ||
+        !std::isfinite(wind) || !std::isfinite(delta) || !out)
+      fail(LRPOST_EINVAL, "bad arguments");
+    const CdParams c = cd_params(N, nt, T, nu, wind, delta);
+    const double v[7] = {c.delta, c.fov_re, c.fov_im, c.ns_alpha, c.ns_radius, (double)c.ns_iters, c.lam_min};
+    std::copy(v, v + 7, out);
+  });
+}
+
 int lrpost_set_convection(lrpost_problem* p, double nu, double wind, double delta) {
   return guarded([&] {
     Problem* P = impl(p);

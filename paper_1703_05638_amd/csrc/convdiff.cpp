@@ -16,6 +16,60 @@
 
 namespace lrp {
 
+// Host settings of the operator on the N x N mesh with nt steps over [0, T]
+// (no device work; exported for checks without a GPU).
+CdParams cd_params(int N, int nt, double T, double nu, double w, double delta) {
+  CdParams c{};
+  const double h = 1.0 / N, tau = T / nt;
+  if (delta < 0.0) {
+    // element Peclet number of the square elements along the wind (the
+    // element's length along the wind is h): delta = h / (2|w|) (1 - 1/Pe)
+    // for Pe = |w| h / (2 nu) > 1, else 0
+    const double wn = std::abs(w);
+    const double pe = wn * h / (2.0 * nu);
+    delta = (wn > 0.0 && pe > 1.0) ? h / (2.0 * wn) * (1.0 - 1.0 / pe) : 0.0;
+  }
+  c.delta = delta;
+  // Spectrum of the symmetric part of M^{-1} L: D (M1^{-1} K1) along x2 plus
+  // nu (M1^{-1} K1) along x1, so within [(D + nu) kappa_1 / mu_1, (D + nu) 12 / h^2);
+  // the skew part w C1 (x) M1 has ||M^{-1/2} (C1 (x) M1) M^{-1/2}|| <=
+  // ||C1|| / lambda_min(M1) < 3 / h.
+  const double D = nu + delta * w * w;
+  const double th = M_PI * h;
+  const double kap1 = (4.0 / h) * std::sin(th / 2) * std::sin(th / 2), mu1 = (h / 3.0) * (2.0 + std::cos(th));
+  c.lam_min = (D + nu) * kap1 / mu1;
+  c.lam_sym = (D + nu) * 12.0 / (h * h);
+  c.skew = 3.0 * std::abs(w) / h;
+  // Newton-Schulz for the projected A = I + Kt, Kt = Q^T tau L Q with Q
+  // M-orthonormal: the field of values of A lies in the rectangle
+  // [1, 1 + s] x i[-b, b], s = tau lam_sym, b = tau skew (5% margin for the
+  // rounding of the basis).  With X_0 = alpha I the error I - A X_k is
+  // (I - alpha A)^(2^k), whose numerical radius is at most r^(2^k), r the
+  // largest |1 - alpha z| over the rectangle (attained at a corner: the
+  // modulus is convex), and its norm at most twice that.  alpha minimizes r.
+  const double s = 1.05 * tau * c.lam_sym, b = 1.05 * tau * c.skew;
+  c.fov_re = 1.0 + s;
+  c.fov_im = b;
+  auto radius = [&](double a) {
+    double r2 = 0.0;
+    for (double x : {1.0, 1.0 + s}) r2 = std::max(r2, (1.0 - a * x) * (1.0 - a * x) + a * a * b * b);
+    return std::sqrt(r2);
+  };
+  double lo = 0.0, hi = 2.0 / (1.0 + s);
+  for (int it = 0; it < 200; ++it) {
+    const double m1 = lo + (hi - lo) / 3.0, m2 = hi - (hi - lo) / 3.0;
+    if (radius(m1) < radius(m2)) hi = m2;
+    else lo = m1;
+  }
+  c.ns_alpha = 0.5 * (lo + hi);
+  c.ns_radius = radius(c.ns_alpha);
+  // 2 r^(2^k) <= 1e-18, plus one step
+  c.ns_iters = c.ns_radius > 0.0 && c.ns_radius < 1.0
+                   ? std::max(1, (int)std::ceil(std::log2(std::log(5e-19) / std::log(c.ns_radius))) + 1)
+                   : 1;
+  return c;
+}
+
 void Problem::set_convection(double nu, double w, double delta) {
   sync();
   if (!(nu > 0.0)) {
@@ -27,14 +81,9 @@ void Problem::set_convection(double nu, double w, double delta) {
   }
   if (!std::isfinite(nu) || !std::isfinite(w) || !std::isfinite(delta))
     fail(LRPOST_EINVAL, "convection parameters must be finite");
-  if (delta < 0.0) {
-    // element Peclet number of the square elements along the wind (the
-    // element's length along the wind is h): delta = h / (2|w|) (1 - 1/Pe)
-    // for Pe = |w| h / (2 nu) > 1, else 0
-    const double wn = std::abs(w);
-    const double pe = wn * h / (2.0 * nu);
-    delta = (wn > 0.0 && pe > 1.0) ? h / (2.0 * wn) * (1.0 - 1.0 / pe) : 0.0;
-  }
+  const CdParams cp = cd_params(N, nt, desc.T, nu, w, delta);
+  if (!(cp.ns_radius < 1.0)) fail(LRPOST_EINVAL, "convection operator: no convergent Newton-Schulz start");
+  delta = cp.delta;
   cd_nu = nu;
   cd_w = w;
   cd_delta = delta;
@@ -66,50 +115,22 @@ void Problem::set_convection(double nu, double w, double delta) {
     to_device(cd_kap_.as<double>(), cd_kap_h_.data(), n);
     sync();
   }
-  // Spectrum of the symmetric part of M^{-1} L: D (M1^{-1} K1) along x2 plus
-  // nu (M1^{-1} K1) along x1, so within [(D + nu) kappa_1 / mu_1, (D + nu) 12 / h^2);
-  // the skew part w C1 (x) M1 has ||M^{-1/2} (C1 (x) M1) M^{-1/2}|| <=
-  // ||C1|| / lambda_min(M1) < 3 / h.  Poles over the larger of the two
-  // scales, more than for the heat operator: transport keeps the space-time
-  // solutions' rank higher (at 32^2, nt = 90 a rank-one initial state gives
-  // rank 21 at 1e-8 against 11 for the heat equation), and a source of rank
-  // one gets one basis column per pole.  Measured in a CPU emulation of the
-  // solver at 32^2, nu = 1e-3 and 1e-2, nt = 90, tol 1e-8: rank-one sources
-  // keep a relative error of 2e-3 with the heat operator's 13 poles, 5e-6
-  // with 26 and 3-4e-7 with 52; the adjoint sources (rank 20-30) 3e-6 with
-  // 13 and 3e-8 with 20.  So sources of rank <= 2 take four times the heat
+  // Poles over the larger of the symmetric and skew scales (cd_params), more
+  // than for the heat operator: transport keeps the space-time solutions'
+  // rank higher (at 32^2, nt = 90 a rank-one initial state gives rank 21 at
+  // 1e-8 against 11 for the heat equation), and a source of rank one gets
+  // one basis column per pole.  Measured in a CPU emulation of the solver at
+  // 32^2, nu = 1e-3 and 1e-2, nt = 90, tol 1e-8: rank-one sources keep a
+  // relative error of 2e-3 with the heat operator's 13 poles, 5e-6 with 26
+  // and 3-4e-7 with 52; the adjoint sources (rank 20-30) 3e-6 with 13 and
+  // 3e-8 with 20.  So sources of rank <= 2 take four times the heat
   // operator's count, the others one and a half times.
-  const double D = nu + delta * w * w;
-  const double lam_min = (D + nu) * cd_kap_h_[0] / cd_mu_h_[0];
-  const double lam_sym = (D + nu) * 12.0 / (h * h);
-  const double skew = 3.0 * std::abs(w) / h;
-  init_st_poles(lam_min, std::max(lam_sym, skew), 4.0);
+  init_st_poles(cp.lam_min, std::max(cp.lam_sym, cp.skew), 4.0);
   poles_low_ = poles;
-  init_st_poles(lam_min, std::max(lam_sym, skew), 1.5);
-  // Newton-Schulz for the projected A = I + Kt, Kt = Q^T tau L Q with Q
-  // M-orthonormal: the field of values of A lies in the rectangle
-  // [1, 1 + s] x i[-b, b], s = tau lam_sym, b = tau skew (5% margin for the
-  // rounding of the basis).  With X_0 = alpha I the error I - A X_k is
-  // (I - alpha A)^(2^k), whose numerical radius is at most r^(2^k), r the
-  // largest |1 - alpha z| over the rectangle (attained at a corner: the
-  // modulus is convex), and its norm at most twice that.  alpha minimizes r.
-  const double s = 1.05 * tau * lam_sym, b = 1.05 * tau * skew;
-  auto radius = [&](double a) {
-    double r2 = 0.0;
-    for (double x : {1.0, 1.0 + s}) r2 = std::max(r2, (1.0 - a * x) * (1.0 - a * x) + a * a * b * b);
-    return std::sqrt(r2);
-  };
-  double lo = 0.0, hi = 2.0 / (1.0 + s);
-  for (int it = 0; it < 200; ++it) {
-    const double m1 = lo + (hi - lo) / 3.0, m2 = hi - (hi - lo) / 3.0;
-    if (radius(m1) < radius(m2)) hi = m2;
-    else lo = m1;
-  }
-  cd_ns_alpha_ = 0.5 * (lo + hi);
-  const double r = radius(cd_ns_alpha_);
-  if (!(r < 1.0)) fail(LRPOST_EINVAL, "convection operator: no convergent Newton-Schulz start");
-  // 2 r^(2^k) <= 1e-18, plus one step
-  cd_ns_iters_ = r > 0.0 ? std::max(1, (int)std::ceil(std::log2(std::log(5e-19) / std::log(r))) + 1) : 1;
+  init_st_poles(cp.lam_min, std::max(cp.lam_sym, cp.skew), 1.5);
+  // Newton-Schulz start and step count of the non-symmetric projected problem
+  cd_ns_alpha_ = cp.ns_alpha;
+  cd_ns_iters_ = cp.ns_iters;
 }
 
 void Problem::cd_apply(int ncols, const double* X, double* Y, const std::vector<ShiftCoef>& ab, int sign) {

@@ -127,6 +127,17 @@ struct ShiftCoef {
   double a, b;
 };
 
+// Host settings of the convection-diffusion operator (convdiff.cpp): delta
+// (from the Peclet rule when given < 0), the symmetric part's spectrum bounds
+// of M^{-1} L and the skew part's bound, the rectangle [1, fov_re] x
+// i[-fov_im, fov_im] holding the field of values of the projected I + tau K~,
+// and the Newton-Schulz start, its radius bound and step count.
+struct CdParams {
+  double delta, lam_min, lam_sym, skew, fov_re, fov_im, ns_alpha, ns_radius;
+  int ns_iters;
+};
+CdParams cd_params(int N, int nt, double T, double nu, double w, double delta);
+
 class Problem {
  public:
   explicit Problem(const lrpost_problem_desc& d);

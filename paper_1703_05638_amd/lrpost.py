@@ -37,6 +37,14 @@ class LrpostError(RuntimeError):
         self.code = code
 
 
+def convdiff_params(N: int, nt: int, T: float, nu: float, wind: float = 1.0, delta: float = -1.0) -> dict:
+    """Host settings of the convection-diffusion operator (no GPU needed)."""
+    out = np.zeros(7)
+    _check(_lib.lrpost_convdiff_params(int(N), int(nt), float(T), float(nu), float(wind), float(delta), _hptr(out)))
+    return {"delta": out[0], "fov_re": out[1], "fov_im": out[2], "ns_alpha": out[3], "ns_radius": out[4],
+            "ns_iters": int(out[5]), "lam_min": out[6]}
+
+
 class Desc(ctypes.Structure):
     _fields_ = [
         ("N", ctypes.c_int32), ("nt", ctypes.c_int32), ("T", ctypes.c_double), ("alpha", ctypes.c_double),
@@ -121,6 +129,7 @@ def load(path: str = LIB_PATH):
         "lrpost_ic_eigensolve": (I, [P, D, I, I, D, pd, P, ctypes.POINTER(ctypes.c_int)]),
         "lrpost_ic_post_variance": (I, [P, D, I, pd, P, P, I]),
         "lrpost_set_convection": (I, [P, D, D, D]),
+        "lrpost_convdiff_params": (I, [I, I, D, D, D, D, pd]),
         "lrpost_convdiff_apply": (I, [P, I, P, P, pd, I]),
         "lrpost_convdiff_solve": (I, [P, I, P, P, pd, I]),
         "lrpost_set_apply_batch": (I, [P, I]),
