@@ -185,3 +185,41 @@ def test_convdiff_spacetime_solve_low_rank_source(lp, adjoint, rank):
     print("convdiff spacetime rel err %.3e rank %d residual %.3e enriched %d" %
           (err, Y1.shape[0], st["last_st_presid"], st["st_enrichments"]), flush=True)
     assert err <= 100 * tol
+
+
+def test_no_wind_convection_path_equals_the_multigrid_heat_path(lp):
+    """nu = 1, no wind: the convection path (sine transform and tridiagonal
+    solves, non-symmetric projected problem) gives the heat operator's G,
+    which the same problem computes through its multigrid solves when the
+    convection operator is switched off: two independent spatial solvers."""
+    import torch
+    print("case convdiff no wind vs heat N=32 nt=12", flush=True)
+    N, nt, sigma, c = 32, 12, 0.03, 10.0
+    prob = _problem(lp, N, nt, sigma)
+    rng = np.random.default_rng(21)
+    U = torch.tensor(rng.standard_normal((2, prob.nx)), device="cuda")
+    heat = prob.ic_apply(U, c).cpu().numpy()
+    prob.set_convection(1.0, 0.0)
+    cd = prob.ic_apply(U, c).cpu().numpy()
+    err = np.abs(cd - heat).max() / np.abs(heat).max()
+    print("no-wind convection vs heat rel err %.3e" % err, flush=True)
+    assert err < 1e-8
+
+
+def test_reversed_wind_matches_oracle(lp):
+    """Wind (0, -1): the convection sign in the stencil, the tridiagonal
+    systems and the adjoint's transpose."""
+    import torch
+    print("case convdiff reversed wind N=32 nt=12", flush=True)
+    N, nt, sigma, c, nu = 32, 12, 0.03, 10.0, 1e-3
+    prob = _problem(lp, N, nt, sigma)
+    prob.set_convection(nu, -1.0)
+    ora = cd_ic_problem(N, nt, nu, wind=(0.0, -1.0), sigma=sigma, prior_var=c)
+    rng = np.random.default_rng(22)
+    U = rng.standard_normal((2, ora.nx))
+    Y = prob.ic_apply(torch.tensor(U, device="cuda"), c).cpu().numpy()
+    for j in range(2):
+        ref = ora.G(U[j])
+        err = np.abs(Y[j] - ref).max() / np.abs(ref).max()
+        print("reversed wind rel err %.3e" % err, flush=True)
+        assert err < 1e-8
