@@ -6,11 +6,18 @@
 #include "dense.h"
 
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <limits>
 #include <numeric>
 
 namespace lrp {
+
+namespace {
+inline double dot4(const double* x, const double* y, int len);
+void householder_reduce(int m, int n, std::vector<double>& W, std::vector<std::vector<double>>* vs,
+                        std::vector<double>& betas);
+}  // namespace
 
 void matmul(int m, int n, int k, const double* A, int lda, bool ta, const double* B, int ldb, bool tb, double* C,
             int ldc, double alpha, double beta) {
@@ -230,24 +237,30 @@ static void jacobi_columns(int m, int n, double* A, double* V) {
 }
 
 void svd(int m, int n, const double* A, int lda, std::vector<double>& s, std::vector<double>& U,
-         std::vector<double>& V) {
-  // A = U diag(s) V^T, U: m x r, V: n x r, r = min(m, n), s descending
+         std::vector<double>& V, const std::function<int(const std::vector<double>&)>& keep) {
+  // A = U diag(s) V^T, U: m x r, V: n x r, r = min(m, n), s descending; with
+  // keep, only the first keep(s) columns of U and V are formed
   const bool tr = m < n;
   const int mm = tr ? n : m, nn = tr ? m : n;
   std::vector<double> W((size_t)mm * nn), Vw((size_t)nn * nn);
   for (int j = 0; j < nn; ++j)
     for (int i = 0; i < mm; ++i) W[(size_t)j * mm + i] = tr ? A[(size_t)i * lda + j] : A[(size_t)j * lda + i];
-  // precondition by a Householder QR when tall, so Jacobi works on nn x nn
-  std::vector<double> Qh;
-  if (mm > 2 * nn) {
-    std::vector<double> R((size_t)nn * nn);
-    householder_qr(mm, nn, W.data(), mm, Qh, R);
-    W = R;
+  // precondition by a Householder QR when tall, so Jacobi works on nn x nn;
+  // the reflectors are kept and applied to the left vectors that are wanted
+  const bool tall = mm > 2 * nn;
+  std::vector<std::vector<double>> refl;
+  std::vector<double> betas;
+  if (tall) {
+    householder_reduce(mm, nn, W, &refl, betas);
+    std::vector<double> R((size_t)nn * nn, 0.0);
+    for (int j = 0; j < nn; ++j)
+      for (int i = 0; i <= j; ++i) R[(size_t)j * nn + i] = W[(size_t)j * mm + i];
+    W.swap(R);
     jacobi_columns(nn, nn, W.data(), Vw.data());
   } else {
     jacobi_columns(mm, nn, W.data(), Vw.data());
   }
-  const int wrows = Qh.empty() ? mm : nn;
+  const int wrows = tall ? nn : mm;
   std::vector<double> sv(nn);
   for (int j = 0; j < nn; ++j) {
     double t = 0.0;
@@ -257,22 +270,30 @@ void svd(int m, int n, const double* A, int lda, std::vector<double>& s, std::ve
   std::vector<int> idx(nn);
   std::iota(idx.begin(), idx.end(), 0);
   std::sort(idx.begin(), idx.end(), [&](int x, int y) { return sv[x] > sv[y]; });
-  // left vectors of the (possibly reduced) matrix
-  std::vector<double> Ul((size_t)wrows * nn), Vr((size_t)nn * nn);
   s.assign(nn, 0.0);
-  for (int jj = 0; jj < nn; ++jj) {
+  for (int jj = 0; jj < nn; ++jj) s[jj] = sv[idx[jj]];
+  const int k = keep ? std::max(0, std::min(nn, keep(s))) : nn;
+  // the first k left vectors of the (possibly reduced) matrix and right vectors
+  std::vector<double> Ufull((size_t)mm * k, 0.0), Vr((size_t)nn * k);
+  for (int jj = 0; jj < k; ++jj) {
     const int j = idx[jj];
-    s[jj] = sv[j];
-    for (int i = 0; i < wrows; ++i) Ul[(size_t)jj * wrows + i] = sv[j] > 0 ? W[(size_t)j * wrows + i] / sv[j] : 0.0;
+    for (int i = 0; i < wrows; ++i) Ufull[(size_t)jj * mm + i] = sv[j] > 0 ? W[(size_t)j * wrows + i] / sv[j] : 0.0;
     for (int i = 0; i < nn; ++i) Vr[(size_t)jj * nn + i] = Vw[(size_t)j * nn + i];
   }
-  // zero singular values: complete the left vectors with an orthonormal basis is not needed by callers
-  std::vector<double> Ufull;
-  if (!Qh.empty()) {
-    Ufull.assign((size_t)mm * nn, 0.0);
-    matmul(mm, nn, nn, Qh.data(), mm, false, Ul.data(), nn, false, Ufull.data(), mm, 1.0, 0.0);
-  } else {
-    Ufull.swap(Ul);
+  // (zero singular values: the left vectors stay zero; callers do not need
+  // them completed to an orthonormal basis)
+  if (tall) {
+    // Q [Ul; 0]: the reflectors applied last to first
+    for (int r = nn - 1; r >= 0; --r) {
+      if (betas[r] == 0.0) continue;
+      const std::vector<double>& v = refl[r];
+      const int len = mm - r;
+      for (int jj = 0; jj < k; ++jj) {
+        double* x = Ufull.data() + (size_t)jj * mm + r;
+        const double sdot = betas[r] * dot4(v.data(), x, len);
+        for (int i = 0; i < len; ++i) x[i] -= sdot * v[i];
+      }
+    }
   }
   if (!tr) {
     U.swap(Ufull);

@@ -1,6 +1,7 @@
 // Small dense float64 linear algebra on the host (column-major).
 #pragma once
 #include <cstddef>
+#include <functional>
 #include <vector>
 
 namespace lrp {
@@ -14,9 +15,11 @@ void upper_inverse(int n, const double* R, double* Ri);
 
 // Symmetric eigensolver: eigenvalues ascending in w, eigenvectors in V (n x n).
 bool syev(int n, const double* A, int lda, double* w, double* V);
-// Thin SVD A = U diag(s) V^T (U m x r, V n x r, r = min(m, n)), s descending.
+// Thin SVD A = U diag(s) V^T (U m x r, V n x r, r = min(m, n)), s descending,
+// by one-sided Jacobi (after a Householder QR when A is tall or wide).  With
+// keep, U and V hold only their first keep(s) columns (keep sees s).
 void svd(int m, int n, const double* A, int lda, std::vector<double>& s, std::vector<double>& U,
-         std::vector<double>& V);
+         std::vector<double>& V, const std::function<int(const std::vector<double>&)>& keep = nullptr);
 // Householder QR A (m x n) = Q (m x K) R (K x n), K = min(m, n), R upper trapezoidal.
 void householder_qr(int m, int n, const double* A, int lda, std::vector<double>& Q, std::vector<double>& R);
 void householder_r(int m, int n, const double* A, int lda, std::vector<double>& R);

@@ -1818,7 +1818,12 @@ void Problem::st_truncate(std::vector<StFin>& fins, const std::vector<LowRank*>&
       to_host(Zhs[j].data(), fins[j].Zp.as<double>(), Zhs[j].size());
     }
     host_parallel(nb, [&](int j) {
-      if (fins[j].q > 0) svd(fins[j].q, nt, Zhs[j].data(), fins[j].q, svs[j], Uzs[j], Vzs[j]);
+      // only the kept singular vectors are formed
+      if (fins[j].q > 0)
+        svd(fins[j].q, nt, Zhs[j].data(), fins[j].q, svs[j], Uzs[j], Vzs[j], [&](const std::vector<double>& sv) {
+          double t = 0.0;
+          return truncation_rank(sv, desc.trunc_tol, desc.rank_cap, &t);
+        });
     });
     for (int j = 0; j < nb; ++j) {
       const int q = fins[j].q;
