@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 CSV output for the library's kernels.
 
-Two modes, each printing a short text report:
+Modes, each printing a short text report:
 
   python -m paper_1703_05638_amd.profile_summary stats DIR REGEX
       kernel-trace statistics (``*_kernel_stats.csv``): the kernels by total
@@ -23,6 +23,11 @@ Two modes, each printing a short text report:
       average readings per dispatch are divided by them.  The report records
       a digest of the kernel's source so that a reader can tell when the
       figure no longer describes the kernel.
+
+  python -m paper_1703_05638_amd.profile_summary counters DIR 'REGEX[;REGEX...]'
+      counter collection (``*_counter_collection.csv``) of one --pmc run: per
+      kernel regex the number of dispatches and the sum of every collected
+      counter over them.
 """
 import csv
 import glob
@@ -204,11 +209,25 @@ def read_traffic(path):
         return None
 
 
+def counters(d, regexes):
+    """Per kernel (one regex each, separated by ';'): dispatches and the sum
+    of every counter of a rocprofv3 --pmc run over them."""
+    rows = _rows(d, "counter_collection.csv")
+    names = sorted({r["Counter_Name"] for r in rows})
+    for regex in regexes.split(";"):
+        n = len(_per_dispatch(rows, regex, names[0])) if names else 0
+        print("%s: dispatches %d" % (regex, n))
+        for c in names:
+            print("  %s sum %.6e" % (c, sum(_per_dispatch(rows, regex, c))))
+
+
 if __name__ == "__main__":
     if len(sys.argv) >= 4 and sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3])
     elif len(sys.argv) >= 4 and sys.argv[1] == "busy":
         busy(sys.argv[2], sys.argv[3])
+    elif len(sys.argv) >= 4 and sys.argv[1] == "counters":
+        counters(sys.argv[2], sys.argv[3])
     elif len(sys.argv) >= 7 and sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], int(sys.argv[6]))
     else:
