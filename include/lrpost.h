@@ -554,6 +554,17 @@ int lrpost_server_info(lrpost_server* s, int* peak_running, size_t* peak_admitte
 int lrpost_server_class_stats(lrpost_server* s, int64_t* served, int64_t* resident_hits);
 int lrpost_server_destroy(lrpost_server* s);
 
+/* Attainable float64 rates of the current device (instrumentation; no
+ * passage of the paper): times v_mfma_f64_16x16x4f64 (the instruction of the
+ * float64 Gram, projection and sine-transform kernels) and the vector FMA
+ * with operands in registers only, each over 2048 workgroups of 256 threads
+ * and `iters` (1..100000) unrolled rounds, best of three launches after one
+ * untimed.  out[0] = matrix-core TFLOP/s, out[1] = vector-FMA TFLOP/s (host
+ * memory, two doubles).  Allocates and frees 4 MiB of device memory and a
+ * stream of its own; synchronizes.  EINVAL for iters out of range or a NULL
+ * out, EHIP for a failed HIP call. */
+int lrpost_measure_fp64_rates(int iters, double* out);
+
 const char* lrpost_last_error(void);
 const char* lrpost_version(void);
 

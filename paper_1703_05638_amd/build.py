@@ -14,7 +14,7 @@ OUT = os.path.join(HERE, "liblrpost.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["kernels.hip", "dense.cpp", "gpu_dense.cpp", "problem.cpp", "eigen.cpp", "ic.cpp", "convdiff.cpp", "api.cpp",
-           "server.cpp"]
+           "server.cpp", "rates.hip"]
 ARCH = os.environ.get("LRPOST_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

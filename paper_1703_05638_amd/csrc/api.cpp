@@ -96,6 +96,13 @@ extern "C" {
 const char* lrpost_last_error(void) { return g_last_error.c_str(); }
 const char* lrpost_version(void) { return "lrpost 0.1 (gfx950)"; }
 
+int lrpost_measure_fp64_rates(int iters, double* out) {
+  return guarded([&] {
+    if (!out) fail(LRPOST_EINVAL, "rate probe: null output");
+    measure_fp64_rates(iters, &out[0], &out[1]);
+  });
+}
+
 int lrpost_create(const lrpost_problem_desc* desc, lrpost_problem** out) {
   return guarded([&] {
     if (!desc || !out) fail(LRPOST_EINVAL, "null argument");

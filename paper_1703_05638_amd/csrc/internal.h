@@ -25,6 +25,9 @@ struct Error : std::runtime_error {
 };
 [[noreturn]] void fail(int code, const std::string& msg);
 
+// matrix-core and vector-FMA float64 TFLOP/s of the current device (rates.hip)
+void measure_fp64_rates(int iters, double* mfma_tflops, double* valu_tflops);
+
 #define LRP_HIP(call)                                                                              \
   do {                                                                                             \
     hipError_t e_ = (call);                                                                        \

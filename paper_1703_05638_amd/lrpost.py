@@ -142,6 +142,7 @@ def load(path: str = LIB_PATH):
         "lrpost_server_info": (I, [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_size_t)]),
         "lrpost_server_destroy": (I, [P]),
         "lrpost_server_class_stats": (I, [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+        "lrpost_measure_fp64_rates": (I, [I, pd]),
         "lrpost_last_error": (ctypes.c_char_p, []),
         "lrpost_version": (ctypes.c_char_p, []),
     }
@@ -191,6 +192,14 @@ def autotune_report() -> str:
     buf = ctypes.create_string_buffer(n + 1)
     lib.lrpost_autotune_report(buf, n + 1)
     return buf.value.decode()
+
+
+def measure_fp64_rates(iters: int = 4000) -> dict:
+    """Attainable float64 TFLOP/s of the current device: the matrix-core
+    instruction of the float64 kernels and the vector FMA, registers only."""
+    out = np.zeros(2)
+    _check(load().lrpost_measure_fp64_rates(int(iters), _hptr(out)))
+    return {"mfma_f64_16x16x4": float(out[0]), "valu_fma_f64": float(out[1])}
 
 
 def set_autotune(on: bool):

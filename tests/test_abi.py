@@ -53,3 +53,7 @@ def test_rejections_before_device_work():
     assert lib.lrpost_set_st_check(None, 1, 0.0) == -1
     res = (ctypes.c_double * 1)()
     assert lib.lrpost_eig_residuals(None, None, res) == -1
+    rates = (ctypes.c_double * 2)()
+    assert lib.lrpost_measure_fp64_rates(0, rates) == -1
+    assert lib.lrpost_measure_fp64_rates(100001, rates) == -1
+    assert lib.lrpost_measure_fp64_rates(10, None) == -1
