@@ -21,6 +21,7 @@
 #include <stdexcept>
 #include <string>
 #include <tuple>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -1093,7 +1094,13 @@ int gram_chunks(long nrows, int m, int q) {
 // grid (8 or 16 waves); each owns (16 BM) x (64 BQ / WQ) of the tile as
 // blocks of v_mfma_f64_16x16x4f64: for the 16 x 4 operand lane l holds
 // element (l % 16, l / 16), for the 4 x 16 operand element (l / 16, l % 16),
-// and the 16 x 16 result element (l / 16 + 4 v, l % 16) in slot v.
+// and the 16 x 16 result element (l / 16 + 4 v, l % 16) in slot v.  The row
+// blocks of the m waves interleave (block a of m-wave wm starts at row
+// 64 a + 16 wm), and on a tile that the product covers only in part each
+// wave skips the products of its blocks that lie wholly outside it: the
+// waves of one m index share a SIMD, so a ragged tile's remaining work stays
+// spread over the four matrix units (the products of 64 rows and fewer than
+// 64 columns, and the last tile of a wide one, are most of the launches).
 // ---------------------------------------------------------------------------
 typedef double gram_d4 __attribute__((ext_vector_type(4)));
 constexpr int GTH = 512;  // threads per workgroup of the 64-wide and float32 tiles
@@ -1134,7 +1141,7 @@ __device__ __forceinline__ void gram_tile(long nrows, long rows_per_chunk, int m
   constexpr int NU = NC / (TH / GK);          // columns per loading thread
   static_assert(NC % (TH / GK) == 0 && GM % (TH / GK) == 0, "loader layout");
   __shared__ double S[2][NC][GK + 1];         // two stages of [column][row]: A columns, then B columns
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave & 3, wq = wave >> 2;
   const long r0 = (long)chunk * rows_per_chunk;
   const long r1 = min(nrows, r0 + rows_per_chunk);
@@ -1176,62 +1183,87 @@ __device__ __forceinline__ void gram_tile(long nrows, long rows_per_chunk, int m
     for (int u = 0; u < NU; ++u) S[buf][lc + (TH / GK) * u][lr] = rv[u] * keep;
   };
   const int ci = lane & 15, ck = lane >> 4;
-  auto mma = [&](int cb) {
+  // blocks of this wave inside the product (wave-uniform)
+  bool va[BM], vb[BW];
+  bool whole = true;
+#pragma unroll
+  for (int a = 0; a < BM; ++a) {
+    va[a] = 64 * a + 16 * wm <= ma;
+    whole = whole && va[a];
+  }
+#pragma unroll
+  for (int b = 0; b < BW; ++b) {
+    vb[b] = wq * 16 * BW + 16 * b <= qb;
+    whole = whole && vb[b];
+  }
+  // MASKED: skip the blocks outside the product (the operands are read
+  // either way: LDS holds every staged column)
+  auto mma_step = [&](int cb, auto masked) {
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 4) {
-      double bf[BW];
+      double bf[BW], af[BM];
 #pragma unroll
       for (int b = 0; b < BW; ++b) bf[b] = S[cb][GM + wq * 16 * BW + 16 * b + ci][kk + ck];
 #pragma unroll
-      for (int a = 0; a < BM; ++a) {
-        const double af = S[cb][wm * 16 * BM + 16 * a + ci][kk + ck];
+      for (int a = 0; a < BM; ++a) af[a] = S[cb][64 * a + 16 * wm + ci][kk + ck];
+#pragma unroll
+      for (int a = 0; a < BM; ++a)
 #pragma unroll
         for (int b = 0; b < BW; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf[b], acc[a][b], 0, 0, 0);
+          if (!decltype(masked)::value || (va[a] && vb[b]))
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+  };
+  // the pipeline over the chunk, with the products of every block or of the
+  // blocks inside the product only
+  auto run = [&](auto masked) {
+    auto mma = [&](int cb) { mma_step(cb, masked); };
+    // AHEAD = 2: while stage it is multiplied out of LDS buffer
+    // it % 2, stage it + 1 is arriving in one register set (issued one stage
+    // earlier) and stage it + 2 is issued into the other; after the products,
+    // stage it + 1 goes to the other LDS buffer (its readers, stage it - 1,
+    // passed the previous barrier): one barrier per stage
+    if constexpr (GramShape<BM, BQ>::AHEAD == 2) {
+      double ra[NU], rb[NU];
+      if (nst > 0) {
+        fetch(0, ra);
+        stage(0, ra, 0);
+      }
+      if (nst > 1) fetch(1, rb);
+      __syncthreads();
+      for (long it = 0; it < nst; it += 2) {
+        if (it + 2 < nst) fetch(it + 2, ra);
+        mma(0);
+        if (it + 1 < nst) stage(it + 1, rb, 1);
+        __syncthreads();
+        if (it + 1 >= nst) break;
+        if (it + 3 < nst) fetch(it + 3, rb);
+        mma(1);
+        if (it + 2 < nst) stage(it + 2, ra, 0);
+        __syncthreads();
+      }
+    } else {
+      // one stage in flight: stage it + 1 arrives in registers while stage it
+      // is multiplied, then goes to the other LDS buffer
+      double rv[NU];
+      if (nst > 0) {
+        fetch(0, rv);
+        stage(0, rv, 0);
+      }
+      __syncthreads();
+      for (long it = 0; it < nst; ++it) {
+        const int cb = (int)(it & 1);
+        if (it + 1 < nst) fetch(it + 1, rv);
+        mma(cb);
+        if (it + 1 < nst) stage(it + 1, rv, cb ^ 1);
+        __syncthreads();
       }
     }
   };
-  // AHEAD = 2: while stage it is multiplied out of LDS buffer
-  // it % 2, stage it + 1 is arriving in one register set (issued one stage
-  // earlier) and stage it + 2 is issued into the other; after the products,
-  // stage it + 1 goes to the other LDS buffer (its readers, stage it - 1,
-  // passed the previous barrier): one barrier per stage
-  if constexpr (GramShape<BM, BQ>::AHEAD == 2) {
-    double ra[NU], rb[NU];
-    if (nst > 0) {
-      fetch(0, ra);
-      stage(0, ra, 0);
-    }
-    if (nst > 1) fetch(1, rb);
-    __syncthreads();
-    for (long it = 0; it < nst; it += 2) {
-      if (it + 2 < nst) fetch(it + 2, ra);
-      mma(0);
-      if (it + 1 < nst) stage(it + 1, rb, 1);
-      __syncthreads();
-      if (it + 1 >= nst) break;
-      if (it + 3 < nst) fetch(it + 3, rb);
-      mma(1);
-      if (it + 2 < nst) stage(it + 2, ra, 0);
-      __syncthreads();
-    }
-  } else {
-    // one stage in flight: stage it + 1 arrives in registers while stage it
-    // is multiplied, then goes to the other LDS buffer
-    double rv[NU];
-    if (nst > 0) {
-      fetch(0, rv);
-      stage(0, rv, 0);
-    }
-    __syncthreads();
-    for (long it = 0; it < nst; ++it) {
-      const int cb = (int)(it & 1);
-      if (it + 1 < nst) fetch(it + 1, rv);
-      mma(cb);
-      if (it + 1 < nst) stage(it + 1, rv, cb ^ 1);
-      __syncthreads();
-    }
-  }
+  if (whole)
+    run(std::false_type{});
+  else
+    run(std::true_type{});
   // partial layout: [chunk] column-major ldp x q
   double* P = part + (long)chunk * ldp * q + row0;
 #pragma unroll
@@ -1240,7 +1272,7 @@ __device__ __forceinline__ void gram_tile(long nrows, long rows_per_chunk, int m
     for (int b = 0; b < BW; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = tm * GM + wm * 16 * BM + 16 * a + (lane >> 4) + 4 * v;
+        const int i = tm * GM + 64 * a + 16 * wm + (lane >> 4) + 4 * v;
         const int j = tq * GQ + wq * 16 * BW + 16 * b + (lane & 15);
         if (i < m && j < q) P[(long)j * ldp + i] = acc[a][b][v];
       }

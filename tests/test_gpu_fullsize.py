@@ -40,10 +40,13 @@ def _dev(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
 
 
-@pytest.mark.parametrize("m,q", [(100, 64), (180, 180), (250, 61), (400, 135)])
+@pytest.mark.parametrize("m,q", [(100, 64), (180, 180), (250, 61), (400, 135), (450, 40), (17, 5)])
 def test_gram_tiles_at_bench_size(lp, m, q):
-    """C = A^T B at nx = 65,025 for tile heights 2 and 3 (m = 100, 180) and the
-    multi-tile path (m = 250, 400), against the float64 definition."""
+    """C = A^T B at nx = 65,025 for tile heights 2 and 3 (m = 100, 180), the
+    multi-tile path (m = 250, 400, 450) and tiles the product covers only in
+    part (their outside blocks skipped: m = 450 leaves 66 rows in the last
+    tile, q = 40 and 5 part of one column block), against the float64
+    definition."""
     print("case gram nx=65025 m=%d q=%d" % (m, q), flush=True)
     prob = lp.Problem(synthetic.ProblemDesc(N=256, nt=4, trunc_tol=1e-6, rank_cap=8))
     rng = np.random.default_rng(m + 7 * q)
