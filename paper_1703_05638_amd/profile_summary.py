@@ -215,7 +215,8 @@ def counters(d, regexes):
     rows = _rows(d, "counter_collection.csv")
     names = sorted({r["Counter_Name"] for r in rows})
     for regex in regexes.split(";"):
-        n = len(_per_dispatch(rows, regex, names[0])) if names else 0
+        pat = re.compile(regex)
+        n = len({r.get("Dispatch_Id") or r.get("Correlation_Id") for r in rows if pat.search(r["Kernel_Name"])})
         print("%s: dispatches %d" % (regex, n))
         for c in names:
             print("  %s sum %.6e" % (c, sum(_per_dispatch(rows, regex, c))))

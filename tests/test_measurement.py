@@ -60,3 +60,51 @@ def test_bench_kernel_table_matches_the_library_kinds():
     # the dominant kernel's committed traffic reports exist under the names the bench looks for
     for name in ("k_gram_mfma", "k_mg_up", "k_mg_down"):
         assert os.path.exists(bench.traffic_report(name, "mixed", "mesh1024_nt1000"))
+
+
+def _write_counters(d, rows):
+    import csv
+    with open(d / "run_counter_collection.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for r in rows:
+            w.writerow(dict(zip(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"], r)))
+
+
+def test_counter_sums_per_kernel_regex(tmp_path, capsys):
+    """The counters mode sums each counter over the dispatches a regex
+    matches (several rows of one dispatch, e.g. one per XCD, add up); the
+    regexes are separated by ';' so that a template argument list with a
+    comma stays one regex."""
+    _write_counters(tmp_path, [
+        (1, "void k_gram_mfma<3, 2>(long)", "SQ_WAVES", 2), (1, "void k_gram_mfma<3, 2>(long)", "SQ_WAVES", 3),
+        (2, "void k_gram_mfma<1, 1>(long)", "SQ_WAVES", 7), (3, "k_proj_grouped(x)", "SQ_WAVES", 11),
+        (1, "void k_gram_mfma<3, 2>(long)", "SQ_BUSY_CYCLES", 100),
+    ])
+    ps.counters(str(tmp_path), "k_gram_mfma<3, 2>;k_gram_mfma;k_proj_grouped\\(")
+    out = capsys.readouterr().out.splitlines()
+    assert out[0] == "k_gram_mfma<3, 2>: dispatches 1"
+    assert "SQ_BUSY_CYCLES sum 1.000000e+02" in out[1] and "SQ_WAVES sum 5.000000e+00" in out[2]
+    assert out[3] == "k_gram_mfma: dispatches 2"
+    assert "SQ_WAVES sum 1.200000e+01" in out[5]
+    assert out[6] == "k_proj_grouped\\(: dispatches 1"
+    assert "SQ_WAVES sum 1.100000e+01" in out[8]
+
+
+def test_traffic_scales_each_counter_by_the_copy(tmp_path, capsys):
+    """traffic divides the kernel's mean FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch) by what each counter reads for the copy of known size."""
+    f, w = tmp_path / "f", tmp_path / "w"
+    f.mkdir()
+    w.mkdir()
+    copy = 1 << 20  # bytes each way
+    # the copy: FETCH reads half its bytes, WRITE all of them
+    _write_counters(f, [(1, "MulFunctor", "FETCH_SIZE", copy / 2048), (2, "k_x", "FETCH_SIZE", 100.0),
+                        (3, "k_x", "FETCH_SIZE", 300.0)])
+    _write_counters(w, [(1, "MulFunctor", "WRITE_SIZE", copy / 1024), (2, "k_x", "WRITE_SIZE", 10.0),
+                        (3, "k_x", "WRITE_SIZE", 30.0)])
+    ps.traffic(str(f), str(w), "k_x", "MulFunctor", copy)
+    vals = dict(line.split(": ", 1) for line in capsys.readouterr().out.splitlines())
+    assert float(vals["fetch_scale_factor"]) == 0.5 and float(vals["write_scale_factor"]) == 1.0
+    # (200 KiB / 0.5 + 20 KiB / 1.0) per launch
+    assert float(vals["traffic_bytes_per_launch"]) == (400.0 + 20.0) * 1024
