@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <numeric>
 #include <thread>
 
@@ -110,7 +111,10 @@ static int ns_steps(double L) {
 }
 
 // f(0) .. f(n-1) on up to kHostThreads host threads (pure host work only:
-// no HIP calls and no exceptions inside f).
+// no HIP calls inside f).  An exception thrown by f (an allocation failure)
+// is caught in its thread; once every thread has joined, the first one is
+// rethrown in the caller.  Slices whose thread cannot be started run on the
+// calling thread.
 static constexpr int kHostThreads = 8;
 template <class F>
 static void host_parallel(int n, F&& f) {
@@ -119,13 +123,26 @@ static void host_parallel(int n, F&& f) {
     return;
   }
   const int nt = std::min(n, kHostThreads);
-  std::vector<std::thread> th;
-  for (int t = 1; t < nt; ++t)
-    th.emplace_back([&, t] {
+  std::vector<std::exception_ptr> err(nt);
+  auto slice = [&](int t) {
+    try {
       for (int i = t; i < n; i += nt) f(i);
-    });
-  for (int i = 0; i < n; i += nt) f(i);
+    } catch (...) {
+      err[t] = std::current_exception();
+    }
+  };
+  std::vector<std::thread> th;
+  th.reserve(nt - 1);
+  int t = 1;
+  try {
+    for (; t < nt; ++t) th.emplace_back(slice, t);
+  } catch (...) {
+  }
+  for (int u = t; u < nt; ++u) slice(u);
+  slice(0);
   for (auto& x : th) x.join();
+  for (const auto& e : err)
+    if (e) std::rethrow_exception(e);
 }
 
 Problem::Problem(const lrpost_problem_desc& d) : desc(d) {
