@@ -29,6 +29,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <new>
 #include <string>
 #include <thread>
 #include <vector>
@@ -197,16 +198,29 @@ struct lrpost_server {
       if (rc == LRPOST_OK) rc = lrpost_set_graphs(p, 0);
     }
     if (rc == LRPOST_OK) rc = lrpost_eigensolve(p, rq->k, LRPOST_BLOCK_LANCZOS, 0, &e);
-    if (rc == LRPOST_OK) {
-      const int kk = lrpost_eig_count(e);
-      rq->lambda.assign(kk, 0.0);
-      rc = lrpost_eig_values(e, rq->lambda.data());
+    // the request's host buffers may fail to allocate: that request fails,
+    // the worker goes on
+    bool host_oom = false;
+    try {
+      if (rc == LRPOST_OK) {
+        const int kk = lrpost_eig_count(e);
+        rq->lambda.assign(kk, 0.0);
+        rc = lrpost_eig_values(e, rq->lambda.data());
+      }
+      if (rc == LRPOST_OK && rq->want_diag) {
+        rq->diag.assign((size_t)(d.N - 1) * (d.N - 1) * d.nt, 0.0);
+        rc = lrpost_post_variance(p, e, rq->diag.data(), 0);
+      }
+      if (rc != LRPOST_OK) rq->error = lrpost_last_error();
+    } catch (const std::bad_alloc&) {
+      host_oom = true;
     }
-    if (rc == LRPOST_OK && rq->want_diag) {
-      rq->diag.assign((size_t)(d.N - 1) * (d.N - 1) * d.nt, 0.0);
-      rc = lrpost_post_variance(p, e, rq->diag.data(), 0);
+    if (host_oom) {
+      rc = LRPOST_ENOMEM;
+      std::vector<double>().swap(rq->lambda);
+      std::vector<double>().swap(rq->diag);
+      rq->error = "host memory";  // (short enough to need no allocation)
     }
-    if (rc != LRPOST_OK) rq->error = lrpost_last_error();
     rq->status = rc;
     if (e) lrpost_eigs_free(e);
     if (rc == LRPOST_OK) {
