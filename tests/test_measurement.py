@@ -1,6 +1,7 @@
 """Host-side pieces of the measurement path (no GPU): the source digests that
-tie a committed HBM-traffic report to the kernel it was taken on, and the
-report reader the bench uses."""
+tie a committed HBM-traffic report to the kernel it was taken on, the report
+reader the bench uses, the summary modes on synthetic counter CSV, and the
+bench's refusal of more than one GPU."""
 import os
 
 from paper_1703_05638_amd import profile_summary as ps
@@ -108,3 +109,15 @@ def test_traffic_scales_each_counter_by_the_copy(tmp_path, capsys):
     assert float(vals["fetch_scale_factor"]) == 0.5 and float(vals["write_scale_factor"]) == 1.0
     # (200 KiB / 0.5 + 20 KiB / 1.0) per launch
     assert float(vals["traffic_bytes_per_launch"]) == (400.0 + 20.0) * 1024
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The bench measures one GPU: --gpus 2 ends with status 2 and says so,
+    before any device work."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
